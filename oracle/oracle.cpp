@@ -1,0 +1,758 @@
+// FP64 CPU oracle for the semi-stochastic local energy of arXiv:2507.19276.
+//
+// TEST INFRASTRUCTURE ONLY.  Nothing in the product path may link, load or
+// call this file; it exists so that tests, the smoke check and the CPU
+// baseline of the benchmark can compare the HIP library against plain,
+// slow, obviously correct definitions.  It shares no code, header, table or
+// helper with the HIP library.
+//
+// Build: g++ -O2 -fopenmp -ffp-contract=off -shared -fPIC (see build.py).
+// -ffp-contract=off is essential: Hamiltonian elements are compared bit for
+// bit with the GPU, so no multiply-add may be fused behind our back.
+//
+// What each part follows in the paper:
+//   * Hamiltonian, Sec. 2.1 Eq. (2): H = sum h_pq a+_p a_q
+//       + 1/4 sum <pq||rs> a+_p a+_q a_s a_r over spin orbitals.
+//   * ONV ordering, Sec. 3: x_{2p} = n_{p alpha}, x_{2p+1} = n_{p beta}.
+//   * Local energy, Sec. 2.1 Eq. (6); deterministic part Eq. (20), stochastic
+//     part Eq. (21), their sum Eq. (22) (Sec. 2.4).
+//   * MPS-RNN / BDG-RNN amplitude, Sec. 2.1 Eqs. (9)-(10), Sec. 2.2 Eq. (12)
+//     without the tensor term; conditional P_t = h^T eta h; phase from
+//     w^T h + c (Sec. 2.1).
+//   * Particle-number / S_z masking of the conditionals, Sec. 3 Eqs. (23)-(24).
+//   * Correlator factorisation Psi = f Phi with cos-RBM f, Sec. 2.3
+//     Eqs. (14)-(15); reweighted local energy Eq. (18).
+//   * Gradient of ln|Psi| used by Eqs. (7) and (19).
+//
+// Readings of points the paper leaves open (each one listed in the design
+// notes of the repository):
+//   - spatial chemist integrals (pq|rs) give <PQ|RS> = (pr|qs) for matching
+//     spins, zero otherwise;
+//   - |n> = prod_{P ascending} (a+_P)^{x_P} |vac>, lowest index leftmost; signs
+//     are obtained by applying the operators one at a time to a bit array;
+//   - local state of spatial site t is s = n_alpha + 2 n_beta;
+//   - one matrix M_ij^{s_i} per (site, parent) edge, indexed by the child's
+//     local state; a site without parents has h = v;
+//   - the conditional is normalised over the local states that keep the
+//     electron counts reachable (exact feasibility mask);
+//   - real parameters, phase = sign(w^T h + c) with sign(0) = +1;
+//   - the deterministic set is |H_nm| >= eps with H_nm != 0, m != n; the
+//     remainder 0 < |H_nm| < eps is sampled with replacement with integer
+//     weights q = ceil(|H| 2^(40-e)), eps = f 2^e, f in [0.5,1);
+//   - draws use Philox4x32-10 (Salmon et al., SC'11) with key (seed lo, hi) and
+//     counter (sample index, draw index, stream lo, stream hi); the 128-bit
+//     output U (word 0 least significant) picks r = floor(U Q / 2^128).
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <limits>
+#include <vector>
+#include <algorithm>
+#include <omp.h>
+
+namespace {
+
+typedef unsigned __int128 u128;
+
+// --------------------------------------------------------------------------
+// integrals over spin orbitals (P = 2p + sigma)
+// --------------------------------------------------------------------------
+struct Ham {
+  int K;
+  const double* h;    // K*K
+  const double* eri;  // K^4, chemist (pq|rs)
+  double ecore;
+};
+
+inline int spatial(int P) { return P >> 1; }
+inline int spin(int P) { return P & 1; }
+
+double h_so(const Ham& H, int P, int Q) {
+  if (spin(P) != spin(Q)) return 0.0;
+  return H.h[spatial(P) * H.K + spatial(Q)];
+}
+
+// physicist <PQ|RS> = (PR|QS) = (pr|qs) delta(sP,sR) delta(sQ,sS)
+double g_so(const Ham& H, int P, int Q, int R, int S) {
+  if (spin(P) != spin(R) || spin(Q) != spin(S)) return 0.0;
+  const size_t K = H.K;
+  const size_t p = spatial(P), q = spatial(Q), r = spatial(R), s = spatial(S);
+  return H.eri[((p * K + r) * K + q) * K + s];
+}
+
+// antisymmetrised <PQ||RS> = <PQ|RS> - <PQ|SR>
+double anti(const Ham& H, int P, int Q, int R, int S) {
+  return g_so(H, P, Q, R, S) - g_so(H, P, Q, S, R);
+}
+
+// --------------------------------------------------------------------------
+// occupation-number vectors as plain bit arrays
+// --------------------------------------------------------------------------
+struct Det {
+  int n;            // number of spin orbitals (2K)
+  uint8_t x[128];
+};
+
+Det det_from_words(int K, const uint64_t* w) {
+  Det d;
+  d.n = 2 * K;
+  for (int P = 0; P < 128; ++P) d.x[P] = 0;
+  for (int P = 0; P < 2 * K; ++P) d.x[P] = (w[P >> 6] >> (P & 63)) & 1u;
+  return d;
+}
+
+void det_to_words(const Det& d, uint64_t* w) {
+  w[0] = w[1] = 0;
+  for (int P = 0; P < d.n; ++P)
+    if (d.x[P]) w[P >> 6] |= uint64_t(1) << (P & 63);
+}
+
+// a_P |d>: 0 if empty, else (-1)^(number of occupied Q < P); updates d.
+int annihilate(Det& d, int P) {
+  if (!d.x[P]) return 0;
+  int c = 0;
+  for (int Q = 0; Q < P; ++Q) c += d.x[Q];
+  d.x[P] = 0;
+  return (c & 1) ? -1 : 1;
+}
+
+// a+_P |d>: 0 if occupied, else (-1)^(number of occupied Q < P); updates d.
+int create(Det& d, int P) {
+  if (d.x[P]) return 0;
+  int c = 0;
+  for (int Q = 0; Q < P; ++Q) c += d.x[Q];
+  d.x[P] = 1;
+  return (c & 1) ? -1 : 1;
+}
+
+bool count_ok(const Det& d, int K, int na, int nb) {
+  int a = 0, b = 0;
+  for (int p = 0; p < K; ++p) { a += d.x[2 * p]; b += d.x[2 * p + 1]; }
+  for (int P = 2 * K; P < 128; ++P) if (d.x[P]) return false;
+  return a == na && b == nb;
+}
+
+// --------------------------------------------------------------------------
+// Slater-Condon rules
+// --------------------------------------------------------------------------
+
+// <n|H|n> = e_core + sum_P h_PP + 1/2 sum_{P,Q occ} <PQ||PQ>
+double diag_element(const Ham& H, const Det& n) {
+  double d1 = 0.0;
+  for (int P = 0; P < n.n; ++P)
+    if (n.x[P]) d1 += h_so(H, P, P);
+  double d2 = 0.0;
+  for (int P = 0; P < n.n; ++P) {
+    if (!n.x[P]) continue;
+    for (int Q = 0; Q < n.n; ++Q)
+      if (n.x[Q]) d2 += anti(H, P, Q, P, Q);
+  }
+  return H.ecore + d1 + 0.5 * d2;
+}
+
+struct Conn {
+  uint64_t m[2];
+  double H;
+};
+
+// single I -> A: |m> = g a+_A a_I |n>, H_mn = g (h_AI + sum_{J occ in n} <AJ||IJ>)
+Conn single_exc(const Ham& H, const Det& n, int I, int A) {
+  Det d = n;
+  int g = annihilate(d, I);
+  g *= create(d, A);
+  double acc = h_so(H, A, I);
+  for (int J = 0; J < n.n; ++J)
+    if (n.x[J]) acc += anti(H, A, J, I, J);
+  Conn c;
+  det_to_words(d, c.m);
+  c.H = g * acc;
+  return c;
+}
+
+// double (I<J) -> (A<B): |m> = g a+_A a+_B a_J a_I |n>, H_mn = g <AB||IJ>
+Conn double_exc(const Ham& H, const Det& n, int I, int J, int A, int B) {
+  if (I > J) std::swap(I, J);
+  if (A > B) std::swap(A, B);
+  Det d = n;
+  int g = annihilate(d, I);
+  g *= annihilate(d, J);
+  g *= create(d, B);
+  g *= create(d, A);
+  Conn c;
+  det_to_words(d, c.m);
+  c.H = g * anti(H, A, B, I, J);
+  return c;
+}
+
+// All S_z-conserving singles and doubles of n in the canonical order:
+//   alpha singles, beta singles, alpha-alpha doubles, beta-beta doubles,
+//   alpha-beta doubles; inside each block the nested loops below (holes
+//   outer, particles inner, ascending spatial indices, pairs i<j in
+//   lexicographic order).
+void connected(const Ham& H, const Det& n, std::vector<Conn>& out) {
+  const int K = H.K;
+  std::vector<int> oa, va, ob, vb;
+  for (int p = 0; p < K; ++p) {
+    (n.x[2 * p] ? oa : va).push_back(p);
+    (n.x[2 * p + 1] ? ob : vb).push_back(p);
+  }
+  out.clear();
+  for (int i : oa) for (int a : va) out.push_back(single_exc(H, n, 2 * i, 2 * a));
+  for (int i : ob) for (int a : vb) out.push_back(single_exc(H, n, 2 * i + 1, 2 * a + 1));
+  for (int s = 0; s < 2; ++s) {
+    const std::vector<int>& o = s ? ob : oa;
+    const std::vector<int>& v = s ? vb : va;
+    for (size_t i = 0; i < o.size(); ++i)
+      for (size_t j = i + 1; j < o.size(); ++j)
+        for (size_t a = 0; a < v.size(); ++a)
+          for (size_t b = a + 1; b < v.size(); ++b)
+            out.push_back(double_exc(H, n, 2 * o[i] + s, 2 * o[j] + s, 2 * v[a] + s, 2 * v[b] + s));
+  }
+  for (int i : oa)
+    for (int a : va)
+      for (int j : ob)
+        for (int b : vb)
+          out.push_back(double_exc(H, n, 2 * i, 2 * j + 1, 2 * a, 2 * b + 1));
+}
+
+// --------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as
+// easy as 1, 2, 3", SC'11): 10 rounds of the 4x32 Philox S-box, key bumped by
+// the Weyl constants between rounds.
+// --------------------------------------------------------------------------
+void philox4x32_10(const uint32_t ctr_in[4], const uint32_t key_in[2], uint32_t out[4]) {
+  const uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;
+  const uint32_t W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
+  uint32_t c[4] = {ctr_in[0], ctr_in[1], ctr_in[2], ctr_in[3]};
+  uint32_t k[2] = {key_in[0], key_in[1]};
+  for (int round = 0; round < 10; ++round) {
+    if (round > 0) { k[0] += W0; k[1] += W1; }
+    const uint64_t p0 = uint64_t(M0) * c[0];
+    const uint64_t p1 = uint64_t(M1) * c[2];
+    const uint32_t hi0 = uint32_t(p0 >> 32), lo0 = uint32_t(p0);
+    const uint32_t hi1 = uint32_t(p1 >> 32), lo1 = uint32_t(p1);
+    uint32_t n[4];
+    n[0] = hi1 ^ c[1] ^ k[0];
+    n[1] = lo1;
+    n[2] = hi0 ^ c[3] ^ k[1];
+    n[3] = lo0;
+    std::memcpy(c, n, sizeof c);
+  }
+  std::memcpy(out, c, sizeof c);
+}
+
+// --------------------------------------------------------------------------
+// BDG-RNN / MPS-RNN amplitude and cos-RBM correlator (direct definition)
+// --------------------------------------------------------------------------
+struct Ansatz {
+  int K, chi, na, nb, nh;
+  const int* pptr;
+  const int* pidx;
+  const double* prm;
+  std::vector<size_t> offM;                 // per edge: [4][chi][chi]
+  std::vector<size_t> offV, offEta, offW, offC;
+  size_t offB = 0, offWc = 0, total = 0;
+};
+
+Ansatz make_ansatz(int K, int chi, int na, int nb, const int* pptr, const int* pidx,
+                   int nh, const double* prm) {
+  Ansatz A;
+  A.K = K; A.chi = chi; A.na = na; A.nb = nb; A.nh = nh;
+  A.pptr = pptr; A.pidx = pidx; A.prm = prm;
+  size_t o = 0;
+  A.offM.resize(pptr[K]);
+  A.offV.resize(K); A.offEta.resize(K); A.offW.resize(K); A.offC.resize(K);
+  for (int i = 0; i < K; ++i) {
+    for (int e = pptr[i]; e < pptr[i + 1]; ++e) { A.offM[e] = o; o += size_t(4) * chi * chi; }
+    A.offV[i] = o; o += size_t(4) * chi;
+    A.offEta[i] = o; o += chi;
+    A.offW[i] = o; o += chi;
+    A.offC[i] = o; o += 1;
+  }
+  A.offB = o; o += nh;
+  A.offWc = o; o += size_t(nh) * 2 * K;
+  A.total = o;
+  return A;
+}
+
+// feasibility of local state s at site i given counts over sites < i
+bool allowed(const Ansatz& A, int i, int a_prev, int b_prev, int s) {
+  const int a = a_prev + (s & 1), b = b_prev + (s >> 1);
+  const int rest = A.K - 1 - i;
+  return a <= A.na && a + rest >= A.na && b <= A.nb && b + rest >= A.nb;
+}
+
+struct Trace {  // per-site forward quantities kept for the reverse sweep
+  std::vector<double> cand;  // [K][4][chi]
+  std::vector<double> p;     // [K][4]
+  std::vector<double> Z;     // [K]
+  std::vector<uint8_t> ok;   // [K][4]
+  std::vector<int> s;        // [K]
+};
+
+// candidates h_i^s = sum_{j in N(i)} M_ij^s h_j + v_i^s for s = 0..3
+void site_candidates(const Ansatz& A, int i, const std::vector<double>& carried, double* cand) {
+  const int chi = A.chi;
+  for (int s = 0; s < 4; ++s) {
+    for (int u = 0; u < chi; ++u) {
+      double acc = 0.0;
+      for (int e = A.pptr[i]; e < A.pptr[i + 1]; ++e) {
+        const int j = A.pidx[e];
+        const double* M = A.prm + A.offM[e] + size_t(s) * chi * chi + size_t(u) * chi;
+        const double* hj = carried.data() + size_t(j) * chi;
+        for (int k = 0; k < chi; ++k) acc += M[k] * hj[k];
+      }
+      cand[s * chi + u] = acc + A.prm[A.offV[i] + s * chi + u];
+    }
+  }
+}
+
+// log|Phi(n)| and sign Phi(n); returns false for an ONV outside the sector.
+bool phi_eval(const Ansatz& A, const Det& n, double* logabs, int* sgn, Trace* tr) {
+  const int K = A.K, chi = A.chi;
+  std::vector<double> carried(size_t(K) * chi, 0.0);
+  std::vector<double> cand(4 * chi);
+  if (tr) {
+    tr->cand.assign(size_t(K) * 4 * chi, 0.0);
+    tr->p.assign(size_t(K) * 4, 0.0);
+    tr->Z.assign(K, 0.0);
+    tr->ok.assign(size_t(K) * 4, 0);
+    tr->s.assign(K, 0);
+  }
+  double la = 0.0;
+  int sg = 1;
+  int a_prev = 0, b_prev = 0;
+  for (int i = 0; i < K; ++i) {
+    const int si = n.x[2 * i] + 2 * n.x[2 * i + 1];
+    site_candidates(A, i, carried, cand.data());
+    double p[4], Z = 0.0;
+    bool ok[4];
+    for (int s = 0; s < 4; ++s) {
+      double acc = 0.0;
+      for (int u = 0; u < chi; ++u) acc += A.prm[A.offEta[i] + u] * cand[s * chi + u] * cand[s * chi + u];
+      p[s] = acc;
+      ok[s] = allowed(A, i, a_prev, b_prev, s);
+      if (ok[s]) Z += p[s];
+    }
+    if (!ok[si]) { *logabs = -std::numeric_limits<double>::infinity(); *sgn = 0; return false; }
+    la += 0.5 * (std::log(p[si]) - std::log(Z));
+    double t = A.prm[A.offC[i]];
+    for (int u = 0; u < chi; ++u) t += A.prm[A.offW[i] + u] * cand[si * chi + u];
+    if (t < 0) sg = -sg;
+    for (int u = 0; u < chi; ++u) carried[size_t(i) * chi + u] = cand[si * chi + u];
+    if (tr) {
+      std::copy(cand.begin(), cand.end(), tr->cand.begin() + size_t(i) * 4 * chi);
+      for (int s = 0; s < 4; ++s) { tr->p[i * 4 + s] = p[s]; tr->ok[i * 4 + s] = ok[s]; }
+      tr->Z[i] = Z;
+      tr->s[i] = si;
+    }
+    a_prev += si & 1;
+    b_prev += si >> 1;
+  }
+  *logabs = la;
+  *sgn = sg;
+  return true;
+}
+
+// cos-RBM: theta_k = b_k + sum_P W_kP x_P, f = prod_k cos(theta_k)
+void corr_eval(const Ansatz& A, const Det& n, double* logabs, int* sgn) {
+  double la = 0.0;
+  int sg = 1;
+  const int nv = 2 * A.K;
+  for (int k = 0; k < A.nh; ++k) {
+    double th = A.prm[A.offB + k];
+    for (int P = 0; P < nv; ++P)
+      if (n.x[P]) th += A.prm[A.offWc + size_t(k) * nv + P];
+    const double c = std::cos(th);
+    la += std::log(std::fabs(c));
+    if (c < 0) sg = -sg;
+  }
+  *logabs = la;
+  *sgn = sg;
+}
+
+struct Amp {
+  double lphi, lf;
+  int sphi, sf;
+  bool valid;
+};
+
+Amp amp_eval(const Ansatz& A, const Det& n) {
+  Amp r;
+  r.valid = phi_eval(A, n, &r.lphi, &r.sphi, nullptr);
+  r.lf = 0.0; r.sf = 1;
+  if (A.nh) corr_eval(A, n, &r.lf, &r.sf);
+  return r;
+}
+
+// --------------------------------------------------------------------------
+// reverse sweep: g * d ln|Psi(n)| / d theta accumulated into grad
+// --------------------------------------------------------------------------
+void grad_accumulate(const Ansatz& A, const Det& n, double g, double* grad) {
+  const int K = A.K, chi = A.chi;
+  Trace tr;
+  double la;
+  int sg;
+  if (!phi_eval(A, n, &la, &sg, &tr)) return;
+  std::vector<double> carried(size_t(K) * chi);
+  for (int i = 0; i < K; ++i)
+    for (int u = 0; u < chi; ++u)
+      carried[size_t(i) * chi + u] = tr.cand[(size_t(i) * 4 + tr.s[i]) * chi + u];
+  std::vector<double> dcarry(size_t(K) * chi, 0.0);
+  std::vector<double> dcand(4 * chi);
+  for (int i = K - 1; i >= 0; --i) {
+    const int si = tr.s[i];
+    const double psi_ = tr.p[i * 4 + si], Z = tr.Z[i];
+    const double* eta = A.prm + A.offEta[i];
+    const double* cand = tr.cand.data() + size_t(i) * 4 * chi;
+    for (int s = 0; s < 4; ++s)
+      for (int u = 0; u < chi; ++u) {
+        double d = 0.0;
+        if (tr.ok[i * 4 + s]) {
+          if (s == si) d += g * eta[u] * cand[s * chi + u] / psi_;
+          d -= g * eta[u] * cand[s * chi + u] / Z;
+        }
+        if (s == si) d += dcarry[size_t(i) * chi + u];
+        dcand[s * chi + u] = d;
+      }
+    for (int u = 0; u < chi; ++u) {
+      double d = 0.5 * cand[si * chi + u] * cand[si * chi + u] / psi_;
+      for (int s = 0; s < 4; ++s)
+        if (tr.ok[i * 4 + s]) d -= 0.5 * cand[s * chi + u] * cand[s * chi + u] / Z;
+      grad[A.offEta[i] + u] += g * d;
+    }
+    for (int s = 0; s < 4; ++s)
+      for (int u = 0; u < chi; ++u) grad[A.offV[i] + s * chi + u] += dcand[s * chi + u];
+    for (int e = A.pptr[i]; e < A.pptr[i + 1]; ++e) {
+      const int j = A.pidx[e];
+      const double* hj = carried.data() + size_t(j) * chi;
+      for (int s = 0; s < 4; ++s) {
+        const double* M = A.prm + A.offM[e] + size_t(s) * chi * chi;
+        double* dM = grad + A.offM[e] + size_t(s) * chi * chi;
+        for (int u = 0; u < chi; ++u) {
+          const double du = dcand[s * chi + u];
+          for (int k = 0; k < chi; ++k) {
+            dM[u * chi + k] += du * hj[k];
+            dcarry[size_t(j) * chi + k] += M[u * chi + k] * du;
+          }
+        }
+      }
+    }
+  }
+  if (A.nh) {
+    const int nv = 2 * K;
+    for (int k = 0; k < A.nh; ++k) {
+      double th = A.prm[A.offB + k];
+      for (int P = 0; P < nv; ++P)
+        if (n.x[P]) th += A.prm[A.offWc + size_t(k) * nv + P];
+      const double dth = -g * std::tan(th);
+      grad[A.offB + k] += dth;
+      for (int P = 0; P < nv; ++P)
+        if (n.x[P]) grad[A.offWc + size_t(k) * nv + P] += dth;
+    }
+  }
+}
+
+// --------------------------------------------------------------------------
+// semi-stochastic local energy for one sample
+// --------------------------------------------------------------------------
+struct ElocOut {
+  double eloc, etnum, logabs, fsq;
+  int sign;
+  int64_t n_det, n_rem, n_uniq;
+  uint64_t Q;
+};
+
+// integer proposal weight of a remainder element (|H| < eps, H != 0)
+uint64_t proposal_weight(double absH, double eps) {
+  int e;
+  std::frexp(eps, &e);                      // eps = f 2^e, f in [0.5, 1)
+  return uint64_t(std::ceil(std::ldexp(absH, 40 - e)));
+}
+
+// floor(U * Q / 2^128) for a 128-bit U given as four 32-bit words (LS first)
+uint64_t scaled_draw(const uint32_t U[4], uint64_t Q) {
+  const uint64_t ulo = uint64_t(U[0]) | (uint64_t(U[1]) << 32);
+  const uint64_t uhi = uint64_t(U[2]) | (uint64_t(U[3]) << 32);
+  const u128 t = u128(uhi) * Q + ((u128(ulo) * Q) >> 64);
+  return uint64_t(t >> 64);
+}
+
+template <class AmpFn>
+ElocOut eloc_one(const Ham& H, const Det& n, int64_t sample_idx, double eps, int n_eps,
+                 uint64_t seed, uint64_t stream, AmpFn amp,
+                 std::vector<int64_t>* det_ranks, std::vector<int64_t>* draw_ranks) {
+  ElocOut o{};
+  std::vector<Conn> conns;
+  connected(H, n, conns);
+  const double Hnn = diag_element(H, n);
+  const Amp an = amp(n);
+  o.logabs = an.lphi + an.lf;
+  o.sign = an.sphi * an.sf;
+  o.fsq = std::exp(2.0 * an.lf);
+  double ed = 0.0, ed_t = 0.0;     // E^d and its reweighted numerator part
+  std::vector<int64_t> rem;       // ranks of the remainder, in canonical order
+  std::vector<uint64_t> q;
+  for (size_t r = 0; r < conns.size(); ++r) {
+    const double h = conns[r].H;
+    if (h == 0.0) continue;
+    if (std::fabs(h) >= eps) {
+      Det m = det_from_words(H.K, conns[r].m);
+      const Amp am = amp(m);
+      const int s = an.sphi * an.sf * am.sphi * am.sf;
+      ed += h * s * std::exp(am.lphi + am.lf - an.lphi - an.lf);
+      ed_t += h * s * std::exp(an.lf + am.lf + am.lphi - an.lphi);
+      ++o.n_det;
+      if (det_ranks) det_ranks->push_back(int64_t(r));
+    } else {
+      rem.push_back(int64_t(r));
+      q.push_back(proposal_weight(std::fabs(h), eps));
+    }
+  }
+  o.n_rem = int64_t(rem.size());
+  uint64_t Q = 0;
+  for (uint64_t x : q) Q += x;
+  o.Q = Q;
+  double es = 0.0, es_t = 0.0;
+  if (n_eps > 0 && Q > 0) {
+    std::vector<int64_t> picked;
+    for (int k = 0; k < n_eps; ++k) {
+      const uint32_t ctr[4] = {uint32_t(uint64_t(sample_idx)), uint32_t(k), uint32_t(stream),
+                               uint32_t(stream >> 32)};
+      const uint32_t key[2] = {uint32_t(seed), uint32_t(seed >> 32)};
+      uint32_t U[4];
+      philox4x32_10(ctr, key, U);
+      const uint64_t r = scaled_draw(U, Q);
+      uint64_t run = 0;
+      size_t t = 0;
+      for (; t < q.size(); ++t) {
+        run += q[t];
+        if (run > r) break;
+      }
+      const int64_t rank = rem[t];
+      picked.push_back(rank);
+      if (draw_ranks) draw_ranks->push_back(rank);
+      const double h = conns[rank].H;
+      const double w = h * (double(Q) / (double(q[t]) * double(n_eps)));
+      Det m = det_from_words(H.K, conns[rank].m);
+      const Amp am = amp(m);
+      const int s = an.sphi * an.sf * am.sphi * am.sf;
+      es += w * s * std::exp(am.lphi + am.lf - an.lphi - an.lf);
+      es_t += w * s * std::exp(an.lf + am.lf + am.lphi - an.lphi);
+    }
+    std::sort(picked.begin(), picked.end());
+    o.n_uniq = int64_t(std::unique(picked.begin(), picked.end()) - picked.begin());
+  }
+  o.eloc = Hnn + ed + es;
+  o.etnum = o.fsq * Hnn + ed_t + es_t;
+  if (!an.valid || !std::isfinite(o.logabs)) { o.eloc = o.etnum = std::nan(""); }
+  return o;
+}
+
+int nthreads_or_default(int nt) { return nt > 0 ? nt : omp_get_max_threads(); }
+
+}  // namespace
+
+// ==========================================================================
+// C entry points for the Python test wrapper
+// ==========================================================================
+extern "C" {
+
+int or_philox4x32_10(const uint32_t* ctr, const uint32_t* key, uint32_t* out) {
+  philox4x32_10(ctr, key, out);
+  return 0;
+}
+
+uint64_t or_proposal_weight(double absH, double eps) { return proposal_weight(absH, eps); }
+
+uint64_t or_scaled_draw(const uint32_t* U, uint64_t Q) { return scaled_draw(U, Q); }
+
+// diagonal elements for N samples; returns -1 for a sample outside the sector
+int or_hdiag(int K, int na, int nb, const double* h, const double* eri, double ecore,
+             const uint64_t* samples, int64_t N, double* out) {
+  Ham H{K, h, eri, ecore};
+  for (int64_t i = 0; i < N; ++i) {
+    Det d = det_from_words(K, samples + 2 * i);
+    if (!count_ok(d, K, na, nb)) return -1;
+    out[i] = diag_element(H, d);
+  }
+  return 0;
+}
+
+// connected determinants of one sample in canonical order; returns their
+// number (written only up to cap) or -1 for an invalid sample
+int64_t or_connected(int K, int na, int nb, const double* h, const double* eri, double ecore,
+                     const uint64_t* sample, uint64_t* m_out, double* h_out, int64_t cap) {
+  Ham H{K, h, eri, ecore};
+  Det d = det_from_words(K, sample);
+  if (!count_ok(d, K, na, nb)) return -1;
+  std::vector<Conn> c;
+  connected(H, d, c);
+  for (int64_t r = 0; r < int64_t(c.size()) && r < cap; ++r) {
+    m_out[2 * r] = c[r].m[0];
+    m_out[2 * r + 1] = c[r].m[1];
+    h_out[r] = c[r].H;
+  }
+  return int64_t(c.size());
+}
+
+int64_t or_n_params(int K, int chi, const int* pptr, int nh) {
+  Ansatz A = make_ansatz(K, chi, 0, 0, pptr, nullptr, nh, nullptr);
+  return int64_t(A.total);
+}
+
+// log|Phi|, sign Phi, log|f|, sign f for N samples
+int or_amplitudes(int K, int chi, int na, int nb, const int* pptr, const int* pidx, int nh,
+                  const double* prm, const uint64_t* samples, int64_t N, double* lphi,
+                  int* sphi, double* lf, int* sf, int nthreads) {
+  Ansatz A = make_ansatz(K, chi, na, nb, pptr, pidx, nh, prm);
+#pragma omp parallel for schedule(dynamic, 16) num_threads(nthreads_or_default(nthreads))
+  for (int64_t i = 0; i < N; ++i) {
+    Det d = det_from_words(K, samples + 2 * i);
+    Amp a = amp_eval(A, d);
+    lphi[i] = a.lphi; sphi[i] = a.sphi; lf[i] = a.lf; sf[i] = a.sf;
+  }
+  return 0;
+}
+
+// exact autoregressive draws from Phi^2 using the caller's uniforms u[N][K]
+int or_sample(int K, int chi, int na, int nb, const int* pptr, const int* pidx,
+              const double* prm, const double* u, int64_t N, uint64_t* out) {
+  Ansatz A = make_ansatz(K, chi, na, nb, pptr, pidx, 0, prm);
+  for (int64_t t = 0; t < N; ++t) {
+    Det d;
+    d.n = 2 * K;
+    std::memset(d.x, 0, sizeof d.x);
+    std::vector<double> carried(size_t(K) * chi, 0.0), cand(4 * chi);
+    int a_prev = 0, b_prev = 0;
+    for (int i = 0; i < K; ++i) {
+      site_candidates(A, i, carried, cand.data());
+      double p[4], Z = 0.0;
+      for (int s = 0; s < 4; ++s) {
+        double acc = 0.0;
+        for (int uu = 0; uu < chi; ++uu) acc += A.prm[A.offEta[i] + uu] * cand[s * chi + uu] * cand[s * chi + uu];
+        p[s] = allowed(A, i, a_prev, b_prev, s) ? acc : 0.0;
+        Z += p[s];
+      }
+      const double target = u[t * K + i] * Z;
+      double run = 0.0;
+      int pick = -1, last = -1;
+      for (int s = 0; s < 4; ++s) {
+        if (p[s] <= 0.0) continue;
+        last = s;
+        run += p[s];
+        if (run > target) { pick = s; break; }
+      }
+      if (pick < 0) pick = last;
+      d.x[2 * i] = pick & 1;
+      d.x[2 * i + 1] = pick >> 1;
+      for (int uu = 0; uu < chi; ++uu) carried[size_t(i) * chi + uu] = cand[pick * chi + uu];
+      a_prev += pick & 1;
+      b_prev += pick >> 1;
+    }
+    det_to_words(d, out + 2 * t);
+  }
+  return 0;
+}
+
+// sum_n g_n d ln|Psi(n)| / d theta, accumulated into grad (length n_params)
+int or_grad(int K, int chi, int na, int nb, const int* pptr, const int* pidx, int nh,
+            const double* prm, const uint64_t* samples, int64_t N, const double* g,
+            double* grad, int nthreads) {
+  Ansatz A = make_ansatz(K, chi, na, nb, pptr, pidx, nh, prm);
+  const int nt = nthreads_or_default(nthreads);
+  std::vector<std::vector<double>> part(nt, std::vector<double>(A.total, 0.0));
+#pragma omp parallel for schedule(static) num_threads(nt)
+  for (int64_t i = 0; i < N; ++i) {
+    Det d = det_from_words(K, samples + 2 * i);
+    grad_accumulate(A, d, g[i], part[omp_get_thread_num()].data());
+  }
+  for (int t = 0; t < nt; ++t)
+    for (size_t k = 0; k < A.total; ++k) grad[k] += part[t][k];
+  return 0;
+}
+
+// semi-stochastic local energies with the BDG-RNN x cos-RBM amplitude.
+// Optional per-sample counters n_det / n_rem / n_uniq (nullable).
+int or_eloc(int K, int na, int nb, const double* h, const double* eri, double ecore,
+            int chi, const int* pptr, const int* pidx, int nh, const double* prm,
+            const uint64_t* samples, int64_t N, double eps, int n_eps, uint64_t seed,
+            uint64_t stream, double* eloc, double* etnum, double* logabs, int8_t* sign,
+            double* fsq, int64_t* n_det, int64_t* n_rem, int64_t* n_uniq, int nthreads) {
+  Ham H{K, h, eri, ecore};
+  Ansatz A = make_ansatz(K, chi, na, nb, pptr, pidx, nh, prm);
+  for (int64_t i = 0; i < N; ++i) {
+    Det d = det_from_words(K, samples + 2 * i);
+    if (!count_ok(d, K, na, nb)) return -1;
+  }
+  auto amp = [&](const Det& d) { return amp_eval(A, d); };
+#pragma omp parallel for schedule(dynamic, 1) num_threads(nthreads_or_default(nthreads))
+  for (int64_t i = 0; i < N; ++i) {
+    Det d = det_from_words(K, samples + 2 * i);
+    ElocOut o = eloc_one(H, d, i, eps, n_eps, seed, stream, amp, nullptr, nullptr);
+    eloc[i] = o.eloc; etnum[i] = o.etnum; logabs[i] = o.logabs; sign[i] = int8_t(o.sign);
+    fsq[i] = o.fsq;
+    if (n_det) n_det[i] = o.n_det;
+    if (n_rem) n_rem[i] = o.n_rem;
+    if (n_uniq) n_uniq[i] = o.n_uniq;
+  }
+  return 0;
+}
+
+// one sample in detail: deterministic ranks, drawn ranks (in draw order), Q
+int or_eloc_detail(int K, int na, int nb, const double* h, const double* eri, double ecore,
+                   int chi, const int* pptr, const int* pidx, int nh, const double* prm,
+                   const uint64_t* sample, int64_t sample_idx, double eps, int n_eps,
+                   uint64_t seed, uint64_t stream, int64_t* det_ranks, int64_t det_cap,
+                   int64_t* n_det_out, int64_t* draw_ranks, uint64_t* Q_out, double* eloc_out) {
+  Ham H{K, h, eri, ecore};
+  Ansatz A = make_ansatz(K, chi, na, nb, pptr, pidx, nh, prm);
+  Det d = det_from_words(K, sample);
+  if (!count_ok(d, K, na, nb)) return -1;
+  auto amp = [&](const Det& x) { return amp_eval(A, x); };
+  std::vector<int64_t> dr, wr;
+  ElocOut o = eloc_one(H, d, sample_idx, eps, n_eps, seed, stream, amp, &dr, &wr);
+  *n_det_out = int64_t(dr.size());
+  for (size_t t = 0; t < dr.size() && int64_t(t) < det_cap; ++t) det_ranks[t] = dr[t];
+  for (size_t t = 0; t < wr.size(); ++t) draw_ranks[t] = wr[t];
+  *Q_out = o.Q;
+  *eloc_out = o.eloc;
+  return 0;
+}
+
+// local energies with the amplitude given as a table over sorted ONV keys
+// (keys as [T][2] words, ascending as 128-bit integers); an ONV missing from
+// the table has amplitude 0.
+int or_eloc_table(int K, int na, int nb, const double* h, const double* eri, double ecore,
+                  const uint64_t* keys, const double* vals, int64_t T,
+                  const uint64_t* samples, int64_t N, double eps, int n_eps, uint64_t seed,
+                  uint64_t stream, double* eloc, int nthreads) {
+  Ham H{K, h, eri, ecore};
+  auto lookup = [&](const Det& d) {
+    uint64_t w[2];
+    det_to_words(d, w);
+    const u128 key = (u128(w[1]) << 64) | w[0];
+    int64_t lo = 0, hi = T;
+    while (lo < hi) {
+      const int64_t mid = (lo + hi) / 2;
+      const u128 km = (u128(keys[2 * mid + 1]) << 64) | keys[2 * mid];
+      if (km < key) lo = mid + 1; else hi = mid;
+    }
+    Amp a;
+    a.lf = 0.0; a.sf = 1; a.valid = true;
+    const u128 kf = lo < T ? ((u128(keys[2 * lo + 1]) << 64) | keys[2 * lo]) : 0;
+    const double v = (lo < T && kf == key) ? vals[lo] : 0.0;
+    a.lphi = std::log(std::fabs(v));
+    a.sphi = v < 0 ? -1 : 1;
+    return a;
+  };
+#pragma omp parallel for schedule(dynamic, 1) num_threads(nthreads_or_default(nthreads))
+  for (int64_t i = 0; i < N; ++i) {
+    Det d = det_from_words(K, samples + 2 * i);
+    ElocOut o = eloc_one(H, d, i, eps, n_eps, seed, stream, lookup, nullptr, nullptr);
+    eloc[i] = o.eloc;
+  }
+  return 0;
+}
+
+}  // extern "C"

@@ -1,0 +1,156 @@
+"""Pins of the oracle's amplitude (Sec. 2.1-2.3, Sec. 3 masking) and gradient."""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2507_19276_amd import workloads as W
+
+
+def _amps(w, params=None, samples=None, nh=None):
+    return oracle.amplitudes(w.K, w.chi, w.n_alpha, w.n_beta, w.parent_ptr, w.parent_idx,
+                             w.n_hidden if nh is None else nh,
+                             w.params if params is None else params,
+                             w.samples if samples is None else samples)
+
+
+def _small(graph="chain", K=6, na=3, nb=3, chi=4, nh=0, seed=11):
+    h, eri = W.chain_integrals(K, seed)
+    pp, pi = {"chain": W.graph_chain, "nnn": W.graph_nn_nnn}[graph](K)
+    prm = W.ansatz_params(K, chi, pp, pi, nh, seed + 1)
+    return W.Workload(name="t", K=K, n_alpha=na, n_beta=nb, h=h, eri=eri, e_core=0.0, chi=chi,
+                      parent_ptr=pp, parent_idx=pi, n_hidden=nh, params=prm,
+                      samples=W.all_onvs(K, na, nb), eps=0.0, n_eps=0, seed=1, precision="f64")
+
+
+def test_param_counts_match_paper():
+    path = os.path.join(os.path.dirname(__file__), "golden", "param_counts.txt")
+    for line in open(path):
+        if line.startswith("#") or not line.strip():
+            continue
+        K, chi, nh, count = map(int, line.split())
+        pp, _ = W.graph_chain(K)
+        real_bdg = oracle.n_params(K, chi, pp, 0)
+        assert real_bdg == W.n_params(K, chi, pp, 0)
+        paper_bdg = 2 * (real_bdg + 4 * chi * chi)
+        corr = oracle.n_params(K, chi, pp, nh) - real_bdg
+        assert paper_bdg + corr == count
+
+
+@pytest.mark.parametrize("graph,na,nb", [("chain", 3, 3), ("nnn", 3, 3), ("nnn", 4, 2), ("chain", 2, 5)])
+def test_phi_normalised(graph, na, nb):
+    """Sec. 2.3 Eq. (14) requires sum_n |Phi(n)|^2 = 1; the masked conditionals
+    of Sec. 3 Eq. (24) must keep it (sum over the whole sector)."""
+    w = _small(graph=graph, na=na, nb=nb)
+    a = _amps(w)
+    total = np.exp(2 * a["lphi"]).sum()
+    assert abs(total - 1.0) < 1e-13
+
+
+def test_phi_normalised_lattice_like():
+    pp, pi = W.graph_lattice((2, 2, 2))
+    K = 8
+    prm = W.ansatz_params(K, 3, pp, pi, 0, 5)
+    s = W.all_onvs(K, 4, 4)
+    a = oracle.amplitudes(K, 3, 4, 4, pp, pi, 0, prm, s)
+    assert abs(np.exp(2 * a["lphi"]).sum() - 1.0) < 1e-13
+
+
+def test_eta_scale_and_phase_flip_invariance():
+    w = _small(graph="nnn", nh=0)
+    a0 = _amps(w)
+    prm = w.params.copy()
+    chi, K = w.chi, w.K
+    # locate per-site blocks in the packed layout
+    o = 0
+    for i in range(K):
+        d = w.parent_ptr[i + 1] - w.parent_ptr[i]
+        o += d * 4 * chi * chi + 4 * chi
+        prm[o:o + chi] *= 3.7            # eta_i -> 3.7 eta_i
+        o += chi
+        prm[o:o + chi + 1] *= -1.0       # (w_i, c_i) -> -(w_i, c_i)
+        o += chi + 1
+    a1 = _amps(w, params=prm)
+    np.testing.assert_allclose(a1["lphi"], a0["lphi"], rtol=0, atol=1e-13)
+    assert np.all(a1["sphi"] == a0["sphi"] * (-1) ** K)
+
+
+def test_correlator_zero_is_identity_and_closed_form():
+    w = _small(graph="nnn", nh=5)
+    nb = w.params.size - 5 * (2 * w.K + 1)
+    prm = w.params.copy()
+    prm[nb:] = 0.0
+    a = _amps(w, params=prm)
+    assert np.all(a["lf"] == 0.0) and np.all(a["sf"] == 1)
+    # W = 0: f = prod_k cos(b_k) for every ONV
+    b = np.array([0.3, -1.2, 2.0, 0.05, 1.7])
+    prm[nb:nb + 5] = b
+    a = _amps(w, params=prm)
+    np.testing.assert_allclose(a["lf"], np.log(np.abs(np.cos(b))).sum(), rtol=0, atol=1e-14)
+    assert np.all(a["sf"] == np.prod(np.sign(np.cos(b))))
+    # one hidden unit coupled to one spin orbital P: theta = b + W x_P
+    prm[nb:] = 0.0
+    P = 7
+    prm[nb + 5 + P] = 0.9       # W[0, P]
+    a = _amps(w, params=prm)
+    xP = np.array([(int(s[0]) >> P) & 1 for s in w.samples])
+    np.testing.assert_allclose(a["lf"], np.log(np.abs(np.cos(0.9 * xP))), rtol=0, atol=1e-14)
+
+
+def test_sampler_distribution():
+    """Exact autoregressive draws follow Phi^2 (chi-square over the sector)."""
+    w = _small(graph="chain")
+    a = _amps(w)
+    p = np.exp(2 * a["lphi"])
+    keys = {(int(s[0]), int(s[1])): k for k, s in enumerate(w.samples)}
+    N = 200_000
+    u = W.uniforms((N, w.K), 5)
+    draws = oracle.sample(w.K, w.chi, w.n_alpha, w.n_beta, w.parent_ptr, w.parent_idx, w.params, u)
+    cnt = np.zeros(len(p))
+    for d in draws:
+        cnt[keys[(int(d[0]), int(d[1]))]] += 1
+    exp = p * N
+    m = exp > 5
+    chi2 = ((cnt[m] - exp[m]) ** 2 / exp[m]).sum()
+    dof = m.sum() - 1
+    assert chi2 < dof + 6 * np.sqrt(2 * dof)
+    assert cnt[~m].sum() < 5 * max(exp[~m].sum(), 1.0) + 20
+
+
+def _fd_grad(w, idx, hstep=1e-6):
+    out = []
+    for k in idx:
+        pp_ = w.params.copy(); pp_[k] += hstep
+        pm_ = w.params.copy(); pm_[k] -= hstep
+        out.append((_amps(w, params=pp_)["logabs"] - _amps(w, params=pm_)["logabs"]) / (2 * hstep))
+    return np.array(out)
+
+
+@pytest.mark.parametrize("graph,nh", [("chain", 0), ("nnn", 4)])
+def test_grad_matches_finite_differences(graph, nh):
+    w = _small(graph=graph, nh=nh, chi=3)
+    rng = np.random.default_rng(3)
+    samples = w.samples[rng.choice(len(w.samples), 12, replace=False)]
+    w.samples = samples
+    g = rng.standard_normal(len(samples))
+    gr = oracle.grad(w.K, w.chi, w.n_alpha, w.n_beta, w.parent_ptr, w.parent_idx, w.n_hidden,
+                     w.params, samples, g)
+    idx = rng.choice(w.params.size, 64, replace=False)
+    fd = _fd_grad(w, idx) @ g
+    np.testing.assert_allclose(gr[idx], fd, rtol=1e-6, atol=1e-8)
+
+
+def test_grad_of_normalisation_vanishes():
+    """sum_n Phi(n)^2 d ln|Phi(n)| = d/dtheta (1/2) sum Phi^2 = 0 exactly."""
+    w = _small(graph="nnn", chi=3)
+    a = _amps(w)
+    g = np.exp(2 * a["lphi"])
+    gr = oracle.grad(w.K, w.chi, w.n_alpha, w.n_beta, w.parent_ptr, w.parent_idx, 0,
+                     w.params, w.samples, g)
+    assert np.abs(gr).max() < 1e-13
+    # but the individual terms are not zero
+    g1 = np.zeros_like(g); g1[0] = 1.0
+    gr1 = oracle.grad(w.K, w.chi, w.n_alpha, w.n_beta, w.parent_ptr, w.parent_idx, 0,
+                      w.params, w.samples, g1)
+    assert np.abs(gr1).max() > 1e-3
