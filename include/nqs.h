@@ -1,0 +1,214 @@
+/*
+ * nqs.h — C ABI of the MI355X (gfx950) semi-stochastic local-energy library.
+ *
+ * The library evaluates, for a batch of sampled occupation-number vectors n,
+ *
+ *   E_loc(n) = sum_m H_nm Psi(m) / Psi(n)                (Sec. 2.1, Eq. (6))
+ *
+ * split into a deterministic part over |H_nm| >= eps (Sec. 2.4, Eq. (20)) and
+ * a stochastic part that draws N_eps connected determinants with probability
+ * proportional to |H_nm| among the rest (Sec. 2.4, Eqs. (21)-(22)).  Psi = f Phi
+ * where Phi is a BDG-RNN / MPS-RNN amplitude (Sec. 2.1 Eq. (10), Sec. 2.2
+ * Eq. (12) without the tensor term) with particle-number / S_z masking (Sec. 3,
+ * Eqs. (23)-(24)) and f the optional cos-RBM correlator (Sec. 2.3, Eq. (15)).
+ * It also returns the reweighted numerator of Sec. 2.3 Eq. (18), log|Psi| and
+ * the vector-Jacobian product of log|Psi| used by the gradients of Eqs. (7)
+ * and (19).
+ *
+ * Conventions
+ *  - K spatial orbitals (K <= 64), spin orbital P = 2p + sigma (sigma 0 alpha,
+ *    1 beta), interleaved as in Sec. 3.  An ONV is two uint64 words
+ *    (little-endian 128-bit integer), bit P = occupation of spin orbital P.
+ *  - |n> = prod_{P ascending} (a+_P)^{x_P} |vac>; fermionic signs follow.
+ *  - Integrals: h[p*K+q] = h_pq and eri[((p*K+q)*K+r)*K+s] = (pq|rs) (chemist
+ *    notation, real orbitals, 8-fold symmetric); <PQ|RS> = (pr|qs) for matching
+ *    spins.  Row-major FP64 host arrays.
+ *  - Graph: parents N(i) of site i as CSR (parent_ptr[K+1], parent_idx[]),
+ *    every parent index lower than i, ascending within a site.
+ *  - Packed FP64 parameters, per site i ascending: for each parent j (in
+ *    parent_idx order) and local state s = 0..3 (s = n_alpha + 2 n_beta), the
+ *    chi x chi matrix M_ij^s row-major (h_out[u] = sum_k M[u][k] h_in[k]);
+ *    then v_i^s (4 x chi), eta_i (chi, >= 0), w_i (chi), c_i (1).  After all
+ *    sites, when n_hidden > 0: b (n_hidden) then W (n_hidden x 2K row-major).
+ *
+ * Errors: every call returns an nqs_status; nothing else crosses the ABI.
+ * nqs_last_error() returns a thread-local message describing the last
+ * failure of a call made by the calling thread.
+ *
+ * Streams: device work is ordered on the hipStream_t passed in (0 = the null
+ * stream).  Calls that size data-dependent work (nqs_eloc, nqs_rows)
+ * synchronise that stream once internally; all calls have completed their
+ * device work when they return, unless stated otherwise.
+ */
+#ifndef NQS_H
+#define NQS_H
+
+#include <stdint.h>
+#include <stddef.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int nqs_status;
+enum {
+  NQS_OK = 0,
+  NQS_EINVAL = 1,       /* bad shape, bad argument, sample outside the sector */
+  NQS_ENOMEM = 2,       /* device memory exhausted (or the allocation hook fired) */
+  NQS_EDEVICE = 3,      /* a HIP runtime error; the message holds the HIP string */
+  NQS_EUNSUPPORTED = 4, /* combination not implemented (e.g. chi > 64) */
+  NQS_EBUSY = 5         /* serving: no request completed yet / queue full */
+};
+
+typedef enum {
+  NQS_F64 = 0,   /* bond contractions in FP64 (the paper's precision, Sec. 3) */
+  NQS_F32 = 1,   /* FP32 operands on MFMA, FP32 accumulate */
+  NQS_BF16 = 2   /* BF16 operands on MFMA, FP32 accumulate, per-row scaled hidden states */
+} nqs_precision;
+
+typedef struct nqs_ctx nqs_ctx;
+typedef struct nqs_instance nqs_instance;
+typedef struct nqs_ansatz nqs_ansatz;
+
+/* Options of one local-energy call (Sec. 2.4 hyperparameters and RNG keys). */
+typedef struct {
+  double eps;          /* deterministic cutoff: |H_nm| >= eps is summed exactly; eps >= 0 */
+  int32_t n_eps;       /* number of i.i.d. draws from the remainder per sample; >= 0 */
+  int32_t precision;   /* nqs_precision of the amplitude evaluation */
+  uint64_t seed;       /* Philox4x32-10 key (low word, high word) */
+  uint64_t stream_id;  /* third and fourth Philox counter words */
+  int32_t sample_base; /* added to the sample index in the Philox counter */
+  int32_t reserved;
+} nqs_eloc_opts;
+
+/* Per-call statistics (host struct, filled when a non-NULL pointer is passed). */
+typedef struct {
+  int64_t n_samples;
+  int64_t n_conn;        /* connected determinants per sample (same for all samples) */
+  int64_t n_rows;        /* amplitude rows evaluated (samples + deterministic + unique drawn) */
+  int64_t n_det_rows;    /* total |D_n| */
+  int64_t n_draw_rows;   /* total unique drawn determinants */
+  int64_t n_zero_amp;    /* samples with Psi(n) = 0 (their E_loc is NaN) */
+  double sum_c;          /* sum of counts */
+  double B;              /* sum c |f|^2 / sum c                       (Sec. 2.3) */
+  double E;              /* sum c Etilde_num / sum c |f|^2           (Eq. (17)) */
+  double var;            /* sum c |f|^2 (E_loc - E)^2 / sum c |f|^2 */
+  double ms_enumerate, ms_draw, ms_rows, ms_amplitude, ms_reduce;  /* stage times (device events) */
+} nqs_eloc_stats;
+
+/* ---- context --------------------------------------------------------- */
+
+/* Create a context on HIP device `device`; all objects made from it live on
+ * that device.  The context owns a pool of device workspaces. */
+nqs_status nqs_ctx_create(int device, nqs_ctx** out);
+/* Destroy a context; objects created from it must be destroyed first. */
+nqs_status nqs_ctx_destroy(nqs_ctx* ctx);
+/* Message of the calling thread's last failed call ("" if none). */
+const char* nqs_last_error(void);
+/* Library version string. */
+const char* nqs_version(void);
+
+/* ---- instance: the Hamiltonian of Sec. 2.1 Eq. (2) ------------------- */
+
+/* Copy h (K*K) and eri (K^4) from host memory to the device and keep them
+ * resident.  EINVAL if K < 1 or K > 64, n_alpha/n_beta outside [0,K], h not
+ * symmetric or eri not 8-fold symmetric within 1e-10 * max|eri| (values are
+ * replaced by their canonical representative). */
+nqs_status nqs_instance_create(nqs_ctx* ctx, int K, int n_alpha, int n_beta, const double* h1,
+                               const double* eri, double e_core, nqs_instance** out);
+nqs_status nqs_instance_destroy(nqs_instance* inst);
+/* Number of S_z-conserving singles + doubles of any ONV of the sector. */
+int64_t nqs_instance_n_conn(const nqs_instance* inst);
+
+/* Hamiltonian engine (Sec. 2.4, Slater-Condon rules): for each of the N
+ * samples (device, [N][2] uint64), all n_conn connected determinants in the
+ * canonical order (alpha singles, beta singles, alpha-alpha doubles,
+ * beta-beta doubles, alpha-beta doubles; holes outer, particles inner,
+ * ascending orbitals, pairs lexicographic) with H_mn, plus H_nn.
+ * m_out: device [N][n_conn][2] uint64; h_out: device [N][n_conn] double;
+ * hdiag_out: device [N] double (any may be NULL).  EINVAL for a sample outside
+ * the (n_alpha, n_beta) sector. */
+nqs_status nqs_connected(nqs_ctx* ctx, const nqs_instance* inst, const uint64_t* samples, int64_t N,
+                         uint64_t* m_out, double* h_out, double* hdiag_out, hipStream_t stream);
+
+/* ---- ansatz: BDG-RNN / MPS-RNN (Sec. 2.1-2.2) x cos-RBM (Sec. 2.3) ---- */
+
+/* Describe the ansatz: K sites, electron counts of the sector (they define the
+ * mask of Sec. 3), bond dimension chi (1..64), parent CSR (host arrays), and
+ * n_hidden cos-RBM units (0 = no correlator).  EINVAL for a malformed graph. */
+nqs_status nqs_ansatz_create(nqs_ctx* ctx, int K, int n_alpha, int n_beta, int chi,
+                             const int32_t* parent_ptr, const int32_t* parent_idx, int n_hidden,
+                             nqs_ansatz** out);
+nqs_status nqs_ansatz_destroy(nqs_ansatz* ans);
+/* Length of the packed parameter vector. */
+int64_t nqs_ansatz_n_params(const nqs_ansatz* ans);
+/* Copy the packed FP64 parameters (device pointer, nqs_ansatz_n_params
+ * doubles) into the library's kernel layouts for every precision.  The caller's
+ * buffer may be freed or changed afterwards; call again after an update.
+ * EINVAL if some eta < 0 (checked on the device copy). */
+nqs_status nqs_ansatz_bind_params(nqs_ansatz* ans, const double* params, hipStream_t stream);
+
+/* log|Psi(n)| (device double[N]) and sign Psi(n) (device int8[N]) of N samples.
+ * A sample outside the sector is EINVAL; Psi(n) = 0 gives -inf and sign 0. */
+nqs_status nqs_logpsi(nqs_ctx* ctx, const nqs_ansatz* ans, const uint64_t* samples, int64_t N,
+                      int32_t precision, double* logabs, int8_t* sign, hipStream_t stream);
+
+/* Vector-Jacobian product of log|Psi| (Eqs. (7), (19)): grad[k] +=
+ * sum_n cot[n] d log|Psi(n)| / d theta_k over the packed parameters (device
+ * double[n_params], accumulated, not overwritten).  cot: device double[N].
+ * precision NQS_F64 or NQS_F32 (the FP32 path accumulates in FP32 per block and
+ * in FP64 across blocks). */
+nqs_status nqs_logpsi_vjp(nqs_ctx* ctx, const nqs_ansatz* ans, const uint64_t* samples, int64_t N,
+                          const double* cot, int32_t precision, double* grad, hipStream_t stream);
+
+/* ---- local energy (Sec. 2.4) ------------------------------------------ */
+
+/* Semi-stochastic local energies of N samples (device [N][2] uint64).
+ * counts: device double[N] weights of the batch sums (NULL = all 1).
+ * Outputs (device, length N, any may be NULL):
+ *   eloc  = H_nn + sum_{D_n} H_nm r_m + (1/N_eps) sum_k H_nm_k / P(m_k) r_mk,
+ *           r = Psi(m)/Psi(n)                                   (Eq. (22))
+ *   etnum = f_n sum_m H_nm f_m Phi(m)/Phi(n) = |f_n|^2 E_loc(n)  (numerator of Eq. (18))
+ *   logabs = log|Psi(n)|, sign = sign Psi(n), fsq = |f_n|^2.
+ * The proposal is P(m) = q_m / sum q with q_m = ceil(|H_nm| 2^(40-e)),
+ * eps = f 2^e, f in [0.5,1); draw k of sample s uses Philox4x32-10 with key
+ * (seed lo, seed hi) and counter (sample_base + s, k, stream_id lo, hi).
+ * stats (host, nullable) receives the batch sums of Sec. 2.3.  Synchronises
+ * `stream` once to size the amplitude rows. */
+nqs_status nqs_eloc(nqs_ctx* ctx, const nqs_instance* inst, const nqs_ansatz* ans,
+                    const uint64_t* samples, const double* counts, int64_t N,
+                    const nqs_eloc_opts* opts, double* eloc, double* etnum, double* logabs,
+                    int8_t* sign, double* fsq, nqs_eloc_stats* stats, hipStream_t stream);
+
+/* The amplitude rows of the same computation, for inspection: per sample
+ * its own ONV (rank -1, coefficient 0), the deterministic set in canonical
+ * rank order (coefficient H_nm) and the unique drawn determinants in rank
+ * order (coefficient multiplicity * H_nm Q / (N_eps q_m)).  row_ptr: device
+ * int64[N+1]; n_det: device int64[N]; Q: device uint64[N] (remainder weight
+ * sum); rank: device int64[cap]; coef: device double[cap]; m: device
+ * uint64[cap][2].  *n_rows (host) receives the total; rows beyond cap are not
+ * written. */
+nqs_status nqs_rows(nqs_ctx* ctx, const nqs_instance* inst, const uint64_t* samples, int64_t N,
+                    const nqs_eloc_opts* opts, int64_t cap, int64_t* row_ptr, int64_t* n_det,
+                    uint64_t* Q, int64_t* rank, double* coef, uint64_t* m, int64_t* n_rows,
+                    hipStream_t stream);
+
+/* Device bytes an nqs_eloc call of this shape will take from the pool at
+ * most, given the number of amplitude rows it will evaluate (pass 0 to get
+ * the row-independent part); used for admission by footprint. */
+nqs_status nqs_eloc_workspace_bytes(const nqs_instance* inst, const nqs_ansatz* ans, int64_t N,
+                                    const nqs_eloc_opts* opts, int64_t n_rows, size_t* bytes);
+
+/* ---- test hooks --------------------------------------------------------- */
+
+/* Make the k-th subsequent workspace allocation of this context fail with
+ * NQS_ENOMEM (k >= 1; 0 disables).  For failure-handling tests. */
+nqs_status nqs_ctx_fail_alloc_at(nqs_ctx* ctx, int64_t k);
+/* Bytes currently held by the context's workspace pool (in use, cached). */
+nqs_status nqs_ctx_pool_bytes(const nqs_ctx* ctx, size_t* in_use, size_t* cached);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NQS_H */

@@ -50,7 +50,7 @@ def _load():
     lib.or_sample.argtypes = [_i, _i, _i, _i, _p, _p, _p, _p, _i64, _p]
     lib.or_grad.argtypes = [_i, _i, _i, _i, _p, _p, _i, _p, _p, _i64, _p, _p, _i]
     lib.or_eloc.argtypes = [_i, _i, _i, _p, _p, _d, _i, _p, _p, _i, _p, _p, _i64, _d, _i, _u64,
-                            _u64, _p, _p, _p, _p, _p, _p, _p, _p, _i]
+                            _u64, _i64, _p, _p, _p, _p, _p, _p, _p, _p, _i]
     lib.or_eloc_detail.argtypes = [_i, _i, _i, _p, _p, _d, _i, _p, _p, _i, _p, _p, _i64, _d, _i,
                                    _u64, _u64, _p, _i64, _p, _p, _p, _p]
     lib.or_eloc_table.argtypes = [_i, _i, _i, _p, _p, _d, _p, _p, _i64, _p, _i64, _d, _i, _u64,
@@ -158,8 +158,10 @@ def grad(K, chi, na, nb, parent_ptr, parent_idx, n_hidden, params, samples, g,
 
 
 def eloc(K, na, nb, h, eri, chi, parent_ptr, parent_idx, n_hidden, params, samples,
-         eps=0.0, n_eps=0, seed=0, stream=0, e_core=0.0, nthreads: int = 0) -> Dict[str, np.ndarray]:
-    """Semi-stochastic local energies and the reweighted numerators."""
+         eps=0.0, n_eps=0, seed=0, stream=0, e_core=0.0, nthreads: int = 0,
+         sample_base: int = 0) -> Dict[str, np.ndarray]:
+    """Semi-stochastic local energies and the reweighted numerators; the draws
+    of sample i use Philox counter word 0 = sample_base + i."""
     h, eri = _f64(h), _f64(eri)
     pp, pi, prm = _i32(parent_ptr), _i32(parent_idx), _f64(params)
     s = _u64a(samples).reshape(-1, 2)
@@ -168,7 +170,7 @@ def eloc(K, na, nb, h, eri, chi, parent_ptr, parent_idx, n_hidden, params, sampl
     sign = np.zeros(N, dtype=np.int8)
     cnt = {k: np.zeros(N, dtype=np.int64) for k in ("n_det", "n_rem", "n_uniq")}
     rc = _load().or_eloc(K, na, nb, _ptr(h), _ptr(eri), e_core, chi, _ptr(pp), _ptr(pi), n_hidden,
-                         _ptr(prm), _ptr(s), N, eps, n_eps, seed, stream, _ptr(out["eloc"]),
+                         _ptr(prm), _ptr(s), N, eps, n_eps, seed, stream, sample_base, _ptr(out["eloc"]),
                          _ptr(out["etnum"]), _ptr(out["logabs"]), _ptr(sign), _ptr(out["fsq"]),
                          _ptr(cnt["n_det"]), _ptr(cnt["n_rem"]), _ptr(cnt["n_uniq"]), nthreads)
     if rc != 0:

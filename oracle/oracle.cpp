@@ -672,13 +672,15 @@ int or_grad(int K, int chi, int na, int nb, const int* pptr, const int* pidx, in
   return 0;
 }
 
-// semi-stochastic local energies with the BDG-RNN x cos-RBM amplitude.
-// Optional per-sample counters n_det / n_rem / n_uniq (nullable).
+// semi-stochastic local energies with the BDG-RNN x cos-RBM amplitude; the
+// draw counter of sample i is sample_base + i.  Optional per-sample counters
+// n_det / n_rem / n_uniq (nullable).
 int or_eloc(int K, int na, int nb, const double* h, const double* eri, double ecore,
             int chi, const int* pptr, const int* pidx, int nh, const double* prm,
             const uint64_t* samples, int64_t N, double eps, int n_eps, uint64_t seed,
-            uint64_t stream, double* eloc, double* etnum, double* logabs, int8_t* sign,
-            double* fsq, int64_t* n_det, int64_t* n_rem, int64_t* n_uniq, int nthreads) {
+            uint64_t stream, int64_t sample_base, double* eloc, double* etnum, double* logabs,
+            int8_t* sign, double* fsq, int64_t* n_det, int64_t* n_rem, int64_t* n_uniq,
+            int nthreads) {
   Ham H{K, h, eri, ecore};
   Ansatz A = make_ansatz(K, chi, na, nb, pptr, pidx, nh, prm);
   for (int64_t i = 0; i < N; ++i) {
@@ -689,7 +691,7 @@ int or_eloc(int K, int na, int nb, const double* h, const double* eri, double ec
 #pragma omp parallel for schedule(dynamic, 1) num_threads(nthreads_or_default(nthreads))
   for (int64_t i = 0; i < N; ++i) {
     Det d = det_from_words(K, samples + 2 * i);
-    ElocOut o = eloc_one(H, d, i, eps, n_eps, seed, stream, amp, nullptr, nullptr);
+    ElocOut o = eloc_one(H, d, sample_base + i, eps, n_eps, seed, stream, amp, nullptr, nullptr);
     eloc[i] = o.eloc; etnum[i] = o.etnum; logabs[i] = o.logabs; sign[i] = int8_t(o.sign);
     fsq[i] = o.fsq;
     if (n_det) n_det[i] = o.n_det;

@@ -1,0 +1,442 @@
+// Amplitude side of the local energy on gfx950 (arXiv:2507.19276):
+//   * BDG-RNN / MPS-RNN forward over a batch of rows (Sec. 2.1 Eqs. (9)-(10),
+//     Sec. 2.2 Eq. (12) without the tensor term): per site i the candidates
+//     h_i^s = sum_{j in N(i)} M_ij^s h_j + v_i^s for the four local states,
+//     the conditional P^s = h^T eta h normalised over the states allowed by
+//     the particle-number / S_z mask (Sec. 3, Eqs. (23)-(24)), the phase sign
+//     of w^T h + c, and the carried state h_i^{s_i};
+//   * the cos-RBM correlator (Sec. 2.3, Eq. (15));
+//   * the per-sample local-energy reduction (Eqs. (6), (18), (22)) and the
+//     batch sums of Sec. 2.3.
+//
+// Bond contractions run on MFMA in the transposed form
+//   H_i^T [4chi x rows] = W_i^T [4chi x d_i chi] . X_i^T [d_i chi x rows]
+// so that one wavefront owns 16 rows (the N dimension of a 16x16 MFMA tile)
+// and every lane holds 4 consecutive hidden units of one row and candidate:
+// the epilogue (P^s, mask, log, sign, carry) then needs only two cross-lane
+// exchanges per quantity.  Carried hidden states live in a per-wavefront LDS
+// ring of W = (max parent offset + 1) slots.
+#include "internal.h"
+#include <cmath>
+
+namespace nqs {
+namespace {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+template <typename T> struct V4;
+template <> struct V4<double> { typedef d4 type; };
+template <> struct V4<float> { typedef f4 type; };
+
+__device__ inline d4 mfma(double a, double b, d4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+__device__ inline f4 mfma(float a, float b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+__device__ inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ inline int site_state(uint64_t lo, uint64_t hi, int i) {
+  const int P = 2 * i;
+  const uint64_t w = P < 64 ? (lo >> P) : (hi >> (P - 64));
+  return int(w & 3ull);
+}
+
+__device__ inline bool allowed(int a_prev, int b_prev, int s, int rest, int na, int nb) {
+  const int a = a_prev + (s & 1), b = b_prev + (s >> 1);
+  return a <= na && a + rest >= na && b <= nb && b + rest >= nb;
+}
+
+__device__ inline double tlog(double x) { return log(x); }
+__device__ inline float tlog(float x) { return logf(x); }
+
+// One wavefront = 16 rows.  CH = chi rounded up to 16.
+template <typename T, int CH>
+__global__ __launch_bounds__(256) void k_psi(PsiParams<T> P, const uint64_t* m, int64_t R,
+                                             double* lphi, int8_t* sphi, int rs, int wpb) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  typedef typename V4<T>::type V;
+  constexpr int TPC = CH / 16;     // 16-unit tiles per candidate
+  constexpr int NT = 4 * TPC;      // output tiles (4 candidates)
+  constexpr int KS = CH / 4;       // k-steps per parent
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int j = lane & 15, g = lane >> 4;
+  T* ring = reinterpret_cast<T*>(smem) + size_t(wv) * P.W * 16 * rs;
+  const int64_t tile = int64_t(blockIdx.x) * wpb + wv;
+  const int64_t row = tile * 16 + j;
+  const bool live = row < R;
+  const int64_t rr = live ? row : (R - 1);
+  const uint64_t lo = m[2 * rr], hi = m[2 * rr + 1];
+  double logacc = 0.0;
+  int sgn = 1, ca = 0, cb = 0;
+  bool bad = false;
+  for (int i = 0; i < P.K; ++i) {
+    V acc[NT];
+#pragma unroll
+    for (int ot = 0; ot < NT; ++ot) acc[ot] = V{0, 0, 0, 0};
+    const int e0 = P.pptr[i], e1 = P.pptr[i + 1];
+    const T* A = P.A + P.aoff[i] + lane;
+    for (int e = e0; e < e1; ++e) {
+      const int slot = P.pidx[e] % P.W;
+      const T* rp = ring + (slot * 16 + j) * rs + g;
+      const T* Ae = A + size_t(e - e0) * (KS * NT * 64);
+#pragma unroll 4
+      for (int q = 0; q < KS; ++q) {
+        const T b = rp[4 * q];
+#pragma unroll
+        for (int ot = 0; ot < NT; ++ot) acc[ot] = mfma(Ae[(q * NT + ot) * 64], b, acc[ot]);
+      }
+    }
+    // epilogue: add v, conditional weights P^s summed over the 4 lane groups
+    const T* vi = P.v + size_t(i) * 4 * CH;
+    const T* ei = P.eta + size_t(i) * CH;
+    T ps[4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      T p = 0;
+#pragma unroll
+      for (int t = 0; t < TPC; ++t) {
+        const int u0 = 16 * t + 4 * g;
+        const V vv = *reinterpret_cast<const V*>(vi + s * CH + u0);
+        const V ee = *reinterpret_cast<const V*>(ei + u0);
+        const V x = acc[s * TPC + t] + vv;
+        acc[s * TPC + t] = x;
+        p += ee.x * x.x * x.x + ee.y * x.y * x.y + ee.z * x.z * x.z + ee.w * x.w * x.w;
+      }
+      p += __shfl_xor(p, 16);
+      p += __shfl_xor(p, 32);
+      ps[s] = p;
+    }
+    const int si = site_state(lo, hi, i);
+    const int rest = P.K - 1 - i;
+    T Z = 0;
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+      if (allowed(ca, cb, s, rest, P.na, P.nb)) Z += ps[s];
+    if (!allowed(ca, cb, si, rest, P.na, P.nb)) bad = true;
+    const T psi_ = si == 0 ? ps[0] : si == 1 ? ps[1] : si == 2 ? ps[2] : ps[3];
+    logacc += 0.5 * (double(tlog(psi_)) - double(tlog(Z)));
+    // carried state h_i^{s_i} and the phase sign of w^T h + c
+    V sel[TPC];
+#pragma unroll
+    for (int t = 0; t < TPC; ++t) {
+      sel[t] = acc[t];
+#pragma unroll
+      for (int s = 1; s < 4; ++s)
+        if (si == s) sel[t] = acc[s * TPC + t];
+    }
+    const T* wi = P.w + size_t(i) * CH;
+    T dot = 0;
+#pragma unroll
+    for (int t = 0; t < TPC; ++t) {
+      const V ww = *reinterpret_cast<const V*>(wi + 16 * t + 4 * g);
+      dot += ww.x * sel[t].x + ww.y * sel[t].y + ww.z * sel[t].z + ww.w * sel[t].w;
+    }
+    dot += __shfl_xor(dot, 16);
+    dot += __shfl_xor(dot, 32);
+    dot += P.c[i];
+    if (dot < 0) sgn = -sgn;
+    T* wp = ring + ((i % P.W) * 16 + j) * rs + 4 * g;
+#pragma unroll
+    for (int t = 0; t < TPC; ++t) *reinterpret_cast<V*>(wp + 16 * t) = sel[t];
+    wave_sync();
+    ca += si & 1;
+    cb += si >> 1;
+  }
+  if (live && g == 0) {
+    lphi[row] = bad ? -INFINITY : logacc;
+    sphi[row] = int8_t(bad ? 0 : sgn);
+  }
+}
+
+template <typename T, int CH>
+hipError_t run_psi(const PsiParams<T>& P, const uint64_t* m, int64_t R, double* lphi, int8_t* sphi,
+                   hipStream_t st) {
+  if (R <= 0) return hipSuccess;
+  const int rs = CH + (sizeof(T) == 8 ? 2 : 4);
+  const size_t per_wave = size_t(P.W) * 16 * rs * sizeof(T);
+  int wpb = 4;
+  while (wpb > 1 && per_wave * wpb > 64 * 1024) wpb >>= 1;
+  if (per_wave * wpb > 160 * 1024) return hipErrorInvalidValue;
+  const int64_t tiles = (R + 15) / 16;
+  const int64_t blocks = (tiles + wpb - 1) / wpb;
+  hipLaunchKernelGGL((k_psi<T, CH>), dim3(unsigned(blocks)), dim3(64 * wpb), per_wave * wpb, st, P, m, R,
+                     lphi, sphi, rs, wpb);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t dispatch_psi(const PsiParams<T>& P, const uint64_t* m, int64_t R, double* lphi,
+                        int8_t* sphi, hipStream_t st) {
+  switch (P.chip) {
+    case 16: return run_psi<T, 16>(P, m, R, lphi, sphi, st);
+    case 32: return run_psi<T, 32>(P, m, R, lphi, sphi, st);
+    case 48: return run_psi<T, 48>(P, m, R, lphi, sphi, st);
+    case 64: return run_psi<T, 64>(P, m, R, lphi, sphi, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// cos-RBM correlator
+// ---------------------------------------------------------------------------
+
+__device__ inline bool bit_at(uint64_t lo, uint64_t hi, int P) {
+  return P < 64 ? ((lo >> P) & 1ull) : ((hi >> (P - 64)) & 1ull);
+}
+
+// theta_k(n) = b_k + sum_P W_kP x_P, one thread per (sample, k)
+__global__ void k_corr_theta(CorrParams C, const uint64_t* samples, int64_t N, double* theta) {
+  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= N * C.nh) return;
+  const int64_t n = t / C.nh;
+  const int k = int(t % C.nh);
+  const uint64_t lo = samples[2 * n], hi = samples[2 * n + 1];
+  const int nv = 2 * C.K;
+  double th = C.b[k];
+  for (int P = 0; P < nv; ++P)
+    if (bit_at(lo, hi, P)) th += C.W[size_t(k) * nv + P];
+  theta[t] = th;
+}
+
+__device__ inline double tcos(double x) { return cos(x); }
+__device__ inline float tcos(float x) { return cosf(x); }
+__device__ inline double tabs(double x) { return fabs(x); }
+__device__ inline float tabs(float x) { return fabsf(x); }
+
+// theta(m) = theta(n) + sum_{created P} W_:P - sum_{annihilated P} W_:P; one
+// thread per row; cos and log in precision T, the sum of logs in FP64.
+template <typename T>
+__global__ void k_corr_rows(CorrParams C, const uint64_t* m, const int32_t* owner,
+                            const uint64_t* samples, const double* theta, int64_t R, double* lf,
+                            int8_t* sf) {
+  const int64_t r = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (r >= R) return;
+  const int64_t o = owner[r];
+  const uint64_t mlo = m[2 * r], mhi = m[2 * r + 1];
+  const uint64_t nlo = samples[2 * o], nhi = samples[2 * o + 1];
+  int add[4], rem[4], na = 0, nr = 0;
+  uint64_t x = mlo & ~nlo;
+  while (x && na < 4) { add[na++] = __ffsll((unsigned long long)x) - 1; x &= x - 1; }
+  x = mhi & ~nhi;
+  while (x && na < 4) { add[na++] = 64 + __ffsll((unsigned long long)x) - 1; x &= x - 1; }
+  x = nlo & ~mlo;
+  while (x && nr < 4) { rem[nr++] = __ffsll((unsigned long long)x) - 1; x &= x - 1; }
+  x = nhi & ~mhi;
+  while (x && nr < 4) { rem[nr++] = 64 + __ffsll((unsigned long long)x) - 1; x &= x - 1; }
+  const int nv = 2 * C.K;
+  const double* th0 = theta + o * C.nh;
+  double acc = 0.0;
+  int s = 1;
+  for (int k = 0; k < C.nh; ++k) {
+    double th = th0[k];
+    const double* Wk = C.W + size_t(k) * nv;
+    for (int a = 0; a < na; ++a) th += Wk[add[a]];
+    for (int a = 0; a < nr; ++a) th -= Wk[rem[a]];
+    const T c = tcos(T(th));
+    acc += double(tlog(tabs(c)));
+    if (c < T(0)) s = -s;
+  }
+  lf[r] = acc;
+  sf[r] = int8_t(s);
+}
+
+// direct evaluation for arbitrary ONVs (no owner): theta = b + W x
+__global__ void k_corr_direct(CorrParams C, const uint64_t* m, int64_t R, double* lf, int8_t* sf) {
+  const int64_t r = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (r >= R) return;
+  const uint64_t lo = m[2 * r], hi = m[2 * r + 1];
+  const int nv = 2 * C.K;
+  double acc = 0.0;
+  int s = 1;
+  for (int k = 0; k < C.nh; ++k) {
+    double th = C.b[k];
+    for (int P = 0; P < nv; ++P)
+      if (bit_at(lo, hi, P)) th += C.W[size_t(k) * nv + P];
+    const double c = cos(th);
+    acc += log(fabs(c));
+    if (c < 0) s = -s;
+  }
+  lf[r] = acc;
+  sf[r] = int8_t(s);
+}
+
+// ---------------------------------------------------------------------------
+// reductions
+// ---------------------------------------------------------------------------
+
+__device__ inline double wave_sum(double x) {
+  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
+  return x;
+}
+
+// Per sample n (one wavefront): E_loc(n) = H_nn + sum_rows coef * Psi(m)/Psi(n)
+// and Etilde_num(n) = |f_n|^2 H_nn + f_n sum_rows coef f_m Phi(m)/Phi(n).
+__global__ __launch_bounds__(256) void k_reduce(int64_t N, const int64_t* rowptr, const double* coef,
+                                                const double* lphi, const int8_t* sphi,
+                                                const double* lf, const int8_t* sf,
+                                                const double* hdiag, double* eloc, double* etnum,
+                                                double* logabs, int8_t* sign, double* fsq) {
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t n = int64_t(blockIdx.x) * 4 + wv;
+  if (n >= N) return;
+  const int64_t r0 = rowptr[n], r1 = rowptr[n + 1];
+  const double lpn = lphi[r0], lfn = lf[r0];
+  const int sn = int(sphi[r0]) * int(sf[r0]);
+  double se = 0.0, st = 0.0;
+  for (int64_t r = r0 + 1 + lane; r < r1; r += 64) {
+    const double s = double(int(sphi[r]) * int(sf[r]) * sn);
+    se += coef[r] * s * exp(lphi[r] + lf[r] - lpn - lfn);
+    st += coef[r] * s * exp(lfn + lf[r] + lphi[r] - lpn);
+  }
+  se = wave_sum(se);
+  st = wave_sum(st);
+  if (lane == 0) {
+    const double la = lpn + lfn;
+    const bool valid = sn != 0 && isfinite(la);
+    const double f2 = exp(2.0 * lfn);
+    const double hd = hdiag[n];
+    if (eloc) eloc[n] = valid ? hd + se : NAN;
+    if (etnum) etnum[n] = valid ? f2 * hd + st : NAN;
+    if (logabs) logabs[n] = la;
+    if (sign) sign[n] = int8_t(sn);
+    if (fsq) fsq[n] = f2;
+  }
+}
+
+// Batch sums with weights c_n (NaN local energies are left out and counted):
+// out = {sum c, sum c|f|^2, sum c Etilde_num, E, B, var, n_nan, 0}
+__global__ __launch_bounds__(1024) void k_batch_sums(int64_t N, const double* counts, const double* eloc,
+                                                     const double* etnum, const double* fsq,
+                                                     double* out) {
+  __shared__ double red[3][1024];
+  __shared__ double E_sh;
+  const int tid = threadIdx.x;
+  double sc = 0, sf2 = 0, se = 0, nn = 0;
+  for (int64_t n = tid; n < N; n += 1024) {
+    const double c = counts ? counts[n] : 1.0;
+    if (isnan(eloc[n])) { nn += 1; continue; }
+    sc += c;
+    sf2 += c * fsq[n];
+    se += c * etnum[n];
+  }
+  red[0][tid] = sc; red[1][tid] = sf2; red[2][tid] = se;
+  __syncthreads();
+  for (int o = 512; o > 0; o >>= 1) {
+    if (tid < o)
+      for (int k = 0; k < 3; ++k) red[k][tid] += red[k][tid + o];
+    __syncthreads();
+  }
+  if (tid == 0) E_sh = red[2][0] / red[1][0];
+  const double tsc = red[0][0], tsf = red[1][0], tse = red[2][0];
+  __syncthreads();
+  const double E = E_sh;
+  double sv = 0;
+  for (int64_t n = tid; n < N; n += 1024) {
+    const double c = counts ? counts[n] : 1.0;
+    if (isnan(eloc[n])) continue;
+    const double d = eloc[n] - E;
+    sv += c * fsq[n] * d * d;
+  }
+  __syncthreads();
+  red[0][tid] = sv;
+  red[1][tid] = nn;
+  __syncthreads();
+  for (int o = 512; o > 0; o >>= 1) {
+    if (tid < o) { red[0][tid] += red[0][tid + o]; red[1][tid] += red[1][tid + o]; }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    out[0] = tsc; out[1] = tsf; out[2] = tse; out[3] = E; out[4] = tsf / tsc;
+    out[5] = red[0][0] / tsf; out[6] = red[1][0]; out[7] = 0.0;
+  }
+}
+
+__global__ void k_gather_logpsi(int64_t N, const double* lphi, const int8_t* sphi, const double* lf,
+                                const int8_t* sf, double* logabs, int8_t* sign) {
+  const int64_t n = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (n >= N) return;
+  const double l = lphi[n] + (lf ? lf[n] : 0.0);
+  const int s = int(sphi[n]) * (sf ? int(sf[n]) : 1);
+  if (logabs) logabs[n] = l;
+  if (sign) sign[n] = int8_t(s);
+}
+
+inline unsigned grid_for(int64_t units, int per_block) {
+  return unsigned((units + per_block - 1) / per_block);
+}
+
+}  // namespace
+
+hipError_t launch_psi_f64(const PsiParams<double>& P, const uint64_t* m, int64_t R, double* lphi,
+                          int8_t* sphi, hipStream_t st) {
+  return dispatch_psi<double>(P, m, R, lphi, sphi, st);
+}
+
+hipError_t launch_psi_f32(const PsiParams<float>& P, const uint64_t* m, int64_t R, double* lphi,
+                          int8_t* sphi, hipStream_t st) {
+  return dispatch_psi<float>(P, m, R, lphi, sphi, st);
+}
+
+hipError_t launch_corr_theta(const CorrParams& C, const uint64_t* samples, int64_t N, double* theta,
+                             hipStream_t st) {
+  if (N <= 0 || C.nh <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_corr_theta, dim3(grid_for(N * C.nh, 256)), dim3(256), 0, st, C, samples, N, theta);
+  return hipGetLastError();
+}
+
+hipError_t launch_corr_rows(const CorrParams& C, const uint64_t* m, const int32_t* owner,
+                            const uint64_t* samples, const double* theta, int64_t R, int precision,
+                            double* lf, int8_t* sf, hipStream_t st) {
+  if (R <= 0) return hipSuccess;
+  if (precision == 0)
+    hipLaunchKernelGGL(k_corr_rows<double>, dim3(grid_for(R, 256)), dim3(256), 0, st, C, m, owner, samples,
+                       theta, R, lf, sf);
+  else
+    hipLaunchKernelGGL(k_corr_rows<float>, dim3(grid_for(R, 256)), dim3(256), 0, st, C, m, owner, samples,
+                       theta, R, lf, sf);
+  return hipGetLastError();
+}
+
+hipError_t launch_corr_direct(const CorrParams& C, const uint64_t* m, int64_t R, double* lf, int8_t* sf,
+                              hipStream_t st) {
+  if (R <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_corr_direct, dim3(grid_for(R, 256)), dim3(256), 0, st, C, m, R, lf, sf);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce(int64_t N, const int64_t* rowptr, const double* coef, const double* lphi,
+                         const int8_t* sphi, const double* lf, const int8_t* sf, const double* hdiag,
+                         double* eloc, double* etnum, double* logabs, int8_t* sign, double* fsq,
+                         hipStream_t st) {
+  if (N <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_reduce, dim3(grid_for(N, 4)), dim3(256), 0, st, N, rowptr, coef, lphi, sphi, lf, sf,
+                     hdiag, eloc, etnum, logabs, sign, fsq);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_sums(int64_t N, const double* counts, const double* eloc, const double* etnum,
+                             const double* fsq, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_batch_sums, dim3(1), dim3(1024), 0, st, N, counts, eloc, etnum, fsq, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather_logpsi(int64_t N, const double* lphi, const int8_t* sphi, const double* lf,
+                                const int8_t* sf, double* logabs, int8_t* sign, hipStream_t st) {
+  if (N <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_gather_logpsi, dim3(grid_for(N, 256)), dim3(256), 0, st, N, lphi, sphi, lf, sf,
+                     logabs, sign);
+  return hipGetLastError();
+}
+
+hipError_t launch_psi_bf16(const BF16Params&, const uint64_t*, int64_t, double*, int8_t*, hipStream_t) {
+  return hipErrorNotSupported;
+}
+
+}  // namespace nqs

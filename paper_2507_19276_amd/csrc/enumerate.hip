@@ -1,0 +1,641 @@
+// Hamiltonian side of the semi-stochastic local energy on gfx950:
+// Slater-Condon matrix elements of every connected determinant (Sec. 2.4 and
+// Sec. 3 of arXiv:2507.19276), screening into the deterministic set
+// |H_nm| >= eps (Eq. (20)), integer proposal weights over the remainder,
+// Philox draws from P(m) = q_m / Q (Eq. (21)) and the amplitude row list.
+//
+// Work layout: one wavefront owns a chunk of 64 consecutive ranks of one
+// sample, each lane one rank; the occupied/virtual orbital lists of the
+// sample are built once per wavefront in LDS with ballot + popcount.
+// Fermionic signs come from masked popcounts of the 128-bit occupation.
+//
+// This file is compiled without floating-point contraction: the matrix
+// elements are meant to equal a plain sequential evaluation bit for bit.
+#include "internal.h"
+
+#pragma clang fp contract(off)
+
+namespace nqs {
+namespace {
+
+__device__ inline int lane_id() { return threadIdx.x & 63; }
+
+__device__ inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ inline uint32_t mdiv(uint32_t x, uint64_t m) {
+  return uint32_t((uint64_t(x) * m) >> 32);
+}
+
+// number of occupied spin orbitals with index < P in the 128-bit (lo, hi)
+__device__ inline int occ_below(uint64_t lo, uint64_t hi, int P) {
+  return P < 64 ? __popcll(lo & ((1ull << P) - 1ull))
+                : __popcll(lo) + __popcll(hi & ((1ull << (P - 64)) - 1ull));
+}
+
+__device__ inline void flip(uint64_t& lo, uint64_t& hi, int P) {
+  if (P < 64) lo ^= 1ull << P; else hi ^= 1ull << (P - 64);
+}
+
+__device__ inline bool bit_at(uint64_t lo, uint64_t hi, int P) {
+  return P < 64 ? ((lo >> P) & 1ull) : ((hi >> (P - 64)) & 1ull);
+}
+
+struct Lists {
+  uint8_t oa[64], va[64], ob[64], vb[64];
+  uint8_t occ[128];   // occupied spin orbitals, ascending
+};
+
+// Build the orbital lists of one ONV with the whole wavefront (lane p looks at
+// spatial orbital p).  Returns true when the ONV has exactly (na, nb)
+// electrons and no bit beyond 2K.
+__device__ bool decode_lists(const HamDev& H, uint64_t lo, uint64_t hi, Lists& L) {
+  const int p = lane_id();
+  const bool in = p < H.K;
+  L.oa[p] = 0; L.va[p] = 0; L.ob[p] = 0; L.vb[p] = 0;
+  L.occ[p] = 0; L.occ[p + 64] = 0;
+  wave_sync();
+  const bool xa = in && bit_at(lo, hi, 2 * p);
+  const bool xb = in && bit_at(lo, hi, 2 * p + 1);
+  const uint64_t ma = __ballot(xa), mb = __ballot(xb);
+  const uint64_t lt = __lanemask_lt();
+  const int ra = __popcll(ma & lt), rb = __popcll(mb & lt);
+  if (in) {
+    if (xa) L.oa[ra] = p; else L.va[p - ra] = p;
+    if (xb) L.ob[rb] = p; else L.vb[p - rb] = p;
+    const int base = ra + rb;
+    if (xa) L.occ[base] = 2 * p;
+    if (xb) L.occ[base + (xa ? 1 : 0)] = 2 * p + 1;
+  }
+  wave_sync();
+  const int K2 = 2 * H.K;
+  uint64_t stray_lo = K2 >= 64 ? 0ull : (lo >> K2);
+  uint64_t stray_hi = K2 >= 128 ? 0ull : (K2 >= 64 ? (hi >> (K2 - 64)) : hi);
+  return __popcll(ma) == H.na && __popcll(mb) == H.nb && stray_lo == 0 && stray_hi == 0;
+}
+
+__device__ inline size_t eidx(int K, int p, int q, int r, int s) {
+  return ((size_t(p) * K + q) * K + r) * K + s;
+}
+
+// S(i) = number of pairs (i', j') with i' < i in lexicographic order of i<j<n
+__device__ inline int pair_start(int i, int n) { return i * n - (i * (i + 1)) / 2; }
+
+__device__ inline void unpair(uint32_t p, int n, int& i, int& j) {
+  const float b = 2.0f * n - 1.0f;
+  int ii = int((b - sqrtf(fmaxf(b * b - 8.0f * float(p), 0.0f))) * 0.5f);
+  ii = max(0, min(ii, n - 2));
+  while (ii + 1 <= n - 2 && pair_start(ii + 1, n) <= int(p)) ++ii;
+  while (ii > 0 && pair_start(ii, n) > int(p)) --ii;
+  i = ii;
+  j = int(p) - pair_start(ii, n) + ii + 1;
+}
+
+struct Elem {
+  double H;
+  uint64_t mlo, mhi;
+};
+
+// apply a_I a_J a+_B a+_A in the order a_I, a_J, a+_B, a+_A (I<J, A<B) and
+// return the parity of the sign
+__device__ inline int apply_double(uint64_t& lo, uint64_t& hi, int I, int J, int A, int B) {
+  int g = occ_below(lo, hi, I);
+  flip(lo, hi, I);
+  g += occ_below(lo, hi, J);
+  flip(lo, hi, J);
+  g += occ_below(lo, hi, B);
+  flip(lo, hi, B);
+  g += occ_below(lo, hi, A);
+  flip(lo, hi, A);
+  return g & 1;
+}
+
+// Matrix element H_mn and m for canonical rank r of the sample (lo, hi).
+__device__ Elem element(const HamDev& H, const Lists& L, uint64_t lo, uint64_t hi, uint32_t r) {
+  const int K = H.K;
+  Elem e;
+  if (r < H.off_daa) {
+    // single excitation I -> A of spin sigma: |m> = g a+_A a_I |n>,
+    // H_mn = g (h_AI + sum_{J occ} <AJ||IJ>), J ascending
+    const int sg = r >= H.off_sb ? 1 : 0;
+    const uint32_t t = sg ? r - H.off_sb : r;
+    const int v = sg ? H.vb : H.va;
+    const uint32_t ii = mdiv(t, sg ? H.mg_vb : H.mg_va);
+    const uint32_t aa = t - ii * uint32_t(v);
+    const int i = sg ? L.ob[ii] : L.oa[ii];
+    const int a = sg ? L.vb[aa] : L.va[aa];
+    double acc = H.h[a * K + i];
+    const int ne = H.na + H.nb;
+    for (int k = 0; k < ne; ++k) {
+      const int J = L.occ[k];
+      const int j = J >> 1;
+      const double g1 = H.eri[eidx(K, a, i, j, j)];
+      const double g2 = ((J & 1) == sg) ? H.eri[eidx(K, a, j, j, i)] : 0.0;
+      acc += (g1 - g2);
+    }
+    const int I = 2 * i + sg, A = 2 * a + sg;
+    uint64_t ml = lo, mh = hi;
+    int g = occ_below(ml, mh, I);
+    flip(ml, mh, I);
+    g += occ_below(ml, mh, A);
+    flip(ml, mh, A);
+    e.H = (g & 1) ? -acc : acc;
+    e.mlo = ml; e.mhi = mh;
+    return e;
+  }
+  if (r < H.off_dab) {
+    // same-spin double (i<j) -> (a<b): H_mn = g ((ai|bj) - (aj|bi))
+    const int sg = r >= H.off_dbb ? 1 : 0;
+    const uint32_t t = sg ? r - H.off_dbb : r - H.off_daa;
+    const uint32_t npv = sg ? H.npb_v : H.npa_v;
+    const uint32_t pij = mdiv(t, sg ? H.mg_npb_v : H.mg_npa_v);
+    const uint32_t pab = t - pij * npv;
+    int ii, jj, aa, bb;
+    unpair(pij, sg ? H.nb : H.na, ii, jj);
+    unpair(pab, sg ? H.vb : H.va, aa, bb);
+    const int i = sg ? L.ob[ii] : L.oa[ii];
+    const int j = sg ? L.ob[jj] : L.oa[jj];
+    const int a = sg ? L.vb[aa] : L.va[aa];
+    const int b = sg ? L.vb[bb] : L.va[bb];
+    const double val = H.eri[eidx(K, i, a, j, b)] - H.eri[eidx(K, j, a, i, b)];
+    uint64_t ml = lo, mh = hi;
+    const int g = apply_double(ml, mh, 2 * i + sg, 2 * j + sg, 2 * a + sg, 2 * b + sg);
+    e.H = g ? -val : val;
+    e.mlo = ml; e.mhi = mh;
+    return e;
+  }
+  // opposite-spin double (i alpha, j beta) -> (a alpha, b beta): with the spin
+  // orbitals sorted, <AB||IJ> = +(ai|bj) when the alpha hole and the alpha
+  // particle come first together, -(ai|bj) otherwise
+  const uint32_t t = r - H.off_dab;
+  const uint32_t sa = mdiv(t, H.mg_nsb);
+  const uint32_t sb = t - sa * H.nsb;
+  const uint32_t ii = mdiv(sa, H.mg_va);
+  const uint32_t aa = sa - ii * uint32_t(H.va);
+  const uint32_t jj = mdiv(sb, H.mg_vb);
+  const uint32_t bb = sb - jj * uint32_t(H.vb);
+  const int i = L.oa[ii], a = L.va[aa], j = L.ob[jj], b = L.vb[bb];
+  double val = H.eri[eidx(K, i, a, j, b)];
+  if ((i <= j) != (a <= b)) val = -val;
+  const int Ia = 2 * i, Jb = 2 * j + 1, Aa = 2 * a, Bb = 2 * b + 1;
+  uint64_t ml = lo, mh = hi;
+  const int g = apply_double(ml, mh, min(Ia, Jb), max(Ia, Jb), min(Aa, Bb), max(Aa, Bb));
+  e.H = g ? -val : val;
+  e.mlo = ml; e.mhi = mh;
+  return e;
+}
+
+__device__ inline uint64_t wave_sum_u64(uint64_t x) {
+  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
+  return x;
+}
+
+__device__ inline uint64_t wave_incl_scan_u64(uint64_t x) {
+  const int l = lane_id();
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint64_t y = __shfl_up(x, o);
+    if (l >= o) x += y;
+  }
+  return x;
+}
+
+__device__ inline uint64_t proposal_weight(double absH, int qshift) {
+  return uint64_t(ceil(ldexp(absH, qshift)));
+}
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon et al., SC'11)
+// ---------------------------------------------------------------------------
+__device__ inline void philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0,
+                              uint32_t k1, uint32_t out[4]) {
+#pragma unroll
+  for (int rnd = 0; rnd < 10; ++rnd) {
+    if (rnd) { k0 += 0x9E3779B9u; k1 += 0xBB67AE85u; }
+    const uint32_t lo0 = 0xD2511F53u * c0, hi0 = __umulhi(0xD2511F53u, c0);
+    const uint32_t lo1 = 0xCD9E8D57u * c2, hi1 = __umulhi(0xCD9E8D57u, c2);
+    const uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+    c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;
+  }
+  out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+// floor(U * Q / 2^128) with U = (u3 u2 u1 u0) in 32-bit words, Q < 2^60
+__device__ inline uint64_t scaled_draw(const uint32_t U[4], uint64_t Q) {
+  const uint64_t ulo = uint64_t(U[0]) | (uint64_t(U[1]) << 32);
+  const uint64_t uhi = uint64_t(U[2]) | (uint64_t(U[3]) << 32);
+  const uint64_t p_lo_hi = __umul64hi(ulo, Q);          // floor(ulo * Q / 2^64)
+  const uint64_t a_lo = uhi * Q, a_hi = __umul64hi(uhi, Q);
+  const uint64_t s = a_lo + p_lo_hi;
+  return a_hi + (s < a_lo ? 1ull : 0ull);
+}
+
+// ---------------------------------------------------------------------------
+// kernels
+// ---------------------------------------------------------------------------
+
+__global__ void k_validate(const uint64_t* samples, int64_t N, int K, int na, int nb, int* bad) {
+  const int64_t n = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (n >= N) return;
+  const uint64_t lo = samples[2 * n], hi = samples[2 * n + 1];
+  int a = 0, b = 0;
+  for (int p = 0; p < K; ++p) {
+    a += bit_at(lo, hi, 2 * p) ? 1 : 0;
+    b += bit_at(lo, hi, 2 * p + 1) ? 1 : 0;
+  }
+  const int K2 = 2 * K;
+  const uint64_t sl = K2 >= 64 ? 0ull : (lo >> K2);
+  const uint64_t sh = K2 >= 128 ? 0ull : (K2 >= 64 ? (hi >> (K2 - 64)) : hi);
+  if (a != na || b != nb || sl || sh) *bad = 1;
+}
+
+// Pass 1: per chunk the ballot of deterministic ranks and the inclusive
+// (within segment) prefix of remainder weights; per segment the totals.
+__global__ __launch_bounds__(256) void k_enum_count(HamDev H, EnumGeom G, const uint64_t* samples,
+                                                   int64_t N, double eps, int qshift,
+                                                   uint64_t* masks, uint64_t* qpref, uint64_t* segq,
+                                                   uint32_t* segd) {
+  __shared__ Lists lists[4];
+  const int wv = threadIdx.x >> 6, lane = lane_id();
+  const int64_t unit = int64_t(blockIdx.x) * 4 + wv;
+  if (unit >= N * G.S) return;
+  const int64_t n = unit / G.S;
+  const int s = int(unit % G.S);
+  const uint64_t lo = samples[2 * n], hi = samples[2 * n + 1];
+  Lists& L = lists[wv];
+  const bool ok = decode_lists(H, lo, hi, L);
+  const int c0 = s * G.cps, c1 = min(c0 + G.cps, G.nchunks);
+  uint64_t runq = 0;
+  uint32_t rund = 0;
+  for (int c = c0; c < c1; ++c) {
+    const uint32_t r = uint32_t(c) * 64u + uint32_t(lane);
+    double hv = 0.0;
+    if (ok && r < H.n_conn) hv = element(H, L, lo, hi, r).H;
+    const double ah = fabs(hv);
+    const bool det = hv != 0.0 && ah >= eps;
+    const uint64_t q = (hv != 0.0 && !det) ? proposal_weight(ah, qshift) : 0ull;
+    const uint64_t mask = __ballot(det);
+    runq += wave_sum_u64(q);
+    rund += uint32_t(__popcll(mask));
+    if (lane == 0) {
+      masks[n * G.nchunks + c] = mask;
+      qpref[n * G.nchunks + c] = runq;
+    }
+  }
+  if (lane == 0) {
+    segq[n * G.S + s] = runq;
+    segd[n * G.S + s] = rund;
+  }
+}
+
+// Per sample: segment totals -> exclusive segment offsets (in place), Q_n, |D_n|.
+__global__ void k_sample_scan(EnumGeom G, int64_t N, uint64_t* segq, uint32_t* segd, uint64_t* Qn,
+                              int64_t* Dn) {
+  const int64_t n = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (n >= N) return;
+  uint64_t q = 0;
+  int64_t d = 0;
+  for (int s = 0; s < G.S; ++s) {
+    const uint64_t tq = segq[n * G.S + s];
+    const uint32_t td = segd[n * G.S + s];
+    segq[n * G.S + s] = q;
+    segd[n * G.S + s] = uint32_t(d);
+    q += tq;
+    d += td;
+  }
+  Qn[n] = q;
+  Dn[n] = d;
+}
+
+constexpr int kMaxDraws = 1024;
+
+// Draws of one sample per workgroup: Philox -> r in [0, Q) -> segment ->
+// chunk (binary search over the inclusive prefixes) -> lane (wavefront scan of
+// the chunk's weights); then sort the drawn ranks and merge duplicates.
+__global__ __launch_bounds__(256) void k_draw(HamDev H, EnumGeom G, const uint64_t* samples, int64_t N,
+                                              double eps, int qshift, int n_eps, DrawKeys keys,
+                                              const uint64_t* qpref, const uint64_t* segq_off,
+                                              const uint64_t* Qn, int32_t* urank, double* ucoef,
+                                              uint64_t* um, int64_t* Un) {
+  __shared__ Lists L;
+  __shared__ int32_t chunk_of[kMaxDraws];
+  __shared__ uint64_t rin_of[kMaxDraws];
+  __shared__ int32_t rank_of[kMaxDraws];
+  __shared__ int32_t idx_of[kMaxDraws];
+  __shared__ double h_of[kMaxDraws];
+  __shared__ uint64_t q_of[kMaxDraws];
+  __shared__ uint64_t mlo_of[kMaxDraws], mhi_of[kMaxDraws];
+  const int64_t n = blockIdx.x;
+  const int tid = threadIdx.x, wv = tid >> 6, lane = lane_id();
+  const uint64_t Q = Qn[n];
+  if (Q == 0 || n_eps == 0) {
+    if (tid == 0) Un[n] = 0;
+    return;
+  }
+  const uint64_t lo = samples[2 * n], hi = samples[2 * n + 1];
+  if (wv == 0) decode_lists(H, lo, hi, L);
+  __syncthreads();
+  const uint64_t* qp = qpref + n * G.nchunks;
+  for (int k = tid; k < n_eps; k += blockDim.x) {
+    uint32_t U[4];
+    philox(keys.sample_base + uint32_t(n), uint32_t(k), keys.ctr2, keys.ctr3, keys.key0, keys.key1, U);
+    const uint64_t r = scaled_draw(U, Q);
+    int s = 0;
+    while (s + 1 < G.S && segq_off[n * G.S + s + 1] <= r) ++s;
+    const uint64_t rr = r - segq_off[n * G.S + s];
+    const int c0 = s * G.cps, c1 = min(c0 + G.cps, G.nchunks);
+    int lo_c = c0, hi_c = c1 - 1;          // first chunk with inclusive prefix > rr
+    while (lo_c < hi_c) {
+      const int mid = (lo_c + hi_c) >> 1;
+      if (qp[mid] > rr) hi_c = mid; else lo_c = mid + 1;
+    }
+    chunk_of[k] = lo_c;
+    rin_of[k] = rr - (lo_c > c0 ? qp[lo_c - 1] : 0ull);
+    rank_of[k] = 0;      // overwritten below; keeps every entry defined
+    h_of[k] = 0.0;
+    q_of[k] = 1;
+    mlo_of[k] = lo;
+    mhi_of[k] = hi;
+  }
+  __syncthreads();
+  for (int k = wv; k < n_eps; k += 4) {
+    const int c = chunk_of[k];
+    const uint32_t r = uint32_t(c) * 64u + uint32_t(lane);
+    Elem e{0.0, 0, 0};
+    if (r < H.n_conn) e = element(H, L, lo, hi, r);
+    const double ah = fabs(e.H);
+    const bool det = e.H != 0.0 && ah >= eps;
+    const uint64_t q = (e.H != 0.0 && !det) ? proposal_weight(ah, qshift) : 0ull;
+    const uint64_t incl = wave_incl_scan_u64(q);
+    const uint64_t hit = __ballot(incl > rin_of[k] && q > 0);
+    const int pick = __ffsll((unsigned long long)hit) - 1;   // lowest lane: first prefix exceeding r
+    if (lane == pick) {
+      rank_of[k] = int32_t(r);
+      h_of[k] = e.H;
+      q_of[k] = q;
+      mlo_of[k] = e.mlo;
+      mhi_of[k] = e.mhi;
+    }
+  }
+  __syncthreads();
+  // sort (rank, draw index) by rank: bitonic sort over the next power of two
+  int P2 = 1;
+  while (P2 < n_eps) P2 <<= 1;
+  for (int k = tid; k < P2; k += blockDim.x) {
+    idx_of[k] = k;
+    if (k >= n_eps) rank_of[k] = 0x7fffffff;
+  }
+  __syncthreads();
+  for (int size = 2; size <= P2; size <<= 1) {
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      for (int k = tid; k < P2; k += blockDim.x) {
+        const int o = k ^ stride;
+        if (o > k) {
+          const bool up = (k & size) == 0;
+          const int32_t a = rank_of[k], b = rank_of[o];
+          const int32_t ia = idx_of[k], ib = idx_of[o];
+          const bool swap = up ? (a > b || (a == b && ia > ib)) : (a < b || (a == b && ia < ib));
+          if (swap) {
+            rank_of[k] = b; rank_of[o] = a;
+            idx_of[k] = ib; idx_of[o] = ia;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  if (tid == 0) {
+    int64_t u = 0;
+    const double Qd = double(Q), nd = double(n_eps);
+    int k = 0;
+    while (k < n_eps) {
+      int k2 = k;
+      while (k2 < n_eps && rank_of[k2] == rank_of[k]) ++k2;
+      const int d = idx_of[k];
+      const double w = h_of[d] * (Qd / (double(q_of[d]) * nd));
+      urank[n * n_eps + u] = rank_of[k];
+      ucoef[n * n_eps + u] = double(k2 - k) * w;
+      um[2 * (n * n_eps + u)] = mlo_of[d];
+      um[2 * (n * n_eps + u) + 1] = mhi_of[d];
+      ++u;
+      k = k2;
+    }
+    Un[n] = u;
+  }
+}
+
+// rowptr[n] = sum_{n' < n} (1 + |D_n'| + U_n'), single workgroup of 1024 threads
+__global__ __launch_bounds__(1024) void k_row_counts(int64_t N, const int64_t* Dn, const int64_t* Un,
+                                                     int64_t* rowptr) {
+  __shared__ int64_t part[1024];
+  __shared__ int64_t carry;
+  const int tid = threadIdx.x;
+  if (tid == 0) carry = 0;
+  __syncthreads();
+  for (int64_t base = 0; base < N; base += 1024) {
+    const int64_t n = base + tid;
+    const int64_t v = n < N ? 1 + Dn[n] + Un[n] : 0;
+    part[tid] = v;
+    __syncthreads();
+    for (int o = 1; o < 1024; o <<= 1) {
+      const int64_t y = tid >= o ? part[tid - o] : 0;
+      __syncthreads();
+      part[tid] += y;
+      __syncthreads();
+    }
+    if (n < N) rowptr[n] = carry + part[tid] - v;
+    __syncthreads();
+    if (tid == 1023) carry += part[1023];
+    __syncthreads();
+  }
+  if (tid == 0) rowptr[N] = carry;
+}
+
+// Pass 2: write the rows.  Unit (n, s) writes the deterministic rows of its
+// segment in rank order; segment 0 also writes the sample's own row and its
+// unique drawn rows.
+__global__ __launch_bounds__(256) void k_fill(HamDev H, EnumGeom G, const uint64_t* samples, int64_t N,
+                                              const uint64_t* masks, const uint32_t* segd_off,
+                                              const int64_t* rowptr, const int64_t* Dn,
+                                              const int64_t* Un, const int32_t* urank,
+                                              const double* ucoef, const uint64_t* um, int n_eps,
+                                              Rows rows) {
+  __shared__ Lists lists[4];
+  const int wv = threadIdx.x >> 6, lane = lane_id();
+  const int64_t unit = int64_t(blockIdx.x) * 4 + wv;
+  if (unit >= N * G.S) return;
+  const int64_t n = unit / G.S;
+  const int s = int(unit % G.S);
+  const uint64_t lo = samples[2 * n], hi = samples[2 * n + 1];
+  Lists& L = lists[wv];
+  decode_lists(H, lo, hi, L);
+  const int64_t r0 = rowptr[n];
+  int64_t pos = r0 + 1 + segd_off[n * G.S + s];
+  const int c0 = s * G.cps, c1 = min(c0 + G.cps, G.nchunks);
+  const uint64_t lt = __lanemask_lt();
+  for (int cb = c0; cb < c1; cb += 64) {
+    const int cl = cb + lane;
+    const uint64_t mk = cl < c1 ? masks[n * G.nchunks + cl] : 0ull;
+    uint64_t nz = __ballot(mk != 0ull);
+    while (nz) {
+      const int b = __ffsll((unsigned long long)nz) - 1;
+      nz &= nz - 1;
+      const uint64_t mask = __shfl(mk, b);
+      const uint32_t r = uint32_t(cb + b) * 64u + uint32_t(lane);
+      if ((mask >> lane) & 1ull) {
+        const Elem e = element(H, L, lo, hi, r);
+        const int64_t at = pos + __popcll(mask & lt);
+        rows.m[2 * at] = e.mlo;
+        rows.m[2 * at + 1] = e.mhi;
+        rows.coef[at] = e.H;
+        rows.owner[at] = int32_t(n);
+        rows.rank[at] = int64_t(r);
+      }
+      pos += __popcll(mask);
+    }
+  }
+  if (s == 0) {
+    if (lane == 0) {
+      rows.m[2 * r0] = lo;
+      rows.m[2 * r0 + 1] = hi;
+      rows.coef[r0] = 0.0;
+      rows.owner[r0] = int32_t(n);
+      rows.rank[r0] = -1;
+    }
+    const int64_t u = Un[n];
+    const int64_t d0 = r0 + 1 + Dn[n];
+    for (int64_t t = lane; t < u; t += 64) {
+      const int64_t at = d0 + t;
+      rows.m[2 * at] = um[2 * (n * n_eps + t)];
+      rows.m[2 * at + 1] = um[2 * (n * n_eps + t) + 1];
+      rows.coef[at] = ucoef[n * n_eps + t];
+      rows.owner[at] = int32_t(n);
+      rows.rank[at] = urank[n * n_eps + t];
+    }
+  }
+}
+
+// H_nn = e_core + sum_P h_PP + 1/2 sum_{P,Q occ} <PQ||PQ>, one thread per
+// sample, ascending spin orbitals (the order of the plain definition)
+__global__ void k_diag(HamDev H, const uint64_t* samples, int64_t N, double* hdiag) {
+  const int64_t n = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (n >= N) return;
+  const uint64_t lo = samples[2 * n], hi = samples[2 * n + 1];
+  const int K = H.K, K2 = 2 * K;
+  double d1 = 0.0;
+  for (int P = 0; P < K2; ++P)
+    if (bit_at(lo, hi, P)) d1 += H.h[(P >> 1) * K + (P >> 1)];
+  double d2 = 0.0;
+  for (int P = 0; P < K2; ++P) {
+    if (!bit_at(lo, hi, P)) continue;
+    const int p = P >> 1;
+    for (int Q = 0; Q < K2; ++Q) {
+      if (!bit_at(lo, hi, Q)) continue;
+      const int q = Q >> 1;
+      const double g1 = H.eri[eidx(K, p, p, q, q)];
+      const double g2 = ((P & 1) == (Q & 1)) ? H.eri[eidx(K, p, q, q, p)] : 0.0;
+      d2 += (g1 - g2);
+    }
+  }
+  hdiag[n] = H.ecore + d1 + 0.5 * d2;
+}
+
+// every connected determinant of every sample (Hamiltonian-engine entry point)
+__global__ __launch_bounds__(256) void k_connected(HamDev H, const uint64_t* samples, int64_t N,
+                                                   int nchunks, uint64_t* m_out, double* h_out) {
+  __shared__ Lists lists[4];
+  const int wv = threadIdx.x >> 6, lane = lane_id();
+  const int64_t unit = int64_t(blockIdx.x) * 4 + wv;
+  if (unit >= N * nchunks) return;
+  const int64_t n = unit / nchunks;
+  const int c = int(unit % nchunks);
+  const uint64_t lo = samples[2 * n], hi = samples[2 * n + 1];
+  Lists& L = lists[wv];
+  const bool ok = decode_lists(H, lo, hi, L);
+  const uint32_t r = uint32_t(c) * 64u + uint32_t(lane);
+  if (r >= H.n_conn) return;
+  Elem e{0.0, 0, 0};
+  if (ok) e = element(H, L, lo, hi, r);
+  const int64_t at = n * int64_t(H.n_conn) + r;
+  if (m_out) {
+    m_out[2 * at] = e.mlo;
+    m_out[2 * at + 1] = e.mhi;
+  }
+  if (h_out) h_out[at] = e.H;
+}
+
+inline unsigned grid_for(int64_t units, int per_block) {
+  return unsigned((units + per_block - 1) / per_block);
+}
+
+}  // namespace
+
+hipError_t launch_validate(const uint64_t* samples, int64_t N, int K, int na, int nb, int* bad,
+                           hipStream_t st) {
+  if (N <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_validate, dim3(grid_for(N, 256)), dim3(256), 0, st, samples, N, K, na, nb, bad);
+  return hipGetLastError();
+}
+
+hipError_t launch_enum_count(const HamDev& H, const EnumGeom& G, const uint64_t* samples, int64_t N,
+                             double eps, int qshift, uint64_t* masks, uint64_t* qpref, uint64_t* segq,
+                             uint32_t* segd, hipStream_t st) {
+  if (N <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_enum_count, dim3(grid_for(N * G.S, 4)), dim3(256), 0, st, H, G, samples, N, eps,
+                     qshift, masks, qpref, segq, segd);
+  return hipGetLastError();
+}
+
+hipError_t launch_sample_scan(const EnumGeom& G, int64_t N, uint64_t* segq, uint32_t* segd,
+                              uint64_t* Qn, int64_t* Dn, hipStream_t st) {
+  if (N <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_sample_scan, dim3(grid_for(N, 256)), dim3(256), 0, st, G, N, segq, segd, Qn, Dn);
+  return hipGetLastError();
+}
+
+hipError_t launch_draw(const HamDev& H, const EnumGeom& G, const uint64_t* samples, int64_t N,
+                       double eps, int qshift, int n_eps, DrawKeys keys, const uint64_t* qpref,
+                       const uint64_t* segq_off, const uint64_t* Qn, int32_t* urank, double* ucoef,
+                       uint64_t* um, int64_t* Un, hipStream_t st) {
+  if (N <= 0) return hipSuccess;
+  if (n_eps > kMaxDraws) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_draw, dim3(unsigned(N)), dim3(256), 0, st, H, G, samples, N, eps, qshift, n_eps,
+                     keys, qpref, segq_off, Qn, urank, ucoef, um, Un);
+  return hipGetLastError();
+}
+
+hipError_t launch_row_counts(int64_t N, const int64_t* Dn, const int64_t* Un, int64_t* rowptr,
+                             hipStream_t st) {
+  hipLaunchKernelGGL(k_row_counts, dim3(1), dim3(1024), 0, st, N, Dn, Un, rowptr);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill(const HamDev& H, const EnumGeom& G, const uint64_t* samples, int64_t N,
+                       const uint64_t* masks, const uint32_t* segd_off, const int64_t* rowptr,
+                       const int64_t* Dn, const int64_t* Un, const int32_t* urank, const double* ucoef,
+                       const uint64_t* um, int n_eps, Rows rows, hipStream_t st) {
+  if (N <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill, dim3(grid_for(N * G.S, 4)), dim3(256), 0, st, H, G, samples, N, masks,
+                     segd_off, rowptr, Dn, Un, urank, ucoef, um, n_eps, rows);
+  return hipGetLastError();
+}
+
+hipError_t launch_diag(const HamDev& H, const uint64_t* samples, int64_t N, double* hdiag,
+                       hipStream_t st) {
+  if (N <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_diag, dim3(grid_for(N, 128)), dim3(128), 0, st, H, samples, N, hdiag);
+  return hipGetLastError();
+}
+
+hipError_t launch_connected(const HamDev& H, const uint64_t* samples, int64_t N, uint64_t* m_out,
+                            double* h_out, hipStream_t st) {
+  if (N <= 0) return hipSuccess;
+  const int nchunks = int((H.n_conn + 63) / 64);
+  hipLaunchKernelGGL(k_connected, dim3(grid_for(N * nchunks, 4)), dim3(256), 0, st, H, samples, N,
+                     nchunks, m_out, h_out);
+  return hipGetLastError();
+}
+
+}  // namespace nqs

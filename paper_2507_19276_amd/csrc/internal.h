@@ -1,0 +1,131 @@
+// Internal declarations shared by the HIP kernels and the host runtime of
+// libnqs.  Nothing here is part of the C ABI (include/nqs.h).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace nqs {
+
+constexpr int kWave = 64;
+
+// Hamiltonian of one instance as the kernels see it.  Ranks of the connected
+// determinants of a sample run over five blocks (alpha singles, beta
+// singles, alpha-alpha doubles, beta-beta doubles, alpha-beta doubles); the
+// block sizes depend only on (K, n_alpha, n_beta), so every sample of an
+// instance has the same rank space [0, n_conn).
+struct HamDev {
+  const double* h;     // [K][K]
+  const double* eri;   // [K][K][K][K] chemist (pq|rs), exactly 8-fold symmetric
+  double ecore;
+  int K, na, nb, va, vb;                 // va = K - na, vb = K - nb
+  uint32_t off_sb, off_daa, off_dbb, off_dab, n_conn;
+  uint32_t npa_v, npb_v, nsb;            // C(va,2), C(vb,2), nb*vb
+  // ceil(2^32 / d) for exact division q = (x * m) >> 32 of the operands the
+  // unranking meets (x * d < 2^32 holds for every K <= 64, checked on the host)
+  uint64_t mg_va, mg_vb, mg_npa_v, mg_npb_v, mg_nsb;
+};
+
+// Geometry of the chunked enumeration: a chunk is 64 consecutive ranks of one
+// sample (one wavefront); the chunks of a sample are split into S contiguous
+// segments processed by different wavefronts.
+struct EnumGeom {
+  int nchunks;   // ceil(n_conn / 64)
+  int S;         // segments per sample
+  int cps;       // chunks per segment
+};
+
+struct DrawKeys {
+  uint32_t key0, key1;       // Philox key (seed lo, hi)
+  uint32_t ctr2, ctr3;       // stream id lo, hi
+  uint32_t sample_base;
+};
+
+// Ansatz parameters in kernel layouts for one precision T (double or float).
+// chip = chi rounded up to 16; padded entries are zero so they never change
+// a result.
+template <typename T>
+struct PsiParams {
+  int K, chi, chip, na, nb, W;   // W = ring slots = max parent offset + 1
+  const int* pptr;               // [K+1]
+  const int* pidx;               // [sum d]
+  const T* A;                    // MFMA A operands, see pack layout in runtime.cpp
+  const int64_t* aoff;           // [K] element offset of site i in A
+  const T* v;                    // [K][4][chip]
+  const T* eta;                  // [K][chip]
+  const T* w;                    // [K][chip]
+  const T* c;                    // [K]
+};
+
+struct BF16Params {
+  int K, chi, chip, na, nb, W;
+  const int* pptr;
+  const int* pidx;
+  const uint16_t* A;             // bf16 A operands (16x16x32 layout)
+  const int64_t* aoff;
+  const float* v;                // [K][4][chip]
+  const float* eta;              // [K][chip]
+  const float* w;                // [K][chip]
+  const float* c;                // [K]
+};
+
+struct CorrParams {
+  int K, nh;
+  const double* b;   // [nh]
+  const double* W;   // [nh][2K]
+};
+
+// Row list of one local-energy call (structure of arrays).
+struct Rows {
+  uint64_t* m;       // [R][2]
+  double* coef;      // [R]
+  int32_t* owner;    // [R]
+  int64_t* rank;     // [R]   (-1 for the sample's own row)
+};
+
+// ---- launchers (enumerate.hip) ----------------------------------------
+hipError_t launch_validate(const uint64_t* samples, int64_t N, int K, int na, int nb, int* bad,
+                           hipStream_t st);
+hipError_t launch_enum_count(const HamDev& H, const EnumGeom& G, const uint64_t* samples, int64_t N,
+                             double eps, int qshift, uint64_t* masks, uint64_t* qpref, uint64_t* segq,
+                             uint32_t* segd, hipStream_t st);
+hipError_t launch_sample_scan(const EnumGeom& G, int64_t N, uint64_t* segq, uint32_t* segd,
+                              uint64_t* Qn, int64_t* Dn, hipStream_t st);
+hipError_t launch_draw(const HamDev& H, const EnumGeom& G, const uint64_t* samples, int64_t N,
+                       double eps, int qshift, int n_eps, DrawKeys keys, const uint64_t* qpref,
+                       const uint64_t* segq_off, const uint64_t* Qn, int32_t* urank, double* ucoef,
+                       uint64_t* um, int64_t* Un, hipStream_t st);
+hipError_t launch_row_counts(int64_t N, const int64_t* Dn, const int64_t* Un, int64_t* rowptr,
+                             hipStream_t st);
+hipError_t launch_fill(const HamDev& H, const EnumGeom& G, const uint64_t* samples, int64_t N,
+                       const uint64_t* masks, const uint32_t* segd_off, const int64_t* rowptr,
+                       const int64_t* Dn, const int64_t* Un, const int32_t* urank, const double* ucoef,
+                       const uint64_t* um, int n_eps, Rows rows, hipStream_t st);
+hipError_t launch_diag(const HamDev& H, const uint64_t* samples, int64_t N, double* hdiag,
+                       hipStream_t st);
+hipError_t launch_connected(const HamDev& H, const uint64_t* samples, int64_t N, uint64_t* m_out,
+                            double* h_out, hipStream_t st);
+
+// ---- launchers (amplitude.hip) -----------------------------------------
+hipError_t launch_psi_f64(const PsiParams<double>& P, const uint64_t* m, int64_t R, double* lphi,
+                          int8_t* sphi, hipStream_t st);
+hipError_t launch_psi_f32(const PsiParams<float>& P, const uint64_t* m, int64_t R, double* lphi,
+                          int8_t* sphi, hipStream_t st);
+hipError_t launch_psi_bf16(const BF16Params& P, const uint64_t* m, int64_t R, double* lphi,
+                           int8_t* sphi, hipStream_t st);
+hipError_t launch_corr_theta(const CorrParams& C, const uint64_t* samples, int64_t N, double* theta,
+                             hipStream_t st);
+hipError_t launch_corr_rows(const CorrParams& C, const uint64_t* m, const int32_t* owner,
+                            const uint64_t* samples, const double* theta, int64_t R, int precision,
+                            double* lf, int8_t* sf, hipStream_t st);
+hipError_t launch_corr_direct(const CorrParams& C, const uint64_t* m, int64_t R, double* lf, int8_t* sf,
+                              hipStream_t st);
+hipError_t launch_reduce(int64_t N, const int64_t* rowptr, const double* coef, const double* lphi,
+                         const int8_t* sphi, const double* lf, const int8_t* sf, const double* hdiag,
+                         double* eloc, double* etnum, double* logabs, int8_t* sign, double* fsq,
+                         hipStream_t st);
+hipError_t launch_batch_sums(int64_t N, const double* counts, const double* eloc, const double* etnum,
+                             const double* fsq, double* out /*[8]*/, hipStream_t st);
+hipError_t launch_gather_logpsi(int64_t N, const double* lphi, const int8_t* sphi, const double* lf,
+                                const int8_t* sf, double* logabs, int8_t* sign, hipStream_t st);
+
+}  // namespace nqs

@@ -1,0 +1,761 @@
+// Host runtime and C ABI of libnqs (include/nqs.h): contexts with a device
+// workspace pool, resident Hamiltonian instances and ansatz parameter
+// layouts, and the orchestration of the local-energy pipeline
+// (enumerate -> screen -> draw -> rows -> amplitudes -> reduce) on one
+// HIP stream.
+#include "nqs.h"
+#include "internal.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
+
+using namespace nqs;
+
+namespace {
+
+thread_local std::string g_err;
+
+nqs_status fail(nqs_status code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+#define HIPCHK(expr)                                                                         \
+  do {                                                                                       \
+    hipError_t _e = (expr);                                                                  \
+    if (_e != hipSuccess)                                                                    \
+      return fail(NQS_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(_e));               \
+  } while (0)
+
+struct DeviceGuard {
+  int prev = -1;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (prev != dev) (void)hipSetDevice(dev);
+  }
+  ~DeviceGuard() {
+    int cur = -1;
+    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+  }
+};
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// context and workspace pool
+// ---------------------------------------------------------------------------
+struct nqs_ctx {
+  int device = 0;
+  std::mutex mu;
+  std::multimap<size_t, void*> free_blocks;   // cached blocks by size
+  std::map<void*, size_t> sizes;              // every block we own
+  size_t in_use = 0, cached = 0;
+  int64_t fail_at = 0;                        // test hook: k-th acquire fails
+
+  void* acquire(size_t bytes) {
+    bytes = std::max<size_t>(256, (bytes + 255) & ~size_t(255));
+    std::lock_guard<std::mutex> lk(mu);
+    if (fail_at > 0 && --fail_at == 0) return nullptr;
+    auto it = free_blocks.lower_bound(bytes);
+    if (it != free_blocks.end() && it->first <= bytes * 2) {
+      void* p = it->second;
+      size_t sz = it->first;
+      free_blocks.erase(it);
+      cached -= sz;
+      in_use += sz;
+      return p;
+    }
+    void* p = nullptr;
+    if (hipMalloc(&p, bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      // release the cache and retry once
+      for (auto& kv : free_blocks) { (void)hipFree(kv.second); sizes.erase(kv.second); }
+      free_blocks.clear();
+      cached = 0;
+      if (hipMalloc(&p, bytes) != hipSuccess) { (void)hipGetLastError(); return nullptr; }
+    }
+    sizes[p] = bytes;
+    in_use += bytes;
+    return p;
+  }
+  void release(void* p) {
+    if (!p) return;
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = sizes.find(p);
+    if (it == sizes.end()) return;
+    in_use -= it->second;
+    cached += it->second;
+    free_blocks.emplace(it->second, p);
+  }
+  ~nqs_ctx() {
+    for (auto& kv : sizes) (void)hipFree(kv.first);
+  }
+};
+
+namespace {
+
+// Workspace of one call: blocks return to the pool when the call ends (after
+// the call has synchronised its stream).
+struct Scratch {
+  nqs_ctx* ctx;
+  std::vector<void*> blocks;
+  bool oom = false;
+  explicit Scratch(nqs_ctx* c) : ctx(c) {}
+  template <typename T>
+  T* get(size_t count) {
+    void* p = ctx->acquire(std::max<size_t>(count, 1) * sizeof(T));
+    if (!p) { oom = true; return nullptr; }
+    blocks.push_back(p);
+    return static_cast<T*>(p);
+  }
+  ~Scratch() { for (void* p : blocks) ctx->release(p); }
+};
+
+uint64_t magic(uint64_t d) { return d == 0 ? 0 : ((uint64_t(1) << 32) + d - 1) / d; }
+
+int64_t choose2(int64_t n) { return n < 2 ? 0 : n * (n - 1) / 2; }
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// instance
+// ---------------------------------------------------------------------------
+struct nqs_instance {
+  nqs_ctx* ctx = nullptr;
+  int K = 0, na = 0, nb = 0;
+  double ecore = 0;
+  double* d_h = nullptr;
+  double* d_eri = nullptr;
+  HamDev H{};
+  ~nqs_instance() {
+    if (d_h) (void)hipFree(d_h);
+    if (d_eri) (void)hipFree(d_eri);
+  }
+};
+
+// ---------------------------------------------------------------------------
+// ansatz
+// ---------------------------------------------------------------------------
+template <typename T>
+struct PsiLayout {
+  T* A = nullptr;
+  int64_t* aoff = nullptr;
+  T* v = nullptr;
+  T* eta = nullptr;
+  T* w = nullptr;
+  T* c = nullptr;
+  void free_all() {
+    for (void* p : {(void*)A, (void*)aoff, (void*)v, (void*)eta, (void*)w, (void*)c})
+      if (p) (void)hipFree(p);
+    A = nullptr; aoff = nullptr; v = eta = w = c = nullptr;
+  }
+};
+
+struct nqs_ansatz {
+  nqs_ctx* ctx = nullptr;
+  int K = 0, na = 0, nb = 0, chi = 0, chip = 0, nh = 0, W = 1;
+  std::vector<int32_t> pptr, pidx;
+  std::vector<int64_t> offM, offV, offEta, offW, offC;
+  int64_t offB = 0, offWc = 0, n_params = 0;
+  int* d_pptr = nullptr;
+  int* d_pidx = nullptr;
+  bool bound = false;
+  PsiLayout<double> L64;
+  PsiLayout<float> L32;
+  uint16_t* bfA = nullptr;
+  int64_t* bfAoff = nullptr;
+  double* d_cb = nullptr;   // correlator b
+  double* d_cW = nullptr;   // correlator W
+  ~nqs_ansatz() {
+    L64.free_all();
+    L32.free_all();
+    for (void* p : {(void*)d_pptr, (void*)d_pidx, (void*)bfA, (void*)bfAoff, (void*)d_cb, (void*)d_cW})
+      if (p) (void)hipFree(p);
+  }
+  template <typename T>
+  PsiParams<T> params(const PsiLayout<T>& L) const {
+    PsiParams<T> P;
+    P.K = K; P.chi = chi; P.chip = chip; P.na = na; P.nb = nb; P.W = W;
+    P.pptr = d_pptr; P.pidx = d_pidx;
+    P.A = L.A; P.aoff = L.aoff; P.v = L.v; P.eta = L.eta; P.w = L.w; P.c = L.c;
+    return P;
+  }
+  CorrParams corr() const {
+    CorrParams C;
+    C.K = K; C.nh = nh; C.b = d_cb; C.W = d_cW;
+    return C;
+  }
+};
+
+namespace {
+
+template <typename T>
+nqs_status upload(T** dst, const std::vector<T>& src) {
+  HIPCHK(hipMalloc((void**)dst, std::max<size_t>(src.size(), 1) * sizeof(T)));
+  if (!src.empty()) HIPCHK(hipMemcpy(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice));
+  return NQS_OK;
+}
+
+// MFMA A operand of site i: W_i^T tiles, [edge][k-step q][output tile ot][lane],
+// lane l holding W^T[o = 16 ot + l%16][k = 4 q + l/16] = M_ij^s[u][k] with
+// s = o / chip, u = o % chip (zero outside chi).
+template <typename T>
+nqs_status build_layout(nqs_ansatz* a, const std::vector<double>& prm, PsiLayout<T>& L) {
+  const int K = a->K, chi = a->chi, CH = a->chip;
+  const int KS = CH / 4, NT = CH / 4;
+  std::vector<int64_t> aoff(K);
+  std::vector<T> A;
+  for (int i = 0; i < K; ++i) {
+    aoff[i] = int64_t(A.size());
+    for (int e = a->pptr[i]; e < a->pptr[i + 1]; ++e) {
+      const double* M = prm.data() + a->offM[e];
+      for (int q = 0; q < KS; ++q)
+        for (int ot = 0; ot < NT; ++ot)
+          for (int l = 0; l < 64; ++l) {
+            const int o = ot * 16 + (l & 15);
+            const int k = q * 4 + (l >> 4);
+            const int s = o / CH, u = o % CH;
+            double val = 0.0;
+            if (u < chi && k < chi) val = M[(size_t(s) * chi + u) * chi + k];
+            A.push_back(T(val));
+          }
+    }
+  }
+  std::vector<T> v(size_t(K) * 4 * CH, T(0)), eta(size_t(K) * CH, T(0)), w(size_t(K) * CH, T(0)), c(K);
+  for (int i = 0; i < K; ++i) {
+    for (int s = 0; s < 4; ++s)
+      for (int u = 0; u < chi; ++u) v[(size_t(i) * 4 + s) * CH + u] = T(prm[a->offV[i] + s * chi + u]);
+    for (int u = 0; u < chi; ++u) {
+      eta[size_t(i) * CH + u] = T(prm[a->offEta[i] + u]);
+      w[size_t(i) * CH + u] = T(prm[a->offW[i] + u]);
+    }
+    c[i] = T(prm[a->offC[i]]);
+  }
+  L.free_all();
+  nqs_status st;
+  if ((st = upload(&L.A, A)) != NQS_OK) return st;
+  if ((st = upload(&L.aoff, aoff)) != NQS_OK) return st;
+  if ((st = upload(&L.v, v)) != NQS_OK) return st;
+  if ((st = upload(&L.eta, eta)) != NQS_OK) return st;
+  if ((st = upload(&L.w, w)) != NQS_OK) return st;
+  if ((st = upload(&L.c, c)) != NQS_OK) return st;
+  return NQS_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+const char* nqs_last_error(void) { return g_err.c_str(); }
+const char* nqs_version(void) { return "nqs-eloc gfx950 0.1"; }
+
+nqs_status nqs_ctx_create(int device, nqs_ctx** out) {
+  if (!out) return fail(NQS_EINVAL, "out is NULL");
+  int n = 0;
+  HIPCHK(hipGetDeviceCount(&n));
+  if (device < 0 || device >= n) return fail(NQS_EINVAL, "device %d out of range (%d devices)", device, n);
+  DeviceGuard g(device);
+  HIPCHK(hipFree(nullptr));
+  auto* c = new nqs_ctx();
+  c->device = device;
+  *out = c;
+  return NQS_OK;
+}
+
+nqs_status nqs_ctx_destroy(nqs_ctx* ctx) {
+  if (!ctx) return NQS_OK;
+  DeviceGuard g(ctx->device);
+  (void)hipDeviceSynchronize();
+  delete ctx;
+  return NQS_OK;
+}
+
+nqs_status nqs_ctx_fail_alloc_at(nqs_ctx* ctx, int64_t k) {
+  if (!ctx || k < 0) return fail(NQS_EINVAL, "bad arguments");
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  ctx->fail_at = k;
+  return NQS_OK;
+}
+
+nqs_status nqs_ctx_pool_bytes(const nqs_ctx* ctx, size_t* in_use, size_t* cached) {
+  if (!ctx) return fail(NQS_EINVAL, "ctx is NULL");
+  auto* c = const_cast<nqs_ctx*>(ctx);
+  std::lock_guard<std::mutex> lk(c->mu);
+  if (in_use) *in_use = c->in_use;
+  if (cached) *cached = c->cached;
+  return NQS_OK;
+}
+
+nqs_status nqs_instance_create(nqs_ctx* ctx, int K, int n_alpha, int n_beta, const double* h1,
+                               const double* eri, double e_core, nqs_instance** out) {
+  if (!ctx || !h1 || !eri || !out) return fail(NQS_EINVAL, "NULL argument");
+  if (K < 1 || K > 64) return fail(NQS_EINVAL, "K=%d outside [1,64]", K);
+  if (n_alpha < 0 || n_alpha > K || n_beta < 0 || n_beta > K)
+    return fail(NQS_EINVAL, "electron counts (%d,%d) outside [0,K]", n_alpha, n_beta);
+  const size_t K2 = size_t(K) * K, K4 = K2 * K2;
+  for (int p = 0; p < K; ++p)
+    for (int q = 0; q < K; ++q)
+      if (std::fabs(h1[p * K + q] - h1[q * K + p]) > 1e-10 * (1.0 + std::fabs(h1[p * K + q])))
+        return fail(NQS_EINVAL, "h is not symmetric at (%d,%d)", p, q);
+  double emax = 0.0;
+  for (size_t t = 0; t < K4; ++t) emax = std::max(emax, std::fabs(eri[t]));
+  const double tol = 1e-10 * std::max(emax, 1e-300);
+  std::vector<double> canon(K4);
+  auto at = [&](size_t p, size_t q, size_t r, size_t s) { return ((p * K + q) * K + r) * K + s; };
+  for (size_t p = 0; p < size_t(K); ++p)
+    for (size_t q = 0; q < size_t(K); ++q)
+      for (size_t r = 0; r < size_t(K); ++r)
+        for (size_t s = 0; s < size_t(K); ++s) {
+          size_t a = std::max(p, q), b = std::min(p, q), c = std::max(r, s), d = std::min(r, s);
+          size_t ab = a * (a + 1) / 2 + b, cd = c * (c + 1) / 2 + d;
+          if (ab < cd) { std::swap(a, c); std::swap(b, d); }
+          const double ref = eri[at(a, b, c, d)];
+          const double v = eri[at(p, q, r, s)];
+          if (std::fabs(v - ref) > tol)
+            return fail(NQS_EINVAL, "eri not 8-fold symmetric at (%zu,%zu,%zu,%zu)", p, q, r, s);
+          canon[at(p, q, r, s)] = ref;
+        }
+  std::vector<double> hs(h1, h1 + K2);
+  for (int p = 0; p < K; ++p)
+    for (int q = 0; q < p; ++q) hs[q * K + p] = hs[p * K + q];
+  DeviceGuard g(ctx->device);
+  std::unique_ptr<nqs_instance> inst(new nqs_instance());
+  inst->ctx = ctx;
+  inst->K = K; inst->na = n_alpha; inst->nb = n_beta; inst->ecore = e_core;
+  nqs_status st;
+  if ((st = upload(&inst->d_h, hs)) != NQS_OK) return st;
+  if ((st = upload(&inst->d_eri, canon)) != NQS_OK) return st;
+  HamDev& H = inst->H;
+  H.h = inst->d_h; H.eri = inst->d_eri; H.ecore = e_core;
+  H.K = K; H.na = n_alpha; H.nb = n_beta; H.va = K - n_alpha; H.vb = K - n_beta;
+  const int64_t nsa = int64_t(n_alpha) * H.va, nsb = int64_t(n_beta) * H.vb;
+  const int64_t daa = choose2(n_alpha) * choose2(H.va), dbb = choose2(n_beta) * choose2(H.vb);
+  const int64_t dab = nsa * nsb;
+  const int64_t total = nsa + nsb + daa + dbb + dab;
+  if (total >= (int64_t(1) << 31)) return fail(NQS_EUNSUPPORTED, "too many connected determinants");
+  H.off_sb = uint32_t(nsa);
+  H.off_daa = uint32_t(nsa + nsb);
+  H.off_dbb = uint32_t(nsa + nsb + daa);
+  H.off_dab = uint32_t(nsa + nsb + daa + dbb);
+  H.n_conn = uint32_t(total);
+  H.npa_v = uint32_t(choose2(H.va));
+  H.npb_v = uint32_t(choose2(H.vb));
+  H.nsb = uint32_t(nsb);
+  H.mg_va = magic(H.va); H.mg_vb = magic(H.vb);
+  H.mg_npa_v = magic(H.npa_v); H.mg_npb_v = magic(H.npb_v); H.mg_nsb = magic(H.nsb);
+  // exactness of (x * ceil(2^32/d)) >> 32 needs x * d < 2^32 for every use
+  const uint64_t lim = uint64_t(1) << 32;
+  const uint64_t checks[][2] = {{uint64_t(nsa), uint64_t(H.va)}, {uint64_t(nsb), uint64_t(H.vb)},
+                                {uint64_t(daa), uint64_t(H.npa_v)}, {uint64_t(dbb), uint64_t(H.npb_v)},
+                                {uint64_t(dab), uint64_t(nsb)}};
+  for (auto& c : checks)
+    if (c[0] * c[1] >= lim) return fail(NQS_EUNSUPPORTED, "rank arithmetic would overflow");
+  *out = inst.release();
+  return NQS_OK;
+}
+
+nqs_status nqs_instance_destroy(nqs_instance* inst) {
+  if (!inst) return NQS_OK;
+  DeviceGuard g(inst->ctx->device);
+  delete inst;
+  return NQS_OK;
+}
+
+int64_t nqs_instance_n_conn(const nqs_instance* inst) { return inst ? int64_t(inst->H.n_conn) : -1; }
+
+nqs_status nqs_ansatz_create(nqs_ctx* ctx, int K, int n_alpha, int n_beta, int chi,
+                             const int32_t* parent_ptr, const int32_t* parent_idx, int n_hidden,
+                             nqs_ansatz** out) {
+  if (!ctx || !parent_ptr || !out) return fail(NQS_EINVAL, "NULL argument");
+  if (K < 1 || K > 64) return fail(NQS_EINVAL, "K=%d outside [1,64]", K);
+  if (chi < 1 || chi > 64) return fail(NQS_EUNSUPPORTED, "chi=%d outside [1,64]", chi);
+  if (n_alpha < 0 || n_alpha > K || n_beta < 0 || n_beta > K) return fail(NQS_EINVAL, "bad electron counts");
+  if (n_hidden < 0) return fail(NQS_EINVAL, "n_hidden < 0");
+  if (parent_ptr[0] != 0) return fail(NQS_EINVAL, "parent_ptr[0] != 0");
+  std::unique_ptr<nqs_ansatz> a(new nqs_ansatz());
+  a->ctx = ctx;
+  a->K = K; a->na = n_alpha; a->nb = n_beta; a->chi = chi; a->nh = n_hidden;
+  a->chip = ((chi + 15) / 16) * 16;
+  a->pptr.assign(parent_ptr, parent_ptr + K + 1);
+  int maxoff = 0;
+  for (int i = 0; i < K; ++i) {
+    if (a->pptr[i + 1] < a->pptr[i]) return fail(NQS_EINVAL, "parent_ptr not monotone at %d", i);
+    if (a->pptr[i + 1] - a->pptr[i] > 16) return fail(NQS_EUNSUPPORTED, "in-degree above 16 at %d", i);
+    for (int e = a->pptr[i]; e < a->pptr[i + 1]; ++e) {
+      if (!parent_idx) return fail(NQS_EINVAL, "parent_idx is NULL");
+      const int j = parent_idx[e];
+      if (j < 0 || j >= i) return fail(NQS_EINVAL, "parent %d of site %d does not precede it", j, i);
+      if (e > a->pptr[i] && parent_idx[e - 1] >= j) return fail(NQS_EINVAL, "parents of %d not ascending", i);
+      maxoff = std::max(maxoff, i - j);
+    }
+  }
+  a->pidx.assign(parent_idx ? parent_idx : parent_ptr, parent_idx ? parent_idx + a->pptr[K] : parent_ptr);
+  a->W = maxoff + 1;
+  int64_t o = 0;
+  a->offM.resize(a->pptr[K]);
+  a->offV.resize(K); a->offEta.resize(K); a->offW.resize(K); a->offC.resize(K);
+  for (int i = 0; i < K; ++i) {
+    for (int e = a->pptr[i]; e < a->pptr[i + 1]; ++e) { a->offM[e] = o; o += int64_t(4) * chi * chi; }
+    a->offV[i] = o; o += 4 * chi;
+    a->offEta[i] = o; o += chi;
+    a->offW[i] = o; o += chi;
+    a->offC[i] = o; o += 1;
+  }
+  a->offB = o; o += n_hidden;
+  a->offWc = o; o += int64_t(n_hidden) * 2 * K;
+  a->n_params = o;
+  DeviceGuard g(ctx->device);
+  nqs_status st;
+  std::vector<int> pp(a->pptr.begin(), a->pptr.end()), pi(a->pidx.begin(), a->pidx.end());
+  if ((st = upload(&a->d_pptr, pp)) != NQS_OK) return st;
+  if ((st = upload(&a->d_pidx, pi)) != NQS_OK) return st;
+  *out = a.release();
+  return NQS_OK;
+}
+
+nqs_status nqs_ansatz_destroy(nqs_ansatz* ans) {
+  if (!ans) return NQS_OK;
+  DeviceGuard g(ans->ctx->device);
+  delete ans;
+  return NQS_OK;
+}
+
+int64_t nqs_ansatz_n_params(const nqs_ansatz* ans) { return ans ? ans->n_params : -1; }
+
+nqs_status nqs_ansatz_bind_params(nqs_ansatz* ans, const double* params, hipStream_t stream) {
+  if (!ans || !params) return fail(NQS_EINVAL, "NULL argument");
+  DeviceGuard g(ans->ctx->device);
+  std::vector<double> prm(ans->n_params);
+  HIPCHK(hipMemcpyAsync(prm.data(), params, prm.size() * sizeof(double), hipMemcpyDeviceToHost, stream));
+  HIPCHK(hipStreamSynchronize(stream));
+  for (int i = 0; i < ans->K; ++i)
+    for (int u = 0; u < ans->chi; ++u)
+      if (!(prm[ans->offEta[i] + u] >= 0.0))
+        return fail(NQS_EINVAL, "eta[%d][%d] = %g is negative or NaN", i, u, prm[ans->offEta[i] + u]);
+  nqs_status st;
+  if ((st = build_layout<double>(ans, prm, ans->L64)) != NQS_OK) return st;
+  if ((st = build_layout<float>(ans, prm, ans->L32)) != NQS_OK) return st;
+  if (ans->d_cb) { (void)hipFree(ans->d_cb); ans->d_cb = nullptr; }
+  if (ans->d_cW) { (void)hipFree(ans->d_cW); ans->d_cW = nullptr; }
+  if (ans->nh) {
+    std::vector<double> b(prm.begin() + ans->offB, prm.begin() + ans->offB + ans->nh);
+    std::vector<double> W(prm.begin() + ans->offWc, prm.begin() + ans->offWc + int64_t(ans->nh) * 2 * ans->K);
+    if ((st = upload(&ans->d_cb, b)) != NQS_OK) return st;
+    if ((st = upload(&ans->d_cW, W)) != NQS_OK) return st;
+  }
+  ans->bound = true;
+  return NQS_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+nqs_status check_samples(nqs_ctx* ctx, const uint64_t* samples, int64_t N, int K, int na, int nb,
+                         hipStream_t st) {
+  if (N == 0) return NQS_OK;
+  Scratch S(ctx);
+  int* bad = S.get<int>(1);
+  if (!bad) return fail(NQS_ENOMEM, "workspace allocation failed");
+  HIPCHK(hipMemsetAsync(bad, 0, sizeof(int), st));
+  HIPCHK(launch_validate(samples, N, K, na, nb, bad, st));
+  int hb = 0;
+  HIPCHK(hipMemcpyAsync(&hb, bad, sizeof(int), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  if (hb) return fail(NQS_EINVAL, "a sample lies outside the (%d,%d) sector of K=%d", na, nb, K);
+  return NQS_OK;
+}
+
+// amplitudes of R rows into (lphi, sphi)
+nqs_status run_amplitudes(const nqs_ansatz* a, int precision, const uint64_t* m, int64_t R, double* lphi,
+                          int8_t* sphi, hipStream_t st) {
+  if (precision == NQS_F64) {
+    HIPCHK(launch_psi_f64(a->params(a->L64), m, R, lphi, sphi, st));
+  } else if (precision == NQS_F32) {
+    HIPCHK(launch_psi_f32(a->params(a->L32), m, R, lphi, sphi, st));
+  } else if (precision == NQS_BF16) {
+    BF16Params P{};
+    P.K = a->K; P.chi = a->chi; P.chip = a->chip; P.na = a->na; P.nb = a->nb; P.W = a->W;
+    P.pptr = a->d_pptr; P.pidx = a->d_pidx; P.A = a->bfA; P.aoff = a->bfAoff;
+    P.v = a->L32.v; P.eta = a->L32.eta; P.w = a->L32.w; P.c = a->L32.c;
+    hipError_t e = launch_psi_bf16(P, m, R, lphi, sphi, st);
+    if (e == hipErrorNotSupported) return fail(NQS_EUNSUPPORTED, "BF16 amplitude path not available");
+    HIPCHK(e);
+  } else {
+    return fail(NQS_EINVAL, "unknown precision %d", precision);
+  }
+  return NQS_OK;
+}
+
+struct Pipeline {
+  // per-sample
+  uint64_t *masks, *qpref, *segq, *Qn, *um;
+  uint32_t* segd;
+  int64_t *Dn, *Un, *rowptr;
+  int32_t* urank;
+  double *ucoef, *hdiag;
+  EnumGeom G;
+  int qshift;
+  int64_t R;
+  Rows rows;
+};
+
+EnumGeom make_geom(int64_t n_conn, int64_t N) {
+  EnumGeom G;
+  G.nchunks = int((n_conn + 63) / 64);
+  int64_t S = (32768 + N - 1) / std::max<int64_t>(N, 1);
+  S = std::max<int64_t>(1, std::min<int64_t>(S, std::min<int64_t>(64, std::max(G.nchunks, 1))));
+  G.S = int(S);
+  G.cps = (std::max(G.nchunks, 1) + G.S - 1) / G.S;
+  return G;
+}
+
+// enumerate + screen + draw + rows; leaves R rows in P.rows (device)
+nqs_status build_rows(nqs_ctx* ctx, Scratch& S, const nqs_instance* inst, const uint64_t* samples,
+                      int64_t N, const nqs_eloc_opts& o, Pipeline& P, hipStream_t st, hipEvent_t* ev) {
+  const HamDev& H = inst->H;
+  P.G = make_geom(H.n_conn, N);
+  int e2 = 0;
+  if (o.eps > 0) std::frexp(o.eps, &e2);
+  P.qshift = 40 - e2;
+  const int ne = std::max(o.n_eps, 0);
+  const size_t NC = size_t(N) * P.G.nchunks;
+  P.masks = S.get<uint64_t>(NC);
+  P.qpref = S.get<uint64_t>(NC);
+  P.segq = S.get<uint64_t>(size_t(N) * P.G.S);
+  P.segd = S.get<uint32_t>(size_t(N) * P.G.S);
+  P.Qn = S.get<uint64_t>(N);
+  P.Dn = S.get<int64_t>(N);
+  P.Un = S.get<int64_t>(N);
+  P.rowptr = S.get<int64_t>(N + 1);
+  P.urank = S.get<int32_t>(size_t(N) * std::max(ne, 1));
+  P.ucoef = S.get<double>(size_t(N) * std::max(ne, 1));
+  P.um = S.get<uint64_t>(size_t(N) * std::max(ne, 1) * 2);
+  P.hdiag = S.get<double>(N);
+  if (S.oom) return fail(NQS_ENOMEM, "workspace allocation failed");
+  if (ev) HIPCHK(hipEventRecord(ev[0], st));
+  HIPCHK(launch_enum_count(H, P.G, samples, N, o.eps, P.qshift, P.masks, P.qpref, P.segq, P.segd, st));
+  HIPCHK(launch_sample_scan(P.G, N, P.segq, P.segd, P.Qn, P.Dn, st));
+  if (ev) HIPCHK(hipEventRecord(ev[1], st));
+  if (ne > 0) {
+    DrawKeys k;
+    k.key0 = uint32_t(o.seed); k.key1 = uint32_t(o.seed >> 32);
+    k.ctr2 = uint32_t(o.stream_id); k.ctr3 = uint32_t(o.stream_id >> 32);
+    k.sample_base = uint32_t(o.sample_base);
+    HIPCHK(launch_draw(H, P.G, samples, N, o.eps, P.qshift, ne, k, P.qpref, P.segq, P.Qn, P.urank, P.ucoef,
+                       P.um, P.Un, st));
+  } else {
+    HIPCHK(hipMemsetAsync(P.Un, 0, sizeof(int64_t) * N, st));
+  }
+  HIPCHK(launch_row_counts(N, P.Dn, P.Un, P.rowptr, st));
+  if (ev) HIPCHK(hipEventRecord(ev[2], st));
+  int64_t R = 0;
+  HIPCHK(hipMemcpyAsync(&R, P.rowptr + N, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  P.R = R;
+  P.rows.m = S.get<uint64_t>(size_t(R) * 2);
+  P.rows.coef = S.get<double>(R);
+  P.rows.owner = S.get<int32_t>(R);
+  P.rows.rank = S.get<int64_t>(R);
+  if (S.oom) return fail(NQS_ENOMEM, "row workspace allocation failed (%lld rows)", (long long)R);
+  HIPCHK(launch_fill(H, P.G, samples, N, P.masks, P.segd, P.rowptr, P.Dn, P.Un, P.urank, P.ucoef, P.um,
+                     std::max(ne, 1), P.rows, st));
+  HIPCHK(launch_diag(H, samples, N, P.hdiag, st));
+  if (ev) HIPCHK(hipEventRecord(ev[3], st));
+  return NQS_OK;
+}
+
+nqs_status check_opts(const nqs_eloc_opts* o) {
+  if (!o) return fail(NQS_EINVAL, "opts is NULL");
+  if (!(o->eps >= 0.0) || std::isinf(o->eps)) return fail(NQS_EINVAL, "eps must be finite and >= 0");
+  if (o->n_eps < 0) return fail(NQS_EINVAL, "n_eps < 0");
+  if (o->n_eps > 1024) return fail(NQS_EUNSUPPORTED, "n_eps > 1024 per sample");
+  if (o->precision < 0 || o->precision > 2) return fail(NQS_EINVAL, "unknown precision");
+  return NQS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+nqs_status nqs_connected(nqs_ctx* ctx, const nqs_instance* inst, const uint64_t* samples, int64_t N,
+                         uint64_t* m_out, double* h_out, double* hdiag_out, hipStream_t stream) {
+  if (!ctx || !inst || (!samples && N > 0) || N < 0) return fail(NQS_EINVAL, "bad arguments");
+  DeviceGuard g(ctx->device);
+  nqs_status s = check_samples(ctx, samples, N, inst->K, inst->na, inst->nb, stream);
+  if (s != NQS_OK) return s;
+  if (m_out || h_out) HIPCHK(launch_connected(inst->H, samples, N, m_out, h_out, stream));
+  if (hdiag_out) HIPCHK(launch_diag(inst->H, samples, N, hdiag_out, stream));
+  HIPCHK(hipStreamSynchronize(stream));
+  return NQS_OK;
+}
+
+nqs_status nqs_logpsi(nqs_ctx* ctx, const nqs_ansatz* ans, const uint64_t* samples, int64_t N,
+                      int32_t precision, double* logabs, int8_t* sign, hipStream_t stream) {
+  if (!ctx || !ans || (!samples && N > 0) || N < 0) return fail(NQS_EINVAL, "bad arguments");
+  if (!ans->bound) return fail(NQS_EINVAL, "parameters not bound");
+  DeviceGuard g(ctx->device);
+  nqs_status s = check_samples(ctx, samples, N, ans->K, ans->na, ans->nb, stream);
+  if (s != NQS_OK) return s;
+  if (N == 0) return NQS_OK;
+  Scratch S(ctx);
+  double* lphi = S.get<double>(N);
+  int8_t* sphi = S.get<int8_t>(N);
+  double* lf = ans->nh ? S.get<double>(N) : nullptr;
+  int8_t* sf = ans->nh ? S.get<int8_t>(N) : nullptr;
+  if (S.oom) return fail(NQS_ENOMEM, "workspace allocation failed");
+  if ((s = run_amplitudes(ans, precision, samples, N, lphi, sphi, stream)) != NQS_OK) return s;
+  if (ans->nh) HIPCHK(launch_corr_direct(ans->corr(), samples, N, lf, sf, stream));
+  HIPCHK(launch_gather_logpsi(N, lphi, sphi, lf, sf, logabs, sign, stream));
+  HIPCHK(hipStreamSynchronize(stream));
+  return NQS_OK;
+}
+
+nqs_status nqs_logpsi_vjp(nqs_ctx*, const nqs_ansatz*, const uint64_t*, int64_t, const double*, int32_t,
+                          double*, hipStream_t) {
+  return fail(NQS_EUNSUPPORTED, "vjp not built yet");
+}
+
+nqs_status nqs_eloc(nqs_ctx* ctx, const nqs_instance* inst, const nqs_ansatz* ans,
+                    const uint64_t* samples, const double* counts, int64_t N,
+                    const nqs_eloc_opts* opts, double* eloc, double* etnum, double* logabs,
+                    int8_t* sign, double* fsq, nqs_eloc_stats* stats, hipStream_t stream) {
+  if (!ctx || !inst || !ans || (!samples && N > 0) || N < 0) return fail(NQS_EINVAL, "bad arguments");
+  nqs_status s = check_opts(opts);
+  if (s != NQS_OK) return s;
+  if (!ans->bound) return fail(NQS_EINVAL, "parameters not bound");
+  if (ans->K != inst->K || ans->na != inst->na || ans->nb != inst->nb)
+    return fail(NQS_EINVAL, "ansatz and instance describe different sectors");
+  if (N > (int64_t(1) << 31) - 1) return fail(NQS_EUNSUPPORTED, "N too large");
+  DeviceGuard g(ctx->device);
+  if ((s = check_samples(ctx, samples, N, inst->K, inst->na, inst->nb, stream)) != NQS_OK) return s;
+  if (N == 0) {
+    if (stats) { std::memset(stats, 0, sizeof *stats); stats->n_conn = inst->H.n_conn; }
+    return NQS_OK;
+  }
+  Scratch S(ctx);
+  hipEvent_t ev[6] = {};
+  const bool timing = stats != nullptr;
+  if (timing)
+    for (auto& e : ev) HIPCHK(hipEventCreate(&e));
+  struct EvGuard {
+    hipEvent_t* e; bool on;
+    ~EvGuard() { if (on) for (int k = 0; k < 6; ++k) (void)hipEventDestroy(e[k]); }
+  } evg{ev, timing};
+  Pipeline P{};
+  if ((s = build_rows(ctx, S, inst, samples, N, *opts, P, stream, timing ? ev : nullptr)) != NQS_OK) return s;
+  const int64_t R = P.R;
+  double* lphi = S.get<double>(R);
+  int8_t* sphi = S.get<int8_t>(R);
+  double* lf = S.get<double>(R);
+  int8_t* sf = S.get<int8_t>(R);
+  double* theta = ans->nh ? S.get<double>(size_t(N) * ans->nh) : nullptr;
+  double* el = eloc ? eloc : S.get<double>(N);
+  double* et = etnum ? etnum : S.get<double>(N);
+  double* f2 = fsq ? fsq : S.get<double>(N);
+  double* sums = S.get<double>(8);
+  if (S.oom) return fail(NQS_ENOMEM, "workspace allocation failed");
+  if ((s = run_amplitudes(ans, opts->precision, P.rows.m, R, lphi, sphi, stream)) != NQS_OK) return s;
+  if (ans->nh) {
+    HIPCHK(launch_corr_theta(ans->corr(), samples, N, theta, stream));
+    HIPCHK(launch_corr_rows(ans->corr(), P.rows.m, P.rows.owner, samples, theta, R, opts->precision, lf, sf,
+                            stream));
+  } else {
+    HIPCHK(hipMemsetAsync(lf, 0, sizeof(double) * R, stream));
+    HIPCHK(hipMemsetAsync(sf, 1, sizeof(int8_t) * R, stream));
+  }
+  if (timing) HIPCHK(hipEventRecord(ev[4], stream));
+  HIPCHK(launch_reduce(N, P.rowptr, P.rows.coef, lphi, sphi, lf, sf, P.hdiag, el, et, logabs, sign, f2, stream));
+  HIPCHK(launch_batch_sums(N, counts, el, et, f2, sums, stream));
+  if (timing) HIPCHK(hipEventRecord(ev[5], stream));
+  double hs[8] = {0};
+  if (stats) HIPCHK(hipMemcpyAsync(hs, sums, sizeof hs, hipMemcpyDeviceToHost, stream));
+  HIPCHK(hipStreamSynchronize(stream));
+  if (stats) {
+    std::vector<int64_t> Dn(N), Un(N);
+    HIPCHK(hipMemcpy(Dn.data(), P.Dn, sizeof(int64_t) * N, hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(Un.data(), P.Un, sizeof(int64_t) * N, hipMemcpyDeviceToHost));
+    std::memset(stats, 0, sizeof *stats);
+    stats->n_samples = N;
+    stats->n_conn = inst->H.n_conn;
+    stats->n_rows = R;
+    for (int64_t n = 0; n < N; ++n) { stats->n_det_rows += Dn[n]; stats->n_draw_rows += Un[n]; }
+    stats->sum_c = hs[0];
+    stats->B = hs[4];
+    stats->E = hs[3];
+    stats->var = hs[5];
+    stats->n_zero_amp = int64_t(hs[6]);
+    float t = 0;
+    HIPCHK(hipEventElapsedTime(&t, ev[0], ev[1])); stats->ms_enumerate = t;
+    HIPCHK(hipEventElapsedTime(&t, ev[1], ev[2])); stats->ms_draw = t;
+    HIPCHK(hipEventElapsedTime(&t, ev[2], ev[3])); stats->ms_rows = t;
+    HIPCHK(hipEventElapsedTime(&t, ev[3], ev[4])); stats->ms_amplitude = t;
+    HIPCHK(hipEventElapsedTime(&t, ev[4], ev[5])); stats->ms_reduce = t;
+  }
+  return NQS_OK;
+}
+
+nqs_status nqs_rows(nqs_ctx* ctx, const nqs_instance* inst, const uint64_t* samples, int64_t N,
+                    const nqs_eloc_opts* opts, int64_t cap, int64_t* row_ptr, int64_t* n_det,
+                    uint64_t* Q, int64_t* rank, double* coef, uint64_t* m, int64_t* n_rows,
+                    hipStream_t stream) {
+  if (!ctx || !inst || (!samples && N > 0) || N < 0 || cap < 0) return fail(NQS_EINVAL, "bad arguments");
+  nqs_status s = check_opts(opts);
+  if (s != NQS_OK) return s;
+  DeviceGuard g(ctx->device);
+  if ((s = check_samples(ctx, samples, N, inst->K, inst->na, inst->nb, stream)) != NQS_OK) return s;
+  if (N == 0) { if (n_rows) *n_rows = 0; return NQS_OK; }
+  Scratch S(ctx);
+  Pipeline P{};
+  if ((s = build_rows(ctx, S, inst, samples, N, *opts, P, stream, nullptr)) != NQS_OK) return s;
+  const int64_t R = P.R, w = std::min(R, cap);
+  if (row_ptr) HIPCHK(hipMemcpyAsync(row_ptr, P.rowptr, sizeof(int64_t) * (N + 1), hipMemcpyDeviceToDevice, stream));
+  if (n_det) HIPCHK(hipMemcpyAsync(n_det, P.Dn, sizeof(int64_t) * N, hipMemcpyDeviceToDevice, stream));
+  if (Q) HIPCHK(hipMemcpyAsync(Q, P.Qn, sizeof(uint64_t) * N, hipMemcpyDeviceToDevice, stream));
+  if (w > 0) {
+    if (rank) HIPCHK(hipMemcpyAsync(rank, P.rows.rank, sizeof(int64_t) * w, hipMemcpyDeviceToDevice, stream));
+    if (coef) HIPCHK(hipMemcpyAsync(coef, P.rows.coef, sizeof(double) * w, hipMemcpyDeviceToDevice, stream));
+    if (m) HIPCHK(hipMemcpyAsync(m, P.rows.m, sizeof(uint64_t) * 2 * w, hipMemcpyDeviceToDevice, stream));
+  }
+  HIPCHK(hipStreamSynchronize(stream));
+  if (n_rows) *n_rows = R;
+  return NQS_OK;
+}
+
+nqs_status nqs_eloc_workspace_bytes(const nqs_instance* inst, const nqs_ansatz* ans, int64_t N,
+                                    const nqs_eloc_opts* opts, int64_t n_rows, size_t* bytes) {
+  if (!inst || !ans || !opts || !bytes || N < 0 || n_rows < 0) return fail(NQS_EINVAL, "bad arguments");
+  const EnumGeom G = make_geom(inst->H.n_conn, N);
+  const int64_t ne = std::max(opts->n_eps, 1);
+  auto al = [](size_t b) { return std::max<size_t>(256, (b + 255) & ~size_t(255)); };
+  size_t b = 0;
+  b += 2 * al(size_t(N) * G.nchunks * 8);
+  b += al(size_t(N) * G.S * 8) + al(size_t(N) * G.S * 4);
+  b += 4 * al(size_t(N) * 8) + al(size_t(N + 1) * 8);
+  b += al(size_t(N) * ne * 4) + al(size_t(N) * ne * 8) + al(size_t(N) * ne * 16);
+  b += 4 * al(size_t(N) * 8) + al(64) + al(4);
+  if (ans->nh) b += al(size_t(N) * ans->nh * 8);
+  // per row: m(16) coef(8) owner(4) rank(8) lphi(8) sphi(1) lf(8) sf(1)
+  b += al(size_t(n_rows) * 16) + 3 * al(size_t(n_rows) * 8) + al(size_t(n_rows) * 4) + al(size_t(n_rows) * 8) +
+       2 * al(size_t(n_rows));
+  *bytes = b;
+  return NQS_OK;
+}
+
+}  // extern "C"

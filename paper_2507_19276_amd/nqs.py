@@ -1,0 +1,315 @@
+"""Python binding of libnqs (include/nqs.h): argument marshalling only.
+
+Every step of the local-energy path runs in the HIP library; this module
+passes device pointers of torch tensors and the current HIP stream.  It never
+computes a result itself and raises if the library is not built.
+
+Samples are int64 tensors of shape [N, 2] on the GPU holding the two uint64
+words of each ONV (bit P = occupation of spin orbital P = 2p + sigma).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Dict, Optional
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libnqs.so")
+
+NQS_OK, NQS_EINVAL, NQS_ENOMEM, NQS_EDEVICE, NQS_EUNSUPPORTED, NQS_EBUSY = range(6)
+PRECISIONS = {"f64": 0, "f32": 1, "bf16": 2}
+
+
+class NqsError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"nqs error {code}: {msg}")
+        self.code = code
+
+
+class ElocOpts(C.Structure):
+    _fields_ = [("eps", C.c_double), ("n_eps", C.c_int32), ("precision", C.c_int32),
+                ("seed", C.c_uint64), ("stream_id", C.c_uint64), ("sample_base", C.c_int32),
+                ("reserved", C.c_int32)]
+
+
+class ElocStats(C.Structure):
+    _fields_ = [("n_samples", C.c_int64), ("n_conn", C.c_int64), ("n_rows", C.c_int64),
+                ("n_det_rows", C.c_int64), ("n_draw_rows", C.c_int64), ("n_zero_amp", C.c_int64),
+                ("sum_c", C.c_double), ("B", C.c_double), ("E", C.c_double), ("var", C.c_double),
+                ("ms_enumerate", C.c_double), ("ms_draw", C.c_double), ("ms_rows", C.c_double),
+                ("ms_amplitude", C.c_double), ("ms_reduce", C.c_double)]
+
+    def to_dict(self) -> Dict[str, float]:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+_p = C.c_void_p
+
+
+def lib():
+    """The loaded library; raises when it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_2507_19276_amd/build.py "
+                           "(there is no fallback path)")
+    L = C.CDLL(LIB_PATH)
+    L.nqs_last_error.restype = C.c_char_p
+    L.nqs_version.restype = C.c_char_p
+    L.nqs_ctx_create.argtypes = [C.c_int, C.POINTER(_p)]
+    L.nqs_ctx_destroy.argtypes = [_p]
+    L.nqs_ctx_fail_alloc_at.argtypes = [_p, C.c_int64]
+    L.nqs_ctx_pool_bytes.argtypes = [_p, C.POINTER(C.c_size_t), C.POINTER(C.c_size_t)]
+    L.nqs_instance_create.argtypes = [_p, C.c_int, C.c_int, C.c_int, _p, _p, C.c_double, C.POINTER(_p)]
+    L.nqs_instance_destroy.argtypes = [_p]
+    L.nqs_instance_n_conn.argtypes = [_p]
+    L.nqs_instance_n_conn.restype = C.c_int64
+    L.nqs_connected.argtypes = [_p, _p, _p, C.c_int64, _p, _p, _p, _p]
+    L.nqs_ansatz_create.argtypes = [_p, C.c_int, C.c_int, C.c_int, C.c_int, _p, _p, C.c_int, C.POINTER(_p)]
+    L.nqs_ansatz_destroy.argtypes = [_p]
+    L.nqs_ansatz_n_params.argtypes = [_p]
+    L.nqs_ansatz_n_params.restype = C.c_int64
+    L.nqs_ansatz_bind_params.argtypes = [_p, _p, _p]
+    L.nqs_logpsi.argtypes = [_p, _p, _p, C.c_int64, C.c_int32, _p, _p, _p]
+    L.nqs_logpsi_vjp.argtypes = [_p, _p, _p, C.c_int64, _p, C.c_int32, _p, _p]
+    L.nqs_eloc.argtypes = [_p, _p, _p, _p, _p, C.c_int64, C.POINTER(ElocOpts), _p, _p, _p, _p, _p,
+                           C.POINTER(ElocStats), _p]
+    L.nqs_rows.argtypes = [_p, _p, _p, C.c_int64, C.POINTER(ElocOpts), C.c_int64, _p, _p, _p, _p, _p, _p,
+                           C.POINTER(C.c_int64), _p]
+    L.nqs_eloc_workspace_bytes.argtypes = [_p, _p, C.c_int64, C.POINTER(ElocOpts), C.c_int64,
+                                           C.POINTER(C.c_size_t)]
+    _lib = L
+    return L
+
+
+def check(code: int):
+    if code != NQS_OK:
+        raise NqsError(code, lib().nqs_last_error().decode())
+
+
+def _stream() -> int:
+    return torch.cuda.current_stream().cuda_stream
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    if t is None:
+        return None
+    assert t.is_cuda and t.is_contiguous(), "device tensors must be contiguous CUDA tensors"
+    return C.c_void_p(t.data_ptr())
+
+
+def _samples(s) -> torch.Tensor:
+    if isinstance(s, np.ndarray):
+        s = torch.from_numpy(np.ascontiguousarray(s).view(np.int64))
+    s = s.reshape(-1, 2)
+    if not s.is_cuda:
+        s = s.cuda()
+    return s.contiguous()
+
+
+def opts(eps: float = 0.0, n_eps: int = 0, precision="f64", seed: int = 0, stream_id: int = 0,
+         sample_base: int = 0) -> ElocOpts:
+    p = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    return ElocOpts(float(eps), int(n_eps), p, int(seed) & 0xFFFFFFFFFFFFFFFF,
+                    int(stream_id) & 0xFFFFFFFFFFFFFFFF, int(sample_base), 0)
+
+
+class Context:
+    def __init__(self, device: int = 0):
+        h = _p()
+        check(lib().nqs_ctx_create(int(device), C.byref(h)))
+        self.h = h
+        self.device = device
+
+    def fail_alloc_at(self, k: int):
+        check(lib().nqs_ctx_fail_alloc_at(self.h, int(k)))
+
+    def pool_bytes(self):
+        a, b = C.c_size_t(), C.c_size_t()
+        check(lib().nqs_ctx_pool_bytes(self.h, C.byref(a), C.byref(b)))
+        return a.value, b.value
+
+    def close(self):
+        if self.h:
+            lib().nqs_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Instance:
+    """Resident Hamiltonian: h (K x K) and eri (K^4, chemist) copied to HBM."""
+
+    def __init__(self, ctx: Context, K: int, n_alpha: int, n_beta: int, h, eri, e_core: float = 0.0):
+        h = np.ascontiguousarray(h, dtype=np.float64)
+        eri = np.ascontiguousarray(eri, dtype=np.float64)
+        assert h.shape == (K, K) and eri.shape == (K, K, K, K)
+        out = _p()
+        check(lib().nqs_instance_create(ctx.h, K, n_alpha, n_beta, h.ctypes.data_as(_p),
+                                        eri.ctypes.data_as(_p), float(e_core), C.byref(out)))
+        self.h = out
+        self.ctx = ctx
+        self.K, self.n_alpha, self.n_beta = K, n_alpha, n_beta
+        self.n_conn = int(lib().nqs_instance_n_conn(out))
+
+    def connected(self, samples):
+        """(m [N, n_conn, 2] int64, H [N, n_conn], H_nn [N]) on the device."""
+        s = _samples(samples)
+        N = s.shape[0]
+        m = torch.empty((N, self.n_conn, 2), dtype=torch.int64, device=s.device)
+        hv = torch.empty((N, self.n_conn), dtype=torch.float64, device=s.device)
+        hd = torch.empty(N, dtype=torch.float64, device=s.device)
+        check(lib().nqs_connected(self.ctx.h, self.h, _ptr(s), N, _ptr(m), _ptr(hv), _ptr(hd), _p(_stream())))
+        return m, hv, hd
+
+    def close(self):
+        if self.h:
+            lib().nqs_instance_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Ansatz:
+    """BDG-RNN / MPS-RNN (+ cos-RBM) layout; parameters bound from a device tensor."""
+
+    def __init__(self, ctx: Context, K: int, n_alpha: int, n_beta: int, chi: int, parent_ptr, parent_idx,
+                 n_hidden: int = 0):
+        pp = np.ascontiguousarray(parent_ptr, dtype=np.int32)
+        pi = np.ascontiguousarray(parent_idx, dtype=np.int32)
+        if pi.size == 0:
+            pi = np.zeros(1, dtype=np.int32)
+        out = _p()
+        check(lib().nqs_ansatz_create(ctx.h, K, n_alpha, n_beta, chi, pp.ctypes.data_as(_p),
+                                      pi.ctypes.data_as(_p), n_hidden, C.byref(out)))
+        self.h = out
+        self.ctx = ctx
+        self.K, self.n_alpha, self.n_beta, self.chi, self.n_hidden = K, n_alpha, n_beta, chi, n_hidden
+        self.n_params = int(lib().nqs_ansatz_n_params(out))
+
+    def bind(self, params):
+        if isinstance(params, np.ndarray):
+            params = torch.from_numpy(np.ascontiguousarray(params, dtype=np.float64))
+        p = params.detach().to(dtype=torch.float64, device=f"cuda:{self.ctx.device}").contiguous()
+        assert p.numel() == self.n_params
+        check(lib().nqs_ansatz_bind_params(self.h, _ptr(p), _p(_stream())))
+        return self
+
+    def logpsi(self, samples, precision="f64"):
+        s = _samples(samples)
+        N = s.shape[0]
+        la = torch.empty(N, dtype=torch.float64, device=s.device)
+        sg = torch.empty(N, dtype=torch.int8, device=s.device)
+        pr = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+        check(lib().nqs_logpsi(self.ctx.h, self.h, _ptr(s), N, pr, _ptr(la), _ptr(sg), _p(_stream())))
+        return la, sg
+
+    def vjp(self, samples, cot, precision="f64", grad: Optional[torch.Tensor] = None):
+        s = _samples(samples)
+        N = s.shape[0]
+        c = cot.to(dtype=torch.float64, device=s.device).contiguous()
+        if grad is None:
+            grad = torch.zeros(self.n_params, dtype=torch.float64, device=s.device)
+        pr = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+        check(lib().nqs_logpsi_vjp(self.ctx.h, self.h, _ptr(s), N, _ptr(c), pr, _ptr(grad), _p(_stream())))
+        return grad
+
+    def close(self):
+        if self.h:
+            lib().nqs_ansatz_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def eloc(ctx: Context, inst: Instance, ans: Ansatz, samples, counts: Optional[torch.Tensor] = None,
+         eps: float = 0.0, n_eps: int = 0, precision="f64", seed: int = 0, stream_id: int = 0,
+         sample_base: int = 0, want_stats: bool = True):
+    """Semi-stochastic local energies; returns (dict of device tensors, stats dict or None)."""
+    s = _samples(samples)
+    N = s.shape[0]
+    dev = s.device
+    out = {
+        "eloc": torch.empty(N, dtype=torch.float64, device=dev),
+        "etnum": torch.empty(N, dtype=torch.float64, device=dev),
+        "logabs": torch.empty(N, dtype=torch.float64, device=dev),
+        "sign": torch.empty(N, dtype=torch.int8, device=dev),
+        "fsq": torch.empty(N, dtype=torch.float64, device=dev),
+    }
+    c = None if counts is None else counts.to(dtype=torch.float64, device=dev).contiguous()
+    o = opts(eps, n_eps, precision, seed, stream_id, sample_base)
+    st = ElocStats()
+    check(lib().nqs_eloc(ctx.h, inst.h, ans.h, _ptr(s), _ptr(c), N, C.byref(o), _ptr(out["eloc"]),
+                         _ptr(out["etnum"]), _ptr(out["logabs"]), _ptr(out["sign"]), _ptr(out["fsq"]),
+                         C.byref(st) if want_stats else None, _p(_stream())))
+    return out, (st.to_dict() if want_stats else None)
+
+
+def rows(ctx: Context, inst: Instance, samples, eps: float = 0.0, n_eps: int = 0, seed: int = 0,
+         stream_id: int = 0, sample_base: int = 0, cap: Optional[int] = None):
+    """Row list of the local-energy computation (see nqs_rows in include/nqs.h)."""
+    s = _samples(samples)
+    N = s.shape[0]
+    dev = s.device
+    o = opts(eps, n_eps, "f64", seed, stream_id, sample_base)
+    row_ptr = torch.empty(N + 1, dtype=torch.int64, device=dev)
+    n_det = torch.empty(N, dtype=torch.int64, device=dev)
+    Q = torch.empty(N, dtype=torch.int64, device=dev)
+    nr = C.c_int64()
+    if cap is None:
+        check(lib().nqs_rows(ctx.h, inst.h, _ptr(s), N, C.byref(o), 0, _ptr(row_ptr), _ptr(n_det), _ptr(Q),
+                             None, None, None, C.byref(nr), _p(_stream())))
+        cap = nr.value
+    rank = torch.empty(max(cap, 1), dtype=torch.int64, device=dev)
+    coef = torch.empty(max(cap, 1), dtype=torch.float64, device=dev)
+    m = torch.empty((max(cap, 1), 2), dtype=torch.int64, device=dev)
+    check(lib().nqs_rows(ctx.h, inst.h, _ptr(s), N, C.byref(o), cap, _ptr(row_ptr), _ptr(n_det), _ptr(Q),
+                         _ptr(rank), _ptr(coef), _ptr(m), C.byref(nr), _p(_stream())))
+    R = nr.value
+    return dict(row_ptr=row_ptr, n_det=n_det, Q=Q, rank=rank[:R], coef=coef[:R], m=m[:R], n_rows=R)
+
+
+def workspace_bytes(inst: Instance, ans: Ansatz, N: int, n_rows: int, eps=0.0, n_eps=0, precision="f64") -> int:
+    b = C.c_size_t()
+    o = opts(eps, n_eps, precision)
+    check(lib().nqs_eloc_workspace_bytes(inst.h, ans.h, int(N), C.byref(o), int(n_rows), C.byref(b)))
+    return b.value
+
+
+class LogPsi(torch.autograd.Function):
+    """log|Psi(n)| with a backward pass through the hand-written adjoint kernel.
+
+    forward(params, samples, ans, precision) -> log|Psi| [N] (float64); the
+    gradient with respect to params is sum_n g_n d log|Psi(n)| / d theta."""
+
+    @staticmethod
+    def forward(ctx_, params, samples, ans: Ansatz, precision="f64"):
+        ans.bind(params)
+        la, _ = ans.logpsi(samples, precision)
+        ctx_.ans = ans
+        ctx_.precision = precision
+        ctx_.save_for_backward(_samples(samples))
+        return la
+
+    @staticmethod
+    def backward(ctx_, g):
+        (s,) = ctx_.saved_tensors
+        grad = ctx_.ans.vjp(s, g.contiguous(), ctx_.precision)
+        return grad, None, None, None
