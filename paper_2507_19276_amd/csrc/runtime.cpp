@@ -210,8 +210,12 @@ nqs_status upload(T** dst, const std::vector<T>& src) {
 }
 
 // MFMA A operand of site i: W_i^T tiles, [edge][k-step q][output tile ot][lane],
-// lane l holding W^T[o = 16 ot + l%16][k = 4 q + l/16] = M_ij^s[u][k] with
-// s = o / chip, u = o % chip (zero outside chi).
+// lane l holding W^T[o][k = 4 q + l/16] = M_ij^s[u][k] with s = o / chip,
+// u = o % chip (zero outside chi) for the tile row m = l%16.  The 16x16x4
+// f32 MFMA returns row m = 4 g + v of the tile in register v of lane group
+// g = lane/16; the f64 MFMA returns row m = g + 4 v.  Tile row m therefore
+// carries unit o = 16 ot + m for f32 and o = 16 ot + 4 (m%4) + m/4 for f64,
+// so that in both cases lane group g ends up with units 16 ot + 4 g + v.
 template <typename T>
 nqs_status build_layout(nqs_ansatz* a, const std::vector<double>& prm, PsiLayout<T>& L) {
   const int K = a->K, chi = a->chi, CH = a->chip;
@@ -225,7 +229,8 @@ nqs_status build_layout(nqs_ansatz* a, const std::vector<double>& prm, PsiLayout
       for (int q = 0; q < KS; ++q)
         for (int ot = 0; ot < NT; ++ot)
           for (int l = 0; l < 64; ++l) {
-            const int o = ot * 16 + (l & 15);
+            const int mrow = l & 15;
+            const int o = ot * 16 + (sizeof(T) == 8 ? 4 * (mrow & 3) + (mrow >> 2) : mrow);
             const int k = q * 4 + (l >> 4);
             const int s = o / CH, u = o % CH;
             double val = 0.0;
