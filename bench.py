@@ -46,7 +46,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--precision", default="f32", choices=["f64", "f32", "bf16"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-samples", type=int, default=768)
+    ap.add_argument("--cpu-samples", type=int, default=4096)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
@@ -71,7 +71,7 @@ def main():
                         seed=w.seed + k, stream_id=0)
 
     results = {}
-    for prec in dict.fromkeys([args.precision, "f64"]):
+    for prec in dict.fromkeys([args.precision, "f64", "f32", "bf16"]):
         for k in range(args.warmup):
             step(k, prec)
         torch.cuda.synchronize()
@@ -108,7 +108,8 @@ def main():
         "config": {"workload": "chain K=20 10a+10b, BDG-RNN chain chi=16, 4096 unique samples, "
                                "eps=1e-3, N_eps=64", "global_batch": N, "precision": args.precision},
         "rows_per_step": head["rows"],
-        "f64_value": args.steps * N / results["f64"]["dt"],
+        "by_precision": {p: {"value": args.steps * N / r["dt"], "amplitude_ms": r["psi_ms"]}
+                         for p, r in results.items()},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "frac": achieved / peak, "traffic": None,
                      "kernel": "k_psi (bond contractions)"},

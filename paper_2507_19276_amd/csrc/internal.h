@@ -56,6 +56,24 @@ struct PsiParams {
   const T* c;                    // [K]
 };
 
+// Adjoint (backward) layouts for one precision T.
+template <typename T>
+struct AdjParams {
+  int K, chi, chip, na, nb;
+  const int* pptr;               // device [K+1]
+  const int* pidx;               // device
+  const int* pptr_host;          // host copy, launch sizing only
+  const T* AF;                   // recompute A operands, k-permuted (see adjoint.hip)
+  const int64_t* afoff;          // device [K]
+  const T* BT;                   // M^T operands for the parent cotangents
+  const int64_t* btoff;          // device [K]
+  const T* v;                    // [K][4][chip]
+  const T* eta;                  // [K][chip]
+  const int64_t* offM;           // device: packed offset of each edge's M block
+  const int64_t* offV;           // device [K]
+  const int64_t* offEta;         // device [K]
+};
+
 struct BF16Params {
   int K, chi, chip, na, nb, W;
   const int* pptr;
@@ -106,10 +124,11 @@ hipError_t launch_connected(const HamDev& H, const uint64_t* samples, int64_t N,
                             double* h_out, hipStream_t st);
 
 // ---- launchers (amplitude.hip) -----------------------------------------
+// hstore (nullable): carried states h_i^{s_i} of every row, [K][rpad][chip]
 hipError_t launch_psi_f64(const PsiParams<double>& P, const uint64_t* m, int64_t R, double* lphi,
-                          int8_t* sphi, hipStream_t st);
+                          int8_t* sphi, hipStream_t st, double* hstore = nullptr, int64_t rpad = 0);
 hipError_t launch_psi_f32(const PsiParams<float>& P, const uint64_t* m, int64_t R, double* lphi,
-                          int8_t* sphi, hipStream_t st);
+                          int8_t* sphi, hipStream_t st, float* hstore = nullptr, int64_t rpad = 0);
 hipError_t launch_psi_bf16(const BF16Params& P, const uint64_t* m, int64_t R, double* lphi,
                            int8_t* sphi, hipStream_t st);
 hipError_t launch_corr_theta(const CorrParams& C, const uint64_t* samples, int64_t N, double* theta,
@@ -127,5 +146,19 @@ hipError_t launch_batch_sums(int64_t N, const double* counts, const double* eloc
                              const double* fsq, double* out /*[8]*/, hipStream_t st);
 hipError_t launch_gather_logpsi(int64_t N, const double* lphi, const int8_t* sphi, const double* lf,
                                 const int8_t* sf, double* logabs, int8_t* sign, hipStream_t st);
+
+// ---- launchers (adjoint.hip) -------------------------------------------
+hipError_t launch_bwd_sweep_f64(const AdjParams<double>& P, const uint64_t* m, int64_t R, int64_t Rpad,
+                                const double* cot, const double* Hbuf, double* dcarry, double* Dc,
+                                double* Eeta, int rows_per_split, int nsplit, double* gpart,
+                                int64_t n_params, hipStream_t st);
+hipError_t launch_bwd_sweep_f32(const AdjParams<float>& P, const uint64_t* m, int64_t R, int64_t Rpad,
+                                const double* cot, const float* Hbuf, float* dcarry, float* Dc,
+                                float* Eeta, int rows_per_split, int nsplit, double* gpart,
+                                int64_t n_params, hipStream_t st);
+hipError_t launch_corr_backward(const CorrParams& C, const uint64_t* m, int64_t R, const double* cot,
+                                double* dth, int rows_per_split, int nsplit, int64_t offB, int64_t offW,
+                                double* gpart, int64_t n_params, hipStream_t st);
+hipError_t launch_sum_parts(int64_t n_params, int nsplit, const double* gpart, double* grad, hipStream_t st);
 
 }  // namespace nqs

@@ -157,10 +157,16 @@ struct PsiLayout {
   T* eta = nullptr;
   T* w = nullptr;
   T* c = nullptr;
+  T* AF = nullptr;          // adjoint: recompute operands (k-permuted)
+  int64_t* afoff = nullptr;
+  T* BT = nullptr;          // adjoint: M^T operands
+  int64_t* btoff = nullptr;
   void free_all() {
-    for (void* p : {(void*)A, (void*)aoff, (void*)v, (void*)eta, (void*)w, (void*)c})
+    for (void* p : {(void*)A, (void*)aoff, (void*)v, (void*)eta, (void*)w, (void*)c, (void*)AF,
+                    (void*)afoff, (void*)BT, (void*)btoff})
       if (p) (void)hipFree(p);
     A = nullptr; aoff = nullptr; v = eta = w = c = nullptr;
+    AF = nullptr; afoff = nullptr; BT = nullptr; btoff = nullptr;
   }
 };
 
@@ -179,11 +185,25 @@ struct nqs_ansatz {
   int64_t* bfAoff = nullptr;
   double* d_cb = nullptr;   // correlator b
   double* d_cW = nullptr;   // correlator W
+  int64_t* d_offM = nullptr;
+  int64_t* d_offV = nullptr;
+  int64_t* d_offEta = nullptr;
   ~nqs_ansatz() {
     L64.free_all();
     L32.free_all();
-    for (void* p : {(void*)d_pptr, (void*)d_pidx, (void*)bfA, (void*)bfAoff, (void*)d_cb, (void*)d_cW})
+    for (void* p : {(void*)d_pptr, (void*)d_pidx, (void*)bfA, (void*)bfAoff, (void*)d_cb, (void*)d_cW,
+                    (void*)d_offM, (void*)d_offV, (void*)d_offEta})
       if (p) (void)hipFree(p);
+  }
+  template <typename T>
+  AdjParams<T> adj(const PsiLayout<T>& L) const {
+    AdjParams<T> P;
+    P.K = K; P.chi = chi; P.chip = chip; P.na = na; P.nb = nb;
+    P.pptr = d_pptr; P.pidx = d_pidx; P.pptr_host = pptr.data();
+    P.AF = L.AF; P.afoff = L.afoff; P.BT = L.BT; P.btoff = L.btoff;
+    P.v = L.v; P.eta = L.eta;
+    P.offM = d_offM; P.offV = d_offV; P.offEta = d_offEta;
+    return P;
   }
   template <typename T>
   PsiParams<T> params(const PsiLayout<T>& L) const {
@@ -249,14 +269,94 @@ nqs_status build_layout(nqs_ansatz* a, const std::vector<double>& prm, PsiLayout
     }
     c[i] = T(prm[a->offC[i]]);
   }
+  // adjoint operands.  AF: like A but k-step q = 4t + v pairs lane group k'
+  // with parent unit 16t + 4k' + v.  BT: k-step q = (s*TPC + t)*4 + v over the
+  // candidate units (s, 16t + 4k' + v) and output tiles ot over the parent
+  // unit kk = 16 ot + n: B[k'][n] = M_ij^s[u][kk].
+  const int TPC = CH / 16;
+  std::vector<int64_t> afoff(K), btoff(K);
+  std::vector<T> AF, BT;
+  for (int i = 0; i < K; ++i) {
+    afoff[i] = int64_t(AF.size());
+    btoff[i] = int64_t(BT.size());
+    for (int e = a->pptr[i]; e < a->pptr[i + 1]; ++e) {
+      const double* M = prm.data() + a->offM[e];
+      for (int q = 0; q < KS; ++q)
+        for (int ot = 0; ot < NT; ++ot)
+          for (int l = 0; l < 64; ++l) {
+            const int mrow = l & 15;
+            const int o = ot * 16 + (sizeof(T) == 8 ? 4 * (mrow & 3) + (mrow >> 2) : mrow);
+            const int k = 16 * (q >> 2) + 4 * (l >> 4) + (q & 3);
+            const int s = o / CH, u = o % CH;
+            double val = 0.0;
+            if (u < chi && k < chi) val = M[(size_t(s) * chi + u) * chi + k];
+            AF.push_back(T(val));
+          }
+      for (int q = 0; q < 4 * KS; ++q)
+        for (int ot = 0; ot < TPC; ++ot)
+          for (int l = 0; l < 64; ++l) {
+            const int v = q & 3, t = (q >> 2) % TPC, s = (q >> 2) / TPC;
+            const int u = 16 * t + 4 * (l >> 4) + v;
+            const int kk = 16 * ot + (l & 15);
+            double val = 0.0;
+            if (u < chi && kk < chi) val = M[(size_t(s) * chi + u) * chi + kk];
+            BT.push_back(T(val));
+          }
+    }
+  }
   L.free_all();
   nqs_status st;
+  if ((st = upload(&L.AF, AF)) != NQS_OK) return st;
+  if ((st = upload(&L.afoff, afoff)) != NQS_OK) return st;
+  if ((st = upload(&L.BT, BT)) != NQS_OK) return st;
+  if ((st = upload(&L.btoff, btoff)) != NQS_OK) return st;
   if ((st = upload(&L.A, A)) != NQS_OK) return st;
   if ((st = upload(&L.aoff, aoff)) != NQS_OK) return st;
   if ((st = upload(&L.v, v)) != NQS_OK) return st;
   if ((st = upload(&L.eta, eta)) != NQS_OK) return st;
   if ((st = upload(&L.w, w)) != NQS_OK) return st;
   if ((st = upload(&L.c, c)) != NQS_OK) return st;
+  return NQS_OK;
+}
+
+// round-to-nearest-even FP32 -> BF16 bit pattern (finite inputs)
+uint16_t to_bf16(float f) {
+  uint32_t b;
+  std::memcpy(&b, &f, 4);
+  b += 0x7FFFu + ((b >> 16) & 1u);
+  return uint16_t(b >> 16);
+}
+
+// BF16 A operands for the 16x16x32 MFMA: per site, k-steps of 32 over the
+// concatenated parent states (k = e_local * chip + kk, zero beyond d_i * chi),
+// [q][ot][lane][8]: lane l holds rows m = l%16 (unit o = 16 ot + m, the f32
+// output layout) and k = 32 q + 8 (l/16) + 0..7.
+nqs_status build_bf16(nqs_ansatz* a, const std::vector<double>& prm) {
+  const int K = a->K, chi = a->chi, CH = a->chip, NT = CH / 4;
+  std::vector<int64_t> aoff(K);
+  std::vector<uint16_t> A;
+  for (int i = 0; i < K; ++i) {
+    aoff[i] = int64_t(A.size());
+    const int e0 = a->pptr[i], d = a->pptr[i + 1] - e0;
+    const int KQ = (d * CH + 31) / 32;
+    for (int q = 0; q < KQ; ++q)
+      for (int ot = 0; ot < NT; ++ot)
+        for (int l = 0; l < 64; ++l)
+          for (int t = 0; t < 8; ++t) {
+            const int k = 32 * q + 8 * (l >> 4) + t;
+            const int el = k / CH, kk = k % CH;
+            const int o = ot * 16 + (l & 15);
+            const int s = o / CH, u = o % CH;
+            double val = 0.0;
+            if (el < d && u < chi && kk < chi) val = prm[a->offM[e0 + el] + (size_t(s) * chi + u) * chi + kk];
+            A.push_back(to_bf16(float(val)));
+          }
+  }
+  if (a->bfA) { (void)hipFree(a->bfA); a->bfA = nullptr; }
+  if (a->bfAoff) { (void)hipFree(a->bfAoff); a->bfAoff = nullptr; }
+  nqs_status st;
+  if ((st = upload(&a->bfA, A)) != NQS_OK) return st;
+  if ((st = upload(&a->bfAoff, aoff)) != NQS_OK) return st;
   return NQS_OK;
 }
 
@@ -430,6 +530,9 @@ nqs_status nqs_ansatz_create(nqs_ctx* ctx, int K, int n_alpha, int n_beta, int c
   std::vector<int> pp(a->pptr.begin(), a->pptr.end()), pi(a->pidx.begin(), a->pidx.end());
   if ((st = upload(&a->d_pptr, pp)) != NQS_OK) return st;
   if ((st = upload(&a->d_pidx, pi)) != NQS_OK) return st;
+  if ((st = upload(&a->d_offM, a->offM)) != NQS_OK) return st;
+  if ((st = upload(&a->d_offV, a->offV)) != NQS_OK) return st;
+  if ((st = upload(&a->d_offEta, a->offEta)) != NQS_OK) return st;
   *out = a.release();
   return NQS_OK;
 }
@@ -456,6 +559,7 @@ nqs_status nqs_ansatz_bind_params(nqs_ansatz* ans, const double* params, hipStre
   nqs_status st;
   if ((st = build_layout<double>(ans, prm, ans->L64)) != NQS_OK) return st;
   if ((st = build_layout<float>(ans, prm, ans->L32)) != NQS_OK) return st;
+  if ((st = build_bf16(ans, prm)) != NQS_OK) return st;
   if (ans->d_cb) { (void)hipFree(ans->d_cb); ans->d_cb = nullptr; }
   if (ans->d_cW) { (void)hipFree(ans->d_cW); ans->d_cW = nullptr; }
   if (ans->nh) {
@@ -632,9 +736,56 @@ nqs_status nqs_logpsi(nqs_ctx* ctx, const nqs_ansatz* ans, const uint64_t* sampl
   return NQS_OK;
 }
 
-nqs_status nqs_logpsi_vjp(nqs_ctx*, const nqs_ansatz*, const uint64_t*, int64_t, const double*, int32_t,
-                          double*, hipStream_t) {
-  return fail(NQS_EUNSUPPORTED, "vjp not built yet");
+nqs_status nqs_logpsi_vjp(nqs_ctx* ctx, const nqs_ansatz* ans, const uint64_t* samples, int64_t N,
+                          const double* cot, int32_t precision, double* grad, hipStream_t stream) {
+  if (!ctx || !ans || (!samples && N > 0) || N < 0 || (!cot && N > 0) || !grad)
+    return fail(NQS_EINVAL, "bad arguments");
+  if (!ans->bound) return fail(NQS_EINVAL, "parameters not bound");
+  if (precision != NQS_F64 && precision != NQS_F32)
+    return fail(NQS_EUNSUPPORTED, "the adjoint runs in FP64 or FP32");
+  DeviceGuard g(ctx->device);
+  nqs_status s = check_samples(ctx, samples, N, ans->K, ans->na, ans->nb, stream);
+  if (s != NQS_OK) return s;
+  if (N == 0) return NQS_OK;
+  const int64_t Rpad = (N + 15) / 16 * 16;
+  const int64_t per = std::max<int64_t>(64, (Rpad / 32 + 15) / 16 * 16);
+  const int rows_per_split = int(per);
+  const int nsplit = int((Rpad + per - 1) / per);
+  const int64_t np = ans->n_params;
+  const size_t hsz = size_t(ans->K) * Rpad * ans->chip;
+  const size_t esz = precision == NQS_F64 ? 8 : 4;
+  Scratch S(ctx);
+  void* Hbuf = S.get<unsigned char>(hsz * esz);
+  void* dcarry = S.get<unsigned char>(hsz * esz);
+  void* Dc = S.get<unsigned char>(size_t(Rpad) * 4 * ans->chip * esz);
+  void* Eeta = S.get<unsigned char>(size_t(Rpad) * ans->chip * esz);
+  double* lphi = S.get<double>(N);
+  int8_t* sphi = S.get<int8_t>(N);
+  double* gpart = S.get<double>(size_t(nsplit) * np);
+  double* cotp = S.get<double>(Rpad);
+  double* dth = ans->nh ? S.get<double>(size_t(N) * ans->nh) : nullptr;
+  if (S.oom) return fail(NQS_ENOMEM, "workspace allocation failed");
+  HIPCHK(hipMemsetAsync(dcarry, 0, hsz * esz, stream));
+  HIPCHK(hipMemsetAsync(gpart, 0, sizeof(double) * nsplit * np, stream));
+  HIPCHK(hipMemsetAsync(cotp, 0, sizeof(double) * Rpad, stream));
+  HIPCHK(hipMemcpyAsync(cotp, cot, sizeof(double) * N, hipMemcpyDeviceToDevice, stream));
+  if (precision == NQS_F64) {
+    HIPCHK(launch_psi_f64(ans->params(ans->L64), samples, N, lphi, sphi, stream, (double*)Hbuf, Rpad));
+    HIPCHK(launch_bwd_sweep_f64(ans->adj(ans->L64), samples, N, Rpad, cotp, (const double*)Hbuf,
+                                (double*)dcarry, (double*)Dc, (double*)Eeta, rows_per_split, nsplit, gpart,
+                                np, stream));
+  } else {
+    HIPCHK(launch_psi_f32(ans->params(ans->L32), samples, N, lphi, sphi, stream, (float*)Hbuf, Rpad));
+    HIPCHK(launch_bwd_sweep_f32(ans->adj(ans->L32), samples, N, Rpad, cotp, (const float*)Hbuf,
+                                (float*)dcarry, (float*)Dc, (float*)Eeta, rows_per_split, nsplit, gpart,
+                                np, stream));
+  }
+  if (ans->nh)
+    HIPCHK(launch_corr_backward(ans->corr(), samples, N, cotp, dth, rows_per_split, nsplit, ans->offB,
+                                ans->offWc, gpart, np, stream));
+  HIPCHK(launch_sum_parts(np, nsplit, gpart, grad, stream));
+  HIPCHK(hipStreamSynchronize(stream));
+  return NQS_OK;
 }
 
 nqs_status nqs_eloc(nqs_ctx* ctx, const nqs_instance* inst, const nqs_ansatz* ans,
