@@ -79,7 +79,10 @@ typedef struct {
   uint64_t seed;       /* Philox4x32-10 key (low word, high word) */
   uint64_t stream_id;  /* third and fourth Philox counter words */
   int32_t sample_base; /* added to the sample index in the Philox counter */
-  int32_t reserved;
+  int32_t max_rows_per_pass; /* 0 = evaluate all amplitude rows at once; otherwise rows are
+                                evaluated in passes over whole samples holding at most
+                                max(max_rows_per_pass, 1 + n_conn + n_eps) rows, which bounds
+                                the device memory of the call (nqs_eloc_workspace_bytes) */
 } nqs_eloc_opts;
 
 /* Per-call statistics (host struct, filled when a non-NULL pointer is passed). */
@@ -95,6 +98,7 @@ typedef struct {
   double E;              /* sum c Etilde_num / sum c |f|^2           (Eq. (17)) */
   double var;            /* sum c |f|^2 (E_loc - E)^2 / sum c |f|^2 */
   double ms_enumerate, ms_draw, ms_rows, ms_amplitude, ms_reduce;  /* stage times (device events) */
+  int64_t n_passes;      /* amplitude passes (see max_rows_per_pass) */
 } nqs_eloc_stats;
 
 /* ---- context --------------------------------------------------------- */
@@ -194,11 +198,84 @@ nqs_status nqs_rows(nqs_ctx* ctx, const nqs_instance* inst, const uint64_t* samp
                     uint64_t* Q, int64_t* rank, double* coef, uint64_t* m, int64_t* n_rows,
                     hipStream_t stream);
 
-/* Device bytes an nqs_eloc call of this shape will take from the pool at
- * most, given the number of amplitude rows it will evaluate (pass 0 to get
- * the row-independent part); used for admission by footprint. */
+/* Device bytes an nqs_eloc call of this shape takes from the context's pool
+ * at most.  With opts->max_rows_per_pass > 0 the bound holds for any sample
+ * data; otherwise pass the number of amplitude rows the call will evaluate
+ * (n_rows; 0 gives the row-independent part).  Used for admission by
+ * footprint in the serving loop. */
 nqs_status nqs_eloc_workspace_bytes(const nqs_instance* inst, const nqs_ansatz* ans, int64_t N,
                                     const nqs_eloc_opts* opts, int64_t n_rows, size_t* bytes);
+
+/* ---- serving: continuous batching of local-energy requests ------------- */
+
+typedef struct nqs_server nqs_server;
+
+/* One local-energy request.  samples and the outputs are caller-owned device
+ * buffers that must stay valid until the request's completion is returned;
+ * inst/ans must outlive it too. */
+typedef struct {
+  const nqs_instance* inst;
+  const nqs_ansatz* ans;
+  const uint64_t* samples;   /* device [N][2] */
+  int64_t N;
+  nqs_eloc_opts opts;        /* opts.max_rows_per_pass = 0: the server's default */
+  double* eloc;              /* device outputs as in nqs_eloc (nullable) */
+  double* etnum;
+  double* logabs;
+  int8_t* sign;
+  double* fsq;
+  double t_arrival;          /* host monotonic seconds (nqs_monotonic_seconds); 0 = now */
+  uint64_t user_tag;
+} nqs_request;
+
+typedef struct {
+  int64_t ticket;
+  uint64_t user_tag;
+  nqs_status status;         /* the nqs_eloc status of the request */
+  int32_t pad;
+  double t_submit;           /* arrival (host monotonic seconds) */
+  double t_start;            /* admission to a slot */
+  double t_end;              /* completion; latency = t_end - t_submit */
+  size_t footprint;          /* device bytes reserved for the request */
+  nqs_eloc_stats stats;
+  char message[256];         /* error message when status != NQS_OK */
+} nqs_completion;
+
+typedef struct {
+  size_t budget, reserved, peak_reserved;
+  int32_t in_flight, peak_in_flight;
+  int64_t queued, skips;
+} nqs_serve_status;
+
+/* Host monotonic clock used for arrival and completion times (seconds). */
+double nqs_monotonic_seconds(void);
+/* Device of a context. */
+int nqs_ctx_device(const nqs_ctx* ctx);
+
+/* Start a server on ctx with n_slots concurrent requests (one device stream
+ * each, 1..64) and a device-memory budget in bytes for all admitted requests;
+ * the context's pool is capped at the budget while the server lives.
+ * max_rows_per_pass (> 0) bounds the amplitude rows held per pass and hence
+ * each request's footprint (see nqs_eloc_opts). */
+nqs_status nqs_serve_create(nqs_ctx* ctx, int n_slots, size_t budget_bytes, int32_t max_rows_per_pass,
+                            nqs_server** out);
+/* Finish every queued and running request, then stop (completions not yet
+ * polled are dropped). */
+nqs_status nqs_serve_destroy(nqs_server* srv);
+/* Queue a request; *ticket identifies its completion.  A request is admitted
+ * when a slot is free and its footprint fits the unreserved budget (FIFO; a
+ * later request that fits may go ahead of a head that does not, at most 8
+ * times per head).  NQS_ENOMEM if its footprint exceeds the whole budget. */
+nqs_status nqs_serve_submit(nqs_server* srv, const nqs_request* req, int64_t* ticket);
+/* Device bytes the server would reserve for req. */
+nqs_status nqs_serve_footprint(nqs_server* srv, const nqs_request* req, size_t* bytes);
+/* Next completion, without blocking (NQS_EBUSY if none) or waiting up to
+ * timeout_s seconds (NQS_EBUSY on timeout). */
+nqs_status nqs_serve_poll(nqs_server* srv, nqs_completion* out);
+nqs_status nqs_serve_wait(nqs_server* srv, double timeout_s, nqs_completion* out);
+/* Budget, reserved bytes (current and peak), slots in use (current and
+ * peak), queue length and skip-ahead count. */
+nqs_status nqs_serve_info(nqs_server* srv, nqs_serve_status* out);
 
 /* ---- test hooks --------------------------------------------------------- */
 
@@ -207,6 +284,13 @@ nqs_status nqs_eloc_workspace_bytes(const nqs_instance* inst, const nqs_ansatz* 
 nqs_status nqs_ctx_fail_alloc_at(nqs_ctx* ctx, int64_t k);
 /* Bytes currently held by the context's workspace pool (in use, cached). */
 nqs_status nqs_ctx_pool_bytes(const nqs_ctx* ctx, size_t* in_use, size_t* cached);
+/* High-water mark of the pool's in-use bytes; reset != 0 restarts it at the
+ * current in-use value. */
+nqs_status nqs_ctx_pool_peak(nqs_ctx* ctx, size_t* peak, int reset);
+/* Cap the pool's device memory (in use + cached, bytes; 0 = no cap).  Cached
+ * blocks are released to stay under the cap; an allocation that cannot fit
+ * fails with NQS_ENOMEM. */
+nqs_status nqs_ctx_set_pool_limit(nqs_ctx* ctx, size_t bytes);
 
 #ifdef __cplusplus
 }

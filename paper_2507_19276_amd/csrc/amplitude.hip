@@ -445,15 +445,16 @@ __device__ inline double wave_sum(double x) {
 
 // Per sample n (one wavefront): E_loc(n) = H_nn + sum_rows coef * Psi(m)/Psi(n)
 // and Etilde_num(n) = |f_n|^2 H_nn + f_n sum_rows coef f_m Phi(m)/Phi(n).
-__global__ __launch_bounds__(256) void k_reduce(int64_t N, const int64_t* rowptr, const double* coef,
+__global__ __launch_bounds__(256) void k_reduce(int64_t n0, int64_t n1, const int64_t* rowptr,
+                                                int64_t row_base, const double* coef,
                                                 const double* lphi, const int8_t* sphi,
                                                 const double* lf, const int8_t* sf,
                                                 const double* hdiag, double* eloc, double* etnum,
                                                 double* logabs, int8_t* sign, double* fsq) {
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int64_t n = int64_t(blockIdx.x) * 4 + wv;
-  if (n >= N) return;
-  const int64_t r0 = rowptr[n], r1 = rowptr[n + 1];
+  const int64_t n = n0 + int64_t(blockIdx.x) * 4 + wv;
+  if (n >= n1) return;
+  const int64_t r0 = rowptr[n] - row_base, r1 = rowptr[n + 1] - row_base;
   const double lpn = lphi[r0], lfn = lf[r0];
   const int sn = int(sphi[r0]) * int(sf[r0]);
   double se = 0.0, st = 0.0;
@@ -578,13 +579,13 @@ hipError_t launch_corr_direct(const CorrParams& C, const uint64_t* m, int64_t R,
   return hipGetLastError();
 }
 
-hipError_t launch_reduce(int64_t N, const int64_t* rowptr, const double* coef, const double* lphi,
-                         const int8_t* sphi, const double* lf, const int8_t* sf, const double* hdiag,
-                         double* eloc, double* etnum, double* logabs, int8_t* sign, double* fsq,
-                         hipStream_t st) {
-  if (N <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_reduce, dim3(grid_for(N, 4)), dim3(256), 0, st, N, rowptr, coef, lphi, sphi, lf, sf,
-                     hdiag, eloc, etnum, logabs, sign, fsq);
+hipError_t launch_reduce(int64_t n0, int64_t n1, const int64_t* rowptr, int64_t row_base, const double* coef,
+                         const double* lphi, const int8_t* sphi, const double* lf, const int8_t* sf,
+                         const double* hdiag, double* eloc, double* etnum, double* logabs, int8_t* sign,
+                         double* fsq, hipStream_t st) {
+  if (n1 <= n0) return hipSuccess;
+  hipLaunchKernelGGL(k_reduce, dim3(grid_for(n1 - n0, 4)), dim3(256), 0, st, n0, n1, rowptr, row_base, coef,
+                     lphi, sphi, lf, sf, hdiag, eloc, etnum, logabs, sign, fsq);
   return hipGetLastError();
 }
 

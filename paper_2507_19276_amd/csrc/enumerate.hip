@@ -456,22 +456,23 @@ __global__ __launch_bounds__(1024) void k_row_counts(int64_t N, const int64_t* D
 // Pass 2: write the rows.  Unit (n, s) writes the deterministic rows of its
 // segment in rank order; segment 0 also writes the sample's own row and its
 // unique drawn rows.
-__global__ __launch_bounds__(256) void k_fill(HamDev H, EnumGeom G, const uint64_t* samples, int64_t N,
-                                              const uint64_t* masks, const uint32_t* segd_off,
-                                              const int64_t* rowptr, const int64_t* Dn,
+// Rows of samples [n0, n1) are written at (global row index - row_base).
+__global__ __launch_bounds__(256) void k_fill(HamDev H, EnumGeom G, const uint64_t* samples, int64_t n0,
+                                              int64_t n1, const uint64_t* masks, const uint32_t* segd_off,
+                                              const int64_t* rowptr, int64_t row_base, const int64_t* Dn,
                                               const int64_t* Un, const int32_t* urank,
                                               const double* ucoef, const uint64_t* um, int n_eps,
                                               Rows rows) {
   __shared__ Lists lists[4];
   const int wv = threadIdx.x >> 6, lane = lane_id();
   const int64_t unit = int64_t(blockIdx.x) * 4 + wv;
-  if (unit >= N * G.S) return;
-  const int64_t n = unit / G.S;
+  if (unit >= (n1 - n0) * G.S) return;
+  const int64_t n = n0 + unit / G.S;
   const int s = int(unit % G.S);
   const uint64_t lo = samples[2 * n], hi = samples[2 * n + 1];
   Lists& L = lists[wv];
   decode_lists(H, lo, hi, L);
-  const int64_t r0 = rowptr[n];
+  const int64_t r0 = rowptr[n] - row_base;
   int64_t pos = r0 + 1 + segd_off[n * G.S + s];
   const int c0 = s * G.cps, c1 = min(c0 + G.cps, G.nchunks);
   const uint64_t lt = __lanemask_lt();
@@ -612,13 +613,13 @@ hipError_t launch_row_counts(int64_t N, const int64_t* Dn, const int64_t* Un, in
   return hipGetLastError();
 }
 
-hipError_t launch_fill(const HamDev& H, const EnumGeom& G, const uint64_t* samples, int64_t N,
+hipError_t launch_fill(const HamDev& H, const EnumGeom& G, const uint64_t* samples, int64_t n0, int64_t n1,
                        const uint64_t* masks, const uint32_t* segd_off, const int64_t* rowptr,
-                       const int64_t* Dn, const int64_t* Un, const int32_t* urank, const double* ucoef,
-                       const uint64_t* um, int n_eps, Rows rows, hipStream_t st) {
-  if (N <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_fill, dim3(grid_for(N * G.S, 4)), dim3(256), 0, st, H, G, samples, N, masks,
-                     segd_off, rowptr, Dn, Un, urank, ucoef, um, n_eps, rows);
+                       int64_t row_base, const int64_t* Dn, const int64_t* Un, const int32_t* urank,
+                       const double* ucoef, const uint64_t* um, int n_eps, Rows rows, hipStream_t st) {
+  if (n1 <= n0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill, dim3(grid_for((n1 - n0) * G.S, 4)), dim3(256), 0, st, H, G, samples, n0, n1,
+                     masks, segd_off, rowptr, row_base, Dn, Un, urank, ucoef, um, n_eps, rows);
   return hipGetLastError();
 }
 

@@ -114,10 +114,10 @@ hipError_t launch_draw(const HamDev& H, const EnumGeom& G, const uint64_t* sampl
                        uint64_t* um, int64_t* Un, hipStream_t st);
 hipError_t launch_row_counts(int64_t N, const int64_t* Dn, const int64_t* Un, int64_t* rowptr,
                              hipStream_t st);
-hipError_t launch_fill(const HamDev& H, const EnumGeom& G, const uint64_t* samples, int64_t N,
+hipError_t launch_fill(const HamDev& H, const EnumGeom& G, const uint64_t* samples, int64_t n0, int64_t n1,
                        const uint64_t* masks, const uint32_t* segd_off, const int64_t* rowptr,
-                       const int64_t* Dn, const int64_t* Un, const int32_t* urank, const double* ucoef,
-                       const uint64_t* um, int n_eps, Rows rows, hipStream_t st);
+                       int64_t row_base, const int64_t* Dn, const int64_t* Un, const int32_t* urank,
+                       const double* ucoef, const uint64_t* um, int n_eps, Rows rows, hipStream_t st);
 hipError_t launch_diag(const HamDev& H, const uint64_t* samples, int64_t N, double* hdiag,
                        hipStream_t st);
 hipError_t launch_connected(const HamDev& H, const uint64_t* samples, int64_t N, uint64_t* m_out,
@@ -138,10 +138,10 @@ hipError_t launch_corr_rows(const CorrParams& C, const uint64_t* m, const int32_
                             double* lf, int8_t* sf, hipStream_t st);
 hipError_t launch_corr_direct(const CorrParams& C, const uint64_t* m, int64_t R, double* lf, int8_t* sf,
                               hipStream_t st);
-hipError_t launch_reduce(int64_t N, const int64_t* rowptr, const double* coef, const double* lphi,
-                         const int8_t* sphi, const double* lf, const int8_t* sf, const double* hdiag,
-                         double* eloc, double* etnum, double* logabs, int8_t* sign, double* fsq,
-                         hipStream_t st);
+hipError_t launch_reduce(int64_t n0, int64_t n1, const int64_t* rowptr, int64_t row_base, const double* coef,
+                         const double* lphi, const int8_t* sphi, const double* lf, const int8_t* sf,
+                         const double* hdiag, double* eloc, double* etnum, double* logabs, int8_t* sign,
+                         double* fsq, hipStream_t st);
 hipError_t launch_batch_sums(int64_t N, const double* counts, const double* eloc, const double* etnum,
                              const double* fsq, double* out /*[8]*/, hipStream_t st);
 hipError_t launch_gather_logpsi(int64_t N, const double* lphi, const int8_t* sphi, const double* lf,

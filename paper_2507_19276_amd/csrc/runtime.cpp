@@ -23,6 +23,18 @@ namespace {
 
 thread_local std::string g_err;
 
+// Allocation size classes of the workspace pool: multiples of 256 B up to
+// 64 KiB, above that the power-of-two octave split in 8 steps (<= 12.5%
+// rounding).  Blocks are reused only within the same class, so the bytes a
+// call holds are exactly the sum of the classes of its requests.
+size_t size_class(size_t bytes) {
+  size_t b = std::max<size_t>(256, (bytes + 255) & ~size_t(255));
+  if (b <= 65536) return b;
+  int k = 63 - __builtin_clzll(b);            // 2^k <= b < 2^(k+1)
+  const size_t step = size_t(1) << (k - 3);   // octave / 8
+  return (b + step - 1) / step * step;
+}
+
 nqs_status fail(nqs_status code, const char* fmt, ...) {
   char buf[512];
   va_list ap;
@@ -62,33 +74,46 @@ struct nqs_ctx {
   std::mutex mu;
   std::multimap<size_t, void*> free_blocks;   // cached blocks by size
   std::map<void*, size_t> sizes;              // every block we own
-  size_t in_use = 0, cached = 0;
+  size_t in_use = 0, cached = 0, peak = 0;
+  size_t cap = 0;                             // 0 = no limit on in_use + cached
   int64_t fail_at = 0;                        // test hook: k-th acquire fails
 
+  void drop_cache() {
+    for (auto& kv : free_blocks) { (void)hipFree(kv.second); sizes.erase(kv.second); }
+    free_blocks.clear();
+    cached = 0;
+  }
   void* acquire(size_t bytes) {
-    bytes = std::max<size_t>(256, (bytes + 255) & ~size_t(255));
+    bytes = size_class(bytes);
     std::lock_guard<std::mutex> lk(mu);
     if (fail_at > 0 && --fail_at == 0) return nullptr;
-    auto it = free_blocks.lower_bound(bytes);
-    if (it != free_blocks.end() && it->first <= bytes * 2) {
+    auto it = free_blocks.find(bytes);
+    if (it != free_blocks.end()) {
       void* p = it->second;
       size_t sz = it->first;
       free_blocks.erase(it);
       cached -= sz;
       in_use += sz;
+      peak = std::max(peak, in_use);
       return p;
     }
+    while (cap && in_use + cached + bytes > cap && !free_blocks.empty()) {
+      auto big = std::prev(free_blocks.end());          // release the largest cached block
+      (void)hipFree(big->second);
+      sizes.erase(big->second);
+      cached -= big->first;
+      free_blocks.erase(big);
+    }
+    if (cap && in_use + bytes > cap) return nullptr;
     void* p = nullptr;
     if (hipMalloc(&p, bytes) != hipSuccess) {
       (void)hipGetLastError();
-      // release the cache and retry once
-      for (auto& kv : free_blocks) { (void)hipFree(kv.second); sizes.erase(kv.second); }
-      free_blocks.clear();
-      cached = 0;
+      drop_cache();   // release the cache and retry once
       if (hipMalloc(&p, bytes) != hipSuccess) { (void)hipGetLastError(); return nullptr; }
     }
     sizes[p] = bytes;
     in_use += bytes;
+    peak = std::max(peak, in_use);
     return p;
   }
   void release(void* p) {
@@ -383,6 +408,8 @@ nqs_status nqs_ctx_create(int device, nqs_ctx** out) {
   return NQS_OK;
 }
 
+int nqs_ctx_device(const nqs_ctx* ctx) { return ctx ? ctx->device : -1; }
+
 nqs_status nqs_ctx_destroy(nqs_ctx* ctx) {
   if (!ctx) return NQS_OK;
   DeviceGuard g(ctx->device);
@@ -404,6 +431,23 @@ nqs_status nqs_ctx_pool_bytes(const nqs_ctx* ctx, size_t* in_use, size_t* cached
   std::lock_guard<std::mutex> lk(c->mu);
   if (in_use) *in_use = c->in_use;
   if (cached) *cached = c->cached;
+  return NQS_OK;
+}
+
+nqs_status nqs_ctx_pool_peak(nqs_ctx* ctx, size_t* peak, int reset) {
+  if (!ctx) return fail(NQS_EINVAL, "ctx is NULL");
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  if (peak) *peak = ctx->peak;
+  if (reset) ctx->peak = ctx->in_use;
+  return NQS_OK;
+}
+
+nqs_status nqs_ctx_set_pool_limit(nqs_ctx* ctx, size_t bytes) {
+  if (!ctx) return fail(NQS_EINVAL, "ctx is NULL");
+  DeviceGuard g(ctx->device);
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  ctx->cap = bytes;
+  if (bytes && ctx->in_use + ctx->cached > bytes) ctx->drop_cache();
   return NQS_OK;
 }
 
@@ -613,7 +657,7 @@ nqs_status run_amplitudes(const nqs_ansatz* a, int precision, const uint64_t* m,
 }
 
 struct Pipeline {
-  // per-sample
+  // per sample
   uint64_t *masks, *qpref, *segq, *Qn, *um;
   uint32_t* segd;
   int64_t *Dn, *Un, *rowptr;
@@ -621,8 +665,11 @@ struct Pipeline {
   double *ucoef, *hdiag;
   EnumGeom G;
   int qshift;
-  int64_t R;
+  int64_t R;                        // total rows
+  std::vector<int64_t> rowptr_host; // [N+1]
+  // rows of the current pass
   Rows rows;
+  int64_t rows_cap;
 };
 
 EnumGeom make_geom(int64_t n_conn, int64_t N) {
@@ -635,9 +682,17 @@ EnumGeom make_geom(int64_t n_conn, int64_t N) {
   return G;
 }
 
-// enumerate + screen + draw + rows; leaves R rows in P.rows (device)
-nqs_status build_rows(nqs_ctx* ctx, Scratch& S, const nqs_instance* inst, const uint64_t* samples,
-                      int64_t N, const nqs_eloc_opts& o, Pipeline& P, hipStream_t st, hipEvent_t* ev) {
+// largest number of rows any pass can hold: a pass takes whole samples, so it
+// holds at most max(max_rows_per_pass, rows of the largest sample)
+int64_t pass_rows_bound(const HamDev& H, const nqs_eloc_opts& o, int64_t total_rows) {
+  if (o.max_rows_per_pass <= 0) return total_rows;
+  const int64_t one = 1 + int64_t(H.n_conn) + std::max(o.n_eps, 0);
+  return std::max<int64_t>(o.max_rows_per_pass, one);
+}
+
+// enumerate + screen + draw + row pointer (host copy); no rows yet
+nqs_status count_and_draw(Scratch& S, const nqs_instance* inst, const uint64_t* samples, int64_t N,
+                          const nqs_eloc_opts& o, Pipeline& P, hipStream_t st, hipEvent_t* ev) {
   const HamDev& H = inst->H;
   P.G = make_geom(H.n_conn, N);
   int e2 = 0;
@@ -673,21 +728,44 @@ nqs_status build_rows(nqs_ctx* ctx, Scratch& S, const nqs_instance* inst, const 
     HIPCHK(hipMemsetAsync(P.Un, 0, sizeof(int64_t) * N, st));
   }
   HIPCHK(launch_row_counts(N, P.Dn, P.Un, P.rowptr, st));
-  if (ev) HIPCHK(hipEventRecord(ev[2], st));
-  int64_t R = 0;
-  HIPCHK(hipMemcpyAsync(&R, P.rowptr + N, sizeof(int64_t), hipMemcpyDeviceToHost, st));
-  HIPCHK(hipStreamSynchronize(st));
-  P.R = R;
-  P.rows.m = S.get<uint64_t>(size_t(R) * 2);
-  P.rows.coef = S.get<double>(R);
-  P.rows.owner = S.get<int32_t>(R);
-  P.rows.rank = S.get<int64_t>(R);
-  if (S.oom) return fail(NQS_ENOMEM, "row workspace allocation failed (%lld rows)", (long long)R);
-  HIPCHK(launch_fill(H, P.G, samples, N, P.masks, P.segd, P.rowptr, P.Dn, P.Un, P.urank, P.ucoef, P.um,
-                     std::max(ne, 1), P.rows, st));
   HIPCHK(launch_diag(H, samples, N, P.hdiag, st));
-  if (ev) HIPCHK(hipEventRecord(ev[3], st));
+  if (ev) HIPCHK(hipEventRecord(ev[2], st));
+  P.rowptr_host.resize(N + 1);
+  HIPCHK(hipMemcpyAsync(P.rowptr_host.data(), P.rowptr, sizeof(int64_t) * (N + 1), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  P.R = P.rowptr_host[N];
   return NQS_OK;
+}
+
+nqs_status alloc_rows(Scratch& S, Pipeline& P, int64_t cap) {
+  P.rows_cap = cap;
+  P.rows.m = S.get<uint64_t>(size_t(cap) * 2);
+  P.rows.coef = S.get<double>(cap);
+  P.rows.owner = S.get<int32_t>(cap);
+  P.rows.rank = S.get<int64_t>(cap);
+  if (S.oom) return fail(NQS_ENOMEM, "row workspace allocation failed (%lld rows)", (long long)cap);
+  return NQS_OK;
+}
+
+nqs_status fill_range(const nqs_instance* inst, const uint64_t* samples, int64_t n0, int64_t n1,
+                      const nqs_eloc_opts& o, Pipeline& P, hipStream_t st) {
+  HIPCHK(launch_fill(inst->H, P.G, samples, n0, n1, P.masks, P.segd, P.rowptr, P.rowptr_host[n0], P.Dn, P.Un,
+                     P.urank, P.ucoef, P.um, std::max(o.n_eps, 1), P.rows, st));
+  return NQS_OK;
+}
+
+// greedy split of [0, N) into sample ranges whose rows fit `cap`
+std::vector<std::pair<int64_t, int64_t>> plan_passes(const std::vector<int64_t>& rp, int64_t cap) {
+  std::vector<std::pair<int64_t, int64_t>> out;
+  const int64_t N = int64_t(rp.size()) - 1;
+  int64_t n0 = 0;
+  while (n0 < N) {
+    int64_t n1 = n0 + 1;
+    while (n1 < N && rp[n1 + 1] - rp[n0] <= cap) ++n1;
+    out.emplace_back(n0, n1);
+    n0 = n1;
+  }
+  return out;
 }
 
 nqs_status check_opts(const nqs_eloc_opts* o) {
@@ -696,6 +774,7 @@ nqs_status check_opts(const nqs_eloc_opts* o) {
   if (o->n_eps < 0) return fail(NQS_EINVAL, "n_eps < 0");
   if (o->n_eps > 1024) return fail(NQS_EUNSUPPORTED, "n_eps > 1024 per sample");
   if (o->precision < 0 || o->precision > 2) return fail(NQS_EINVAL, "unknown precision");
+  if (o->max_rows_per_pass < 0) return fail(NQS_EINVAL, "max_rows_per_pass < 0");
   return NQS_OK;
 }
 
@@ -806,40 +885,66 @@ nqs_status nqs_eloc(nqs_ctx* ctx, const nqs_instance* inst, const nqs_ansatz* an
     return NQS_OK;
   }
   Scratch S(ctx);
-  hipEvent_t ev[6] = {};
+  hipEvent_t ev[3] = {}, pe[3] = {};
   const bool timing = stats != nullptr;
-  if (timing)
+  if (timing) {
     for (auto& e : ev) HIPCHK(hipEventCreate(&e));
+    for (auto& e : pe) HIPCHK(hipEventCreate(&e));
+  }
   struct EvGuard {
-    hipEvent_t* e; bool on;
-    ~EvGuard() { if (on) for (int k = 0; k < 6; ++k) (void)hipEventDestroy(e[k]); }
-  } evg{ev, timing};
+    hipEvent_t* a; hipEvent_t* b; bool on;
+    ~EvGuard() { if (on) for (int k = 0; k < 3; ++k) { (void)hipEventDestroy(a[k]); (void)hipEventDestroy(b[k]); } }
+  } evg{ev, pe, timing};
   Pipeline P{};
-  if ((s = build_rows(ctx, S, inst, samples, N, *opts, P, stream, timing ? ev : nullptr)) != NQS_OK) return s;
+  if ((s = count_and_draw(S, inst, samples, N, *opts, P, stream, timing ? ev : nullptr)) != NQS_OK) return s;
   const int64_t R = P.R;
-  double* lphi = S.get<double>(R);
-  int8_t* sphi = S.get<int8_t>(R);
-  double* lf = S.get<double>(R);
-  int8_t* sf = S.get<int8_t>(R);
+  const int64_t cap = std::min<int64_t>(R, pass_rows_bound(inst->H, *opts, R));
+  auto passes = plan_passes(P.rowptr_host, cap);
+  int64_t cap_used = 0;
+  for (auto& pr : passes) cap_used = std::max(cap_used, P.rowptr_host[pr.second] - P.rowptr_host[pr.first]);
+  if ((s = alloc_rows(S, P, cap_used)) != NQS_OK) return s;
+  double* lphi = S.get<double>(cap_used);
+  int8_t* sphi = S.get<int8_t>(cap_used);
+  double* lf = S.get<double>(cap_used);
+  int8_t* sf = S.get<int8_t>(cap_used);
   double* theta = ans->nh ? S.get<double>(size_t(N) * ans->nh) : nullptr;
   double* el = eloc ? eloc : S.get<double>(N);
   double* et = etnum ? etnum : S.get<double>(N);
   double* f2 = fsq ? fsq : S.get<double>(N);
   double* sums = S.get<double>(8);
   if (S.oom) return fail(NQS_ENOMEM, "workspace allocation failed");
-  if ((s = run_amplitudes(ans, opts->precision, P.rows.m, R, lphi, sphi, stream)) != NQS_OK) return s;
-  if (ans->nh) {
-    HIPCHK(launch_corr_theta(ans->corr(), samples, N, theta, stream));
-    HIPCHK(launch_corr_rows(ans->corr(), P.rows.m, P.rows.owner, samples, theta, R, opts->precision, lf, sf,
-                            stream));
-  } else {
-    HIPCHK(hipMemsetAsync(lf, 0, sizeof(double) * R, stream));
-    HIPCHK(hipMemsetAsync(sf, 1, sizeof(int8_t) * R, stream));
+  if (ans->nh) HIPCHK(launch_corr_theta(ans->corr(), samples, N, theta, stream));
+  float ms_rows = 0, ms_amp = 0, ms_red = 0;
+  for (auto& pr : passes) {
+    const int64_t n0 = pr.first, n1 = pr.second;
+    const int64_t Rp = P.rowptr_host[n1] - P.rowptr_host[n0];
+    if (timing) HIPCHK(hipEventRecord(pe[0], stream));
+    if ((s = fill_range(inst, samples, n0, n1, *opts, P, stream)) != NQS_OK) return s;
+    if (timing) HIPCHK(hipEventRecord(pe[1], stream));
+    if ((s = run_amplitudes(ans, opts->precision, P.rows.m, Rp, lphi, sphi, stream)) != NQS_OK) return s;
+    if (timing) HIPCHK(hipEventRecord(pe[2], stream));
+    if (ans->nh) {
+      HIPCHK(launch_corr_rows(ans->corr(), P.rows.m, P.rows.owner, samples, theta, Rp, opts->precision, lf, sf,
+                              stream));
+    } else {
+      HIPCHK(hipMemsetAsync(lf, 0, sizeof(double) * Rp, stream));
+      HIPCHK(hipMemsetAsync(sf, 1, sizeof(int8_t) * Rp, stream));
+    }
+    HIPCHK(launch_reduce(n0, n1, P.rowptr, P.rowptr_host[n0], P.rows.coef, lphi, sphi, lf, sf, P.hdiag, el, et,
+                         logabs, sign, f2, stream));
+    if (timing) {
+      hipEvent_t done;
+      HIPCHK(hipEventCreate(&done));
+      HIPCHK(hipEventRecord(done, stream));
+      HIPCHK(hipEventSynchronize(done));
+      float t = 0;
+      HIPCHK(hipEventElapsedTime(&t, pe[0], pe[1])); ms_rows += t;
+      HIPCHK(hipEventElapsedTime(&t, pe[1], pe[2])); ms_amp += t;
+      HIPCHK(hipEventElapsedTime(&t, pe[2], done)); ms_red += t;
+      (void)hipEventDestroy(done);
+    }
   }
-  if (timing) HIPCHK(hipEventRecord(ev[4], stream));
-  HIPCHK(launch_reduce(N, P.rowptr, P.rows.coef, lphi, sphi, lf, sf, P.hdiag, el, et, logabs, sign, f2, stream));
   HIPCHK(launch_batch_sums(N, counts, el, et, f2, sums, stream));
-  if (timing) HIPCHK(hipEventRecord(ev[5], stream));
   double hs[8] = {0};
   if (stats) HIPCHK(hipMemcpyAsync(hs, sums, sizeof hs, hipMemcpyDeviceToHost, stream));
   HIPCHK(hipStreamSynchronize(stream));
@@ -857,12 +962,13 @@ nqs_status nqs_eloc(nqs_ctx* ctx, const nqs_instance* inst, const nqs_ansatz* an
     stats->E = hs[3];
     stats->var = hs[5];
     stats->n_zero_amp = int64_t(hs[6]);
+    stats->n_passes = int64_t(passes.size());
     float t = 0;
     HIPCHK(hipEventElapsedTime(&t, ev[0], ev[1])); stats->ms_enumerate = t;
     HIPCHK(hipEventElapsedTime(&t, ev[1], ev[2])); stats->ms_draw = t;
-    HIPCHK(hipEventElapsedTime(&t, ev[2], ev[3])); stats->ms_rows = t;
-    HIPCHK(hipEventElapsedTime(&t, ev[3], ev[4])); stats->ms_amplitude = t;
-    HIPCHK(hipEventElapsedTime(&t, ev[4], ev[5])); stats->ms_reduce = t;
+    stats->ms_rows = ms_rows;
+    stats->ms_amplitude = ms_amp;
+    stats->ms_reduce = ms_red;
   }
   return NQS_OK;
 }
@@ -879,8 +985,12 @@ nqs_status nqs_rows(nqs_ctx* ctx, const nqs_instance* inst, const uint64_t* samp
   if (N == 0) { if (n_rows) *n_rows = 0; return NQS_OK; }
   Scratch S(ctx);
   Pipeline P{};
-  if ((s = build_rows(ctx, S, inst, samples, N, *opts, P, stream, nullptr)) != NQS_OK) return s;
+  if ((s = count_and_draw(S, inst, samples, N, *opts, P, stream, nullptr)) != NQS_OK) return s;
   const int64_t R = P.R, w = std::min(R, cap);
+  if (w > 0) {
+    if ((s = alloc_rows(S, P, R)) != NQS_OK) return s;
+    if ((s = fill_range(inst, samples, 0, N, *opts, P, stream)) != NQS_OK) return s;
+  }
   if (row_ptr) HIPCHK(hipMemcpyAsync(row_ptr, P.rowptr, sizeof(int64_t) * (N + 1), hipMemcpyDeviceToDevice, stream));
   if (n_det) HIPCHK(hipMemcpyAsync(n_det, P.Dn, sizeof(int64_t) * N, hipMemcpyDeviceToDevice, stream));
   if (Q) HIPCHK(hipMemcpyAsync(Q, P.Qn, sizeof(uint64_t) * N, hipMemcpyDeviceToDevice, stream));
@@ -897,19 +1007,24 @@ nqs_status nqs_rows(nqs_ctx* ctx, const nqs_instance* inst, const uint64_t* samp
 nqs_status nqs_eloc_workspace_bytes(const nqs_instance* inst, const nqs_ansatz* ans, int64_t N,
                                     const nqs_eloc_opts* opts, int64_t n_rows, size_t* bytes) {
   if (!inst || !ans || !opts || !bytes || N < 0 || n_rows < 0) return fail(NQS_EINVAL, "bad arguments");
+  if (N == 0) { *bytes = 0; return NQS_OK; }
   const EnumGeom G = make_geom(inst->H.n_conn, N);
   const int64_t ne = std::max(opts->n_eps, 1);
-  auto al = [](size_t b) { return std::max<size_t>(256, (b + 255) & ~size_t(255)); };
+  auto al = [](size_t b) { return size_class(b); };
   size_t b = 0;
+  // count_and_draw
   b += 2 * al(size_t(N) * G.nchunks * 8);
   b += al(size_t(N) * G.S * 8) + al(size_t(N) * G.S * 4);
-  b += 4 * al(size_t(N) * 8) + al(size_t(N + 1) * 8);
+  b += 3 * al(size_t(N) * 8) + al(size_t(N + 1) * 8);
   b += al(size_t(N) * ne * 4) + al(size_t(N) * ne * 8) + al(size_t(N) * ne * 16);
-  b += 4 * al(size_t(N) * 8) + al(64) + al(4);
+  b += al(size_t(N) * 8);
+  // rows of the largest pass: m(16) coef(8) owner(4) rank(8) lphi(8) sphi(1) lf(8) sf(1)
+  const int64_t rows = opts->max_rows_per_pass > 0 ? pass_rows_bound(inst->H, *opts, 0) : n_rows;
+  b += al(size_t(rows) * 16) + al(size_t(rows) * 8) + al(size_t(rows) * 4) + al(size_t(rows) * 8);
+  b += al(size_t(rows) * 8) + al(size_t(rows)) + al(size_t(rows) * 8) + al(size_t(rows));
   if (ans->nh) b += al(size_t(N) * ans->nh * 8);
-  // per row: m(16) coef(8) owner(4) rank(8) lphi(8) sphi(1) lf(8) sf(1)
-  b += al(size_t(n_rows) * 16) + 3 * al(size_t(n_rows) * 8) + al(size_t(n_rows) * 4) + al(size_t(n_rows) * 8) +
-       2 * al(size_t(n_rows));
+  b += 3 * al(size_t(N) * 8) + al(64);     // outputs the caller did not provide, batch sums
+  b += al(4);                              // sample validation flag
   *bytes = b;
   return NQS_OK;
 }

@@ -32,7 +32,7 @@ class NqsError(RuntimeError):
 class ElocOpts(C.Structure):
     _fields_ = [("eps", C.c_double), ("n_eps", C.c_int32), ("precision", C.c_int32),
                 ("seed", C.c_uint64), ("stream_id", C.c_uint64), ("sample_base", C.c_int32),
-                ("reserved", C.c_int32)]
+                ("max_rows_per_pass", C.c_int32)]
 
 
 class ElocStats(C.Structure):
@@ -40,7 +40,7 @@ class ElocStats(C.Structure):
                 ("n_det_rows", C.c_int64), ("n_draw_rows", C.c_int64), ("n_zero_amp", C.c_int64),
                 ("sum_c", C.c_double), ("B", C.c_double), ("E", C.c_double), ("var", C.c_double),
                 ("ms_enumerate", C.c_double), ("ms_draw", C.c_double), ("ms_rows", C.c_double),
-                ("ms_amplitude", C.c_double), ("ms_reduce", C.c_double)]
+                ("ms_amplitude", C.c_double), ("ms_reduce", C.c_double), ("n_passes", C.c_int64)]
 
     def to_dict(self) -> Dict[str, float]:
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -65,6 +65,8 @@ def lib():
     L.nqs_ctx_destroy.argtypes = [_p]
     L.nqs_ctx_fail_alloc_at.argtypes = [_p, C.c_int64]
     L.nqs_ctx_pool_bytes.argtypes = [_p, C.POINTER(C.c_size_t), C.POINTER(C.c_size_t)]
+    L.nqs_ctx_pool_peak.argtypes = [_p, C.POINTER(C.c_size_t), C.c_int]
+    L.nqs_ctx_set_pool_limit.argtypes = [_p, C.c_size_t]
     L.nqs_instance_create.argtypes = [_p, C.c_int, C.c_int, C.c_int, _p, _p, C.c_double, C.POINTER(_p)]
     L.nqs_instance_destroy.argtypes = [_p]
     L.nqs_instance_n_conn.argtypes = [_p]
@@ -113,10 +115,10 @@ def _samples(s) -> torch.Tensor:
 
 
 def opts(eps: float = 0.0, n_eps: int = 0, precision="f64", seed: int = 0, stream_id: int = 0,
-         sample_base: int = 0) -> ElocOpts:
+         sample_base: int = 0, max_rows_per_pass: int = 0) -> ElocOpts:
     p = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
     return ElocOpts(float(eps), int(n_eps), p, int(seed) & 0xFFFFFFFFFFFFFFFF,
-                    int(stream_id) & 0xFFFFFFFFFFFFFFFF, int(sample_base), 0)
+                    int(stream_id) & 0xFFFFFFFFFFFFFFFF, int(sample_base), int(max_rows_per_pass))
 
 
 class Context:
@@ -133,6 +135,14 @@ class Context:
         a, b = C.c_size_t(), C.c_size_t()
         check(lib().nqs_ctx_pool_bytes(self.h, C.byref(a), C.byref(b)))
         return a.value, b.value
+
+    def pool_peak(self, reset: bool = False) -> int:
+        a = C.c_size_t()
+        check(lib().nqs_ctx_pool_peak(self.h, C.byref(a), 1 if reset else 0))
+        return a.value
+
+    def set_pool_limit(self, nbytes: int):
+        check(lib().nqs_ctx_set_pool_limit(self.h, int(nbytes)))
 
     def close(self):
         if self.h:
@@ -241,7 +251,7 @@ class Ansatz:
 
 def eloc(ctx: Context, inst: Instance, ans: Ansatz, samples, counts: Optional[torch.Tensor] = None,
          eps: float = 0.0, n_eps: int = 0, precision="f64", seed: int = 0, stream_id: int = 0,
-         sample_base: int = 0, want_stats: bool = True):
+         sample_base: int = 0, want_stats: bool = True, max_rows_per_pass: int = 0):
     """Semi-stochastic local energies; returns (dict of device tensors, stats dict or None)."""
     s = _samples(samples)
     N = s.shape[0]
@@ -254,7 +264,7 @@ def eloc(ctx: Context, inst: Instance, ans: Ansatz, samples, counts: Optional[to
         "fsq": torch.empty(N, dtype=torch.float64, device=dev),
     }
     c = None if counts is None else counts.to(dtype=torch.float64, device=dev).contiguous()
-    o = opts(eps, n_eps, precision, seed, stream_id, sample_base)
+    o = opts(eps, n_eps, precision, seed, stream_id, sample_base, max_rows_per_pass)
     st = ElocStats()
     check(lib().nqs_eloc(ctx.h, inst.h, ans.h, _ptr(s), _ptr(c), N, C.byref(o), _ptr(out["eloc"]),
                          _ptr(out["etnum"]), _ptr(out["logabs"]), _ptr(out["sign"]), _ptr(out["fsq"]),
@@ -286,9 +296,10 @@ def rows(ctx: Context, inst: Instance, samples, eps: float = 0.0, n_eps: int = 0
     return dict(row_ptr=row_ptr, n_det=n_det, Q=Q, rank=rank[:R], coef=coef[:R], m=m[:R], n_rows=R)
 
 
-def workspace_bytes(inst: Instance, ans: Ansatz, N: int, n_rows: int, eps=0.0, n_eps=0, precision="f64") -> int:
+def workspace_bytes(inst: Instance, ans: Ansatz, N: int, n_rows: int = 0, eps=0.0, n_eps=0, precision="f64",
+                    max_rows_per_pass: int = 0) -> int:
     b = C.c_size_t()
-    o = opts(eps, n_eps, precision)
+    o = opts(eps, n_eps, precision, max_rows_per_pass=max_rows_per_pass)
     check(lib().nqs_eloc_workspace_bytes(inst.h, ans.h, int(N), C.byref(o), int(n_rows), C.byref(b)))
     return b.value
 
@@ -313,3 +324,128 @@ class LogPsi(torch.autograd.Function):
         (s,) = ctx_.saved_tensors
         grad = ctx_.ans.vjp(s, g.contiguous(), ctx_.precision)
         return grad, None, None, None
+
+
+# ---------------------------------------------------------------------------
+# serving
+# ---------------------------------------------------------------------------
+
+class Request(C.Structure):
+    _fields_ = [("inst", _p), ("ans", _p), ("samples", _p), ("N", C.c_int64), ("opts", ElocOpts),
+                ("eloc", _p), ("etnum", _p), ("logabs", _p), ("sign", _p), ("fsq", _p),
+                ("t_arrival", C.c_double), ("user_tag", C.c_uint64)]
+
+
+class Completion(C.Structure):
+    _fields_ = [("ticket", C.c_int64), ("user_tag", C.c_uint64), ("status", C.c_int), ("pad", C.c_int32),
+                ("t_submit", C.c_double), ("t_start", C.c_double), ("t_end", C.c_double),
+                ("footprint", C.c_size_t), ("stats", ElocStats), ("message", C.c_char * 256)]
+
+
+class ServeStatus(C.Structure):
+    _fields_ = [("budget", C.c_size_t), ("reserved", C.c_size_t), ("peak_reserved", C.c_size_t),
+                ("in_flight", C.c_int32), ("peak_in_flight", C.c_int32), ("queued", C.c_int64),
+                ("skips", C.c_int64)]
+
+
+def _serve_lib():
+    L = lib()
+    if not getattr(L, "_serve_ready", False):
+        L.nqs_monotonic_seconds.restype = C.c_double
+        L.nqs_serve_create.argtypes = [_p, C.c_int, C.c_size_t, C.c_int32, C.POINTER(_p)]
+        L.nqs_serve_destroy.argtypes = [_p]
+        L.nqs_serve_submit.argtypes = [_p, C.POINTER(Request), C.POINTER(C.c_int64)]
+        L.nqs_serve_footprint.argtypes = [_p, C.POINTER(Request), C.POINTER(C.c_size_t)]
+        L.nqs_serve_poll.argtypes = [_p, C.POINTER(Completion)]
+        L.nqs_serve_wait.argtypes = [_p, C.c_double, C.POINTER(Completion)]
+        L.nqs_serve_info.argtypes = [_p, C.POINTER(ServeStatus)]
+        L._serve_ready = True
+    return L
+
+
+def monotonic() -> float:
+    return _serve_lib().nqs_monotonic_seconds()
+
+
+class Server:
+    """Continuous-batching server over a context: n_slots concurrent requests
+    (one device stream each) admitted by exact device-memory footprint within
+    budget_bytes.  Requests keep their tensors alive until completion."""
+
+    def __init__(self, ctx: Context, n_slots: int, budget_bytes: int, max_rows_per_pass: int):
+        L = _serve_lib()
+        h = _p()
+        check(L.nqs_serve_create(ctx.h, int(n_slots), int(budget_bytes), int(max_rows_per_pass), C.byref(h)))
+        self.h = h
+        self.ctx = ctx
+        self._live = {}
+
+    def _request(self, inst, ans, samples, out, eps, n_eps, precision, seed, stream_id, t_arrival, tag):
+        s = _samples(samples)
+        r = Request(inst.h, ans.h, _ptr(s), s.shape[0], opts(eps, n_eps, precision, seed, stream_id),
+                    _ptr(out["eloc"]), _ptr(out["etnum"]), _ptr(out["logabs"]), _ptr(out["sign"]),
+                    _ptr(out["fsq"]), float(t_arrival), int(tag))
+        return r, s
+
+    def submit(self, inst: Instance, ans: Ansatz, samples, eps=0.0, n_eps=0, precision="f64", seed=0,
+               stream_id=0, t_arrival=0.0, tag=0) -> int:
+        s = _samples(samples)
+        N = s.shape[0]
+        dev = s.device
+        out = {"eloc": torch.empty(N, dtype=torch.float64, device=dev),
+               "etnum": torch.empty(N, dtype=torch.float64, device=dev),
+               "logabs": torch.empty(N, dtype=torch.float64, device=dev),
+               "sign": torch.empty(N, dtype=torch.int8, device=dev),
+               "fsq": torch.empty(N, dtype=torch.float64, device=dev)}
+        r, s = self._request(inst, ans, s, out, eps, n_eps, precision, seed, stream_id, t_arrival, tag)
+        torch.cuda.current_stream().synchronize()   # inputs are complete before another stream reads them
+        t = C.c_int64()
+        check(_serve_lib().nqs_serve_submit(self.h, C.byref(r), C.byref(t)))
+        self._live[t.value] = (s, out)
+        return t.value
+
+    def footprint(self, inst, ans, samples, eps=0.0, n_eps=0, precision="f64") -> int:
+        s = _samples(samples)
+        dummy = {k: None for k in ("eloc", "etnum", "logabs", "sign", "fsq")}
+        r, _ = self._request(inst, ans, s, dummy, eps, n_eps, precision, 0, 0, 0.0, 0)
+        b = C.c_size_t()
+        check(_serve_lib().nqs_serve_footprint(self.h, C.byref(r), C.byref(b)))
+        return b.value
+
+    def _done(self, c: Completion):
+        s, out = self._live.pop(c.ticket)
+        return dict(ticket=c.ticket, tag=c.user_tag, status=c.status, t_submit=c.t_submit, t_start=c.t_start,
+                    t_end=c.t_end, footprint=c.footprint, stats=c.stats.to_dict(),
+                    message=c.message.decode(), out=out)
+
+    def poll(self):
+        c = Completion()
+        rc = _serve_lib().nqs_serve_poll(self.h, C.byref(c))
+        if rc == NQS_EBUSY:
+            return None
+        check(rc)
+        return self._done(c)
+
+    def wait(self, timeout_s: float = 60.0):
+        c = Completion()
+        rc = _serve_lib().nqs_serve_wait(self.h, float(timeout_s), C.byref(c))
+        if rc == NQS_EBUSY:
+            return None
+        check(rc)
+        return self._done(c)
+
+    def info(self) -> Dict[str, int]:
+        st = ServeStatus()
+        check(_serve_lib().nqs_serve_info(self.h, C.byref(st)))
+        return {k: getattr(st, k) for k, _ in st._fields_}
+
+    def close(self):
+        if self.h:
+            _serve_lib().nqs_serve_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
