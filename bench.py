@@ -1,23 +1,53 @@
 """Throughput of the semi-stochastic local energy on one MI355X.
 
-One step = one nqs_eloc call over the whole synthetic batch of the chain
-workload (K = 20 spatial orbitals, 10a+10b, chain BDG-RNN chi = 16, 4096 unique
-samples, eps = 1e-3, N_eps = 64): enumerate every connected determinant,
-screen, draw, evaluate the amplitude of every row, reduce.  Inputs (integrals,
-parameters, samples) are resident in HBM before the timed region.
+Default: one step = one nqs_eloc call over the whole synthetic batch of the
+chain workload (K = 20 spatial orbitals, 10a+10b, chain BDG-RNN chi = 16, 4096
+unique samples, eps = 1e-3, N_eps = 64): enumerate every connected
+determinant, screen, draw, evaluate the amplitude of every row, reduce.
+Integrals, parameters and samples are resident in HBM before the timed
+region; outputs stay on the device.  The headline precision is FP32 bond
+contractions (FP64 Hamiltonian elements, ratios and sums); FP64 and BF16 are
+timed alongside.  The CPU-baseline leg runs the FP64 oracle on the same
+4096 samples with the draws of one GPU step and reports the GPU error
+against it.
 
-Prints one JSON line (see the design doc for the fields).
+--serve: the serving workload instead (500 Poisson-arriving requests over 12
+resident instances, norb in {12,20,36,50} x chi in {16,32,64}, BF16 path,
+eps = 1e-2, N_eps = 100, batch sizes log-uniform in [256, 16384]) at 0.8 x
+the measured capacity; reports total local energies/s and latency
+percentiles.
+
+Prints one JSON line.
 """
 import argparse
 import json
+import math
 import os
 import sys
+import threading
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 WORKLOAD = "c2"
+PEAKS = {"f64": 78.6, "f32": 157.3, "bf16": 2500.0}   # MI355X dense MFMA, TFLOP/s
+# HBM bytes per amplitude row of the FP32 bond-contraction kernel from the
+# FETCH_SIZE / WRITE_SIZE counters (copy-calibrated) recorded in
+# profiles/k_psi_chain_K20_chi16_N4096_pmc.txt; valid only for the amplitude
+# source they were taken on (first 16 hex digits of its sha256).
+MEASURED_TRAFFIC = {"f32": {"amplitude_sha16": "0fb40e876bf0d6ef", "bytes_per_row": 25.02}}
+
+
+def measured_traffic(prec, rows):
+    import hashlib
+    rec = MEASURED_TRAFFIC.get(prec)
+    if rec is None:
+        return None
+    src = os.path.join(ROOT, "paper_2507_19276_amd", "csrc", "amplitude.hip")
+    if hashlib.sha256(open(src, "rb").read()).hexdigest()[:16] != rec["amplitude_sha16"]:
+        return None
+    return rec["bytes_per_row"] * rows
 
 
 def algorithmic_flops_per_row(chi, parent_ptr):
@@ -25,34 +55,31 @@ def algorithmic_flops_per_row(chi, parent_ptr):
     return 8 * chi * chi * int(parent_ptr[-1])
 
 
-def cpu_baseline(w, n_sub, eps, n_eps, seed):
+def cpu_baseline(w, seed, gpu_out):
+    """The FP64 oracle on the full batch with the draws of the GPU step that
+    used `seed`; returns the baseline record and the GPU error against it."""
     import numpy as np
     import oracle
     threads = os.cpu_count() or 1
-    sub = w.samples[:n_sub]
     t0 = time.perf_counter()
-    oracle.eloc(w.K, w.n_alpha, w.n_beta, w.h, w.eri, w.chi, w.parent_ptr, w.parent_idx, w.n_hidden,
-                w.params, sub, eps=eps, n_eps=n_eps, seed=seed, stream=0, nthreads=threads)
+    ref = oracle.eloc(w.K, w.n_alpha, w.n_beta, w.h, w.eri, w.chi, w.parent_ptr, w.parent_idx, w.n_hidden,
+                      w.params, w.samples, eps=w.eps, n_eps=w.n_eps, seed=seed, stream=0, nthreads=threads)
     dt = time.perf_counter() - t0
-    return {"value": n_sub / dt, "unit": "local energies/s", "cores": threads, "kind": "oracle",
-            "sample": f"first {n_sub} of {w.n_samples} samples of the same workload, FP64 oracle, "
-                      f"{dt:.1f} s"}
+    rec = {"value": w.n_samples / dt, "unit": "local energies/s", "cores": threads, "kind": "oracle",
+           "sample": f"all {w.n_samples} samples of the benchmark batch, FP64 oracle, {dt:.1f} s"}
+    e_ref = ref["eloc"]
+    E_ref = ref["etnum"].sum() / ref["fsq"].sum()
+    se = math.sqrt((ref["fsq"] * (e_ref - E_ref) ** 2).sum() / ref["fsq"].sum() / w.n_samples)
+    tau = 1e-3 * float(np.sqrt(np.mean(e_ref ** 2)))
+    errs = {}
+    for prec, (el, E) in gpu_out.items():
+        r = np.abs(el - e_ref) / np.maximum(np.abs(e_ref), tau)
+        errs[prec] = {"p50": float(np.median(r)), "p99": float(np.quantile(r, 0.99)), "max": float(r.max()),
+                      "dE_over_SE": abs(E - E_ref) / se}
+    return rec, errs
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--precision", default="f32", choices=["f64", "f32", "bf16"])
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-samples", type=int, default=4096)
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path "
-              "(samples would be sharded across GPUs with one scalar all-reduce)", file=sys.stderr)
-        sys.exit(2)
-
+def run_eloc_bench(args):
     import numpy as np
     import torch
     from paper_2507_19276_amd import nqs, workloads
@@ -65,33 +92,45 @@ def main():
     ans.bind(w.params)
     samples = torch.from_numpy(w.samples.view(np.int64)).cuda().contiguous()
     N = w.n_samples
+    if args.copy_calibration_mib:
+        nbytes = args.copy_calibration_mib << 20
+        a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        print(f"# copy calibration: {nbytes} bytes read, {nbytes} bytes written", file=sys.stderr)
 
     def step(k, prec):
         return nqs.eloc(ctx, inst, ans, samples, eps=w.eps, n_eps=w.n_eps, precision=prec,
                         seed=w.seed + k, stream_id=0)
 
-    results = {}
-    for prec in dict.fromkeys([args.precision, "f64", "f32", "bf16"]):
+    precs = list(dict.fromkeys(args.precisions.split(",")))
+    head_prec = precs[0]
+    results, keep = {}, {}
+    for prec in precs:
         for k in range(args.warmup):
             step(k, prec)
         torch.cuda.synchronize()
-        psi_ms, rows = [], []
+        amp_ms, rows = [], []
         t0 = time.perf_counter()
         for k in range(args.steps):
             out, st = step(1000 + k, prec)
-            psi_ms.append(st["ms_amplitude"])
+            amp_ms.append(st["ms_amplitude"])
             rows.append(st["n_rows"])
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
-        results[prec] = dict(dt=dt, psi_ms=float(np.mean(psi_ms)), rows=float(np.mean(rows)), st=st)
+        results[prec] = dict(dt=dt, amp_ms=float(np.mean(amp_ms)), rows=float(np.mean(rows)), st=st)
         print(f"# {prec}: {args.steps} steps in {dt:.3f} s, rows/step {np.mean(rows):.0f}, "
-              f"amplitude kernel {np.mean(psi_ms):.3f} ms", file=sys.stderr, flush=True)
+              f"amplitude kernel {np.mean(amp_ms):.3f} ms", file=sys.stderr, flush=True)
+        if not args.no_cpu_baseline:
+            out, st = step(7, prec)
+            keep[prec] = (out["eloc"].cpu().numpy(), st["E"])
 
-    head = results[args.precision]
+    head = results[head_prec]
     value = args.steps * N / head["dt"]
     flops = algorithmic_flops_per_row(w.chi, w.parent_ptr) * head["rows"]
-    achieved = flops / (head["psi_ms"] * 1e-3) / 1e12
-    peak = {"f64": 78.6, "f32": 157.3, "bf16": 2500.0}[args.precision]
+    achieved = flops / (head["amp_ms"] * 1e-3) / 1e12
+    peak = PEAKS[head_prec]
     line = {
         "metric": "local energies/sec at fixed bond dim D",
         "value": value,
@@ -103,20 +142,151 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": args.precision,
+        "dtype": head_prec,
         "data": "synthetic",
         "config": {"workload": "chain K=20 10a+10b, BDG-RNN chain chi=16, 4096 unique samples, "
-                               "eps=1e-3, N_eps=64", "global_batch": N, "precision": args.precision},
+                               "eps=1e-3, N_eps=64", "global_batch": N, "precision": head_prec},
         "rows_per_step": head["rows"],
-        "by_precision": {p: {"value": args.steps * N / r["dt"], "amplitude_ms": r["psi_ms"]}
-                         for p, r in results.items()},
+        "by_precision": {p: {"value": args.steps * N / r["dt"], "amplitude_ms": r["amp_ms"],
+                             "ms_per_step": r["dt"] / args.steps * 1e3} for p, r in results.items()},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                     "frac": achieved / peak, "traffic": None,
+                     "frac": achieved / peak,
+                     "traffic": args.traffic_bytes if args.traffic_bytes else measured_traffic(head_prec, head["rows"]),
                      "kernel": "k_psi (bond contractions)"},
     }
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(w, args.cpu_samples, w.eps, w.n_eps, w.seed)
+        rec, errs = cpu_baseline(w, w.seed + 7, keep)
+        line["cpu_baseline"] = rec
+        line["eloc_error_vs_fp64_oracle"] = errs
     print(json.dumps(line), flush=True)
+
+
+def run_serve_bench(args):
+    import numpy as np
+    import torch
+    from paper_2507_19276_amd import nqs, workloads
+
+    torch.cuda.set_device(0)
+    ctx = nqs.Context(0)
+    objs, pools = [], []
+    for k, s in enumerate(workloads.serving_instances()):
+        inst = nqs.Instance(ctx, s["K"], s["n_alpha"], s["n_beta"], s["h"], s["eri"])
+        ans = nqs.Ansatz(ctx, s["K"], s["n_alpha"], s["n_beta"], s["chi"], s["parent_ptr"], s["parent_idx"], 0)
+        ans.bind(s["params"])
+        objs.append((s, inst, ans))
+        pool = workloads.random_onvs(s["K"], s["n_alpha"], s["n_beta"], 16384, 500 + k)
+        pools.append(torch.from_numpy(pool.view(np.int64)).cuda().contiguous())
+    eps, n_eps, prec = 1e-2, 100, "bf16"
+    # capacity: per-sample service time of every instance, one request at a time
+    tps = []
+    for (s, inst, ans), pool in zip(objs, pools):
+        n = 2048
+        nqs.eloc(ctx, inst, ans, pool[:n], eps=eps, n_eps=n_eps, precision=prec, seed=1, max_rows_per_pass=args.max_rows)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        nqs.eloc(ctx, inst, ans, pool[:n], eps=eps, n_eps=n_eps, precision=prec, seed=2, max_rows_per_pass=args.max_rows)
+        torch.cuda.synchronize()
+        tps.append((time.perf_counter() - t0) / n)
+    reqs = workloads.serving_requests(args.requests, 1.0, len(objs), seed=20250725)
+    mean_service = float(np.mean([r["n"] * tps[r["instance"]] for r in reqs]))
+    capacity = 1.0 / mean_service
+    lam = args.load * capacity
+    print(f"# serving: capacity {capacity:.2f} req/s (serial), arrival rate {lam:.2f} req/s", file=sys.stderr, flush=True)
+    gaps = np.random.default_rng(7).exponential(1.0 / lam, args.requests)
+    t_arr = np.cumsum(gaps) - gaps[0]
+    srv = nqs.Server(ctx, n_slots=args.slots, budget_bytes=args.budget_gib << 30, max_rows_per_pass=args.max_rows)
+    rng = np.random.default_rng(11)
+    total = {"n": 0}
+    lat, qd, nsamp = [], [], []
+    done = threading.Event()
+
+    def collector():
+        got = 0
+        while got < args.requests:
+            c = srv.wait(300.0)
+            if c is None:
+                break
+            if c["status"] != 0:
+                print("# request failed:", c["message"], file=sys.stderr)
+            lat.append(c["t_end"] - c["t_submit"])
+            qd.append(c["t_start"] - c["t_submit"])
+            nsamp.append(c["stats"]["n_samples"])
+            got += 1
+        done.set()
+
+    th = threading.Thread(target=collector)
+    th.start()
+    t_base = nqs.monotonic() + 0.05
+    for k, r in enumerate(reqs):
+        s, inst, ans = objs[r["instance"]]
+        off = int(rng.integers(0, 16384 - r["n"] + 1))
+        smp = pools[r["instance"]][off:off + r["n"]]
+        target = t_base + t_arr[k]
+        while nqs.monotonic() < target:
+            time.sleep(min(0.002, max(0.0, target - nqs.monotonic())))
+        srv.submit(inst, ans, smp, eps=eps, n_eps=n_eps, precision=prec, seed=r["seed"], t_arrival=target, tag=k)
+    done.wait()
+    th.join()
+    t_end = nqs.monotonic()
+    info = srv.info()
+    srv.close()
+    makespan = t_end - t_base
+    lat_ms = np.array(lat) * 1e3
+    line = {
+        "metric": "serving: total local energies/s with p50/p99 request latency",
+        "value": float(np.sum(nsamp)) / makespan,
+        "unit": "local energies/s",
+        "n_gpus": 1,
+        "steps": args.requests,
+        "warmup": 0,
+        "ms_per_step": makespan / args.requests * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": prec,
+        "data": "synthetic",
+        "config": {"workload": "serving: 12 instances norb {12,20,36,50} x chi {16,32,64}, half filling, "
+                               "NN+NNN BDG-RNN, eps=1e-2, N_eps=100, batch log-uniform 256-16384",
+                   "requests": args.requests, "arrival_rate_hz": lam, "load": args.load,
+                   "slots": args.slots, "budget_gib": args.budget_gib, "max_rows_per_pass": args.max_rows},
+        "latency_ms": {"p50": float(np.percentile(lat_ms, 50)), "p99": float(np.percentile(lat_ms, 99)),
+                       "max": float(lat_ms.max()), "mean": float(lat_ms.mean())},
+        "queue_delay_ms": {"p50": float(np.percentile(qd, 50) * 1e3), "p99": float(np.percentile(qd, 99) * 1e3)},
+        "capacity_req_per_s_serial": capacity,
+        "peak_in_flight": info["peak_in_flight"],
+        "peak_reserved_gib": info["peak_reserved"] / 2 ** 30,
+        "completed": len(lat),
+    }
+    print(json.dumps(line), flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--precisions", default="f32,f64,bf16",
+                    help="comma list; the first is the headline")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="run one device copy of this size first (scales PMC byte counters)")
+    ap.add_argument("--traffic-bytes", type=float, default=None,
+                    help="HBM bytes per amplitude-kernel launch from rocprofv3 PMC counters")
+    ap.add_argument("--serve", action="store_true")
+    ap.add_argument("--requests", type=int, default=500)
+    ap.add_argument("--load", type=float, default=0.8)
+    ap.add_argument("--slots", type=int, default=4)
+    ap.add_argument("--budget-gib", type=int, default=64)
+    ap.add_argument("--max-rows", type=int, default=4_000_000)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(samples would be sharded across GPUs with one scalar all-reduce)", file=sys.stderr)
+        sys.exit(2)
+    if args.serve:
+        run_serve_bench(args)
+    else:
+        run_eloc_bench(args)
 
 
 if __name__ == "__main__":
