@@ -11,11 +11,10 @@
 //
 // Bond contractions run on MFMA in the transposed form
 //   H_i^T [4chi x rows] = W_i^T [4chi x d_i chi] . X_i^T [d_i chi x rows]
-// so that one wavefront owns 16 rows (the N dimension of a 16x16 MFMA tile)
-// and every lane holds 4 consecutive hidden units of one row and candidate:
-// the epilogue (P^s, mask, log, sign, carry) then needs only two cross-lane
-// exchanges per quantity.  Carried hidden states live in a per-wavefront LDS
-// ring of W = (max parent offset + 1) slots.
+// so that rows are the N dimension of 16x16 MFMA tiles and every lane holds 4
+// consecutive hidden units of one row and candidate in the MFMA output layout.
+// Carried hidden states live in a lane-private LDS ring of
+// W = (max parent offset + 1) slots.
 #include "internal.h"
 #include <cmath>
 
@@ -56,136 +55,330 @@ __device__ inline bool allowed(int a_prev, int b_prev, int s, int rest, int na, 
 __device__ inline double tlog(double x) { return log(x); }
 __device__ inline float tlog(float x) { return logf(x); }
 
-// One wavefront = 16 rows.  CH = chi rounded up to 16.
-template <typename T, int CH>
-__global__ __launch_bounds__(256) void k_psi(PsiParams<T> P, const uint64_t* m, int64_t R,
-                                             double* lphi, int8_t* sphi, int rs, int wpb, T* hstore,
-                                             int64_t rpad) {
+// ---------------------------------------------------------------------------
+// Multi-tile forward: one wavefront owns NTL tiles of 16 rows.  Every A operand
+// fetched from memory feeds NTL MFMAs; after the per-tile partial sums in the
+// MFMA output layout, a reduce-scatter across the four lane groups
+// (permlane32_swap / permlane16_swap, plain VALU) leaves each lane group with
+// the full sums of one tile, so the per-row work (mask, normalisation, sign)
+// runs once per row instead of once per lane group.  log|Phi| is accumulated
+// as a renormalised product of the conditionals P^{s_i} / Z_i (mantissa in T,
+// exponent as an integer) and converted with one log at the end.
+// ---------------------------------------------------------------------------
+__device__ inline void pl16(float a, float b, float& na, float& nb) {
+  auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+  na = __uint_as_float(r[0]);
+  nb = __uint_as_float(r[1]);
+}
+__device__ inline void pl32(float a, float b, float& na, float& nb) {
+  auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+  na = __uint_as_float(r[0]);
+  nb = __uint_as_float(r[1]);
+}
+__device__ inline void pl16(double a, double b, double& na, double& nb) {
+  const uint64_t ua = __double_as_longlong(a), ub = __double_as_longlong(b);
+  auto lo = __builtin_amdgcn_permlane16_swap(uint32_t(ua), uint32_t(ub), false, false);
+  auto hi = __builtin_amdgcn_permlane16_swap(uint32_t(ua >> 32), uint32_t(ub >> 32), false, false);
+  na = __longlong_as_double(int64_t(uint64_t(lo[0]) | (uint64_t(hi[0]) << 32)));
+  nb = __longlong_as_double(int64_t(uint64_t(lo[1]) | (uint64_t(hi[1]) << 32)));
+}
+__device__ inline void pl32(double a, double b, double& na, double& nb) {
+  const uint64_t ua = __double_as_longlong(a), ub = __double_as_longlong(b);
+  auto lo = __builtin_amdgcn_permlane32_swap(uint32_t(ua), uint32_t(ub), false, false);
+  auto hi = __builtin_amdgcn_permlane32_swap(uint32_t(ua >> 32), uint32_t(ub >> 32), false, false);
+  na = __longlong_as_double(int64_t(uint64_t(lo[0]) | (uint64_t(hi[0]) << 32)));
+  nb = __longlong_as_double(int64_t(uint64_t(lo[1]) | (uint64_t(hi[1]) << 32)));
+}
+
+// x[t] is lane group g's partial of tile t; returns the sum over the four lane
+// groups of tile own(g): own = g (4 tiles), g/2 (2 tiles), 0 (1 tile).
+// permlane32_swap(a, b) exchanges the upper half of a with the lower half of
+// b; permlane16_swap(a, b) exchanges the odd 16-lane rows of a with the even
+// rows of b.
+template <typename T, int NTL> struct ReduceOwn;
+template <typename T> struct ReduceOwn<T, 4> {
+  __device__ static T run(const T (&x)[4]) {
+    T a, b, c, d;
+    pl32(x[0], x[2], a, b);
+    const T y02 = a + b;      // lanes 0-31: tile 0, lanes 32-63: tile 2
+    pl32(x[1], x[3], c, d);
+    const T y13 = c + d;      // lanes 0-31: tile 1, lanes 32-63: tile 3
+    pl16(y02, y13, a, b);
+    return a + b;             // lane group g: tile g
+  }
+};
+template <typename T> struct ReduceOwn<T, 2> {
+  __device__ static T run(const T (&x)[2]) {
+    T a, b;
+    pl32(x[0], x[1], a, b);
+    const T y = a + b;        // lanes 0-31: tile 0, lanes 32-63: tile 1 (pair sums)
+    pl16(y, y, a, b);
+    return a + b;
+  }
+};
+template <typename T> struct ReduceOwn<T, 1> {
+  __device__ static T run(const T (&x)[1]) {
+    T a, b;
+    pl32(x[0], x[0], a, b);
+    const T y = a + b;
+    pl16(y, y, a, b);
+    return a + b;
+  }
+};
+
+__device__ inline float tfrexp(float x, int* e) { return frexpf(x, e); }
+__device__ inline double tfrexp(double x, int* e) { return frexp(x, e); }
+
+// Forward amplitude kernel.  One wavefront owns NTL tiles of 16 rows.
+//
+// Operands.  The A stream holds, for every forward edge e (the parents of each
+// site in order; a parentless site has one zero edge), KS = CH/4 k-steps of NT
+// values per lane.  k-step q = 4 tt + v pairs lane group g with parent unit
+// 16 tt + 4 g + v, which is exactly the unit that lane (j, g) produced for
+// row j in register v of output tile tt of the parent site.  The B operand of
+// every MFMA is therefore the lane's own carried state, kept in a lane-private
+// LDS ring: no cross-lane exchange and no barrier between sites.
+//
+// The accumulators start from the bias v_i^s, so after the contractions
+// acc[t][s*TPC + tt] holds the candidates h_i^s for units 16 tt + 4 g + 0..3.
+// The A operands of the next edge are fetched before the current edge's
+// MFMAs, so their latency hides behind the contractions and the epilogue.
+//
+// FOLD: the operands carry sigma = sqrt(eta) (A' = sigma_i M / sigma_j,
+// v' = sigma v, w' = w / sigma, all eta > 0), so the ring holds sigma h and
+// P^s = sum_u x'^2 needs no eta.  STORE: the selected carried state of every
+// site is also written to hstore[K][rpad][CH] for the adjoint.
+// read-only uniform tables in the constant address space: the compiler reads
+// them with scalar loads
+typedef const __attribute__((address_space(4))) int CInt;
+template <typename T> using CT = const __attribute__((address_space(4))) T;
+
+#ifndef NQS_MFMA_PRIO
+#define NQS_MFMA_PRIO 2
+#endif
+constexpr int PRIO = NQS_MFMA_PRIO;
+
+template <typename T> constexpr int prefetch_ksteps(int CH) {
+  return (CH / 4) < 64 / ((CH / 4) * int(sizeof(T) / 4)) ? (CH / 4) : 64 / ((CH / 4) * int(sizeof(T) / 4));
+}
+
+template <typename T, int CH, int NTL, bool FOLD, bool STORE>
+__global__ __launch_bounds__(256) void k_psi_mt(PsiParams<T> P, const uint64_t* __restrict__ m, int64_t R,
+                                                double* __restrict__ lphi, int8_t* __restrict__ sphi, int wpb,
+                                                T* __restrict__ hstore, int64_t rpad) {
   extern __shared__ __align__(16) unsigned char smem[];
   typedef typename V4<T>::type V;
-  constexpr int TPC = CH / 16;     // 16-unit tiles per candidate
-  constexpr int NT = 4 * TPC;      // output tiles (4 candidates)
-  constexpr int KS = CH / 4;       // k-steps per parent
+  constexpr int TPC = CH / 16, NT = 4 * TPC, KS = CH / 4, RW = 16 * NTL;
+  constexpr int PQ = prefetch_ksteps<T>(CH);
+  constexpr int ES = KS * NT * 64;              // A values per edge
+  constexpr int SLOT = NTL * TPC * 64;          // V entries per ring slot
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int j = lane & 15, g = lane >> 4;
-  T* ring = reinterpret_cast<T*>(smem) + size_t(wv) * P.W * 16 * rs;
-  const int64_t tile = int64_t(blockIdx.x) * wpb + wv;
-  if (tile * 16 >= R) return;   // surplus wavefront of the last block (no block barrier below)
-  const int64_t row = tile * 16 + j;
-  const bool live = row < R;
-  const int64_t rr = live ? row : (R - 1);
-  const uint64_t lo = m[2 * rr], hi = m[2 * rr + 1];
-  double logacc = 0.0;
-  int sgn = 1, ca = 0, cb = 0;
+  const int own = NTL == 4 ? g : (NTL == 2 ? (g >> 1) : 0);
+  const int64_t base = (int64_t(blockIdx.x) * wpb + wv) * RW;
+  if (base >= R) return;   // surplus wavefront of the last block (no block barrier below)
+  // ring: slots 0..W-1 carry states, slot W stays zero (read by the zero edges);
+  // entry ((slot * NTL + t) * TPC + tt) * 64 + lane belongs to this lane only
+  V* ring = reinterpret_cast<V*>(smem) + size_t(wv) * (P.W + 1) * SLOT + lane;
+#pragma unroll
+  for (int k = 0; k < NTL * TPC; ++k) ring[(P.W * NTL * TPC + k) * 64] = V{0, 0, 0, 0};
+  // edge tables and c are uniform and read-only: scalar loads
+  const CInt* fptr = (const CInt*)(P.pptr);
+  const CInt* slots = (const CInt*)(P.slot);
+  const CT<T>* cc = (const CT<T>*)(P.c);
+  uint64_t lo[NTL], hi[NTL];
+  uint64_t olo = 0, ohi = 0;
+#pragma unroll
+  for (int t = 0; t < NTL; ++t) {
+    const int64_t r = base + 16 * t + j;
+    const int64_t rr = r < R ? r : R - 1;
+    lo[t] = m[2 * rr];
+    hi[t] = m[2 * rr + 1];
+    if (t == own) { olo = lo[t]; ohi = hi[t]; }
+  }
+  const int64_t orow = base + 16 * own + j;
+  const T* __restrict__ Ab = P.A + lane;
+  T an[PQ][NT];
+#pragma unroll
+  for (int q = 0; q < PQ; ++q)
+#pragma unroll
+    for (int ot = 0; ot < NT; ++ot) an[q][ot] = Ab[(q * NT + ot) * 64];
+  // bias v of the next site, fetched one site ahead where it fits in 64
+  // registers (otherwise at the start of the site): the accumulators start
+  // from it
+  constexpr bool BPF = NT * 4 * int(sizeof(T) / 4) <= 64;
+  V vn[NT];
+  auto fetch_bias = [&](int i) {
+#pragma unroll
+    for (int ot = 0; ot < NT; ++ot)
+      vn[ot] = *reinterpret_cast<const V*>(P.v + (size_t(i) * 4 + ot / TPC) * CH + 16 * (ot % TPC) + 4 * g);
+  };
+  if (BPF) fetch_bias(0);
+  T prod = T(1);
+  int pexp = 0, sgn = 1, ca = 0, cb = 0, wslot = 0, e = 0;
   bool bad = false;
   for (int i = 0; i < P.K; ++i) {
-    V acc[NT];
+    V acc[NTL][NT], wv4[TPC], ev4[TPC];
+    // w and eta of this site are needed only after the contractions
 #pragma unroll
-    for (int ot = 0; ot < NT; ++ot) acc[ot] = V{0, 0, 0, 0};
-    const int e0 = P.pptr[i], e1 = P.pptr[i + 1];
-    const T* A = P.A + P.aoff[i] + lane;
-    for (int e = e0; e < e1; ++e) {
-      const int slot = P.pidx[e] % P.W;
-      const T* rp = ring + (slot * 16 + j) * rs + g;
-      const T* Ae = A + size_t(e - e0) * (KS * NT * 64);
-#pragma unroll 4
-      for (int q = 0; q < KS; ++q) {
-        const T b = rp[4 * q];
+    for (int tt = 0; tt < TPC; ++tt) {
+      wv4[tt] = *reinterpret_cast<const V*>(P.w + size_t(i) * CH + 16 * tt + 4 * g);
+      if (!FOLD) ev4[tt] = *reinterpret_cast<const V*>(P.eta + size_t(i) * CH + 16 * tt + 4 * g);
+    }
+    const int e1 = fptr[i + 1];
+    // one edge: a chi-wide slice of the contraction over the parents
+    auto edge = [&]() {
+      const T* Ae = Ab + size_t(e) * ES;
+      V b[NTL][TPC];
+      const V* rp = ring + size_t(slots[e]) * SLOT;
 #pragma unroll
-        for (int ot = 0; ot < NT; ++ot) acc[ot] = mfma(Ae[(q * NT + ot) * 64], b, acc[ot]);
+      for (int t = 0; t < NTL; ++t)
+#pragma unroll
+        for (int tt = 0; tt < TPC; ++tt) b[t][tt] = rp[(t * TPC + tt) * 64];
+      // next edge (the A stream carries one zero edge past the last one)
+      T nx[PQ][NT];
+#pragma unroll
+      for (int q = 0; q < PQ; ++q)
+#pragma unroll
+        for (int ot = 0; ot < NT; ++ot) nx[q][ot] = Ae[ES + (q * NT + ot) * 64];
+#pragma unroll
+      for (int q = 0; q < KS; ++q)
+#pragma unroll
+        for (int ot = 0; ot < NT; ++ot) {
+          const T a = q < PQ ? an[q < PQ ? q : 0][ot] : Ae[(q * NT + ot) * 64];
+#pragma unroll
+          for (int t = 0; t < NTL; ++t) acc[t][ot] = mfma(a, b[t][q / 4][q % 4], acc[t][ot]);
+        }
+#pragma unroll
+      for (int q = 0; q < PQ; ++q)
+#pragma unroll
+        for (int ot = 0; ot < NT; ++ot) an[q][ot] = nx[q][ot];
+    };
+    // the contractions run at raised wave priority: an MFMA then issues as soon
+    // as the matrix core frees up, and the other wavefronts' epilogues fill
+    // the VALU slots in between
+    if (!BPF) fetch_bias(i);
+    __builtin_amdgcn_s_setprio(PRIO);
+#pragma unroll
+    for (int ot = 0; ot < NT; ++ot)
+#pragma unroll
+      for (int t = 0; t < NTL; ++t) acc[t][ot] = vn[ot];
+    if (BPF) fetch_bias(i + 1 < P.K ? i + 1 : i);
+    do edge(); while (++e < e1);
+    __builtin_amdgcn_s_setprio(0);
+    // epilogue in the MFMA output layout: lane (j, g) holds units 16tt+4g..+3
+    int si[NTL];
+#pragma unroll
+    for (int t = 0; t < NTL; ++t) si[t] = site_state(lo[t], hi[t], i);
+    T pp[4][NTL], dp[NTL];
+#pragma unroll
+    for (int t = 0; t < NTL; ++t) {
+      dp[t] = T(0);
+#pragma unroll
+      for (int s = 0; s < 4; ++s) pp[s][t] = T(0);
+    }
+    V* wr = ring + size_t(wslot) * SLOT;
+#pragma unroll
+    for (int tt = 0; tt < TPC; ++tt) {
+      const V ee = FOLD ? V{1, 1, 1, 1} : ev4[tt];
+      const V ww = wv4[tt];
+#pragma unroll
+      for (int t = 0; t < NTL; ++t) {
+        V x[4];
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          x[s] = acc[t][s * TPC + tt];
+          const V ex = FOLD ? x[s] : ee * x[s];
+          T q = pp[s][t];
+          q += ex.x * x[s].x;
+          q += ex.y * x[s].y;
+          q += ex.z * x[s].z;
+          q += ex.w * x[s].w;
+          pp[s][t] = q;
+        }
+        const V sel01 = (si[t] & 1) ? x[1] : x[0];
+        const V sel23 = (si[t] & 1) ? x[3] : x[2];
+        const V sel = (si[t] & 2) ? sel23 : sel01;
+        dp[t] += ww.x * sel.x + ww.y * sel.y + ww.z * sel.z + ww.w * sel.w;
+        wr[(t * TPC + tt) * 64] = sel;
+        if (STORE) {
+          const int64_t r = base + 16 * t + j;
+          if (r < rpad) *reinterpret_cast<V*>(hstore + (size_t(i) * rpad + r) * CH + 16 * tt + 4 * g) = sel;
+        }
       }
     }
-    // epilogue: add v, conditional weights P^s summed over the 4 lane groups
-    const T* vi = P.v + size_t(i) * 4 * CH;
-    const T* ei = P.eta + size_t(i) * CH;
+    wslot = wslot + 1 == P.W ? 0 : wslot + 1;
     T ps[4];
 #pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      T p = 0;
-#pragma unroll
-      for (int t = 0; t < TPC; ++t) {
-        const int u0 = 16 * t + 4 * g;
-        const V vv = *reinterpret_cast<const V*>(vi + s * CH + u0);
-        const V ee = *reinterpret_cast<const V*>(ei + u0);
-        const V x = acc[s * TPC + t] + vv;
-        acc[s * TPC + t] = x;
-        p += ee.x * x.x * x.x + ee.y * x.y * x.y + ee.z * x.z * x.z + ee.w * x.w * x.w;
-      }
-      p += __shfl_xor(p, 16);
-      p += __shfl_xor(p, 32);
-      ps[s] = p;
-    }
-    const int si = site_state(lo, hi, i);
+    for (int s = 0; s < 4; ++s) ps[s] = ReduceOwn<T, NTL>::run(pp[s]);
+    const T dot = ReduceOwn<T, NTL>::run(dp) + T(cc[i]);
+    // per-row work, once per row: lane group g owns tile own(g)
+    const int osi = site_state(olo, ohi, i);
     const int rest = P.K - 1 - i;
-    T Z = 0;
+    T Z = T(0);
 #pragma unroll
     for (int s = 0; s < 4; ++s)
       if (allowed(ca, cb, s, rest, P.na, P.nb)) Z += ps[s];
-    if (!allowed(ca, cb, si, rest, P.na, P.nb)) bad = true;
-    const T psi_ = si == 0 ? ps[0] : si == 1 ? ps[1] : si == 2 ? ps[2] : ps[3];
-    logacc += 0.5 * (double(tlog(psi_)) - double(tlog(Z)));
-    // carried state h_i^{s_i} and the phase sign of w^T h + c
-    V sel[TPC];
-#pragma unroll
-    for (int t = 0; t < TPC; ++t) {
-      sel[t] = acc[t];
-#pragma unroll
-      for (int s = 1; s < 4; ++s)
-        if (si == s) sel[t] = acc[s * TPC + t];
-    }
-    const T* wi = P.w + size_t(i) * CH;
-    T dot = 0;
-#pragma unroll
-    for (int t = 0; t < TPC; ++t) {
-      const V ww = *reinterpret_cast<const V*>(wi + 16 * t + 4 * g);
-      dot += ww.x * sel[t].x + ww.y * sel[t].y + ww.z * sel[t].z + ww.w * sel[t].w;
-    }
-    dot += __shfl_xor(dot, 16);
-    dot += __shfl_xor(dot, 32);
-    dot += P.c[i];
-    if (dot < 0) sgn = -sgn;
-    T* wp = ring + ((i % P.W) * 16 + j) * rs + 4 * g;
-#pragma unroll
-    for (int t = 0; t < TPC; ++t) *reinterpret_cast<V*>(wp + 16 * t) = sel[t];
-    if (hstore && row < rpad) {
-      T* hp = hstore + (size_t(i) * rpad + row) * CH + 4 * g;
-#pragma unroll
-      for (int t = 0; t < TPC; ++t) *reinterpret_cast<V*>(hp + 16 * t) = sel[t];
-    }
-    wave_sync();
-    ca += si & 1;
-    cb += si >> 1;
+    if (!allowed(ca, cb, osi, rest, P.na, P.nb)) bad = true;
+    const T p01 = (osi & 1) ? ps[1] : ps[0];
+    const T p23 = (osi & 1) ? ps[3] : ps[2];
+    const T psi_ = (osi & 2) ? p23 : p01;
+    int ex;
+    prod = tfrexp(prod * (psi_ / Z), &ex);
+    pexp += ex;
+    if (dot < T(0)) sgn = -sgn;
+    ca += osi & 1;
+    cb += osi >> 1;
   }
-  if (live && g == 0) {
-    lphi[row] = bad ? -INFINITY : logacc;
-    sphi[row] = int8_t(bad ? 0 : sgn);
+  const bool writer = NTL == 4 || (NTL == 2 ? (g & 1) == 0 : g == 0);
+  if (writer && orow < R) {
+    lphi[orow] = bad ? -INFINITY : 0.5 * (log(double(prod)) + double(pexp) * 0.69314718055994530942);
+    sphi[orow] = int8_t(bad ? 0 : sgn);
   }
 }
 
-template <typename T, int CH>
-hipError_t run_psi(const PsiParams<T>& P, const uint64_t* m, int64_t R, double* lphi, int8_t* sphi,
-                   hipStream_t st, T* hstore, int64_t rpad) {
+#ifndef NQS_NTL_F32_16
+#define NQS_NTL_F32_16 4
+#endif
+template <typename T> constexpr int ntiles(int CH) {
+  return sizeof(T) == 4 ? (CH <= 16 ? NQS_NTL_F32_16 : (CH <= 32 ? 2 : 1)) : (CH <= 16 ? 2 : 1);
+}
+
+template <typename T, int CH, bool FOLD, bool STORE>
+hipError_t run_psi_mt(const PsiParams<T>& P, const uint64_t* m, int64_t R, double* lphi, int8_t* sphi,
+                      hipStream_t st, T* hstore, int64_t rpad) {
   if (R <= 0) return hipSuccess;
-  const int rs = CH + (sizeof(T) == 8 ? 2 : 4);
-  const size_t per_wave = size_t(P.W) * 16 * rs * sizeof(T);
+  constexpr int NTL = ntiles<T>(CH);
+  const size_t per_wave = size_t(P.W + 1) * 16 * NTL * CH * sizeof(T);
   int wpb = 4;
   while (wpb > 1 && per_wave * wpb > 64 * 1024) wpb >>= 1;
   if (per_wave * wpb > 160 * 1024) return hipErrorInvalidValue;
-  const int64_t tiles = (R + 15) / 16;
+  const int64_t tiles = (R + 16 * NTL - 1) / (16 * NTL);
   const int64_t blocks = (tiles + wpb - 1) / wpb;
-  hipLaunchKernelGGL((k_psi<T, CH>), dim3(unsigned(blocks)), dim3(64 * wpb), per_wave * wpb, st, P, m, R,
-                     lphi, sphi, rs, wpb, hstore, rpad);
+  hipLaunchKernelGGL((k_psi_mt<T, CH, NTL, FOLD, STORE>), dim3(unsigned(blocks)), dim3(64 * wpb),
+                     per_wave * wpb, st, P, m, R, lphi, sphi, wpb, hstore, rpad);
   return hipGetLastError();
+}
+
+template <typename T, int CH>
+hipError_t run_psi_ch(const PsiParams<T>& P, const uint64_t* m, int64_t R, double* lphi, int8_t* sphi,
+                      hipStream_t st, T* hstore, int64_t rpad) {
+  if (hstore) {
+    if (P.folded) return hipErrorInvalidValue;   // the carried-state store needs the unfolded states
+    return run_psi_mt<T, CH, false, true>(P, m, R, lphi, sphi, st, hstore, rpad);
+  }
+  if (P.folded) return run_psi_mt<T, CH, true, false>(P, m, R, lphi, sphi, st, nullptr, 0);
+  return run_psi_mt<T, CH, false, false>(P, m, R, lphi, sphi, st, nullptr, 0);
 }
 
 template <typename T>
 hipError_t dispatch_psi(const PsiParams<T>& P, const uint64_t* m, int64_t R, double* lphi,
                         int8_t* sphi, hipStream_t st, T* hstore, int64_t rpad) {
   switch (P.chip) {
-    case 16: return run_psi<T, 16>(P, m, R, lphi, sphi, st, hstore, rpad);
-    case 32: return run_psi<T, 32>(P, m, R, lphi, sphi, st, hstore, rpad);
-    case 48: return run_psi<T, 48>(P, m, R, lphi, sphi, st, hstore, rpad);
-    case 64: return run_psi<T, 64>(P, m, R, lphi, sphi, st, hstore, rpad);
+    case 16: return run_psi_ch<T, 16>(P, m, R, lphi, sphi, st, hstore, rpad);
+    case 32: return run_psi_ch<T, 32>(P, m, R, lphi, sphi, st, hstore, rpad);
+    case 48: return run_psi_ch<T, 48>(P, m, R, lphi, sphi, st, hstore, rpad);
+    case 64: return run_psi_ch<T, 64>(P, m, R, lphi, sphi, st, hstore, rpad);
     default: return hipErrorInvalidValue;
   }
 }

@@ -46,14 +46,14 @@ struct DrawKeys {
 template <typename T>
 struct PsiParams {
   int K, chi, chip, na, nb, W;   // W = ring slots = max parent offset + 1
-  const int* pptr;               // [K+1]
-  const int* pidx;               // [sum d]
-  const T* A;                    // MFMA A operands, see pack layout in runtime.cpp
-  const int64_t* aoff;           // [K] element offset of site i in A
+  const int* pptr;               // [K+1] forward edges of site i: pptr[i]..pptr[i+1]-1 (never empty)
+  const int* slot;               // [edges] ring slot read by each edge (W for a parentless site's zero edge)
+  const T* A;                    // [edges + 1][CH/4][CH/4][64] k-permuted MFMA A operands, see runtime.cpp
   const T* v;                    // [K][4][chip]
   const T* eta;                  // [K][chip]
   const T* w;                    // [K][chip]
   const T* c;                    // [K]
+  bool folded;                   // operands carry sqrt(eta) (see k_psi_mt); never with a carried-state store
 };
 
 // Adjoint (backward) layouts for one precision T.

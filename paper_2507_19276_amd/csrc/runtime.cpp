@@ -176,8 +176,7 @@ struct nqs_instance {
 // ---------------------------------------------------------------------------
 template <typename T>
 struct PsiLayout {
-  T* A = nullptr;
-  int64_t* aoff = nullptr;
+  T* A = nullptr;           // forward: per forward edge, then one zero edge
   T* v = nullptr;
   T* eta = nullptr;
   T* w = nullptr;
@@ -186,11 +185,12 @@ struct PsiLayout {
   int64_t* afoff = nullptr;
   T* BT = nullptr;          // adjoint: M^T operands
   int64_t* btoff = nullptr;
+  bool folded = false;      // operands carry sqrt(eta)
   void free_all() {
-    for (void* p : {(void*)A, (void*)aoff, (void*)v, (void*)eta, (void*)w, (void*)c, (void*)AF,
-                    (void*)afoff, (void*)BT, (void*)btoff})
+    for (void* p : {(void*)A, (void*)v, (void*)eta, (void*)w, (void*)c, (void*)AF, (void*)afoff, (void*)BT,
+                    (void*)btoff})
       if (p) (void)hipFree(p);
-    A = nullptr; aoff = nullptr; v = eta = w = c = nullptr;
+    A = nullptr; v = eta = w = c = nullptr;
     AF = nullptr; afoff = nullptr; BT = nullptr; btoff = nullptr;
   }
 };
@@ -203,9 +203,13 @@ struct nqs_ansatz {
   int64_t offB = 0, offWc = 0, n_params = 0;
   int* d_pptr = nullptr;
   int* d_pidx = nullptr;
+  int* d_slot = nullptr;    // ring slot of each parent edge (pidx % W)
+  int* d_fptr = nullptr;    // forward edge CSR: every parentless site gets one zero-weight edge
+  int* d_fslot = nullptr;   // forward edge slots (a dummy edge reads slot W, which stays zero)
   bool bound = false;
-  PsiLayout<double> L64;
-  PsiLayout<float> L32;
+  PsiLayout<double> L64, F64;   // F*: sqrt(eta)-folded forward layouts (when every eta > 0)
+  PsiLayout<float> L32, F32;
+  bool has_fold = false;
   uint16_t* bfA = nullptr;
   int64_t* bfAoff = nullptr;
   double* d_cb = nullptr;   // correlator b
@@ -216,8 +220,10 @@ struct nqs_ansatz {
   ~nqs_ansatz() {
     L64.free_all();
     L32.free_all();
-    for (void* p : {(void*)d_pptr, (void*)d_pidx, (void*)bfA, (void*)bfAoff, (void*)d_cb, (void*)d_cW,
-                    (void*)d_offM, (void*)d_offV, (void*)d_offEta})
+    F64.free_all();
+    F32.free_all();
+    for (void* p : {(void*)d_pptr, (void*)d_pidx, (void*)d_slot, (void*)d_fptr, (void*)d_fslot, (void*)bfA,
+                    (void*)bfAoff, (void*)d_cb, (void*)d_cW, (void*)d_offM, (void*)d_offV, (void*)d_offEta})
       if (p) (void)hipFree(p);
   }
   template <typename T>
@@ -234,10 +240,14 @@ struct nqs_ansatz {
   PsiParams<T> params(const PsiLayout<T>& L) const {
     PsiParams<T> P;
     P.K = K; P.chi = chi; P.chip = chip; P.na = na; P.nb = nb; P.W = W;
-    P.pptr = d_pptr; P.pidx = d_pidx;
-    P.A = L.A; P.aoff = L.aoff; P.v = L.v; P.eta = L.eta; P.w = L.w; P.c = L.c;
+    P.pptr = d_fptr; P.slot = d_fslot;
+    P.A = L.A; P.v = L.v; P.eta = L.eta; P.w = L.w; P.c = L.c;
+    P.folded = L.folded;
     return P;
   }
+  // forward layout for amplitudes without a carried-state store
+  const PsiLayout<double>& fwd64() const { return has_fold ? F64 : L64; }
+  const PsiLayout<float>& fwd32() const { return has_fold ? F32 : L32; }
   CorrParams corr() const {
     CorrParams C;
     C.K = K; C.nh = nh; C.b = d_cb; C.W = d_cW;
@@ -254,45 +264,75 @@ nqs_status upload(T** dst, const std::vector<T>& src) {
   return NQS_OK;
 }
 
-// MFMA A operand of site i: W_i^T tiles, [edge][k-step q][output tile ot][lane],
-// lane l holding W^T[o][k = 4 q + l/16] = M_ij^s[u][k] with s = o / chip,
-// u = o % chip (zero outside chi) for the tile row m = l%16.  The 16x16x4
-// f32 MFMA returns row m = 4 g + v of the tile in register v of lane group
-// g = lane/16; the f64 MFMA returns row m = g + 4 v.  Tile row m therefore
-// carries unit o = 16 ot + m for f32 and o = 16 ot + 4 (m%4) + m/4 for f64,
-// so that in both cases lane group g ends up with units 16 ot + 4 g + v.
+// Forward MFMA A operands: W_i^T tiles over the forward edges (the parents of
+// each site in order; a parentless site gets one zero edge), then one more
+// zero edge so that the kernel's one-edge-ahead fetch stays in bounds.  Per
+// edge [k-step q][output tile ot][lane]: lane l holds W^T[o][k] = M_ij^s[u][k]
+// with s = o / chip, u = o % chip (zero outside chi), tile row m = l%16 and
+// parent unit k = 16 (q/4) + 4 (l/16) + q%4.  The 16x16x4 f32 MFMA returns
+// row m = 4 g + v of the tile in register v of lane group g = lane/16; the f64
+// MFMA returns row m = g + 4 v.  Tile row m therefore carries unit
+// o = 16 ot + m for f32 and o = 16 ot + 4 (m%4) + m/4 for f64, so that in both
+// cases lane group g ends up with units 16 ot + 4 g + v, and k-step q of lane
+// group g reads the parent unit that the same lane produced in register q%4 of
+// output tile q/4.
+//
+// fold = true: every operand carries sigma = sqrt(eta) (requires eta > 0):
+// A' = sigma_i[u] M[u][k] / sigma_j[k], v' = sigma_i v, w' = w / sigma_i, so the
+// forward kernel carries sigma h and P^s = sum x'^2.  The adjoint operands are
+// built only for the unfolded layout.
 template <typename T>
-nqs_status build_layout(nqs_ansatz* a, const std::vector<double>& prm, PsiLayout<T>& L) {
+nqs_status build_layout(nqs_ansatz* a, const std::vector<double>& prm, PsiLayout<T>& L, bool fold) {
   const int K = a->K, chi = a->chi, CH = a->chip;
   const int KS = CH / 4, NT = CH / 4;
-  std::vector<int64_t> aoff(K);
+  const size_t ES = size_t(KS) * NT * 64;
+  std::vector<double> sig(size_t(K) * chi, 1.0);
+  if (fold)
+    for (int i = 0; i < K; ++i)
+      for (int u = 0; u < chi; ++u) sig[size_t(i) * chi + u] = std::sqrt(prm[a->offEta[i] + u]);
   std::vector<T> A;
   for (int i = 0; i < K; ++i) {
-    aoff[i] = int64_t(A.size());
+    if (a->pptr[i + 1] == a->pptr[i]) A.resize(A.size() + ES, T(0));   // zero edge
     for (int e = a->pptr[i]; e < a->pptr[i + 1]; ++e) {
       const double* M = prm.data() + a->offM[e];
+      const double* sj = sig.data() + size_t(a->pidx[e]) * chi;
+      const double* si = sig.data() + size_t(i) * chi;
       for (int q = 0; q < KS; ++q)
         for (int ot = 0; ot < NT; ++ot)
           for (int l = 0; l < 64; ++l) {
             const int mrow = l & 15;
             const int o = ot * 16 + (sizeof(T) == 8 ? 4 * (mrow & 3) + (mrow >> 2) : mrow);
-            const int k = q * 4 + (l >> 4);
+            const int k = 16 * (q >> 2) + 4 * (l >> 4) + (q & 3);
             const int s = o / CH, u = o % CH;
             double val = 0.0;
-            if (u < chi && k < chi) val = M[(size_t(s) * chi + u) * chi + k];
+            if (u < chi && k < chi) val = si[u] * M[(size_t(s) * chi + u) * chi + k] / sj[k];
             A.push_back(T(val));
           }
     }
   }
+  A.resize(A.size() + ES, T(0));   // fetch-ahead edge
   std::vector<T> v(size_t(K) * 4 * CH, T(0)), eta(size_t(K) * CH, T(0)), w(size_t(K) * CH, T(0)), c(K);
   for (int i = 0; i < K; ++i) {
+    const double* si = sig.data() + size_t(i) * chi;
     for (int s = 0; s < 4; ++s)
-      for (int u = 0; u < chi; ++u) v[(size_t(i) * 4 + s) * CH + u] = T(prm[a->offV[i] + s * chi + u]);
+      for (int u = 0; u < chi; ++u)
+        v[(size_t(i) * 4 + s) * CH + u] = T(si[u] * prm[a->offV[i] + s * chi + u]);
     for (int u = 0; u < chi; ++u) {
       eta[size_t(i) * CH + u] = T(prm[a->offEta[i] + u]);
-      w[size_t(i) * CH + u] = T(prm[a->offW[i] + u]);
+      w[size_t(i) * CH + u] = T(prm[a->offW[i] + u] / si[u]);
     }
     c[i] = T(prm[a->offC[i]]);
+  }
+  if (fold) {
+    L.free_all();
+    L.folded = true;
+    nqs_status st;
+    if ((st = upload(&L.A, A)) != NQS_OK) return st;
+    if ((st = upload(&L.v, v)) != NQS_OK) return st;
+    if ((st = upload(&L.eta, eta)) != NQS_OK) return st;
+    if ((st = upload(&L.w, w)) != NQS_OK) return st;
+    if ((st = upload(&L.c, c)) != NQS_OK) return st;
+    return NQS_OK;
   }
   // adjoint operands.  AF: like A but k-step q = 4t + v pairs lane group k'
   // with parent unit 16t + 4k' + v.  BT: k-step q = (s*TPC + t)*4 + v over the
@@ -336,7 +376,6 @@ nqs_status build_layout(nqs_ansatz* a, const std::vector<double>& prm, PsiLayout
   if ((st = upload(&L.BT, BT)) != NQS_OK) return st;
   if ((st = upload(&L.btoff, btoff)) != NQS_OK) return st;
   if ((st = upload(&L.A, A)) != NQS_OK) return st;
-  if ((st = upload(&L.aoff, aoff)) != NQS_OK) return st;
   if ((st = upload(&L.v, v)) != NQS_OK) return st;
   if ((st = upload(&L.eta, eta)) != NQS_OK) return st;
   if ((st = upload(&L.w, w)) != NQS_OK) return st;
@@ -574,6 +613,17 @@ nqs_status nqs_ansatz_create(nqs_ctx* ctx, int K, int n_alpha, int n_beta, int c
   std::vector<int> pp(a->pptr.begin(), a->pptr.end()), pi(a->pidx.begin(), a->pidx.end());
   if ((st = upload(&a->d_pptr, pp)) != NQS_OK) return st;
   if ((st = upload(&a->d_pidx, pi)) != NQS_OK) return st;
+  std::vector<int> slot(pi.size());
+  for (size_t e = 0; e < pi.size(); ++e) slot[e] = pi[e] % a->W;
+  if ((st = upload(&a->d_slot, slot)) != NQS_OK) return st;
+  std::vector<int> fptr(1, 0), fslot;
+  for (int i = 0; i < K; ++i) {
+    if (a->pptr[i + 1] == a->pptr[i]) fslot.push_back(a->W);
+    for (int e = a->pptr[i]; e < a->pptr[i + 1]; ++e) fslot.push_back(slot[e]);
+    fptr.push_back(int(fslot.size()));
+  }
+  if ((st = upload(&a->d_fptr, fptr)) != NQS_OK) return st;
+  if ((st = upload(&a->d_fslot, fslot)) != NQS_OK) return st;
   if ((st = upload(&a->d_offM, a->offM)) != NQS_OK) return st;
   if ((st = upload(&a->d_offV, a->offV)) != NQS_OK) return st;
   if ((st = upload(&a->d_offEta, a->offEta)) != NQS_OK) return st;
@@ -601,8 +651,19 @@ nqs_status nqs_ansatz_bind_params(nqs_ansatz* ans, const double* params, hipStre
       if (!(prm[ans->offEta[i] + u] >= 0.0))
         return fail(NQS_EINVAL, "eta[%d][%d] = %g is negative or NaN", i, u, prm[ans->offEta[i] + u]);
   nqs_status st;
-  if ((st = build_layout<double>(ans, prm, ans->L64)) != NQS_OK) return st;
-  if ((st = build_layout<float>(ans, prm, ans->L32)) != NQS_OK) return st;
+  if ((st = build_layout<double>(ans, prm, ans->L64, false)) != NQS_OK) return st;
+  if ((st = build_layout<float>(ans, prm, ans->L32, false)) != NQS_OK) return st;
+  bool all_pos = true;
+  for (int i = 0; i < ans->K; ++i)
+    for (int u = 0; u < ans->chi; ++u) all_pos = all_pos && prm[ans->offEta[i] + u] > 0.0;
+  ans->has_fold = false;
+  ans->F64.free_all();
+  ans->F32.free_all();
+  if (all_pos) {
+    if ((st = build_layout<double>(ans, prm, ans->F64, true)) != NQS_OK) return st;
+    if ((st = build_layout<float>(ans, prm, ans->F32, true)) != NQS_OK) return st;
+    ans->has_fold = true;
+  }
   if ((st = build_bf16(ans, prm)) != NQS_OK) return st;
   if (ans->d_cb) { (void)hipFree(ans->d_cb); ans->d_cb = nullptr; }
   if (ans->d_cW) { (void)hipFree(ans->d_cW); ans->d_cW = nullptr; }
@@ -639,9 +700,9 @@ nqs_status check_samples(nqs_ctx* ctx, const uint64_t* samples, int64_t N, int K
 nqs_status run_amplitudes(const nqs_ansatz* a, int precision, const uint64_t* m, int64_t R, double* lphi,
                           int8_t* sphi, hipStream_t st) {
   if (precision == NQS_F64) {
-    HIPCHK(launch_psi_f64(a->params(a->L64), m, R, lphi, sphi, st));
+    HIPCHK(launch_psi_f64(a->params(a->fwd64()), m, R, lphi, sphi, st));
   } else if (precision == NQS_F32) {
-    HIPCHK(launch_psi_f32(a->params(a->L32), m, R, lphi, sphi, st));
+    HIPCHK(launch_psi_f32(a->params(a->fwd32()), m, R, lphi, sphi, st));
   } else if (precision == NQS_BF16) {
     BF16Params P{};
     P.K = a->K; P.chi = a->chi; P.chip = a->chip; P.na = a->na; P.nb = a->nb; P.W = a->W;
