@@ -102,7 +102,7 @@ def run_eloc_bench(args):
 
     def step(k, prec):
         return nqs.eloc(ctx, inst, ans, samples, eps=w.eps, n_eps=w.n_eps, precision=prec,
-                        seed=w.seed + k, stream_id=0)
+                        seed=w.seed + k, stream_id=0, resume=not args.full_recompute)
 
     precs = list(dict.fromkeys(args.precisions.split(",")))
     head_prec = precs[0]
@@ -121,7 +121,8 @@ def run_eloc_bench(args):
         dt = time.perf_counter() - t0
         results[prec] = dict(dt=dt, amp_ms=float(np.mean(amp_ms)), rows=float(np.mean(rows)), st=st)
         print(f"# {prec}: {args.steps} steps in {dt:.3f} s, rows/step {np.mean(rows):.0f}, "
-              f"amplitude kernel {np.mean(amp_ms):.3f} ms", file=sys.stderr, flush=True)
+              f"site-rows/step {st['n_site_rows']}, amplitude stage {np.mean(amp_ms):.3f} ms",
+              file=sys.stderr, flush=True)
         if not args.no_cpu_baseline:
             out, st = step(7, prec)
             keep[prec] = (out["eloc"].cpu().numpy(), st["E"])
@@ -268,6 +269,8 @@ def main():
     ap.add_argument("--precisions", default="f32,f64,bf16",
                     help="comma list; the first is the headline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--full-recompute", action="store_true",
+                    help="evaluate every amplitude row from site 0 (no resumption at the first changed site)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run one device copy of this size first (scales PMC byte counters)")
     ap.add_argument("--traffic-bytes", type=float, default=None,

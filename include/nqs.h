@@ -83,7 +83,15 @@ typedef struct {
                                 evaluated in passes over whole samples holding at most
                                 max(max_rows_per_pass, 1 + n_conn + n_eps) rows, which bounds
                                 the device memory of the call (nqs_eloc_workspace_bytes) */
+  int32_t flags;       /* NQS_ELOC_* bits; 0 = defaults */
 } nqs_eloc_opts;
+
+/* nqs_eloc_opts.flags.  By default the FP64 and FP32 amplitude rows resume at
+ * their first changed site from the state their sample reached there (the
+ * conditionals of Eqs. (9)-(10) below that site see the sample's
+ * occupations); the results are bit-identical to evaluating every row from
+ * site 0, which this flag selects. */
+#define NQS_ELOC_FULL_RECOMPUTE 1
 
 /* Per-call statistics (host struct, filled when a non-NULL pointer is passed). */
 typedef struct {
@@ -99,6 +107,9 @@ typedef struct {
   double var;            /* sum c |f|^2 (E_loc - E)^2 / sum c |f|^2 */
   double ms_enumerate, ms_draw, ms_rows, ms_amplitude, ms_reduce;  /* stage times (device events) */
   int64_t n_passes;      /* amplitude passes (see max_rows_per_pass) */
+  int64_t n_site_rows;   /* per-site amplitude evaluations executed: sum over rows of the
+                            sites computed (K per row without resumption), plus the
+                            samples' own pass when rows resume */
 } nqs_eloc_stats;
 
 /* ---- context --------------------------------------------------------- */

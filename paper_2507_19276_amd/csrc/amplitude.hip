@@ -126,6 +126,8 @@ template <typename T> struct ReduceOwn<T, 1> {
   }
 };
 
+__device__ inline float tfma(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ inline double tfma(double a, double b, double c) { return __builtin_fma(a, b, c); }
 __device__ inline float tfrexp(float x, int* e) { return frexpf(x, e); }
 __device__ inline double tfrexp(double x, int* e) { return frexp(x, e); }
 
@@ -162,17 +164,24 @@ template <typename T> constexpr int prefetch_ksteps(int CH) {
   return (CH / 4) < 64 / ((CH / 4) * int(sizeof(T) / 4)) ? (CH / 4) : 64 / ((CH / 4) * int(sizeof(T) / 4));
 }
 
-template <typename T, int CH, int NTL, bool FOLD, bool STORE>
+template <typename T, int CH, int NTL, bool FOLD, bool STORE, bool SEED>
 __global__ __launch_bounds__(256) void k_psi_mt(PsiParams<T> P, const uint64_t* __restrict__ m, int64_t R,
                                                 double* __restrict__ lphi, int8_t* __restrict__ sphi, int wpb,
-                                                T* __restrict__ hstore, int64_t rpad) {
+                                                PsiStates<T> X) {
+  // every floating-point operation below is written out (explicit fma where
+  // one is meant), so that all instances of this kernel round alike: a row
+  // resumed from its sample's stored state ends bit-identical to a row
+  // computed from site 0
+#pragma clang fp contract(off)
   extern __shared__ __align__(16) unsigned char smem[];
   typedef typename V4<T>::type V;
   constexpr int TPC = CH / 16, NT = 4 * TPC, KS = CH / 4, RW = 16 * NTL;
   constexpr int PQ = prefetch_ksteps<T>(CH);
   constexpr int ES = KS * NT * 64;              // A values per edge
   constexpr int SLOT = NTL * TPC * 64;          // V entries per ring slot
-  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  // the wavefront index is uniform: keep it (and all that derives from it:
+  // rows, start site, edge and slot counters) in scalar registers
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   const int j = lane & 15, g = lane >> 4;
   const int own = NTL == 4 ? g : (NTL == 2 ? (g >> 1) : 0);
   const int64_t base = (int64_t(blockIdx.x) * wpb + wv) * RW;
@@ -186,23 +195,60 @@ __global__ __launch_bounds__(256) void k_psi_mt(PsiParams<T> P, const uint64_t* 
   const CInt* fptr = (const CInt*)(P.pptr);
   const CInt* slots = (const CInt*)(P.slot);
   const CT<T>* cc = (const CT<T>*)(P.c);
+  // SEED: positions base.. map to rows X.perm[pos], sorted by their first
+  // changed site, and the wavefront starts at the site of its first row
+  const int i0 = SEED ? int(((const __attribute__((address_space(4))) uint8_t*)X.t0)[base]) : 0;
   uint64_t lo[NTL], hi[NTL];
+  int64_t rowt[NTL];
   uint64_t olo = 0, ohi = 0;
 #pragma unroll
   for (int t = 0; t < NTL; ++t) {
     const int64_t r = base + 16 * t + j;
     const int64_t rr = r < R ? r : R - 1;
-    lo[t] = m[2 * rr];
-    hi[t] = m[2 * rr + 1];
+    rowt[t] = SEED ? int64_t(X.perm[rr]) : rr;
+    lo[t] = m[2 * rowt[t]];
+    hi[t] = m[2 * rowt[t] + 1];
     if (t == own) { olo = lo[t]; ohi = hi[t]; }
   }
-  const int64_t orow = base + 16 * own + j;
+  const bool olive = base + 16 * own + j < R;
+  int64_t orow = rowt[0];
+#pragma unroll
+  for (int t = 1; t < NTL; ++t)
+    if (t == own) orow = rowt[t];
+  T prod = T(1);
+  int pexp = 0, sgn = 1, ca = 0, cb = 0, wslot = 0, e = 0;
+  bool bad = false;
+  if (SEED && i0 > 0) {
+    // carried states of the parents of sites >= i0 and the log-product state
+    // before site i0, taken from the row's sample (rows agree with their
+    // sample on every site below their first changed site >= i0)
+    const int s0 = i0 - P.W + 1 > 0 ? i0 - P.W + 1 : 0;
+    for (int s = s0; s < i0; ++s) {
+      V* wr = ring + size_t(s % P.W) * SLOT;
+#pragma unroll
+      for (int t = 0; t < NTL; ++t) {
+        const T* src = X.hs + (size_t(s) * X.ns + X.owner[rowt[t]]) * CH + 4 * g;
+#pragma unroll
+        for (int tt = 0; tt < TPC; ++tt) wr[(t * TPC + tt) * 64] = *reinterpret_cast<const V*>(src + 16 * tt);
+      }
+    }
+    const size_t so = size_t(i0) * X.ns + X.owner[orow];
+    prod = X.pm[so];
+    pexp = X.pe[so];
+    sgn = X.pg[so];
+    const uint64_t below = 2 * i0 >= 64 ? ~0ull : ((1ull << (2 * i0)) - 1);
+    const uint64_t belowh = 2 * i0 <= 64 ? 0ull : (2 * i0 >= 128 ? ~0ull : ((1ull << (2 * i0 - 64)) - 1));
+    ca = __popcll(olo & below & 0x5555555555555555ull) + __popcll(ohi & belowh & 0x5555555555555555ull);
+    cb = __popcll(olo & below & 0xAAAAAAAAAAAAAAAAull) + __popcll(ohi & belowh & 0xAAAAAAAAAAAAAAAAull);
+    wslot = i0 % P.W;
+    e = fptr[i0];
+  }
   const T* __restrict__ Ab = P.A + lane;
   T an[PQ][NT];
 #pragma unroll
   for (int q = 0; q < PQ; ++q)
 #pragma unroll
-    for (int ot = 0; ot < NT; ++ot) an[q][ot] = Ab[(q * NT + ot) * 64];
+    for (int ot = 0; ot < NT; ++ot) an[q][ot] = Ab[size_t(e) * ES + (q * NT + ot) * 64];
   // bias v of the next site, fetched one site ahead where it fits in 64
   // registers (otherwise at the start of the site): the accumulators start
   // from it
@@ -213,11 +259,20 @@ __global__ __launch_bounds__(256) void k_psi_mt(PsiParams<T> P, const uint64_t* 
     for (int ot = 0; ot < NT; ++ot)
       vn[ot] = *reinterpret_cast<const V*>(P.v + (size_t(i) * 4 + ot / TPC) * CH + 16 * (ot % TPC) + 4 * g);
   };
-  if (BPF) fetch_bias(0);
-  T prod = T(1);
-  int pexp = 0, sgn = 1, ca = 0, cb = 0, wslot = 0, e = 0;
-  bool bad = false;
-  for (int i = 0; i < P.K; ++i) {
+  if (BPF) fetch_bias(i0 < P.K ? i0 : 0);
+  // STORE: the log-product state before each site and the carried state
+  // after it, for rows r < X.ns
+  auto store_pre = [&](int i) {
+    const bool writer = NTL == 4 || (NTL == 2 ? (g & 1) == 0 : g == 0);
+    if (STORE && X.pm && writer && olive && orow < X.ns) {
+      const size_t so = size_t(i) * X.ns + orow;
+      X.pm[so] = prod;
+      X.pe[so] = pexp;
+      X.pg[so] = int8_t(sgn);
+    }
+  };
+  for (int i = i0; i < P.K; ++i) {
+    store_pre(i);
     V acc[NTL][NT], wv4[TPC], ev4[TPC];
     // w and eta of this site are needed only after the contractions
 #pragma unroll
@@ -254,10 +309,10 @@ __global__ __launch_bounds__(256) void k_psi_mt(PsiParams<T> P, const uint64_t* 
 #pragma unroll
         for (int ot = 0; ot < NT; ++ot) an[q][ot] = nx[q][ot];
     };
+    if (!BPF) fetch_bias(i);
     // the contractions run at raised wave priority: an MFMA then issues as soon
     // as the matrix core frees up, and the other wavefronts' epilogues fill
     // the VALU slots in between
-    if (!BPF) fetch_bias(i);
     __builtin_amdgcn_s_setprio(PRIO);
 #pragma unroll
     for (int ot = 0; ot < NT; ++ot)
@@ -280,7 +335,6 @@ __global__ __launch_bounds__(256) void k_psi_mt(PsiParams<T> P, const uint64_t* 
     V* wr = ring + size_t(wslot) * SLOT;
 #pragma unroll
     for (int tt = 0; tt < TPC; ++tt) {
-      const V ee = FOLD ? V{1, 1, 1, 1} : ev4[tt];
       const V ww = wv4[tt];
 #pragma unroll
       for (int t = 0; t < NTL; ++t) {
@@ -288,22 +342,29 @@ __global__ __launch_bounds__(256) void k_psi_mt(PsiParams<T> P, const uint64_t* 
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
           x[s] = acc[t][s * TPC + tt];
-          const V ex = FOLD ? x[s] : ee * x[s];
+          const V ex = FOLD ? x[s] : ev4[tt] * x[s];
           T q = pp[s][t];
-          q += ex.x * x[s].x;
-          q += ex.y * x[s].y;
-          q += ex.z * x[s].z;
-          q += ex.w * x[s].w;
+          q = tfma(ex.x, x[s].x, q);
+          q = tfma(ex.y, x[s].y, q);
+          q = tfma(ex.z, x[s].z, q);
+          q = tfma(ex.w, x[s].w, q);
           pp[s][t] = q;
         }
         const V sel01 = (si[t] & 1) ? x[1] : x[0];
         const V sel23 = (si[t] & 1) ? x[3] : x[2];
         const V sel = (si[t] & 2) ? sel23 : sel01;
-        dp[t] += ww.x * sel.x + ww.y * sel.y + ww.z * sel.z + ww.w * sel.w;
+        T d = dp[t];
+        d = tfma(ww.x, sel.x, d);
+        d = tfma(ww.y, sel.y, d);
+        d = tfma(ww.z, sel.z, d);
+        d = tfma(ww.w, sel.w, d);
+        dp[t] = d;
         wr[(t * TPC + tt) * 64] = sel;
         if (STORE) {
+          // positions past R (up to the stride X.ns) get the last row's state:
+          // the adjoint reads padded rows
           const int64_t r = base + 16 * t + j;
-          if (r < rpad) *reinterpret_cast<V*>(hstore + (size_t(i) * rpad + r) * CH + 16 * tt + 4 * g) = sel;
+          if (r < X.ns) *reinterpret_cast<V*>(X.hs + (size_t(i) * X.ns + r) * CH + 16 * tt + 4 * g) = sel;
         }
       }
     }
@@ -330,8 +391,9 @@ __global__ __launch_bounds__(256) void k_psi_mt(PsiParams<T> P, const uint64_t* 
     ca += osi & 1;
     cb += osi >> 1;
   }
+  store_pre(P.K);
   const bool writer = NTL == 4 || (NTL == 2 ? (g & 1) == 0 : g == 0);
-  if (writer && orow < R) {
+  if (writer && olive) {
     lphi[orow] = bad ? -INFINITY : 0.5 * (log(double(prod)) + double(pexp) * 0.69314718055994530942);
     sphi[orow] = int8_t(bad ? 0 : sgn);
   }
@@ -344,9 +406,9 @@ template <typename T> constexpr int ntiles(int CH) {
   return sizeof(T) == 4 ? (CH <= 16 ? NQS_NTL_F32_16 : (CH <= 32 ? 2 : 1)) : (CH <= 16 ? 2 : 1);
 }
 
-template <typename T, int CH, bool FOLD, bool STORE>
+template <typename T, int CH, bool FOLD, bool STORE, bool SEED>
 hipError_t run_psi_mt(const PsiParams<T>& P, const uint64_t* m, int64_t R, double* lphi, int8_t* sphi,
-                      hipStream_t st, T* hstore, int64_t rpad) {
+                      hipStream_t st, const PsiStates<T>& X) {
   if (R <= 0) return hipSuccess;
   constexpr int NTL = ntiles<T>(CH);
   const size_t per_wave = size_t(P.W + 1) * 16 * NTL * CH * sizeof(T);
@@ -355,30 +417,37 @@ hipError_t run_psi_mt(const PsiParams<T>& P, const uint64_t* m, int64_t R, doubl
   if (per_wave * wpb > 160 * 1024) return hipErrorInvalidValue;
   const int64_t tiles = (R + 16 * NTL - 1) / (16 * NTL);
   const int64_t blocks = (tiles + wpb - 1) / wpb;
-  hipLaunchKernelGGL((k_psi_mt<T, CH, NTL, FOLD, STORE>), dim3(unsigned(blocks)), dim3(64 * wpb),
-                     per_wave * wpb, st, P, m, R, lphi, sphi, wpb, hstore, rpad);
+  hipLaunchKernelGGL((k_psi_mt<T, CH, NTL, FOLD, STORE, SEED>), dim3(unsigned(blocks)), dim3(64 * wpb),
+                     per_wave * wpb, st, P, m, R, lphi, sphi, wpb, X);
   return hipGetLastError();
 }
 
 template <typename T, int CH>
 hipError_t run_psi_ch(const PsiParams<T>& P, const uint64_t* m, int64_t R, double* lphi, int8_t* sphi,
-                      hipStream_t st, T* hstore, int64_t rpad) {
-  if (hstore) {
-    if (P.folded) return hipErrorInvalidValue;   // the carried-state store needs the unfolded states
-    return run_psi_mt<T, CH, false, true>(P, m, R, lphi, sphi, st, hstore, rpad);
+                      hipStream_t st, const PsiStates<T>& X, int mode) {
+  switch (mode) {
+    case PSI_PLAIN:
+      if (P.folded) return run_psi_mt<T, CH, true, false, false>(P, m, R, lphi, sphi, st, X);
+      return run_psi_mt<T, CH, false, false, false>(P, m, R, lphi, sphi, st, X);
+    case PSI_STORE:
+      if (P.folded) return run_psi_mt<T, CH, true, true, false>(P, m, R, lphi, sphi, st, X);
+      return run_psi_mt<T, CH, false, true, false>(P, m, R, lphi, sphi, st, X);
+    case PSI_SEED:
+      if (P.folded) return run_psi_mt<T, CH, true, false, true>(P, m, R, lphi, sphi, st, X);
+      return run_psi_mt<T, CH, false, false, true>(P, m, R, lphi, sphi, st, X);
+    default:
+      return hipErrorInvalidValue;
   }
-  if (P.folded) return run_psi_mt<T, CH, true, false>(P, m, R, lphi, sphi, st, nullptr, 0);
-  return run_psi_mt<T, CH, false, false>(P, m, R, lphi, sphi, st, nullptr, 0);
 }
 
 template <typename T>
 hipError_t dispatch_psi(const PsiParams<T>& P, const uint64_t* m, int64_t R, double* lphi,
-                        int8_t* sphi, hipStream_t st, T* hstore, int64_t rpad) {
+                        int8_t* sphi, hipStream_t st, const PsiStates<T>& X, int mode) {
   switch (P.chip) {
-    case 16: return run_psi_ch<T, 16>(P, m, R, lphi, sphi, st, hstore, rpad);
-    case 32: return run_psi_ch<T, 32>(P, m, R, lphi, sphi, st, hstore, rpad);
-    case 48: return run_psi_ch<T, 48>(P, m, R, lphi, sphi, st, hstore, rpad);
-    case 64: return run_psi_ch<T, 64>(P, m, R, lphi, sphi, st, hstore, rpad);
+    case 16: return run_psi_ch<T, 16>(P, m, R, lphi, sphi, st, X, mode);
+    case 32: return run_psi_ch<T, 32>(P, m, R, lphi, sphi, st, X, mode);
+    case 48: return run_psi_ch<T, 48>(P, m, R, lphi, sphi, st, X, mode);
+    case 64: return run_psi_ch<T, 64>(P, m, R, lphi, sphi, st, X, mode);
     default: return hipErrorInvalidValue;
   }
 }
@@ -736,13 +805,13 @@ inline unsigned grid_for(int64_t units, int per_block) {
 }  // namespace
 
 hipError_t launch_psi_f64(const PsiParams<double>& P, const uint64_t* m, int64_t R, double* lphi,
-                          int8_t* sphi, hipStream_t st, double* hstore, int64_t rpad) {
-  return dispatch_psi<double>(P, m, R, lphi, sphi, st, hstore, rpad);
+                          int8_t* sphi, hipStream_t st, const PsiStates<double>& X, int mode) {
+  return dispatch_psi<double>(P, m, R, lphi, sphi, st, X, mode);
 }
 
 hipError_t launch_psi_f32(const PsiParams<float>& P, const uint64_t* m, int64_t R, double* lphi,
-                          int8_t* sphi, hipStream_t st, float* hstore, int64_t rpad) {
-  return dispatch_psi<float>(P, m, R, lphi, sphi, st, hstore, rpad);
+                          int8_t* sphi, hipStream_t st, const PsiStates<float>& X, int mode) {
+  return dispatch_psi<float>(P, m, R, lphi, sphi, st, X, mode);
 }
 
 hipError_t launch_corr_theta(const CorrParams& C, const uint64_t* samples, int64_t N, double* theta,

@@ -40,6 +40,13 @@ __device__ inline void flip(uint64_t& lo, uint64_t& hi, int P) {
   if (P < 64) lo ^= 1ull << P; else hi ^= 1ull << (P - 64);
 }
 
+// site (spatial orbital) of the lowest set spin-orbital bit of a nonzero XOR
+// of two ONVs, with P = 2 p + sigma
+__device__ inline int first_changed_site(uint64_t xlo, uint64_t xhi) {
+  if (xlo) return (__ffsll((unsigned long long)xlo) - 1) >> 1;
+  return (64 + __ffsll((unsigned long long)xhi) - 1) >> 1;
+}
+
 __device__ inline bool bit_at(uint64_t lo, uint64_t hi, int P) {
   return P < 64 ? ((lo >> P) & 1ull) : ((hi >> (P - 64)) & 1ull);
 }
@@ -493,6 +500,7 @@ __global__ __launch_bounds__(256) void k_fill(HamDev H, EnumGeom G, const uint64
         rows.coef[at] = e.H;
         rows.owner[at] = int32_t(n);
         rows.rank[at] = int64_t(r);
+        if (rows.t0) rows.t0[at] = uint8_t(first_changed_site(e.mlo ^ lo, e.mhi ^ hi));
       }
       pos += __popcll(mask);
     }
@@ -504,6 +512,7 @@ __global__ __launch_bounds__(256) void k_fill(HamDev H, EnumGeom G, const uint64
       rows.coef[r0] = 0.0;
       rows.owner[r0] = int32_t(n);
       rows.rank[r0] = -1;
+      if (rows.t0) rows.t0[r0] = uint8_t(H.K);
     }
     const int64_t u = Un[n];
     const int64_t d0 = r0 + 1 + Dn[n];
@@ -514,6 +523,8 @@ __global__ __launch_bounds__(256) void k_fill(HamDev H, EnumGeom G, const uint64
       rows.coef[at] = ucoef[n * n_eps + t];
       rows.owner[at] = int32_t(n);
       rows.rank[at] = urank[n * n_eps + t];
+      if (rows.t0)
+        rows.t0[at] = uint8_t(first_changed_site(um[2 * (n * n_eps + t)] ^ lo, um[2 * (n * n_eps + t) + 1] ^ hi));
     }
   }
 }

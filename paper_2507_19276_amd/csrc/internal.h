@@ -98,6 +98,7 @@ struct Rows {
   double* coef;      // [R]
   int32_t* owner;    // [R]
   int64_t* rank;     // [R]   (-1 for the sample's own row)
+  uint8_t* t0;       // [R]   first site where m differs from its sample (K when equal); may be null
 };
 
 // ---- launchers (enumerate.hip) ----------------------------------------
@@ -125,10 +126,40 @@ hipError_t launch_connected(const HamDev& H, const uint64_t* samples, int64_t N,
 
 // ---- launchers (amplitude.hip) -----------------------------------------
 // hstore (nullable): carried states h_i^{s_i} of every row, [K][rpad][chip]
+// Forward modes.  PLAIN: rows 0..R-1 from site 0.  STORE: as PLAIN, and for
+// rows r < X.ns the carried state after every site goes to X.hs and, when
+// X.pm is set, the log-product state (mantissa, exponent, sign) before every
+// site and after the last to X.pm/pe/pg.  SEED: position p evaluates row
+// X.perm[p]; positions are sorted by the row's first changed site X.t0[p],
+// and each wavefront resumes at the site of its first position from the state
+// that a STORE pass left for the row's sample X.owner[row].
+enum { PSI_PLAIN = 0, PSI_STORE = 1, PSI_SEED = 2 };
+template <typename T>
+struct PsiStates {
+  T* hs = nullptr;               // [K][ns][chip] carried states
+  T* pm = nullptr;               // [K+1][ns] product mantissa before site i
+  int32_t* pe = nullptr;         // [K+1][ns] product exponent
+  int8_t* pg = nullptr;          // [K+1][ns] sign
+  int64_t ns = 0;                // sample stride
+  const int32_t* perm = nullptr; // SEED: [R] row of each position
+  const uint8_t* t0 = nullptr;   // SEED: [R] first changed site of each position (ascending)
+  const int32_t* owner = nullptr;// SEED: [rows] sample of each row
+};
 hipError_t launch_psi_f64(const PsiParams<double>& P, const uint64_t* m, int64_t R, double* lphi,
-                          int8_t* sphi, hipStream_t st, double* hstore = nullptr, int64_t rpad = 0);
+                          int8_t* sphi, hipStream_t st, const PsiStates<double>& X = PsiStates<double>(),
+                          int mode = PSI_PLAIN);
 hipError_t launch_psi_f32(const PsiParams<float>& P, const uint64_t* m, int64_t R, double* lphi,
-                          int8_t* sphi, hipStream_t st, float* hstore = nullptr, int64_t rpad = 0);
+                          int8_t* sphi, hipStream_t st, const PsiStates<float>& X = PsiStates<float>(),
+                          int mode = PSI_PLAIN);
+// ---- row order by first changed site (order.hip) ----------------------
+// chunk of rows per block of the counting sort
+constexpr int kOrderChunk = 16384;
+inline int64_t order_blocks(int64_t R) { return (R + kOrderChunk - 1) / kOrderChunk; }
+// Stable counting sort of rows 0..R-1 by their first changed site t0[r] in
+// [0, K].  cnt: [blocks][K+1] int32 scratch; tot: [K+1] int64 bucket totals
+// (device); perm: [R] rows in (t0, row) order; t0s: [R] t0 of each position.
+hipError_t launch_order_t0(const uint8_t* t0, int64_t R, int K, int32_t* cnt, int64_t* tot, int32_t* perm,
+                           uint8_t* t0s, hipStream_t st);
 hipError_t launch_psi_bf16(const BF16Params& P, const uint64_t* m, int64_t R, double* lphi,
                            int8_t* sphi, hipStream_t st);
 hipError_t launch_corr_theta(const CorrParams& C, const uint64_t* samples, int64_t N, double* theta,

@@ -696,13 +696,46 @@ nqs_status check_samples(nqs_ctx* ctx, const uint64_t* samples, int64_t N, int K
   return NQS_OK;
 }
 
-// amplitudes of R rows into (lphi, sphi)
+// Device state of resumed amplitude rows (FP64/FP32): the samples' carried
+// states and log-product states, and the order of the current pass's rows.
+struct Resume {
+  void* hs = nullptr;       // [K][N][chip] T
+  void* pm = nullptr;       // [K+1][N] T
+  int32_t* pe = nullptr;    // [K+1][N]
+  int8_t* pg = nullptr;     // [K+1][N]
+  int64_t ns = 0;
+  int32_t* perm = nullptr;  // [rows of a pass] row of each sorted position
+  uint8_t* t0 = nullptr;    // [rows of a pass] sorted first changed sites
+  int32_t* cnt = nullptr;   // [order blocks][K+1]
+  int64_t* tot = nullptr;   // [K+1]
+  const int32_t* owner = nullptr;
+};
+
+template <typename T>
+PsiStates<T> states(const Resume& r) {
+  PsiStates<T> X;
+  X.hs = static_cast<T*>(r.hs);
+  X.pm = static_cast<T*>(r.pm);
+  X.pe = r.pe;
+  X.pg = r.pg;
+  X.ns = r.ns;
+  X.perm = r.perm;
+  X.t0 = r.t0;
+  X.owner = r.owner;
+  return X;
+}
+
+// amplitudes of R rows into (lphi, sphi).  mode PSI_STORE (samples, with rs)
+// or PSI_SEED (rows of a pass, with rs and its order) for FP64/FP32 only.
 nqs_status run_amplitudes(const nqs_ansatz* a, int precision, const uint64_t* m, int64_t R, double* lphi,
-                          int8_t* sphi, hipStream_t st) {
+                          int8_t* sphi, hipStream_t st, const Resume* rs = nullptr, int mode = PSI_PLAIN) {
+  if (mode != PSI_PLAIN && (!rs || precision == NQS_BF16)) return fail(NQS_EINVAL, "resume state missing");
   if (precision == NQS_F64) {
-    HIPCHK(launch_psi_f64(a->params(a->fwd64()), m, R, lphi, sphi, st));
+    HIPCHK(launch_psi_f64(a->params(a->fwd64()), m, R, lphi, sphi, st,
+                          rs ? states<double>(*rs) : PsiStates<double>(), mode));
   } else if (precision == NQS_F32) {
-    HIPCHK(launch_psi_f32(a->params(a->fwd32()), m, R, lphi, sphi, st));
+    HIPCHK(launch_psi_f32(a->params(a->fwd32()), m, R, lphi, sphi, st,
+                          rs ? states<float>(*rs) : PsiStates<float>(), mode));
   } else if (precision == NQS_BF16) {
     BF16Params P{};
     P.K = a->K; P.chi = a->chi; P.chip = a->chip; P.na = a->na; P.nb = a->nb; P.W = a->W;
@@ -836,7 +869,13 @@ nqs_status check_opts(const nqs_eloc_opts* o) {
   if (o->n_eps > 1024) return fail(NQS_EUNSUPPORTED, "n_eps > 1024 per sample");
   if (o->precision < 0 || o->precision > 2) return fail(NQS_EINVAL, "unknown precision");
   if (o->max_rows_per_pass < 0) return fail(NQS_EINVAL, "max_rows_per_pass < 0");
+  if (o->flags & ~NQS_ELOC_FULL_RECOMPUTE) return fail(NQS_EINVAL, "unknown flags 0x%x", unsigned(o->flags));
   return NQS_OK;
+}
+
+// rows resume from their samples' states (FP64/FP32 amplitude paths)
+bool resumes(const nqs_eloc_opts& o) {
+  return o.precision != NQS_BF16 && !(o.flags & NQS_ELOC_FULL_RECOMPUTE);
 }
 
 }  // namespace
@@ -910,12 +949,18 @@ nqs_status nqs_logpsi_vjp(nqs_ctx* ctx, const nqs_ansatz* ans, const uint64_t* s
   HIPCHK(hipMemsetAsync(cotp, 0, sizeof(double) * Rpad, stream));
   HIPCHK(hipMemcpyAsync(cotp, cot, sizeof(double) * N, hipMemcpyDeviceToDevice, stream));
   if (precision == NQS_F64) {
-    HIPCHK(launch_psi_f64(ans->params(ans->L64), samples, N, lphi, sphi, stream, (double*)Hbuf, Rpad));
+    PsiStates<double> X;
+    X.hs = (double*)Hbuf;
+    X.ns = Rpad;
+    HIPCHK(launch_psi_f64(ans->params(ans->L64), samples, N, lphi, sphi, stream, X, PSI_STORE));
     HIPCHK(launch_bwd_sweep_f64(ans->adj(ans->L64), samples, N, Rpad, cotp, (const double*)Hbuf,
                                 (double*)dcarry, (double*)Dc, (double*)Eeta, rows_per_split, nsplit, gpart,
                                 np, stream));
   } else {
-    HIPCHK(launch_psi_f32(ans->params(ans->L32), samples, N, lphi, sphi, stream, (float*)Hbuf, Rpad));
+    PsiStates<float> X;
+    X.hs = (float*)Hbuf;
+    X.ns = Rpad;
+    HIPCHK(launch_psi_f32(ans->params(ans->L32), samples, N, lphi, sphi, stream, X, PSI_STORE));
     HIPCHK(launch_bwd_sweep_f32(ans->adj(ans->L32), samples, N, Rpad, cotp, (const float*)Hbuf,
                                 (float*)dcarry, (float*)Dc, (float*)Eeta, rows_per_split, nsplit, gpart,
                                 np, stream));
@@ -973,16 +1018,65 @@ nqs_status nqs_eloc(nqs_ctx* ctx, const nqs_instance* inst, const nqs_ansatz* an
   double* et = etnum ? etnum : S.get<double>(N);
   double* f2 = fsq ? fsq : S.get<double>(N);
   double* sums = S.get<double>(8);
+  const int K = ans->K;
+  const bool resume = resumes(*opts) && cap_used < (int64_t(1) << 31);
+  Resume rs;
+  double* lphi_s = nullptr;
+  int8_t* sphi_s = nullptr;
+  if (resume) {
+    const size_t esz = opts->precision == NQS_F64 ? 8 : 4;
+    rs.hs = S.get<unsigned char>(size_t(K) * N * ans->chip * esz);
+    rs.pm = S.get<unsigned char>(size_t(K + 1) * N * esz);
+    rs.pe = S.get<int32_t>(size_t(K + 1) * N);
+    rs.pg = S.get<int8_t>(size_t(K + 1) * N);
+    rs.ns = N;
+    rs.perm = S.get<int32_t>(cap_used);
+    rs.t0 = S.get<uint8_t>(cap_used);
+    P.rows.t0 = S.get<uint8_t>(cap_used);
+    rs.cnt = S.get<int32_t>(size_t(order_blocks(cap_used)) * (K + 1));
+    rs.tot = S.get<int64_t>(K + 1);
+    rs.owner = P.rows.owner;
+    lphi_s = S.get<double>(N);
+    sphi_s = S.get<int8_t>(N);
+  }
   if (S.oom) return fail(NQS_ENOMEM, "workspace allocation failed");
   if (ans->nh) HIPCHK(launch_corr_theta(ans->corr(), samples, N, theta, stream));
   float ms_rows = 0, ms_amp = 0, ms_red = 0;
+  int64_t site_rows = 0;
+  if (resume) {
+    // the samples' own pass: carried and log-product states at every site
+    if (timing) HIPCHK(hipEventRecord(pe[0], stream));
+    if ((s = run_amplitudes(ans, opts->precision, samples, N, lphi_s, sphi_s, stream, &rs, PSI_STORE)) != NQS_OK)
+      return s;
+    site_rows += int64_t(N) * K;
+    if (timing) {
+      HIPCHK(hipEventRecord(pe[1], stream));
+      HIPCHK(hipEventSynchronize(pe[1]));
+      float t = 0;
+      HIPCHK(hipEventElapsedTime(&t, pe[0], pe[1]));
+      ms_amp += t;
+    }
+  }
   for (auto& pr : passes) {
     const int64_t n0 = pr.first, n1 = pr.second;
     const int64_t Rp = P.rowptr_host[n1] - P.rowptr_host[n0];
     if (timing) HIPCHK(hipEventRecord(pe[0], stream));
     if ((s = fill_range(inst, samples, n0, n1, *opts, P, stream)) != NQS_OK) return s;
     if (timing) HIPCHK(hipEventRecord(pe[1], stream));
-    if ((s = run_amplitudes(ans, opts->precision, P.rows.m, Rp, lphi, sphi, stream)) != NQS_OK) return s;
+    if (resume) {
+      HIPCHK(launch_order_t0(P.rows.t0, Rp, K, rs.cnt, rs.tot, rs.perm, rs.t0, stream));
+      if ((s = run_amplitudes(ans, opts->precision, P.rows.m, Rp, lphi, sphi, stream, &rs, PSI_SEED)) != NQS_OK)
+        return s;
+      if (stats) {
+        std::vector<int64_t> tot(K + 1);
+        HIPCHK(hipMemcpyAsync(tot.data(), rs.tot, sizeof(int64_t) * (K + 1), hipMemcpyDeviceToHost, stream));
+        HIPCHK(hipStreamSynchronize(stream));
+        for (int k = 0; k <= K; ++k) site_rows += tot[k] * (K - k);
+      }
+    } else {
+      if ((s = run_amplitudes(ans, opts->precision, P.rows.m, Rp, lphi, sphi, stream)) != NQS_OK) return s;
+      site_rows += Rp * K;
+    }
     if (timing) HIPCHK(hipEventRecord(pe[2], stream));
     if (ans->nh) {
       HIPCHK(launch_corr_rows(ans->corr(), P.rows.m, P.rows.owner, samples, theta, Rp, opts->precision, lf, sf,
@@ -1030,6 +1124,7 @@ nqs_status nqs_eloc(nqs_ctx* ctx, const nqs_instance* inst, const nqs_ansatz* an
     stats->ms_rows = ms_rows;
     stats->ms_amplitude = ms_amp;
     stats->ms_reduce = ms_red;
+    stats->n_site_rows = site_rows;
   }
   return NQS_OK;
 }
@@ -1084,6 +1179,15 @@ nqs_status nqs_eloc_workspace_bytes(const nqs_instance* inst, const nqs_ansatz* 
   b += al(size_t(rows) * 16) + al(size_t(rows) * 8) + al(size_t(rows) * 4) + al(size_t(rows) * 8);
   b += al(size_t(rows) * 8) + al(size_t(rows)) + al(size_t(rows) * 8) + al(size_t(rows));
   if (ans->nh) b += al(size_t(N) * ans->nh * 8);
+  if (resumes(*opts)) {
+    // samples' carried and log-product states, the pass's row order
+    const size_t esz = opts->precision == NQS_F64 ? 8 : 4;
+    const int K = ans->K;
+    b += al(size_t(K) * N * ans->chip * esz) + al(size_t(K + 1) * N * esz) + al(size_t(K + 1) * N * 4);
+    b += al(size_t(K + 1) * N) + al(size_t(rows) * 4) + 2 * al(size_t(rows));
+    b += al(size_t(order_blocks(rows)) * (K + 1) * 4) + al(size_t(K + 1) * 8);
+    b += al(size_t(N) * 8) + al(size_t(N));
+  }
   b += 3 * al(size_t(N) * 8) + al(64);     // outputs the caller did not provide, batch sums
   b += al(4);                              // sample validation flag
   *bytes = b;

@@ -32,7 +32,10 @@ class NqsError(RuntimeError):
 class ElocOpts(C.Structure):
     _fields_ = [("eps", C.c_double), ("n_eps", C.c_int32), ("precision", C.c_int32),
                 ("seed", C.c_uint64), ("stream_id", C.c_uint64), ("sample_base", C.c_int32),
-                ("max_rows_per_pass", C.c_int32)]
+                ("max_rows_per_pass", C.c_int32), ("flags", C.c_int32)]
+
+
+ELOC_FULL_RECOMPUTE = 1
 
 
 class ElocStats(C.Structure):
@@ -40,7 +43,8 @@ class ElocStats(C.Structure):
                 ("n_det_rows", C.c_int64), ("n_draw_rows", C.c_int64), ("n_zero_amp", C.c_int64),
                 ("sum_c", C.c_double), ("B", C.c_double), ("E", C.c_double), ("var", C.c_double),
                 ("ms_enumerate", C.c_double), ("ms_draw", C.c_double), ("ms_rows", C.c_double),
-                ("ms_amplitude", C.c_double), ("ms_reduce", C.c_double), ("n_passes", C.c_int64)]
+                ("ms_amplitude", C.c_double), ("ms_reduce", C.c_double), ("n_passes", C.c_int64),
+                ("n_site_rows", C.c_int64)]
 
     def to_dict(self) -> Dict[str, float]:
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -115,10 +119,11 @@ def _samples(s) -> torch.Tensor:
 
 
 def opts(eps: float = 0.0, n_eps: int = 0, precision="f64", seed: int = 0, stream_id: int = 0,
-         sample_base: int = 0, max_rows_per_pass: int = 0) -> ElocOpts:
+         sample_base: int = 0, max_rows_per_pass: int = 0, resume: bool = True) -> ElocOpts:
     p = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
     return ElocOpts(float(eps), int(n_eps), p, int(seed) & 0xFFFFFFFFFFFFFFFF,
-                    int(stream_id) & 0xFFFFFFFFFFFFFFFF, int(sample_base), int(max_rows_per_pass))
+                    int(stream_id) & 0xFFFFFFFFFFFFFFFF, int(sample_base), int(max_rows_per_pass),
+                    0 if resume else ELOC_FULL_RECOMPUTE)
 
 
 class Context:
@@ -251,8 +256,9 @@ class Ansatz:
 
 def eloc(ctx: Context, inst: Instance, ans: Ansatz, samples, counts: Optional[torch.Tensor] = None,
          eps: float = 0.0, n_eps: int = 0, precision="f64", seed: int = 0, stream_id: int = 0,
-         sample_base: int = 0, want_stats: bool = True, max_rows_per_pass: int = 0):
-    """Semi-stochastic local energies; returns (dict of device tensors, stats dict or None)."""
+         sample_base: int = 0, want_stats: bool = True, max_rows_per_pass: int = 0, resume: bool = True):
+    """Semi-stochastic local energies; returns (dict of device tensors, stats dict or None).
+    resume=False evaluates every amplitude row from site 0 (NQS_ELOC_FULL_RECOMPUTE)."""
     s = _samples(samples)
     N = s.shape[0]
     dev = s.device
@@ -264,7 +270,7 @@ def eloc(ctx: Context, inst: Instance, ans: Ansatz, samples, counts: Optional[to
         "fsq": torch.empty(N, dtype=torch.float64, device=dev),
     }
     c = None if counts is None else counts.to(dtype=torch.float64, device=dev).contiguous()
-    o = opts(eps, n_eps, precision, seed, stream_id, sample_base, max_rows_per_pass)
+    o = opts(eps, n_eps, precision, seed, stream_id, sample_base, max_rows_per_pass, resume)
     st = ElocStats()
     check(lib().nqs_eloc(ctx.h, inst.h, ans.h, _ptr(s), _ptr(c), N, C.byref(o), _ptr(out["eloc"]),
                          _ptr(out["etnum"]), _ptr(out["logabs"]), _ptr(out["sign"]), _ptr(out["fsq"]),
@@ -297,9 +303,9 @@ def rows(ctx: Context, inst: Instance, samples, eps: float = 0.0, n_eps: int = 0
 
 
 def workspace_bytes(inst: Instance, ans: Ansatz, N: int, n_rows: int = 0, eps=0.0, n_eps=0, precision="f64",
-                    max_rows_per_pass: int = 0) -> int:
+                    max_rows_per_pass: int = 0, resume: bool = True) -> int:
     b = C.c_size_t()
-    o = opts(eps, n_eps, precision, max_rows_per_pass=max_rows_per_pass)
+    o = opts(eps, n_eps, precision, max_rows_per_pass=max_rows_per_pass, resume=resume)
     check(lib().nqs_eloc_workspace_bytes(inst.h, ans.h, int(N), C.byref(o), int(n_rows), C.byref(b)))
     return b.value
 

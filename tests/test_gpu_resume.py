@@ -1,0 +1,109 @@
+"""Resumed amplitude rows: every FP64/FP32 row starts at its first changed
+site from its sample's stored state instead of site 0.  The autoregressive
+conditionals below that site see only occupations the row shares with its
+sample, so the result must be bit-identical to evaluating every row from
+site 0, on every workload, with and without row passes; and the executed
+site count must equal the sum over rows of (K - first changed site) plus the
+samples' own pass."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2507_19276_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+NAMES = ("eloc", "etnum", "logabs", "sign", "fsq")
+
+
+@pytest.fixture(scope="module")
+def nqs():
+    from paper_2507_19276_amd import nqs as N
+    N.lib()
+    return N
+
+
+@pytest.fixture(scope="module")
+def ctx(nqs):
+    c = nqs.Context(0)
+    yield c
+    c.close()
+
+
+_cache = {}
+
+
+def setup(nqs, ctx, name, n):
+    key = (name, n)
+    if key not in _cache:
+        w = W.make_workload(name, n_samples=n)
+        inst = nqs.Instance(ctx, w.K, w.n_alpha, w.n_beta, w.h, w.eri, w.e_core)
+        ans = nqs.Ansatz(ctx, w.K, w.n_alpha, w.n_beta, w.chi, w.parent_ptr, w.parent_idx, w.n_hidden)
+        ans.bind(w.params)
+        _cache[key] = (w, inst, ans)
+    return _cache[key]
+
+
+def first_changed_sites(m, s, K):
+    """First site where row m differs from its sample s (K when equal)."""
+    out = np.full(len(m), K, dtype=np.int64)
+    for k in range(len(m)):
+        x = (int(m[k, 0]) ^ int(s[0])) | ((int(m[k, 1]) ^ int(s[1])) << 64)
+        if x:
+            out[k] = ((x & -x).bit_length() - 1) // 2
+    return out
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("name,n", [("c1", None), ("c2", 200), ("c3", 24), ("c4a", 24), ("c4b", 40)])
+def test_resume_bit_identical(nqs, ctx, name, n, prec):
+    w, inst, ans = setup(nqs, ctx, name, n)
+    kw = dict(eps=w.eps, n_eps=w.n_eps, precision=prec, seed=w.seed, stream_id=5)
+    full, st_full = nqs.eloc(ctx, inst, ans, w.samples, resume=False, **kw)
+    res, st_res = nqs.eloc(ctx, inst, ans, w.samples, **kw)
+    for k in NAMES:
+        assert np.array_equal(full[k].cpu().numpy(), res[k].cpu().numpy(), equal_nan=True), (name, prec, k)
+    assert st_full["n_rows"] == st_res["n_rows"]
+    assert st_full["n_site_rows"] == st_full["n_rows"] * w.K
+    assert st_res["n_site_rows"] < st_full["n_site_rows"]
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_resume_with_passes(nqs, ctx, prec):
+    """Several passes: each pass sorts its own rows; results are unchanged."""
+    w, inst, ans = setup(nqs, ctx, "c2", 200)
+    kw = dict(eps=w.eps, n_eps=w.n_eps, precision=prec, seed=w.seed, stream_id=6)
+    full, _ = nqs.eloc(ctx, inst, ans, w.samples, resume=False, **kw)
+    many, st = nqs.eloc(ctx, inst, ans, w.samples, max_rows_per_pass=100_000, **kw)
+    assert st["n_passes"] > 1
+    for k in NAMES:
+        assert np.array_equal(full[k].cpu().numpy(), many[k].cpu().numpy(), equal_nan=True), (prec, k)
+
+
+def test_site_count_matches_first_changed_sites(nqs, ctx):
+    """n_site_rows = N K (samples' pass) + sum over rows of (K - t0), with t0
+    computed here from the row list of the same call."""
+    w, inst, ans = setup(nqs, ctx, "c2", 64)
+    kw = dict(eps=w.eps, n_eps=w.n_eps, seed=w.seed, stream_id=7)
+    r = nqs.rows(ctx, inst, w.samples, **kw)
+    rp = r["row_ptr"].cpu().numpy()
+    m = r["m"].cpu().numpy().view(np.uint64)
+    total = w.n_samples * w.K
+    for s in range(w.n_samples):
+        t0 = first_changed_sites(m[rp[s]:rp[s + 1]], w.samples[s], w.K)
+        assert t0[0] == w.K          # the sample's own row
+        total += int((w.K - t0).sum())
+    _, st = nqs.eloc(ctx, inst, ans, w.samples, precision="f32", **kw)
+    assert st["n_site_rows"] == total
+
+
+def test_resume_matches_oracle_f64(nqs, ctx):
+    """The resumed FP64 path against the oracle at the FP64 bar."""
+    w, inst, ans = setup(nqs, ctx, "c4b", 16)
+    out, _ = nqs.eloc(ctx, inst, ans, w.samples, eps=w.eps, n_eps=w.n_eps, precision="f64", seed=w.seed,
+                      stream_id=2)
+    ref = oracle.eloc(w.K, w.n_alpha, w.n_beta, w.h, w.eri, w.chi, w.parent_ptr, w.parent_idx, w.n_hidden,
+                      w.params, w.samples, eps=w.eps, n_eps=w.n_eps, seed=w.seed, stream=2)
+    el = out["eloc"].cpu().numpy()
+    tau = 1e-3 * np.sqrt(np.mean(ref["eloc"] ** 2))
+    assert (np.abs(el - ref["eloc"]) / np.maximum(np.abs(ref["eloc"]), tau)).max() <= 1e-10
