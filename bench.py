@@ -32,27 +32,27 @@ sys.path.insert(0, ROOT)
 
 WORKLOAD = "c2"
 PEAKS = {"f64": 78.6, "f32": 157.3, "bf16": 2500.0}   # MI355X dense MFMA, TFLOP/s
-# HBM bytes per amplitude row of the FP32 bond-contraction kernel from the
-# FETCH_SIZE / WRITE_SIZE counters (copy-calibrated) recorded in
-# profiles/k_psi_chain_K20_chi16_N4096_pmc.txt; valid only for the amplitude
-# source they were taken on (first 16 hex digits of its sha256).
-MEASURED_TRAFFIC = {"f32": {"amplitude_sha16": "0fb40e876bf0d6ef", "bytes_per_row": 25.02}}
+# HBM bytes per launch of the row amplitude kernel of the headline precision,
+# from the FETCH_SIZE / WRITE_SIZE counters (copy-calibrated) recorded in
+# profiles/; valid only for the kernel source they were taken on (first 16 hex
+# digits of the sha256 of psi.hip followed by device.h).
+MEASURED_TRAFFIC = {"f32": {"sha16": "715ef6c50b01b968", "bytes_per_launch": 2.871475e9}}
+KERNEL_SOURCES = ("psi.hip", "device.h")
 
 
-def measured_traffic(prec, rows):
+def kernel_sha16():
     import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, "paper_2507_19276_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(prec):
     rec = MEASURED_TRAFFIC.get(prec)
-    if rec is None:
+    if rec is None or rec["sha16"] != kernel_sha16():
         return None
-    src = os.path.join(ROOT, "paper_2507_19276_amd", "csrc", "amplitude.hip")
-    if hashlib.sha256(open(src, "rb").read()).hexdigest()[:16] != rec["amplitude_sha16"]:
-        return None
-    return rec["bytes_per_row"] * rows
-
-
-def algorithmic_flops_per_row(chi, parent_ptr):
-    # 4 candidates x chi outputs x (d_i chi) inputs x 2 flops, summed over sites
-    return 8 * chi * chi * int(parent_ptr[-1])
+    return rec["bytes_per_launch"]
 
 
 def cpu_baseline(w, seed, gpu_out):
@@ -111,26 +111,28 @@ def run_eloc_bench(args):
         for k in range(args.warmup):
             step(k, prec)
         torch.cuda.synchronize()
-        amp_ms, rows = [], []
+        amp_ms, psi_ms, psi_fl, rows = [], [], [], []
         t0 = time.perf_counter()
         for k in range(args.steps):
             out, st = step(1000 + k, prec)
             amp_ms.append(st["ms_amplitude"])
+            psi_ms.append(st["ms_psi"])
+            psi_fl.append(st["psi_flops"])
             rows.append(st["n_rows"])
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
-        results[prec] = dict(dt=dt, amp_ms=float(np.mean(amp_ms)), rows=float(np.mean(rows)), st=st)
+        results[prec] = dict(dt=dt, amp_ms=float(np.mean(amp_ms)), psi_ms=float(np.mean(psi_ms)),
+                             psi_flops=float(np.mean(psi_fl)), rows=float(np.mean(rows)), st=st)
         print(f"# {prec}: {args.steps} steps in {dt:.3f} s, rows/step {np.mean(rows):.0f}, "
-              f"site-rows/step {st['n_site_rows']}, amplitude stage {np.mean(amp_ms):.3f} ms",
-              file=sys.stderr, flush=True)
+              f"site-rows/step {st['n_site_rows']}, amplitude stage {np.mean(amp_ms):.3f} ms, "
+              f"row amplitude kernel {np.mean(psi_ms):.3f} ms", file=sys.stderr, flush=True)
         if not args.no_cpu_baseline:
             out, st = step(7, prec)
             keep[prec] = (out["eloc"].cpu().numpy(), st["E"])
 
     head = results[head_prec]
     value = args.steps * N / head["dt"]
-    flops = algorithmic_flops_per_row(w.chi, w.parent_ptr) * head["rows"]
-    achieved = flops / (head["amp_ms"] * 1e-3) / 1e12
+    achieved = head["psi_flops"] / (head["psi_ms"] * 1e-3) / 1e12
     peak = PEAKS[head_prec]
     line = {
         "metric": "local energies/sec at fixed bond dim D",
@@ -148,12 +150,16 @@ def run_eloc_bench(args):
         "config": {"workload": "chain K=20 10a+10b, BDG-RNN chain chi=16, 4096 unique samples, "
                                "eps=1e-3, N_eps=64", "global_batch": N, "precision": head_prec},
         "rows_per_step": head["rows"],
-        "by_precision": {p: {"value": args.steps * N / r["dt"], "amplitude_ms": r["amp_ms"],
+        "by_precision": {p: {"value": args.steps * N / r["dt"], "amplitude_stage_ms": r["amp_ms"],
+                             "row_kernel_ms": r["psi_ms"], "row_kernel_tflops": r["psi_flops"] / r["psi_ms"] / 1e9,
                              "ms_per_step": r["dt"] / args.steps * 1e3} for p, r in results.items()},
+        "site_rows_per_step": int(head["st"]["n_site_rows"]),
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "frac": achieved / peak,
-                     "traffic": args.traffic_bytes if args.traffic_bytes else measured_traffic(head_prec, head["rows"]),
-                     "kernel": "k_psi (bond contractions)"},
+                     "traffic": args.traffic_bytes if args.traffic_bytes else measured_traffic(head_prec),
+                     "kernel": "k_psi_mt (row amplitude kernel: bond contractions and conditionals)",
+                     "flops_per_launch": head["psi_flops"], "ms_per_launch": head["psi_ms"],
+                     "kernel_sha16": kernel_sha16()},
     }
     if not args.no_cpu_baseline:
         rec, errs = cpu_baseline(w, w.seed + 7, keep)

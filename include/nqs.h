@@ -110,6 +110,9 @@ typedef struct {
   int64_t n_site_rows;   /* per-site amplitude evaluations executed: sum over rows of the
                             sites computed (K per row without resumption), plus the
                             samples' own pass when rows resume */
+  double ms_psi;         /* device time of the row amplitude kernel launches alone */
+  double psi_flops;      /* their algorithmic bond-contraction flops: 8 chi^2 d_i per
+                            evaluated site i with d_i parents */
 } nqs_eloc_stats;
 
 /* ---- context --------------------------------------------------------- */

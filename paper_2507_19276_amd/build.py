@@ -8,7 +8,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libnqs.so")
 BUILD = os.path.join(ROOT, "_build")
-SOURCES = ["enumerate.hip", "order.hip", "amplitude.hip", "adjoint.hip", "runtime.cpp", "serve.cpp"]
+SOURCES = ["enumerate.hip", "order.hip", "psi.hip", "psi_bf16.hip", "energy.hip", "adjoint.hip", "runtime.cpp",
+           "serve.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-x", "hip", "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
@@ -16,7 +17,7 @@ FLAGS = ["-x", "hip", "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
 # MFMA accumulators in ordinary VGPRs: the epilogues read them directly
 # instead of copying them out of the accumulation registers, and the kernels
 # need fewer registers in total.
-EXTRA = {src: ["-mllvm", "-amdgpu-mfma-vgpr-form"] for src in ("amplitude.hip", "adjoint.hip")}
+EXTRA = {src: ["-mllvm", "-amdgpu-mfma-vgpr-form"] for src in ("psi.hip", "psi_bf16.hip", "adjoint.hip")}
 
 
 def build(verbose: bool = False) -> str:

@@ -1,0 +1,257 @@
+// Energy side of the local energy on gfx950 (arXiv:2507.19276):
+//   * the cos-RBM correlator (Sec. 2.3, Eq. (15));
+//   * the per-sample local-energy reduction (Eqs. (6), (18), (22)) and the
+//     batch sums of Sec. 2.3.
+#include "internal.h"
+#include <cmath>
+
+namespace nqs {
+namespace {
+
+__device__ inline double tlog(double x) { return log(x); }
+__device__ inline float tlog(float x) { return logf(x); }
+
+// ---------------------------------------------------------------------------
+// cos-RBM correlator
+// ---------------------------------------------------------------------------
+
+__device__ inline bool bit_at(uint64_t lo, uint64_t hi, int P) {
+  return P < 64 ? ((lo >> P) & 1ull) : ((hi >> (P - 64)) & 1ull);
+}
+
+// theta_k(n) = b_k + sum_P W_kP x_P, one thread per (sample, k)
+__global__ void k_corr_theta(CorrParams C, const uint64_t* samples, int64_t N, double* theta) {
+  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= N * C.nh) return;
+  const int64_t n = t / C.nh;
+  const int k = int(t % C.nh);
+  const uint64_t lo = samples[2 * n], hi = samples[2 * n + 1];
+  const int nv = 2 * C.K;
+  double th = C.b[k];
+  for (int P = 0; P < nv; ++P)
+    if (bit_at(lo, hi, P)) th += C.W[size_t(k) * nv + P];
+  theta[t] = th;
+}
+
+__device__ inline double tcos(double x) { return cos(x); }
+__device__ inline float tcos(float x) { return cosf(x); }
+__device__ inline double tabs(double x) { return fabs(x); }
+__device__ inline float tabs(float x) { return fabsf(x); }
+
+// theta(m) = theta(n) + sum_{created P} W_:P - sum_{annihilated P} W_:P; one
+// thread per row; cos and log in precision T, the sum of logs in FP64.
+template <typename T>
+__global__ void k_corr_rows(CorrParams C, const uint64_t* m, const int32_t* owner,
+                            const uint64_t* samples, const double* theta, int64_t R, double* lf,
+                            int8_t* sf) {
+  const int64_t r = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (r >= R) return;
+  const int64_t o = owner[r];
+  const uint64_t mlo = m[2 * r], mhi = m[2 * r + 1];
+  const uint64_t nlo = samples[2 * o], nhi = samples[2 * o + 1];
+  int add[4], rem[4], na = 0, nr = 0;
+  uint64_t x = mlo & ~nlo;
+  while (x && na < 4) { add[na++] = __ffsll((unsigned long long)x) - 1; x &= x - 1; }
+  x = mhi & ~nhi;
+  while (x && na < 4) { add[na++] = 64 + __ffsll((unsigned long long)x) - 1; x &= x - 1; }
+  x = nlo & ~mlo;
+  while (x && nr < 4) { rem[nr++] = __ffsll((unsigned long long)x) - 1; x &= x - 1; }
+  x = nhi & ~mhi;
+  while (x && nr < 4) { rem[nr++] = 64 + __ffsll((unsigned long long)x) - 1; x &= x - 1; }
+  const int nv = 2 * C.K;
+  const double* th0 = theta + o * C.nh;
+  double acc = 0.0;
+  int s = 1;
+  for (int k = 0; k < C.nh; ++k) {
+    double th = th0[k];
+    const double* Wk = C.W + size_t(k) * nv;
+    for (int a = 0; a < na; ++a) th += Wk[add[a]];
+    for (int a = 0; a < nr; ++a) th -= Wk[rem[a]];
+    const T c = tcos(T(th));
+    acc += double(tlog(tabs(c)));
+    if (c < T(0)) s = -s;
+  }
+  lf[r] = acc;
+  sf[r] = int8_t(s);
+}
+
+// direct evaluation for arbitrary ONVs (no owner): theta = b + W x
+__global__ void k_corr_direct(CorrParams C, const uint64_t* m, int64_t R, double* lf, int8_t* sf) {
+  const int64_t r = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (r >= R) return;
+  const uint64_t lo = m[2 * r], hi = m[2 * r + 1];
+  const int nv = 2 * C.K;
+  double acc = 0.0;
+  int s = 1;
+  for (int k = 0; k < C.nh; ++k) {
+    double th = C.b[k];
+    for (int P = 0; P < nv; ++P)
+      if (bit_at(lo, hi, P)) th += C.W[size_t(k) * nv + P];
+    const double c = cos(th);
+    acc += log(fabs(c));
+    if (c < 0) s = -s;
+  }
+  lf[r] = acc;
+  sf[r] = int8_t(s);
+}
+
+// ---------------------------------------------------------------------------
+// reductions
+// ---------------------------------------------------------------------------
+
+__device__ inline double wave_sum(double x) {
+  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
+  return x;
+}
+
+// Per sample n (one wavefront): E_loc(n) = H_nn + sum_rows coef * Psi(m)/Psi(n)
+// and Etilde_num(n) = |f_n|^2 H_nn + f_n sum_rows coef f_m Phi(m)/Phi(n).
+__global__ __launch_bounds__(256) void k_reduce(int64_t n0, int64_t n1, const int64_t* rowptr,
+                                                int64_t row_base, const double* coef,
+                                                const double* lphi, const int8_t* sphi,
+                                                const double* lf, const int8_t* sf,
+                                                const double* hdiag, double* eloc, double* etnum,
+                                                double* logabs, int8_t* sign, double* fsq) {
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t n = n0 + int64_t(blockIdx.x) * 4 + wv;
+  if (n >= n1) return;
+  const int64_t r0 = rowptr[n] - row_base, r1 = rowptr[n + 1] - row_base;
+  const double lpn = lphi[r0], lfn = lf[r0];
+  const int sn = int(sphi[r0]) * int(sf[r0]);
+  double se = 0.0, st = 0.0;
+  for (int64_t r = r0 + 1 + lane; r < r1; r += 64) {
+    const double s = double(int(sphi[r]) * int(sf[r]) * sn);
+    se += coef[r] * s * exp(lphi[r] + lf[r] - lpn - lfn);
+    st += coef[r] * s * exp(lfn + lf[r] + lphi[r] - lpn);
+  }
+  se = wave_sum(se);
+  st = wave_sum(st);
+  if (lane == 0) {
+    const double la = lpn + lfn;
+    const bool valid = sn != 0 && isfinite(la);
+    const double f2 = exp(2.0 * lfn);
+    const double hd = hdiag[n];
+    if (eloc) eloc[n] = valid ? hd + se : NAN;
+    if (etnum) etnum[n] = valid ? f2 * hd + st : NAN;
+    if (logabs) logabs[n] = la;
+    if (sign) sign[n] = int8_t(sn);
+    if (fsq) fsq[n] = f2;
+  }
+}
+
+// Batch sums with weights c_n (NaN local energies are left out and counted):
+// out = {sum c, sum c|f|^2, sum c Etilde_num, E, B, var, n_nan, 0}
+__global__ __launch_bounds__(1024) void k_batch_sums(int64_t N, const double* counts, const double* eloc,
+                                                     const double* etnum, const double* fsq,
+                                                     double* out) {
+  __shared__ double red[3][1024];
+  __shared__ double E_sh;
+  const int tid = threadIdx.x;
+  double sc = 0, sf2 = 0, se = 0, nn = 0;
+  for (int64_t n = tid; n < N; n += 1024) {
+    const double c = counts ? counts[n] : 1.0;
+    if (isnan(eloc[n])) { nn += 1; continue; }
+    sc += c;
+    sf2 += c * fsq[n];
+    se += c * etnum[n];
+  }
+  red[0][tid] = sc; red[1][tid] = sf2; red[2][tid] = se;
+  __syncthreads();
+  for (int o = 512; o > 0; o >>= 1) {
+    if (tid < o)
+      for (int k = 0; k < 3; ++k) red[k][tid] += red[k][tid + o];
+    __syncthreads();
+  }
+  if (tid == 0) E_sh = red[2][0] / red[1][0];
+  const double tsc = red[0][0], tsf = red[1][0], tse = red[2][0];
+  __syncthreads();
+  const double E = E_sh;
+  double sv = 0;
+  for (int64_t n = tid; n < N; n += 1024) {
+    const double c = counts ? counts[n] : 1.0;
+    if (isnan(eloc[n])) continue;
+    const double d = eloc[n] - E;
+    sv += c * fsq[n] * d * d;
+  }
+  __syncthreads();
+  red[0][tid] = sv;
+  red[1][tid] = nn;
+  __syncthreads();
+  for (int o = 512; o > 0; o >>= 1) {
+    if (tid < o) { red[0][tid] += red[0][tid + o]; red[1][tid] += red[1][tid + o]; }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    out[0] = tsc; out[1] = tsf; out[2] = tse; out[3] = E; out[4] = tsf / tsc;
+    out[5] = red[0][0] / tsf; out[6] = red[1][0]; out[7] = 0.0;
+  }
+}
+
+__global__ void k_gather_logpsi(int64_t N, const double* lphi, const int8_t* sphi, const double* lf,
+                                const int8_t* sf, double* logabs, int8_t* sign) {
+  const int64_t n = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (n >= N) return;
+  const double l = lphi[n] + (lf ? lf[n] : 0.0);
+  const int s = int(sphi[n]) * (sf ? int(sf[n]) : 1);
+  if (logabs) logabs[n] = l;
+  if (sign) sign[n] = int8_t(s);
+}
+
+inline unsigned grid_for(int64_t units, int per_block) {
+  return unsigned((units + per_block - 1) / per_block);
+}
+
+}  // namespace
+
+hipError_t launch_corr_theta(const CorrParams& C, const uint64_t* samples, int64_t N, double* theta,
+                             hipStream_t st) {
+  if (N <= 0 || C.nh <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_corr_theta, dim3(grid_for(N * C.nh, 256)), dim3(256), 0, st, C, samples, N, theta);
+  return hipGetLastError();
+}
+
+hipError_t launch_corr_rows(const CorrParams& C, const uint64_t* m, const int32_t* owner,
+                            const uint64_t* samples, const double* theta, int64_t R, int precision,
+                            double* lf, int8_t* sf, hipStream_t st) {
+  if (R <= 0) return hipSuccess;
+  if (precision == 0)
+    hipLaunchKernelGGL(k_corr_rows<double>, dim3(grid_for(R, 256)), dim3(256), 0, st, C, m, owner, samples,
+                       theta, R, lf, sf);
+  else
+    hipLaunchKernelGGL(k_corr_rows<float>, dim3(grid_for(R, 256)), dim3(256), 0, st, C, m, owner, samples,
+                       theta, R, lf, sf);
+  return hipGetLastError();
+}
+
+hipError_t launch_corr_direct(const CorrParams& C, const uint64_t* m, int64_t R, double* lf, int8_t* sf,
+                              hipStream_t st) {
+  if (R <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_corr_direct, dim3(grid_for(R, 256)), dim3(256), 0, st, C, m, R, lf, sf);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce(int64_t n0, int64_t n1, const int64_t* rowptr, int64_t row_base, const double* coef,
+                         const double* lphi, const int8_t* sphi, const double* lf, const int8_t* sf,
+                         const double* hdiag, double* eloc, double* etnum, double* logabs, int8_t* sign,
+                         double* fsq, hipStream_t st) {
+  if (n1 <= n0) return hipSuccess;
+  hipLaunchKernelGGL(k_reduce, dim3(grid_for(n1 - n0, 4)), dim3(256), 0, st, n0, n1, rowptr, row_base, coef,
+                     lphi, sphi, lf, sf, hdiag, eloc, etnum, logabs, sign, fsq);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_sums(int64_t N, const double* counts, const double* eloc, const double* etnum,
+                             const double* fsq, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_batch_sums, dim3(1), dim3(1024), 0, st, N, counts, eloc, etnum, fsq, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather_logpsi(int64_t N, const double* lphi, const int8_t* sphi, const double* lf,
+                                const int8_t* sf, double* logabs, int8_t* sign, hipStream_t st) {
+  if (N <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_gather_logpsi, dim3(grid_for(N, 256)), dim3(256), 0, st, N, lphi, sphi, lf, sf,
+                     logabs, sign);
+  return hipGetLastError();
+}
+
+}  // namespace nqs

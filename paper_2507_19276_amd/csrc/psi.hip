@@ -1,0 +1,428 @@
+// BDG-RNN / MPS-RNN forward in FP64 and FP32 on gfx950 (arXiv:2507.19276,
+// Sec. 2.1 Eqs. (9)-(10), Sec. 2.2 Eq. (12) without the tensor term): per
+// site i the candidates h_i^s = sum_{j in N(i)} M_ij^s h_j + v_i^s for the
+// four local states, the conditional P^s = h^T eta h normalised over the
+// states allowed by the particle-number / S_z mask (Sec. 3, Eqs. (23)-(24)),
+// the phase sign of w^T h + c, and the carried state h_i^{s_i}.
+//
+// Bond contractions run on MFMA in the transposed form
+//   H_i^T [4chi x rows] = W_i^T [4chi x d_i chi] . X_i^T [d_i chi x rows]
+// so that rows are the N dimension of 16x16 MFMA tiles and every lane holds 4
+// consecutive hidden units of one row and candidate in the MFMA output layout.
+// Carried hidden states live in a lane-private LDS ring of
+// W = (max parent offset + 1) slots.
+#include "device.h"
+
+namespace nqs {
+namespace {
+
+// ---------------------------------------------------------------------------
+// Multi-tile forward: one wavefront owns NTL tiles of 16 rows.  Every A operand
+// fetched from memory feeds NTL MFMAs; after the per-tile partial sums in the
+// MFMA output layout, a reduce-scatter across the four lane groups
+// (permlane32_swap / permlane16_swap, plain VALU) leaves each lane group with
+// the full sums of one tile, so the per-row work (mask, normalisation, sign)
+// runs once per row instead of once per lane group.  log|Phi| is accumulated
+// as a renormalised product of the conditionals P^{s_i} / Z_i (mantissa in T,
+// exponent as an integer) and converted with one log at the end.
+// ---------------------------------------------------------------------------
+__device__ inline void pl16(float a, float b, float& na, float& nb) {
+  auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+  na = __uint_as_float(r[0]);
+  nb = __uint_as_float(r[1]);
+}
+__device__ inline void pl32(float a, float b, float& na, float& nb) {
+  auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+  na = __uint_as_float(r[0]);
+  nb = __uint_as_float(r[1]);
+}
+__device__ inline void pl16(double a, double b, double& na, double& nb) {
+  const uint64_t ua = __double_as_longlong(a), ub = __double_as_longlong(b);
+  auto lo = __builtin_amdgcn_permlane16_swap(uint32_t(ua), uint32_t(ub), false, false);
+  auto hi = __builtin_amdgcn_permlane16_swap(uint32_t(ua >> 32), uint32_t(ub >> 32), false, false);
+  na = __longlong_as_double(int64_t(uint64_t(lo[0]) | (uint64_t(hi[0]) << 32)));
+  nb = __longlong_as_double(int64_t(uint64_t(lo[1]) | (uint64_t(hi[1]) << 32)));
+}
+__device__ inline void pl32(double a, double b, double& na, double& nb) {
+  const uint64_t ua = __double_as_longlong(a), ub = __double_as_longlong(b);
+  auto lo = __builtin_amdgcn_permlane32_swap(uint32_t(ua), uint32_t(ub), false, false);
+  auto hi = __builtin_amdgcn_permlane32_swap(uint32_t(ua >> 32), uint32_t(ub >> 32), false, false);
+  na = __longlong_as_double(int64_t(uint64_t(lo[0]) | (uint64_t(hi[0]) << 32)));
+  nb = __longlong_as_double(int64_t(uint64_t(lo[1]) | (uint64_t(hi[1]) << 32)));
+}
+
+// x[t] is lane group g's partial of tile t; returns the sum over the four lane
+// groups of tile own(g): own = g (4 tiles), g/2 (2 tiles), 0 (1 tile).
+// permlane32_swap(a, b) exchanges the upper half of a with the lower half of
+// b; permlane16_swap(a, b) exchanges the odd 16-lane rows of a with the even
+// rows of b.
+template <typename T, int NTL> struct ReduceOwn;
+template <typename T> struct ReduceOwn<T, 4> {
+  __device__ static T run(const T (&x)[4]) {
+    T a, b, c, d;
+    pl32(x[0], x[2], a, b);
+    const T y02 = a + b;      // lanes 0-31: tile 0, lanes 32-63: tile 2
+    pl32(x[1], x[3], c, d);
+    const T y13 = c + d;      // lanes 0-31: tile 1, lanes 32-63: tile 3
+    pl16(y02, y13, a, b);
+    return a + b;             // lane group g: tile g
+  }
+};
+template <typename T> struct ReduceOwn<T, 2> {
+  __device__ static T run(const T (&x)[2]) {
+    T a, b;
+    pl32(x[0], x[1], a, b);
+    const T y = a + b;        // lanes 0-31: tile 0, lanes 32-63: tile 1 (pair sums)
+    pl16(y, y, a, b);
+    return a + b;
+  }
+};
+template <typename T> struct ReduceOwn<T, 1> {
+  __device__ static T run(const T (&x)[1]) {
+    T a, b;
+    pl32(x[0], x[0], a, b);
+    const T y = a + b;
+    pl16(y, y, a, b);
+    return a + b;
+  }
+};
+
+__device__ inline float tfma(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ inline double tfma(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ inline float tfrexp(float x, int* e) { return frexpf(x, e); }
+__device__ inline double tfrexp(double x, int* e) { return frexp(x, e); }
+
+// Forward amplitude kernel.  One wavefront owns NTL tiles of 16 rows.
+//
+// Operands.  The A stream holds, for every forward edge e (the parents of each
+// site in order; a parentless site has one zero edge), KS = CH/4 k-steps of NT
+// values per lane.  k-step q = 4 tt + v pairs lane group g with parent unit
+// 16 tt + 4 g + v, which is exactly the unit that lane (j, g) produced for
+// row j in register v of output tile tt of the parent site.  The B operand of
+// every MFMA is therefore the lane's own carried state, kept in a lane-private
+// LDS ring: no cross-lane exchange and no barrier between sites.
+//
+// The accumulators start from the bias v_i^s, so after the contractions
+// acc[t][s*TPC + tt] holds the candidates h_i^s for units 16 tt + 4 g + 0..3.
+// The A operands of the next edge are fetched before the current edge's
+// MFMAs, so their latency hides behind the contractions and the epilogue.
+//
+// FOLD: the operands carry sigma = sqrt(eta) (A' = sigma_i M / sigma_j,
+// v' = sigma v, w' = w / sigma, all eta > 0), so the ring holds sigma h and
+// P^s = sum_u x'^2 needs no eta.  STORE: the selected carried state of every
+// site is also written to hstore[K][rpad][CH] for the adjoint.
+// read-only uniform tables in the constant address space: the compiler reads
+// them with scalar loads
+typedef const __attribute__((address_space(4))) int CInt;
+template <typename T> using CT = const __attribute__((address_space(4))) T;
+
+#ifndef NQS_MFMA_PRIO
+#define NQS_MFMA_PRIO 2
+#endif
+constexpr int PRIO = NQS_MFMA_PRIO;
+
+template <typename T> constexpr int prefetch_ksteps(int CH) {
+  return (CH / 4) < 64 / ((CH / 4) * int(sizeof(T) / 4)) ? (CH / 4) : 64 / ((CH / 4) * int(sizeof(T) / 4));
+}
+
+template <typename T, int CH, int NTL, bool FOLD, bool STORE, bool SEED>
+__global__ __launch_bounds__(256) void k_psi_mt(PsiParams<T> P, const uint64_t* __restrict__ m, int64_t R,
+                                                double* __restrict__ lphi, int8_t* __restrict__ sphi, int wpb,
+                                                PsiStates<T> X) {
+  // every floating-point operation below is written out (explicit fma where
+  // one is meant), so that all instances of this kernel round alike: a row
+  // resumed from its sample's stored state ends bit-identical to a row
+  // computed from site 0
+#pragma clang fp contract(off)
+  extern __shared__ __align__(16) unsigned char smem[];
+  typedef typename V4<T>::type V;
+  constexpr int TPC = CH / 16, NT = 4 * TPC, KS = CH / 4, RW = 16 * NTL;
+  constexpr int PQ = prefetch_ksteps<T>(CH);
+  constexpr int ES = KS * NT * 64;              // A values per edge
+  constexpr int SLOT = NTL * TPC * 64;          // V entries per ring slot
+  // the wavefront index is uniform: keep it (and all that derives from it:
+  // rows, start site, edge and slot counters) in scalar registers
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  const int j = lane & 15, g = lane >> 4;
+  const int own = NTL == 4 ? g : (NTL == 2 ? (g >> 1) : 0);
+  const int64_t base = (int64_t(blockIdx.x) * wpb + wv) * RW;
+  if (base >= R) return;   // surplus wavefront of the last block (no block barrier below)
+  // ring: slots 0..W-1 carry states, slot W stays zero (read by the zero edges);
+  // entry ((slot * NTL + t) * TPC + tt) * 64 + lane belongs to this lane only
+  V* ring = reinterpret_cast<V*>(smem) + size_t(wv) * (P.W + 1) * SLOT + lane;
+#pragma unroll
+  for (int k = 0; k < NTL * TPC; ++k) ring[(P.W * NTL * TPC + k) * 64] = V{0, 0, 0, 0};
+  // edge tables and c are uniform and read-only: scalar loads
+  const CInt* fptr = (const CInt*)(P.pptr);
+  const CInt* slots = (const CInt*)(P.slot);
+  const CT<T>* cc = (const CT<T>*)(P.c);
+  // SEED: positions base.. map to rows X.perm[pos], sorted by their first
+  // changed site, and the wavefront starts at the site of its first row
+  const int i0 = SEED ? int(((const __attribute__((address_space(4))) uint8_t*)X.t0)[base]) : 0;
+  uint64_t lo[NTL], hi[NTL];
+  int64_t rowt[NTL];
+  uint64_t olo = 0, ohi = 0;
+#pragma unroll
+  for (int t = 0; t < NTL; ++t) {
+    const int64_t r = base + 16 * t + j;
+    const int64_t rr = r < R ? r : R - 1;
+    rowt[t] = SEED ? int64_t(X.perm[rr]) : rr;
+    lo[t] = m[2 * rowt[t]];
+    hi[t] = m[2 * rowt[t] + 1];
+    if (t == own) { olo = lo[t]; ohi = hi[t]; }
+  }
+  const bool olive = base + 16 * own + j < R;
+  int64_t orow = rowt[0];
+#pragma unroll
+  for (int t = 1; t < NTL; ++t)
+    if (t == own) orow = rowt[t];
+  T prod = T(1);
+  int pexp = 0, sgn = 1, ca = 0, cb = 0, wslot = 0, e = 0;
+  bool bad = false;
+  if (SEED && i0 > 0) {
+    // carried states of the parents of sites >= i0 and the log-product state
+    // before site i0, taken from the row's sample (rows agree with their
+    // sample on every site below their first changed site >= i0)
+    const int s0 = i0 - P.W + 1 > 0 ? i0 - P.W + 1 : 0;
+    for (int s = s0; s < i0; ++s) {
+      V* wr = ring + size_t(s % P.W) * SLOT;
+#pragma unroll
+      for (int t = 0; t < NTL; ++t) {
+        const T* src = X.hs + (size_t(s) * X.ns + X.owner[rowt[t]]) * CH + 4 * g;
+#pragma unroll
+        for (int tt = 0; tt < TPC; ++tt) wr[(t * TPC + tt) * 64] = *reinterpret_cast<const V*>(src + 16 * tt);
+      }
+    }
+    const size_t so = size_t(i0) * X.ns + X.owner[orow];
+    prod = X.pm[so];
+    pexp = X.pe[so];
+    sgn = X.pg[so];
+    const uint64_t below = 2 * i0 >= 64 ? ~0ull : ((1ull << (2 * i0)) - 1);
+    const uint64_t belowh = 2 * i0 <= 64 ? 0ull : (2 * i0 >= 128 ? ~0ull : ((1ull << (2 * i0 - 64)) - 1));
+    ca = __popcll(olo & below & 0x5555555555555555ull) + __popcll(ohi & belowh & 0x5555555555555555ull);
+    cb = __popcll(olo & below & 0xAAAAAAAAAAAAAAAAull) + __popcll(ohi & belowh & 0xAAAAAAAAAAAAAAAAull);
+    wslot = i0 % P.W;
+    e = fptr[i0];
+  }
+  const T* __restrict__ Ab = P.A + lane;
+  T an[PQ][NT];
+#pragma unroll
+  for (int q = 0; q < PQ; ++q)
+#pragma unroll
+    for (int ot = 0; ot < NT; ++ot) an[q][ot] = Ab[size_t(e) * ES + (q * NT + ot) * 64];
+  // bias v of the next site, fetched one site ahead where it fits in 64
+  // registers (otherwise at the start of the site): the accumulators start
+  // from it
+  constexpr bool BPF = NT * 4 * int(sizeof(T) / 4) <= 64;
+  V vn[NT];
+  auto fetch_bias = [&](int i) {
+#pragma unroll
+    for (int ot = 0; ot < NT; ++ot)
+      vn[ot] = *reinterpret_cast<const V*>(P.v + (size_t(i) * 4 + ot / TPC) * CH + 16 * (ot % TPC) + 4 * g);
+  };
+  if (BPF) fetch_bias(i0 < P.K ? i0 : 0);
+  // STORE: the log-product state before each site and the carried state
+  // after it, for rows r < X.ns
+  auto store_pre = [&](int i) {
+    const bool writer = NTL == 4 || (NTL == 2 ? (g & 1) == 0 : g == 0);
+    if (STORE && X.pm && writer && olive && orow < X.ns) {
+      const size_t so = size_t(i) * X.ns + orow;
+      X.pm[so] = prod;
+      X.pe[so] = pexp;
+      X.pg[so] = int8_t(sgn);
+    }
+  };
+  for (int i = i0; i < P.K; ++i) {
+    store_pre(i);
+    V acc[NTL][NT], wv4[TPC], ev4[TPC];
+    // w and eta of this site are needed only after the contractions
+#pragma unroll
+    for (int tt = 0; tt < TPC; ++tt) {
+      wv4[tt] = *reinterpret_cast<const V*>(P.w + size_t(i) * CH + 16 * tt + 4 * g);
+      if (!FOLD) ev4[tt] = *reinterpret_cast<const V*>(P.eta + size_t(i) * CH + 16 * tt + 4 * g);
+    }
+    const int e1 = fptr[i + 1];
+    // one edge: a chi-wide slice of the contraction over the parents
+    auto edge = [&]() {
+      const T* Ae = Ab + size_t(e) * ES;
+      V b[NTL][TPC];
+      const V* rp = ring + size_t(slots[e]) * SLOT;
+#pragma unroll
+      for (int t = 0; t < NTL; ++t)
+#pragma unroll
+        for (int tt = 0; tt < TPC; ++tt) b[t][tt] = rp[(t * TPC + tt) * 64];
+      // next edge (the A stream carries one zero edge past the last one)
+      T nx[PQ][NT];
+#pragma unroll
+      for (int q = 0; q < PQ; ++q)
+#pragma unroll
+        for (int ot = 0; ot < NT; ++ot) nx[q][ot] = Ae[ES + (q * NT + ot) * 64];
+#pragma unroll
+      for (int q = 0; q < KS; ++q)
+#pragma unroll
+        for (int ot = 0; ot < NT; ++ot) {
+          const T a = q < PQ ? an[q < PQ ? q : 0][ot] : Ae[(q * NT + ot) * 64];
+#pragma unroll
+          for (int t = 0; t < NTL; ++t) acc[t][ot] = mfma(a, b[t][q / 4][q % 4], acc[t][ot]);
+        }
+#pragma unroll
+      for (int q = 0; q < PQ; ++q)
+#pragma unroll
+        for (int ot = 0; ot < NT; ++ot) an[q][ot] = nx[q][ot];
+    };
+    if (!BPF) fetch_bias(i);
+    // the contractions run at raised wave priority: an MFMA then issues as soon
+    // as the matrix core frees up, and the other wavefronts' epilogues fill
+    // the VALU slots in between
+    __builtin_amdgcn_s_setprio(PRIO);
+#pragma unroll
+    for (int ot = 0; ot < NT; ++ot)
+#pragma unroll
+      for (int t = 0; t < NTL; ++t) acc[t][ot] = vn[ot];
+    if (BPF) fetch_bias(i + 1 < P.K ? i + 1 : i);
+    do edge(); while (++e < e1);
+    __builtin_amdgcn_s_setprio(0);
+    // epilogue in the MFMA output layout: lane (j, g) holds units 16tt+4g..+3
+    int si[NTL];
+#pragma unroll
+    for (int t = 0; t < NTL; ++t) si[t] = site_state(lo[t], hi[t], i);
+    T pp[4][NTL], dp[NTL];
+#pragma unroll
+    for (int t = 0; t < NTL; ++t) {
+      dp[t] = T(0);
+#pragma unroll
+      for (int s = 0; s < 4; ++s) pp[s][t] = T(0);
+    }
+    V* wr = ring + size_t(wslot) * SLOT;
+#pragma unroll
+    for (int tt = 0; tt < TPC; ++tt) {
+      const V ww = wv4[tt];
+#pragma unroll
+      for (int t = 0; t < NTL; ++t) {
+        V x[4];
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          x[s] = acc[t][s * TPC + tt];
+          const V ex = FOLD ? x[s] : ev4[tt] * x[s];
+          T q = pp[s][t];
+          q = tfma(ex.x, x[s].x, q);
+          q = tfma(ex.y, x[s].y, q);
+          q = tfma(ex.z, x[s].z, q);
+          q = tfma(ex.w, x[s].w, q);
+          pp[s][t] = q;
+        }
+        const V sel01 = (si[t] & 1) ? x[1] : x[0];
+        const V sel23 = (si[t] & 1) ? x[3] : x[2];
+        const V sel = (si[t] & 2) ? sel23 : sel01;
+        T d = dp[t];
+        d = tfma(ww.x, sel.x, d);
+        d = tfma(ww.y, sel.y, d);
+        d = tfma(ww.z, sel.z, d);
+        d = tfma(ww.w, sel.w, d);
+        dp[t] = d;
+        wr[(t * TPC + tt) * 64] = sel;
+        if (STORE) {
+          // positions past R (up to the stride X.ns) get the last row's state:
+          // the adjoint reads padded rows
+          const int64_t r = base + 16 * t + j;
+          if (r < X.ns) *reinterpret_cast<V*>(X.hs + (size_t(i) * X.ns + r) * CH + 16 * tt + 4 * g) = sel;
+        }
+      }
+    }
+    wslot = wslot + 1 == P.W ? 0 : wslot + 1;
+    T ps[4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) ps[s] = ReduceOwn<T, NTL>::run(pp[s]);
+    const T dot = ReduceOwn<T, NTL>::run(dp) + T(cc[i]);
+    // per-row work, once per row: lane group g owns tile own(g)
+    const int osi = site_state(olo, ohi, i);
+    const int rest = P.K - 1 - i;
+    T Z = T(0);
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+      if (allowed(ca, cb, s, rest, P.na, P.nb)) Z += ps[s];
+    if (!allowed(ca, cb, osi, rest, P.na, P.nb)) bad = true;
+    const T p01 = (osi & 1) ? ps[1] : ps[0];
+    const T p23 = (osi & 1) ? ps[3] : ps[2];
+    const T psi_ = (osi & 2) ? p23 : p01;
+    int ex;
+    prod = tfrexp(prod * (psi_ / Z), &ex);
+    pexp += ex;
+    if (dot < T(0)) sgn = -sgn;
+    ca += osi & 1;
+    cb += osi >> 1;
+  }
+  store_pre(P.K);
+  const bool writer = NTL == 4 || (NTL == 2 ? (g & 1) == 0 : g == 0);
+  if (writer && olive) {
+    lphi[orow] = bad ? -INFINITY : 0.5 * (log(double(prod)) + double(pexp) * 0.69314718055994530942);
+    sphi[orow] = int8_t(bad ? 0 : sgn);
+  }
+}
+
+#ifndef NQS_NTL_F32_16
+#define NQS_NTL_F32_16 4
+#endif
+template <typename T> constexpr int ntiles(int CH) {
+  return sizeof(T) == 4 ? (CH <= 16 ? NQS_NTL_F32_16 : (CH <= 32 ? 2 : 1)) : (CH <= 16 ? 2 : 1);
+}
+
+template <typename T, int CH, bool FOLD, bool STORE, bool SEED>
+hipError_t run_psi_mt(const PsiParams<T>& P, const uint64_t* m, int64_t R, double* lphi, int8_t* sphi,
+                      hipStream_t st, const PsiStates<T>& X) {
+  if (R <= 0) return hipSuccess;
+  constexpr int NTL = ntiles<T>(CH);
+  const size_t per_wave = size_t(P.W + 1) * 16 * NTL * CH * sizeof(T);
+  int wpb = 4;
+  while (wpb > 1 && per_wave * wpb > 64 * 1024) wpb >>= 1;
+  if (per_wave * wpb > 160 * 1024) return hipErrorInvalidValue;
+  const int64_t tiles = (R + 16 * NTL - 1) / (16 * NTL);
+  const int64_t blocks = (tiles + wpb - 1) / wpb;
+  hipLaunchKernelGGL((k_psi_mt<T, CH, NTL, FOLD, STORE, SEED>), dim3(unsigned(blocks)), dim3(64 * wpb),
+                     per_wave * wpb, st, P, m, R, lphi, sphi, wpb, X);
+  return hipGetLastError();
+}
+
+template <typename T, int CH>
+hipError_t run_psi_ch(const PsiParams<T>& P, const uint64_t* m, int64_t R, double* lphi, int8_t* sphi,
+                      hipStream_t st, const PsiStates<T>& X, int mode) {
+  switch (mode) {
+    case PSI_PLAIN:
+      if (P.folded) return run_psi_mt<T, CH, true, false, false>(P, m, R, lphi, sphi, st, X);
+      return run_psi_mt<T, CH, false, false, false>(P, m, R, lphi, sphi, st, X);
+    case PSI_STORE:
+      if (P.folded) return run_psi_mt<T, CH, true, true, false>(P, m, R, lphi, sphi, st, X);
+      return run_psi_mt<T, CH, false, true, false>(P, m, R, lphi, sphi, st, X);
+    case PSI_SEED:
+      if (P.folded) return run_psi_mt<T, CH, true, false, true>(P, m, R, lphi, sphi, st, X);
+      return run_psi_mt<T, CH, false, false, true>(P, m, R, lphi, sphi, st, X);
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+template <typename T>
+hipError_t dispatch_psi(const PsiParams<T>& P, const uint64_t* m, int64_t R, double* lphi,
+                        int8_t* sphi, hipStream_t st, const PsiStates<T>& X, int mode) {
+  switch (P.chip) {
+    case 16: return run_psi_ch<T, 16>(P, m, R, lphi, sphi, st, X, mode);
+    case 32: return run_psi_ch<T, 32>(P, m, R, lphi, sphi, st, X, mode);
+    case 48: return run_psi_ch<T, 48>(P, m, R, lphi, sphi, st, X, mode);
+    case 64: return run_psi_ch<T, 64>(P, m, R, lphi, sphi, st, X, mode);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_psi_f64(const PsiParams<double>& P, const uint64_t* m, int64_t R, double* lphi,
+                          int8_t* sphi, hipStream_t st, const PsiStates<double>& X, int mode) {
+  return dispatch_psi<double>(P, m, R, lphi, sphi, st, X, mode);
+}
+
+hipError_t launch_psi_f32(const PsiParams<float>& P, const uint64_t* m, int64_t R, double* lphi,
+                          int8_t* sphi, hipStream_t st, const PsiStates<float>& X, int mode) {
+  return dispatch_psi<float>(P, m, R, lphi, sphi, st, X, mode);
+}
+
+}  // namespace nqs

@@ -1041,8 +1041,19 @@ nqs_status nqs_eloc(nqs_ctx* ctx, const nqs_instance* inst, const nqs_ansatz* an
   }
   if (S.oom) return fail(NQS_ENOMEM, "workspace allocation failed");
   if (ans->nh) HIPCHK(launch_corr_theta(ans->corr(), samples, N, theta, stream));
-  float ms_rows = 0, ms_amp = 0, ms_red = 0;
+  float ms_rows = 0, ms_amp = 0, ms_red = 0, ms_psi = 0;
   int64_t site_rows = 0;
+  double psi_flops = 0;
+  // algorithmic flops of a row evaluated from site k on: 8 chi^2 d_i per site i >= k
+  std::vector<double> tail_flops(K + 1, 0.0);
+  for (int i = K - 1; i >= 0; --i)
+    tail_flops[i] = tail_flops[i + 1] + 8.0 * ans->chi * ans->chi * (ans->pptr[i + 1] - ans->pptr[i]);
+  hipEvent_t kq[2] = {};
+  struct KqGuard {
+    hipEvent_t* e;
+    ~KqGuard() { for (int k = 0; k < 2; ++k) if (e[k]) (void)hipEventDestroy(e[k]); }
+  } kqg{kq};
+  if (timing) for (auto& e : kq) HIPCHK(hipEventCreate(&e));
   if (resume) {
     // the samples' own pass: carried and log-product states at every site
     if (timing) HIPCHK(hipEventRecord(pe[0], stream));
@@ -1065,17 +1076,25 @@ nqs_status nqs_eloc(nqs_ctx* ctx, const nqs_instance* inst, const nqs_ansatz* an
     if (timing) HIPCHK(hipEventRecord(pe[1], stream));
     if (resume) {
       HIPCHK(launch_order_t0(P.rows.t0, Rp, K, rs.cnt, rs.tot, rs.perm, rs.t0, stream));
+      if (timing) HIPCHK(hipEventRecord(kq[0], stream));
       if ((s = run_amplitudes(ans, opts->precision, P.rows.m, Rp, lphi, sphi, stream, &rs, PSI_SEED)) != NQS_OK)
         return s;
+      if (timing) HIPCHK(hipEventRecord(kq[1], stream));
       if (stats) {
         std::vector<int64_t> tot(K + 1);
         HIPCHK(hipMemcpyAsync(tot.data(), rs.tot, sizeof(int64_t) * (K + 1), hipMemcpyDeviceToHost, stream));
         HIPCHK(hipStreamSynchronize(stream));
-        for (int k = 0; k <= K; ++k) site_rows += tot[k] * (K - k);
+        for (int k = 0; k <= K; ++k) {
+          site_rows += tot[k] * (K - k);
+          psi_flops += double(tot[k]) * tail_flops[k];
+        }
       }
     } else {
+      if (timing) HIPCHK(hipEventRecord(kq[0], stream));
       if ((s = run_amplitudes(ans, opts->precision, P.rows.m, Rp, lphi, sphi, stream)) != NQS_OK) return s;
+      if (timing) HIPCHK(hipEventRecord(kq[1], stream));
       site_rows += Rp * K;
+      psi_flops += double(Rp) * tail_flops[0];
     }
     if (timing) HIPCHK(hipEventRecord(pe[2], stream));
     if (ans->nh) {
@@ -1096,6 +1115,7 @@ nqs_status nqs_eloc(nqs_ctx* ctx, const nqs_instance* inst, const nqs_ansatz* an
       HIPCHK(hipEventElapsedTime(&t, pe[0], pe[1])); ms_rows += t;
       HIPCHK(hipEventElapsedTime(&t, pe[1], pe[2])); ms_amp += t;
       HIPCHK(hipEventElapsedTime(&t, pe[2], done)); ms_red += t;
+      HIPCHK(hipEventElapsedTime(&t, kq[0], kq[1])); ms_psi += t;
       (void)hipEventDestroy(done);
     }
   }
@@ -1125,6 +1145,8 @@ nqs_status nqs_eloc(nqs_ctx* ctx, const nqs_instance* inst, const nqs_ansatz* an
     stats->ms_amplitude = ms_amp;
     stats->ms_reduce = ms_red;
     stats->n_site_rows = site_rows;
+    stats->ms_psi = ms_psi;
+    stats->psi_flops = psi_flops;
   }
   return NQS_OK;
 }

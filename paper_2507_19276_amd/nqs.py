@@ -44,7 +44,7 @@ class ElocStats(C.Structure):
                 ("sum_c", C.c_double), ("B", C.c_double), ("E", C.c_double), ("var", C.c_double),
                 ("ms_enumerate", C.c_double), ("ms_draw", C.c_double), ("ms_rows", C.c_double),
                 ("ms_amplitude", C.c_double), ("ms_reduce", C.c_double), ("n_passes", C.c_int64),
-                ("n_site_rows", C.c_int64)]
+                ("n_site_rows", C.c_int64), ("ms_psi", C.c_double), ("psi_flops", C.c_double)]
 
     def to_dict(self) -> Dict[str, float]:
         return {k: getattr(self, k) for k, _ in self._fields_}
