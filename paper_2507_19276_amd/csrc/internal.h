@@ -74,16 +74,30 @@ struct AdjParams {
   const int64_t* offEta;         // device [K]
 };
 
-struct BF16Params {
+// BF16 forward (psi_bf16.hip): same edge tables as PsiParams; FP32 vectors.
+struct B16Params {
   int K, chi, chip, na, nb, W;
-  const int* pptr;
-  const int* pidx;
-  const uint16_t* A;             // bf16 A operands (16x16x32 layout)
-  const int64_t* aoff;
+  const int* pptr;               // [K+1] forward edges (never empty per site)
+  const int* slot;               // [edges] ring slot read by each edge (W: zero slot)
+  const uint16_t* A;             // BF16 A stream, per forward edge + one zero edge (runtime.cpp)
   const float* v;                // [K][4][chip]
   const float* eta;              // [K][chip]
   const float* w;                // [K][chip]
   const float* c;                // [K]
+  bool folded;                   // operands carry sqrt(eta)
+};
+// States of the BF16 forward's STORE / SEED modes (as PsiStates): carried
+// states as BF16 with one power-of-two exponent per (site, row).
+struct B16States {
+  uint16_t* hs = nullptr;        // [K][ns][chip] BF16 carried state / 2^he
+  int32_t* he = nullptr;         // [K][ns]
+  float* pm = nullptr;           // [K+1][ns]
+  int32_t* pe = nullptr;         // [K+1][ns]
+  int8_t* pg = nullptr;          // [K+1][ns]
+  int64_t ns = 0;
+  const int32_t* perm = nullptr;
+  const uint8_t* t0 = nullptr;
+  const int32_t* owner = nullptr;
 };
 
 struct CorrParams {
@@ -160,8 +174,8 @@ inline int64_t order_blocks(int64_t R) { return (R + kOrderChunk - 1) / kOrderCh
 // (device); perm: [R] rows in (t0, row) order; t0s: [R] t0 of each position.
 hipError_t launch_order_t0(const uint8_t* t0, int64_t R, int K, int32_t* cnt, int64_t* tot, int32_t* perm,
                            uint8_t* t0s, hipStream_t st);
-hipError_t launch_psi_bf16(const BF16Params& P, const uint64_t* m, int64_t R, double* lphi,
-                           int8_t* sphi, hipStream_t st);
+hipError_t launch_psi_bf16(const B16Params& P, const uint64_t* m, int64_t R, double* lphi, int8_t* sphi,
+                           hipStream_t st, const B16States& X = B16States(), int mode = PSI_PLAIN);
 hipError_t launch_corr_theta(const CorrParams& C, const uint64_t* samples, int64_t N, double* theta,
                              hipStream_t st);
 hipError_t launch_corr_rows(const CorrParams& C, const uint64_t* m, const int32_t* owner,

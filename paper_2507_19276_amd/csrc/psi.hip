@@ -16,82 +16,6 @@
 namespace nqs {
 namespace {
 
-// ---------------------------------------------------------------------------
-// Multi-tile forward: one wavefront owns NTL tiles of 16 rows.  Every A operand
-// fetched from memory feeds NTL MFMAs; after the per-tile partial sums in the
-// MFMA output layout, a reduce-scatter across the four lane groups
-// (permlane32_swap / permlane16_swap, plain VALU) leaves each lane group with
-// the full sums of one tile, so the per-row work (mask, normalisation, sign)
-// runs once per row instead of once per lane group.  log|Phi| is accumulated
-// as a renormalised product of the conditionals P^{s_i} / Z_i (mantissa in T,
-// exponent as an integer) and converted with one log at the end.
-// ---------------------------------------------------------------------------
-__device__ inline void pl16(float a, float b, float& na, float& nb) {
-  auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(a), __float_as_uint(b), false, false);
-  na = __uint_as_float(r[0]);
-  nb = __uint_as_float(r[1]);
-}
-__device__ inline void pl32(float a, float b, float& na, float& nb) {
-  auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(a), __float_as_uint(b), false, false);
-  na = __uint_as_float(r[0]);
-  nb = __uint_as_float(r[1]);
-}
-__device__ inline void pl16(double a, double b, double& na, double& nb) {
-  const uint64_t ua = __double_as_longlong(a), ub = __double_as_longlong(b);
-  auto lo = __builtin_amdgcn_permlane16_swap(uint32_t(ua), uint32_t(ub), false, false);
-  auto hi = __builtin_amdgcn_permlane16_swap(uint32_t(ua >> 32), uint32_t(ub >> 32), false, false);
-  na = __longlong_as_double(int64_t(uint64_t(lo[0]) | (uint64_t(hi[0]) << 32)));
-  nb = __longlong_as_double(int64_t(uint64_t(lo[1]) | (uint64_t(hi[1]) << 32)));
-}
-__device__ inline void pl32(double a, double b, double& na, double& nb) {
-  const uint64_t ua = __double_as_longlong(a), ub = __double_as_longlong(b);
-  auto lo = __builtin_amdgcn_permlane32_swap(uint32_t(ua), uint32_t(ub), false, false);
-  auto hi = __builtin_amdgcn_permlane32_swap(uint32_t(ua >> 32), uint32_t(ub >> 32), false, false);
-  na = __longlong_as_double(int64_t(uint64_t(lo[0]) | (uint64_t(hi[0]) << 32)));
-  nb = __longlong_as_double(int64_t(uint64_t(lo[1]) | (uint64_t(hi[1]) << 32)));
-}
-
-// x[t] is lane group g's partial of tile t; returns the sum over the four lane
-// groups of tile own(g): own = g (4 tiles), g/2 (2 tiles), 0 (1 tile).
-// permlane32_swap(a, b) exchanges the upper half of a with the lower half of
-// b; permlane16_swap(a, b) exchanges the odd 16-lane rows of a with the even
-// rows of b.
-template <typename T, int NTL> struct ReduceOwn;
-template <typename T> struct ReduceOwn<T, 4> {
-  __device__ static T run(const T (&x)[4]) {
-    T a, b, c, d;
-    pl32(x[0], x[2], a, b);
-    const T y02 = a + b;      // lanes 0-31: tile 0, lanes 32-63: tile 2
-    pl32(x[1], x[3], c, d);
-    const T y13 = c + d;      // lanes 0-31: tile 1, lanes 32-63: tile 3
-    pl16(y02, y13, a, b);
-    return a + b;             // lane group g: tile g
-  }
-};
-template <typename T> struct ReduceOwn<T, 2> {
-  __device__ static T run(const T (&x)[2]) {
-    T a, b;
-    pl32(x[0], x[1], a, b);
-    const T y = a + b;        // lanes 0-31: tile 0, lanes 32-63: tile 1 (pair sums)
-    pl16(y, y, a, b);
-    return a + b;
-  }
-};
-template <typename T> struct ReduceOwn<T, 1> {
-  __device__ static T run(const T (&x)[1]) {
-    T a, b;
-    pl32(x[0], x[0], a, b);
-    const T y = a + b;
-    pl16(y, y, a, b);
-    return a + b;
-  }
-};
-
-__device__ inline float tfma(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
-__device__ inline double tfma(double a, double b, double c) { return __builtin_fma(a, b, c); }
-__device__ inline float tfrexp(float x, int* e) { return frexpf(x, e); }
-__device__ inline double tfrexp(double x, int* e) { return frexp(x, e); }
-
 // Forward amplitude kernel.  One wavefront owns NTL tiles of 16 rows.
 //
 // Operands.  The A stream holds, for every forward edge e (the parents of each
@@ -109,18 +33,8 @@ __device__ inline double tfrexp(double x, int* e) { return frexp(x, e); }
 //
 // FOLD: the operands carry sigma = sqrt(eta) (A' = sigma_i M / sigma_j,
 // v' = sigma v, w' = w / sigma, all eta > 0), so the ring holds sigma h and
-// P^s = sum_u x'^2 needs no eta.  STORE: the selected carried state of every
-// site is also written to hstore[K][rpad][CH] for the adjoint.
-// read-only uniform tables in the constant address space: the compiler reads
-// them with scalar loads
-typedef const __attribute__((address_space(4))) int CInt;
-template <typename T> using CT = const __attribute__((address_space(4))) T;
-
-#ifndef NQS_MFMA_PRIO
-#define NQS_MFMA_PRIO 2
-#endif
-constexpr int PRIO = NQS_MFMA_PRIO;
-
+// P^s = sum_u x'^2 needs no eta.  STORE and SEED: see PsiStates (the
+// samples' pass that stores states, and the resumed row pass).
 template <typename T> constexpr int prefetch_ksteps(int CH) {
   return (CH / 4) < 64 / ((CH / 4) * int(sizeof(T) / 4)) ? (CH / 4) : 64 / ((CH / 4) * int(sizeof(T) / 4));
 }
@@ -197,8 +111,7 @@ __global__ __launch_bounds__(256) void k_psi_mt(PsiParams<T> P, const uint64_t* 
     prod = X.pm[so];
     pexp = X.pe[so];
     sgn = X.pg[so];
-    const uint64_t below = 2 * i0 >= 64 ? ~0ull : ((1ull << (2 * i0)) - 1);
-    const uint64_t belowh = 2 * i0 <= 64 ? 0ull : (2 * i0 >= 128 ? ~0ull : ((1ull << (2 * i0 - 64)) - 1));
+    const uint64_t below = low_bits(2 * i0), belowh = low_bits(2 * i0 - 64);
     ca = __popcll(olo & below & 0x5555555555555555ull) + __popcll(ohi & belowh & 0x5555555555555555ull);
     cb = __popcll(olo & below & 0xAAAAAAAAAAAAAAAAull) + __popcll(ohi & belowh & 0xAAAAAAAAAAAAAAAAull);
     wslot = i0 % P.W;

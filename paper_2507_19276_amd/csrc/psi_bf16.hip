@@ -1,181 +1,440 @@
 // BDG-RNN / MPS-RNN forward with BF16 bond contractions on gfx950
-// (arXiv:2507.19276, Sec. 2.1 Eqs. (9)-(10); the reduced-precision form of
-// the amplitude evaluation): BF16 operands on the 16x16x32 MFMA with FP32
-// accumulation and per-row power-of-two scaled hidden states.
+// (arXiv:2507.19276, Sec. 2.1 Eqs. (9)-(10), Sec. 2.2 Eq. (12) without the
+// tensor term; the reduced-precision form of the amplitude evaluation): BF16
+// operands on MFMA with FP32 accumulation, FP32 epilogue, scaled carried
+// states.
+//
+// Same organisation as the FP64/FP32 kernel (psi.hip): a wavefront owns NTL
+// tiles of 16 rows, rows are the N dimension of the MFMA, and the A operand is
+// k-permuted so that the B operand of every MFMA is the lane's own carried
+// state (lane (j, g) holds units 16 tt + 4 g + 0..3 of row j).  A k-step of the
+// 16x16x32 BF16 MFMA takes two of a lane's quads (tt = 2q, 2q+1: element e is
+// unit 16 (2q + e/4) + 4 g + e%4); when chip/16 is odd the last quad goes
+// through one 16x16x16 step (element e is unit 16 tt + 4 g + e).
+//
+// Scaled states.  The ring keeps each carried state as BF16 h / 2^E, with one
+// exponent E per ring slot shared by the wavefront.  A site with parents of
+// exponents E_p works at E_ref = max E_p: parents with E_p < E_ref are scaled
+// by 2^(E_p - E_ref), the accumulators start from v / 2^E_ref and the sign
+// test uses c / 2^E_ref.  The conditionals P^s / sum P and the sign of
+// w^T h + c do not depend on a common power-of-two scale, and every operation
+// here (BF16 rounding, MFMA products and sums, FP32 arithmetic) commutes with
+// it exactly barring underflow, so the result does not depend on the
+// exponents chosen.  A new state keeps E_ref unless the largest normaliser Z
+// of the wavefront leaves [2^-40, 2^40]; then it is renormalised by 2^(e/2)
+// with e the exponent of that Z, which keeps every operand far from the ends
+// of the FP32/BF16 range whatever the magnitudes of v and M.
 #include "device.h"
+#include <type_traits>
 
 namespace nqs {
 namespace {
 
-// ---------------------------------------------------------------------------
-// BF16 bond contractions (16x16x32 MFMA, FP32 accumulate) with scaled hidden
-// states: the ring keeps h_j / 2^e_j in BF16 with a per-row exponent e_j per
-// slot.  At site i the parents are brought to the common exponent
-// e_ref = max_j e_j (exact power-of-two rescaling), the MFMA result is
-// h_i / 2^e_ref, and v, c are scaled alike.  The conditional ratios
-// P^s / sum P and the sign of w^T h + c do not depend on the common scale, so
-// the scaling is exact in exact arithmetic and keeps every operand near 1.
-// ---------------------------------------------------------------------------
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
-typedef __bf16 bf4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf2 __attribute__((ext_vector_type(2)));
+typedef short s4 __attribute__((ext_vector_type(4)));
+typedef unsigned u2 __attribute__((ext_vector_type(2)));
+typedef unsigned u4 __attribute__((ext_vector_type(4)));
 
-__device__ inline f4 mfma_bf16(bf8 a, bf8 b, f4 c) {
-  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+__device__ inline f4 mfma_k32(u4 a, u4 b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8, a), __builtin_bit_cast(bf8, b), c, 0, 0,
+                                                 0);
+}
+__device__ inline f4 mfma_k16(u2 a, u2 b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(__builtin_bit_cast(s4, a), __builtin_bit_cast(s4, b), c, 0, 0,
+                                                   0);
 }
 
-template <int CH>
-__global__ __launch_bounds__(256) void k_psi_bf16(BF16Params P, const uint64_t* m, int64_t R,
-                                                  double* lphi, int8_t* sphi, int rs, int wpb) {
+// four FP32 values to a BF16 quad (round to nearest even)
+__device__ inline u2 pack_bf16(f4 x) {
+  const bf2 lo = {(__bf16)x.x, (__bf16)x.y};
+  const bf2 hi = {(__bf16)x.z, (__bf16)x.w};
+  return u2{__builtin_bit_cast(unsigned, lo), __builtin_bit_cast(unsigned, hi)};
+}
+__device__ inline f4 unpack_bf16(u2 q) {
+  return f4{__uint_as_float(q.x << 16), __uint_as_float(q.x & 0xFFFF0000u), __uint_as_float(q.y << 16),
+            __uint_as_float(q.y & 0xFFFF0000u)};
+}
+// a BF16 quad times 2^k, k <= 0 (exact barring underflow)
+__device__ inline u2 scale_bf16(u2 q, int k) {
+  f4 x = unpack_bf16(q);
+  x.x = ldexpf(x.x, k);
+  x.y = ldexpf(x.y, k);
+  x.z = ldexpf(x.z, k);
+  x.w = ldexpf(x.w, k);
+  return pack_bf16(x);
+}
+
+// maximum over the wavefront (all lanes receive it)
+__device__ inline float wave_max(float x) {
+  float a, b;
+  pl32(x, x, a, b);
+  x = fmaxf(a, b);
+  pl16(x, x, a, b);
+  x = fmaxf(a, b);
+  // within each row of 16 lanes: rotations by 1, 2, 4, 8 (DPP row_ror)
+  x = fmaxf(x, __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x121, 0xF, 0xF, false)));
+  x = fmaxf(x, __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x122, 0xF, 0xF, false)));
+  x = fmaxf(x, __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x124, 0xF, 0xF, false)));
+  x = fmaxf(x, __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x128, 0xF, 0xF, false)));
+  return x;
+}
+__device__ inline int wave_max(int x) {
+  float a, b;
+  pl32(__int_as_float(x), __int_as_float(x), a, b);
+  x = max(__float_as_int(a), __float_as_int(b));
+  pl16(__int_as_float(x), __int_as_float(x), a, b);
+  x = max(__float_as_int(a), __float_as_int(b));
+  x = max(x, __builtin_amdgcn_update_dpp(0, x, 0x121, 0xF, 0xF, false));
+  x = max(x, __builtin_amdgcn_update_dpp(0, x, 0x122, 0xF, 0xF, false));
+  x = max(x, __builtin_amdgcn_update_dpp(0, x, 0x124, 0xF, 0xF, false));
+  x = max(x, __builtin_amdgcn_update_dpp(0, x, 0x128, 0xF, 0xF, false));
+  return x;
+}
+
+template <int CH> constexpr int ntiles_b16() { return CH <= 16 ? 4 : (CH <= 32 ? 2 : 1); }
+
+template <int CH, int NTL, bool FOLD, bool STORE, bool SEED>
+__global__ __launch_bounds__(256) void k_psi_b16(B16Params P, const uint64_t* __restrict__ m, int64_t R,
+                                                 double* __restrict__ lphi, int8_t* __restrict__ sphi, int wpb,
+                                                 B16States X) {
+  // explicit floating-point operations only (see psi.hip): resumed rows end
+  // bit-identical to rows evaluated from site 0
+#pragma clang fp contract(off)
   extern __shared__ __align__(16) unsigned char smem[];
-  constexpr int TPC = CH / 16;
-  constexpr int NT = 4 * TPC;
-  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  constexpr int TPC = CH / 16, NT = 4 * TPC, NP = TPC / 2, ODD = TPC & 1, RW = 16 * NTL;
+  constexpr int SLOT = NTL * TPC * 64;                          // quads per ring slot
+  constexpr int64_t EQ = int64_t(NP) * NT * 64 * 2 + ODD * NT * 64;       // A stream: u2 units per edge
+  constexpr bool APF = NT * (NP ? 4 : 2) <= 32;                 // fetch the next edge's first k-step ahead
+  constexpr bool BPF = NT * 4 <= 32;                            // fetch the next site's bias ahead
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   const int j = lane & 15, g = lane >> 4;
-  const size_t ring_elems = size_t(P.W) * 16 * rs;
-  unsigned char* base = smem + size_t(wv) * (ring_elems * 2 + size_t(P.W) * 16 * 4);
-  __bf16* ring = reinterpret_cast<__bf16*>(base);
-  int* exps = reinterpret_cast<int*>(base + ring_elems * 2);
-  const int64_t tile = int64_t(blockIdx.x) * wpb + wv;
-  if (tile * 16 >= R) return;   // surplus wavefront of the last block (no block barrier below)
-  const int64_t row = tile * 16 + j;
-  const bool live = row < R;
-  const int64_t rr = live ? row : (R - 1);
-  const uint64_t lo = m[2 * rr], hi = m[2 * rr + 1];
-  const bf8* Abase = reinterpret_cast<const bf8*>(P.A);
-  double logacc = 0.0;
-  int sgn = 1, ca = 0, cb = 0;
+  const int own = NTL == 4 ? g : (NTL == 2 ? (g >> 1) : 0);
+  const int64_t base = (int64_t(blockIdx.x) * wpb + wv) * RW;
+  if (base >= R) return;   // surplus wavefront of the last block (no block barrier below)
+  // per wavefront: (W+1) slots of quads, then (W+1) exponents, all lane-private
+  // (every lane keeps its own copy of the wavefront-uniform exponents)
+  const size_t wbytes = size_t(P.W + 1) * (SLOT * 8 + 64 * 4);
+  u2* ring = reinterpret_cast<u2*>(smem + size_t(wv) * wbytes) + lane;
+  int* Ering = reinterpret_cast<int*>(smem + size_t(wv) * wbytes + size_t(P.W + 1) * SLOT * 8) + lane;
+#pragma unroll
+  for (int k = 0; k < NTL * TPC; ++k) ring[(P.W * NTL * TPC + k) * 64] = u2{0u, 0u};
+  Ering[P.W * 64] = 0;
+  const CInt* fptr = (const CInt*)(P.pptr);
+  const CInt* slots = (const CInt*)(P.slot);
+  const CT<float>* cc = (const CT<float>*)(P.c);
+  const int i0 = SEED ? int(((const __attribute__((address_space(4))) uint8_t*)X.t0)[base]) : 0;
+  uint64_t lo[NTL], hi[NTL];
+  int64_t rowt[NTL];
+  uint64_t olo = 0, ohi = 0;
+#pragma unroll
+  for (int t = 0; t < NTL; ++t) {
+    const int64_t r = base + 16 * t + j;
+    const int64_t rr = r < R ? r : R - 1;
+    rowt[t] = SEED ? int64_t(X.perm[rr]) : rr;
+    lo[t] = m[2 * rowt[t]];
+    hi[t] = m[2 * rowt[t] + 1];
+    if (t == own) { olo = lo[t]; ohi = hi[t]; }
+  }
+  const bool olive = base + 16 * own + j < R;
+  int64_t orow = rowt[0];
+#pragma unroll
+  for (int t = 1; t < NTL; ++t)
+    if (t == own) orow = rowt[t];
+  float prod = 1.0f;
+  int pexp = 0, sgn = 1, ca = 0, cb = 0, wslot = 0, e = 0;
   bool bad = false;
-  for (int i = 0; i < P.K; ++i) {
-    f4 acc[NT];
+  if (SEED && i0 > 0) {
+    // carried states of the parents of sites >= i0 from the rows' samples,
+    // brought to one exponent per slot (the wavefront's largest)
+    const int s0 = i0 - P.W + 1 > 0 ? i0 - P.W + 1 : 0;
+    for (int s = s0; s < i0; ++s) {
+      int es[NTL], emax = -(1 << 30);
 #pragma unroll
-    for (int ot = 0; ot < NT; ++ot) acc[ot] = f4{0, 0, 0, 0};
-    const int e0 = P.pptr[i], d = P.pptr[i + 1] - e0;
-    int eref = 0;
-    if (d > 0) {
-      eref = -100000;
-      for (int e = 0; e < d; ++e) eref = max(eref, exps[(P.pidx[e0 + e] % P.W) * 16 + j]);
-    }
-    const int KQ = (d * CH + 31) / 32;
-    const bf8* A = Abase + P.aoff[i] / 8 + lane;
-    for (int q = 0; q < KQ; ++q) {
-      const int k0 = 32 * q + 8 * g;
-      const int el = k0 / CH, kk = k0 % CH;
-      bf8 b;
-      if (el < d) {
-        const int slot = P.pidx[e0 + el] % P.W;
-        b = *reinterpret_cast<const bf8*>(ring + (slot * 16 + j) * rs + kk);
-        const int sh = exps[slot * 16 + j] - eref;
-        if (sh != 0) {
-#pragma unroll
-          for (int t = 0; t < 8; ++t) b[t] = (__bf16)ldexpf(float(b[t]), sh);
-        }
-      } else {
-#pragma unroll
-        for (int t = 0; t < 8; ++t) b[t] = (__bf16)0.0f;
+      for (int t = 0; t < NTL; ++t) {
+        es[t] = X.he[size_t(s) * X.ns + X.owner[rowt[t]]];
+        emax = max(emax, es[t]);
       }
+      const int ew = __builtin_amdgcn_readfirstlane(wave_max(emax));
+      u2* wr = ring + size_t(s % P.W) * SLOT;
 #pragma unroll
-      for (int ot = 0; ot < NT; ++ot) acc[ot] = mfma_bf16(A[(q * NT + ot) * 64], b, acc[ot]);
+      for (int t = 0; t < NTL; ++t) {
+        const u2* src = reinterpret_cast<const u2*>(X.hs + (size_t(s) * X.ns + X.owner[rowt[t]]) * CH + 4 * g);
+#pragma unroll
+        for (int tt = 0; tt < TPC; ++tt) {
+          u2 q = src[4 * tt];
+          if (es[t] != ew) q = scale_bf16(q, es[t] - ew);
+          wr[(t * TPC + tt) * 64] = q;
+        }
+      }
+      Ering[(s % P.W) * 64] = ew;
     }
+    const size_t so = size_t(i0) * X.ns + X.owner[orow];
+    prod = X.pm[so];
+    pexp = X.pe[so];
+    sgn = X.pg[so];
+    const uint64_t below = low_bits(2 * i0), belowh = low_bits(2 * i0 - 64);
+    ca = __popcll(olo & below & 0x5555555555555555ull) + __popcll(ohi & belowh & 0x5555555555555555ull);
+    cb = __popcll(olo & below & 0xAAAAAAAAAAAAAAAAull) + __popcll(ohi & belowh & 0xAAAAAAAAAAAAAAAAull);
+    wslot = i0 % P.W;
+    e = fptr[i0];
+  }
+  // A stream in u2 units: per edge NP pair steps of [ot][lane] u4, then (ODD)
+  // one step of [ot][lane] u2
+  const u2* __restrict__ Ab = reinterpret_cast<const u2*>(P.A);
+  typedef typename std::conditional<(NP > 0), u4, u2>::type FA;   // first k-step operand type
+  FA an[APF ? NT : 1];
+  auto first_step = [&](int64_t edge, FA (&dst)[APF ? NT : 1]) {
+#pragma unroll
+    for (int ot = 0; ot < (APF ? NT : 1); ++ot) {
+      if constexpr (NP > 0)
+        dst[ot] = reinterpret_cast<const u4*>(Ab + edge * EQ)[ot * 64 + lane];
+      else
+        dst[ot] = (Ab + edge * EQ)[ot * 64 + lane];
+    }
+  };
+  if (APF) first_step(e, an);
+  f4 vn[NT];
+  auto fetch_bias = [&](int i) {
+#pragma unroll
+    for (int ot = 0; ot < NT; ++ot)
+      vn[ot] = *reinterpret_cast<const f4*>(P.v + (size_t(i) * 4 + ot / TPC) * CH + 16 * (ot % TPC) + 4 * g);
+  };
+  if (BPF) fetch_bias(i0 < P.K ? i0 : 0);
+  auto store_pre = [&](int i) {
+    const bool writer = NTL == 4 || (NTL == 2 ? (g & 1) == 0 : g == 0);
+    if (STORE && writer && olive && orow < X.ns) {
+      const size_t so = size_t(i) * X.ns + orow;
+      X.pm[so] = prod;
+      X.pe[so] = pexp;
+      X.pg[so] = int8_t(sgn);
+    }
+  };
+  for (int i = i0; i < P.K; ++i) {
+    store_pre(i);
+    f4 acc[NTL][NT], wv4[TPC], ev4[TPC];
+#pragma unroll
+    for (int tt = 0; tt < TPC; ++tt) {
+      wv4[tt] = *reinterpret_cast<const f4*>(P.w + size_t(i) * CH + 16 * tt + 4 * g);
+      if (!FOLD) ev4[tt] = *reinterpret_cast<const f4*>(P.eta + size_t(i) * CH + 16 * tt + 4 * g);
+    }
+    const int e1 = fptr[i + 1];
+    // the parents' common exponent
+    int eref = -(1 << 30);
+    for (int ee = e; ee < e1; ++ee) eref = max(eref, __builtin_amdgcn_readfirstlane(Ering[slots[ee] * 64]));
+    auto edge = [&]() {
+      const u2* Ae = Ab + int64_t(e) * EQ;
+      const int ep = __builtin_amdgcn_readfirstlane(Ering[slots[e] * 64]);
+      u2 b[NTL][TPC];
+      const u2* rp = ring + size_t(slots[e]) * SLOT;
+#pragma unroll
+      for (int t = 0; t < NTL; ++t)
+#pragma unroll
+        for (int tt = 0; tt < TPC; ++tt) b[t][tt] = rp[(t * TPC + tt) * 64];
+      if (ep != eref) {
+#pragma unroll
+        for (int t = 0; t < NTL; ++t)
+#pragma unroll
+          for (int tt = 0; tt < TPC; ++tt) b[t][tt] = scale_bf16(b[t][tt], ep - eref);
+      }
+      FA nx[APF ? NT : 1];
+      if (APF) first_step(int64_t(e) + 1, nx);   // the stream carries one zero edge past the last
+#pragma unroll
+      for (int q = 0; q < NP; ++q)
+#pragma unroll
+        for (int ot = 0; ot < NT; ++ot) {
+          u4 a;
+          if constexpr (NP > 0 && APF)
+            a = q == 0 ? an[ot] : reinterpret_cast<const u4*>(Ae)[(q * NT + ot) * 64 + lane];
+          else
+            a = reinterpret_cast<const u4*>(Ae)[(q * NT + ot) * 64 + lane];
+#pragma unroll
+          for (int t = 0; t < NTL; ++t) {
+            const u4 bq = {b[t][2 * q].x, b[t][2 * q].y, b[t][2 * q + 1].x, b[t][2 * q + 1].y};
+            acc[t][ot] = mfma_k32(a, bq, acc[t][ot]);
+          }
+        }
+      if constexpr (ODD) {
+#pragma unroll
+        for (int ot = 0; ot < NT; ++ot) {
+          u2 a;
+          if constexpr (NP == 0 && APF)
+            a = an[ot];
+          else
+            a = (Ae + int64_t(NP) * NT * 64 * 2)[ot * 64 + lane];
+#pragma unroll
+          for (int t = 0; t < NTL; ++t) acc[t][ot] = mfma_k16(a, b[t][TPC - 1], acc[t][ot]);
+        }
+      }
+      if (APF) {
+#pragma unroll
+        for (int ot = 0; ot < NT; ++ot) an[ot] = nx[ot];
+      }
+    };
+    if (!BPF) fetch_bias(i);
     const float sc = ldexpf(1.0f, -eref);
-    const float* vi = P.v + size_t(i) * 4 * CH;
-    const float* ei = P.eta + size_t(i) * CH;
+    __builtin_amdgcn_s_setprio(PRIO);
+    if (eref == 0) {
+#pragma unroll
+      for (int ot = 0; ot < NT; ++ot)
+#pragma unroll
+        for (int t = 0; t < NTL; ++t) acc[t][ot] = vn[ot];
+    } else {
+#pragma unroll
+      for (int ot = 0; ot < NT; ++ot) {
+        const f4 vs = vn[ot] * sc;
+#pragma unroll
+        for (int t = 0; t < NTL; ++t) acc[t][ot] = vs;
+      }
+    }
+    if (BPF) fetch_bias(i + 1 < P.K ? i + 1 : i);
+    do edge(); while (++e < e1);
+    __builtin_amdgcn_s_setprio(0);
+    // epilogue (FP32): P^s, selection, w.h; the new states are written after
+    // the renormalisation decision
+    int si[NTL];
+#pragma unroll
+    for (int t = 0; t < NTL; ++t) si[t] = site_state(lo[t], hi[t], i);
+    float pp[4][NTL], dp[NTL];
+    f4 selv[NTL][TPC];
+#pragma unroll
+    for (int t = 0; t < NTL; ++t) {
+      dp[t] = 0.0f;
+#pragma unroll
+      for (int s = 0; s < 4; ++s) pp[s][t] = 0.0f;
+    }
+#pragma unroll
+    for (int tt = 0; tt < TPC; ++tt) {
+      const f4 ww = wv4[tt];
+#pragma unroll
+      for (int t = 0; t < NTL; ++t) {
+        f4 x[4];
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          x[s] = acc[t][s * TPC + tt];
+          const f4 ex = FOLD ? x[s] : ev4[tt] * x[s];
+          float q = pp[s][t];
+          q = tfma(ex.x, x[s].x, q);
+          q = tfma(ex.y, x[s].y, q);
+          q = tfma(ex.z, x[s].z, q);
+          q = tfma(ex.w, x[s].w, q);
+          pp[s][t] = q;
+        }
+        const f4 sel01 = (si[t] & 1) ? x[1] : x[0];
+        const f4 sel23 = (si[t] & 1) ? x[3] : x[2];
+        const f4 sel = (si[t] & 2) ? sel23 : sel01;
+        float d = dp[t];
+        d = tfma(ww.x, sel.x, d);
+        d = tfma(ww.y, sel.y, d);
+        d = tfma(ww.z, sel.z, d);
+        d = tfma(ww.w, sel.w, d);
+        dp[t] = d;
+        selv[t][tt] = sel;
+      }
+    }
     float ps[4];
 #pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      float p = 0;
-#pragma unroll
-      for (int t = 0; t < TPC; ++t) {
-        const int u0 = 16 * t + 4 * g;
-        const f4 vv = *reinterpret_cast<const f4*>(vi + s * CH + u0);
-        const f4 ee = *reinterpret_cast<const f4*>(ei + u0);
-        const f4 x = acc[s * TPC + t] + vv * sc;
-        acc[s * TPC + t] = x;
-        p += ee.x * x.x * x.x + ee.y * x.y * x.y + ee.z * x.z * x.z + ee.w * x.w * x.w;
-      }
-      p += __shfl_xor(p, 16);
-      p += __shfl_xor(p, 32);
-      ps[s] = p;
-    }
-    const int si = site_state(lo, hi, i);
+    for (int s = 0; s < 4; ++s) ps[s] = ReduceOwn<float, NTL>::run(pp[s]);
+    const float dot = ReduceOwn<float, NTL>::run(dp) + float(cc[i]) * sc;
+    const int osi = site_state(olo, ohi, i);
     const int rest = P.K - 1 - i;
-    float Z = 0;
+    float Z = 0.0f;
 #pragma unroll
     for (int s = 0; s < 4; ++s)
       if (allowed(ca, cb, s, rest, P.na, P.nb)) Z += ps[s];
-    if (!allowed(ca, cb, si, rest, P.na, P.nb)) bad = true;
-    const float psi_ = si == 0 ? ps[0] : si == 1 ? ps[1] : si == 2 ? ps[2] : ps[3];
-    logacc += 0.5 * (double(logf(psi_)) - double(logf(Z)));
-    f4 sel[TPC];
+    if (!allowed(ca, cb, osi, rest, P.na, P.nb)) bad = true;
+    const float p01 = (osi & 1) ? ps[1] : ps[0];
+    const float p23 = (osi & 1) ? ps[3] : ps[2];
+    const float psi_ = (osi & 2) ? p23 : p01;
+    int ex;
+    prod = tfrexp(prod * (psi_ / Z), &ex);
+    pexp += ex;
+    if (dot < 0.0f) sgn = -sgn;
+    ca += osi & 1;
+    cb += osi >> 1;
+    // renormalise the new states when the wavefront's largest Z leaves
+    // [2^-40, 2^40] (Z = sum_s |x_s|^2 bounds every unit of the state by sqrt(Z))
+    const float zmax = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(wave_max(Z))));
+    int ez = 0;
+    if (zmax > 0.0f && zmax < INFINITY) (void)frexpf(zmax, &ez);
+    const int kz = (ez > 40 || ez < -40) ? (ez >> 1) : 0;
+    const int enew = eref + kz;
+    u2* wr = ring + size_t(wslot) * SLOT;
 #pragma unroll
-    for (int t = 0; t < TPC; ++t) {
-      sel[t] = acc[t];
+    for (int t = 0; t < NTL; ++t)
 #pragma unroll
-      for (int s = 1; s < 4; ++s)
-        if (si == s) sel[t] = acc[s * TPC + t];
+      for (int tt = 0; tt < TPC; ++tt) {
+        f4 v = selv[t][tt];
+        if (kz != 0) v = v * ldexpf(1.0f, -kz);
+        const u2 q = pack_bf16(v);
+        wr[(t * TPC + tt) * 64] = q;
+        if (STORE) {
+          const int64_t r = base + 16 * t + j;
+          if (r < X.ns) *reinterpret_cast<u2*>(X.hs + (size_t(i) * X.ns + r) * CH + 16 * tt + 4 * g) = q;
+        }
+      }
+    Ering[wslot * 64] = enew;
+    if (STORE) {
+#pragma unroll
+      for (int t = 0; t < NTL; ++t) {
+        const int64_t r = base + 16 * t + j;
+        if (g == 0 && r < X.ns) X.he[size_t(i) * X.ns + r] = enew;
+      }
     }
-    const float* wi = P.w + size_t(i) * CH;
-    float dot = 0, mx = 0;
-#pragma unroll
-    for (int t = 0; t < TPC; ++t) {
-      const f4 ww = *reinterpret_cast<const f4*>(wi + 16 * t + 4 * g);
-      dot += ww.x * sel[t].x + ww.y * sel[t].y + ww.z * sel[t].z + ww.w * sel[t].w;
-      mx = fmaxf(mx, fmaxf(fmaxf(fabsf(sel[t].x), fabsf(sel[t].y)), fmaxf(fabsf(sel[t].z), fabsf(sel[t].w))));
-    }
-    dot += __shfl_xor(dot, 16);
-    dot += __shfl_xor(dot, 32);
-    dot += P.c[i] * sc;
-    if (dot < 0) sgn = -sgn;
-    mx = fmaxf(mx, __shfl_xor(mx, 16));
-    mx = fmaxf(mx, __shfl_xor(mx, 32));
-    int en = 0;
-    if (mx > 0.0f) frexpf(mx, &en);
-    const int slot_i = i % P.W;
-    __bf16* wp = ring + (slot_i * 16 + j) * rs + 4 * g;
-#pragma unroll
-    for (int t = 0; t < TPC; ++t) {
-      bf4 o;
-      o[0] = (__bf16)ldexpf(sel[t].x, -en);
-      o[1] = (__bf16)ldexpf(sel[t].y, -en);
-      o[2] = (__bf16)ldexpf(sel[t].z, -en);
-      o[3] = (__bf16)ldexpf(sel[t].w, -en);
-      *reinterpret_cast<bf4*>(wp + 16 * t) = o;
-    }
-    if (g == 0) exps[slot_i * 16 + j] = eref + en;
-    wave_sync();
-    ca += si & 1;
-    cb += si >> 1;
+    wslot = wslot + 1 == P.W ? 0 : wslot + 1;
   }
-  if (live && g == 0) {
-    lphi[row] = bad ? -INFINITY : logacc;
-    sphi[row] = int8_t(bad ? 0 : sgn);
+  store_pre(P.K);
+  const bool writer = NTL == 4 || (NTL == 2 ? (g & 1) == 0 : g == 0);
+  if (writer && olive) {
+    lphi[orow] = bad ? -INFINITY : 0.5 * (log(double(prod)) + double(pexp) * 0.69314718055994530942);
+    sphi[orow] = int8_t(bad ? 0 : sgn);
   }
 }
 
-template <int CH>
-hipError_t run_psi_bf16(const BF16Params& P, const uint64_t* m, int64_t R, double* lphi, int8_t* sphi,
-                        hipStream_t st) {
+template <int CH, bool FOLD, bool STORE, bool SEED>
+hipError_t run_b16(const B16Params& P, const uint64_t* m, int64_t R, double* lphi, int8_t* sphi, hipStream_t st,
+                   const B16States& X) {
   if (R <= 0) return hipSuccess;
-  const int rs = CH + 8;
-  const size_t per_wave = size_t(P.W) * 16 * rs * 2 + size_t(P.W) * 16 * 4;
+  constexpr int NTL = ntiles_b16<CH>();
+  constexpr int TPC = CH / 16;
+  const size_t per_wave = size_t(P.W + 1) * (NTL * TPC * 64 * 8 + 64 * 4);
   int wpb = 4;
   while (wpb > 1 && per_wave * wpb > 64 * 1024) wpb >>= 1;
   if (per_wave * wpb > 160 * 1024) return hipErrorInvalidValue;
-  const int64_t tiles = (R + 15) / 16;
+  const int64_t tiles = (R + 16 * NTL - 1) / (16 * NTL);
   const int64_t blocks = (tiles + wpb - 1) / wpb;
-  hipLaunchKernelGGL((k_psi_bf16<CH>), dim3(unsigned(blocks)), dim3(64 * wpb), per_wave * wpb, st, P, m, R,
-                     lphi, sphi, rs, wpb);
+  hipLaunchKernelGGL((k_psi_b16<CH, NTL, FOLD, STORE, SEED>), dim3(unsigned(blocks)), dim3(64 * wpb),
+                     per_wave * wpb, st, P, m, R, lphi, sphi, wpb, X);
   return hipGetLastError();
+}
+
+template <int CH>
+hipError_t run_b16_ch(const B16Params& P, const uint64_t* m, int64_t R, double* lphi, int8_t* sphi,
+                      hipStream_t st, const B16States& X, int mode) {
+  switch (mode) {
+    case PSI_PLAIN:
+      if (P.folded) return run_b16<CH, true, false, false>(P, m, R, lphi, sphi, st, X);
+      return run_b16<CH, false, false, false>(P, m, R, lphi, sphi, st, X);
+    case PSI_STORE:
+      if (P.folded) return run_b16<CH, true, true, false>(P, m, R, lphi, sphi, st, X);
+      return run_b16<CH, false, true, false>(P, m, R, lphi, sphi, st, X);
+    case PSI_SEED:
+      if (P.folded) return run_b16<CH, true, false, true>(P, m, R, lphi, sphi, st, X);
+      return run_b16<CH, false, false, true>(P, m, R, lphi, sphi, st, X);
+    default:
+      return hipErrorInvalidValue;
+  }
 }
 
 }  // namespace
 
-hipError_t launch_psi_bf16(const BF16Params& P, const uint64_t* m, int64_t R, double* lphi,
-                           int8_t* sphi, hipStream_t st) {
+hipError_t launch_psi_bf16(const B16Params& P, const uint64_t* m, int64_t R, double* lphi, int8_t* sphi,
+                           hipStream_t st, const B16States& X, int mode) {
   switch (P.chip) {
-    case 16: return run_psi_bf16<16>(P, m, R, lphi, sphi, st);
-    case 32: return run_psi_bf16<32>(P, m, R, lphi, sphi, st);
-    case 48: return run_psi_bf16<48>(P, m, R, lphi, sphi, st);
-    case 64: return run_psi_bf16<64>(P, m, R, lphi, sphi, st);
+    case 16: return run_b16_ch<16>(P, m, R, lphi, sphi, st, X, mode);
+    case 32: return run_b16_ch<32>(P, m, R, lphi, sphi, st, X, mode);
+    case 48: return run_b16_ch<48>(P, m, R, lphi, sphi, st, X, mode);
+    case 64: return run_b16_ch<64>(P, m, R, lphi, sphi, st, X, mode);
     default: return hipErrorInvalidValue;
   }
 }

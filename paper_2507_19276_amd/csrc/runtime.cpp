@@ -210,8 +210,7 @@ struct nqs_ansatz {
   PsiLayout<double> L64, F64;   // F*: sqrt(eta)-folded forward layouts (when every eta > 0)
   PsiLayout<float> L32, F32;
   bool has_fold = false;
-  uint16_t* bfA = nullptr;
-  int64_t* bfAoff = nullptr;
+  uint16_t* bfA = nullptr;  // BF16 forward A stream (folded when has_fold)
   double* d_cb = nullptr;   // correlator b
   double* d_cW = nullptr;   // correlator W
   int64_t* d_offM = nullptr;
@@ -223,7 +222,7 @@ struct nqs_ansatz {
     F64.free_all();
     F32.free_all();
     for (void* p : {(void*)d_pptr, (void*)d_pidx, (void*)d_slot, (void*)d_fptr, (void*)d_fslot, (void*)bfA,
-                    (void*)bfAoff, (void*)d_cb, (void*)d_cW, (void*)d_offM, (void*)d_offV, (void*)d_offEta})
+                    (void*)d_cb, (void*)d_cW, (void*)d_offM, (void*)d_offV, (void*)d_offEta})
       if (p) (void)hipFree(p);
   }
   template <typename T>
@@ -391,37 +390,48 @@ uint16_t to_bf16(float f) {
   return uint16_t(b >> 16);
 }
 
-// BF16 A operands for the 16x16x32 MFMA: per site, k-steps of 32 over the
-// concatenated parent states (k = e_local * chip + kk, zero beyond d_i * chi),
-// [q][ot][lane][8]: lane l holds rows m = l%16 (unit o = 16 ot + m, the f32
-// output layout) and k = 32 q + 8 (l/16) + 0..7.
-nqs_status build_bf16(nqs_ansatz* a, const std::vector<double>& prm) {
-  const int K = a->K, chi = a->chi, CH = a->chip, NT = CH / 4;
-  std::vector<int64_t> aoff(K);
+// BF16 forward A stream (psi_bf16.hip): per forward edge (a parentless site
+// has one zero edge; one more zero edge at the end), TPC/2 pair k-steps of
+// [output tile ot][lane][8] then, when TPC = chip/16 is odd, one k-step of
+// [ot][lane][4].  Lane l holds tile row m = l%16 (output unit o = 16 ot + m,
+// the FP32 output layout) and, for lane group g = l/16, the parent units
+// k = 16 (2q + e/4) + 4 g + e%4 (pair step q, element e) or 16 (TPC-1) + 4 g + e
+// (odd step): each lane's own quads of the parent state.  With fold the
+// operands carry sigma = sqrt(eta) as in build_layout.  Round to nearest even.
+nqs_status build_bf16(nqs_ansatz* a, const std::vector<double>& prm, bool fold) {
+  const int K = a->K, chi = a->chi, CH = a->chip, NT = CH / 4, TPC = CH / 16, NP = TPC / 2;
+  const size_t EQ = size_t(NP) * NT * 64 * 8 + size_t(TPC & 1) * NT * 64 * 4;   // bf16 values per edge
+  std::vector<double> sig(size_t(K) * chi, 1.0);
+  if (fold)
+    for (int i = 0; i < K; ++i)
+      for (int u = 0; u < chi; ++u) sig[size_t(i) * chi + u] = std::sqrt(prm[a->offEta[i] + u]);
   std::vector<uint16_t> A;
+  auto value = [&](int e, int i, int o, int k) -> uint16_t {
+    const int s = o / CH, u = o % CH;
+    if (u >= chi || k >= chi) return 0;
+    const double* M = prm.data() + a->offM[e];
+    const double v = sig[size_t(i) * chi + u] * M[(size_t(s) * chi + u) * chi + k] /
+                     sig[size_t(a->pidx[e]) * chi + k];
+    return to_bf16(float(v));
+  };
   for (int i = 0; i < K; ++i) {
-    aoff[i] = int64_t(A.size());
-    const int e0 = a->pptr[i], d = a->pptr[i + 1] - e0;
-    const int KQ = (d * CH + 31) / 32;
-    for (int q = 0; q < KQ; ++q)
-      for (int ot = 0; ot < NT; ++ot)
-        for (int l = 0; l < 64; ++l)
-          for (int t = 0; t < 8; ++t) {
-            const int k = 32 * q + 8 * (l >> 4) + t;
-            const int el = k / CH, kk = k % CH;
-            const int o = ot * 16 + (l & 15);
-            const int s = o / CH, u = o % CH;
-            double val = 0.0;
-            if (el < d && u < chi && kk < chi) val = prm[a->offM[e0 + el] + (size_t(s) * chi + u) * chi + kk];
-            A.push_back(to_bf16(float(val)));
-          }
+    if (a->pptr[i + 1] == a->pptr[i]) A.resize(A.size() + EQ, 0);   // zero edge
+    for (int e = a->pptr[i]; e < a->pptr[i + 1]; ++e) {
+      for (int q = 0; q < NP; ++q)
+        for (int ot = 0; ot < NT; ++ot)
+          for (int l = 0; l < 64; ++l)
+            for (int el = 0; el < 8; ++el)
+              A.push_back(value(e, i, 16 * ot + (l & 15), 16 * (2 * q + el / 4) + 4 * (l >> 4) + el % 4));
+      if (TPC & 1)
+        for (int ot = 0; ot < NT; ++ot)
+          for (int l = 0; l < 64; ++l)
+            for (int el = 0; el < 4; ++el)
+              A.push_back(value(e, i, 16 * ot + (l & 15), 16 * (TPC - 1) + 4 * (l >> 4) + el));
+    }
   }
+  A.resize(A.size() + EQ, 0);   // fetch-ahead edge
   if (a->bfA) { (void)hipFree(a->bfA); a->bfA = nullptr; }
-  if (a->bfAoff) { (void)hipFree(a->bfAoff); a->bfAoff = nullptr; }
-  nqs_status st;
-  if ((st = upload(&a->bfA, A)) != NQS_OK) return st;
-  if ((st = upload(&a->bfAoff, aoff)) != NQS_OK) return st;
-  return NQS_OK;
+  return upload(&a->bfA, A);
 }
 
 }  // namespace
@@ -664,7 +674,7 @@ nqs_status nqs_ansatz_bind_params(nqs_ansatz* ans, const double* params, hipStre
     if ((st = build_layout<float>(ans, prm, ans->F32, true)) != NQS_OK) return st;
     ans->has_fold = true;
   }
-  if ((st = build_bf16(ans, prm)) != NQS_OK) return st;
+  if ((st = build_bf16(ans, prm, ans->has_fold)) != NQS_OK) return st;
   if (ans->d_cb) { (void)hipFree(ans->d_cb); ans->d_cb = nullptr; }
   if (ans->d_cW) { (void)hipFree(ans->d_cW); ans->d_cW = nullptr; }
   if (ans->nh) {
@@ -699,8 +709,9 @@ nqs_status check_samples(nqs_ctx* ctx, const uint64_t* samples, int64_t N, int K
 // Device state of resumed amplitude rows (FP64/FP32): the samples' carried
 // states and log-product states, and the order of the current pass's rows.
 struct Resume {
-  void* hs = nullptr;       // [K][N][chip] T
-  void* pm = nullptr;       // [K+1][N] T
+  void* hs = nullptr;       // [K][N][chip] T (BF16: uint16)
+  int32_t* he = nullptr;    // BF16: [K][N] state exponents
+  void* pm = nullptr;       // [K+1][N] T (BF16: float)
   int32_t* pe = nullptr;    // [K+1][N]
   int8_t* pg = nullptr;     // [K+1][N]
   int64_t ns = 0;
@@ -725,11 +736,29 @@ PsiStates<T> states(const Resume& r) {
   return X;
 }
 
+B16States states_b16(const Resume& r) {
+  B16States X;
+  X.hs = static_cast<uint16_t*>(r.hs);
+  X.he = r.he;
+  X.pm = static_cast<float*>(r.pm);
+  X.pe = r.pe;
+  X.pg = r.pg;
+  X.ns = r.ns;
+  X.perm = r.perm;
+  X.t0 = r.t0;
+  X.owner = r.owner;
+  return X;
+}
+
+// bytes per element of the resume state arrays: carried state, log-product mantissa
+size_t state_bytes(int precision) { return precision == NQS_F64 ? 8 : (precision == NQS_F32 ? 4 : 2); }
+size_t mantissa_bytes(int precision) { return precision == NQS_F64 ? 8 : 4; }
+
 // amplitudes of R rows into (lphi, sphi).  mode PSI_STORE (samples, with rs)
-// or PSI_SEED (rows of a pass, with rs and its order) for FP64/FP32 only.
+// or PSI_SEED (rows of a pass, with rs and its order).
 nqs_status run_amplitudes(const nqs_ansatz* a, int precision, const uint64_t* m, int64_t R, double* lphi,
                           int8_t* sphi, hipStream_t st, const Resume* rs = nullptr, int mode = PSI_PLAIN) {
-  if (mode != PSI_PLAIN && (!rs || precision == NQS_BF16)) return fail(NQS_EINVAL, "resume state missing");
+  if (mode != PSI_PLAIN && !rs) return fail(NQS_EINVAL, "resume state missing");
   if (precision == NQS_F64) {
     HIPCHK(launch_psi_f64(a->params(a->fwd64()), m, R, lphi, sphi, st,
                           rs ? states<double>(*rs) : PsiStates<double>(), mode));
@@ -737,11 +766,12 @@ nqs_status run_amplitudes(const nqs_ansatz* a, int precision, const uint64_t* m,
     HIPCHK(launch_psi_f32(a->params(a->fwd32()), m, R, lphi, sphi, st,
                           rs ? states<float>(*rs) : PsiStates<float>(), mode));
   } else if (precision == NQS_BF16) {
-    BF16Params P{};
+    const PsiLayout<float>& L = a->fwd32();
+    B16Params P{};
     P.K = a->K; P.chi = a->chi; P.chip = a->chip; P.na = a->na; P.nb = a->nb; P.W = a->W;
-    P.pptr = a->d_pptr; P.pidx = a->d_pidx; P.A = a->bfA; P.aoff = a->bfAoff;
-    P.v = a->L32.v; P.eta = a->L32.eta; P.w = a->L32.w; P.c = a->L32.c;
-    hipError_t e = launch_psi_bf16(P, m, R, lphi, sphi, st);
+    P.pptr = a->d_fptr; P.slot = a->d_fslot; P.A = a->bfA;
+    P.v = L.v; P.eta = L.eta; P.w = L.w; P.c = L.c; P.folded = L.folded;
+    hipError_t e = launch_psi_bf16(P, m, R, lphi, sphi, st, rs ? states_b16(*rs) : B16States(), mode);
     if (e == hipErrorNotSupported) return fail(NQS_EUNSUPPORTED, "BF16 amplitude path not available");
     HIPCHK(e);
   } else {
@@ -873,10 +903,8 @@ nqs_status check_opts(const nqs_eloc_opts* o) {
   return NQS_OK;
 }
 
-// rows resume from their samples' states (FP64/FP32 amplitude paths)
-bool resumes(const nqs_eloc_opts& o) {
-  return o.precision != NQS_BF16 && !(o.flags & NQS_ELOC_FULL_RECOMPUTE);
-}
+// rows resume from their samples' states
+bool resumes(const nqs_eloc_opts& o) { return !(o.flags & NQS_ELOC_FULL_RECOMPUTE); }
 
 }  // namespace
 
@@ -1024,9 +1052,9 @@ nqs_status nqs_eloc(nqs_ctx* ctx, const nqs_instance* inst, const nqs_ansatz* an
   double* lphi_s = nullptr;
   int8_t* sphi_s = nullptr;
   if (resume) {
-    const size_t esz = opts->precision == NQS_F64 ? 8 : 4;
-    rs.hs = S.get<unsigned char>(size_t(K) * N * ans->chip * esz);
-    rs.pm = S.get<unsigned char>(size_t(K + 1) * N * esz);
+    rs.hs = S.get<unsigned char>(size_t(K) * N * ans->chip * state_bytes(opts->precision));
+    if (opts->precision == NQS_BF16) rs.he = S.get<int32_t>(size_t(K) * N);
+    rs.pm = S.get<unsigned char>(size_t(K + 1) * N * mantissa_bytes(opts->precision));
     rs.pe = S.get<int32_t>(size_t(K + 1) * N);
     rs.pg = S.get<int8_t>(size_t(K + 1) * N);
     rs.ns = N;
@@ -1203,9 +1231,10 @@ nqs_status nqs_eloc_workspace_bytes(const nqs_instance* inst, const nqs_ansatz* 
   if (ans->nh) b += al(size_t(N) * ans->nh * 8);
   if (resumes(*opts)) {
     // samples' carried and log-product states, the pass's row order
-    const size_t esz = opts->precision == NQS_F64 ? 8 : 4;
     const int K = ans->K;
-    b += al(size_t(K) * N * ans->chip * esz) + al(size_t(K + 1) * N * esz) + al(size_t(K + 1) * N * 4);
+    b += al(size_t(K) * N * ans->chip * state_bytes(opts->precision));
+    if (opts->precision == NQS_BF16) b += al(size_t(K) * N * 4);
+    b += al(size_t(K + 1) * N * mantissa_bytes(opts->precision)) + al(size_t(K + 1) * N * 4);
     b += al(size_t(K + 1) * N) + al(size_t(rows) * 4) + 2 * al(size_t(rows));
     b += al(size_t(order_blocks(rows)) * (K + 1) * 4) + al(size_t(K + 1) * 8);
     b += al(size_t(N) * 8) + al(size_t(N));
