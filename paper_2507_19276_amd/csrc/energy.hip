@@ -106,6 +106,9 @@ __device__ inline double wave_sum(double x) {
 
 // Per sample n (one wavefront): E_loc(n) = H_nn + sum_rows coef * Psi(m)/Psi(n)
 // and Etilde_num(n) = |f_n|^2 H_nn + f_n sum_rows coef f_m Phi(m)/Phi(n).
+// CORR = false: no correlator (log|f| = 0, sign f = +1; the same arithmetic
+// with the zero terms left out, which changes no bit)
+template <bool CORR>
 __global__ __launch_bounds__(256) void k_reduce(int64_t n0, int64_t n1, const int64_t* rowptr,
                                                 int64_t row_base, const double* coef,
                                                 const double* lphi, const int8_t* sphi,
@@ -116,13 +119,20 @@ __global__ __launch_bounds__(256) void k_reduce(int64_t n0, int64_t n1, const in
   const int64_t n = n0 + int64_t(blockIdx.x) * 4 + wv;
   if (n >= n1) return;
   const int64_t r0 = rowptr[n] - row_base, r1 = rowptr[n + 1] - row_base;
-  const double lpn = lphi[r0], lfn = lf[r0];
-  const int sn = int(sphi[r0]) * int(sf[r0]);
+  const double lpn = lphi[r0], lfn = CORR ? lf[r0] : 0.0;
+  const int sn = CORR ? int(sphi[r0]) * int(sf[r0]) : int(sphi[r0]);
   double se = 0.0, st = 0.0;
   for (int64_t r = r0 + 1 + lane; r < r1; r += 64) {
-    const double s = double(int(sphi[r]) * int(sf[r]) * sn);
-    se += coef[r] * s * exp(lphi[r] + lf[r] - lpn - lfn);
-    st += coef[r] * s * exp(lfn + lf[r] + lphi[r] - lpn);
+    if (CORR) {
+      const double s = double(int(sphi[r]) * int(sf[r]) * sn);
+      se += coef[r] * s * exp(lphi[r] + lf[r] - lpn - lfn);
+      st += coef[r] * s * exp(lfn + lf[r] + lphi[r] - lpn);
+    } else {
+      const double s = double(int(sphi[r]) * sn);
+      const double x = coef[r] * s * exp(lphi[r] - lpn);
+      se += x;
+      st += x;
+    }
   }
   se = wave_sum(se);
   st = wave_sum(st);
@@ -235,8 +245,12 @@ hipError_t launch_reduce(int64_t n0, int64_t n1, const int64_t* rowptr, int64_t 
                          const double* hdiag, double* eloc, double* etnum, double* logabs, int8_t* sign,
                          double* fsq, hipStream_t st) {
   if (n1 <= n0) return hipSuccess;
-  hipLaunchKernelGGL(k_reduce, dim3(grid_for(n1 - n0, 4)), dim3(256), 0, st, n0, n1, rowptr, row_base, coef,
-                     lphi, sphi, lf, sf, hdiag, eloc, etnum, logabs, sign, fsq);
+  if (lf && sf)
+    hipLaunchKernelGGL(k_reduce<true>, dim3(grid_for(n1 - n0, 4)), dim3(256), 0, st, n0, n1, rowptr, row_base,
+                       coef, lphi, sphi, lf, sf, hdiag, eloc, etnum, logabs, sign, fsq);
+  else
+    hipLaunchKernelGGL(k_reduce<false>, dim3(grid_for(n1 - n0, 4)), dim3(256), 0, st, n0, n1, rowptr, row_base,
+                       coef, lphi, sphi, lf, sf, hdiag, eloc, etnum, logabs, sign, fsq);
   return hipGetLastError();
 }
 

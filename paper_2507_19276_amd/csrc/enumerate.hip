@@ -499,7 +499,7 @@ __global__ __launch_bounds__(256) void k_fill(HamDev H, EnumGeom G, const uint64
         rows.m[2 * at + 1] = e.mhi;
         rows.coef[at] = e.H;
         rows.owner[at] = int32_t(n);
-        rows.rank[at] = int64_t(r);
+        if (rows.rank) rows.rank[at] = int64_t(r);
         if (rows.t0) rows.t0[at] = uint8_t(first_changed_site(e.mlo ^ lo, e.mhi ^ hi));
       }
       pos += __popcll(mask);
@@ -511,7 +511,7 @@ __global__ __launch_bounds__(256) void k_fill(HamDev H, EnumGeom G, const uint64
       rows.m[2 * r0 + 1] = hi;
       rows.coef[r0] = 0.0;
       rows.owner[r0] = int32_t(n);
-      rows.rank[r0] = -1;
+      if (rows.rank) rows.rank[r0] = -1;
       if (rows.t0) rows.t0[r0] = uint8_t(H.K);
     }
     const int64_t u = Un[n];
@@ -522,7 +522,7 @@ __global__ __launch_bounds__(256) void k_fill(HamDev H, EnumGeom G, const uint64
       rows.m[2 * at + 1] = um[2 * (n * n_eps + t) + 1];
       rows.coef[at] = ucoef[n * n_eps + t];
       rows.owner[at] = int32_t(n);
-      rows.rank[at] = urank[n * n_eps + t];
+      if (rows.rank) rows.rank[at] = urank[n * n_eps + t];
       if (rows.t0)
         rows.t0[at] = uint8_t(first_changed_site(um[2 * (n * n_eps + t)] ^ lo, um[2 * (n * n_eps + t) + 1] ^ hi));
     }
@@ -530,24 +530,40 @@ __global__ __launch_bounds__(256) void k_fill(HamDev H, EnumGeom G, const uint64
 }
 
 // H_nn = e_core + sum_P h_PP + 1/2 sum_{P,Q occ} <PQ||PQ>, one thread per
-// sample, ascending spin orbitals (the order of the plain definition)
+// sample, over the occupied spin orbitals in ascending order (the order of the
+// plain definition); <PQ||PQ> = (pp|qq) - delta_{sigma_P sigma_Q} (pq|qp) from
+// the K x K tables of those entries
+__device__ inline int next_set(uint64_t& lo, uint64_t& hi) {
+  int P;
+  if (lo) {
+    P = __ffsll((unsigned long long)lo) - 1;
+    lo &= lo - 1;
+  } else {
+    P = 64 + __ffsll((unsigned long long)hi) - 1;
+    hi &= hi - 1;
+  }
+  return P;
+}
+
 __global__ void k_diag(HamDev H, const uint64_t* samples, int64_t N, double* hdiag) {
   const int64_t n = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (n >= N) return;
   const uint64_t lo = samples[2 * n], hi = samples[2 * n + 1];
-  const int K = H.K, K2 = 2 * K;
+  const int K = H.K;
+  const double* J = H.jk;
+  const double* X = H.jk + size_t(K) * K;
   double d1 = 0.0;
-  for (int P = 0; P < K2; ++P)
-    if (bit_at(lo, hi, P)) d1 += H.h[(P >> 1) * K + (P >> 1)];
+  for (uint64_t a = lo, b = hi; a | b;) {
+    const int p = next_set(a, b) >> 1;
+    d1 += H.h[p * K + p];
+  }
   double d2 = 0.0;
-  for (int P = 0; P < K2; ++P) {
-    if (!bit_at(lo, hi, P)) continue;
-    const int p = P >> 1;
-    for (int Q = 0; Q < K2; ++Q) {
-      if (!bit_at(lo, hi, Q)) continue;
-      const int q = Q >> 1;
-      const double g1 = H.eri[eidx(K, p, p, q, q)];
-      const double g2 = ((P & 1) == (Q & 1)) ? H.eri[eidx(K, p, q, q, p)] : 0.0;
+  for (uint64_t a = lo, b = hi; a | b;) {
+    const int P = next_set(a, b), p = P >> 1;
+    for (uint64_t c = lo, d = hi; c | d;) {
+      const int Q = next_set(c, d), q = Q >> 1;
+      const double g1 = J[p * K + q];
+      const double g2 = ((P & 1) == (Q & 1)) ? X[p * K + q] : 0.0;
       d2 += (g1 - g2);
     }
   }
@@ -637,7 +653,7 @@ hipError_t launch_fill(const HamDev& H, const EnumGeom& G, const uint64_t* sampl
 hipError_t launch_diag(const HamDev& H, const uint64_t* samples, int64_t N, double* hdiag,
                        hipStream_t st) {
   if (N <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_diag, dim3(grid_for(N, 128)), dim3(128), 0, st, H, samples, N, hdiag);
+  hipLaunchKernelGGL(k_diag, dim3(grid_for(N, 64)), dim3(64), 0, st, H, samples, N, hdiag);
   return hipGetLastError();
 }
 

@@ -164,10 +164,12 @@ struct nqs_instance {
   double ecore = 0;
   double* d_h = nullptr;
   double* d_eri = nullptr;
+  double* d_jk = nullptr;
   HamDev H{};
   ~nqs_instance() {
     if (d_h) (void)hipFree(d_h);
     if (d_eri) (void)hipFree(d_eri);
+    if (d_jk) (void)hipFree(d_jk);
   }
 };
 
@@ -539,8 +541,15 @@ nqs_status nqs_instance_create(nqs_ctx* ctx, int K, int n_alpha, int n_beta, con
   nqs_status st;
   if ((st = upload(&inst->d_h, hs)) != NQS_OK) return st;
   if ((st = upload(&inst->d_eri, canon)) != NQS_OK) return st;
+  std::vector<double> jk(size_t(2) * K * K);
+  for (int p = 0; p < K; ++p)
+    for (int q = 0; q < K; ++q) {
+      jk[size_t(p) * K + q] = canon[((size_t(p) * K + p) * K + q) * K + q];
+      jk[size_t(K) * K + size_t(p) * K + q] = canon[((size_t(p) * K + q) * K + q) * K + p];
+    }
+  if ((st = upload(&inst->d_jk, jk)) != NQS_OK) return st;
   HamDev& H = inst->H;
-  H.h = inst->d_h; H.eri = inst->d_eri; H.ecore = e_core;
+  H.h = inst->d_h; H.eri = inst->d_eri; H.jk = inst->d_jk; H.ecore = e_core;
   H.K = K; H.na = n_alpha; H.nb = n_beta; H.va = K - n_alpha; H.vb = K - n_beta;
   const int64_t nsa = int64_t(n_alpha) * H.va, nsb = int64_t(n_beta) * H.vb;
   const int64_t daa = choose2(n_alpha) * choose2(H.va), dbb = choose2(n_beta) * choose2(H.vb);
@@ -861,12 +870,13 @@ nqs_status count_and_draw(Scratch& S, const nqs_instance* inst, const uint64_t* 
   return NQS_OK;
 }
 
-nqs_status alloc_rows(Scratch& S, Pipeline& P, int64_t cap) {
+// rank: only for inspection (nqs_rows); the local energy does not need it
+nqs_status alloc_rows(Scratch& S, Pipeline& P, int64_t cap, bool with_rank) {
   P.rows_cap = cap;
   P.rows.m = S.get<uint64_t>(size_t(cap) * 2);
   P.rows.coef = S.get<double>(cap);
   P.rows.owner = S.get<int32_t>(cap);
-  P.rows.rank = S.get<int64_t>(cap);
+  P.rows.rank = with_rank ? S.get<int64_t>(cap) : nullptr;
   if (S.oom) return fail(NQS_ENOMEM, "row workspace allocation failed (%lld rows)", (long long)cap);
   return NQS_OK;
 }
@@ -1036,11 +1046,11 @@ nqs_status nqs_eloc(nqs_ctx* ctx, const nqs_instance* inst, const nqs_ansatz* an
   auto passes = plan_passes(P.rowptr_host, cap);
   int64_t cap_used = 0;
   for (auto& pr : passes) cap_used = std::max(cap_used, P.rowptr_host[pr.second] - P.rowptr_host[pr.first]);
-  if ((s = alloc_rows(S, P, cap_used)) != NQS_OK) return s;
+  if ((s = alloc_rows(S, P, cap_used, false)) != NQS_OK) return s;
   double* lphi = S.get<double>(cap_used);
   int8_t* sphi = S.get<int8_t>(cap_used);
-  double* lf = S.get<double>(cap_used);
-  int8_t* sf = S.get<int8_t>(cap_used);
+  double* lf = ans->nh ? S.get<double>(cap_used) : nullptr;
+  int8_t* sf = ans->nh ? S.get<int8_t>(cap_used) : nullptr;
   double* theta = ans->nh ? S.get<double>(size_t(N) * ans->nh) : nullptr;
   double* el = eloc ? eloc : S.get<double>(N);
   double* et = etnum ? etnum : S.get<double>(N);
@@ -1125,13 +1135,9 @@ nqs_status nqs_eloc(nqs_ctx* ctx, const nqs_instance* inst, const nqs_ansatz* an
       psi_flops += double(Rp) * tail_flops[0];
     }
     if (timing) HIPCHK(hipEventRecord(pe[2], stream));
-    if (ans->nh) {
+    if (ans->nh)
       HIPCHK(launch_corr_rows(ans->corr(), P.rows.m, P.rows.owner, samples, theta, Rp, opts->precision, lf, sf,
                               stream));
-    } else {
-      HIPCHK(hipMemsetAsync(lf, 0, sizeof(double) * Rp, stream));
-      HIPCHK(hipMemsetAsync(sf, 1, sizeof(int8_t) * Rp, stream));
-    }
     HIPCHK(launch_reduce(n0, n1, P.rowptr, P.rowptr_host[n0], P.rows.coef, lphi, sphi, lf, sf, P.hdiag, el, et,
                          logabs, sign, f2, stream));
     if (timing) {
@@ -1194,7 +1200,7 @@ nqs_status nqs_rows(nqs_ctx* ctx, const nqs_instance* inst, const uint64_t* samp
   if ((s = count_and_draw(S, inst, samples, N, *opts, P, stream, nullptr)) != NQS_OK) return s;
   const int64_t R = P.R, w = std::min(R, cap);
   if (w > 0) {
-    if ((s = alloc_rows(S, P, R)) != NQS_OK) return s;
+    if ((s = alloc_rows(S, P, R, true)) != NQS_OK) return s;
     if ((s = fill_range(inst, samples, 0, N, *opts, P, stream)) != NQS_OK) return s;
   }
   if (row_ptr) HIPCHK(hipMemcpyAsync(row_ptr, P.rowptr, sizeof(int64_t) * (N + 1), hipMemcpyDeviceToDevice, stream));
@@ -1224,10 +1230,11 @@ nqs_status nqs_eloc_workspace_bytes(const nqs_instance* inst, const nqs_ansatz* 
   b += 3 * al(size_t(N) * 8) + al(size_t(N + 1) * 8);
   b += al(size_t(N) * ne * 4) + al(size_t(N) * ne * 8) + al(size_t(N) * ne * 16);
   b += al(size_t(N) * 8);
-  // rows of the largest pass: m(16) coef(8) owner(4) rank(8) lphi(8) sphi(1) lf(8) sf(1)
+  // rows of the largest pass: m(16) coef(8) owner(4) lphi(8) sphi(1), with a correlator lf(8) sf(1)
   const int64_t rows = opts->max_rows_per_pass > 0 ? pass_rows_bound(inst->H, *opts, 0) : n_rows;
-  b += al(size_t(rows) * 16) + al(size_t(rows) * 8) + al(size_t(rows) * 4) + al(size_t(rows) * 8);
-  b += al(size_t(rows) * 8) + al(size_t(rows)) + al(size_t(rows) * 8) + al(size_t(rows));
+  b += al(size_t(rows) * 16) + al(size_t(rows) * 8) + al(size_t(rows) * 4);
+  b += al(size_t(rows) * 8) + al(size_t(rows));
+  if (ans->nh) b += al(size_t(rows) * 8) + al(size_t(rows));
   if (ans->nh) b += al(size_t(N) * ans->nh * 8);
   if (resumes(*opts)) {
     // samples' carried and log-product states, the pass's row order
