@@ -148,7 +148,9 @@ hipError_t launch_connected(const HamDev& H, const uint64_t* samples, int64_t N,
 // X.perm[p]; positions are sorted by the row's first changed site X.t0[p],
 // and each wavefront resumes at the site of its first position from the state
 // that a STORE pass left for the row's sample X.owner[row].
-enum { PSI_PLAIN = 0, PSI_STORE = 1, PSI_SEED = 2 };
+// PSI_NODE: SEED for the units of a node list (resumed from their samples)
+// plus the compact store of nodes.hip.
+enum { PSI_PLAIN = 0, PSI_STORE = 1, PSI_SEED = 2, PSI_NODE = 3 };
 template <typename T>
 struct PsiStates {
   T* hs = nullptr;               // [K][ns][chip] carried states
@@ -159,7 +161,35 @@ struct PsiStates {
   const int32_t* perm = nullptr; // SEED: [R] row of each position
   const uint8_t* t0 = nullptr;   // SEED: [R] first changed site of each position (ascending)
   const int32_t* owner = nullptr;// SEED: [rows] sample of each row
+  // one level of shared prefixes (nodes.hip), compact per node: entry
+  // noff[u] + k holds the carried state after site nc1[u] + k (k < ne1 - nc1)
+  // and the log-product state before site nc1[u] + k (k <= ne1 - nc1)
+  T* nhs = nullptr;              // [entries][chip]
+  T* npm = nullptr;              // [entries]
+  int32_t* npe = nullptr;        // [entries]
+  int8_t* npg = nullptr;         // [entries]
+  const int64_t* noff = nullptr; // [nodes]
+  const uint8_t* nc1 = nullptr;  // [nodes] the node's changed site
+  const uint8_t* ne1 = nullptr;  // [nodes] the last site its rows resume at
+  const int32_t* unode = nullptr;// SEED rows: [rows] node the row resumes from (-1: its sample)
 };
+// node list written by nodes.hip
+struct NodeList {
+  uint64_t* m;                   // [nodes][2] ONV: the sample with one site changed
+  int32_t* owner;                // [nodes] sample
+  uint8_t* c1;                   // [nodes] changed site
+  uint8_t* e1;                   // [nodes] largest resume site of its rows
+  int64_t* off;                  // [nodes] first storage entry
+};
+hipError_t launch_node_count(const uint64_t* m, const uint8_t* t0, const uint64_t* samples, const int64_t* rowptr,
+                             int64_t n0, int64_t n1, int64_t row_base, int K, int32_t* ncnt, int64_t* nent,
+                             hipStream_t st);
+hipError_t launch_node_scan(int64_t ns, int64_t cap, int32_t* ncnt, int64_t* nent, int64_t* nbase, int64_t* ebase,
+                            int64_t* totals, hipStream_t st);
+hipError_t launch_node_assign(const uint64_t* m, const uint8_t* t0, const uint64_t* samples, const int64_t* rowptr,
+                              int64_t n0, int64_t n1, int64_t row_base, int K, const int64_t* nbase,
+                              const int64_t* ebase, const NodeList& nl, int32_t* row_node, uint8_t* row_site,
+                              hipStream_t st);
 hipError_t launch_psi_f64(const PsiParams<double>& P, const uint64_t* m, int64_t R, double* lphi,
                           int8_t* sphi, hipStream_t st, const PsiStates<double>& X = PsiStates<double>(),
                           int mode = PSI_PLAIN);

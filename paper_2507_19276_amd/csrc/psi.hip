@@ -39,7 +39,7 @@ template <typename T> constexpr int prefetch_ksteps(int CH) {
   return (CH / 4) < 64 / ((CH / 4) * int(sizeof(T) / 4)) ? (CH / 4) : 64 / ((CH / 4) * int(sizeof(T) / 4));
 }
 
-template <typename T, int CH, int NTL, bool FOLD, bool STORE, bool SEED>
+template <typename T, int CH, int NTL, bool FOLD, int STORE, bool SEED>
 __global__ __launch_bounds__(256) void k_psi_mt(PsiParams<T> P, const uint64_t* __restrict__ m, int64_t R,
                                                 double* __restrict__ lphi, int8_t* __restrict__ sphi, int wpb,
                                                 PsiStates<T> X) {
@@ -97,20 +97,45 @@ __global__ __launch_bounds__(256) void k_psi_mt(PsiParams<T> P, const uint64_t* 
     // carried states of the parents of sites >= i0 and the log-product state
     // before site i0, taken from the row's sample (rows agree with their
     // sample on every site below their first changed site >= i0)
+    // With a node level (X.unode), a row's node covers the sites from its
+    // changed site nc1 on: the node agrees with the row below the row's
+    // resume site, the sample below nc1.
     const int s0 = i0 - P.W + 1 > 0 ? i0 - P.W + 1 : 0;
+    int nd[NTL], nb[NTL];
+    int64_t no[NTL];
+#pragma unroll
+    for (int t = 0; t < NTL; ++t) {
+      nd[t] = X.unode ? X.unode[rowt[t]] : -1;
+      nb[t] = nd[t] >= 0 ? int(X.nc1[nd[t]]) : P.K + 1;
+      no[t] = nd[t] >= 0 ? X.noff[nd[t]] : 0;
+    }
     for (int s = s0; s < i0; ++s) {
       V* wr = ring + size_t(s % P.W) * SLOT;
 #pragma unroll
       for (int t = 0; t < NTL; ++t) {
-        const T* src = X.hs + (size_t(s) * X.ns + X.owner[rowt[t]]) * CH + 4 * g;
+        const T* src = s >= nb[t] ? X.nhs + size_t(no[t] + (s - nb[t])) * CH + 4 * g
+                                  : X.hs + (size_t(s) * X.ns + X.owner[rowt[t]]) * CH + 4 * g;
 #pragma unroll
         for (int tt = 0; tt < TPC; ++tt) wr[(t * TPC + tt) * 64] = *reinterpret_cast<const V*>(src + 16 * tt);
       }
     }
-    const size_t so = size_t(i0) * X.ns + X.owner[orow];
-    prod = X.pm[so];
-    pexp = X.pe[so];
-    sgn = X.pg[so];
+    int ond = nd[0], onb = nb[0];
+    int64_t ono = no[0];
+#pragma unroll
+    for (int t = 1; t < NTL; ++t)
+      if (t == own) { ond = nd[t]; onb = nb[t]; ono = no[t]; }
+    if (i0 >= onb) {
+      const size_t so = size_t(ono + (i0 - onb));
+      prod = X.npm[so];
+      pexp = X.npe[so];
+      sgn = X.npg[so];
+    } else {
+      const size_t so = size_t(i0) * X.ns + X.owner[orow];
+      prod = X.pm[so];
+      pexp = X.pe[so];
+      sgn = X.pg[so];
+    }
+    (void)ond;
     const uint64_t below = low_bits(2 * i0), belowh = low_bits(2 * i0 - 64);
     ca = __popcll(olo & below & 0x5555555555555555ull) + __popcll(ohi & belowh & 0x5555555555555555ull);
     cb = __popcll(olo & below & 0xAAAAAAAAAAAAAAAAull) + __popcll(ohi & belowh & 0xAAAAAAAAAAAAAAAAull);
@@ -134,15 +159,37 @@ __global__ __launch_bounds__(256) void k_psi_mt(PsiParams<T> P, const uint64_t* 
       vn[ot] = *reinterpret_cast<const V*>(P.v + (size_t(i) * 4 + ot / TPC) * CH + 16 * (ot % TPC) + 4 * g);
   };
   if (BPF) fetch_bias(i0 < P.K ? i0 : 0);
-  // STORE: the log-product state before each site and the carried state
-  // after it, for rows r < X.ns
+  // STORE 1: the log-product state before each site and the carried state
+  // after it, for rows r < X.ns; STORE 2 (node units): compact, for the sites
+  // nc1 .. ne1 of each unit
+  int sc1 = 0, se1 = -1;
+  int64_t soff = 0;
+  if (STORE == 2) {
+    sc1 = X.nc1[orow];
+    se1 = X.ne1[orow];
+    soff = X.noff[orow];
+  }
+  int tc1[NTL], te1[NTL];
+  int64_t toff[NTL];
+#pragma unroll
+  for (int t = 0; t < NTL; ++t) {
+    tc1[t] = STORE == 2 ? int(X.nc1[rowt[t]]) : 0;
+    te1[t] = STORE == 2 ? int(X.ne1[rowt[t]]) : -1;
+    toff[t] = STORE == 2 ? X.noff[rowt[t]] : 0;
+  }
   auto store_pre = [&](int i) {
     const bool writer = NTL == 4 || (NTL == 2 ? (g & 1) == 0 : g == 0);
-    if (STORE && X.pm && writer && olive && orow < X.ns) {
+    if (STORE == 1 && X.pm && writer && olive && orow < X.ns) {
       const size_t so = size_t(i) * X.ns + orow;
       X.pm[so] = prod;
       X.pe[so] = pexp;
       X.pg[so] = int8_t(sgn);
+    }
+    if (STORE == 2 && writer && olive && i >= sc1 && i <= se1) {
+      const size_t so = size_t(soff + (i - sc1));
+      X.npm[so] = prod;
+      X.npe[so] = pexp;
+      X.npg[so] = int8_t(sgn);
     }
   };
   for (int i = i0; i < P.K; ++i) {
@@ -234,12 +281,14 @@ __global__ __launch_bounds__(256) void k_psi_mt(PsiParams<T> P, const uint64_t* 
         d = tfma(ww.w, sel.w, d);
         dp[t] = d;
         wr[(t * TPC + tt) * 64] = sel;
-        if (STORE) {
+        if (STORE == 1) {
           // positions past R (up to the stride X.ns) get the last row's state:
           // the adjoint reads padded rows
           const int64_t r = base + 16 * t + j;
           if (r < X.ns) *reinterpret_cast<V*>(X.hs + (size_t(i) * X.ns + r) * CH + 16 * tt + 4 * g) = sel;
         }
+        if (STORE == 2 && base + 16 * t + j < R && i >= tc1[t] && i < te1[t])
+          *reinterpret_cast<V*>(X.nhs + size_t(toff[t] + (i - tc1[t])) * CH + 16 * tt + 4 * g) = sel;
       }
     }
     wslot = wslot + 1 == P.W ? 0 : wslot + 1;
@@ -280,7 +329,7 @@ template <typename T> constexpr int ntiles(int CH) {
   return sizeof(T) == 4 ? (CH <= 16 ? NQS_NTL_F32_16 : (CH <= 32 ? 2 : 1)) : (CH <= 16 ? 2 : 1);
 }
 
-template <typename T, int CH, bool FOLD, bool STORE, bool SEED>
+template <typename T, int CH, bool FOLD, int STORE, bool SEED>
 hipError_t run_psi_mt(const PsiParams<T>& P, const uint64_t* m, int64_t R, double* lphi, int8_t* sphi,
                       hipStream_t st, const PsiStates<T>& X) {
   if (R <= 0) return hipSuccess;
@@ -301,14 +350,17 @@ hipError_t run_psi_ch(const PsiParams<T>& P, const uint64_t* m, int64_t R, doubl
                       hipStream_t st, const PsiStates<T>& X, int mode) {
   switch (mode) {
     case PSI_PLAIN:
-      if (P.folded) return run_psi_mt<T, CH, true, false, false>(P, m, R, lphi, sphi, st, X);
-      return run_psi_mt<T, CH, false, false, false>(P, m, R, lphi, sphi, st, X);
+      if (P.folded) return run_psi_mt<T, CH, true, 0, false>(P, m, R, lphi, sphi, st, X);
+      return run_psi_mt<T, CH, false, 0, false>(P, m, R, lphi, sphi, st, X);
     case PSI_STORE:
-      if (P.folded) return run_psi_mt<T, CH, true, true, false>(P, m, R, lphi, sphi, st, X);
-      return run_psi_mt<T, CH, false, true, false>(P, m, R, lphi, sphi, st, X);
+      if (P.folded) return run_psi_mt<T, CH, true, 1, false>(P, m, R, lphi, sphi, st, X);
+      return run_psi_mt<T, CH, false, 1, false>(P, m, R, lphi, sphi, st, X);
     case PSI_SEED:
-      if (P.folded) return run_psi_mt<T, CH, true, false, true>(P, m, R, lphi, sphi, st, X);
-      return run_psi_mt<T, CH, false, false, true>(P, m, R, lphi, sphi, st, X);
+      if (P.folded) return run_psi_mt<T, CH, true, 0, true>(P, m, R, lphi, sphi, st, X);
+      return run_psi_mt<T, CH, false, 0, true>(P, m, R, lphi, sphi, st, X);
+    case PSI_NODE:
+      if (P.folded) return run_psi_mt<T, CH, true, 2, true>(P, m, R, lphi, sphi, st, X);
+      return run_psi_mt<T, CH, false, 2, true>(P, m, R, lphi, sphi, st, X);
     default:
       return hipErrorInvalidValue;
   }

@@ -729,6 +729,15 @@ struct Resume {
   int32_t* cnt = nullptr;   // [order blocks][K+1]
   int64_t* tot = nullptr;   // [K+1]
   const int32_t* owner = nullptr;
+  // one node level (FP64/FP32): node storage and the rows' nodes
+  void* nhs = nullptr;      // [entries][chip] T
+  void* npm = nullptr;      // [entries] T
+  int32_t* npe = nullptr;
+  int8_t* npg = nullptr;
+  const int64_t* noff = nullptr;
+  const uint8_t* nc1 = nullptr;
+  const uint8_t* ne1 = nullptr;
+  const int32_t* unode = nullptr;
 };
 
 template <typename T>
@@ -742,6 +751,14 @@ PsiStates<T> states(const Resume& r) {
   X.perm = r.perm;
   X.t0 = r.t0;
   X.owner = r.owner;
+  X.nhs = static_cast<T*>(r.nhs);
+  X.npm = static_cast<T*>(r.npm);
+  X.npe = r.npe;
+  X.npg = r.npg;
+  X.noff = r.noff;
+  X.nc1 = r.nc1;
+  X.ne1 = r.ne1;
+  X.unode = r.unode;
   return X;
 }
 
@@ -813,6 +830,19 @@ EnumGeom make_geom(int64_t n_conn, int64_t N) {
   G.S = int(S);
   G.cps = (std::max(G.nchunks, 1) + G.S - 1) / G.S;
   return G;
+}
+
+// node storage entries of a pass (one entry: a carried state and a log-product
+// state): one per 8 rows, at least one sample's worth (at most 4K nodes of at
+// most K+1 entries each)
+int64_t node_entry_cap(int64_t pass_rows, int K) {
+  return std::max<int64_t>(pass_rows / 8, int64_t(4) * K * (K + 1));
+}
+
+int64_t max_samples_per_pass(const std::vector<std::pair<int64_t, int64_t>>& passes) {
+  int64_t m = 1;
+  for (auto& p : passes) m = std::max(m, p.second - p.first);
+  return m;
 }
 
 // largest number of rows any pass can hold: a pass takes whole samples, so it
@@ -1077,6 +1107,39 @@ nqs_status nqs_eloc(nqs_ctx* ctx, const nqs_instance* inst, const nqs_ansatz* an
     lphi_s = S.get<double>(N);
     sphi_s = S.get<int8_t>(N);
   }
+  // one level of shared prefixes (FP64/FP32): node list, compact storage
+  const bool nodes = resume && opts->precision != NQS_BF16;
+  const int64_t max_pass_samples = max_samples_per_pass(passes);
+  const int64_t ecap = node_entry_cap(cap_used, K);
+  NodeList nl{};
+  int32_t *ncnt = nullptr, *row_node = nullptr, *nperm = nullptr;
+  int64_t *nent = nullptr, *nbase = nullptr, *ebase = nullptr, *ntot = nullptr;
+  uint8_t *row_site = nullptr, *nt0s = nullptr;
+  double* lphi_n = nullptr;
+  int8_t* sphi_n = nullptr;
+  if (nodes) {
+    const size_t esz = state_bytes(opts->precision);
+    ncnt = S.get<int32_t>(max_pass_samples);
+    nent = S.get<int64_t>(max_pass_samples);
+    nbase = S.get<int64_t>(max_pass_samples);
+    ebase = S.get<int64_t>(max_pass_samples);
+    ntot = S.get<int64_t>(2);
+    nl.m = S.get<uint64_t>(size_t(ecap) * 2);
+    nl.owner = S.get<int32_t>(ecap);
+    nl.c1 = S.get<uint8_t>(ecap);
+    nl.e1 = S.get<uint8_t>(ecap);
+    nl.off = S.get<int64_t>(ecap);
+    nperm = S.get<int32_t>(ecap);
+    nt0s = S.get<uint8_t>(ecap);
+    lphi_n = S.get<double>(ecap);
+    sphi_n = S.get<int8_t>(ecap);
+    rs.nhs = S.get<unsigned char>(size_t(ecap) * ans->chip * esz);
+    rs.npm = S.get<unsigned char>(size_t(ecap) * esz);
+    rs.npe = S.get<int32_t>(ecap);
+    rs.npg = S.get<int8_t>(ecap);
+    row_node = S.get<int32_t>(cap_used);
+    row_site = S.get<uint8_t>(cap_used);
+  }
   if (S.oom) return fail(NQS_ENOMEM, "workspace allocation failed");
   if (ans->nh) HIPCHK(launch_corr_theta(ans->corr(), samples, N, theta, stream));
   float ms_rows = 0, ms_amp = 0, ms_red = 0, ms_psi = 0;
@@ -1113,7 +1176,46 @@ nqs_status nqs_eloc(nqs_ctx* ctx, const nqs_instance* inst, const nqs_ansatz* an
     if ((s = fill_range(inst, samples, n0, n1, *opts, P, stream)) != NQS_OK) return s;
     if (timing) HIPCHK(hipEventRecord(pe[1], stream));
     if (resume) {
-      HIPCHK(launch_order_t0(P.rows.t0, Rp, K, rs.cnt, rs.tot, rs.perm, rs.t0, stream));
+      const uint8_t* key = P.rows.t0;
+      rs.unode = nullptr;
+      if (nodes) {
+        // nodes of this pass: count, place (host learns the totals), assign
+        const int64_t ns = n1 - n0, row_base = P.rowptr_host[n0];
+        HIPCHK(launch_node_count(P.rows.m, P.rows.t0, samples, P.rowptr, n0, n1, row_base, K, ncnt, nent, stream));
+        HIPCHK(launch_node_scan(ns, ecap, ncnt, nent, nbase, ebase, ntot, stream));
+        int64_t tot2[2] = {0, 0};
+        HIPCHK(hipMemcpyAsync(tot2, ntot, sizeof tot2, hipMemcpyDeviceToHost, stream));
+        HIPCHK(hipStreamSynchronize(stream));
+        HIPCHK(launch_node_assign(P.rows.m, P.rows.t0, samples, P.rowptr, n0, n1, row_base, K, nbase, ebase, nl,
+                                  row_node, row_site, stream));
+        const int64_t nn = tot2[0];
+        if (nn > 0) {
+          // the node pass: resumed from the samples at the changed site, stores compactly
+          HIPCHK(launch_order_t0(nl.c1, nn, K, rs.cnt, rs.tot, nperm, nt0s, stream));
+          Resume rn = rs;
+          rn.perm = nperm;
+          rn.t0 = nt0s;
+          rn.owner = nl.owner;
+          rn.noff = nl.off;
+          rn.nc1 = nl.c1;
+          rn.ne1 = nl.e1;
+          rn.unode = nullptr;
+          if ((s = run_amplitudes(ans, opts->precision, nl.m, nn, lphi_n, sphi_n, stream, &rn, PSI_NODE)) != NQS_OK)
+            return s;
+          if (stats) {
+            std::vector<int64_t> tot(K + 1);
+            HIPCHK(hipMemcpyAsync(tot.data(), rs.tot, sizeof(int64_t) * (K + 1), hipMemcpyDeviceToHost, stream));
+            HIPCHK(hipStreamSynchronize(stream));
+            for (int k = 0; k <= K; ++k) site_rows += tot[k] * (K - k);
+          }
+        }
+        rs.noff = nl.off;
+        rs.nc1 = nl.c1;
+        rs.ne1 = nl.e1;
+        rs.unode = row_node;
+        key = row_site;
+      }
+      HIPCHK(launch_order_t0(key, Rp, K, rs.cnt, rs.tot, rs.perm, rs.t0, stream));
       if (timing) HIPCHK(hipEventRecord(kq[0], stream));
       if ((s = run_amplitudes(ans, opts->precision, P.rows.m, Rp, lphi, sphi, stream, &rs, PSI_SEED)) != NQS_OK)
         return s;
@@ -1245,6 +1347,16 @@ nqs_status nqs_eloc_workspace_bytes(const nqs_instance* inst, const nqs_ansatz* 
     b += al(size_t(K + 1) * N) + al(size_t(rows) * 4) + 2 * al(size_t(rows));
     b += al(size_t(order_blocks(rows)) * (K + 1) * 4) + al(size_t(K + 1) * 8);
     b += al(size_t(N) * 8) + al(size_t(N));
+    if (opts->precision != NQS_BF16) {
+      // node level: per-sample counts, node list, node order, storage, rows' nodes
+      const int64_t ecap = node_entry_cap(rows, K);
+      const size_t esz = state_bytes(opts->precision);
+      b += al(size_t(N) * 4) + 3 * al(size_t(N) * 8) + al(16);
+      b += al(size_t(ecap) * 16) + al(size_t(ecap) * 4) + 2 * al(size_t(ecap)) + al(size_t(ecap) * 8);
+      b += al(size_t(ecap) * 4) + al(size_t(ecap)) + al(size_t(ecap) * 8) + al(size_t(ecap));
+      b += al(size_t(ecap) * ans->chip * esz) + al(size_t(ecap) * esz) + al(size_t(ecap) * 4) + al(size_t(ecap));
+      b += al(size_t(rows) * 4) + al(size_t(rows));
+    }
   }
   b += 3 * al(size_t(N) * 8) + al(64);     // outputs the caller did not provide, batch sums
   b += al(4);                              // sample validation flag

@@ -1,10 +1,10 @@
-"""Resumed amplitude rows: every row (FP64, FP32, BF16) starts at its first changed
-site from its sample's stored state instead of site 0.  The autoregressive
-conditionals below that site see only occupations the row shares with its
-sample, so the result must be bit-identical to evaluating every row from
-site 0, on every workload, with and without row passes; and the executed
-site count must equal the sum over rows of (K - first changed site) plus the
-samples' own pass."""
+"""Resumed amplitude rows.  BF16 rows start at their first changed site from
+their sample's stored state; FP64/FP32 rows start at their second changed
+site from a node shared by the rows with the same first change (itself
+resumed from the sample).  The autoregressive conditionals at a site see only
+the occupations below it, so every result must be bit-identical to evaluating
+every row from site 0, on every workload, with and without row passes; and
+the executed site count must match the count from the row list."""
 import numpy as np
 import pytest
 
@@ -80,21 +80,47 @@ def test_resume_with_passes(nqs, ctx, prec):
         assert np.array_equal(full[k].cpu().numpy(), many[k].cpu().numpy(), equal_nan=True), (prec, k)
 
 
-def test_site_count_matches_first_changed_sites(nqs, ctx):
-    """n_site_rows = N K (samples' pass) + sum over rows of (K - t0), with t0
-    computed here from the row list of the same call."""
+def changed_sites(m, s, K):
+    """Sites (ascending) where row m differs from its sample s."""
+    out = []
+    for k in range(len(m)):
+        x = (int(m[k, 0]) ^ int(s[0])) | ((int(m[k, 1]) ^ int(s[1])) << 64)
+        out.append(sorted({b // 2 for b in range(128) if (x >> b) & 1}))
+    return out
+
+
+def site_state(w0, w1, i):
+    v = (int(w0) | (int(w1) << 64)) >> (2 * i)
+    return v & 3
+
+
+def test_site_count_matches_changed_sites(nqs, ctx):
+    """Executed site evaluations.  FP32/FP64: the samples' pass (N K), one
+    node per (sample, first changed site, state there) from that site on, and
+    every row from its second changed site on.  BF16 (no node level): N K plus
+    every row from its first changed site.  Counted here from the row list of
+    the same call."""
     w, inst, ans = setup(nqs, ctx, "c2", 64)
     kw = dict(eps=w.eps, n_eps=w.n_eps, seed=w.seed, stream_id=7)
     r = nqs.rows(ctx, inst, w.samples, **kw)
     rp = r["row_ptr"].cpu().numpy()
     m = r["m"].cpu().numpy().view(np.uint64)
-    total = w.n_samples * w.K
+    K = w.K
+    two = one = w.n_samples * K
     for s in range(w.n_samples):
-        t0 = first_changed_sites(m[rp[s]:rp[s + 1]], w.samples[s], w.K)
-        assert t0[0] == w.K          # the sample's own row
-        total += int((w.K - t0).sum())
+        rows = m[rp[s]:rp[s + 1]]
+        ch = changed_sites(rows, w.samples[s], K)
+        assert ch[0] == []            # the sample's own row
+        nodes = set()
+        for k, c in enumerate(ch[1:], start=1):
+            one += K - c[0]
+            nodes.add((c[0], site_state(rows[k, 0], rows[k, 1], c[0])))
+            two += K - (c[1] if len(c) > 1 else K)
+        two += sum(K - c1 for c1, _ in nodes)
     _, st = nqs.eloc(ctx, inst, ans, w.samples, precision="f32", **kw)
-    assert st["n_site_rows"] == total
+    assert st["n_site_rows"] == two
+    _, st = nqs.eloc(ctx, inst, ans, w.samples, precision="bf16", **kw)
+    assert st["n_site_rows"] == one
 
 
 def test_resume_matches_oracle_f64(nqs, ctx):
