@@ -47,6 +47,28 @@ __device__ inline int first_changed_site(uint64_t xlo, uint64_t xhi) {
   return (64 + __ffsll((unsigned long long)xhi) - 1) >> 1;
 }
 
+// first changed site c1 of row m against its sample n, and the row's second
+// changed site c2 (K if none) with its local state at c1 packed as
+// c2 | state << 8
+__device__ inline void row_sites(uint64_t mlo, uint64_t mhi, uint64_t nlo, uint64_t nhi, int K, uint8_t* t0,
+                                 uint16_t* sec) {
+  uint64_t xl = mlo ^ nlo, xh = mhi ^ nhi;
+  const int c1 = first_changed_site(xl, xh);
+  *t0 = uint8_t(c1);
+  if (!sec) return;
+  const int P = 2 * c1;
+  int st;
+  if (P < 64) {
+    st = int((mlo >> P) & 3ull);
+    xl &= ~(3ull << P);
+  } else {
+    st = int((mhi >> (P - 64)) & 3ull);
+    xh &= ~(3ull << (P - 64));
+  }
+  const int c2 = (xl | xh) ? first_changed_site(xl, xh) : K;
+  *sec = uint16_t(c2 | (st << 8));
+}
+
 __device__ inline bool bit_at(uint64_t lo, uint64_t hi, int P) {
   return P < 64 ? ((lo >> P) & 1ull) : ((hi >> (P - 64)) & 1ull);
 }
@@ -500,7 +522,7 @@ __global__ __launch_bounds__(256) void k_fill(HamDev H, EnumGeom G, const uint64
         rows.coef[at] = e.H;
         rows.owner[at] = int32_t(n);
         if (rows.rank) rows.rank[at] = int64_t(r);
-        if (rows.t0) rows.t0[at] = uint8_t(first_changed_site(e.mlo ^ lo, e.mhi ^ hi));
+        if (rows.t0) row_sites(e.mlo, e.mhi, lo, hi, H.K, rows.t0 + at, rows.sec ? rows.sec + at : nullptr);
       }
       pos += __popcll(mask);
     }
@@ -513,6 +535,7 @@ __global__ __launch_bounds__(256) void k_fill(HamDev H, EnumGeom G, const uint64
       rows.owner[r0] = int32_t(n);
       if (rows.rank) rows.rank[r0] = -1;
       if (rows.t0) rows.t0[r0] = uint8_t(H.K);
+      if (rows.sec) rows.sec[r0] = uint16_t(H.K);
     }
     const int64_t u = Un[n];
     const int64_t d0 = r0 + 1 + Dn[n];
@@ -524,7 +547,8 @@ __global__ __launch_bounds__(256) void k_fill(HamDev H, EnumGeom G, const uint64
       rows.owner[at] = int32_t(n);
       if (rows.rank) rows.rank[at] = urank[n * n_eps + t];
       if (rows.t0)
-        rows.t0[at] = uint8_t(first_changed_site(um[2 * (n * n_eps + t)] ^ lo, um[2 * (n * n_eps + t) + 1] ^ hi));
+        row_sites(um[2 * (n * n_eps + t)], um[2 * (n * n_eps + t) + 1], lo, hi, H.K, rows.t0 + at,
+                  rows.sec ? rows.sec + at : nullptr);
     }
   }
 }

@@ -114,6 +114,7 @@ struct Rows {
   int32_t* owner;    // [R]
   int64_t* rank;     // [R]   (-1 for the sample's own row)
   uint8_t* t0;       // [R]   first site where m differs from its sample (K when equal); may be null
+  uint16_t* sec;     // [R]   second changed site | state of m at the first << 8; may be null
 };
 
 // ---- launchers (enumerate.hip) ----------------------------------------
@@ -181,15 +182,14 @@ struct NodeList {
   uint8_t* e1;                   // [nodes] largest resume site of its rows
   int64_t* off;                  // [nodes] first storage entry
 };
-hipError_t launch_node_count(const uint64_t* m, const uint8_t* t0, const uint64_t* samples, const int64_t* rowptr,
-                             int64_t n0, int64_t n1, int64_t row_base, int K, int32_t* ncnt, int64_t* nent,
-                             hipStream_t st);
+hipError_t launch_node_count(const uint8_t* t0, const uint16_t* sec, const int64_t* rowptr, int64_t n0, int64_t n1,
+                             int64_t row_base, int K, int32_t* ncnt, int64_t* nent, hipStream_t st);
 hipError_t launch_node_scan(int64_t ns, int64_t cap, int32_t* ncnt, int64_t* nent, int64_t* nbase, int64_t* ebase,
                             int64_t* totals, hipStream_t st);
-hipError_t launch_node_assign(const uint64_t* m, const uint8_t* t0, const uint64_t* samples, const int64_t* rowptr,
-                              int64_t n0, int64_t n1, int64_t row_base, int K, const int64_t* nbase,
-                              const int64_t* ebase, const NodeList& nl, int32_t* row_node, uint8_t* row_site,
-                              hipStream_t st);
+hipError_t launch_node_assign(const uint8_t* t0, const uint16_t* sec, const uint64_t* samples,
+                              const int64_t* rowptr, int64_t n0, int64_t n1, int64_t row_base, int K,
+                              const int64_t* nbase, const int64_t* ebase, const NodeList& nl, int32_t* row_node,
+                              uint8_t* row_site, hipStream_t st);
 hipError_t launch_psi_f64(const PsiParams<double>& P, const uint64_t* m, int64_t R, double* lphi,
                           int8_t* sphi, hipStream_t st, const PsiStates<double>& X = PsiStates<double>(),
                           int mode = PSI_PLAIN);

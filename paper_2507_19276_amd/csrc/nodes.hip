@@ -23,54 +23,27 @@
 namespace nqs {
 namespace {
 
-__device__ inline int site_of(uint64_t lo, uint64_t hi, int i) {
-  const int P = 2 * i;
-  return int((P < 64 ? (lo >> P) : (hi >> (P - 64))) & 3ull);
-}
-
-__device__ inline int first_set_site(uint64_t xlo, uint64_t xhi, int K) {
-  if (xlo) return (__ffsll((unsigned long long)xlo) - 1) >> 1;
-  if (xhi) return (64 + __ffsll((unsigned long long)xhi) - 1) >> 1;
-  return K;
-}
-
-// the row's key (c1 * 4 + state at c1) and second changed site; key < 0 for
-// the sample's own row
-__device__ inline void row_key(uint64_t mlo, uint64_t mhi, uint64_t nlo, uint64_t nhi, int c1, int K, int& key,
-                               int& c2) {
-  if (c1 >= K) {
-    key = -1;
-    c2 = K;
-    return;
-  }
-  key = c1 * 4 + site_of(mlo, mhi, c1);
-  uint64_t xl = mlo ^ nlo, xh = mhi ^ nhi;
-  const int P = 2 * c1;
-  if (P < 64) xl &= ~(3ull << P); else xh &= ~(3ull << (P - 64));
-  c2 = first_set_site(xl, xh, K);
-}
-
-// table of one sample: e[key] = largest c2 + 1 (0 = key absent)
-__device__ void build_table(const uint64_t* m, const uint8_t* t0, const uint64_t* samples, int64_t n, int64_t r0,
-                            int64_t r1, int K, int* e) {
+// table of one sample: e[key] = largest c2 + 1 (0 = key absent), key =
+// c1 * 4 + state at c1, from the bytes the fill kernel wrote per row (the
+// sample's own row has c1 = K)
+__device__ void build_table(const uint8_t* t0, const uint16_t* sec, int64_t r0, int64_t r1, int K, int* e) {
   for (int k = threadIdx.x; k < 4 * K; k += blockDim.x) e[k] = 0;
   __syncthreads();
-  const uint64_t nlo = samples[2 * n], nhi = samples[2 * n + 1];
   for (int64_t r = r0 + threadIdx.x; r < r1; r += blockDim.x) {
-    int key, c2;
-    row_key(m[2 * r], m[2 * r + 1], nlo, nhi, int(t0[r]), K, key, c2);
-    if (key >= 0) atomicMax(&e[key], c2 + 1);
+    const int c1 = t0[r];
+    if (c1 >= K) continue;
+    const int v = sec[r];
+    atomicMax(&e[c1 * 4 + (v >> 8)], (v & 0xFF) + 1);
   }
   __syncthreads();
 }
 
-__global__ __launch_bounds__(256) void k_node_count(const uint64_t* __restrict__ m, const uint8_t* __restrict__ t0,
-                                                    const uint64_t* __restrict__ samples, const int64_t* rowptr,
-                                                    int64_t n0, int64_t row_base, int K, int32_t* ncnt,
-                                                    int64_t* nent) {
+__global__ __launch_bounds__(256) void k_node_count(const uint8_t* __restrict__ t0, const uint16_t* __restrict__ sec,
+                                                    const int64_t* rowptr, int64_t n0, int64_t row_base, int K,
+                                                    int32_t* ncnt, int64_t* nent) {
   __shared__ int e[256];
   const int64_t n = n0 + blockIdx.x;
-  build_table(m, t0, samples, n, rowptr[n] - row_base, rowptr[n + 1] - row_base, K, e);
+  build_table(t0, sec, rowptr[n] - row_base, rowptr[n + 1] - row_base, K, e);
   if (threadIdx.x == 0) {
     int cnt = 0;
     int64_t ent = 0;
@@ -131,7 +104,7 @@ __global__ __launch_bounds__(1024) void k_node_scan(int64_t ns, int64_t cap, int
   }
 }
 
-__global__ __launch_bounds__(256) void k_node_assign(const uint64_t* __restrict__ m, const uint8_t* __restrict__ t0,
+__global__ __launch_bounds__(256) void k_node_assign(const uint8_t* __restrict__ t0, const uint16_t* __restrict__ sec,
                                                      const uint64_t* __restrict__ samples, const int64_t* rowptr,
                                                      int64_t n0, int64_t row_base, int K, const int64_t* nbase,
                                                      const int64_t* ebase, NodeList nl,
@@ -140,7 +113,7 @@ __global__ __launch_bounds__(256) void k_node_assign(const uint64_t* __restrict_
   __shared__ int id[256];
   const int64_t n = n0 + blockIdx.x;
   const int64_t r0 = rowptr[n] - row_base, r1 = rowptr[n + 1] - row_base;
-  build_table(m, t0, samples, n, r0, r1, K, e);
+  build_table(t0, sec, r0, r1, K, e);
   const int64_t nb = nbase[blockIdx.x];
   const bool keep = nb >= 0;
   const uint64_t nlo = samples[2 * n], nhi = samples[2 * n + 1];
@@ -172,23 +145,21 @@ __global__ __launch_bounds__(256) void k_node_assign(const uint64_t* __restrict_
   __syncthreads();
   for (int64_t r = r0 + threadIdx.x; r < r1; r += blockDim.x) {
     const int c1 = int(t0[r]);
-    int key, c2;
-    row_key(m[2 * r], m[2 * r + 1], nlo, nhi, c1, K, key, c2);
-    const int node = key >= 0 ? id[key] : -1;
+    const int v = sec[r];
+    const int node = c1 < K ? id[c1 * 4 + (v >> 8)] : -1;
     row_node[r] = node;
-    row_site[r] = uint8_t(key < 0 ? K : (node >= 0 ? c2 : c1));
+    row_site[r] = uint8_t(c1 >= K ? K : (node >= 0 ? (v & 0xFF) : c1));
   }
 }
 
 }  // namespace
 
-hipError_t launch_node_count(const uint64_t* m, const uint8_t* t0, const uint64_t* samples, const int64_t* rowptr,
-                             int64_t n0, int64_t n1, int64_t row_base, int K, int32_t* ncnt, int64_t* nent,
-                             hipStream_t st) {
+hipError_t launch_node_count(const uint8_t* t0, const uint16_t* sec, const int64_t* rowptr, int64_t n0, int64_t n1,
+                             int64_t row_base, int K, int32_t* ncnt, int64_t* nent, hipStream_t st) {
   if (n1 <= n0) return hipSuccess;
   if (K < 1 || K > 64) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_node_count, dim3(unsigned(n1 - n0)), dim3(256), 0, st, m, t0, samples, rowptr, n0, row_base,
-                     K, ncnt, nent);
+  hipLaunchKernelGGL(k_node_count, dim3(unsigned(n1 - n0)), dim3(256), 0, st, t0, sec, rowptr, n0, row_base, K,
+                     ncnt, nent);
   return hipGetLastError();
 }
 
@@ -199,12 +170,12 @@ hipError_t launch_node_scan(int64_t ns, int64_t cap, int32_t* ncnt, int64_t* nen
   return hipGetLastError();
 }
 
-hipError_t launch_node_assign(const uint64_t* m, const uint8_t* t0, const uint64_t* samples, const int64_t* rowptr,
-                              int64_t n0, int64_t n1, int64_t row_base, int K, const int64_t* nbase,
-                              const int64_t* ebase, const NodeList& nl, int32_t* row_node,
+hipError_t launch_node_assign(const uint8_t* t0, const uint16_t* sec, const uint64_t* samples,
+                              const int64_t* rowptr, int64_t n0, int64_t n1, int64_t row_base, int K,
+                              const int64_t* nbase, const int64_t* ebase, const NodeList& nl, int32_t* row_node,
                               uint8_t* row_site, hipStream_t st) {
   if (n1 <= n0) return hipSuccess;
-  hipLaunchKernelGGL(k_node_assign, dim3(unsigned(n1 - n0)), dim3(256), 0, st, m, t0, samples, rowptr, n0,
+  hipLaunchKernelGGL(k_node_assign, dim3(unsigned(n1 - n0)), dim3(256), 0, st, t0, sec, samples, rowptr, n0,
                      row_base, K, nbase, ebase, nl, row_node, row_site);
   return hipGetLastError();
 }

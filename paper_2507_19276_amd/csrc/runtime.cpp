@@ -1139,6 +1139,7 @@ nqs_status nqs_eloc(nqs_ctx* ctx, const nqs_instance* inst, const nqs_ansatz* an
     rs.npg = S.get<int8_t>(ecap);
     row_node = S.get<int32_t>(cap_used);
     row_site = S.get<uint8_t>(cap_used);
+    P.rows.sec = S.get<uint16_t>(cap_used);
   }
   if (S.oom) return fail(NQS_ENOMEM, "workspace allocation failed");
   if (ans->nh) HIPCHK(launch_corr_theta(ans->corr(), samples, N, theta, stream));
@@ -1181,12 +1182,12 @@ nqs_status nqs_eloc(nqs_ctx* ctx, const nqs_instance* inst, const nqs_ansatz* an
       if (nodes) {
         // nodes of this pass: count, place (host learns the totals), assign
         const int64_t ns = n1 - n0, row_base = P.rowptr_host[n0];
-        HIPCHK(launch_node_count(P.rows.m, P.rows.t0, samples, P.rowptr, n0, n1, row_base, K, ncnt, nent, stream));
+        HIPCHK(launch_node_count(P.rows.t0, P.rows.sec, P.rowptr, n0, n1, row_base, K, ncnt, nent, stream));
         HIPCHK(launch_node_scan(ns, ecap, ncnt, nent, nbase, ebase, ntot, stream));
         int64_t tot2[2] = {0, 0};
         HIPCHK(hipMemcpyAsync(tot2, ntot, sizeof tot2, hipMemcpyDeviceToHost, stream));
         HIPCHK(hipStreamSynchronize(stream));
-        HIPCHK(launch_node_assign(P.rows.m, P.rows.t0, samples, P.rowptr, n0, n1, row_base, K, nbase, ebase, nl,
+        HIPCHK(launch_node_assign(P.rows.t0, P.rows.sec, samples, P.rowptr, n0, n1, row_base, K, nbase, ebase, nl,
                                   row_node, row_site, stream));
         const int64_t nn = tot2[0];
         if (nn > 0) {
@@ -1355,7 +1356,7 @@ nqs_status nqs_eloc_workspace_bytes(const nqs_instance* inst, const nqs_ansatz* 
       b += al(size_t(ecap) * 16) + al(size_t(ecap) * 4) + 2 * al(size_t(ecap)) + al(size_t(ecap) * 8);
       b += al(size_t(ecap) * 4) + al(size_t(ecap)) + al(size_t(ecap) * 8) + al(size_t(ecap));
       b += al(size_t(ecap) * ans->chip * esz) + al(size_t(ecap) * esz) + al(size_t(ecap) * 4) + al(size_t(ecap));
-      b += al(size_t(rows) * 4) + al(size_t(rows));
+      b += al(size_t(rows) * 4) + al(size_t(rows)) + al(size_t(rows) * 2);
     }
   }
   b += 3 * al(size_t(N) * 8) + al(64);     // outputs the caller did not provide, batch sums
