@@ -48,6 +48,8 @@ def _load():
     lib.or_n_params.restype = _i64
     lib.or_amplitudes.argtypes = [_i, _i, _i, _i, _p, _p, _i, _p, _p, _i64, _p, _p, _p, _p, _i]
     lib.or_sample.argtypes = [_i, _i, _i, _i, _p, _p, _p, _p, _i64, _p]
+    lib.or_sample_unique.argtypes = [_i, _i, _i, _i, _p, _p, _p, _u64, _i64, _i64, _i64, _p, _p]
+    lib.or_sample_unique.restype = _i64
     lib.or_grad.argtypes = [_i, _i, _i, _i, _p, _p, _i, _p, _p, _i64, _p, _p, _i]
     lib.or_eloc.argtypes = [_i, _i, _i, _p, _p, _d, _i, _p, _p, _i, _p, _p, _i64, _d, _i, _u64,
                             _u64, _i64, _p, _p, _p, _p, _p, _p, _p, _p, _i]
@@ -143,6 +145,20 @@ def sample(K, chi, na, nb, parent_ptr, parent_idx, params, u) -> np.ndarray:
     out = np.zeros((N, 2), dtype=np.uint64)
     _load().or_sample(K, chi, na, nb, _ptr(pp), _ptr(pi), _ptr(prm), _ptr(uu), N, _ptr(out))
     return out
+
+
+def sample_unique(K, chi, na, nb, parent_ptr, parent_idx, params, seed: int, n_draws: int, draw_base: int = 0):
+    """Draws draw_base .. draw_base+n_draws-1 of the counter-keyed sampler (the
+    uniform of draw t at site i comes from Philox4x32-10 at counter
+    (t lo, t hi, i, 0x53414D50), key (seed lo, seed hi)), merged into unique
+    ONVs in ascending (hi, lo) order with counts."""
+    pp, pi, prm = _i32(parent_ptr), _i32(parent_idx), _f64(params)
+    cap = max(int(n_draws), 1)
+    out = np.zeros((cap, 2), dtype=np.uint64)
+    cnt = np.zeros(cap, dtype=np.int64)
+    n = _load().or_sample_unique(K, chi, na, nb, _ptr(pp), _ptr(pi), _ptr(prm), int(seed) & 0xFFFFFFFFFFFFFFFF,
+                                 int(draw_base), int(n_draws), cap, _ptr(out), _ptr(cnt))
+    return out[:n], cnt[:n]
 
 
 def grad(K, chi, na, nb, parent_ptr, parent_idx, n_hidden, params, samples, g,

@@ -47,6 +47,7 @@
 #include <cstring>
 #include <limits>
 #include <vector>
+#include <map>
 #include <algorithm>
 #include <omp.h>
 
@@ -615,6 +616,18 @@ int or_amplitudes(int K, int chi, int na, int nb, const int* pptr, const int* pi
   return 0;
 }
 
+// the uniform of draw t at site i for the counter-keyed sampler: the 53-bit
+// fraction of words 0, 1 of Philox4x32-10 at counter (t lo, t hi, i, 0x53414D50)
+// under key (seed lo, seed hi)
+double sampler_uniform(uint64_t seed, uint64_t t, int i) {
+  const uint32_t ctr[4] = {uint32_t(t), uint32_t(t >> 32), uint32_t(i), 0x53414D50u};
+  const uint32_t key[2] = {uint32_t(seed), uint32_t(seed >> 32)};
+  uint32_t w[4];
+  philox4x32_10(ctr, key, w);
+  const uint64_t bits = ((uint64_t(w[1]) << 32) | w[0]) >> 11;
+  return double(bits) / 9007199254740992.0;   // 2^53
+}
+
 // exact autoregressive draws from Phi^2 using the caller's uniforms u[N][K]
 int or_sample(int K, int chi, int na, int nb, const int* pptr, const int* pidx,
               const double* prm, const double* u, int64_t N, uint64_t* out) {
@@ -653,6 +666,30 @@ int or_sample(int K, int chi, int na, int nb, const int* pptr, const int* pidx,
     det_to_words(d, out + 2 * t);
   }
   return 0;
+}
+
+// draws t = t0 .. t0+N-1 of the counter-keyed sampler (uniforms from
+// sampler_uniform), then merged: unique ONVs in ascending (hi, lo) order with
+// their counts; returns the number of unique ONVs (at most cap are written)
+int64_t or_sample_unique(int K, int chi, int na, int nb, const int* pptr, const int* pidx, const double* prm,
+                         uint64_t seed, int64_t t0, int64_t N, int64_t cap, uint64_t* out, int64_t* counts) {
+  std::vector<double> u(size_t(N) * K);
+  for (int64_t t = 0; t < N; ++t)
+    for (int i = 0; i < K; ++i) u[size_t(t) * K + i] = sampler_uniform(seed, uint64_t(t0 + t), i);
+  std::vector<uint64_t> d(size_t(N) * 2);
+  or_sample(K, chi, na, nb, pptr, pidx, prm, u.data(), N, d.data());
+  std::map<std::pair<uint64_t, uint64_t>, int64_t> merged;   // ordered by (hi, lo)
+  for (int64_t t = 0; t < N; ++t) ++merged[{d[2 * t + 1], d[2 * t]}];
+  int64_t k = 0;
+  for (const auto& kv : merged) {
+    if (k < cap) {
+      out[2 * k] = kv.first.second;
+      out[2 * k + 1] = kv.first.first;
+      counts[k] = kv.second;
+    }
+    ++k;
+  }
+  return k;
 }
 
 // sum_n g_n d ln|Psi(n)| / d theta, accumulated into grad (length n_params)

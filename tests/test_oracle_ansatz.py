@@ -154,3 +154,64 @@ def test_grad_of_normalisation_vanishes():
     gr1 = oracle.grad(w.K, w.chi, w.n_alpha, w.n_beta, w.parent_ptr, w.parent_idx, 0,
                       w.params, w.samples, g1)
     assert np.abs(gr1).max() > 1e-3
+
+
+def _sampler_uniforms(seed, t0, n, K):
+    """The counter-keyed sampler's uniforms, rebuilt from the known-answer-checked
+    Philox4x32-10: words 0 and 1 of counter (t lo, t hi, i, 0x53414D50) under
+    key (seed lo, seed hi), as a 53-bit fraction."""
+    u = np.zeros((n, K))
+    key = [seed & 0xFFFFFFFF, (seed >> 32) & 0xFFFFFFFF]
+    for t in range(n):
+        for i in range(K):
+            tt = t0 + t
+            w = oracle.philox4x32_10([tt & 0xFFFFFFFF, tt >> 32, i, 0x53414D50], key)
+            u[t, i] = float((((int(w[1]) << 32) | int(w[0])) >> 11)) / 2.0 ** 53
+    return u
+
+
+def test_unique_sampler_is_the_plain_sampler_on_its_uniforms():
+    """or_sample_unique = or_sample on the uniforms of the published generator,
+    merged: same ONV multiset, ascending (hi, lo) order, counts summing to N;
+    a draw offset selects the matching slice of the stream."""
+    w = _small(graph="nnn")
+    seed, n = 0xC0FFEE1234, 3000
+    u = _sampler_uniforms(seed, 0, n, w.K)
+    draws = oracle.sample(w.K, w.chi, w.n_alpha, w.n_beta, w.parent_ptr, w.parent_idx, w.params, u)
+    uniq, cnt = oracle.sample_unique(w.K, w.chi, w.n_alpha, w.n_beta, w.parent_ptr, w.parent_idx, w.params,
+                                     seed, n)
+    ref = {}
+    for d in draws:
+        key = (int(d[1]), int(d[0]))
+        ref[key] = ref.get(key, 0) + 1
+    keys = sorted(ref)
+    assert [(int(x[1]), int(x[0])) for x in uniq] == keys
+    assert list(cnt) == [ref[k] for k in keys]
+    assert cnt.sum() == n
+    # draws 1000..1999 are the middle slice of the same stream
+    mid = oracle.sample(w.K, w.chi, w.n_alpha, w.n_beta, w.parent_ptr, w.parent_idx, w.params, u[1000:2000])
+    u2, c2 = oracle.sample_unique(w.K, w.chi, w.n_alpha, w.n_beta, w.parent_ptr, w.parent_idx, w.params,
+                                  seed, 1000, draw_base=1000)
+    ref2 = {}
+    for d in mid:
+        key = (int(d[1]), int(d[0]))
+        ref2[key] = ref2.get(key, 0) + 1
+    assert {(int(x[1]), int(x[0])): int(c) for x, c in zip(u2, c2)} == ref2
+
+
+def test_unique_sampler_distribution():
+    """Counts of the counter-keyed sampler follow Phi^2 (chi-square over the sector)."""
+    w = _small(graph="chain")
+    p = np.exp(2 * _amps(w)["lphi"])
+    keys = {(int(s[0]), int(s[1])): k for k, s in enumerate(w.samples)}
+    N = 200_000
+    uniq, cnt = oracle.sample_unique(w.K, w.chi, w.n_alpha, w.n_beta, w.parent_ptr, w.parent_idx, w.params,
+                                     20250725, N)
+    obs = np.zeros(len(p))
+    for x, c in zip(uniq, cnt):
+        obs[keys[(int(x[0]), int(x[1]))]] += c
+    exp = p * N
+    m = exp > 5
+    chi2 = ((obs[m] - exp[m]) ** 2 / exp[m]).sum()
+    dof = m.sum() - 1
+    assert chi2 < dof + 6 * np.sqrt(2 * dof)
