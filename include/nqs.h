@@ -180,6 +180,27 @@ nqs_status nqs_logpsi(nqs_ctx* ctx, const nqs_ansatz* ans, const uint64_t* sampl
 nqs_status nqs_logpsi_vjp(nqs_ctx* ctx, const nqs_ansatz* ans, const uint64_t* samples, int64_t N,
                           const double* cot, int32_t precision, double* grad, hipStream_t stream);
 
+/* ---- sampling (Sec. 2.1 autoregressive sampling, masks of Sec. 3) ------ */
+
+/* Exact autoregressive draws from Phi^2 (the BDG-RNN / MPS-RNN modulus of
+ * Eqs. (9)-(10); the correlator is left to reweighting, Sec. 2.3), with the
+ * particle-number / S_z mask of Eqs. (23)-(24).  Draw t (t = draw_base ..
+ * draw_base + n_draws - 1) takes site i's local state s from the masked
+ * conditionals p_s (s = 0..3, n_alpha + 2 n_beta): with the uniform u of
+ * words 0 and 1 of Philox4x32-10 at counter (t lo, t hi, i, 0x53414D50) under
+ * key (seed lo, seed hi) as a 53-bit fraction, the first s whose running sum of
+ * the allowed p exceeds u * sum p (the last allowed s if none).  Draws are
+ * independent of each other and of how they are split into calls.  Equal
+ * draws are merged: samples (device uint64[cap][2], ascending by high then
+ * low word), counts (device int64[cap]), logabs (device double[cap],
+ * log|Phi|, nullable), sign (device int8[cap], sign of Phi, nullable);
+ * *n_unique (host) receives the number of unique draws, of which at most cap
+ * are written.  precision NQS_F64 or NQS_F32 (the conditionals' precision).
+ * Synchronises `stream`. */
+nqs_status nqs_sample(nqs_ctx* ctx, const nqs_ansatz* ans, int64_t n_draws, uint64_t seed, int64_t draw_base,
+                      int32_t precision, int64_t cap, uint64_t* samples, int64_t* counts, double* logabs,
+                      int8_t* sign, int64_t* n_unique, hipStream_t stream);
+
 /* ---- local energy (Sec. 2.4) ------------------------------------------ */
 
 /* Semi-stochastic local energies of N samples (device [N][2] uint64).

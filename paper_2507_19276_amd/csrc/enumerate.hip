@@ -12,6 +12,7 @@
 // This file is compiled without floating-point contraction: the matrix
 // elements are meant to equal a plain sequential evaluation bit for bit.
 #include "internal.h"
+#include "philox.h"
 
 #pragma clang fp contract(off)
 
@@ -235,22 +236,6 @@ __device__ inline uint64_t proposal_weight(double absH, int qshift) {
   return uint64_t(ceil(ldexp(absH, qshift)));
 }
 
-// ---------------------------------------------------------------------------
-// Philox4x32-10 (Salmon et al., SC'11)
-// ---------------------------------------------------------------------------
-__device__ inline void philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0,
-                              uint32_t k1, uint32_t out[4]) {
-#pragma unroll
-  for (int rnd = 0; rnd < 10; ++rnd) {
-    if (rnd) { k0 += 0x9E3779B9u; k1 += 0xBB67AE85u; }
-    const uint32_t lo0 = 0xD2511F53u * c0, hi0 = __umulhi(0xD2511F53u, c0);
-    const uint32_t lo1 = 0xCD9E8D57u * c2, hi1 = __umulhi(0xCD9E8D57u, c2);
-    const uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
-    c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;
-  }
-  out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
-}
-
 // floor(U * Q / 2^128) with U = (u3 u2 u1 u0) in 32-bit words, Q < 2^60
 __device__ inline uint64_t scaled_draw(const uint32_t U[4], uint64_t Q) {
   const uint64_t ulo = uint64_t(U[0]) | (uint64_t(U[1]) << 32);
@@ -369,7 +354,7 @@ __global__ __launch_bounds__(256) void k_draw(HamDev H, EnumGeom G, const uint64
   const uint64_t* qp = qpref + n * G.nchunks;
   for (int k = tid; k < n_eps; k += blockDim.x) {
     uint32_t U[4];
-    philox(keys.sample_base + uint32_t(n), uint32_t(k), keys.ctr2, keys.ctr3, keys.key0, keys.key1, U);
+    philox4x32_10(keys.sample_base + uint32_t(n), uint32_t(k), keys.ctr2, keys.ctr3, keys.key0, keys.key1, U);
     const uint64_t r = scaled_draw(U, Q);
     int s = 0;
     while (s + 1 < G.S && segq_off[n * G.S + s + 1] <= r) ++s;

@@ -149,6 +149,16 @@ hipError_t launch_connected(const HamDev& H, const uint64_t* samples, int64_t N,
 // X.perm[p]; positions are sorted by the row's first changed site X.t0[p],
 // and each wavefront resumes at the site of its first position from the state
 // that a STORE pass left for the row's sample X.owner[row].
+// Sampling (psi.hip, sampling mode of the forward): particle p = p0 + row
+// draws its local state at site i with the uniform of Philox4x32-10 counter
+// (p lo, p hi, i, kSampleTag) and key (k0, k1); out receives its ONV.
+constexpr uint32_t kSampleTag = 0x53414D50u;
+struct SampleArgs {
+  uint32_t k0 = 0, k1 = 0;
+  int64_t p0 = 0;
+  uint64_t* out = nullptr;       // [R][2]
+};
+template <typename T> struct PsiParams;
 // PSI_NODE: SEED for the units of a node list (resumed from their samples)
 // plus the compact store of nodes.hip.
 enum { PSI_PLAIN = 0, PSI_STORE = 1, PSI_SEED = 2, PSI_NODE = 3 };
@@ -196,6 +206,26 @@ hipError_t launch_psi_f64(const PsiParams<double>& P, const uint64_t* m, int64_t
 hipError_t launch_psi_f32(const PsiParams<float>& P, const uint64_t* m, int64_t R, double* lphi,
                           int8_t* sphi, hipStream_t st, const PsiStates<float>& X = PsiStates<float>(),
                           int mode = PSI_PLAIN);
+hipError_t launch_sample_f64(const PsiParams<double>& P, int64_t R, double* lphi, int8_t* sphi, hipStream_t st,
+                             const SampleArgs& SA);
+hipError_t launch_sample_f32(const PsiParams<float>& P, int64_t R, double* lphi, int8_t* sphi, hipStream_t st,
+                             const SampleArgs& SA);
+// ---- unique ONVs with counts (unique.hip) ------------------------------
+struct UniqueScratch {
+  void* temp;                    // hipCUB temporary storage
+  size_t temp_bytes;
+  uint64_t *key_a, *key_b;       // [N]
+  uint32_t *ord_a, *ord_b;       // [N]
+  int32_t *flag, *pos;           // [N]
+  int64_t* start;                // [N]
+};
+hipError_t unique_temp_bytes(int64_t N, size_t* bytes);
+// merges m [N][2] into unique ONVs (ascending high, low word), their counts and
+// the lphi/sphi of a representative; *nu (device) = number of unique ONVs,
+// at most cap written
+hipError_t launch_unique(const uint64_t* m, const double* lphi, const int8_t* sphi, int64_t N, bool two_words,
+                         const UniqueScratch& w, int64_t cap, uint64_t* um, int64_t* ucnt, double* ul, int8_t* us,
+                         int64_t* nu, hipStream_t st);
 // ---- row order by first changed site (order.hip) ----------------------
 // chunk of rows per block of the counting sort
 constexpr int kOrderChunk = 16384;

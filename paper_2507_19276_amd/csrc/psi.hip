@@ -12,6 +12,7 @@
 // Carried hidden states live in a lane-private LDS ring of
 // W = (max parent offset + 1) slots.
 #include "device.h"
+#include "philox.h"
 
 namespace nqs {
 namespace {
@@ -39,10 +40,10 @@ template <typename T> constexpr int prefetch_ksteps(int CH) {
   return (CH / 4) < 64 / ((CH / 4) * int(sizeof(T) / 4)) ? (CH / 4) : 64 / ((CH / 4) * int(sizeof(T) / 4));
 }
 
-template <typename T, int CH, int NTL, bool FOLD, int STORE, bool SEED>
+template <typename T, int CH, int NTL, bool FOLD, int STORE, bool SEED, bool SAMPLE>
 __global__ __launch_bounds__(256) void k_psi_mt(PsiParams<T> P, const uint64_t* __restrict__ m, int64_t R,
                                                 double* __restrict__ lphi, int8_t* __restrict__ sphi, int wpb,
-                                                PsiStates<T> X) {
+                                                PsiStates<T> X, SampleArgs SA) {
   // every floating-point operation below is written out (explicit fma where
   // one is meant), so that all instances of this kernel round alike: a row
   // resumed from its sample's stored state ends bit-identical to a row
@@ -81,8 +82,8 @@ __global__ __launch_bounds__(256) void k_psi_mt(PsiParams<T> P, const uint64_t* 
     const int64_t r = base + 16 * t + j;
     const int64_t rr = r < R ? r : R - 1;
     rowt[t] = SEED ? int64_t(X.perm[rr]) : rr;
-    lo[t] = m[2 * rowt[t]];
-    hi[t] = m[2 * rowt[t] + 1];
+    lo[t] = SAMPLE ? 0ull : m[2 * rowt[t]];
+    hi[t] = SAMPLE ? 0ull : m[2 * rowt[t] + 1];
     if (t == own) { olo = lo[t]; ohi = hi[t]; }
   }
   const bool olive = base + 16 * own + j < R;
@@ -242,6 +243,97 @@ __global__ __launch_bounds__(256) void k_psi_mt(PsiParams<T> P, const uint64_t* 
     if (BPF) fetch_bias(i + 1 < P.K ? i + 1 : i);
     do edge(); while (++e < e1);
     __builtin_amdgcn_s_setprio(0);
+    if constexpr (SAMPLE) {
+      // sampling: the row's local state is drawn from its masked conditionals
+      // before the carried state is selected
+      T pp[4][NTL], dp[NTL];
+#pragma unroll
+      for (int t = 0; t < NTL; ++t) {
+        dp[t] = T(0);
+#pragma unroll
+        for (int s = 0; s < 4; ++s) pp[s][t] = T(0);
+      }
+#pragma unroll
+      for (int tt = 0; tt < TPC; ++tt)
+#pragma unroll
+        for (int t = 0; t < NTL; ++t)
+#pragma unroll
+          for (int s = 0; s < 4; ++s) {
+            const V x = acc[t][s * TPC + tt];
+            const V ex = FOLD ? x : ev4[tt] * x;
+            T q = pp[s][t];
+            q = tfma(ex.x, x.x, q);
+            q = tfma(ex.y, x.y, q);
+            q = tfma(ex.z, x.z, q);
+            q = tfma(ex.w, x.w, q);
+            pp[s][t] = q;
+          }
+      T ps[4];
+#pragma unroll
+      for (int s = 0; s < 4; ++s) ps[s] = ReduceOwn<T, NTL>::run(pp[s]);
+      const int rest = P.K - 1 - i;
+      T pr[4], Z = T(0);
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        pr[s] = allowed(ca, cb, s, rest, P.na, P.nb) ? ps[s] : T(0);
+        Z += pr[s];
+      }
+      // the particle's uniform for this site (53-bit fraction of Philox words 0, 1)
+      const uint64_t pid = uint64_t(SA.p0 + base + 16 * own + j);
+      uint32_t U[4];
+      philox4x32_10(uint32_t(pid), uint32_t(pid >> 32), uint32_t(i), kSampleTag, SA.k0, SA.k1, U);
+      const double u = double(((uint64_t(U[1]) << 32) | U[0]) >> 11) * 0x1p-53;
+      const T target = T(u) * Z;
+      T run = T(0);
+      int pick = -1, last = -1;
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        if (pr[s] > T(0)) {
+          last = s;
+          run += pr[s];
+          if (pick < 0 && run > target) pick = s;
+        }
+      }
+      if (pick < 0) pick = last;
+      if (pick < 0) {                     // no state has weight: the row is dead
+        bad = true;
+        pick = 0;
+      }
+      // the draw of row j of tile t sits in the lane group that owns tile t
+      int ch[NTL];
+#pragma unroll
+      for (int t = 0; t < NTL; ++t)
+        ch[t] = NTL == 4 ? __shfl(pick, j + 16 * t) : (NTL == 2 ? __shfl(pick, j + 32 * t) : pick);
+      V* wr = ring + size_t(wslot) * SLOT;
+#pragma unroll
+      for (int tt = 0; tt < TPC; ++tt) {
+        const V ww = wv4[tt];
+#pragma unroll
+        for (int t = 0; t < NTL; ++t) {
+          const V sel01 = (ch[t] & 1) ? acc[t][1 * TPC + tt] : acc[t][0 * TPC + tt];
+          const V sel23 = (ch[t] & 1) ? acc[t][3 * TPC + tt] : acc[t][2 * TPC + tt];
+          const V sel = (ch[t] & 2) ? sel23 : sel01;
+          T d = dp[t];
+          d = tfma(ww.x, sel.x, d);
+          d = tfma(ww.y, sel.y, d);
+          d = tfma(ww.z, sel.z, d);
+          d = tfma(ww.w, sel.w, d);
+          dp[t] = d;
+          wr[(t * TPC + tt) * 64] = sel;
+        }
+      }
+      wslot = wslot + 1 == P.W ? 0 : wslot + 1;
+      const T dot = ReduceOwn<T, NTL>::run(dp) + T(cc[i]);
+      int ex;
+      prod = tfrexp(prod * (pr[pick] / Z), &ex);
+      pexp += ex;
+      if (dot < T(0)) sgn = -sgn;
+      ca += pick & 1;
+      cb += pick >> 1;
+      const int P2 = 2 * i;
+      if (P2 < 64) olo |= uint64_t(pick) << P2; else ohi |= uint64_t(pick) << (P2 - 64);
+      continue;
+    }
     // epilogue in the MFMA output layout: lane (j, g) holds units 16tt+4g..+3
     int si[NTL];
 #pragma unroll
@@ -319,6 +411,10 @@ __global__ __launch_bounds__(256) void k_psi_mt(PsiParams<T> P, const uint64_t* 
   if (writer && olive) {
     lphi[orow] = bad ? -INFINITY : 0.5 * (log(double(prod)) + double(pexp) * 0.69314718055994530942);
     sphi[orow] = int8_t(bad ? 0 : sgn);
+    if (SAMPLE) {
+      SA.out[2 * orow] = olo;
+      SA.out[2 * orow + 1] = ohi;
+    }
   }
 }
 
@@ -329,9 +425,9 @@ template <typename T> constexpr int ntiles(int CH) {
   return sizeof(T) == 4 ? (CH <= 16 ? NQS_NTL_F32_16 : (CH <= 32 ? 2 : 1)) : (CH <= 16 ? 2 : 1);
 }
 
-template <typename T, int CH, bool FOLD, int STORE, bool SEED>
+template <typename T, int CH, bool FOLD, int STORE, bool SEED, bool SAMPLE = false>
 hipError_t run_psi_mt(const PsiParams<T>& P, const uint64_t* m, int64_t R, double* lphi, int8_t* sphi,
-                      hipStream_t st, const PsiStates<T>& X) {
+                      hipStream_t st, const PsiStates<T>& X, const SampleArgs& SA = SampleArgs()) {
   if (R <= 0) return hipSuccess;
   constexpr int NTL = ntiles<T>(CH);
   const size_t per_wave = size_t(P.W + 1) * 16 * NTL * CH * sizeof(T);
@@ -340,8 +436,8 @@ hipError_t run_psi_mt(const PsiParams<T>& P, const uint64_t* m, int64_t R, doubl
   if (per_wave * wpb > 160 * 1024) return hipErrorInvalidValue;
   const int64_t tiles = (R + 16 * NTL - 1) / (16 * NTL);
   const int64_t blocks = (tiles + wpb - 1) / wpb;
-  hipLaunchKernelGGL((k_psi_mt<T, CH, NTL, FOLD, STORE, SEED>), dim3(unsigned(blocks)), dim3(64 * wpb),
-                     per_wave * wpb, st, P, m, R, lphi, sphi, wpb, X);
+  hipLaunchKernelGGL((k_psi_mt<T, CH, NTL, FOLD, STORE, SEED, SAMPLE>), dim3(unsigned(blocks)), dim3(64 * wpb),
+                     per_wave * wpb, st, P, m, R, lphi, sphi, wpb, X, SA);
   return hipGetLastError();
 }
 
@@ -363,6 +459,25 @@ hipError_t run_psi_ch(const PsiParams<T>& P, const uint64_t* m, int64_t R, doubl
       return run_psi_mt<T, CH, false, 2, true>(P, m, R, lphi, sphi, st, X);
     default:
       return hipErrorInvalidValue;
+  }
+}
+
+template <typename T, int CH>
+hipError_t run_sample_ch(const PsiParams<T>& P, int64_t R, double* lphi, int8_t* sphi, hipStream_t st,
+                         const SampleArgs& SA) {
+  if (P.folded) return run_psi_mt<T, CH, true, 0, false, true>(P, nullptr, R, lphi, sphi, st, PsiStates<T>(), SA);
+  return run_psi_mt<T, CH, false, 0, false, true>(P, nullptr, R, lphi, sphi, st, PsiStates<T>(), SA);
+}
+
+template <typename T>
+hipError_t dispatch_sample(const PsiParams<T>& P, int64_t R, double* lphi, int8_t* sphi, hipStream_t st,
+                           const SampleArgs& SA) {
+  switch (P.chip) {
+    case 16: return run_sample_ch<T, 16>(P, R, lphi, sphi, st, SA);
+    case 32: return run_sample_ch<T, 32>(P, R, lphi, sphi, st, SA);
+    case 48: return run_sample_ch<T, 48>(P, R, lphi, sphi, st, SA);
+    case 64: return run_sample_ch<T, 64>(P, R, lphi, sphi, st, SA);
+    default: return hipErrorInvalidValue;
   }
 }
 
@@ -388,6 +503,16 @@ hipError_t launch_psi_f64(const PsiParams<double>& P, const uint64_t* m, int64_t
 hipError_t launch_psi_f32(const PsiParams<float>& P, const uint64_t* m, int64_t R, double* lphi,
                           int8_t* sphi, hipStream_t st, const PsiStates<float>& X, int mode) {
   return dispatch_psi<float>(P, m, R, lphi, sphi, st, X, mode);
+}
+
+hipError_t launch_sample_f64(const PsiParams<double>& P, int64_t R, double* lphi, int8_t* sphi, hipStream_t st,
+                             const SampleArgs& SA) {
+  return dispatch_sample<double>(P, R, lphi, sphi, st, SA);
+}
+
+hipError_t launch_sample_f32(const PsiParams<float>& P, int64_t R, double* lphi, int8_t* sphi, hipStream_t st,
+                             const SampleArgs& SA) {
+  return dispatch_sample<float>(P, R, lphi, sphi, st, SA);
 }
 
 }  // namespace nqs

@@ -1288,6 +1288,51 @@ nqs_status nqs_eloc(nqs_ctx* ctx, const nqs_instance* inst, const nqs_ansatz* an
   return NQS_OK;
 }
 
+nqs_status nqs_sample(nqs_ctx* ctx, const nqs_ansatz* ans, int64_t n_draws, uint64_t seed, int64_t draw_base,
+                      int32_t precision, int64_t cap, uint64_t* samples, int64_t* counts, double* logabs,
+                      int8_t* sign, int64_t* n_unique, hipStream_t stream) {
+  if (!ctx || !ans || n_draws < 0 || draw_base < 0 || cap < 0 || !n_unique || (cap > 0 && (!samples || !counts)))
+    return fail(NQS_EINVAL, "bad arguments");
+  if (!ans->bound) return fail(NQS_EINVAL, "parameters not bound");
+  if (precision != NQS_F64 && precision != NQS_F32)
+    return fail(NQS_EUNSUPPORTED, "sampling runs in FP64 or FP32");
+  if (n_draws >= (int64_t(1) << 31)) return fail(NQS_EUNSUPPORTED, "more than 2^31 - 1 draws in one call");
+  DeviceGuard g(ctx->device);
+  *n_unique = 0;
+  if (n_draws == 0) return NQS_OK;
+  Scratch S(ctx);
+  uint64_t* m = S.get<uint64_t>(size_t(n_draws) * 2);
+  double* lphi = S.get<double>(n_draws);
+  int8_t* sphi = S.get<int8_t>(n_draws);
+  UniqueScratch w{};
+  HIPCHK(unique_temp_bytes(n_draws, &w.temp_bytes));
+  w.temp = S.get<unsigned char>(w.temp_bytes);
+  w.key_a = S.get<uint64_t>(n_draws);
+  w.key_b = S.get<uint64_t>(n_draws);
+  w.ord_a = S.get<uint32_t>(n_draws);
+  w.ord_b = S.get<uint32_t>(n_draws);
+  w.flag = S.get<int32_t>(n_draws);
+  w.pos = S.get<int32_t>(n_draws);
+  w.start = S.get<int64_t>(n_draws);
+  int64_t* nu = S.get<int64_t>(1);
+  if (S.oom) return fail(NQS_ENOMEM, "workspace allocation failed");
+  SampleArgs SA;
+  SA.k0 = uint32_t(seed);
+  SA.k1 = uint32_t(seed >> 32);
+  SA.p0 = draw_base;
+  SA.out = m;
+  if (precision == NQS_F64)
+    HIPCHK(launch_sample_f64(ans->params(ans->fwd64()), n_draws, lphi, sphi, stream, SA));
+  else
+    HIPCHK(launch_sample_f32(ans->params(ans->fwd32()), n_draws, lphi, sphi, stream, SA));
+  HIPCHK(launch_unique(m, lphi, sphi, n_draws, 2 * ans->K > 64, w, cap, samples, counts, logabs, sign, nu, stream));
+  int64_t h = 0;
+  HIPCHK(hipMemcpyAsync(&h, nu, sizeof h, hipMemcpyDeviceToHost, stream));
+  HIPCHK(hipStreamSynchronize(stream));
+  *n_unique = h;
+  return NQS_OK;
+}
+
 nqs_status nqs_rows(nqs_ctx* ctx, const nqs_instance* inst, const uint64_t* samples, int64_t N,
                     const nqs_eloc_opts* opts, int64_t cap, int64_t* row_ptr, int64_t* n_det,
                     uint64_t* Q, int64_t* rank, double* coef, uint64_t* m, int64_t* n_rows,

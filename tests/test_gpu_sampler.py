@@ -1,0 +1,158 @@
+"""GPU autoregressive sampler (exact draws from Phi^2, Sec. 2.1, with the
+particle-number / S_z masks of Eqs. (23)-(24)), merged into unique ONVs.
+
+Draw t's uniform at site i is a function of (seed, t, i) only, so the FP64
+path must give the oracle's draws exactly: both sides take each draw's
+decision in FP64 (the conditionals differ only in rounding order, which can
+flip a draw only when u Z lands within a few ulps of a running sum).  FP32
+draws are checked statistically against Phi^2 over a whole sector."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2507_19276_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def nqs():
+    from paper_2507_19276_amd import nqs as N
+    N.lib()
+    return N
+
+
+@pytest.fixture(scope="module")
+def ctx(nqs):
+    c = nqs.Context(0)
+    yield c
+    c.close()
+
+
+_cache = {}
+
+
+def setup(nqs, ctx, name):
+    if name not in _cache:
+        w = W.make_workload(name, n_samples=16)
+        ans = nqs.Ansatz(ctx, w.K, w.n_alpha, w.n_beta, w.chi, w.parent_ptr, w.parent_idx, w.n_hidden)
+        ans.bind(w.params)
+        _cache[name] = (w, ans)
+    return _cache[name]
+
+
+def ref_unique(w, seed, n, base=0):
+    return oracle.sample_unique(w.K, w.chi, w.n_alpha, w.n_beta, w.parent_ptr, w.parent_idx, w.params, seed, n,
+                                draw_base=base)
+
+
+def host(out):
+    s, c, la, sg, nu = out
+    return s.cpu().numpy().view(np.uint64), c.cpu().numpy(), la.cpu().numpy(), sg.cpu().numpy(), nu
+
+
+@pytest.mark.parametrize("name,n", [("c1", 3000), ("c2", 4096), ("c4b", 2000), ("c4a", 1000), ("c3", 500)])
+def test_f64_draws_match_oracle(nqs, ctx, name, n):
+    """Unique draws and counts bit-exact; log|Phi| and sign of each unique
+    draw against the oracle's amplitudes at the FP64 bar."""
+    w, ans = setup(nqs, ctx, name)
+    seed = 0x9E3779B97F4A7C15
+    s, c, la, sg, nu = host(ans.sample(n, seed=seed, precision="f64"))
+    ru, rc = ref_unique(w, seed, n)
+    assert nu == len(ru)
+    assert np.array_equal(s, ru), name
+    assert np.array_equal(c, rc), name
+    assert c.sum() == n
+    a = oracle.amplitudes(w.K, w.chi, w.n_alpha, w.n_beta, w.parent_ptr, w.parent_idx, 0, w.params, ru)
+    assert np.array_equal(sg.astype(np.int64), a["sphi"].astype(np.int64))
+    assert (np.abs(la - a["lphi"]) / np.maximum(np.abs(a["lphi"]), 1.0)).max() <= 1e-10
+
+
+def test_f64_draw_base_slice(nqs, ctx):
+    """Draws 2^32 + 7 .. + 999 (counter words 0 and 1 both used) against the
+    oracle, and a split of 0..1999 into two calls merges to the single call."""
+    w, ans = setup(nqs, ctx, "c2")
+    base = (1 << 32) + 7
+    s, c, _, _, _ = host(ans.sample(993, seed=5, draw_base=base, precision="f64"))
+    ru, rc = ref_unique(w, 5, 993, base)
+    assert np.array_equal(s, ru) and np.array_equal(c, rc)
+    whole = host(ans.sample(2000, seed=17, precision="f64"))
+    parts = [host(ans.sample(n, seed=17, draw_base=b, precision="f64")) for b, n in ((0, 1234), (1234, 766))]
+    merged = {}
+    for p in parts:
+        for x, k in zip(p[0], p[1]):
+            key = (int(x[1]), int(x[0]))
+            merged[key] = merged.get(key, 0) + int(k)
+    keys = sorted(merged)
+    assert np.array_equal(whole[0], np.array([[lo, hi] for hi, lo in keys], dtype=np.uint64))
+    assert np.array_equal(whole[1], np.array([merged[k] for k in keys]))
+
+
+def test_f32_distribution(nqs, ctx):
+    """FP32 draws over the whole K=6 (3a, 3b) sector: chi-square against the
+    oracle's Phi^2; every draw in the sector; counts sum to the draws."""
+    w, ans = setup(nqs, ctx, "c1")
+    sector = W.all_onvs(w.K, w.n_alpha, w.n_beta)
+    a = oracle.amplitudes(w.K, w.chi, w.n_alpha, w.n_beta, w.parent_ptr, w.parent_idx, 0, w.params, sector)
+    p = np.exp(2 * a["lphi"])
+    assert abs(p.sum() - 1) < 1e-9
+    keys = {(int(x[0]), int(x[1])): k for k, x in enumerate(sector)}
+    N = 400_000
+    s, c, la, _, nu = host(ans.sample(N, seed=77, precision="f32"))
+    assert c.sum() == N and nu == len(s)
+    obs = np.zeros(len(p))
+    for x, k in zip(s, c):
+        obs[keys[(int(x[0]), int(x[1]))]] += k
+    exp = p * N
+    m = exp > 5
+    chi2 = ((obs[m] - exp[m]) ** 2 / exp[m]).sum()
+    dof = m.sum() - 1
+    assert chi2 < dof + 6 * np.sqrt(2 * dof), (chi2, dof)
+    idx = np.array([keys[(int(x[0]), int(x[1]))] for x in s])
+    assert np.abs(la - a["lphi"][idx]).max() < 1e-4
+
+
+def test_f32_mostly_equals_f64(nqs, ctx):
+    """FP32 conditionals differ from FP64 by rounding: the same uniforms give
+    the same draws except where u Z falls within that rounding of a boundary."""
+    w, ans = setup(nqs, ctx, "c2")
+    s64, c64, _, _, _ = host(ans.sample(4096, seed=3, precision="f64"))
+    s32, c32, _, _, _ = host(ans.sample(4096, seed=3, precision="f32"))
+    d64 = {(int(x[0]), int(x[1])): int(k) for x, k in zip(s64, c64)}
+    d32 = {(int(x[0]), int(x[1])): int(k) for x, k in zip(s32, c32)}
+    same = sum(min(k, d32.get(x, 0)) for x, k in d64.items())
+    assert same >= 4096 - 8
+
+
+def test_edge_cases(nqs, ctx):
+    w, ans = setup(nqs, ctx, "c2")
+    s, c, la, sg, nu = ans.sample(0, seed=1)
+    assert nu == 0 and s.shape[0] == 0
+    # cap below the number of unique draws: the first cap in order, full count
+    ru, rc = ref_unique(w, 9, 3000)
+    s, c, _, _, nu = host(ans.sample(3000, seed=9, cap=100))
+    assert nu == len(ru) > 100
+    assert np.array_equal(s, ru[:100]) and np.array_equal(c, rc[:100])
+    # one draw
+    s, c, _, _, nu = host(ans.sample(1, seed=9))
+    assert nu == 1 and c[0] == 1
+    assert np.array_equal(s[0], oracle.sample_unique(w.K, w.chi, w.n_alpha, w.n_beta, w.parent_ptr, w.parent_idx,
+                                                     w.params, 9, 1)[0][0])
+    with pytest.raises(nqs.NqsError):
+        ans.sample(10, precision="bf16")
+    with pytest.raises(nqs.NqsError):
+        ans.sample(10, draw_base=-1)
+
+
+def test_samples_feed_eloc(nqs, ctx):
+    """The unique draws are valid samples of the sector: the local-energy call
+    accepts them with their counts, and its log|Psi| (correlator-free ansatz)
+    equals the sampler's log|Phi|."""
+    w, ans = setup(nqs, ctx, "c2")
+    inst = nqs.Instance(ctx, w.K, w.n_alpha, w.n_beta, w.h, w.eri, w.e_core)
+    s, c, la, sg, nu = ans.sample(4096, seed=21, precision="f64")
+    out, _ = nqs.eloc(ctx, inst, ans, s, counts=c, eps=w.eps, n_eps=w.n_eps, precision="f64", seed=1)
+    assert np.array_equal(out["logabs"].cpu().numpy(), la.cpu().numpy())
+    assert np.array_equal(out["sign"].cpu().numpy().astype(np.int64), sg.cpu().numpy().astype(np.int64))
+    assert np.isfinite(out["eloc"].cpu().numpy()).all()
+    inst.close()
