@@ -196,10 +196,16 @@ nqs_status nqs_logpsi_vjp(nqs_ctx* ctx, const nqs_ansatz* ans, const uint64_t* s
  * log|Phi|, nullable), sign (device int8[cap], sign of Phi, nullable);
  * *n_unique (host) receives the number of unique draws, of which at most cap
  * are written.  precision NQS_F64 or NQS_F32 (the conditionals' precision).
+ * Memory: the draws run in passes of at most max_draws_per_pass (0 = one
+ * pass, at most 2^31 - 1 draws); each pass is merged with the unique draws of
+ * the passes before it, so the workspace is about 25 B per draw of a pass plus
+ * about 150 B per unique draw, independent of n_draws.  The result does not
+ * depend on the pass size.  NQS_EUNSUPPORTED for BF16 or a pass (plus the
+ * unique draws so far) above 2^31 - 1; NQS_ENOMEM when the pool limit is hit.
  * Synchronises `stream`. */
 nqs_status nqs_sample(nqs_ctx* ctx, const nqs_ansatz* ans, int64_t n_draws, uint64_t seed, int64_t draw_base,
-                      int32_t precision, int64_t cap, uint64_t* samples, int64_t* counts, double* logabs,
-                      int8_t* sign, int64_t* n_unique, hipStream_t stream);
+                      int32_t precision, int64_t max_draws_per_pass, int64_t cap, uint64_t* samples,
+                      int64_t* counts, double* logabs, int8_t* sign, int64_t* n_unique, hipStream_t stream);
 
 /* ---- local energy (Sec. 2.4) ------------------------------------------ */
 

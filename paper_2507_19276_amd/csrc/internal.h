@@ -218,14 +218,17 @@ struct UniqueScratch {
   uint32_t *ord_a, *ord_b;       // [N]
   int32_t *flag, *pos;           // [N]
   int64_t* start;                // [N]
+  int64_t* wsum;                 // [N], used with weights
 };
 hipError_t unique_temp_bytes(int64_t N, size_t* bytes);
-// merges m [N][2] into unique ONVs (ascending high, low word), their counts and
+// merges m [N][2] into unique ONVs (ascending high, low word), their counts
+// (entries, or the sum of the entries' weights when weights is not null) and
 // the lphi/sphi of a representative; *nu (device) = number of unique ONVs,
 // at most cap written
-hipError_t launch_unique(const uint64_t* m, const double* lphi, const int8_t* sphi, int64_t N, bool two_words,
-                         const UniqueScratch& w, int64_t cap, uint64_t* um, int64_t* ucnt, double* ul, int8_t* us,
-                         int64_t* nu, hipStream_t st);
+hipError_t launch_unique(const uint64_t* m, const double* lphi, const int8_t* sphi, const int64_t* weights,
+                         int64_t N, bool two_words, const UniqueScratch& w, int64_t cap, uint64_t* um, int64_t* ucnt,
+                         double* ul, int8_t* us, int64_t* nu, hipStream_t st);
+hipError_t launch_fill_i64(int64_t* p, int64_t n, int64_t v, hipStream_t st);
 // ---- row order by first changed site (order.hip) ----------------------
 // chunk of rows per block of the counting sort
 constexpr int kOrderChunk = 16384;

@@ -11,6 +11,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <limits>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -1288,48 +1289,148 @@ nqs_status nqs_eloc(nqs_ctx* ctx, const nqs_instance* inst, const nqs_ansatz* an
   return NQS_OK;
 }
 
+namespace {
+// a pool block released when the holder goes out of scope
+struct PoolBlock {
+  nqs_ctx* ctx = nullptr;
+  void* p = nullptr;
+  PoolBlock() = default;
+  PoolBlock(const PoolBlock&) = delete;
+  PoolBlock& operator=(const PoolBlock&) = delete;
+  bool get(nqs_ctx* c, size_t bytes) {
+    reset();
+    ctx = c;
+    p = c->acquire(std::max<size_t>(bytes, 1));
+    return p != nullptr;
+  }
+  void reset() {
+    if (p) ctx->release(p);
+    p = nullptr;
+  }
+  void swap(PoolBlock& o) {
+    std::swap(ctx, o.ctx);
+    std::swap(p, o.p);
+  }
+  ~PoolBlock() { reset(); }
+};
+
+// unique ONVs with counts and amplitudes, in one pool block
+struct UniqueSet {
+  PoolBlock blk;
+  uint64_t* m = nullptr;
+  int64_t* c = nullptr;
+  double* l = nullptr;
+  int8_t* s = nullptr;
+  bool alloc(nqs_ctx* ctx, int64_t n) {
+    const size_t n8 = size_t(std::max<int64_t>(n, 1));
+    const size_t bm = n8 * 16, bc = n8 * 8, bl = n8 * 8, bs = (n8 + 255) / 256 * 256;
+    if (!blk.get(ctx, bm + bc + bl + bs)) return false;
+    char* q = static_cast<char*>(blk.p);
+    m = reinterpret_cast<uint64_t*>(q);
+    c = reinterpret_cast<int64_t*>(q + bm);
+    l = reinterpret_cast<double*>(q + bm + bc);
+    s = reinterpret_cast<int8_t*>(q + bm + bc + bl);
+    return true;
+  }
+};
+}  // namespace
+
 nqs_status nqs_sample(nqs_ctx* ctx, const nqs_ansatz* ans, int64_t n_draws, uint64_t seed, int64_t draw_base,
-                      int32_t precision, int64_t cap, uint64_t* samples, int64_t* counts, double* logabs,
-                      int8_t* sign, int64_t* n_unique, hipStream_t stream) {
-  if (!ctx || !ans || n_draws < 0 || draw_base < 0 || cap < 0 || !n_unique || (cap > 0 && (!samples || !counts)))
+                      int32_t precision, int64_t max_draws_per_pass, int64_t cap, uint64_t* samples, int64_t* counts,
+                      double* logabs, int8_t* sign, int64_t* n_unique, hipStream_t stream) {
+  if (!ctx || !ans || n_draws < 0 || draw_base < 0 || max_draws_per_pass < 0 || cap < 0 || !n_unique ||
+      (cap > 0 && (!samples || !counts)))
     return fail(NQS_EINVAL, "bad arguments");
+  if (n_draws > std::numeric_limits<int64_t>::max() - draw_base) return fail(NQS_EINVAL, "draw index overflow");
   if (!ans->bound) return fail(NQS_EINVAL, "parameters not bound");
   if (precision != NQS_F64 && precision != NQS_F32)
     return fail(NQS_EUNSUPPORTED, "sampling runs in FP64 or FP32");
-  if (n_draws >= (int64_t(1) << 31)) return fail(NQS_EUNSUPPORTED, "more than 2^31 - 1 draws in one call");
+  const int64_t chunk = max_draws_per_pass > 0 && max_draws_per_pass < n_draws ? max_draws_per_pass : n_draws;
+  constexpr int64_t kMaxSort = (int64_t(1) << 31) - 1;   // hipCUB item count
+  if (chunk > kMaxSort) return fail(NQS_EUNSUPPORTED, "more than 2^31 - 1 draws in one pass");
   DeviceGuard g(ctx->device);
   *n_unique = 0;
   if (n_draws == 0) return NQS_OK;
+  const bool two = 2 * ans->K > 64;
   Scratch S(ctx);
-  uint64_t* m = S.get<uint64_t>(size_t(n_draws) * 2);
-  double* lphi = S.get<double>(n_draws);
-  int8_t* sphi = S.get<int8_t>(n_draws);
-  UniqueScratch w{};
-  HIPCHK(unique_temp_bytes(n_draws, &w.temp_bytes));
-  w.temp = S.get<unsigned char>(w.temp_bytes);
-  w.key_a = S.get<uint64_t>(n_draws);
-  w.key_b = S.get<uint64_t>(n_draws);
-  w.ord_a = S.get<uint32_t>(n_draws);
-  w.ord_b = S.get<uint32_t>(n_draws);
-  w.flag = S.get<int32_t>(n_draws);
-  w.pos = S.get<int32_t>(n_draws);
-  w.start = S.get<int64_t>(n_draws);
+  uint64_t* m = S.get<uint64_t>(size_t(chunk) * 2);
+  double* lphi = S.get<double>(chunk);
+  int8_t* sphi = S.get<int8_t>(chunk);
   int64_t* nu = S.get<int64_t>(1);
   if (S.oom) return fail(NQS_ENOMEM, "workspace allocation failed");
-  SampleArgs SA;
-  SA.k0 = uint32_t(seed);
-  SA.k1 = uint32_t(seed >> 32);
-  SA.p0 = draw_base;
-  SA.out = m;
-  if (precision == NQS_F64)
-    HIPCHK(launch_sample_f64(ans->params(ans->fwd64()), n_draws, lphi, sphi, stream, SA));
-  else
-    HIPCHK(launch_sample_f32(ans->params(ans->fwd32()), n_draws, lphi, sphi, stream, SA));
-  HIPCHK(launch_unique(m, lphi, sphi, n_draws, 2 * ans->K > 64, w, cap, samples, counts, logabs, sign, nu, stream));
-  int64_t h = 0;
-  HIPCHK(hipMemcpyAsync(&h, nu, sizeof h, hipMemcpyDeviceToHost, stream));
-  HIPCHK(hipStreamSynchronize(stream));
-  *n_unique = h;
+  // draws run in passes of at most `chunk`; each pass is merged with the unique
+  // set of the passes before it (their counts as weights), so the workspace is
+  // bounded by the pass size plus the number of unique draws
+  UniqueSet set;
+  int64_t u = 0;
+  for (int64_t d0 = 0; d0 < n_draws; d0 += chunk) {
+    const int64_t ch = std::min(chunk, n_draws - d0);
+    const bool last = d0 + ch >= n_draws;
+    SampleArgs SA;
+    SA.k0 = uint32_t(seed);
+    SA.k1 = uint32_t(seed >> 32);
+    SA.p0 = draw_base + d0;
+    SA.out = m;
+    if (precision == NQS_F64)
+      HIPCHK(launch_sample_f64(ans->params(ans->fwd64()), ch, lphi, sphi, stream, SA));
+    else
+      HIPCHK(launch_sample_f32(ans->params(ans->fwd32()), ch, lphi, sphi, stream, SA));
+    const int64_t n = u + ch;
+    if (n > kMaxSort) return fail(NQS_EUNSUPPORTED, "more than 2^31 - 1 unique draws plus one pass");
+    Scratch T(ctx);
+    const uint64_t* im = m;
+    const double* il = lphi;
+    const int8_t* is = sphi;
+    int64_t* iw = nullptr;
+    if (u > 0) {
+      uint64_t* cm = T.get<uint64_t>(size_t(n) * 2);
+      double* cl = T.get<double>(n);
+      int8_t* cs = T.get<int8_t>(n);
+      iw = T.get<int64_t>(n);
+      if (T.oom) return fail(NQS_ENOMEM, "workspace allocation failed");
+      HIPCHK(hipMemcpyAsync(cm, set.m, size_t(u) * 16, hipMemcpyDeviceToDevice, stream));
+      HIPCHK(hipMemcpyAsync(cm + 2 * u, m, size_t(ch) * 16, hipMemcpyDeviceToDevice, stream));
+      HIPCHK(hipMemcpyAsync(cl, set.l, size_t(u) * 8, hipMemcpyDeviceToDevice, stream));
+      HIPCHK(hipMemcpyAsync(cl + u, lphi, size_t(ch) * 8, hipMemcpyDeviceToDevice, stream));
+      HIPCHK(hipMemcpyAsync(cs, set.s, size_t(u), hipMemcpyDeviceToDevice, stream));
+      HIPCHK(hipMemcpyAsync(cs + u, sphi, size_t(ch), hipMemcpyDeviceToDevice, stream));
+      HIPCHK(hipMemcpyAsync(iw, set.c, size_t(u) * 8, hipMemcpyDeviceToDevice, stream));
+      HIPCHK(launch_fill_i64(iw + u, ch, 1, stream));
+      im = cm;
+      il = cl;
+      is = cs;
+    }
+    UniqueScratch w{};
+    HIPCHK(unique_temp_bytes(n, &w.temp_bytes));
+    w.temp = T.get<unsigned char>(w.temp_bytes);
+    w.key_a = T.get<uint64_t>(n);
+    w.key_b = T.get<uint64_t>(n);
+    w.ord_a = T.get<uint32_t>(n);
+    w.ord_b = T.get<uint32_t>(n);
+    w.flag = T.get<int32_t>(n);
+    w.pos = T.get<int32_t>(n);
+    w.start = T.get<int64_t>(n);
+    w.wsum = iw ? T.get<int64_t>(n) : nullptr;
+    if (T.oom) return fail(NQS_ENOMEM, "workspace allocation failed");
+    if (last) {
+      HIPCHK(launch_unique(im, il, is, iw, n, two, w, cap, samples, counts, logabs, sign, nu, stream));
+      int64_t h = 0;
+      HIPCHK(hipMemcpyAsync(&h, nu, sizeof h, hipMemcpyDeviceToHost, stream));
+      HIPCHK(hipStreamSynchronize(stream));   // before this pass's buffers go back to the pool
+      *n_unique = h;
+    } else {
+      UniqueSet next;
+      if (!next.alloc(ctx, n)) return fail(NQS_ENOMEM, "workspace allocation failed");
+      HIPCHK(launch_unique(im, il, is, iw, n, two, w, n, next.m, next.c, next.l, next.s, nu, stream));
+      HIPCHK(hipMemcpyAsync(&u, nu, sizeof u, hipMemcpyDeviceToHost, stream));
+      HIPCHK(hipStreamSynchronize(stream));   // the old set and this pass's buffers are free after this
+      set.blk.swap(next.blk);
+      set.m = next.m;
+      set.c = next.c;
+      set.l = next.l;
+      set.s = next.s;
+    }
+  }
   return NQS_OK;
 }
 

@@ -1,10 +1,12 @@
 // Merging sampled ONVs into unique ONVs with counts: a stable LSD radix sort of
 // the two 64-bit words (low word, then high word when 2K > 64), head flags,
-// an exclusive scan of the flags and a scatter of the heads.  The sort and
-// the scan are the hipCUB device primitives; the output is in ascending
-// (high, low) order.
+// an exclusive scan of the flags and a scatter of the heads; with weights, a
+// unique ONV's count is the sum of its entries' weights (an inclusive scan of
+// the weights in sorted order).  The sorts and scans are the hipCUB device
+// primitives; the output is in ascending (high, low) order.
 #include "internal.h"
 #include <hipcub/hipcub.hpp>
+#include <algorithm>
 
 namespace nqs {
 namespace {
@@ -50,12 +52,26 @@ __global__ void k_scatter_heads(const uint64_t* __restrict__ m, const double* __
   if (us) us[u] = sphi[a];
 }
 
+// count of unique ONV u: the number of its entries, or with weights the sum of
+// their weights (difference of the inclusive prefix sums wsum in sorted order)
 __global__ void k_counts(int64_t N, const int64_t* __restrict__ start, const int64_t* __restrict__ nu, int64_t cap,
-                         int64_t* __restrict__ cnt) {
+                         const int64_t* __restrict__ wsum, int64_t* __restrict__ cnt) {
   const int64_t u = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   const int64_t n = *nu;
   if (u >= n || u >= cap) return;
-  cnt[u] = (u + 1 < n ? start[u + 1] : N) - start[u];
+  const int64_t a = start[u], b = u + 1 < n ? start[u + 1] : N;
+  cnt[u] = wsum ? wsum[b - 1] - (a > 0 ? wsum[a - 1] : 0) : b - a;
+}
+
+__global__ void k_gather_weights(int64_t N, const uint32_t* __restrict__ ord, const int64_t* __restrict__ wt,
+                                 int64_t* __restrict__ out) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < N) out[i] = wt[ord[i]];
+}
+
+__global__ void k_fill_i64(int64_t* __restrict__ p, int64_t n, int64_t v) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
 }
 
 inline unsigned blocks_for(int64_t n) { return unsigned((n + 255) / 256); }
@@ -69,13 +85,22 @@ hipError_t unique_temp_bytes(int64_t N, size_t* bytes) {
   if (e != hipSuccess) return e;
   e = hipcub::DeviceScan::ExclusiveSum(nullptr, b, (const int32_t*)nullptr, (int32_t*)nullptr, int(N));
   if (e != hipSuccess) return e;
-  *bytes = a > b ? a : b;
+  size_t c = 0;
+  e = hipcub::DeviceScan::InclusiveSum(nullptr, c, (const int64_t*)nullptr, (int64_t*)nullptr, int(N));
+  if (e != hipSuccess) return e;
+  *bytes = std::max(a, std::max(b, c));
   return hipSuccess;
 }
 
-hipError_t launch_unique(const uint64_t* m, const double* lphi, const int8_t* sphi, int64_t N, bool two_words,
-                         const UniqueScratch& w, int64_t cap, uint64_t* um, int64_t* ucnt, double* ul, int8_t* us,
-                         int64_t* nu, hipStream_t st) {
+hipError_t launch_fill_i64(int64_t* p, int64_t n, int64_t v, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_i64, dim3(blocks_for(n)), dim3(256), 0, st, p, n, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_unique(const uint64_t* m, const double* lphi, const int8_t* sphi, const int64_t* weights,
+                         int64_t N, bool two_words, const UniqueScratch& w, int64_t cap, uint64_t* um, int64_t* ucnt,
+                         double* ul, int8_t* us, int64_t* nu, hipStream_t st) {
   if (N <= 0) return hipMemsetAsync(nu, 0, sizeof(int64_t), st);
   if (N >= (int64_t(1) << 31)) return hipErrorInvalidValue;
   size_t tb = w.temp_bytes;
@@ -96,7 +121,14 @@ hipError_t launch_unique(const uint64_t* m, const double* lphi, const int8_t* sp
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_scatter_heads, dim3(blocks_for(N)), dim3(256), 0, st, m, lphi, sphi, N, ord, w.flag, w.pos,
                      cap, um, ul, us, w.start, nu);
-  hipLaunchKernelGGL(k_counts, dim3(blocks_for(N)), dim3(256), 0, st, N, w.start, nu, cap, ucnt);
+  if (weights) {
+    hipLaunchKernelGGL(k_gather_weights, dim3(blocks_for(N)), dim3(256), 0, st, N, ord, weights, w.wsum);
+    tb = w.temp_bytes;
+    e = hipcub::DeviceScan::InclusiveSum(w.temp, tb, w.wsum, w.wsum, int(N), st);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_counts, dim3(blocks_for(N)), dim3(256), 0, st, N, w.start, nu, cap,
+                     weights ? w.wsum : nullptr, ucnt);
   return hipGetLastError();
 }
 

@@ -87,8 +87,8 @@ def lib():
                            C.POINTER(ElocStats), _p]
     L.nqs_rows.argtypes = [_p, _p, _p, C.c_int64, C.POINTER(ElocOpts), C.c_int64, _p, _p, _p, _p, _p, _p,
                            C.POINTER(C.c_int64), _p]
-    L.nqs_sample.argtypes = [_p, _p, C.c_int64, C.c_uint64, C.c_int64, C.c_int32, C.c_int64, _p, _p, _p, _p,
-                             C.POINTER(C.c_int64), _p]
+    L.nqs_sample.argtypes = [_p, _p, C.c_int64, C.c_uint64, C.c_int64, C.c_int32, C.c_int64, C.c_int64, _p, _p,
+                             _p, _p, C.POINTER(C.c_int64), _p]
     L.nqs_eloc_workspace_bytes.argtypes = [_p, _p, C.c_int64, C.POINTER(ElocOpts), C.c_int64,
                                            C.POINTER(C.c_size_t)]
     _lib = L
@@ -245,7 +245,7 @@ class Ansatz:
         return grad
 
     def sample(self, n_draws: int, seed: int = 0, draw_base: int = 0, precision="f64",
-               cap: Optional[int] = None):
+               cap: Optional[int] = None, max_draws_per_pass: int = 0):
         """Exact autoregressive draws draw_base .. draw_base + n_draws - 1 from
         Phi^2 (counter-keyed: independent of how draws are split into calls),
         merged into unique ONVs; returns (samples [U, 2] int64 viewing the two
@@ -260,7 +260,8 @@ class Ansatz:
         nu = C.c_int64(0)
         pr = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
         check(lib().nqs_sample(self.ctx.h, self.h, n_draws, int(seed) & 0xFFFFFFFFFFFFFFFF, int(draw_base), pr,
-                               cap, _ptr(out), _ptr(cnt), _ptr(la), _ptr(sg), C.byref(nu), _p(_stream())))
+                               int(max_draws_per_pass), cap, _ptr(out), _ptr(cnt), _ptr(la), _ptr(sg), C.byref(nu),
+                               _p(_stream())))
         u = min(int(nu.value), cap)
         return out[:u], cnt[:u], la[:u], sg[:u], int(nu.value)
 

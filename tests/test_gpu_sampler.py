@@ -156,3 +156,29 @@ def test_samples_feed_eloc(nqs, ctx):
     assert np.array_equal(out["sign"].cpu().numpy().astype(np.int64), sg.cpu().numpy().astype(np.int64))
     assert np.isfinite(out["eloc"].cpu().numpy()).all()
     inst.close()
+
+
+def test_passes_merge_to_the_single_pass(nqs, ctx):
+    """Draws run in passes merged with the unique set so far: the result is
+    the single pass's, for pass sizes that do and do not divide the draws."""
+    w, ans = setup(nqs, ctx, "c2")
+    one = host(ans.sample(4096, seed=31, draw_base=11, precision="f64"))
+    for per in (700, 1024, 4095):
+        many = host(ans.sample(4096, seed=31, draw_base=11, precision="f64", max_draws_per_pass=per))
+        assert many[4] == one[4]
+        for a, b in zip(one[:4], many[:4]):
+            assert np.array_equal(a, b), per
+
+
+def test_passes_bound_the_workspace(nqs, ctx):
+    """400k draws over the K=6 sector (at most 400 unique): the pool's peak
+    with 20k-draw passes stays far below the single pass's (the sort's
+    temporary storage has a fixed part of a few MB)."""
+    w, ans = setup(nqs, ctx, "c1")
+    ctx.pool_peak(reset=True)
+    one = host(ans.sample(400_000, seed=5, precision="f32"))
+    peak_one = ctx.pool_peak(reset=True)
+    many = host(ans.sample(400_000, seed=5, precision="f32", max_draws_per_pass=20_000))
+    peak_many = ctx.pool_peak(reset=True)
+    assert np.array_equal(one[0], many[0]) and np.array_equal(one[1], many[1])
+    assert peak_many * 5 < peak_one, (peak_many, peak_one)
