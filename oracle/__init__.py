@@ -44,16 +44,16 @@ def _load():
     lib.or_hdiag.argtypes = [_i, _i, _i, _p, _p, _d, _p, _i64, _p]
     lib.or_connected.argtypes = [_i, _i, _i, _p, _p, _d, _p, _p, _p, _i64]
     lib.or_connected.restype = _i64
-    lib.or_n_params.argtypes = [_i, _i, _p, _i]
+    lib.or_n_params.argtypes = [_i, _i, _p, _i, _i]
     lib.or_n_params.restype = _i64
-    lib.or_amplitudes.argtypes = [_i, _i, _i, _i, _p, _p, _i, _p, _p, _i64, _p, _p, _p, _p, _i]
+    lib.or_amplitudes.argtypes = [_i, _i, _i, _i, _p, _p, _i, _i, _p, _p, _i64, _p, _p, _p, _p, _i]
     lib.or_sample.argtypes = [_i, _i, _i, _i, _p, _p, _p, _p, _i64, _p]
     lib.or_sample_unique.argtypes = [_i, _i, _i, _i, _p, _p, _p, _u64, _i64, _i64, _i64, _p, _p]
     lib.or_sample_unique.restype = _i64
-    lib.or_grad.argtypes = [_i, _i, _i, _i, _p, _p, _i, _p, _p, _i64, _p, _p, _i]
-    lib.or_eloc.argtypes = [_i, _i, _i, _p, _p, _d, _i, _p, _p, _i, _p, _p, _i64, _d, _i, _u64,
+    lib.or_grad.argtypes = [_i, _i, _i, _i, _p, _p, _i, _i, _p, _p, _i64, _p, _p, _i]
+    lib.or_eloc.argtypes = [_i, _i, _i, _p, _p, _d, _i, _p, _p, _i, _i, _p, _p, _i64, _d, _i, _u64,
                             _u64, _i64, _p, _p, _p, _p, _p, _p, _p, _p, _i]
-    lib.or_eloc_detail.argtypes = [_i, _i, _i, _p, _p, _d, _i, _p, _p, _i, _p, _p, _i64, _d, _i,
+    lib.or_eloc_detail.argtypes = [_i, _i, _i, _p, _p, _d, _i, _p, _p, _i, _i, _p, _p, _i64, _d, _i,
                                    _u64, _u64, _p, _i64, _p, _p, _p, _p]
     lib.or_eloc_table.argtypes = [_i, _i, _i, _p, _p, _d, _p, _p, _i64, _p, _i64, _d, _i, _u64,
                                   _u64, _p, _i]
@@ -119,20 +119,21 @@ def connected(K, na, nb, h, eri, sample, e_core=0.0):
     return m, H
 
 
-def n_params(K, chi, parent_ptr, n_hidden) -> int:
+def n_params(K, chi, parent_ptr, n_hidden, ising: bool = False) -> int:
     pp = _i32(parent_ptr)
-    return int(_load().or_n_params(K, chi, _ptr(pp), n_hidden))
+    return int(_load().or_n_params(K, chi, _ptr(pp), n_hidden, int(bool(ising))))
 
 
 def amplitudes(K, chi, na, nb, parent_ptr, parent_idx, n_hidden, params, samples,
-               nthreads: int = 0) -> Dict[str, np.ndarray]:
-    """log|Phi|, sign Phi, log|f|, sign f for every sample."""
+               nthreads: int = 0, ising: bool = False) -> Dict[str, np.ndarray]:
+    """log|Phi|, sign Phi, log|f|, sign f for every sample (f: cos-RBM, or
+    Ising-RBM when ising)."""
     pp, pi, prm = _i32(parent_ptr), _i32(parent_idx), _f64(params)
     s = _u64a(samples).reshape(-1, 2)
     N = len(s)
     lphi, lf = np.zeros(N), np.zeros(N)
     sphi, sf = np.zeros(N, dtype=np.int32), np.zeros(N, dtype=np.int32)
-    _load().or_amplitudes(K, chi, na, nb, _ptr(pp), _ptr(pi), n_hidden, _ptr(prm), _ptr(s), N,
+    _load().or_amplitudes(K, chi, na, nb, _ptr(pp), _ptr(pi), n_hidden, int(bool(ising)), _ptr(prm), _ptr(s), N,
                           _ptr(lphi), _ptr(sphi), _ptr(lf), _ptr(sf), nthreads)
     return dict(lphi=lphi, sphi=sphi, lf=lf, sf=sf, logabs=lphi + lf, sign=sphi * sf)
 
@@ -162,20 +163,20 @@ def sample_unique(K, chi, na, nb, parent_ptr, parent_idx, params, seed: int, n_d
 
 
 def grad(K, chi, na, nb, parent_ptr, parent_idx, n_hidden, params, samples, g,
-         nthreads: int = 0) -> np.ndarray:
+         nthreads: int = 0, ising: bool = False) -> np.ndarray:
     """sum_n g_n d ln|Psi(n)| / d theta over the packed parameter vector."""
     pp, pi, prm = _i32(parent_ptr), _i32(parent_idx), _f64(params)
     s = _u64a(samples).reshape(-1, 2)
     gg = _f64(g)
     out = np.zeros(prm.size)
-    _load().or_grad(K, chi, na, nb, _ptr(pp), _ptr(pi), n_hidden, _ptr(prm), _ptr(s), len(s),
+    _load().or_grad(K, chi, na, nb, _ptr(pp), _ptr(pi), n_hidden, int(bool(ising)), _ptr(prm), _ptr(s), len(s),
                     _ptr(gg), _ptr(out), nthreads)
     return out
 
 
 def eloc(K, na, nb, h, eri, chi, parent_ptr, parent_idx, n_hidden, params, samples,
          eps=0.0, n_eps=0, seed=0, stream=0, e_core=0.0, nthreads: int = 0,
-         sample_base: int = 0) -> Dict[str, np.ndarray]:
+         sample_base: int = 0, ising: bool = False) -> Dict[str, np.ndarray]:
     """Semi-stochastic local energies and the reweighted numerators; the draws
     of sample i use Philox counter word 0 = sample_base + i."""
     h, eri = _f64(h), _f64(eri)
@@ -186,7 +187,7 @@ def eloc(K, na, nb, h, eri, chi, parent_ptr, parent_idx, n_hidden, params, sampl
     sign = np.zeros(N, dtype=np.int8)
     cnt = {k: np.zeros(N, dtype=np.int64) for k in ("n_det", "n_rem", "n_uniq")}
     rc = _load().or_eloc(K, na, nb, _ptr(h), _ptr(eri), e_core, chi, _ptr(pp), _ptr(pi), n_hidden,
-                         _ptr(prm), _ptr(s), N, eps, n_eps, seed, stream, sample_base, _ptr(out["eloc"]),
+                         int(bool(ising)), _ptr(prm), _ptr(s), N, eps, n_eps, seed, stream, sample_base, _ptr(out["eloc"]),
                          _ptr(out["etnum"]), _ptr(out["logabs"]), _ptr(sign), _ptr(out["fsq"]),
                          _ptr(cnt["n_det"]), _ptr(cnt["n_rem"]), _ptr(cnt["n_uniq"]), nthreads)
     if rc != 0:
@@ -197,7 +198,7 @@ def eloc(K, na, nb, h, eri, chi, parent_ptr, parent_idx, n_hidden, params, sampl
 
 
 def eloc_detail(K, na, nb, h, eri, chi, parent_ptr, parent_idx, n_hidden, params, sample,
-                sample_idx, eps, n_eps, seed=0, stream=0, e_core=0.0):
+                sample_idx, eps, n_eps, seed=0, stream=0, e_core=0.0, ising: bool = False):
     """One sample: deterministic ranks, drawn ranks in draw order, Q, E_loc."""
     h, eri = _f64(h), _f64(eri)
     pp, pi, prm = _i32(parent_ptr), _i32(parent_idx), _f64(params)
@@ -209,7 +210,7 @@ def eloc_detail(K, na, nb, h, eri, chi, parent_ptr, parent_idx, n_hidden, params
     Q = np.zeros(1, dtype=np.uint64)
     e = np.zeros(1)
     rc = _load().or_eloc_detail(K, na, nb, _ptr(h), _ptr(eri), e_core, chi, _ptr(pp), _ptr(pi),
-                                n_hidden, _ptr(prm), _ptr(s), sample_idx, eps, n_eps, seed, stream,
+                                n_hidden, int(bool(ising)), _ptr(prm), _ptr(s), sample_idx, eps, n_eps, seed, stream,
                                 _ptr(det), cap, _ptr(nd), _ptr(draws), _ptr(Q), _ptr(e))
     if rc != 0:
         raise ValueError("sample outside the (n_alpha, n_beta) sector")

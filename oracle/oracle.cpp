@@ -21,7 +21,10 @@
 //     w^T h + c (Sec. 2.1).
 //   * Particle-number / S_z masking of the conditionals, Sec. 3 Eqs. (23)-(24).
 //   * Correlator factorisation Psi = f Phi with cos-RBM f, Sec. 2.3
-//     Eqs. (14)-(15); reweighted local energy Eq. (18).
+//     Eqs. (14)-(15), or the Ising-RBM f of Eq. (16) (the cos-RBM argument plus
+//     half the quadratic form of a full N_v x N_v matrix per hidden unit, over
+//     all ordered pairs, the diagonal included); reweighted local energy
+//     Eq. (18).
 //   * Gradient of ln|Psi| used by Eqs. (7) and (19).
 //
 // Readings of points the paper leaves open (each one listed in the design
@@ -247,18 +250,19 @@ void philox4x32_10(const uint32_t ctr_in[4], const uint32_t key_in[2], uint32_t 
 // --------------------------------------------------------------------------
 struct Ansatz {
   int K, chi, na, nb, nh;
+  bool ising;
   const int* pptr;
   const int* pidx;
   const double* prm;
   std::vector<size_t> offM;                 // per edge: [4][chi][chi]
   std::vector<size_t> offV, offEta, offW, offC;
-  size_t offB = 0, offWc = 0, total = 0;
+  size_t offB = 0, offWc = 0, offW2 = 0, total = 0;
 };
 
 Ansatz make_ansatz(int K, int chi, int na, int nb, const int* pptr, const int* pidx,
-                   int nh, const double* prm) {
+                   int nh, int ising, const double* prm) {
   Ansatz A;
-  A.K = K; A.chi = chi; A.na = na; A.nb = nb; A.nh = nh;
+  A.K = K; A.chi = chi; A.na = na; A.nb = nb; A.nh = nh; A.ising = nh > 0 && ising != 0;
   A.pptr = pptr; A.pidx = pidx; A.prm = prm;
   size_t o = 0;
   A.offM.resize(pptr[K]);
@@ -272,6 +276,8 @@ Ansatz make_ansatz(int K, int chi, int na, int nb, const int* pptr, const int* p
   }
   A.offB = o; o += nh;
   A.offWc = o; o += size_t(nh) * 2 * K;
+  A.offW2 = o;
+  if (A.ising) o += size_t(nh) * 4 * K * K;   // [nh][2K][2K]
   A.total = o;
   return A;
 }
@@ -355,15 +361,31 @@ bool phi_eval(const Ansatz& A, const Det& n, double* logabs, int* sgn, Trace* tr
   return true;
 }
 
-// cos-RBM: theta_k = b_k + sum_P W_kP x_P, f = prod_k cos(theta_k)
+// cos-RBM: theta_k = b_k + sum_P W_kP x_P; Ising-RBM adds
+// (1/2) sum_{P,Q} W2_kPQ x_P x_Q; f = prod_k cos(theta_k)
+double corr_theta(const Ansatz& A, const Det& n, int k) {
+  const int nv = 2 * A.K;
+  double th = A.prm[A.offB + k];
+  for (int P = 0; P < nv; ++P)
+    if (n.x[P]) th += A.prm[A.offWc + size_t(k) * nv + P];
+  if (A.ising) {
+    // x_P x_Q is nonzero only for occupied P and Q
+    double q = 0.0;
+    for (int P = 0; P < nv; ++P) {
+      if (!n.x[P]) continue;
+      for (int Q = 0; Q < nv; ++Q)
+        if (n.x[Q]) q += A.prm[A.offW2 + (size_t(k) * nv + P) * nv + Q];
+    }
+    th += 0.5 * q;
+  }
+  return th;
+}
+
 void corr_eval(const Ansatz& A, const Det& n, double* logabs, int* sgn) {
   double la = 0.0;
   int sg = 1;
-  const int nv = 2 * A.K;
   for (int k = 0; k < A.nh; ++k) {
-    double th = A.prm[A.offB + k];
-    for (int P = 0; P < nv; ++P)
-      if (n.x[P]) th += A.prm[A.offWc + size_t(k) * nv + P];
+    const double th = corr_theta(A, n, k);
     const double c = std::cos(th);
     la += std::log(std::fabs(c));
     if (c < 0) sg = -sg;
@@ -443,13 +465,16 @@ void grad_accumulate(const Ansatz& A, const Det& n, double g, double* grad) {
   if (A.nh) {
     const int nv = 2 * K;
     for (int k = 0; k < A.nh; ++k) {
-      double th = A.prm[A.offB + k];
-      for (int P = 0; P < nv; ++P)
-        if (n.x[P]) th += A.prm[A.offWc + size_t(k) * nv + P];
-      const double dth = -g * std::tan(th);
+      const double dth = -g * std::tan(corr_theta(A, n, k));
       grad[A.offB + k] += dth;
       for (int P = 0; P < nv; ++P)
         if (n.x[P]) grad[A.offWc + size_t(k) * nv + P] += dth;
+      if (A.ising)
+        for (int P = 0; P < nv; ++P) {
+          if (!n.x[P]) continue;
+          for (int Q = 0; Q < nv; ++Q)
+            if (n.x[Q]) grad[A.offW2 + (size_t(k) * nv + P) * nv + Q] += 0.5 * dth;
+        }
     }
   }
 }
@@ -597,16 +622,16 @@ int64_t or_connected(int K, int na, int nb, const double* h, const double* eri, 
   return int64_t(c.size());
 }
 
-int64_t or_n_params(int K, int chi, const int* pptr, int nh) {
-  Ansatz A = make_ansatz(K, chi, 0, 0, pptr, nullptr, nh, nullptr);
+int64_t or_n_params(int K, int chi, const int* pptr, int nh, int ising) {
+  Ansatz A = make_ansatz(K, chi, 0, 0, pptr, nullptr, nh, ising, nullptr);
   return int64_t(A.total);
 }
 
 // log|Phi|, sign Phi, log|f|, sign f for N samples
-int or_amplitudes(int K, int chi, int na, int nb, const int* pptr, const int* pidx, int nh,
+int or_amplitudes(int K, int chi, int na, int nb, const int* pptr, const int* pidx, int nh, int ising,
                   const double* prm, const uint64_t* samples, int64_t N, double* lphi,
                   int* sphi, double* lf, int* sf, int nthreads) {
-  Ansatz A = make_ansatz(K, chi, na, nb, pptr, pidx, nh, prm);
+  Ansatz A = make_ansatz(K, chi, na, nb, pptr, pidx, nh, ising, prm);
 #pragma omp parallel for schedule(dynamic, 16) num_threads(nthreads_or_default(nthreads))
   for (int64_t i = 0; i < N; ++i) {
     Det d = det_from_words(K, samples + 2 * i);
@@ -631,7 +656,7 @@ double sampler_uniform(uint64_t seed, uint64_t t, int i) {
 // exact autoregressive draws from Phi^2 using the caller's uniforms u[N][K]
 int or_sample(int K, int chi, int na, int nb, const int* pptr, const int* pidx,
               const double* prm, const double* u, int64_t N, uint64_t* out) {
-  Ansatz A = make_ansatz(K, chi, na, nb, pptr, pidx, 0, prm);
+  Ansatz A = make_ansatz(K, chi, na, nb, pptr, pidx, 0, 0, prm);
   for (int64_t t = 0; t < N; ++t) {
     Det d;
     d.n = 2 * K;
@@ -693,10 +718,10 @@ int64_t or_sample_unique(int K, int chi, int na, int nb, const int* pptr, const 
 }
 
 // sum_n g_n d ln|Psi(n)| / d theta, accumulated into grad (length n_params)
-int or_grad(int K, int chi, int na, int nb, const int* pptr, const int* pidx, int nh,
+int or_grad(int K, int chi, int na, int nb, const int* pptr, const int* pidx, int nh, int ising,
             const double* prm, const uint64_t* samples, int64_t N, const double* g,
             double* grad, int nthreads) {
-  Ansatz A = make_ansatz(K, chi, na, nb, pptr, pidx, nh, prm);
+  Ansatz A = make_ansatz(K, chi, na, nb, pptr, pidx, nh, ising, prm);
   const int nt = nthreads_or_default(nthreads);
   std::vector<std::vector<double>> part(nt, std::vector<double>(A.total, 0.0));
 #pragma omp parallel for schedule(static) num_threads(nt)
@@ -713,13 +738,13 @@ int or_grad(int K, int chi, int na, int nb, const int* pptr, const int* pidx, in
 // draw counter of sample i is sample_base + i.  Optional per-sample counters
 // n_det / n_rem / n_uniq (nullable).
 int or_eloc(int K, int na, int nb, const double* h, const double* eri, double ecore,
-            int chi, const int* pptr, const int* pidx, int nh, const double* prm,
+            int chi, const int* pptr, const int* pidx, int nh, int ising, const double* prm,
             const uint64_t* samples, int64_t N, double eps, int n_eps, uint64_t seed,
             uint64_t stream, int64_t sample_base, double* eloc, double* etnum, double* logabs,
             int8_t* sign, double* fsq, int64_t* n_det, int64_t* n_rem, int64_t* n_uniq,
             int nthreads) {
   Ham H{K, h, eri, ecore};
-  Ansatz A = make_ansatz(K, chi, na, nb, pptr, pidx, nh, prm);
+  Ansatz A = make_ansatz(K, chi, na, nb, pptr, pidx, nh, ising, prm);
   for (int64_t i = 0; i < N; ++i) {
     Det d = det_from_words(K, samples + 2 * i);
     if (!count_ok(d, K, na, nb)) return -1;
@@ -740,12 +765,12 @@ int or_eloc(int K, int na, int nb, const double* h, const double* eri, double ec
 
 // one sample in detail: deterministic ranks, drawn ranks (in draw order), Q
 int or_eloc_detail(int K, int na, int nb, const double* h, const double* eri, double ecore,
-                   int chi, const int* pptr, const int* pidx, int nh, const double* prm,
+                   int chi, const int* pptr, const int* pidx, int nh, int ising, const double* prm,
                    const uint64_t* sample, int64_t sample_idx, double eps, int n_eps,
                    uint64_t seed, uint64_t stream, int64_t* det_ranks, int64_t det_cap,
                    int64_t* n_det_out, int64_t* draw_ranks, uint64_t* Q_out, double* eloc_out) {
   Ham H{K, h, eri, ecore};
-  Ansatz A = make_ansatz(K, chi, na, nb, pptr, pidx, nh, prm);
+  Ansatz A = make_ansatz(K, chi, na, nb, pptr, pidx, nh, ising, prm);
   Det d = det_from_words(K, sample);
   if (!count_ok(d, K, na, nb)) return -1;
   auto amp = [&](const Det& x) { return amp_eval(A, x); };

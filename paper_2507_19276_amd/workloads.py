@@ -30,7 +30,8 @@ Conventions (shared by every consumer):
   ascending, for local state s = 0..3, the chi x chi matrix M_ij^s row-major
   (h_out[u] = sum_k M[u, k] h_in[k]); then v_i^s (4 x chi), eta_i (chi),
   w_i (chi), c_i (1).  After all sites the cos-RBM correlator: b (N_h) then
-  W (N_h x 2K, row-major, column P = spin orbital P).
+  W (N_h x 2K, row-major, column P = spin orbital P); with the Ising-RBM
+  correlator, then W2 (N_h x 2K x 2K, row-major: W2[k, P, Q]).
 """
 from __future__ import annotations
 
@@ -173,16 +174,18 @@ def lattice_integrals(dims: Tuple[int, int, int], seed: int, ell: float = 2.0) -
 # ansatz parameters
 # ---------------------------------------------------------------------------
 
-def n_params(K: int, chi: int, parent_ptr: np.ndarray, n_hidden: int) -> int:
+def n_params(K: int, chi: int, parent_ptr: np.ndarray, n_hidden: int, ising: bool = False) -> int:
     sum_d = int(parent_ptr[-1])
-    return sum_d * 4 * chi * chi + K * (4 * chi + chi + chi + 1) + (n_hidden * (2 * K + 1) if n_hidden else 0)
+    corr = n_hidden * (2 * K + 1) + (n_hidden * 4 * K * K if ising else 0)
+    return sum_d * 4 * chi * chi + K * (4 * chi + chi + chi + 1) + (corr if n_hidden else 0)
 
 
 def ansatz_params(K: int, chi: int, parent_ptr: np.ndarray, parent_idx: np.ndarray,
-                  n_hidden: int, seed: int, corr_scale: float = 0.1) -> np.ndarray:
+                  n_hidden: int, seed: int, corr_scale: float = 0.1, ising: bool = False) -> np.ndarray:
     """Random-init parameters in the packed layout (module docstring):
     M ~ N(0, var 1/(chi*max(d_i,1))), v ~ N(0,1), eta ~ U[0.5,1.5], w, c ~ N(0,1),
-    correlator b, W ~ N(0, corr_scale^2)."""
+    correlator b, W ~ N(0, corr_scale^2), Ising W2 ~ N(0, corr_scale^2 / K) (its
+    ~K^2 occupied pairs then spread theta about as much as W's ~K terms)."""
     rng = np.random.default_rng(seed)
     out: List[np.ndarray] = []
     for i in range(K):
@@ -197,8 +200,10 @@ def ansatz_params(K: int, chi: int, parent_ptr: np.ndarray, parent_idx: np.ndarr
     if n_hidden:
         out.append(rng.standard_normal(n_hidden) * corr_scale)            # b
         out.append(rng.standard_normal(n_hidden * 2 * K) * corr_scale)    # W
+        if ising:
+            out.append(rng.standard_normal(n_hidden * 4 * K * K) * (corr_scale / math.sqrt(K)))   # W2
     p = np.concatenate(out).astype(np.float64)
-    assert p.size == n_params(K, chi, parent_ptr, n_hidden)
+    assert p.size == n_params(K, chi, parent_ptr, n_hidden, ising)
     return p
 
 
@@ -284,6 +289,7 @@ class Workload:
     n_eps: int
     seed: int
     precision: str
+    ising: bool = False
 
     @property
     def n_samples(self) -> int:
@@ -312,6 +318,9 @@ def make_workload(name: str, n_samples: Optional[int] = None, seed_offset: int =
         eps=1e-2, N_eps=1000
     c4b K=18 on 3x3x2, 9a+9b, lattice integrals, lattice graph chi=64,
         8192 samples, eps=1e-2, N_eps=100
+    c1i c1 with an Ising-RBM correlator, N_h = 2 N_v = 24
+    c2i c2 with an Ising-RBM correlator, N_h = 2 N_v = 80 (alpha = 2, as in
+        Sec. 4), 4096 unique samples
     """
     base = SEED_BASE + 1000 * seed_offset
     spec = {
@@ -325,7 +334,12 @@ def make_workload(name: str, n_samples: Optional[int] = None, seed_offset: int =
                     eps=1e-2, neps=1000, prec="f32", s=4),
         "c4b": dict(K=18, ne=(9, 9), integ="lattice", graph="lattice332", chi=64, nh=0, N=8192,
                     uniq=True, eps=1e-2, neps=100, prec="f32", s=5),
+        "c1i": dict(K=6, ne=(3, 3), integ="chain", graph="chain", chi=4, nh=24, N=256, uniq=False,
+                    eps=0.0, neps=0, prec="f64", s=6, ising=True),
+        "c2i": dict(K=20, ne=(10, 10), integ="chain", graph="chain", chi=16, nh=80, N=4096, uniq=True,
+                    eps=1e-3, neps=64, prec="f32", s=7, ising=True),
     }[name]
+    ising = spec.get("ising", False)
     K = spec["K"]
     seed = base + 100 * spec["s"]
     if spec["integ"] == "chain":
@@ -335,14 +349,14 @@ def make_workload(name: str, n_samples: Optional[int] = None, seed_offset: int =
     else:
         h, eri = lattice_integrals((3, 3, 2), seed + 1)
     pp, pi = _graph(spec["graph"], K)
-    params = ansatz_params(K, spec["chi"], pp, pi, spec["nh"], seed + 2)
+    params = ansatz_params(K, spec["chi"], pp, pi, spec["nh"], seed + 2, ising=ising)
     N = spec["N"] if n_samples is None else n_samples
     na, nb = spec["ne"]
     samples = random_onvs(K, na, nb, N, seed + 3, unique=spec["uniq"])
     return Workload(name=name, K=K, n_alpha=na, n_beta=nb, h=h, eri=eri, e_core=0.0,
                     chi=spec["chi"], parent_ptr=pp, parent_idx=pi, n_hidden=spec["nh"],
                     params=params, samples=samples, eps=spec["eps"], n_eps=spec["neps"],
-                    seed=seed + 4, precision=spec["prec"])
+                    seed=seed + 4, precision=spec["prec"], ising=ising)
 
 
 def serving_instances(seed_offset: int = 0) -> List[Dict]:
