@@ -150,14 +150,25 @@ int64_t nqs_instance_n_conn(const nqs_instance* inst);
 nqs_status nqs_connected(nqs_ctx* ctx, const nqs_instance* inst, const uint64_t* samples, int64_t N,
                          uint64_t* m_out, double* h_out, double* hdiag_out, hipStream_t stream);
 
-/* ---- ansatz: BDG-RNN / MPS-RNN (Sec. 2.1-2.2) x cos-RBM (Sec. 2.3) ---- */
+/* ---- ansatz: BDG-RNN / MPS-RNN (Sec. 2.1-2.2) x RBM correlator (Sec. 2.3) */
+
+/* Correlators of Sec. 2.3: f(n) = prod_k cos(theta_k(n)) with
+ * theta_k = b_k + sum_P W_kP x_P (cos-RBM, Eq. (15)), or with the Ising-RBM
+ * term (1/2) sum_{P,Q} W2_kPQ x_P x_Q added (Eq. (16), a full 2K x 2K matrix
+ * per hidden unit, all ordered pairs and the diagonal). */
+#define NQS_CORR_COS_RBM 0
+#define NQS_CORR_ISING_RBM 1
 
 /* Describe the ansatz: K sites, electron counts of the sector (they define the
- * mask of Sec. 3), bond dimension chi (1..64), parent CSR (host arrays), and
- * n_hidden cos-RBM units (0 = no correlator).  EINVAL for a malformed graph. */
+ * mask of Sec. 3), bond dimension chi (1..64), parent CSR (host arrays),
+ * n_hidden correlator units (0 = no correlator) and the correlator kind.
+ * Packed parameters: the BDG-RNN block, then b (n_hidden), W (n_hidden x 2K),
+ * and for the Ising-RBM W2 (n_hidden x 2K x 2K, row-major).  EINVAL for a
+ * malformed graph or an unknown correlator.  The Ising-RBM local energy keeps
+ * a table of N x 2K x n_hidden doubles (8 N 2K n_hidden bytes of workspace). */
 nqs_status nqs_ansatz_create(nqs_ctx* ctx, int K, int n_alpha, int n_beta, int chi,
                              const int32_t* parent_ptr, const int32_t* parent_idx, int n_hidden,
-                             nqs_ansatz** out);
+                             int32_t correlator, nqs_ansatz** out);
 nqs_status nqs_ansatz_destroy(nqs_ansatz* ans);
 /* Length of the packed parameter vector. */
 int64_t nqs_ansatz_n_params(const nqs_ansatz* ans);

@@ -303,6 +303,33 @@ __global__ void k_corr_grad(CorrParams C, const uint64_t* m, int64_t R, int rows
   else out[offW + int64_t(k) * nv + P] = acc;
 }
 
+// Ising-RBM: dth = -cot tan(theta) from theta of the rows (written in place)
+__global__ void k_dth_from_theta(int64_t R, int nh, const double* cot, double* dth) {
+  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= R * nh) return;
+  dth[t] = -cot[t / nh] * tan(dth[t]);
+}
+
+// Ising-RBM quadratic couplings: d theta_k / d W2_kPQ = x_P x_Q / 2; block
+// (split, k, P), thread Q
+__global__ void k_ising_grad_W2(CorrParams C, const uint64_t* m, int64_t R, int rows_per_split,
+                                const double* dth, int64_t offW2, double* gpart, int64_t n_params) {
+  const int nv = 2 * C.K, nh = C.nh;
+  const int64_t b = blockIdx.x;
+  const int split = int(b / (int64_t(nh) * nv));
+  const int k = int((b / nv) % nh), P = int(b % nv);
+  const int Q = threadIdx.x;
+  if (Q >= nv) return;
+  const int64_t r0 = int64_t(split) * rows_per_split;
+  const int64_t r1 = r0 + rows_per_split < R ? r0 + rows_per_split : R;
+  double acc = 0.0;
+  for (int64_t r = r0; r < r1; ++r) {
+    const uint64_t lo = m[2 * r], hi = m[2 * r + 1];
+    if (bit_at(lo, hi, P) && bit_at(lo, hi, Q)) acc += dth[r * nh + k];
+  }
+  gpart[size_t(split) * n_params + offW2 + (int64_t(k) * nv + P) * nv + Q] = 0.5 * acc;
+}
+
 // grad[p] += sum_split gpart[split][p], splits in ascending order
 __global__ void k_sum_parts(int64_t n_params, int nsplit, const double* gpart, double* grad) {
   const int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -375,11 +402,23 @@ hipError_t launch_bwd_sweep_f32(const AdjParams<float>& P, const uint64_t* m, in
 
 hipError_t launch_corr_backward(const CorrParams& C, const uint64_t* m, int64_t R, const double* cot,
                                 double* dth, int rows_per_split, int nsplit, int64_t offB, int64_t offW,
-                                double* gpart, int64_t n_params, hipStream_t st) {
+                                int64_t offW2, double* gpart, int64_t n_params, hipStream_t st) {
   if (C.nh <= 0 || R <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_corr_dtheta, dim3(grid_for(R * C.nh, 256)), dim3(256), 0, st, C, m, R, cot, dth);
-  hipError_t e = hipGetLastError();
+  hipError_t e;
+  if (C.ising) {
+    if ((e = launch_corr_theta(C, m, R, dth, nullptr, st)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_dth_from_theta, dim3(grid_for(R * C.nh, 256)), dim3(256), 0, st, R, C.nh, cot, dth);
+  } else {
+    hipLaunchKernelGGL(k_corr_dtheta, dim3(grid_for(R * C.nh, 256)), dim3(256), 0, st, C, m, R, cot, dth);
+  }
+  e = hipGetLastError();
   if (e != hipSuccess) return e;
+  if (C.ising) {
+    const int nv = 2 * C.K;
+    hipLaunchKernelGGL(k_ising_grad_W2, dim3(unsigned(int64_t(nsplit) * C.nh * nv)), dim3((nv + 63) / 64 * 64),
+                       0, st, C, m, R, rows_per_split, dth, offW2, gpart, n_params);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
   const int threads = ((2 * C.K + 1 + 63) / 64) * 64;
   hipLaunchKernelGGL(k_corr_grad, dim3(unsigned(nsplit * C.nh)), dim3(threads), 0, st, C, m, R, rows_per_split,
                      dth, offB, offW, gpart, n_params);

@@ -1,5 +1,6 @@
 // Energy side of the local energy on gfx950 (arXiv:2507.19276):
-//   * the cos-RBM correlator (Sec. 2.3, Eq. (15));
+//   * the cos-RBM correlator (Sec. 2.3, Eq. (15)) and the Ising-RBM
+//     correlator (Eq. (16));
 //   * the per-sample local-energy reduction (Eqs. (6), (18), (22)) and the
 //     batch sums of Sec. 2.3.
 #include "internal.h"
@@ -96,13 +97,149 @@ __global__ void k_corr_direct(CorrParams C, const uint64_t* m, int64_t R, double
 }
 
 // ---------------------------------------------------------------------------
-// reductions
+// Ising-RBM correlator: theta_k = b_k + sum_P W_kP x_P + (1/2) x^T W2_k x.
+// Only S_k = (W2_k + W2_k^T) / 2 enters.  S is kept as [P][Q][k] and W^T as
+// [P][k]: a wavefront with one hidden unit per lane reads them coalesced.
+//
+// A row m of sample n changes the occupations by delta (at most four spin
+// orbitals, +1 created, -1 annihilated), so
+//   theta_k(m) = theta_k(n) + sum_a [delta_a (W_kPa + G_kPa(n)) + S_kPaPa / 2]
+//                + sum_{a<b} delta_a delta_b S_kPaPb,   G_k(n) = S_k x(n).
+// An orbital is created in m only if empty in n and annihilated only if
+// occupied, so delta_a = 1 - 2 x_Pa(n) is fixed by (n, P): the first sum reads
+// one per-sample table E[n][P][k] = (1 - 2 x_P) (W_kP + G_kP) + S_kPP / 2.
 // ---------------------------------------------------------------------------
+
+template <typename F>
+__device__ inline void for_each_bit(uint64_t lo, uint64_t hi, F f) {
+  for (uint64_t x = lo; x; x &= x - 1) f(__ffsll((unsigned long long)x) - 1);
+  for (uint64_t x = hi; x; x &= x - 1) f(64 + __ffsll((unsigned long long)x) - 1);
+}
+
+__device__ inline double ising_theta(const CorrParams& C, uint64_t lo, uint64_t hi, int k) {
+  const int nv = 2 * C.K, nh = C.nh;
+  double lin = 0.0, quad = 0.0;
+  for_each_bit(lo, hi, [&](int P) {
+    lin += C.W1t[size_t(P) * nh + k];
+    double row = 0.0;
+    for_each_bit(lo, hi, [&](int Q) { row += C.S[(size_t(P) * nv + Q) * nh + k]; });
+    quad += row;
+  });
+  return C.b[k] + lin + 0.5 * quad;
+}
 
 __device__ inline double wave_sum(double x) {
   for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
   return x;
 }
+
+// theta of N ONVs: one wavefront per ONV, lanes over hidden units
+__global__ __launch_bounds__(256) void k_ising_theta(CorrParams C, const uint64_t* samples, int64_t N,
+                                                     double* theta) {
+  const int64_t n = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
+  const int lane = threadIdx.x & 63;
+  if (n >= N) return;
+  const uint64_t lo = samples[2 * n], hi = samples[2 * n + 1];
+  for (int k = lane; k < C.nh; k += 64) theta[n * C.nh + k] = ising_theta(C, lo, hi, k);
+}
+
+// E[n][P][k] for a tile of 32 samples (block x) and 256 columns c = P nh + k of
+// one sample's table (block y): G = S x sums the rows S[Q][P][.] (= S[P][Q][.])
+// of the occupied Q, read once per tile
+constexpr int kIsingTile = 32;
+__global__ __launch_bounds__(256) void k_ising_E(CorrParams C, const uint64_t* samples, int64_t N, double* E) {
+  __shared__ uint64_t slo[kIsingTile], shi[kIsingTile];
+  const int nv = 2 * C.K, nh = C.nh;
+  const int64_t cols = int64_t(nv) * nh;
+  const int64_t n0 = int64_t(blockIdx.x) * kIsingTile;
+  const int64_t c = int64_t(blockIdx.y) * blockDim.x + threadIdx.x;
+  if (threadIdx.x < kIsingTile) {
+    const int64_t n = n0 + threadIdx.x;
+    slo[threadIdx.x] = n < N ? samples[2 * n] : 0ull;
+    shi[threadIdx.x] = n < N ? samples[2 * n + 1] : 0ull;
+  }
+  __syncthreads();
+  if (c >= cols) return;
+  const int P = int(c / nh), k = int(c % nh);
+  double acc[kIsingTile];
+#pragma unroll
+  for (int t = 0; t < kIsingTile; ++t) acc[t] = 0.0;
+  for (int Q = 0; Q < nv; ++Q) {
+    const double v = C.S[size_t(Q) * cols + c];
+#pragma unroll
+    for (int t = 0; t < kIsingTile; ++t)
+      if (bit_at(slo[t], shi[t], Q)) acc[t] += v;
+  }
+  const double w = C.W1t[c], d = 0.5 * C.S[size_t(P) * cols + c];
+#pragma unroll
+  for (int t = 0; t < kIsingTile; ++t) {
+    const int64_t n = n0 + t;
+    if (n < N) E[n * cols + c] = (bit_at(slo[t], shi[t], P) ? -(w + acc[t]) : (w + acc[t])) + d;
+  }
+}
+
+// log|f(m)| and sign f(m) of the rows: one wavefront per row, lanes over
+// hidden units; cos and log in precision T, the sum of logs in FP64
+template <typename T>
+__global__ __launch_bounds__(256) void k_ising_rows(CorrParams C, const uint64_t* m, const int32_t* owner,
+                                                    const uint64_t* samples, const double* theta, const double* E,
+                                                    int64_t R, double* lf, int8_t* sf) {
+  const int64_t r = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
+  const int lane = threadIdx.x & 63;
+  if (r >= R) return;
+  const int64_t o = owner[r];
+  const uint64_t mlo = m[2 * r], mhi = m[2 * r + 1];
+  const uint64_t nlo = samples[2 * o], nhi = samples[2 * o + 1];
+  int ch[4], nc = 0;
+  double dl[4];
+  for_each_bit(mlo & ~nlo, mhi & ~nhi, [&](int P) { if (nc < 4) { ch[nc] = P; dl[nc] = 1.0; ++nc; } });
+  for_each_bit(nlo & ~mlo, nhi & ~mhi, [&](int P) { if (nc < 4) { ch[nc] = P; dl[nc] = -1.0; ++nc; } });
+  const int nv = 2 * C.K, nh = C.nh;
+  const double* Eo = E + size_t(o) * nv * nh;
+  double acc = 0.0;
+  int neg = 0;
+  for (int k = lane; k < nh; k += 64) {
+    double th = theta[o * nh + k];
+    for (int a = 0; a < nc; ++a) th += Eo[size_t(ch[a]) * nh + k];
+    for (int a = 0; a < nc; ++a)
+      for (int b = a + 1; b < nc; ++b) th += (dl[a] * dl[b]) * C.S[(size_t(ch[a]) * nv + ch[b]) * nh + k];
+    const T cv = tcos(T(th));
+    acc += double(tlog(tabs(cv)));
+    neg ^= cv < T(0) ? 1 : 0;
+  }
+  acc = wave_sum(acc);
+  const int odd = __popcll(__ballot(neg)) & 1;
+  if (lane == 0) {
+    lf[r] = acc;
+    sf[r] = int8_t(odd ? -1 : 1);
+  }
+}
+
+// direct evaluation for arbitrary ONVs (no owner), FP64
+__global__ __launch_bounds__(256) void k_ising_direct(CorrParams C, const uint64_t* m, int64_t R, double* lf,
+                                                      int8_t* sf) {
+  const int64_t r = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
+  const int lane = threadIdx.x & 63;
+  if (r >= R) return;
+  const uint64_t lo = m[2 * r], hi = m[2 * r + 1];
+  double acc = 0.0;
+  int neg = 0;
+  for (int k = lane; k < C.nh; k += 64) {
+    const double cv = cos(ising_theta(C, lo, hi, k));
+    acc += log(fabs(cv));
+    neg ^= cv < 0.0 ? 1 : 0;
+  }
+  acc = wave_sum(acc);
+  const int odd = __popcll(__ballot(neg)) & 1;
+  if (lane == 0) {
+    lf[r] = acc;
+    sf[r] = int8_t(odd ? -1 : 1);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// reductions
+// ---------------------------------------------------------------------------
 
 // Per sample n (one wavefront): E_loc(n) = H_nn + sum_rows coef * Psi(m)/Psi(n)
 // and Etilde_num(n) = |f_n|^2 H_nn + f_n sum_rows coef f_m Phi(m)/Phi(n).
@@ -214,16 +351,35 @@ inline unsigned grid_for(int64_t units, int per_block) {
 }  // namespace
 
 hipError_t launch_corr_theta(const CorrParams& C, const uint64_t* samples, int64_t N, double* theta,
-                             hipStream_t st) {
+                             double* E, hipStream_t st) {
   if (N <= 0 || C.nh <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_corr_theta, dim3(grid_for(N * C.nh, 256)), dim3(256), 0, st, C, samples, N, theta);
+  if (!C.ising) {
+    hipLaunchKernelGGL(k_corr_theta, dim3(grid_for(N * C.nh, 256)), dim3(256), 0, st, C, samples, N, theta);
+    return hipGetLastError();
+  }
+  hipLaunchKernelGGL(k_ising_theta, dim3(grid_for(N, 4)), dim3(256), 0, st, C, samples, N, theta);
+  if (E) {
+    const int64_t cols = int64_t(2 * C.K) * C.nh;
+    hipLaunchKernelGGL(k_ising_E, dim3(grid_for(N, kIsingTile), grid_for(cols, 256)), dim3(256), 0, st, C,
+                       samples, N, E);
+  }
   return hipGetLastError();
 }
 
 hipError_t launch_corr_rows(const CorrParams& C, const uint64_t* m, const int32_t* owner,
-                            const uint64_t* samples, const double* theta, int64_t R, int precision,
-                            double* lf, int8_t* sf, hipStream_t st) {
+                            const uint64_t* samples, const double* theta, const double* E, int64_t R,
+                            int precision, double* lf, int8_t* sf, hipStream_t st) {
   if (R <= 0) return hipSuccess;
+  if (C.ising) {
+    if (!E) return hipErrorInvalidValue;
+    if (precision == 0)
+      hipLaunchKernelGGL(k_ising_rows<double>, dim3(grid_for(R, 4)), dim3(256), 0, st, C, m, owner, samples,
+                         theta, E, R, lf, sf);
+    else
+      hipLaunchKernelGGL(k_ising_rows<float>, dim3(grid_for(R, 4)), dim3(256), 0, st, C, m, owner, samples,
+                         theta, E, R, lf, sf);
+    return hipGetLastError();
+  }
   if (precision == 0)
     hipLaunchKernelGGL(k_corr_rows<double>, dim3(grid_for(R, 256)), dim3(256), 0, st, C, m, owner, samples,
                        theta, R, lf, sf);
@@ -236,7 +392,10 @@ hipError_t launch_corr_rows(const CorrParams& C, const uint64_t* m, const int32_
 hipError_t launch_corr_direct(const CorrParams& C, const uint64_t* m, int64_t R, double* lf, int8_t* sf,
                               hipStream_t st) {
   if (R <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_corr_direct, dim3(grid_for(R, 256)), dim3(256), 0, st, C, m, R, lf, sf);
+  if (C.ising)
+    hipLaunchKernelGGL(k_ising_direct, dim3(grid_for(R, 4)), dim3(256), 0, st, C, m, R, lf, sf);
+  else
+    hipLaunchKernelGGL(k_corr_direct, dim3(grid_for(R, 256)), dim3(256), 0, st, C, m, R, lf, sf);
   return hipGetLastError();
 }
 

@@ -105,6 +105,11 @@ struct CorrParams {
   int K, nh;
   const double* b;   // [nh]
   const double* W;   // [nh][2K]
+  // Ising-RBM (ising != 0): W transposed [2K][nh] and the symmetric part of
+  // the quadratic couplings S[P][Q][k] = (W2[k][P][Q] + W2[k][Q][P]) / 2
+  int ising = 0;
+  const double* W1t = nullptr;
+  const double* S = nullptr;
 };
 
 // Row list of one local-energy call (structure of arrays).
@@ -240,11 +245,13 @@ hipError_t launch_order_t0(const uint8_t* t0, int64_t R, int K, int32_t* cnt, in
                            uint8_t* t0s, hipStream_t st);
 hipError_t launch_psi_bf16(const B16Params& P, const uint64_t* m, int64_t R, double* lphi, int8_t* sphi,
                            hipStream_t st, const B16States& X = B16States(), int mode = PSI_PLAIN);
+// theta[N][nh] of the samples; with the Ising-RBM also (when E is not null) the
+// per-sample row-update table E[N][2K][nh] (see energy.hip)
 hipError_t launch_corr_theta(const CorrParams& C, const uint64_t* samples, int64_t N, double* theta,
-                             hipStream_t st);
+                             double* E, hipStream_t st);
 hipError_t launch_corr_rows(const CorrParams& C, const uint64_t* m, const int32_t* owner,
-                            const uint64_t* samples, const double* theta, int64_t R, int precision,
-                            double* lf, int8_t* sf, hipStream_t st);
+                            const uint64_t* samples, const double* theta, const double* E, int64_t R,
+                            int precision, double* lf, int8_t* sf, hipStream_t st);
 hipError_t launch_corr_direct(const CorrParams& C, const uint64_t* m, int64_t R, double* lf, int8_t* sf,
                               hipStream_t st);
 hipError_t launch_reduce(int64_t n0, int64_t n1, const int64_t* rowptr, int64_t row_base, const double* coef,
@@ -267,7 +274,7 @@ hipError_t launch_bwd_sweep_f32(const AdjParams<float>& P, const uint64_t* m, in
                                 int64_t n_params, hipStream_t st);
 hipError_t launch_corr_backward(const CorrParams& C, const uint64_t* m, int64_t R, const double* cot,
                                 double* dth, int rows_per_split, int nsplit, int64_t offB, int64_t offW,
-                                double* gpart, int64_t n_params, hipStream_t st);
+                                int64_t offW2, double* gpart, int64_t n_params, hipStream_t st);
 hipError_t launch_sum_parts(int64_t n_params, int nsplit, const double* gpart, double* grad, hipStream_t st);
 
 }  // namespace nqs

@@ -216,6 +216,10 @@ struct nqs_ansatz {
   uint16_t* bfA = nullptr;  // BF16 forward A stream (folded when has_fold)
   double* d_cb = nullptr;   // correlator b
   double* d_cW = nullptr;   // correlator W
+  bool ising = false;       // Ising-RBM correlator (quadratic couplings W2)
+  int64_t offW2 = 0;
+  double* d_cW1t = nullptr; // Ising-RBM: W transposed [2K][nh]
+  double* d_cS = nullptr;   // Ising-RBM: (W2 + W2^T)/2 as [2K][2K][nh]
   int64_t* d_offM = nullptr;
   int64_t* d_offV = nullptr;
   int64_t* d_offEta = nullptr;
@@ -225,7 +229,8 @@ struct nqs_ansatz {
     F64.free_all();
     F32.free_all();
     for (void* p : {(void*)d_pptr, (void*)d_pidx, (void*)d_slot, (void*)d_fptr, (void*)d_fslot, (void*)bfA,
-                    (void*)d_cb, (void*)d_cW, (void*)d_offM, (void*)d_offV, (void*)d_offEta})
+                    (void*)d_cb, (void*)d_cW, (void*)d_cW1t, (void*)d_cS, (void*)d_offM, (void*)d_offV,
+                    (void*)d_offEta})
       if (p) (void)hipFree(p);
   }
   template <typename T>
@@ -253,6 +258,7 @@ struct nqs_ansatz {
   CorrParams corr() const {
     CorrParams C;
     C.K = K; C.nh = nh; C.b = d_cb; C.W = d_cW;
+    C.ising = ising ? 1 : 0; C.W1t = d_cW1t; C.S = d_cS;
     return C;
   }
 };
@@ -589,8 +595,10 @@ int64_t nqs_instance_n_conn(const nqs_instance* inst) { return inst ? int64_t(in
 
 nqs_status nqs_ansatz_create(nqs_ctx* ctx, int K, int n_alpha, int n_beta, int chi,
                              const int32_t* parent_ptr, const int32_t* parent_idx, int n_hidden,
-                             nqs_ansatz** out) {
+                             int32_t correlator, nqs_ansatz** out) {
   if (!ctx || !parent_ptr || !out) return fail(NQS_EINVAL, "NULL argument");
+  if (correlator != NQS_CORR_COS_RBM && correlator != NQS_CORR_ISING_RBM)
+    return fail(NQS_EINVAL, "unknown correlator %d", correlator);
   if (K < 1 || K > 64) return fail(NQS_EINVAL, "K=%d outside [1,64]", K);
   if (chi < 1 || chi > 64) return fail(NQS_EUNSUPPORTED, "chi=%d outside [1,64]", chi);
   if (n_alpha < 0 || n_alpha > K || n_beta < 0 || n_beta > K) return fail(NQS_EINVAL, "bad electron counts");
@@ -599,6 +607,7 @@ nqs_status nqs_ansatz_create(nqs_ctx* ctx, int K, int n_alpha, int n_beta, int c
   std::unique_ptr<nqs_ansatz> a(new nqs_ansatz());
   a->ctx = ctx;
   a->K = K; a->na = n_alpha; a->nb = n_beta; a->chi = chi; a->nh = n_hidden;
+  a->ising = n_hidden > 0 && correlator == NQS_CORR_ISING_RBM;
   a->chip = ((chi + 15) / 16) * 16;
   a->pptr.assign(parent_ptr, parent_ptr + K + 1);
   int maxoff = 0;
@@ -627,6 +636,8 @@ nqs_status nqs_ansatz_create(nqs_ctx* ctx, int K, int n_alpha, int n_beta, int c
   }
   a->offB = o; o += n_hidden;
   a->offWc = o; o += int64_t(n_hidden) * 2 * K;
+  a->offW2 = o;
+  if (a->ising) o += int64_t(n_hidden) * 4 * K * K;
   a->n_params = o;
   DeviceGuard g(ctx->device);
   nqs_status st;
@@ -687,11 +698,28 @@ nqs_status nqs_ansatz_bind_params(nqs_ansatz* ans, const double* params, hipStre
   if ((st = build_bf16(ans, prm, ans->has_fold)) != NQS_OK) return st;
   if (ans->d_cb) { (void)hipFree(ans->d_cb); ans->d_cb = nullptr; }
   if (ans->d_cW) { (void)hipFree(ans->d_cW); ans->d_cW = nullptr; }
+  if (ans->d_cW1t) { (void)hipFree(ans->d_cW1t); ans->d_cW1t = nullptr; }
+  if (ans->d_cS) { (void)hipFree(ans->d_cS); ans->d_cS = nullptr; }
   if (ans->nh) {
-    std::vector<double> b(prm.begin() + ans->offB, prm.begin() + ans->offB + ans->nh);
-    std::vector<double> W(prm.begin() + ans->offWc, prm.begin() + ans->offWc + int64_t(ans->nh) * 2 * ans->K);
+    const int nh = ans->nh, nv = 2 * ans->K;
+    std::vector<double> b(prm.begin() + ans->offB, prm.begin() + ans->offB + nh);
+    std::vector<double> W(prm.begin() + ans->offWc, prm.begin() + ans->offWc + int64_t(nh) * nv);
     if ((st = upload(&ans->d_cb, b)) != NQS_OK) return st;
     if ((st = upload(&ans->d_cW, W)) != NQS_OK) return st;
+    if (ans->ising) {
+      // hidden unit fastest: W^T [P][k] and S [P][Q][k] = (W2[k][P][Q] + W2[k][Q][P]) / 2
+      std::vector<double> Wt(size_t(nv) * nh), Sy(size_t(nv) * nv * nh);
+      const double* W2 = prm.data() + ans->offW2;
+      for (int k = 0; k < nh; ++k)
+        for (int P = 0; P < nv; ++P) {
+          Wt[size_t(P) * nh + k] = W[size_t(k) * nv + P];
+          for (int Q = 0; Q < nv; ++Q)
+            Sy[(size_t(P) * nv + Q) * nh + k] =
+                0.5 * (W2[(size_t(k) * nv + P) * nv + Q] + W2[(size_t(k) * nv + Q) * nv + P]);
+        }
+      if ((st = upload(&ans->d_cW1t, Wt)) != NQS_OK) return st;
+      if ((st = upload(&ans->d_cS, Sy)) != NQS_OK) return st;
+    }
   }
   ans->bound = true;
   return NQS_OK;
@@ -1036,7 +1064,7 @@ nqs_status nqs_logpsi_vjp(nqs_ctx* ctx, const nqs_ansatz* ans, const uint64_t* s
   }
   if (ans->nh)
     HIPCHK(launch_corr_backward(ans->corr(), samples, N, cotp, dth, rows_per_split, nsplit, ans->offB,
-                                ans->offWc, gpart, np, stream));
+                                ans->offWc, ans->offW2, gpart, np, stream));
   HIPCHK(launch_sum_parts(np, nsplit, gpart, grad, stream));
   HIPCHK(hipStreamSynchronize(stream));
   return NQS_OK;
@@ -1083,6 +1111,8 @@ nqs_status nqs_eloc(nqs_ctx* ctx, const nqs_instance* inst, const nqs_ansatz* an
   double* lf = ans->nh ? S.get<double>(cap_used) : nullptr;
   int8_t* sf = ans->nh ? S.get<int8_t>(cap_used) : nullptr;
   double* theta = ans->nh ? S.get<double>(size_t(N) * ans->nh) : nullptr;
+  // Ising-RBM: per-sample row-update table [N][2K][nh]
+  double* Etab = ans->ising ? S.get<double>(size_t(N) * 2 * ans->K * ans->nh) : nullptr;
   double* el = eloc ? eloc : S.get<double>(N);
   double* et = etnum ? etnum : S.get<double>(N);
   double* f2 = fsq ? fsq : S.get<double>(N);
@@ -1143,7 +1173,7 @@ nqs_status nqs_eloc(nqs_ctx* ctx, const nqs_instance* inst, const nqs_ansatz* an
     P.rows.sec = S.get<uint16_t>(cap_used);
   }
   if (S.oom) return fail(NQS_ENOMEM, "workspace allocation failed");
-  if (ans->nh) HIPCHK(launch_corr_theta(ans->corr(), samples, N, theta, stream));
+  if (ans->nh) HIPCHK(launch_corr_theta(ans->corr(), samples, N, theta, Etab, stream));
   float ms_rows = 0, ms_amp = 0, ms_red = 0, ms_psi = 0;
   int64_t site_rows = 0;
   double psi_flops = 0;
@@ -1240,8 +1270,8 @@ nqs_status nqs_eloc(nqs_ctx* ctx, const nqs_instance* inst, const nqs_ansatz* an
     }
     if (timing) HIPCHK(hipEventRecord(pe[2], stream));
     if (ans->nh)
-      HIPCHK(launch_corr_rows(ans->corr(), P.rows.m, P.rows.owner, samples, theta, Rp, opts->precision, lf, sf,
-                              stream));
+      HIPCHK(launch_corr_rows(ans->corr(), P.rows.m, P.rows.owner, samples, theta, Etab, Rp, opts->precision, lf,
+                              sf, stream));
     HIPCHK(launch_reduce(n0, n1, P.rowptr, P.rowptr_host[n0], P.rows.coef, lphi, sphi, lf, sf, P.hdiag, el, et,
                          logabs, sign, f2, stream));
     if (timing) {
@@ -1485,6 +1515,7 @@ nqs_status nqs_eloc_workspace_bytes(const nqs_instance* inst, const nqs_ansatz* 
   b += al(size_t(rows) * 8) + al(size_t(rows));
   if (ans->nh) b += al(size_t(rows) * 8) + al(size_t(rows));
   if (ans->nh) b += al(size_t(N) * ans->nh * 8);
+  if (ans->ising) b += al(size_t(N) * 2 * ans->K * ans->nh * 8);
   if (resumes(*opts)) {
     // samples' carried and log-product states, the pass's row order
     const int K = ans->K;

@@ -76,7 +76,8 @@ def lib():
     L.nqs_instance_n_conn.argtypes = [_p]
     L.nqs_instance_n_conn.restype = C.c_int64
     L.nqs_connected.argtypes = [_p, _p, _p, C.c_int64, _p, _p, _p, _p]
-    L.nqs_ansatz_create.argtypes = [_p, C.c_int, C.c_int, C.c_int, C.c_int, _p, _p, C.c_int, C.POINTER(_p)]
+    L.nqs_ansatz_create.argtypes = [_p, C.c_int, C.c_int, C.c_int, C.c_int, _p, _p, C.c_int, C.c_int32,
+                                    C.POINTER(_p)]
     L.nqs_ansatz_destroy.argtypes = [_p]
     L.nqs_ansatz_n_params.argtypes = [_p]
     L.nqs_ansatz_n_params.restype = C.c_int64
@@ -201,20 +202,22 @@ class Instance:
 
 
 class Ansatz:
-    """BDG-RNN / MPS-RNN (+ cos-RBM) layout; parameters bound from a device tensor."""
+    """BDG-RNN / MPS-RNN (+ cos-RBM or Ising-RBM correlator) layout; parameters
+    bound from a device tensor."""
 
     def __init__(self, ctx: Context, K: int, n_alpha: int, n_beta: int, chi: int, parent_ptr, parent_idx,
-                 n_hidden: int = 0):
+                 n_hidden: int = 0, ising: bool = False):
         pp = np.ascontiguousarray(parent_ptr, dtype=np.int32)
         pi = np.ascontiguousarray(parent_idx, dtype=np.int32)
         if pi.size == 0:
             pi = np.zeros(1, dtype=np.int32)
         out = _p()
         check(lib().nqs_ansatz_create(ctx.h, K, n_alpha, n_beta, chi, pp.ctypes.data_as(_p),
-                                      pi.ctypes.data_as(_p), n_hidden, C.byref(out)))
+                                      pi.ctypes.data_as(_p), n_hidden, 1 if ising else 0, C.byref(out)))
         self.h = out
         self.ctx = ctx
         self.K, self.n_alpha, self.n_beta, self.chi, self.n_hidden = K, n_alpha, n_beta, chi, n_hidden
+        self.ising = bool(ising) and n_hidden > 0
         self.n_params = int(lib().nqs_ansatz_n_params(out))
 
     def bind(self, params):
