@@ -57,6 +57,8 @@ def _load():
                                    _u64, _u64, _p, _i64, _p, _p, _p, _p]
     lib.or_eloc_table.argtypes = [_i, _i, _i, _p, _p, _d, _p, _p, _i64, _p, _i64, _d, _i, _u64,
                                   _u64, _p, _i]
+    lib.or_reweighted_cotangent.argtypes = [_i64, _p, _p, _p, _p, _p]
+    lib.or_adamw.argtypes = [_i64, _p, _p, _p, _p, _i64, _d, _d, _d, _d, _d]
     _lib = lib
     return lib
 
@@ -231,3 +233,37 @@ def eloc_table(K, na, nb, h, eri, keys, vals, samples, eps=0.0, n_eps=0, seed=0,
     _load().or_eloc_table(K, na, nb, _ptr(h), _ptr(eri), e_core, _ptr(k), _ptr(v), len(k),
                           _ptr(s), len(s), eps, n_eps, seed, stream, _ptr(out), nthreads)
     return out
+
+
+def reweighted_cotangent(counts, etnum, fsq):
+    """(cot, E): the VJP cotangent of the reweighted VMC gradient for real
+    parameters (Sec. 2.3, Eq. (19)) and the reweighted energy."""
+    c, et, f2 = _f64(counts), _f64(etnum), _f64(fsq)
+    cot = np.zeros(len(c))
+    E = np.zeros(1)
+    _load().or_reweighted_cotangent(len(c), _ptr(c), _ptr(et), _ptr(f2), _ptr(cot), _ptr(E))
+    return cot, float(E[0])
+
+
+def adamw(params, grad, m, v, step, lr, beta1=0.9, beta2=0.999, eps=1e-8, weight_decay=0.0):
+    """One AdamW step on copies: returns (params, m, v)."""
+    p, g = _f64(params).copy(), _f64(grad)
+    mm, vv = _f64(m).copy(), _f64(v).copy()
+    _load().or_adamw(p.size, _ptr(p), _ptr(g), _ptr(mm), _ptr(vv), int(step), lr, beta1, beta2, eps, weight_decay)
+    return p, mm, vv
+
+
+def vmc_step(K, na, nb, h, eri, chi, parent_ptr, parent_idx, n_hidden, params, m, v, step, n_draws,
+             sample_seed, draw_base=0, eps=0.0, n_eps=0, eloc_seed=0, stream=0, lr=1e-3, beta1=0.9,
+             beta2=0.999, adam_eps=1e-8, weight_decay=0.0, e_core=0.0, ising=False):
+    """One VMC step in the paper's order: exact draws from Phi^2 merged into
+    unique samples with counts, semi-stochastic local energies, the reweighted
+    gradient of Eq. (19) (through the cotangent above and the gradient of
+    ln|Psi|), and one AdamW update."""
+    uniq, cnt = sample_unique(K, chi, na, nb, parent_ptr, parent_idx, params, sample_seed, n_draws, draw_base)
+    out = eloc(K, na, nb, h, eri, chi, parent_ptr, parent_idx, n_hidden, params, uniq, eps=eps, n_eps=n_eps,
+               seed=eloc_seed, stream=stream, e_core=e_core, ising=ising)
+    cot, E = reweighted_cotangent(cnt.astype(np.float64), out["etnum"], out["fsq"])
+    g = grad(K, chi, na, nb, parent_ptr, parent_idx, n_hidden, params, uniq, cot, ising=ising)
+    p, mm, vv = adamw(params, g, m, v, step, lr, beta1, beta2, adam_eps, weight_decay)
+    return dict(params=p, m=mm, v=vv, grad=g, E=E, samples=uniq, counts=cnt, eloc=out)

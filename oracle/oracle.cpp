@@ -784,6 +784,40 @@ int or_eloc_detail(int K, int na, int nb, const double* h, const double* eri, do
   return 0;
 }
 
+// The cotangent of the VMC gradient for real parameters (Sec. 2.3, Eq. (19)):
+// with weights c_n over the samples, B = sum c |f|^2 / sum c and
+// E = sum c Etilde_num / sum c |f|^2, the gradient is
+// 2 <d ln|Psi| (Etilde_loc - |f~|^2 E)> = sum_n cot_n d ln|Psi(n)|,
+// cot_n = 2 c_n (Etilde_num(n) - |f_n|^2 E) / sum c |f|^2.
+int or_reweighted_cotangent(int64_t N, const double* counts, const double* etnum, const double* fsq,
+                            double* cot, double* E_out) {
+  double sc_f2 = 0.0, sc_et = 0.0;
+  for (int64_t n = 0; n < N; ++n) {
+    sc_f2 += counts[n] * fsq[n];
+    sc_et += counts[n] * etnum[n];
+  }
+  const double E = sc_et / sc_f2;
+  for (int64_t n = 0; n < N; ++n) cot[n] = 2.0 * counts[n] * (etnum[n] - fsq[n] * E) / sc_f2;
+  *E_out = E;
+  return 0;
+}
+
+// One AdamW step (Loshchilov and Hutter, decoupled weight decay; the
+// formulation of PyTorch's AdamW): p <- p (1 - lr wd); m <- b1 m + (1 - b1) g;
+// v <- b2 v + (1 - b2) g^2; p <- p - lr (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps).
+int or_adamw(int64_t n, double* p, const double* g, double* m, double* v, int64_t t, double lr, double b1,
+             double b2, double eps, double wd) {
+  const double c1 = 1.0 - std::pow(b1, double(t)), c2 = 1.0 - std::pow(b2, double(t));
+  for (int64_t k = 0; k < n; ++k) {
+    p[k] *= 1.0 - lr * wd;
+    m[k] = b1 * m[k] + (1.0 - b1) * g[k];
+    v[k] = b2 * v[k] + (1.0 - b2) * g[k] * g[k];
+    const double mh = m[k] / c1, vh = v[k] / c2;
+    p[k] -= lr * mh / (std::sqrt(vh) + eps);
+  }
+  return 0;
+}
+
 // local energies with the amplitude given as a table over sorted ONV keys
 // (keys as [T][2] words, ascending as 128-bit integers); an ONV missing from
 // the table has amplitude 0.
