@@ -406,7 +406,7 @@ hipError_t launch_corr_backward(const CorrParams& C, const uint64_t* m, int64_t 
   if (C.nh <= 0 || R <= 0) return hipSuccess;
   hipError_t e;
   if (C.ising) {
-    if ((e = launch_corr_theta(C, m, R, dth, nullptr, st)) != hipSuccess) return e;
+    if ((e = launch_corr_theta(C, m, R, dth, nullptr, 0, st)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_dth_from_theta, dim3(grid_for(R * C.nh, 256)), dim3(256), 0, st, R, C.nh, cot, dth);
   } else {
     hipLaunchKernelGGL(k_corr_dtheta, dim3(grid_for(R * C.nh, 256)), dim3(256), 0, st, C, m, R, cot, dth);

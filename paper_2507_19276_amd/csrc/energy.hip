@@ -147,7 +147,8 @@ __global__ __launch_bounds__(256) void k_ising_theta(CorrParams C, const uint64_
 // one sample's table (block y): G = S x sums the rows S[Q][P][.] (= S[P][Q][.])
 // of the occupied Q, read once per tile
 constexpr int kIsingTile = 32;
-__global__ __launch_bounds__(256) void k_ising_E(CorrParams C, const uint64_t* samples, int64_t N, double* E) {
+template <typename TT>
+__global__ __launch_bounds__(256) void k_ising_E(CorrParams C, const uint64_t* samples, int64_t N, TT* E) {
   __shared__ uint64_t slo[kIsingTile], shi[kIsingTile];
   const int nv = 2 * C.K, nh = C.nh;
   const int64_t cols = int64_t(nv) * nh;
@@ -174,44 +175,98 @@ __global__ __launch_bounds__(256) void k_ising_E(CorrParams C, const uint64_t* s
 #pragma unroll
   for (int t = 0; t < kIsingTile; ++t) {
     const int64_t n = n0 + t;
-    if (n < N) E[n * cols + c] = (bit_at(slo[t], shi[t], P) ? -(w + acc[t]) : (w + acc[t])) + d;
+    if (n < N) E[n * cols + c] = TT((bit_at(slo[t], shi[t], P) ? -(w + acc[t]) : (w + acc[t])) + d);
   }
 }
 
-// log|f(m)| and sign f(m) of the rows: one wavefront per row, lanes over
-// hidden units; cos and log in precision T, the sum of logs in FP64
-template <typename T>
-__global__ __launch_bounds__(256) void k_ising_rows(CorrParams C, const uint64_t* m, const int32_t* owner,
-                                                    const uint64_t* samples, const double* theta, const double* E,
-                                                    int64_t R, double* lf, int8_t* sf) {
-  const int64_t r = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
-  const int lane = threadIdx.x & 63;
-  if (r >= R) return;
-  const int64_t o = owner[r];
-  const uint64_t mlo = m[2 * r], mhi = m[2 * r + 1];
-  const uint64_t nlo = samples[2 * o], nhi = samples[2 * o + 1];
-  int ch[4], nc = 0;
-  double dl[4];
-  for_each_bit(mlo & ~nlo, mhi & ~nhi, [&](int P) { if (nc < 4) { ch[nc] = P; dl[nc] = 1.0; ++nc; } });
-  for_each_bit(nlo & ~mlo, nhi & ~mhi, [&](int P) { if (nc < 4) { ch[nc] = P; dl[nc] = -1.0; ++nc; } });
-  const int nv = 2 * C.K, nh = C.nh;
-  const double* Eo = E + size_t(o) * nv * nh;
-  double acc = 0.0;
-  int neg = 0;
-  for (int k = lane; k < nh; k += 64) {
-    double th = theta[o * nh + k];
-    for (int a = 0; a < nc; ++a) th += Eo[size_t(ch[a]) * nh + k];
-    for (int a = 0; a < nc; ++a)
-      for (int b = a + 1; b < nc; ++b) th += (dl[a] * dl[b]) * C.S[(size_t(ch[a]) * nv + ch[b]) * nh + k];
-    const T cv = tcos(T(th));
-    acc += double(tlog(tabs(cv)));
-    neg ^= cv < T(0) ? 1 : 0;
+// log|f(m)| and sign f(m) of the rows: a wavefront takes kIsingRowsPerWave
+// consecutive rows, kIsingBatch at a time, with hidden units across lanes; a
+// batch's rows are decoded with scalar loads and their table reads issued
+// together, so the wavefront keeps several rows' loads in flight.  Tables E and
+// S in precision TT (FP32 for the FP32/BF16 paths: they then round like the
+// FP32 cos that follows), theta accumulated in FP64, cos and log in precision
+// T, the sum of logs in FP64.
+constexpr int kIsingRowsPerWave = 16, kIsingBatch = 2;
+
+// lowest set bit of the 128-bit (lo, hi), cleared; -1 if none
+__device__ inline int pop_lowest(uint64_t& lo, uint64_t& hi) {
+  if (lo) {
+    const int P = __ffsll((unsigned long long)lo) - 1;
+    lo &= lo - 1;
+    return P;
   }
-  acc = wave_sum(acc);
-  const int odd = __popcll(__ballot(neg)) & 1;
-  if (lane == 0) {
-    lf[r] = acc;
-    sf[r] = int8_t(odd ? -1 : 1);
+  if (hi) {
+    const int P = 64 + __ffsll((unsigned long long)hi) - 1;
+    hi &= hi - 1;
+    return P;
+  }
+  return -1;
+}
+
+template <typename T, typename TT>
+__global__ __launch_bounds__(256) void k_ising_rows(CorrParams C, const TT* S, const uint64_t* m,
+                                                    const int32_t* owner, const uint64_t* samples,
+                                                    const double* theta, const TT* E, int64_t R, double* lf,
+                                                    int8_t* sf) {
+  const int64_t wave = (int64_t(blockIdx.x) * blockDim.x + __builtin_amdgcn_readfirstlane(threadIdx.x)) >> 6;
+  const int lane = threadIdx.x & 63;
+  const int64_t r0 = wave * kIsingRowsPerWave;
+  if (r0 >= R) return;
+  const int64_t r1 = r0 + kIsingRowsPerWave < R ? r0 + kIsingRowsPerWave : R;
+  const int nv = 2 * C.K, nh = C.nh;
+  for (int64_t rb = r0; rb < r1; rb += kIsingBatch) {
+    // per row four fixed slots: the two created orbitals (delta +1), then the
+    // two annihilated ones (delta -1); an absent slot has delta 0 and points
+    // at orbital 0, so every row issues the same loads and adds exact zeros
+    int ch[kIsingBatch][4];
+    double dl[kIsingBatch][4];
+    const TT* Eo[kIsingBatch];
+    const double* To[kIsingBatch];
+#pragma unroll
+    for (int j = 0; j < kIsingBatch; ++j) {
+      const int64_t r = rb + j < r1 ? rb + j : r1 - 1;
+      const int64_t o = owner[r];
+      const uint64_t mlo = m[2 * r], mhi = m[2 * r + 1];
+      const uint64_t nlo = samples[2 * o], nhi = samples[2 * o + 1];
+      uint64_t clo = mlo & ~nlo, chi = mhi & ~nhi, alo = nlo & ~mlo, ahi = nhi & ~mhi;
+#pragma unroll
+      for (int a = 0; a < 4; ++a) {
+        const int P = a < 2 ? pop_lowest(clo, chi) : pop_lowest(alo, ahi);
+        ch[j][a] = P < 0 ? 0 : P;
+        dl[j][a] = P < 0 ? 0.0 : (a < 2 ? 1.0 : -1.0);
+      }
+      Eo[j] = E + size_t(o) * nv * nh;
+      To[j] = theta + size_t(o) * nh;
+    }
+    double acc[kIsingBatch];
+    int neg[kIsingBatch];
+#pragma unroll
+    for (int j = 0; j < kIsingBatch; ++j) { acc[j] = 0.0; neg[j] = 0; }
+    for (int k = lane; k < nh; k += 64) {
+#pragma unroll
+      for (int j = 0; j < kIsingBatch; ++j) {
+        double th = To[j][k];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) th += (dl[j][a] * dl[j][a]) * double(Eo[j][size_t(ch[j][a]) * nh + k]);
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+          for (int b = a + 1; b < 4; ++b)
+            th += (dl[j][a] * dl[j][b]) * double(S[(size_t(ch[j][a]) * nv + ch[j][b]) * nh + k]);
+        const T cv = tcos(T(th));
+        acc[j] += double(tlog(tabs(cv)));
+        neg[j] ^= cv < T(0) ? 1 : 0;
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < kIsingBatch; ++j) {
+      const double sum = wave_sum(acc[j]);
+      const int odd = __popcll(__ballot(neg[j])) & 1;
+      if (lane == 0 && rb + j < r1) {
+        lf[rb + j] = sum;
+        sf[rb + j] = int8_t(odd ? -1 : 1);
+      }
+    }
   }
 }
 
@@ -351,7 +406,7 @@ inline unsigned grid_for(int64_t units, int per_block) {
 }  // namespace
 
 hipError_t launch_corr_theta(const CorrParams& C, const uint64_t* samples, int64_t N, double* theta,
-                             double* E, hipStream_t st) {
+                             void* E, int precision, hipStream_t st) {
   if (N <= 0 || C.nh <= 0) return hipSuccess;
   if (!C.ising) {
     hipLaunchKernelGGL(k_corr_theta, dim3(grid_for(N * C.nh, 256)), dim3(256), 0, st, C, samples, N, theta);
@@ -360,24 +415,28 @@ hipError_t launch_corr_theta(const CorrParams& C, const uint64_t* samples, int64
   hipLaunchKernelGGL(k_ising_theta, dim3(grid_for(N, 4)), dim3(256), 0, st, C, samples, N, theta);
   if (E) {
     const int64_t cols = int64_t(2 * C.K) * C.nh;
-    hipLaunchKernelGGL(k_ising_E, dim3(grid_for(N, kIsingTile), grid_for(cols, 256)), dim3(256), 0, st, C,
-                       samples, N, E);
+    if (precision == 0)
+      hipLaunchKernelGGL(k_ising_E<double>, dim3(grid_for(N, kIsingTile), grid_for(cols, 256)), dim3(256), 0, st,
+                         C, samples, N, (double*)E);
+    else
+      hipLaunchKernelGGL(k_ising_E<float>, dim3(grid_for(N, kIsingTile), grid_for(cols, 256)), dim3(256), 0, st,
+                         C, samples, N, (float*)E);
   }
   return hipGetLastError();
 }
 
 hipError_t launch_corr_rows(const CorrParams& C, const uint64_t* m, const int32_t* owner,
-                            const uint64_t* samples, const double* theta, const double* E, int64_t R,
+                            const uint64_t* samples, const double* theta, const void* E, int64_t R,
                             int precision, double* lf, int8_t* sf, hipStream_t st) {
   if (R <= 0) return hipSuccess;
   if (C.ising) {
     if (!E) return hipErrorInvalidValue;
     if (precision == 0)
-      hipLaunchKernelGGL(k_ising_rows<double>, dim3(grid_for(R, 4)), dim3(256), 0, st, C, m, owner, samples,
-                         theta, E, R, lf, sf);
+      hipLaunchKernelGGL((k_ising_rows<double, double>), dim3(grid_for(R, 4 * kIsingRowsPerWave)), dim3(256), 0,
+                         st, C, C.S, m, owner, samples, theta, (const double*)E, R, lf, sf);
     else
-      hipLaunchKernelGGL(k_ising_rows<float>, dim3(grid_for(R, 4)), dim3(256), 0, st, C, m, owner, samples,
-                         theta, E, R, lf, sf);
+      hipLaunchKernelGGL((k_ising_rows<float, float>), dim3(grid_for(R, 4 * kIsingRowsPerWave)), dim3(256), 0,
+                         st, C, C.S32, m, owner, samples, theta, (const float*)E, R, lf, sf);
     return hipGetLastError();
   }
   if (precision == 0)

@@ -110,6 +110,7 @@ struct CorrParams {
   int ising = 0;
   const double* W1t = nullptr;
   const double* S = nullptr;
+  const float* S32 = nullptr;   // S rounded to FP32 (reduced-precision paths)
 };
 
 // Row list of one local-energy call (structure of arrays).
@@ -246,11 +247,12 @@ hipError_t launch_order_t0(const uint8_t* t0, int64_t R, int K, int32_t* cnt, in
 hipError_t launch_psi_bf16(const B16Params& P, const uint64_t* m, int64_t R, double* lphi, int8_t* sphi,
                            hipStream_t st, const B16States& X = B16States(), int mode = PSI_PLAIN);
 // theta[N][nh] of the samples; with the Ising-RBM also (when E is not null) the
-// per-sample row-update table E[N][2K][nh] (see energy.hip)
+// per-sample row-update table E[N][2K][nh] (see energy.hip), FP64 for
+// precision NQS_F64, else FP32
 hipError_t launch_corr_theta(const CorrParams& C, const uint64_t* samples, int64_t N, double* theta,
-                             double* E, hipStream_t st);
+                             void* E, int precision, hipStream_t st);
 hipError_t launch_corr_rows(const CorrParams& C, const uint64_t* m, const int32_t* owner,
-                            const uint64_t* samples, const double* theta, const double* E, int64_t R,
+                            const uint64_t* samples, const double* theta, const void* E, int64_t R,
                             int precision, double* lf, int8_t* sf, hipStream_t st);
 hipError_t launch_corr_direct(const CorrParams& C, const uint64_t* m, int64_t R, double* lf, int8_t* sf,
                               hipStream_t st);

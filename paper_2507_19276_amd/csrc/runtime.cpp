@@ -220,6 +220,7 @@ struct nqs_ansatz {
   int64_t offW2 = 0;
   double* d_cW1t = nullptr; // Ising-RBM: W transposed [2K][nh]
   double* d_cS = nullptr;   // Ising-RBM: (W2 + W2^T)/2 as [2K][2K][nh]
+  float* d_cS32 = nullptr;  // the same in FP32
   int64_t* d_offM = nullptr;
   int64_t* d_offV = nullptr;
   int64_t* d_offEta = nullptr;
@@ -229,7 +230,7 @@ struct nqs_ansatz {
     F64.free_all();
     F32.free_all();
     for (void* p : {(void*)d_pptr, (void*)d_pidx, (void*)d_slot, (void*)d_fptr, (void*)d_fslot, (void*)bfA,
-                    (void*)d_cb, (void*)d_cW, (void*)d_cW1t, (void*)d_cS, (void*)d_offM, (void*)d_offV,
+                    (void*)d_cb, (void*)d_cW, (void*)d_cW1t, (void*)d_cS, (void*)d_cS32, (void*)d_offM, (void*)d_offV,
                     (void*)d_offEta})
       if (p) (void)hipFree(p);
   }
@@ -258,7 +259,7 @@ struct nqs_ansatz {
   CorrParams corr() const {
     CorrParams C;
     C.K = K; C.nh = nh; C.b = d_cb; C.W = d_cW;
-    C.ising = ising ? 1 : 0; C.W1t = d_cW1t; C.S = d_cS;
+    C.ising = ising ? 1 : 0; C.W1t = d_cW1t; C.S = d_cS; C.S32 = d_cS32;
     return C;
   }
 };
@@ -700,6 +701,7 @@ nqs_status nqs_ansatz_bind_params(nqs_ansatz* ans, const double* params, hipStre
   if (ans->d_cW) { (void)hipFree(ans->d_cW); ans->d_cW = nullptr; }
   if (ans->d_cW1t) { (void)hipFree(ans->d_cW1t); ans->d_cW1t = nullptr; }
   if (ans->d_cS) { (void)hipFree(ans->d_cS); ans->d_cS = nullptr; }
+  if (ans->d_cS32) { (void)hipFree(ans->d_cS32); ans->d_cS32 = nullptr; }
   if (ans->nh) {
     const int nh = ans->nh, nv = 2 * ans->K;
     std::vector<double> b(prm.begin() + ans->offB, prm.begin() + ans->offB + nh);
@@ -719,6 +721,8 @@ nqs_status nqs_ansatz_bind_params(nqs_ansatz* ans, const double* params, hipStre
         }
       if ((st = upload(&ans->d_cW1t, Wt)) != NQS_OK) return st;
       if ((st = upload(&ans->d_cS, Sy)) != NQS_OK) return st;
+      std::vector<float> Sy32(Sy.begin(), Sy.end());
+      if ((st = upload(&ans->d_cS32, Sy32)) != NQS_OK) return st;
     }
   }
   ans->bound = true;
@@ -1173,7 +1177,7 @@ nqs_status nqs_eloc(nqs_ctx* ctx, const nqs_instance* inst, const nqs_ansatz* an
     P.rows.sec = S.get<uint16_t>(cap_used);
   }
   if (S.oom) return fail(NQS_ENOMEM, "workspace allocation failed");
-  if (ans->nh) HIPCHK(launch_corr_theta(ans->corr(), samples, N, theta, Etab, stream));
+  if (ans->nh) HIPCHK(launch_corr_theta(ans->corr(), samples, N, theta, Etab, opts->precision, stream));
   float ms_rows = 0, ms_amp = 0, ms_red = 0, ms_psi = 0;
   int64_t site_rows = 0;
   double psi_flops = 0;
