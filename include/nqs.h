@@ -258,6 +258,40 @@ nqs_status nqs_rows(nqs_ctx* ctx, const nqs_instance* inst, const uint64_t* samp
 nqs_status nqs_eloc_workspace_bytes(const nqs_instance* inst, const nqs_ansatz* ans, int64_t N,
                                     const nqs_eloc_opts* opts, int64_t n_rows, size_t* bytes);
 
+/* ---- one VMC step (Sec. 2.1 Eq. (7), Sec. 2.3 Eq. (19), AdamW of Sec. 3) - */
+
+typedef struct {
+  int64_t n_draws;            /* exact draws from Phi^2 in this step (>= 1) */
+  uint64_t sample_seed;       /* sampler key (see nqs_sample) */
+  int64_t draw_base;          /* index of the step's first draw, e.g. step * n_draws */
+  int64_t max_draws_per_pass; /* sampler passes (0 = one pass) */
+  nqs_eloc_opts eloc;         /* local-energy options; eloc.precision NQS_F64 also selects FP64
+                                 sampling and adjoint, anything else FP32 for both */
+  double lr, beta1, beta2, adam_eps, weight_decay;   /* AdamW (decoupled weight decay) */
+  int64_t step;               /* AdamW step number t >= 1 (bias corrections 1 - beta^t) */
+} nqs_vmc_opts;
+
+typedef struct {
+  int64_t n_unique;           /* unique samples of the step */
+  double E, var, B;           /* reweighted energy, variance and <|f|^2> of the step's samples */
+  double grad_norm;           /* Euclidean norm of the gradient */
+  double ms_sample, ms_eloc, ms_grad, ms_update;   /* host wall time of the four stages */
+} nqs_vmc_stats;
+
+/* One variational step for real parameters: draw n_draws samples from Phi^2
+ * (nqs_sample), merge them into unique samples with counts, evaluate the
+ * semi-stochastic local energies weighted by the counts (nqs_eloc), form the
+ * reweighted gradient of Eq. (19),
+ *   g = sum_n cot_n d ln|Psi(n)|/d theta,  cot_n = 2 c_n (Etilde_num(n) - |f_n|^2 E) / sum c |f|^2
+ * (for f = 1 the plain VMC gradient of Eq. (7)), through nqs_logpsi_vjp, apply
+ * one AdamW update to params (device double[n_params], in place) with the
+ * moment estimates adam_m, adam_v (device, in place, zero before the first
+ * step), and re-bind the ansatz to the new parameters.  grad (device
+ * double[n_params], nullable) receives g.  Synchronises `stream`. */
+nqs_status nqs_vmc_step(nqs_ctx* ctx, const nqs_instance* inst, nqs_ansatz* ans, const nqs_vmc_opts* opts,
+                        double* params, double* adam_m, double* adam_v, double* grad, nqs_vmc_stats* stats,
+                        hipStream_t stream);
+
 /* ---- serving: continuous batching of local-energy requests ------------- */
 
 typedef struct nqs_server nqs_server;

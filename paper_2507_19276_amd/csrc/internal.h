@@ -235,6 +235,15 @@ hipError_t launch_unique(const uint64_t* m, const double* lphi, const int8_t* sp
                          int64_t N, bool two_words, const UniqueScratch& w, int64_t cap, uint64_t* um, int64_t* ucnt,
                          double* ul, int8_t* us, int64_t* nu, hipStream_t st);
 hipError_t launch_fill_i64(int64_t* p, int64_t n, int64_t v, hipStream_t st);
+// ---- VMC step (vmc.hip) -------------------------------------------------
+hipError_t launch_i64_to_f64(int64_t n, const int64_t* a, double* b, hipStream_t st);
+// cot_n = 2 c_n (etnum_n - fsq_n E) / S with S = sum c fsq, E = sum c etnum / S;
+// out (device double[2]) = {E, S}
+hipError_t launch_vmc_cotangent(int64_t N, const double* c, const double* etnum, const double* fsq, double* cot,
+                                double* out, hipStream_t st);
+hipError_t launch_adamw(int64_t n, double* p, const double* g, double* m, double* v, int64_t t, double lr, double b1,
+                        double b2, double eps, double wd, hipStream_t st);
+hipError_t launch_sumsq(int64_t n, const double* g, double* out, hipStream_t st);
 // ---- row order by first changed site (order.hip) ----------------------
 // chunk of rows per block of the counting sort
 constexpr int kOrderChunk = 16384;

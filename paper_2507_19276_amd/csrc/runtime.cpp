@@ -7,6 +7,7 @@
 #include "internal.h"
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -1543,6 +1544,78 @@ nqs_status nqs_eloc_workspace_bytes(const nqs_instance* inst, const nqs_ansatz* 
   b += 3 * al(size_t(N) * 8) + al(64);     // outputs the caller did not provide, batch sums
   b += al(4);                              // sample validation flag
   *bytes = b;
+  return NQS_OK;
+}
+
+nqs_status nqs_vmc_step(nqs_ctx* ctx, const nqs_instance* inst, nqs_ansatz* ans, const nqs_vmc_opts* opts,
+                        double* params, double* adam_m, double* adam_v, double* grad, nqs_vmc_stats* stats,
+                        hipStream_t stream) {
+  if (!ctx || !inst || !ans || !opts || !params || !adam_m || !adam_v) return fail(NQS_EINVAL, "NULL argument");
+  if (opts->n_draws < 1) return fail(NQS_EINVAL, "n_draws < 1");
+  if (opts->step < 1) return fail(NQS_EINVAL, "AdamW step numbers start at 1");
+  if (!(opts->lr >= 0) || !(opts->beta1 >= 0 && opts->beta1 < 1) || !(opts->beta2 >= 0 && opts->beta2 < 1) ||
+      !(opts->adam_eps > 0) || !(opts->weight_decay >= 0))
+    return fail(NQS_EINVAL, "bad AdamW hyperparameters");
+  if (!ans->bound) return fail(NQS_EINVAL, "parameters not bound");
+  const int32_t prec = opts->eloc.precision;
+  const int32_t low = prec == NQS_F64 ? NQS_F64 : NQS_F32;   // sampler and adjoint precision
+  const int64_t np = ans->n_params;
+  DeviceGuard g(ctx->device);
+  auto now = [] { return std::chrono::steady_clock::now(); };
+  auto ms = [](std::chrono::steady_clock::time_point a, std::chrono::steady_clock::time_point b) {
+    return std::chrono::duration<double, std::milli>(b - a).count();
+  };
+  const int64_t D = opts->n_draws;
+  Scratch S(ctx);
+  uint64_t* smp = S.get<uint64_t>(size_t(D) * 2);
+  int64_t* cnt = S.get<int64_t>(D);
+  double* cd = S.get<double>(D);
+  double* etn = S.get<double>(D);
+  double* f2 = S.get<double>(D);
+  double* cot = S.get<double>(D);
+  double* gbuf = grad ? grad : S.get<double>(np);
+  double* red = S.get<double>(4);
+  if (S.oom) return fail(NQS_ENOMEM, "workspace allocation failed");
+  nqs_status st;
+  // 1. exact draws from Phi^2, merged into unique samples with counts
+  const auto t0 = now();
+  int64_t U = 0;
+  if ((st = nqs_sample(ctx, ans, D, opts->sample_seed, opts->draw_base, low, opts->max_draws_per_pass, D, smp, cnt,
+                       nullptr, nullptr, &U, stream)) != NQS_OK)
+    return st;
+  HIPCHK(launch_i64_to_f64(U, cnt, cd, stream));
+  // 2. semi-stochastic local energies of the unique samples, weighted by counts
+  const auto t1 = now();
+  nqs_eloc_stats es;
+  if ((st = nqs_eloc(ctx, inst, ans, smp, cd, U, &opts->eloc, nullptr, etn, nullptr, nullptr, f2, &es, stream)) !=
+      NQS_OK)
+    return st;
+  // 3. the reweighted gradient (Eq. (19)) as the VJP of ln|Psi| with cotangent cot
+  const auto t2 = now();
+  HIPCHK(launch_vmc_cotangent(U, cd, etn, f2, cot, red, stream));
+  HIPCHK(hipMemsetAsync(gbuf, 0, sizeof(double) * np, stream));
+  if ((st = nqs_logpsi_vjp(ctx, ans, smp, U, cot, low, gbuf, stream)) != NQS_OK) return st;
+  // 4. AdamW on the packed parameters, then the kernels' layouts are rebuilt
+  const auto t3 = now();
+  HIPCHK(launch_sumsq(np, gbuf, red + 2, stream));
+  HIPCHK(launch_adamw(np, params, gbuf, adam_m, adam_v, opts->step, opts->lr, opts->beta1, opts->beta2,
+                      opts->adam_eps, opts->weight_decay, stream));
+  double hred[4] = {0, 0, 0, 0};
+  HIPCHK(hipMemcpyAsync(hred, red, sizeof hred, hipMemcpyDeviceToHost, stream));
+  HIPCHK(hipStreamSynchronize(stream));
+  if ((st = nqs_ansatz_bind_params(ans, params, stream)) != NQS_OK) return st;
+  const auto t4 = now();
+  if (stats) {
+    stats->n_unique = U;
+    stats->E = hred[0];
+    stats->var = es.var;
+    stats->B = es.B;
+    stats->grad_norm = std::sqrt(hred[2]);
+    stats->ms_sample = ms(t0, t1);
+    stats->ms_eloc = ms(t1, t2);
+    stats->ms_grad = ms(t2, t3);
+    stats->ms_update = ms(t3, t4);
+  }
   return NQS_OK;
 }
 

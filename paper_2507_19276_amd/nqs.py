@@ -50,6 +50,22 @@ class ElocStats(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class VmcOpts(C.Structure):
+    _fields_ = [("n_draws", C.c_int64), ("sample_seed", C.c_uint64), ("draw_base", C.c_int64),
+                ("max_draws_per_pass", C.c_int64), ("eloc", ElocOpts), ("lr", C.c_double),
+                ("beta1", C.c_double), ("beta2", C.c_double), ("adam_eps", C.c_double),
+                ("weight_decay", C.c_double), ("step", C.c_int64)]
+
+
+class VmcStats(C.Structure):
+    _fields_ = [("n_unique", C.c_int64), ("E", C.c_double), ("var", C.c_double), ("B", C.c_double),
+                ("grad_norm", C.c_double), ("ms_sample", C.c_double), ("ms_eloc", C.c_double),
+                ("ms_grad", C.c_double), ("ms_update", C.c_double)]
+
+    def to_dict(self) -> Dict[str, float]:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 _lib = None
 _p = C.c_void_p
 
@@ -90,6 +106,7 @@ def lib():
                            C.POINTER(C.c_int64), _p]
     L.nqs_sample.argtypes = [_p, _p, C.c_int64, C.c_uint64, C.c_int64, C.c_int32, C.c_int64, C.c_int64, _p, _p,
                              _p, _p, C.POINTER(C.c_int64), _p]
+    L.nqs_vmc_step.argtypes = [_p, _p, _p, C.POINTER(VmcOpts), _p, _p, _p, _p, C.POINTER(VmcStats), _p]
     L.nqs_eloc_workspace_bytes.argtypes = [_p, _p, C.c_int64, C.POINTER(ElocOpts), C.c_int64,
                                            C.POINTER(C.c_size_t)]
     _lib = L
@@ -302,6 +319,25 @@ def eloc(ctx: Context, inst: Instance, ans: Ansatz, samples, counts: Optional[to
                          _ptr(out["etnum"]), _ptr(out["logabs"]), _ptr(out["sign"]), _ptr(out["fsq"]),
                          C.byref(st) if want_stats else None, _p(_stream())))
     return out, (st.to_dict() if want_stats else None)
+
+
+def vmc_step(ctx: Context, inst: Instance, ans: Ansatz, params: torch.Tensor, adam_m: torch.Tensor,
+             adam_v: torch.Tensor, step: int, n_draws: int, sample_seed: int = 0, draw_base: int = 0,
+             max_draws_per_pass: int = 0, eps: float = 0.0, n_eps: int = 0, precision="f64", seed: int = 0,
+             stream_id: int = 0, lr: float = 1e-3, beta1: float = 0.9, beta2: float = 0.999,
+             adam_eps: float = 1e-8, weight_decay: float = 0.0, grad: Optional[torch.Tensor] = None):
+    """One VMC step (see nqs_vmc_step in include/nqs.h): params, adam_m, adam_v
+    (device float64 [n_params]) are updated in place and the ansatz re-bound.
+    Returns the stats dict."""
+    for t in (params, adam_m, adam_v) + ((grad,) if grad is not None else ()):
+        assert t.dtype == torch.float64 and t.is_cuda and t.is_contiguous() and t.numel() == ans.n_params
+    o = VmcOpts(int(n_draws), int(sample_seed) & 0xFFFFFFFFFFFFFFFF, int(draw_base), int(max_draws_per_pass),
+                opts(eps, n_eps, precision, seed, stream_id), float(lr), float(beta1), float(beta2),
+                float(adam_eps), float(weight_decay), int(step))
+    st = VmcStats()
+    check(lib().nqs_vmc_step(ctx.h, inst.h, ans.h, C.byref(o), _ptr(params), _ptr(adam_m), _ptr(adam_v),
+                             _ptr(grad), C.byref(st), _p(_stream())))
+    return st.to_dict()
 
 
 def rows(ctx: Context, inst: Instance, samples, eps: float = 0.0, n_eps: int = 0, seed: int = 0,
