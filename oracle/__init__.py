@@ -47,8 +47,8 @@ def _load():
     lib.or_n_params.argtypes = [_i, _i, _p, _i, _i]
     lib.or_n_params.restype = _i64
     lib.or_amplitudes.argtypes = [_i, _i, _i, _i, _p, _p, _i, _i, _p, _p, _i64, _p, _p, _p, _p, _i]
-    lib.or_sample.argtypes = [_i, _i, _i, _i, _p, _p, _p, _p, _i64, _p]
-    lib.or_sample_unique.argtypes = [_i, _i, _i, _i, _p, _p, _p, _u64, _i64, _i64, _i64, _p, _p]
+    lib.or_sample.argtypes = [_i, _i, _i, _i, _p, _p, _i, _p, _p, _i64, _p]
+    lib.or_sample_unique.argtypes = [_i, _i, _i, _i, _p, _p, _i, _p, _u64, _i64, _i64, _i64, _p, _p]
     lib.or_sample_unique.restype = _i64
     lib.or_grad.argtypes = [_i, _i, _i, _i, _p, _p, _i, _i, _p, _p, _i64, _p, _p, _i]
     lib.or_eloc.argtypes = [_i, _i, _i, _p, _p, _d, _i, _p, _p, _i, _i, _p, _p, _i64, _d, _i, _u64,
@@ -57,6 +57,7 @@ def _load():
                                    _u64, _u64, _p, _i64, _p, _p, _p, _p]
     lib.or_eloc_table.argtypes = [_i, _i, _i, _p, _p, _d, _p, _p, _i64, _p, _i64, _d, _i, _u64,
                                   _u64, _p, _i]
+    lib.or_tucker_rank.argtypes = [_i, _i]
     lib.or_reweighted_cotangent.argtypes = [_i64, _p, _p, _p, _p, _p]
     lib.or_adamw.argtypes = [_i64, _p, _p, _p, _p, _i64, _d, _d, _d, _d, _d]
     _lib = lib
@@ -121,36 +122,47 @@ def connected(K, na, nb, h, eri, sample, e_core=0.0):
     return m, H
 
 
-def n_params(K, chi, parent_ptr, n_hidden, ising: bool = False) -> int:
+def _variant(ising, tensor):
+    return int(bool(ising)) | (int(bool(tensor)) << 1)
+
+
+def tucker_rank(chi: int, d: int) -> int:
+    """chi' = ceil(chi^(2/(d+1))) of a site with d parents (Sec. 2.2)."""
+    return int(_load().or_tucker_rank(chi, d))
+
+
+def n_params(K, chi, parent_ptr, n_hidden, ising: bool = False, tensor: bool = False) -> int:
     pp = _i32(parent_ptr)
-    return int(_load().or_n_params(K, chi, _ptr(pp), n_hidden, int(bool(ising))))
+    return int(_load().or_n_params(K, chi, _ptr(pp), n_hidden, _variant(ising, tensor)))
 
 
 def amplitudes(K, chi, na, nb, parent_ptr, parent_idx, n_hidden, params, samples,
-               nthreads: int = 0, ising: bool = False) -> Dict[str, np.ndarray]:
+               nthreads: int = 0, ising: bool = False, tensor: bool = False) -> Dict[str, np.ndarray]:
     """log|Phi|, sign Phi, log|f|, sign f for every sample (f: cos-RBM, or
-    Ising-RBM when ising)."""
+    Ising-RBM when ising; Phi with the BDG-TensorRNN term when tensor)."""
     pp, pi, prm = _i32(parent_ptr), _i32(parent_idx), _f64(params)
     s = _u64a(samples).reshape(-1, 2)
     N = len(s)
     lphi, lf = np.zeros(N), np.zeros(N)
     sphi, sf = np.zeros(N, dtype=np.int32), np.zeros(N, dtype=np.int32)
-    _load().or_amplitudes(K, chi, na, nb, _ptr(pp), _ptr(pi), n_hidden, int(bool(ising)), _ptr(prm), _ptr(s), N,
+    _load().or_amplitudes(K, chi, na, nb, _ptr(pp), _ptr(pi), n_hidden, _variant(ising, tensor), _ptr(prm), _ptr(s), N,
                           _ptr(lphi), _ptr(sphi), _ptr(lf), _ptr(sf), nthreads)
     return dict(lphi=lphi, sphi=sphi, lf=lf, sf=sf, logabs=lphi + lf, sign=sphi * sf)
 
 
-def sample(K, chi, na, nb, parent_ptr, parent_idx, params, u) -> np.ndarray:
+def sample(K, chi, na, nb, parent_ptr, parent_idx, params, u, tensor: bool = False) -> np.ndarray:
     """Exact autoregressive draws from Phi^2; u is uniform [N, K]."""
     pp, pi, prm = _i32(parent_ptr), _i32(parent_idx), _f64(params)
     uu = _f64(u)
     N = uu.shape[0]
     out = np.zeros((N, 2), dtype=np.uint64)
-    _load().or_sample(K, chi, na, nb, _ptr(pp), _ptr(pi), _ptr(prm), _ptr(uu), N, _ptr(out))
+    _load().or_sample(K, chi, na, nb, _ptr(pp), _ptr(pi), _variant(False, tensor), _ptr(prm), _ptr(uu), N,
+                      _ptr(out))
     return out
 
 
-def sample_unique(K, chi, na, nb, parent_ptr, parent_idx, params, seed: int, n_draws: int, draw_base: int = 0):
+def sample_unique(K, chi, na, nb, parent_ptr, parent_idx, params, seed: int, n_draws: int, draw_base: int = 0,
+                  tensor: bool = False):
     """Draws draw_base .. draw_base+n_draws-1 of the counter-keyed sampler (the
     uniform of draw t at site i comes from Philox4x32-10 at counter
     (t lo, t hi, i, 0x53414D50), key (seed lo, seed hi)), merged into unique
@@ -159,26 +171,27 @@ def sample_unique(K, chi, na, nb, parent_ptr, parent_idx, params, seed: int, n_d
     cap = max(int(n_draws), 1)
     out = np.zeros((cap, 2), dtype=np.uint64)
     cnt = np.zeros(cap, dtype=np.int64)
-    n = _load().or_sample_unique(K, chi, na, nb, _ptr(pp), _ptr(pi), _ptr(prm), int(seed) & 0xFFFFFFFFFFFFFFFF,
+    n = _load().or_sample_unique(K, chi, na, nb, _ptr(pp), _ptr(pi), _variant(False, tensor), _ptr(prm),
+                                 int(seed) & 0xFFFFFFFFFFFFFFFF,
                                  int(draw_base), int(n_draws), cap, _ptr(out), _ptr(cnt))
     return out[:n], cnt[:n]
 
 
 def grad(K, chi, na, nb, parent_ptr, parent_idx, n_hidden, params, samples, g,
-         nthreads: int = 0, ising: bool = False) -> np.ndarray:
+         nthreads: int = 0, ising: bool = False, tensor: bool = False) -> np.ndarray:
     """sum_n g_n d ln|Psi(n)| / d theta over the packed parameter vector."""
     pp, pi, prm = _i32(parent_ptr), _i32(parent_idx), _f64(params)
     s = _u64a(samples).reshape(-1, 2)
     gg = _f64(g)
     out = np.zeros(prm.size)
-    _load().or_grad(K, chi, na, nb, _ptr(pp), _ptr(pi), n_hidden, int(bool(ising)), _ptr(prm), _ptr(s), len(s),
+    _load().or_grad(K, chi, na, nb, _ptr(pp), _ptr(pi), n_hidden, _variant(ising, tensor), _ptr(prm), _ptr(s), len(s),
                     _ptr(gg), _ptr(out), nthreads)
     return out
 
 
 def eloc(K, na, nb, h, eri, chi, parent_ptr, parent_idx, n_hidden, params, samples,
          eps=0.0, n_eps=0, seed=0, stream=0, e_core=0.0, nthreads: int = 0,
-         sample_base: int = 0, ising: bool = False) -> Dict[str, np.ndarray]:
+         sample_base: int = 0, ising: bool = False, tensor: bool = False) -> Dict[str, np.ndarray]:
     """Semi-stochastic local energies and the reweighted numerators; the draws
     of sample i use Philox counter word 0 = sample_base + i."""
     h, eri = _f64(h), _f64(eri)
@@ -189,7 +202,7 @@ def eloc(K, na, nb, h, eri, chi, parent_ptr, parent_idx, n_hidden, params, sampl
     sign = np.zeros(N, dtype=np.int8)
     cnt = {k: np.zeros(N, dtype=np.int64) for k in ("n_det", "n_rem", "n_uniq")}
     rc = _load().or_eloc(K, na, nb, _ptr(h), _ptr(eri), e_core, chi, _ptr(pp), _ptr(pi), n_hidden,
-                         int(bool(ising)), _ptr(prm), _ptr(s), N, eps, n_eps, seed, stream, sample_base, _ptr(out["eloc"]),
+                         _variant(ising, tensor), _ptr(prm), _ptr(s), N, eps, n_eps, seed, stream, sample_base, _ptr(out["eloc"]),
                          _ptr(out["etnum"]), _ptr(out["logabs"]), _ptr(sign), _ptr(out["fsq"]),
                          _ptr(cnt["n_det"]), _ptr(cnt["n_rem"]), _ptr(cnt["n_uniq"]), nthreads)
     if rc != 0:
@@ -200,7 +213,8 @@ def eloc(K, na, nb, h, eri, chi, parent_ptr, parent_idx, n_hidden, params, sampl
 
 
 def eloc_detail(K, na, nb, h, eri, chi, parent_ptr, parent_idx, n_hidden, params, sample,
-                sample_idx, eps, n_eps, seed=0, stream=0, e_core=0.0, ising: bool = False):
+                sample_idx, eps, n_eps, seed=0, stream=0, e_core=0.0, ising: bool = False,
+                tensor: bool = False):
     """One sample: deterministic ranks, drawn ranks in draw order, Q, E_loc."""
     h, eri = _f64(h), _f64(eri)
     pp, pi, prm = _i32(parent_ptr), _i32(parent_idx), _f64(params)
@@ -212,7 +226,7 @@ def eloc_detail(K, na, nb, h, eri, chi, parent_ptr, parent_idx, n_hidden, params
     Q = np.zeros(1, dtype=np.uint64)
     e = np.zeros(1)
     rc = _load().or_eloc_detail(K, na, nb, _ptr(h), _ptr(eri), e_core, chi, _ptr(pp), _ptr(pi),
-                                n_hidden, int(bool(ising)), _ptr(prm), _ptr(s), sample_idx, eps, n_eps, seed, stream,
+                                n_hidden, _variant(ising, tensor), _ptr(prm), _ptr(s), sample_idx, eps, n_eps, seed, stream,
                                 _ptr(det), cap, _ptr(nd), _ptr(draws), _ptr(Q), _ptr(e))
     if rc != 0:
         raise ValueError("sample outside the (n_alpha, n_beta) sector")
@@ -255,15 +269,16 @@ def adamw(params, grad, m, v, step, lr, beta1=0.9, beta2=0.999, eps=1e-8, weight
 
 def vmc_step(K, na, nb, h, eri, chi, parent_ptr, parent_idx, n_hidden, params, m, v, step, n_draws,
              sample_seed, draw_base=0, eps=0.0, n_eps=0, eloc_seed=0, stream=0, lr=1e-3, beta1=0.9,
-             beta2=0.999, adam_eps=1e-8, weight_decay=0.0, e_core=0.0, ising=False):
+             beta2=0.999, adam_eps=1e-8, weight_decay=0.0, e_core=0.0, ising=False, tensor=False):
     """One VMC step in the paper's order: exact draws from Phi^2 merged into
     unique samples with counts, semi-stochastic local energies, the reweighted
     gradient of Eq. (19) (through the cotangent above and the gradient of
     ln|Psi|), and one AdamW update."""
-    uniq, cnt = sample_unique(K, chi, na, nb, parent_ptr, parent_idx, params, sample_seed, n_draws, draw_base)
+    uniq, cnt = sample_unique(K, chi, na, nb, parent_ptr, parent_idx, params, sample_seed, n_draws, draw_base,
+                              tensor=tensor)
     out = eloc(K, na, nb, h, eri, chi, parent_ptr, parent_idx, n_hidden, params, uniq, eps=eps, n_eps=n_eps,
-               seed=eloc_seed, stream=stream, e_core=e_core, ising=ising)
+               seed=eloc_seed, stream=stream, e_core=e_core, ising=ising, tensor=tensor)
     cot, E = reweighted_cotangent(cnt.astype(np.float64), out["etnum"], out["fsq"])
-    g = grad(K, chi, na, nb, parent_ptr, parent_idx, n_hidden, params, uniq, cot, ising=ising)
+    g = grad(K, chi, na, nb, parent_ptr, parent_idx, n_hidden, params, uniq, cot, ising=ising, tensor=tensor)
     p, mm, vv = adamw(params, g, m, v, step, lr, beta1, beta2, adam_eps, weight_decay)
     return dict(params=p, m=mm, v=vv, grad=g, E=E, samples=uniq, counts=cnt, eloc=out)

@@ -17,8 +17,9 @@
 //   * Local energy, Sec. 2.1 Eq. (6); deterministic part Eq. (20), stochastic
 //     part Eq. (21), their sum Eq. (22) (Sec. 2.4).
 //   * MPS-RNN / BDG-RNN amplitude, Sec. 2.1 Eqs. (9)-(10), Sec. 2.2 Eq. (12)
-//     without the tensor term; conditional P_t = h^T eta h; phase from
-//     w^T h + c (Sec. 2.1).
+//     (the BDG-TensorRNN adds the tensor term of Eq. (12) in the Tucker form
+//     of Eq. (13) at every site with two or more parents); conditional
+//     P_t = h^T eta h; phase from w^T h + c (Sec. 2.1).
 //   * Particle-number / S_z masking of the conditionals, Sec. 3 Eqs. (23)-(24).
 //   * Correlator factorisation Psi = f Phi with cos-RBM f, Sec. 2.3
 //     Eqs. (14)-(15), or the Ising-RBM f of Eq. (16) (the cos-RBM argument plus
@@ -250,7 +251,9 @@ void philox4x32_10(const uint32_t ctr_in[4], const uint32_t key_in[2], uint32_t 
 // --------------------------------------------------------------------------
 struct Ansatz {
   int K, chi, na, nb, nh;
-  bool ising;
+  bool ising, tensor;
+  std::vector<int> chiq;                    // Tucker rank chi' of each site (0: no tensor term)
+  std::vector<size_t> offTK, offTU;         // per site: factor matrices [d+1][chi][chi'], cores [4][chi'^(d+1)]
   const int* pptr;
   const int* pidx;
   const double* prm;
@@ -259,10 +262,29 @@ struct Ansatz {
   size_t offB = 0, offWc = 0, offW2 = 0, total = 0;
 };
 
+// smallest integer c >= 1 with c^(d+1) >= chi^2, i.e. ceil(chi^(2/(d+1))) (Sec. 2.2)
+int tucker_rank(int chi, int d) {
+  int c = 1;
+  for (;; ++c) {
+    double p = 1.0;
+    for (int k = 0; k <= d; ++k) p *= c;
+    if (p >= double(chi) * chi) return c;
+  }
+}
+
+size_t ipow(size_t b, int e) {
+  size_t r = 1;
+  for (int k = 0; k < e; ++k) r *= b;
+  return r;
+}
+
+// variant: bit 0 = Ising-RBM correlator (with nh > 0), bit 1 = BDG-TensorRNN
 Ansatz make_ansatz(int K, int chi, int na, int nb, const int* pptr, const int* pidx,
-                   int nh, int ising, const double* prm) {
+                   int nh, int variant, const double* prm) {
   Ansatz A;
-  A.K = K; A.chi = chi; A.na = na; A.nb = nb; A.nh = nh; A.ising = nh > 0 && ising != 0;
+  A.K = K; A.chi = chi; A.na = na; A.nb = nb; A.nh = nh;
+  A.ising = nh > 0 && (variant & 1) != 0;
+  A.tensor = (variant & 2) != 0;
   A.pptr = pptr; A.pidx = pidx; A.prm = prm;
   size_t o = 0;
   A.offM.resize(pptr[K]);
@@ -278,6 +300,22 @@ Ansatz make_ansatz(int K, int chi, int na, int nb, const int* pptr, const int* p
   A.offWc = o; o += size_t(nh) * 2 * K;
   A.offW2 = o;
   if (A.ising) o += size_t(nh) * 4 * K * K;   // [nh][2K][2K]
+  // tensor block (after everything else): per site with d >= 2 parents the
+  // factor matrices K^(0) (output mode) and K^(1..d) (one per parent, in
+  // ascending parent order), each chi x chi' row-major, shared by the local
+  // states; then the cores U^s, s = 0..3, each chi'^(d+1) with index order
+  // [i'][a_1]...[a_d] row-major
+  A.chiq.assign(K, 0);
+  A.offTK.assign(K, 0);
+  A.offTU.assign(K, 0);
+  for (int i = 0; i < K && A.tensor; ++i) {
+    const int d = pptr[i + 1] - pptr[i];
+    if (d < 2) continue;
+    const int q = tucker_rank(chi, d);
+    A.chiq[i] = q;
+    A.offTK[i] = o; o += size_t(d + 1) * chi * q;
+    A.offTU[i] = o; o += 4 * ipow(q, d + 1);
+  }
   A.total = o;
   return A;
 }
@@ -297,9 +335,50 @@ struct Trace {  // per-site forward quantities kept for the reverse sweep
   std::vector<int> s;        // [K]
 };
 
-// candidates h_i^s = sum_{j in N(i)} M_ij^s h_j + v_i^s for s = 0..3
+// Tucker form of the tensor term at site i (Eq. (13)): the parents' states
+// projected on their factor matrices, p_j = K^(j)^T h_(parent j) [d][chi'],
+// then q^s[i'] = sum_a U^s[i'][a_1..a_d] prod_j p_j[a_j] and
+// t^s = K^(0) q^s.  Returns q [4][chi'] and p [d][chi'].
+void tensor_forward(const Ansatz& A, int i, const std::vector<double>& carried, std::vector<double>& p,
+                    std::vector<double>& q) {
+  const int chi = A.chi, qd = A.chiq[i], d = A.pptr[i + 1] - A.pptr[i];
+  p.assign(size_t(d) * qd, 0.0);
+  for (int j = 0; j < d; ++j) {
+    const double* Kj = A.prm + A.offTK[i] + size_t(j + 1) * chi * qd;
+    const double* hj = carried.data() + size_t(A.pidx[A.pptr[i] + j]) * chi;
+    for (int a = 0; a < qd; ++a) {
+      double acc = 0.0;
+      for (int v = 0; v < chi; ++v) acc += Kj[size_t(v) * qd + a] * hj[v];
+      p[size_t(j) * qd + a] = acc;
+    }
+  }
+  const size_t na = ipow(qd, d);   // multi-indices a = (a_1..a_d), a_d fastest
+  q.assign(size_t(4) * qd, 0.0);
+  std::vector<int> a(d);
+  for (int s = 0; s < 4; ++s)
+    for (int ip = 0; ip < qd; ++ip) {
+      const double* U = A.prm + A.offTU[i] + (size_t(s) * qd + ip) * na;
+      double acc = 0.0;
+      for (size_t f = 0; f < na; ++f) {
+        size_t r = f;
+        double prod = 1.0;
+        for (int j = d - 1; j >= 0; --j) {
+          a[j] = int(r % qd);
+          r /= qd;
+        }
+        for (int j = 0; j < d; ++j) prod *= p[size_t(j) * qd + a[j]];
+        acc += U[f] * prod;
+      }
+      q[size_t(s) * qd + ip] = acc;
+    }
+}
+
+// candidates h_i^s = sum_{j in N(i)} M_ij^s h_j [+ K^(0) q^s] + v_i^s for s = 0..3
 void site_candidates(const Ansatz& A, int i, const std::vector<double>& carried, double* cand) {
   const int chi = A.chi;
+  std::vector<double> p, q;
+  const int qd = A.chiq[i];
+  if (qd) tensor_forward(A, i, carried, p, q);
   for (int s = 0; s < 4; ++s) {
     for (int u = 0; u < chi; ++u) {
       double acc = 0.0;
@@ -308,6 +387,12 @@ void site_candidates(const Ansatz& A, int i, const std::vector<double>& carried,
         const double* M = A.prm + A.offM[e] + size_t(s) * chi * chi + size_t(u) * chi;
         const double* hj = carried.data() + size_t(j) * chi;
         for (int k = 0; k < chi; ++k) acc += M[k] * hj[k];
+      }
+      if (qd) {
+        const double* K0 = A.prm + A.offTK[i] + size_t(u) * qd;
+        double t = 0.0;
+        for (int ip = 0; ip < qd; ++ip) t += K0[ip] * q[size_t(s) * qd + ip];
+        acc += t;
       }
       cand[s * chi + u] = acc + A.prm[A.offV[i] + s * chi + u];
     }
@@ -411,6 +496,62 @@ Amp amp_eval(const Ansatz& A, const Det& n) {
 // --------------------------------------------------------------------------
 // reverse sweep: g * d ln|Psi(n)| / d theta accumulated into grad
 // --------------------------------------------------------------------------
+
+// reverse of the tensor term at site i, given dc = d/d h_i^s [4][chi]:
+// dK0 = sum_s dc^s q^s^T, dq^s = K0^T dc^s, dU^s[i'][a] = dq^s[i'] prod_j p_j[a_j],
+// dp_j[b] = sum_{s,i',a: a_j = b} dq^s[i'] U^s[i'][a] prod_{l != j} p_l[a_l],
+// dK^(j) = h_j dp_j^T, d h_j += K^(j) dp_j
+void tensor_reverse(const Ansatz& A, int i, const std::vector<double>& carried, const double* dc, double* grad,
+                    std::vector<double>& dcarry) {
+  const int chi = A.chi, qd = A.chiq[i], d = A.pptr[i + 1] - A.pptr[i];
+  std::vector<double> p, q;
+  tensor_forward(A, i, carried, p, q);
+  const double* K0 = A.prm + A.offTK[i];
+  double* dK0 = grad + A.offTK[i];
+  std::vector<double> dq(size_t(4) * qd, 0.0);
+  for (int s = 0; s < 4; ++s)
+    for (int u = 0; u < chi; ++u)
+      for (int ip = 0; ip < qd; ++ip) {
+        dK0[size_t(u) * qd + ip] += dc[s * chi + u] * q[size_t(s) * qd + ip];
+        dq[size_t(s) * qd + ip] += K0[size_t(u) * qd + ip] * dc[s * chi + u];
+      }
+  const size_t na = ipow(qd, d);
+  std::vector<double> dp(size_t(d) * qd, 0.0);
+  std::vector<int> a(d);
+  for (int s = 0; s < 4; ++s)
+    for (int ip = 0; ip < qd; ++ip) {
+      const double* U = A.prm + A.offTU[i] + (size_t(s) * qd + ip) * na;
+      double* dU = grad + A.offTU[i] + (size_t(s) * qd + ip) * na;
+      const double g = dq[size_t(s) * qd + ip];
+      for (size_t f = 0; f < na; ++f) {
+        size_t r = f;
+        for (int j = d - 1; j >= 0; --j) {
+          a[j] = int(r % qd);
+          r /= qd;
+        }
+        double prod = 1.0;
+        for (int j = 0; j < d; ++j) prod *= p[size_t(j) * qd + a[j]];
+        dU[f] += g * prod;
+        for (int j = 0; j < d; ++j) {
+          double other = 1.0;
+          for (int l = 0; l < d; ++l)
+            if (l != j) other *= p[size_t(l) * qd + a[l]];
+          dp[size_t(j) * qd + a[j]] += g * U[f] * other;
+        }
+      }
+    }
+  for (int j = 0; j < d; ++j) {
+    const int par = A.pidx[A.pptr[i] + j];
+    const double* Kj = A.prm + A.offTK[i] + size_t(j + 1) * chi * qd;
+    double* dKj = grad + A.offTK[i] + size_t(j + 1) * chi * qd;
+    const double* hj = carried.data() + size_t(par) * chi;
+    for (int v = 0; v < chi; ++v)
+      for (int b = 0; b < qd; ++b) {
+        dKj[size_t(v) * qd + b] += hj[v] * dp[size_t(j) * qd + b];
+        dcarry[size_t(par) * chi + v] += Kj[size_t(v) * qd + b] * dp[size_t(j) * qd + b];
+      }
+  }
+}
 void grad_accumulate(const Ansatz& A, const Det& n, double g, double* grad) {
   const int K = A.K, chi = A.chi;
   Trace tr;
@@ -461,6 +602,7 @@ void grad_accumulate(const Ansatz& A, const Det& n, double g, double* grad) {
         }
       }
     }
+    if (A.chiq[i]) tensor_reverse(A, i, carried, dcand.data(), grad, dcarry);
   }
   if (A.nh) {
     const int nv = 2 * K;
@@ -622,16 +764,18 @@ int64_t or_connected(int K, int na, int nb, const double* h, const double* eri, 
   return int64_t(c.size());
 }
 
-int64_t or_n_params(int K, int chi, const int* pptr, int nh, int ising) {
-  Ansatz A = make_ansatz(K, chi, 0, 0, pptr, nullptr, nh, ising, nullptr);
+int or_tucker_rank(int chi, int d) { return tucker_rank(chi, d); }
+
+int64_t or_n_params(int K, int chi, const int* pptr, int nh, int variant) {
+  Ansatz A = make_ansatz(K, chi, 0, 0, pptr, nullptr, nh, variant, nullptr);
   return int64_t(A.total);
 }
 
 // log|Phi|, sign Phi, log|f|, sign f for N samples
-int or_amplitudes(int K, int chi, int na, int nb, const int* pptr, const int* pidx, int nh, int ising,
+int or_amplitudes(int K, int chi, int na, int nb, const int* pptr, const int* pidx, int nh, int variant,
                   const double* prm, const uint64_t* samples, int64_t N, double* lphi,
                   int* sphi, double* lf, int* sf, int nthreads) {
-  Ansatz A = make_ansatz(K, chi, na, nb, pptr, pidx, nh, ising, prm);
+  Ansatz A = make_ansatz(K, chi, na, nb, pptr, pidx, nh, variant, prm);
 #pragma omp parallel for schedule(dynamic, 16) num_threads(nthreads_or_default(nthreads))
   for (int64_t i = 0; i < N; ++i) {
     Det d = det_from_words(K, samples + 2 * i);
@@ -654,9 +798,9 @@ double sampler_uniform(uint64_t seed, uint64_t t, int i) {
 }
 
 // exact autoregressive draws from Phi^2 using the caller's uniforms u[N][K]
-int or_sample(int K, int chi, int na, int nb, const int* pptr, const int* pidx,
+int or_sample(int K, int chi, int na, int nb, const int* pptr, const int* pidx, int variant,
               const double* prm, const double* u, int64_t N, uint64_t* out) {
-  Ansatz A = make_ansatz(K, chi, na, nb, pptr, pidx, 0, 0, prm);
+  Ansatz A = make_ansatz(K, chi, na, nb, pptr, pidx, 0, variant & 2, prm);
   for (int64_t t = 0; t < N; ++t) {
     Det d;
     d.n = 2 * K;
@@ -696,13 +840,14 @@ int or_sample(int K, int chi, int na, int nb, const int* pptr, const int* pidx,
 // draws t = t0 .. t0+N-1 of the counter-keyed sampler (uniforms from
 // sampler_uniform), then merged: unique ONVs in ascending (hi, lo) order with
 // their counts; returns the number of unique ONVs (at most cap are written)
-int64_t or_sample_unique(int K, int chi, int na, int nb, const int* pptr, const int* pidx, const double* prm,
-                         uint64_t seed, int64_t t0, int64_t N, int64_t cap, uint64_t* out, int64_t* counts) {
+int64_t or_sample_unique(int K, int chi, int na, int nb, const int* pptr, const int* pidx, int variant,
+                         const double* prm, uint64_t seed, int64_t t0, int64_t N, int64_t cap, uint64_t* out,
+                         int64_t* counts) {
   std::vector<double> u(size_t(N) * K);
   for (int64_t t = 0; t < N; ++t)
     for (int i = 0; i < K; ++i) u[size_t(t) * K + i] = sampler_uniform(seed, uint64_t(t0 + t), i);
   std::vector<uint64_t> d(size_t(N) * 2);
-  or_sample(K, chi, na, nb, pptr, pidx, prm, u.data(), N, d.data());
+  or_sample(K, chi, na, nb, pptr, pidx, variant, prm, u.data(), N, d.data());
   std::map<std::pair<uint64_t, uint64_t>, int64_t> merged;   // ordered by (hi, lo)
   for (int64_t t = 0; t < N; ++t) ++merged[{d[2 * t + 1], d[2 * t]}];
   int64_t k = 0;
@@ -718,10 +863,10 @@ int64_t or_sample_unique(int K, int chi, int na, int nb, const int* pptr, const 
 }
 
 // sum_n g_n d ln|Psi(n)| / d theta, accumulated into grad (length n_params)
-int or_grad(int K, int chi, int na, int nb, const int* pptr, const int* pidx, int nh, int ising,
+int or_grad(int K, int chi, int na, int nb, const int* pptr, const int* pidx, int nh, int variant,
             const double* prm, const uint64_t* samples, int64_t N, const double* g,
             double* grad, int nthreads) {
-  Ansatz A = make_ansatz(K, chi, na, nb, pptr, pidx, nh, ising, prm);
+  Ansatz A = make_ansatz(K, chi, na, nb, pptr, pidx, nh, variant, prm);
   const int nt = nthreads_or_default(nthreads);
   std::vector<std::vector<double>> part(nt, std::vector<double>(A.total, 0.0));
 #pragma omp parallel for schedule(static) num_threads(nt)
@@ -738,13 +883,13 @@ int or_grad(int K, int chi, int na, int nb, const int* pptr, const int* pidx, in
 // draw counter of sample i is sample_base + i.  Optional per-sample counters
 // n_det / n_rem / n_uniq (nullable).
 int or_eloc(int K, int na, int nb, const double* h, const double* eri, double ecore,
-            int chi, const int* pptr, const int* pidx, int nh, int ising, const double* prm,
+            int chi, const int* pptr, const int* pidx, int nh, int variant, const double* prm,
             const uint64_t* samples, int64_t N, double eps, int n_eps, uint64_t seed,
             uint64_t stream, int64_t sample_base, double* eloc, double* etnum, double* logabs,
             int8_t* sign, double* fsq, int64_t* n_det, int64_t* n_rem, int64_t* n_uniq,
             int nthreads) {
   Ham H{K, h, eri, ecore};
-  Ansatz A = make_ansatz(K, chi, na, nb, pptr, pidx, nh, ising, prm);
+  Ansatz A = make_ansatz(K, chi, na, nb, pptr, pidx, nh, variant, prm);
   for (int64_t i = 0; i < N; ++i) {
     Det d = det_from_words(K, samples + 2 * i);
     if (!count_ok(d, K, na, nb)) return -1;
@@ -765,12 +910,12 @@ int or_eloc(int K, int na, int nb, const double* h, const double* eri, double ec
 
 // one sample in detail: deterministic ranks, drawn ranks (in draw order), Q
 int or_eloc_detail(int K, int na, int nb, const double* h, const double* eri, double ecore,
-                   int chi, const int* pptr, const int* pidx, int nh, int ising, const double* prm,
+                   int chi, const int* pptr, const int* pidx, int nh, int variant, const double* prm,
                    const uint64_t* sample, int64_t sample_idx, double eps, int n_eps,
                    uint64_t seed, uint64_t stream, int64_t* det_ranks, int64_t det_cap,
                    int64_t* n_det_out, int64_t* draw_ranks, uint64_t* Q_out, double* eloc_out) {
   Ham H{K, h, eri, ecore};
-  Ansatz A = make_ansatz(K, chi, na, nb, pptr, pidx, nh, ising, prm);
+  Ansatz A = make_ansatz(K, chi, na, nb, pptr, pidx, nh, variant, prm);
   Det d = det_from_words(K, sample);
   if (!count_ok(d, K, na, nb)) return -1;
   auto amp = [&](const Det& x) { return amp_eval(A, x); };

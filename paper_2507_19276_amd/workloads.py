@@ -31,7 +31,11 @@ Conventions (shared by every consumer):
   (h_out[u] = sum_k M[u, k] h_in[k]); then v_i^s (4 x chi), eta_i (chi),
   w_i (chi), c_i (1).  After all sites the cos-RBM correlator: b (N_h) then
   W (N_h x 2K, row-major, column P = spin orbital P); with the Ising-RBM
-  correlator, then W2 (N_h x 2K x 2K, row-major: W2[k, P, Q]).
+  correlator, then W2 (N_h x 2K x 2K, row-major: W2[k, P, Q]).  With the
+  BDG-TensorRNN term, last, per site i ascending with d_i >= 2 parents: the
+  factor matrices K^(0) (output mode) and K^(1..d) (one per parent, ascending),
+  each chi x chi' row-major, then the cores U^s (s = 0..3), each chi'^(d+1)
+  with index order [i', a_1, ..., a_d]; chi' = ceil(chi^(2/(d+1))).
 """
 from __future__ import annotations
 
@@ -174,18 +178,43 @@ def lattice_integrals(dims: Tuple[int, int, int], seed: int, ell: float = 2.0) -
 # ansatz parameters
 # ---------------------------------------------------------------------------
 
-def n_params(K: int, chi: int, parent_ptr: np.ndarray, n_hidden: int, ising: bool = False) -> int:
+def tucker_rank(chi: int, d: int) -> int:
+    """Shape of the tensor block: the smallest c with c^(d+1) >= chi^2."""
+    c = 1
+    while c ** (d + 1) < chi * chi:
+        c += 1
+    return c
+
+
+def tensor_block_sizes(K: int, chi: int, parent_ptr: np.ndarray) -> List[Tuple[int, int, int]]:
+    """(site, d, chi') of every site carrying a tensor term (d >= 2)."""
+    out = []
+    for i in range(K):
+        d = int(parent_ptr[i + 1] - parent_ptr[i])
+        if d >= 2:
+            out.append((i, d, tucker_rank(chi, d)))
+    return out
+
+
+def n_params(K: int, chi: int, parent_ptr: np.ndarray, n_hidden: int, ising: bool = False,
+             tensor: bool = False) -> int:
     sum_d = int(parent_ptr[-1])
     corr = n_hidden * (2 * K + 1) + (n_hidden * 4 * K * K if ising else 0)
-    return sum_d * 4 * chi * chi + K * (4 * chi + chi + chi + 1) + (corr if n_hidden else 0)
+    tens = sum((d + 1) * chi * q + 4 * q ** (d + 1) for _, d, q in tensor_block_sizes(K, chi, parent_ptr)) \
+        if tensor else 0
+    return sum_d * 4 * chi * chi + K * (4 * chi + chi + chi + 1) + (corr if n_hidden else 0) + tens
 
 
 def ansatz_params(K: int, chi: int, parent_ptr: np.ndarray, parent_idx: np.ndarray,
-                  n_hidden: int, seed: int, corr_scale: float = 0.1, ising: bool = False) -> np.ndarray:
+                  n_hidden: int, seed: int, corr_scale: float = 0.1, ising: bool = False,
+                  tensor: bool = False, tensor_scale: float = 0.3) -> np.ndarray:
     """Random-init parameters in the packed layout (module docstring):
     M ~ N(0, var 1/(chi*max(d_i,1))), v ~ N(0,1), eta ~ U[0.5,1.5], w, c ~ N(0,1),
     correlator b, W ~ N(0, corr_scale^2), Ising W2 ~ N(0, corr_scale^2 / K) (its
-    ~K^2 occupied pairs then spread theta about as much as W's ~K terms)."""
+    ~K^2 occupied pairs then spread theta about as much as W's ~K terms);
+    tensor factors K ~ N(0, 1/chi), cores U ~ N(0, tensor_scale^2 / chi'^d) (the term is quadratic
+    in the hidden states at two parents: at tensor_scale = 1 random states grow
+    without bound along a K = 20 chain, at 0.3 the term shifts log|Phi| by ~0.5)."""
     rng = np.random.default_rng(seed)
     out: List[np.ndarray] = []
     for i in range(K):
@@ -202,8 +231,12 @@ def ansatz_params(K: int, chi: int, parent_ptr: np.ndarray, parent_idx: np.ndarr
         out.append(rng.standard_normal(n_hidden * 2 * K) * corr_scale)    # W
         if ising:
             out.append(rng.standard_normal(n_hidden * 4 * K * K) * (corr_scale / math.sqrt(K)))   # W2
+    if tensor:
+        for _, d, q in tensor_block_sizes(K, chi, parent_ptr):
+            out.append(rng.standard_normal((d + 1) * chi * q) / math.sqrt(chi))                 # K^(0..d)
+            out.append(rng.standard_normal(4 * q ** (d + 1)) * (tensor_scale / math.sqrt(q ** d)))   # U^s
     p = np.concatenate(out).astype(np.float64)
-    assert p.size == n_params(K, chi, parent_ptr, n_hidden, ising)
+    assert p.size == n_params(K, chi, parent_ptr, n_hidden, ising, tensor)
     return p
 
 
@@ -290,6 +323,7 @@ class Workload:
     seed: int
     precision: str
     ising: bool = False
+    tensor: bool = False
 
     @property
     def n_samples(self) -> int:
@@ -303,6 +337,8 @@ def _graph(kind: str, K: int):
         return graph_nn_nnn(K)
     if kind == "lattice332":
         return graph_lattice((3, 3, 2))
+    if kind == "lattice222":
+        return graph_lattice((2, 2, 2))
     raise ValueError(kind)
 
 
@@ -319,6 +355,11 @@ def make_workload(name: str, n_samples: Optional[int] = None, seed_offset: int =
     c4b K=18 on 3x3x2, 9a+9b, lattice integrals, lattice graph chi=64,
         8192 samples, eps=1e-2, N_eps=100
     c1i c1 with an Ising-RBM correlator, N_h = 2 N_v = 24
+    c1t K=6, 3a+3b, NN+NNN graph, BDG-TensorRNN chi=4 (chi' = 3), 256 samples
+    c8t K=8 on a 2x2x2 lattice (in-degrees up to 3), 4a+4b, BDG-TensorRNN chi=4
+        (chi' = 3 at two parents, 2 at three), 256 samples
+    c2t K=20, 10a+10b, chain integrals, NN+NNN graph, BDG(2)-TensorRNN chi=16
+        (chi' = 7), 4096 unique samples, eps=1e-3, N_eps=64
     c2i c2 with an Ising-RBM correlator, N_h = 2 N_v = 80 (alpha = 2, as in
         Sec. 4), 4096 unique samples
     """
@@ -338,25 +379,34 @@ def make_workload(name: str, n_samples: Optional[int] = None, seed_offset: int =
                     eps=0.0, neps=0, prec="f64", s=6, ising=True),
         "c2i": dict(K=20, ne=(10, 10), integ="chain", graph="chain", chi=16, nh=80, N=4096, uniq=True,
                     eps=1e-3, neps=64, prec="f32", s=7, ising=True),
+        "c1t": dict(K=6, ne=(3, 3), integ="chain", graph="nnn", chi=4, nh=0, N=256, uniq=False,
+                    eps=0.0, neps=0, prec="f64", s=8, tensor=True),
+        "c8t": dict(K=8, ne=(4, 4), integ="lattice222", graph="lattice222", chi=4, nh=0, N=256, uniq=False,
+                    eps=0.0, neps=0, prec="f64", s=9, tensor=True),
+        "c2t": dict(K=20, ne=(10, 10), integ="chain", graph="nnn", chi=16, nh=0, N=4096, uniq=True,
+                    eps=1e-3, neps=64, prec="f32", s=10, tensor=True),
     }[name]
     ising = spec.get("ising", False)
+    tensor = spec.get("tensor", False)
     K = spec["K"]
     seed = base + 100 * spec["s"]
     if spec["integ"] == "chain":
         h, eri = chain_integrals(K, seed + 1)
     elif spec["integ"] == "dense":
         h, eri = dense_integrals(K, seed + 1)
+    elif spec["integ"] == "lattice222":
+        h, eri = lattice_integrals((2, 2, 2), seed + 1)
     else:
         h, eri = lattice_integrals((3, 3, 2), seed + 1)
     pp, pi = _graph(spec["graph"], K)
-    params = ansatz_params(K, spec["chi"], pp, pi, spec["nh"], seed + 2, ising=ising)
+    params = ansatz_params(K, spec["chi"], pp, pi, spec["nh"], seed + 2, ising=ising, tensor=tensor)
     N = spec["N"] if n_samples is None else n_samples
     na, nb = spec["ne"]
     samples = random_onvs(K, na, nb, N, seed + 3, unique=spec["uniq"])
     return Workload(name=name, K=K, n_alpha=na, n_beta=nb, h=h, eri=eri, e_core=0.0,
                     chi=spec["chi"], parent_ptr=pp, parent_idx=pi, n_hidden=spec["nh"],
                     params=params, samples=samples, eps=spec["eps"], n_eps=spec["neps"],
-                    seed=seed + 4, precision=spec["prec"], ising=ising)
+                    seed=seed + 4, precision=spec["prec"], ising=ising, tensor=tensor)
 
 
 def serving_instances(seed_offset: int = 0) -> List[Dict]:
