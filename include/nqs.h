@@ -158,17 +158,28 @@ nqs_status nqs_connected(nqs_ctx* ctx, const nqs_instance* inst, const uint64_t*
  * per hidden unit, all ordered pairs and the diagonal). */
 #define NQS_CORR_COS_RBM 0
 #define NQS_CORR_ISING_RBM 1
+/* Flag added to the correlator kind: BDG-TensorRNN (Sec. 2.2, Eqs. (12)-(13)),
+ * the tensor term in Tucker form at every site with d = 2 or 3 parents,
+ * chi' = ceil(chi^(2/(d+1))); its parameters follow everything else: per such
+ * site ascending, K^(0) (output mode) and K^(1..d) (one per parent, ascending),
+ * each chi x chi' row-major, then U^s for s = 0..3, each chi'^(d+1) with index
+ * order [i', a_1, .., a_d].  Forward, local energy and sampling run in FP64 and
+ * FP32 (rows evaluated from site 0; NQS_EUNSUPPORTED for BF16, for the
+ * adjoint, for a site with more than 3 parents, and when a thread's ring of
+ * W x ceil4(chi) states does not fit the LDS). */
+#define NQS_ANSATZ_TENSOR 0x10
 
 /* Describe the ansatz: K sites, electron counts of the sector (they define the
  * mask of Sec. 3), bond dimension chi (1..64), parent CSR (host arrays),
- * n_hidden correlator units (0 = no correlator) and the correlator kind.
+ * n_hidden correlator units (0 = no correlator) and the variant: the
+ * correlator kind, optionally | NQS_ANSATZ_TENSOR.
  * Packed parameters: the BDG-RNN block, then b (n_hidden), W (n_hidden x 2K),
  * and for the Ising-RBM W2 (n_hidden x 2K x 2K, row-major).  EINVAL for a
  * malformed graph or an unknown correlator.  The Ising-RBM local energy keeps
  * a table of N x 2K x n_hidden doubles (8 N 2K n_hidden bytes of workspace). */
 nqs_status nqs_ansatz_create(nqs_ctx* ctx, int K, int n_alpha, int n_beta, int chi,
                              const int32_t* parent_ptr, const int32_t* parent_idx, int n_hidden,
-                             int32_t correlator, nqs_ansatz** out);
+                             int32_t variant, nqs_ansatz** out);
 nqs_status nqs_ansatz_destroy(nqs_ansatz* ans);
 /* Length of the packed parameter vector. */
 int64_t nqs_ansatz_n_params(const nqs_ansatz* ans);

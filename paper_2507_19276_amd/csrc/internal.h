@@ -57,6 +57,18 @@ struct PsiParams {
   bool folded;                   // operands carry sqrt(eta) (see k_psi_mt); never with a carried-state store
 };
 
+// BDG-TensorRNN forward (tensor_rnn.hip), one precision T.
+template <typename T>
+struct TnParams {
+  int K, chi, chip, rw, na, nb, W;   // rw = ceil4(chi): units of a carried state in the ring
+  const T* prm;                  // kernel layout: per edge M^T [4][chip][chip]; per site v [4][chip],
+                                 // eta, w [chip], c; per tensor site K0^T [chi'][chip],
+                                 // K_j [d][chip][16], U [4][chi'^(d+1)]
+  const int* pptr;               // [K+1] parents of site i: pptr[i]..pptr[i+1]-1
+  const int* edge;               // [edges][2]: offset of M^T, ring slot of the parent
+  const int* site;               // [K][8]: offV, offEta, offW, offC, chi' (0: none), offK0, offKj, offU
+};
+
 // Adjoint (backward) layouts for one precision T.
 template <typename T>
 struct AdjParams {
@@ -235,6 +247,16 @@ hipError_t launch_unique(const uint64_t* m, const double* lphi, const int8_t* sp
                          int64_t N, bool two_words, const UniqueScratch& w, int64_t cap, uint64_t* um, int64_t* ucnt,
                          double* ul, int8_t* us, int64_t* nu, hipStream_t st);
 hipError_t launch_fill_i64(int64_t* p, int64_t n, int64_t v, hipStream_t st);
+// ---- BDG-TensorRNN (tensor_rnn.hip) --------------------------------------
+size_t tn_lds_bytes(int W, int rw, int precision);
+hipError_t launch_psi_tn_f64(const TnParams<double>& P, const uint64_t* m, int64_t R, double* lphi, int8_t* sphi,
+                             hipStream_t st);
+hipError_t launch_psi_tn_f32(const TnParams<float>& P, const uint64_t* m, int64_t R, double* lphi, int8_t* sphi,
+                             hipStream_t st);
+hipError_t launch_sample_tn_f64(const TnParams<double>& P, int64_t R, double* lphi, int8_t* sphi, hipStream_t st,
+                                const SampleArgs& SA);
+hipError_t launch_sample_tn_f32(const TnParams<float>& P, int64_t R, double* lphi, int8_t* sphi, hipStream_t st,
+                                const SampleArgs& SA);
 // ---- VMC step (vmc.hip) -------------------------------------------------
 hipError_t launch_i64_to_f64(int64_t n, const int64_t* a, double* b, hipStream_t st);
 // cot_n = 2 c_n (etnum_n - fsq_n E) / S with S = sum c fsq, E = sum c etnum / S;

@@ -222,6 +222,18 @@ struct nqs_ansatz {
   double* d_cW1t = nullptr; // Ising-RBM: W transposed [2K][nh]
   double* d_cS = nullptr;   // Ising-RBM: (W2 + W2^T)/2 as [2K][2K][nh]
   float* d_cS32 = nullptr;  // the same in FP32
+  // BDG-TensorRNN: per site chi' (0: no tensor term) and the packed offsets of
+  // the factor matrices and cores; kernel tables and per-precision layouts
+  bool tensor = false;
+  std::vector<int> tq;
+  std::vector<int64_t> offTK, offTU;
+  int* d_tn_edge = nullptr;
+  int* d_tn_site = nullptr;
+  double* tn64 = nullptr;
+  float* tn32 = nullptr;
+  int64_t tn_size = 0;
+  bool tn_f64_ok = true;    // the FP64 ring fits the LDS
+  std::vector<int> tn_edge_host, tn_site_host;
   int64_t* d_offM = nullptr;
   int64_t* d_offV = nullptr;
   int64_t* d_offEta = nullptr;
@@ -231,7 +243,8 @@ struct nqs_ansatz {
     F64.free_all();
     F32.free_all();
     for (void* p : {(void*)d_pptr, (void*)d_pidx, (void*)d_slot, (void*)d_fptr, (void*)d_fslot, (void*)bfA,
-                    (void*)d_cb, (void*)d_cW, (void*)d_cW1t, (void*)d_cS, (void*)d_cS32, (void*)d_offM, (void*)d_offV,
+                    (void*)d_cb, (void*)d_cW, (void*)d_cW1t, (void*)d_cS, (void*)d_cS32, (void*)d_tn_edge,
+                    (void*)d_tn_site, (void*)tn64, (void*)tn32, (void*)d_offM, (void*)d_offV,
                     (void*)d_offEta})
       if (p) (void)hipFree(p);
   }
@@ -257,6 +270,13 @@ struct nqs_ansatz {
   // forward layout for amplitudes without a carried-state store
   const PsiLayout<double>& fwd64() const { return has_fold ? F64 : L64; }
   const PsiLayout<float>& fwd32() const { return has_fold ? F32 : L32; }
+  template <typename T>
+  TnParams<T> tn(const T* prm) const {
+    TnParams<T> P;
+    P.K = K; P.chi = chi; P.chip = chip; P.rw = (chi + 3) / 4 * 4; P.na = na; P.nb = nb; P.W = W;
+    P.prm = prm; P.pptr = d_pptr; P.edge = d_tn_edge; P.site = d_tn_site;
+    return P;
+  }
   CorrParams corr() const {
     CorrParams C;
     C.K = K; C.nh = nh; C.b = d_cb; C.W = d_cW;
@@ -445,6 +465,48 @@ nqs_status build_bf16(nqs_ansatz* a, const std::vector<double>& prm, bool fold) 
   return upload(&a->bfA, A);
 }
 
+// BDG-TensorRNN kernel layout (see TnParams) in FP64 and FP32, zero-padded to
+// chip units and to 16 projection columns
+nqs_status build_tn(nqs_ansatz* a, const std::vector<double>& prm) {
+  const int K = a->K, chi = a->chi, cp = a->chip;
+  std::vector<double> L(size_t(a->tn_size), 0.0);
+  for (int i = 0; i < K; ++i) {
+    for (int e = a->pptr[i]; e < a->pptr[i + 1]; ++e) {
+      double* Mt = L.data() + a->tn_edge_host[2 * e];
+      for (int s = 0; s < 4; ++s)
+        for (int u = 0; u < chi; ++u)
+          for (int k = 0; k < chi; ++k)
+            Mt[(size_t(s) * cp + k) * cp + u] = prm[a->offM[e] + (size_t(s) * chi + u) * chi + k];
+    }
+    const int* st8 = a->tn_site_host.data() + 8 * i;
+    for (int s = 0; s < 4; ++s)
+      for (int u = 0; u < chi; ++u) L[st8[0] + s * cp + u] = prm[a->offV[i] + s * chi + u];
+    for (int u = 0; u < chi; ++u) {
+      L[st8[1] + u] = prm[a->offEta[i] + u];
+      L[st8[2] + u] = prm[a->offW[i] + u];
+    }
+    L[st8[3]] = prm[a->offC[i]];
+    const int q = a->tq[i], d = a->pptr[i + 1] - a->pptr[i];
+    if (!q) continue;
+    const double* Kp = prm.data() + a->offTK[i];   // K^(0..d), each [chi][q]
+    for (int ip = 0; ip < q; ++ip)
+      for (int u = 0; u < chi; ++u) L[st8[5] + size_t(ip) * cp + u] = Kp[size_t(u) * q + ip];
+    for (int j = 0; j < d; ++j)
+      for (int v = 0; v < chi; ++v)
+        for (int b = 0; b < q; ++b)
+          L[st8[6] + (size_t(j) * cp + v) * 16 + b] = Kp[size_t(j + 1) * chi * q + size_t(v) * q + b];
+    int64_t qd = 1;
+    for (int k = 0; k <= d; ++k) qd *= q;
+    for (int64_t f = 0; f < 4 * qd; ++f) L[st8[7] + f] = prm[a->offTU[i] + f];
+  }
+  if (a->tn64) { (void)hipFree(a->tn64); a->tn64 = nullptr; }
+  if (a->tn32) { (void)hipFree(a->tn32); a->tn32 = nullptr; }
+  nqs_status st;
+  if ((st = upload(&a->tn64, L)) != NQS_OK) return st;
+  std::vector<float> L32(L.begin(), L.end());
+  return upload(&a->tn32, L32);
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -597,10 +659,11 @@ int64_t nqs_instance_n_conn(const nqs_instance* inst) { return inst ? int64_t(in
 
 nqs_status nqs_ansatz_create(nqs_ctx* ctx, int K, int n_alpha, int n_beta, int chi,
                              const int32_t* parent_ptr, const int32_t* parent_idx, int n_hidden,
-                             int32_t correlator, nqs_ansatz** out) {
+                             int32_t variant, nqs_ansatz** out) {
   if (!ctx || !parent_ptr || !out) return fail(NQS_EINVAL, "NULL argument");
-  if (correlator != NQS_CORR_COS_RBM && correlator != NQS_CORR_ISING_RBM)
-    return fail(NQS_EINVAL, "unknown correlator %d", correlator);
+  const int32_t correlator = variant & 0xF;
+  if ((correlator != NQS_CORR_COS_RBM && correlator != NQS_CORR_ISING_RBM) || (variant & ~(0xF | NQS_ANSATZ_TENSOR)))
+    return fail(NQS_EINVAL, "unknown ansatz variant %d", variant);
   if (K < 1 || K > 64) return fail(NQS_EINVAL, "K=%d outside [1,64]", K);
   if (chi < 1 || chi > 64) return fail(NQS_EUNSUPPORTED, "chi=%d outside [1,64]", chi);
   if (n_alpha < 0 || n_alpha > K || n_beta < 0 || n_beta > K) return fail(NQS_EINVAL, "bad electron counts");
@@ -610,6 +673,7 @@ nqs_status nqs_ansatz_create(nqs_ctx* ctx, int K, int n_alpha, int n_beta, int c
   a->ctx = ctx;
   a->K = K; a->na = n_alpha; a->nb = n_beta; a->chi = chi; a->nh = n_hidden;
   a->ising = n_hidden > 0 && correlator == NQS_CORR_ISING_RBM;
+  a->tensor = (variant & NQS_ANSATZ_TENSOR) != 0;
   a->chip = ((chi + 15) / 16) * 16;
   a->pptr.assign(parent_ptr, parent_ptr + K + 1);
   int maxoff = 0;
@@ -640,6 +704,28 @@ nqs_status nqs_ansatz_create(nqs_ctx* ctx, int K, int n_alpha, int n_beta, int c
   a->offWc = o; o += int64_t(n_hidden) * 2 * K;
   a->offW2 = o;
   if (a->ising) o += int64_t(n_hidden) * 4 * K * K;
+  // BDG-TensorRNN block, last: per site with d >= 2 parents the factor
+  // matrices K^(0..d) (chi x chi' each) and the cores U^s (chi'^(d+1) each)
+  a->tq.assign(K, 0);
+  a->offTK.assign(K, 0);
+  a->offTU.assign(K, 0);
+  for (int i = 0; i < K && a->tensor; ++i) {
+    const int d = a->pptr[i + 1] - a->pptr[i];
+    if (d < 2) continue;
+    if (d > 3) return fail(NQS_EUNSUPPORTED, "tensor term at site %d with %d parents (at most 3)", i, d);
+    int q = 1;
+    while (true) {
+      int64_t pw = 1;
+      for (int k = 0; k <= d; ++k) pw *= q;
+      if (pw >= int64_t(chi) * chi) break;
+      ++q;
+    }
+    int64_t qd = 1;
+    for (int k = 0; k <= d; ++k) qd *= q;
+    a->tq[i] = q;
+    a->offTK[i] = o; o += int64_t(d + 1) * chi * q;
+    a->offTU[i] = o; o += 4 * qd;
+  }
   a->n_params = o;
   DeviceGuard g(ctx->device);
   nqs_status st;
@@ -660,6 +746,44 @@ nqs_status nqs_ansatz_create(nqs_ctx* ctx, int K, int n_alpha, int n_beta, int c
   if ((st = upload(&a->d_offM, a->offM)) != NQS_OK) return st;
   if ((st = upload(&a->d_offV, a->offV)) != NQS_OK) return st;
   if ((st = upload(&a->d_offEta, a->offEta)) != NQS_OK) return st;
+  if (a->tensor) {
+    // kernel layout offsets (elements; every block starts on a multiple of 16)
+    const int cp = a->chip;
+    auto r16 = [](int64_t x) { return (x + 15) / 16 * 16; };
+    std::vector<int> edge(size_t(a->pptr[K]) * 2), site(size_t(K) * 8, 0);
+    int64_t q = 0;
+    for (int i = 0; i < K; ++i) {
+      for (int e = a->pptr[i]; e < a->pptr[i + 1]; ++e) {
+        edge[2 * e] = int(q);
+        edge[2 * e + 1] = a->pidx[e] % a->W;
+        q += int64_t(4) * cp * cp;
+      }
+      int* st8 = site.data() + 8 * i;
+      st8[0] = int(q); q += 4 * cp;
+      st8[1] = int(q); q += cp;
+      st8[2] = int(q); q += cp;
+      st8[3] = int(q); q += 16;
+      const int tq = a->tq[i], d = a->pptr[i + 1] - a->pptr[i];
+      st8[4] = tq;
+      if (tq) {
+        int64_t qd = 1;
+        for (int k = 0; k <= d; ++k) qd *= tq;
+        st8[5] = int(q); q += r16(int64_t(tq) * cp);
+        st8[6] = int(q); q += int64_t(d) * cp * 16;
+        st8[7] = int(q); q += r16(4 * qd);
+      }
+    }
+    if (q >= (int64_t(1) << 31)) return fail(NQS_EUNSUPPORTED, "tensor-RNN parameter layout too large");
+    a->tn_size = q;
+    const int rw = (chi + 3) / 4 * 4;
+    a->tn_f64_ok = tn_lds_bytes(a->W, rw, 0) <= 64 * 1024;
+    if (tn_lds_bytes(a->W, rw, 1) > 64 * 1024)
+      return fail(NQS_EUNSUPPORTED, "tensor-RNN ring of %d x %d states does not fit the LDS", a->W, rw);
+    if ((st = upload(&a->d_tn_edge, edge)) != NQS_OK) return st;
+    if ((st = upload(&a->d_tn_site, site)) != NQS_OK) return st;
+    a->tn_edge_host = edge;
+    a->tn_site_host = site;
+  }
   *out = a.release();
   return NQS_OK;
 }
@@ -698,6 +822,7 @@ nqs_status nqs_ansatz_bind_params(nqs_ansatz* ans, const double* params, hipStre
     ans->has_fold = true;
   }
   if ((st = build_bf16(ans, prm, ans->has_fold)) != NQS_OK) return st;
+  if (ans->tensor && (st = build_tn(ans, prm)) != NQS_OK) return st;
   if (ans->d_cb) { (void)hipFree(ans->d_cb); ans->d_cb = nullptr; }
   if (ans->d_cW) { (void)hipFree(ans->d_cW); ans->d_cW = nullptr; }
   if (ans->d_cW1t) { (void)hipFree(ans->d_cW1t); ans->d_cW1t = nullptr; }
@@ -819,6 +944,18 @@ size_t mantissa_bytes(int precision) { return precision == NQS_F64 ? 8 : 4; }
 nqs_status run_amplitudes(const nqs_ansatz* a, int precision, const uint64_t* m, int64_t R, double* lphi,
                           int8_t* sphi, hipStream_t st, const Resume* rs = nullptr, int mode = PSI_PLAIN) {
   if (mode != PSI_PLAIN && !rs) return fail(NQS_EINVAL, "resume state missing");
+  if (a->tensor) {
+    if (mode != PSI_PLAIN) return fail(NQS_EINVAL, "tensor-RNN rows are evaluated from site 0");
+    if (precision == NQS_F64) {
+      if (!a->tn_f64_ok) return fail(NQS_EUNSUPPORTED, "FP64 tensor-RNN ring does not fit the LDS");
+      HIPCHK(launch_psi_tn_f64(a->tn<double>(a->tn64), m, R, lphi, sphi, st));
+    } else if (precision == NQS_F32) {
+      HIPCHK(launch_psi_tn_f32(a->tn<float>(a->tn32), m, R, lphi, sphi, st));
+    } else {
+      return fail(NQS_EUNSUPPORTED, "the tensor-RNN runs in FP64 or FP32");
+    }
+    return NQS_OK;
+  }
   if (precision == NQS_F64) {
     HIPCHK(launch_psi_f64(a->params(a->fwd64()), m, R, lphi, sphi, st,
                           rs ? states<double>(*rs) : PsiStates<double>(), mode));
@@ -1024,6 +1161,7 @@ nqs_status nqs_logpsi_vjp(nqs_ctx* ctx, const nqs_ansatz* ans, const uint64_t* s
   if (!ans->bound) return fail(NQS_EINVAL, "parameters not bound");
   if (precision != NQS_F64 && precision != NQS_F32)
     return fail(NQS_EUNSUPPORTED, "the adjoint runs in FP64 or FP32");
+  if (ans->tensor) return fail(NQS_EUNSUPPORTED, "no adjoint for the tensor-RNN term");
   DeviceGuard g(ctx->device);
   nqs_status s = check_samples(ctx, samples, N, ans->K, ans->na, ans->nb, stream);
   if (s != NQS_OK) return s;
@@ -1123,7 +1261,7 @@ nqs_status nqs_eloc(nqs_ctx* ctx, const nqs_instance* inst, const nqs_ansatz* an
   double* f2 = fsq ? fsq : S.get<double>(N);
   double* sums = S.get<double>(8);
   const int K = ans->K;
-  const bool resume = resumes(*opts) && cap_used < (int64_t(1) << 31);
+  const bool resume = resumes(*opts) && !ans->tensor && cap_used < (int64_t(1) << 31);
   Resume rs;
   double* lphi_s = nullptr;
   int8_t* sphi_s = nullptr;
@@ -1406,10 +1544,16 @@ nqs_status nqs_sample(nqs_ctx* ctx, const nqs_ansatz* ans, int64_t n_draws, uint
     SA.k1 = uint32_t(seed >> 32);
     SA.p0 = draw_base + d0;
     SA.out = m;
-    if (precision == NQS_F64)
+    if (ans->tensor && precision == NQS_F64) {
+      if (!ans->tn_f64_ok) return fail(NQS_EUNSUPPORTED, "FP64 tensor-RNN ring does not fit the LDS");
+      HIPCHK(launch_sample_tn_f64(ans->tn<double>(ans->tn64), ch, lphi, sphi, stream, SA));
+    } else if (ans->tensor) {
+      HIPCHK(launch_sample_tn_f32(ans->tn<float>(ans->tn32), ch, lphi, sphi, stream, SA));
+    } else if (precision == NQS_F64) {
       HIPCHK(launch_sample_f64(ans->params(ans->fwd64()), ch, lphi, sphi, stream, SA));
-    else
+    } else {
       HIPCHK(launch_sample_f32(ans->params(ans->fwd32()), ch, lphi, sphi, stream, SA));
+    }
     const int64_t n = u + ch;
     if (n > kMaxSort) return fail(NQS_EUNSUPPORTED, "more than 2^31 - 1 unique draws plus one pass");
     Scratch T(ctx);

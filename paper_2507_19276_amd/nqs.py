@@ -36,6 +36,7 @@ class ElocOpts(C.Structure):
 
 
 ELOC_FULL_RECOMPUTE = 1
+ANSATZ_TENSOR = 0x10
 
 
 class ElocStats(C.Structure):
@@ -223,18 +224,20 @@ class Ansatz:
     bound from a device tensor."""
 
     def __init__(self, ctx: Context, K: int, n_alpha: int, n_beta: int, chi: int, parent_ptr, parent_idx,
-                 n_hidden: int = 0, ising: bool = False):
+                 n_hidden: int = 0, ising: bool = False, tensor: bool = False):
         pp = np.ascontiguousarray(parent_ptr, dtype=np.int32)
         pi = np.ascontiguousarray(parent_idx, dtype=np.int32)
         if pi.size == 0:
             pi = np.zeros(1, dtype=np.int32)
         out = _p()
         check(lib().nqs_ansatz_create(ctx.h, K, n_alpha, n_beta, chi, pp.ctypes.data_as(_p),
-                                      pi.ctypes.data_as(_p), n_hidden, 1 if ising else 0, C.byref(out)))
+                                      pi.ctypes.data_as(_p), n_hidden,
+                                      (1 if ising else 0) | (ANSATZ_TENSOR if tensor else 0), C.byref(out)))
         self.h = out
         self.ctx = ctx
         self.K, self.n_alpha, self.n_beta, self.chi, self.n_hidden = K, n_alpha, n_beta, chi, n_hidden
         self.ising = bool(ising) and n_hidden > 0
+        self.tensor = bool(tensor)
         self.n_params = int(lib().nqs_ansatz_n_params(out))
 
     def bind(self, params):

@@ -207,14 +207,16 @@ def n_params(K: int, chi: int, parent_ptr: np.ndarray, n_hidden: int, ising: boo
 
 def ansatz_params(K: int, chi: int, parent_ptr: np.ndarray, parent_idx: np.ndarray,
                   n_hidden: int, seed: int, corr_scale: float = 0.1, ising: bool = False,
-                  tensor: bool = False, tensor_scale: float = 0.3) -> np.ndarray:
+                  tensor: bool = False, tensor_scale: float = 0.1) -> np.ndarray:
     """Random-init parameters in the packed layout (module docstring):
     M ~ N(0, var 1/(chi*max(d_i,1))), v ~ N(0,1), eta ~ U[0.5,1.5], w, c ~ N(0,1),
     correlator b, W ~ N(0, corr_scale^2), Ising W2 ~ N(0, corr_scale^2 / K) (its
     ~K^2 occupied pairs then spread theta about as much as W's ~K terms);
     tensor factors K ~ N(0, 1/chi), cores U ~ N(0, tensor_scale^2 / chi'^d) (the term is quadratic
-    in the hidden states at two parents: at tensor_scale = 1 random states grow
-    without bound along a K = 20 chain, at 0.3 the term shifts log|Phi| by ~0.5)."""
+    in the hidden states at two parents, so random states can grow without
+    bound along a K = 20 chain: at tensor_scale = 0.3 some reach |h| ~ 1e79,
+    beyond FP32; at 0.1 the largest |h| is ~25 and the term still shifts
+    log|Phi| by ~0.15)."""
     rng = np.random.default_rng(seed)
     out: List[np.ndarray] = []
     for i in range(K):
