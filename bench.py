@@ -11,6 +11,10 @@ timed alongside.  The CPU-baseline leg runs the FP64 oracle on the same
 4096 samples with the draws of one GPU step and reports the GPU error
 against it.
 
+--next: the sampler, the Ising-RBM and BDG-TensorRNN local energies and one
+VMC step, each on its own K = 20 workload, with the roofline of its dominant
+kernel.
+
 --serve: the serving workload instead (500 Poisson-arriving requests over 12
 resident instances, norb in {12,20,36,50} x chi in {16,32,64}, BF16 path,
 eps = 1e-2, N_eps = 100, batch sizes log-uniform in [256, 16384]) at 0.8 x
@@ -267,6 +271,112 @@ def run_serve_bench(args):
     print(json.dumps(line), flush=True)
 
 
+def run_next_bench(args):
+    """The paths beyond the local energy of the BDG-RNN: exact sampling, the
+    Ising-RBM correlator, the BDG-TensorRNN and one VMC step, each timed on its
+    own synthetic workload (chain K=20, 10a+10b) with a roofline of its
+    dominant kernel.  One JSON line."""
+    import numpy as np
+    import torch
+    from paper_2507_19276_amd import nqs, workloads
+
+    torch.cuda.set_device(0)
+    ctx = nqs.Context(0)
+
+    def make(name):
+        w = workloads.make_workload(name)
+        inst = nqs.Instance(ctx, w.K, w.n_alpha, w.n_beta, w.h, w.eri, w.e_core)
+        ans = nqs.Ansatz(ctx, w.K, w.n_alpha, w.n_beta, w.chi, w.parent_ptr, w.parent_idx, w.n_hidden,
+                         ising=w.ising, tensor=w.tensor)
+        ans.bind(w.params)
+        s = torch.from_numpy(w.samples.view(np.int64)).cuda().contiguous()
+        return w, inst, ans, s
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            r = fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / reps, r
+
+    out = {}
+    # exact sampling (k_psi_mt in sampling mode + radix-sort merge), chain chi=16
+    w, inst, ans, s = make("c2")
+    site_flops = 8.0 * w.chi * w.chi * float(w.parent_ptr[-1])   # per draw, all sites
+    samp = {}
+    for prec in ("f32", "f64"):
+        nd = 10_000_000
+        dt, r = timed(lambda: ans.sample(nd, seed=3, precision=prec), 3)
+        fl = nd * site_flops / dt / 1e12
+        samp[prec] = {"draws": nd, "ms": dt * 1e3, "draws_per_s": nd / dt, "unique": r[4],
+                      "roofline": {"bound": "mfma", "achieved": fl, "peak": PEAKS[prec], "unit": "TFLOP/s",
+                                   "frac": fl / PEAKS[prec],
+                                   "note": "whole call (draws and unique merge) against the contraction flops"}}
+        print(f"# sampler {prec}: {nd / dt:.3e} draws/s", file=sys.stderr, flush=True)
+    out["sampler_chain_K20_chi16"] = samp
+    # Ising-RBM correlator, N_h = 80, 4096 samples
+    w, inst, ans, s = make("c2i")
+    kw = dict(eps=w.eps, n_eps=w.n_eps, precision="f32", stream_id=0)
+    dt, (o, st) = timed(lambda: nqs.eloc(ctx, inst, ans, s, seed=w.seed, **kw), 5)
+    # table reads of the row update: theta, up to 4 E entries and 6 S pairs per hidden unit (FP32)
+    byts = st["n_rows"] * w.n_hidden * 11 * 4
+    gbs = byts / (st["ms_reduce"] * 1e-3) / 1e9
+    out["ising_rbm_chain_K20_nh80"] = {
+        "local_energies_per_s": w.n_samples / dt, "ms_per_step": dt * 1e3, "rows": st["n_rows"],
+        "correlator_and_reduce_ms": st["ms_reduce"], "amplitude_ms": st["ms_amplitude"],
+        "roofline": {"bound": "hbm", "achieved": gbs, "peak": 8000.0, "unit": "GB/s", "frac": gbs / 8000.0,
+                     "kernel": "k_ising_rows<float,float>",
+                     "note": "table bytes read per row (reused from L2), over the correlator and reduce stage"}}
+    print(f"# ising: {w.n_samples / dt:.0f} E_loc/s, correlator stage {st['ms_reduce']:.2f} ms", file=sys.stderr,
+          flush=True)
+    # BDG-TensorRNN, NN+NNN chi=16 (chi' = 7), 4096 samples
+    w, inst, ans, s = make("c2t")
+    tens = {}
+    for prec in ("f32", "f64"):
+        kw = dict(eps=w.eps, n_eps=w.n_eps, precision=prec, stream_id=0)
+        dt, (o, st) = timed(lambda: nqs.eloc(ctx, inst, ans, s, seed=w.seed, **kw), 3)
+        fl = st["psi_flops"] / (st["ms_psi"] * 1e-3) / 1e12
+        peak = 157.3 if prec == "f32" else 78.6
+        tens[prec] = {"local_energies_per_s": w.n_samples / dt, "ms_per_step": dt * 1e3,
+                      "row_kernel_ms": st["ms_psi"], "site_rows": st["n_site_rows"],
+                      "roofline": {"bound": "alu", "achieved": fl, "peak": peak, "unit": "TFLOP/s",
+                                   "frac": fl / peak, "kernel": f"k_psi_tn<{'float' if prec == 'f32' else 'double'},false>",
+                                   "flops_per_launch": st["psi_flops"]}}
+        print(f"# tensor {prec}: {w.n_samples / dt:.0f} E_loc/s, row kernel {st['ms_psi']:.2f} ms, {fl:.2f} TFLOP/s",
+              file=sys.stderr, flush=True)
+    out["bdg_tensor_rnn_nnn_K20_chi16"] = tens
+    # one VMC step (4096 draws, FP32 path), chain chi=16
+    w, inst, ans, s = make("c2")
+    p = torch.from_numpy(w.params.copy()).cuda()
+    m, v = torch.zeros_like(p), torch.zeros_like(p)
+    steps = []
+    for k in range(1, 5):
+        t0 = time.perf_counter()
+        st = nqs.vmc_step(ctx, inst, ans, p, m, v, k, n_draws=4096, sample_seed=k, draw_base=4096 * k,
+                          eps=w.eps, n_eps=w.n_eps, precision="f32", seed=k, lr=1e-3)
+        steps.append((time.perf_counter() - t0, st))
+    dt = float(np.mean([t for t, _ in steps[1:]]))
+    last = steps[-1][1]
+    out["vmc_step_chain_K20_chi16"] = {"ms_per_step": dt * 1e3, "n_unique": last["n_unique"],
+                                       "stage_ms": {k: last[k] for k in ("ms_sample", "ms_eloc", "ms_grad",
+                                                                          "ms_update")},
+                                       "E": [st["E"] for _, st in steps]}
+    print(f"# vmc step: {dt * 1e3:.2f} ms", file=sys.stderr, flush=True)
+    line = {
+        "metric": "next rows: exact sampling, Ising-RBM and BDG-TensorRNN local energies, VMC step",
+        "value": out["sampler_chain_K20_chi16"]["f32"]["draws_per_s"],
+        "unit": "draws/s (FP32 sampler; the other figures in the sub-objects)",
+        "n_gpus": 1, "steps": 1, "warmup": 1, "ms_per_step": out["sampler_chain_K20_chi16"]["f32"]["ms"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "chain K=20 10a+10b: c2 (chain chi=16), c2i (+Ising-RBM N_h=80), "
+                               "c2t (NN+NNN BDG-TensorRNN chi=16)"},
+        **out,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -282,6 +392,8 @@ def main():
     ap.add_argument("--traffic-bytes", type=float, default=None,
                     help="HBM bytes per amplitude-kernel launch from rocprofv3 PMC counters")
     ap.add_argument("--serve", action="store_true")
+    ap.add_argument("--next", action="store_true",
+                    help="time the sampler, the Ising-RBM and BDG-TensorRNN paths and one VMC step")
     ap.add_argument("--requests", type=int, default=500)
     ap.add_argument("--load", type=float, default=0.8)
     ap.add_argument("--slots", type=int, default=4)
@@ -294,6 +406,8 @@ def main():
         sys.exit(2)
     if args.serve:
         run_serve_bench(args)
+    elif args.next:
+        run_next_bench(args)
     else:
         run_eloc_bench(args)
 

@@ -111,8 +111,9 @@ typedef struct {
                             sites computed (K per row without resumption), plus the
                             samples' own pass when rows resume */
   double ms_psi;         /* device time of the row amplitude kernel launches alone */
-  double psi_flops;      /* their algorithmic bond-contraction flops: 8 chi^2 d_i per
-                            evaluated site i with d_i parents */
+  double psi_flops;      /* their algorithmic flops: 8 chi^2 d_i per evaluated site i with
+                            d_i parents, plus for a tensor-RNN site 2 (d chi chi' +
+                            4 chi'^(d+1) + 4 chi chi') */
 } nqs_eloc_stats;
 
 /* ---- context --------------------------------------------------------- */

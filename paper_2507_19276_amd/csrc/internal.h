@@ -63,7 +63,7 @@ struct TnParams {
   int K, chi, chip, rw, na, nb, W;   // rw = ceil4(chi): units of a carried state in the ring
   const T* prm;                  // kernel layout: per edge M^T [4][chip][chip]; per site v [4][chip],
                                  // eta, w [chip], c; per tensor site K0^T [chi'][chip],
-                                 // K_j [d][chip][16], U [4][chi'^(d+1)]
+                                 // K_j [d][chip][16], U [4][chi'^d][16]
   const int* pptr;               // [K+1] parents of site i: pptr[i]..pptr[i+1]-1
   const int* edge;               // [edges][2]: offset of M^T, ring slot of the parent
   const int* site;               // [K][8]: offV, offEta, offW, offC, chi' (0: none), offK0, offKj, offU

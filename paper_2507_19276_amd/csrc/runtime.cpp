@@ -465,6 +465,21 @@ nqs_status build_bf16(nqs_ansatz* a, const std::vector<double>& prm, bool fold) 
   return upload(&a->bfA, A);
 }
 
+// algorithmic flops of one site of one row: 8 chi^2 d (four candidates, d
+// parents); with a tensor term also the projections (d chi chi' MACs), the
+// core (4 chi'^(d+1)) and the output factor (4 chi chi')
+double site_flops(const nqs_ansatz& a, int i) {
+  const int d = a.pptr[i + 1] - a.pptr[i];
+  double f = 8.0 * a.chi * a.chi * d;
+  const int q = a.tensor ? a.tq[i] : 0;
+  if (q) {
+    double qd = 1;
+    for (int k = 0; k <= d; ++k) qd *= q;
+    f += 2.0 * (double(d) * a.chi * q + 4.0 * qd + 4.0 * a.chi * q);
+  }
+  return f;
+}
+
 // BDG-TensorRNN kernel layout (see TnParams) in FP64 and FP32, zero-padded to
 // chip units and to 16 projection columns
 nqs_status build_tn(nqs_ansatz* a, const std::vector<double>& prm) {
@@ -497,7 +512,7 @@ nqs_status build_tn(nqs_ansatz* a, const std::vector<double>& prm) {
           L[st8[6] + (size_t(j) * cp + v) * 16 + b] = Kp[size_t(j + 1) * chi * q + size_t(v) * q + b];
     int64_t qd = 1;
     for (int k = 0; k <= d; ++k) qd *= q;
-    for (int64_t f = 0; f < 4 * qd; ++f) L[st8[7] + f] = prm[a->offTU[i] + f];
+    for (int64_t f = 0; f < 4 * qd; ++f) L[st8[7] + (f / q) * 16 + f % q] = prm[a->offTU[i] + f];
   }
   if (a->tn64) { (void)hipFree(a->tn64); a->tn64 = nullptr; }
   if (a->tn32) { (void)hipFree(a->tn32); a->tn32 = nullptr; }
@@ -770,7 +785,7 @@ nqs_status nqs_ansatz_create(nqs_ctx* ctx, int K, int n_alpha, int n_beta, int c
         for (int k = 0; k <= d; ++k) qd *= tq;
         st8[5] = int(q); q += r16(int64_t(tq) * cp);
         st8[6] = int(q); q += int64_t(d) * cp * 16;
-        st8[7] = int(q); q += r16(4 * qd);
+        st8[7] = int(q); q += 4 * (qd / tq) * 16;   // U^s rows padded to 16 in the last index
       }
     }
     if (q >= (int64_t(1) << 31)) return fail(NQS_EUNSUPPORTED, "tensor-RNN parameter layout too large");
@@ -1323,7 +1338,7 @@ nqs_status nqs_eloc(nqs_ctx* ctx, const nqs_instance* inst, const nqs_ansatz* an
   // algorithmic flops of a row evaluated from site k on: 8 chi^2 d_i per site i >= k
   std::vector<double> tail_flops(K + 1, 0.0);
   for (int i = K - 1; i >= 0; --i)
-    tail_flops[i] = tail_flops[i + 1] + 8.0 * ans->chi * ans->chi * (ans->pptr[i + 1] - ans->pptr[i]);
+    tail_flops[i] = tail_flops[i + 1] + site_flops(*ans, i);
   hipEvent_t kq[2] = {};
   struct KqGuard {
     hipEvent_t* e;

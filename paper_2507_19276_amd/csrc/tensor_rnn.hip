@@ -17,7 +17,10 @@
 // accumulated over (parent, unit) pairs with one LDS read per 16 FMAs.  The
 // parameter layout is the library's (see runtime.cpp): per edge M^T as
 // [s][k][u], per site v, eta, w, c, and per tensor site K0^T [i'][u], K_j as
-// [j][v][a] and U^s as [s][i'][a...], all padded to chip = ceil16(chi) units.
+// [j][v][a] and U^s as [s][i'][a_1..a_(d-1)][a_d padded to 16], all padded to
+// chip = ceil16(chi) units.  The projections and the core contraction are
+// unrolled over 16 (zero-padded) entries, so every weight row is one scalar
+// 16-dword load feeding 16 FMAs.
 #include "device.h"
 #include "philox.h"
 
@@ -36,11 +39,9 @@ __global__ __launch_bounds__(kTnThreads) void k_psi_tn(TnParams<T> P, const uint
   constexpr int NT = kTnThreads;
   const int CP = P.chip, RW = P.rw;
   T* ring = reinterpret_cast<T*>(smem);                          // [W][rw][NT]
-  T* pl = ring + size_t(P.W) * RW * NT;                          // [3][16][NT]
-  T* ql = pl + 3 * 16 * NT;                                      // [16][NT]
+  T* pl = ring + size_t(P.W) * RW * NT;                          // [16][NT]: first projection (d = 3)
   auto RG = [&](int slot, int k) -> T& { return ring[(size_t(slot) * RW + k) * NT + tid]; };
-  auto PL = [&](int j, int a) -> T& { return pl[(j * 16 + a) * NT + tid]; };
-  auto QL = [&](int i) -> T& { return ql[i * NT + tid]; };
+  auto PL = [&](int a) -> T& { return pl[a * NT + tid]; };
   const int64_t r = int64_t(blockIdx.x) * NT + tid;
   const bool live = r < R;
   const int64_t rr = live ? r : R - 1;
@@ -53,25 +54,41 @@ __global__ __launch_bounds__(kTnThreads) void k_psi_tn(TnParams<T> P, const uint
   T prod = T(1);
   int pexp = 0, sgn = 1, ca = 0, cb = 0;
   bool bad = false;
-  // q^s for state s (all rows the same s, or this row's s) into QL
+  // projections p_0..p_(d-1) (16 entries each, zero beyond chi') and the
+  // core contraction q^s (16 entries, zero beyond chi')
+  T p0[16], p1[16], p2[16], q[16];
   auto core = [&](int s, int Q, int d, int offU) {
-    for (int ip = 0; ip < Q; ++ip) {
+#pragma unroll
+    for (int ip = 0; ip < 16; ++ip) {
+      q[ip] = T(0);
+      if (ip >= Q) continue;
       T acc = T(0);
-      const int base = offU + (s * Q + ip) * (d == 2 ? Q * Q : Q * Q * Q);
-      for (int a1 = 0; a1 < Q; ++a1) {
-        T in = T(0);
-        if (d == 2) {
-          for (int a2 = 0; a2 < Q; ++a2) in = tfma(T(W[base + a1 * Q + a2]), PL(1, a2), in);
-        } else {
-          for (int a2 = 0; a2 < Q; ++a2) {
-            T in3 = T(0);
-            for (int a3 = 0; a3 < Q; ++a3) in3 = tfma(T(W[base + (a1 * Q + a2) * Q + a3]), PL(2, a3), in3);
-            in = tfma(PL(1, a2), in3, in);
-          }
+      if (d == 2) {
+        const int base = offU + (s * Q + ip) * Q * 16;
+#pragma unroll
+        for (int a1 = 0; a1 < 16; ++a1) {
+          if (a1 >= Q) continue;
+          T in = T(0);
+#pragma unroll
+          for (int a2 = 0; a2 < 16; ++a2) in = tfma(T(W[base + a1 * 16 + a2]), p1[a2], in);
+          acc = tfma(p0[a1], in, acc);
         }
-        acc = tfma(PL(0, a1), in, acc);
+      } else {
+        const int base = offU + (s * Q + ip) * Q * Q * 16;
+        for (int a1 = 0; a1 < Q; ++a1) {
+          T in = T(0);
+#pragma unroll
+          for (int a2 = 0; a2 < 16; ++a2) {
+            if (a2 >= Q) continue;
+            T in3 = T(0);
+#pragma unroll
+            for (int a3 = 0; a3 < 16; ++a3) in3 = tfma(T(W[base + (a1 * Q + a2) * 16 + a3]), p2[a3], in3);
+            in = tfma(p1[a2], in3, in);
+          }
+          acc = tfma(PL(a1), in, acc);
+        }
       }
-      QL(ip) = acc;
+      q[ip] = acc;
     }
   };
   for (int i = 0; i < P.K; ++i) {
@@ -81,18 +98,29 @@ __global__ __launch_bounds__(kTnThreads) void k_psi_tn(TnParams<T> P, const uint
     const int wslot = i % P.W;
     // projections of the parents' states on their factor matrices
     if (Q) {
-      for (int j = 0; j < d; ++j) {
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        if (j >= d) continue;
         const int ps = edge[2 * (e0 + j) + 1];
         T pa[16];
 #pragma unroll
         for (int a = 0; a < 16; ++a) pa[a] = T(0);
+#pragma unroll 4
         for (int v = 0; v < RW; ++v) {
           const T hv = RG(ps, v);
 #pragma unroll
           for (int a = 0; a < 16; ++a) pa[a] = tfma(T(W[offKj + (j * CP + v) * 16 + a]), hv, pa[a]);
         }
 #pragma unroll
-        for (int a = 0; a < 16; ++a) PL(j, a) = pa[a];
+        for (int a = 0; a < 16; ++a) {
+          if (j == 0) p0[a] = pa[a];
+          if (j == 1) p1[a] = pa[a];
+          if (j == 2) p2[a] = pa[a];
+        }
+      }
+      if (d == 3) {
+#pragma unroll
+        for (int a = 0; a < 16; ++a) PL(a) = p0[a];
       }
     }
     const int si = SAMPLE ? 0 : site_state(lo, hi, i);
@@ -109,6 +137,7 @@ __global__ __launch_bounds__(kTnThreads) void k_psi_tn(TnParams<T> P, const uint
         for (int u = 0; u < 16; ++u) acc[u] = T(W[offV + s * CP + uc + u]);
         for (int e = e0; e < e1; ++e) {
           const int offM = edge[2 * e], ps = edge[2 * e + 1];
+#pragma unroll 4
           for (int k = 0; k < RW; ++k) {
             const T hk = RG(ps, k);
 #pragma unroll
@@ -116,10 +145,11 @@ __global__ __launch_bounds__(kTnThreads) void k_psi_tn(TnParams<T> P, const uint
           }
         }
         if (Q) {
-          for (int ip = 0; ip < Q; ++ip) {
-            const T qv = QL(ip);
 #pragma unroll
-            for (int u = 0; u < 16; ++u) acc[u] = tfma(T(W[offK0 + ip * CP + uc + u]), qv, acc[u]);
+          for (int ip = 0; ip < 16; ++ip) {
+            if (ip >= Q) continue;
+#pragma unroll
+            for (int u = 0; u < 16; ++u) acc[u] = tfma(T(W[offK0 + ip * CP + uc + u]), q[ip], acc[u]);
           }
         }
 #pragma unroll
@@ -199,7 +229,7 @@ template <typename T, bool SAMPLE>
 hipError_t run_tn(const TnParams<T>& P, const uint64_t* m, int64_t R, double* lphi, int8_t* sphi, hipStream_t st,
                   const SampleArgs& SA) {
   if (R <= 0) return hipSuccess;
-  const size_t lds = (size_t(P.W) * P.rw + 3 * 16 + 16) * kTnThreads * sizeof(T);
+  const size_t lds = (size_t(P.W) * P.rw + 16) * kTnThreads * sizeof(T);
   if (lds > 64 * 1024 || P.rw > P.chip || P.rw < P.chi) return hipErrorInvalidValue;
   hipLaunchKernelGGL((k_psi_tn<T, SAMPLE>), dim3(unsigned((R + kTnThreads - 1) / kTnThreads)), dim3(kTnThreads),
                      lds, st, P, m, R, lphi, sphi, SA);
@@ -209,7 +239,7 @@ hipError_t run_tn(const TnParams<T>& P, const uint64_t* m, int64_t R, double* lp
 }  // namespace
 
 size_t tn_lds_bytes(int W, int rw, int precision) {
-  return (size_t(W) * rw + 3 * 16 + 16) * kTnThreads * (precision == 0 ? 8 : 4);
+  return (size_t(W) * rw + 16) * kTnThreads * (precision == 0 ? 8 : 4);
 }
 
 hipError_t launch_psi_tn_f64(const TnParams<double>& P, const uint64_t* m, int64_t R, double* lphi, int8_t* sphi,
