@@ -61,9 +61,10 @@ struct PsiParams {
 template <typename T>
 struct TnParams {
   int K, chi, chip, rw, na, nb, W;   // rw = ceil4(chi): units of a carried state in the ring
+  int qp;                            // padded width of the projections and of U's last index (8 or 16)
   const T* prm;                  // kernel layout: per edge M^T [4][chip][chip]; per site v [4][chip],
                                  // eta, w [chip], c; per tensor site K0^T [chi'][chip],
-                                 // K_j [d][chip][16], U [4][chi'^d][16]
+                                 // K_j [d][chip][qp], U [4][chi'^d][qp]
   const int* pptr;               // [K+1] parents of site i: pptr[i]..pptr[i+1]-1
   const int* edge;               // [edges][2]: offset of M^T, ring slot of the parent
   const int* site;               // [K][8]: offV, offEta, offW, offC, chi' (0: none), offK0, offKj, offU

@@ -232,6 +232,7 @@ struct nqs_ansatz {
   double* tn64 = nullptr;
   float* tn32 = nullptr;
   int64_t tn_size = 0;
+  int tn_qp = 16;           // 8 when every chi' <= 8
   bool tn_f64_ok = true;    // the FP64 ring fits the LDS
   std::vector<int> tn_edge_host, tn_site_host;
   int64_t* d_offM = nullptr;
@@ -273,7 +274,7 @@ struct nqs_ansatz {
   template <typename T>
   TnParams<T> tn(const T* prm) const {
     TnParams<T> P;
-    P.K = K; P.chi = chi; P.chip = chip; P.rw = (chi + 3) / 4 * 4; P.na = na; P.nb = nb; P.W = W;
+    P.K = K; P.chi = chi; P.chip = chip; P.rw = (chi + 3) / 4 * 4; P.na = na; P.nb = nb; P.W = W; P.qp = tn_qp;
     P.prm = prm; P.pptr = d_pptr; P.edge = d_tn_edge; P.site = d_tn_site;
     return P;
   }
@@ -506,13 +507,14 @@ nqs_status build_tn(nqs_ansatz* a, const std::vector<double>& prm) {
     const double* Kp = prm.data() + a->offTK[i];   // K^(0..d), each [chi][q]
     for (int ip = 0; ip < q; ++ip)
       for (int u = 0; u < chi; ++u) L[st8[5] + size_t(ip) * cp + u] = Kp[size_t(u) * q + ip];
+    const int qp = a->tn_qp;
     for (int j = 0; j < d; ++j)
       for (int v = 0; v < chi; ++v)
         for (int b = 0; b < q; ++b)
-          L[st8[6] + (size_t(j) * cp + v) * 16 + b] = Kp[size_t(j + 1) * chi * q + size_t(v) * q + b];
+          L[st8[6] + (size_t(j) * cp + v) * qp + b] = Kp[size_t(j + 1) * chi * q + size_t(v) * q + b];
     int64_t qd = 1;
     for (int k = 0; k <= d; ++k) qd *= q;
-    for (int64_t f = 0; f < 4 * qd; ++f) L[st8[7] + (f / q) * 16 + f % q] = prm[a->offTU[i] + f];
+    for (int64_t f = 0; f < 4 * qd; ++f) L[st8[7] + (f / q) * qp + f % q] = prm[a->offTU[i] + f];
   }
   if (a->tn64) { (void)hipFree(a->tn64); a->tn64 = nullptr; }
   if (a->tn32) { (void)hipFree(a->tn32); a->tn32 = nullptr; }
@@ -765,6 +767,10 @@ nqs_status nqs_ansatz_create(nqs_ctx* ctx, int K, int n_alpha, int n_beta, int c
     // kernel layout offsets (elements; every block starts on a multiple of 16)
     const int cp = a->chip;
     auto r16 = [](int64_t x) { return (x + 15) / 16 * 16; };
+    int qmax = 0;
+    for (int i = 0; i < K; ++i) qmax = std::max(qmax, a->tq[i]);
+    const int qp = qmax <= 8 ? 8 : 16;
+    a->tn_qp = qp;
     std::vector<int> edge(size_t(a->pptr[K]) * 2), site(size_t(K) * 8, 0);
     int64_t q = 0;
     for (int i = 0; i < K; ++i) {
@@ -784,8 +790,8 @@ nqs_status nqs_ansatz_create(nqs_ctx* ctx, int K, int n_alpha, int n_beta, int c
         int64_t qd = 1;
         for (int k = 0; k <= d; ++k) qd *= tq;
         st8[5] = int(q); q += r16(int64_t(tq) * cp);
-        st8[6] = int(q); q += int64_t(d) * cp * 16;
-        st8[7] = int(q); q += 4 * (qd / tq) * 16;   // U^s rows padded to 16 in the last index
+        st8[6] = int(q); q += r16(int64_t(d) * cp * qp);
+        st8[7] = int(q); q += r16(4 * (qd / tq) * qp);   // U^s rows padded to qp in the last index
       }
     }
     if (q >= (int64_t(1) << 31)) return fail(NQS_EUNSUPPORTED, "tensor-RNN parameter layout too large");

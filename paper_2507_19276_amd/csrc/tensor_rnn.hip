@@ -17,10 +17,11 @@
 // accumulated over (parent, unit) pairs with one LDS read per 16 FMAs.  The
 // parameter layout is the library's (see runtime.cpp): per edge M^T as
 // [s][k][u], per site v, eta, w, c, and per tensor site K0^T [i'][u], K_j as
-// [j][v][a] and U^s as [s][i'][a_1..a_(d-1)][a_d padded to 16], all padded to
-// chip = ceil16(chi) units.  The projections and the core contraction are
-// unrolled over 16 (zero-padded) entries, so every weight row is one scalar
-// 16-dword load feeding 16 FMAs.
+// [j][v][a padded to QP] and U^s as [s][i'][a_1..a_(d-1)][a_d padded to QP],
+// QP = 8 when every chi' <= 8, else 16, all padded to chip = ceil16(chi)
+// units.  The projections and the core contraction are unrolled over QP
+// (zero-padded) entries, so every weight row is one scalar QP-dword load
+// feeding QP FMAs.
 #include "device.h"
 #include "philox.h"
 
@@ -29,7 +30,7 @@ namespace {
 
 constexpr int kTnThreads = 64;
 
-template <typename T, bool SAMPLE>
+template <typename T, int QP, bool SAMPLE>
 __global__ __launch_bounds__(kTnThreads) void k_psi_tn(TnParams<T> P, const uint64_t* __restrict__ m, int64_t R,
                                                        double* __restrict__ lphi, int8_t* __restrict__ sphi,
                                                        SampleArgs SA) {
@@ -39,7 +40,7 @@ __global__ __launch_bounds__(kTnThreads) void k_psi_tn(TnParams<T> P, const uint
   constexpr int NT = kTnThreads;
   const int CP = P.chip, RW = P.rw;
   T* ring = reinterpret_cast<T*>(smem);                          // [W][rw][NT]
-  T* pl = ring + size_t(P.W) * RW * NT;                          // [16][NT]: first projection (d = 3)
+  T* pl = ring + size_t(P.W) * RW * NT;                          // [QP][NT]: first projection (d = 3)
   auto RG = [&](int slot, int k) -> T& { return ring[(size_t(slot) * RW + k) * NT + tid]; };
   auto PL = [&](int a) -> T& { return pl[a * NT + tid]; };
   const int64_t r = int64_t(blockIdx.x) * NT + tid;
@@ -54,35 +55,35 @@ __global__ __launch_bounds__(kTnThreads) void k_psi_tn(TnParams<T> P, const uint
   T prod = T(1);
   int pexp = 0, sgn = 1, ca = 0, cb = 0;
   bool bad = false;
-  // projections p_0..p_(d-1) (16 entries each, zero beyond chi') and the
-  // core contraction q^s (16 entries, zero beyond chi')
-  T p0[16], p1[16], p2[16], q[16];
+  // projections p_0..p_(d-1) (QP entries each, zero beyond chi') and the
+  // core contraction q^s (QP entries, zero beyond chi')
+  T p0[QP], p1[QP], p2[QP], q[QP];
   auto core = [&](int s, int Q, int d, int offU) {
 #pragma unroll
-    for (int ip = 0; ip < 16; ++ip) {
+    for (int ip = 0; ip < QP; ++ip) {
       q[ip] = T(0);
       if (ip >= Q) continue;
       T acc = T(0);
       if (d == 2) {
-        const int base = offU + (s * Q + ip) * Q * 16;
+        const int base = offU + (s * Q + ip) * Q * QP;
 #pragma unroll
-        for (int a1 = 0; a1 < 16; ++a1) {
+        for (int a1 = 0; a1 < QP; ++a1) {
           if (a1 >= Q) continue;
           T in = T(0);
 #pragma unroll
-          for (int a2 = 0; a2 < 16; ++a2) in = tfma(T(W[base + a1 * 16 + a2]), p1[a2], in);
+          for (int a2 = 0; a2 < QP; ++a2) in = tfma(T(W[base + a1 * QP + a2]), p1[a2], in);
           acc = tfma(p0[a1], in, acc);
         }
       } else {
-        const int base = offU + (s * Q + ip) * Q * Q * 16;
+        const int base = offU + (s * Q + ip) * Q * Q * QP;
         for (int a1 = 0; a1 < Q; ++a1) {
           T in = T(0);
 #pragma unroll
-          for (int a2 = 0; a2 < 16; ++a2) {
+          for (int a2 = 0; a2 < QP; ++a2) {
             if (a2 >= Q) continue;
             T in3 = T(0);
 #pragma unroll
-            for (int a3 = 0; a3 < 16; ++a3) in3 = tfma(T(W[base + (a1 * Q + a2) * 16 + a3]), p2[a3], in3);
+            for (int a3 = 0; a3 < QP; ++a3) in3 = tfma(T(W[base + (a1 * Q + a2) * QP + a3]), p2[a3], in3);
             in = tfma(p1[a2], in3, in);
           }
           acc = tfma(PL(a1), in, acc);
@@ -102,17 +103,17 @@ __global__ __launch_bounds__(kTnThreads) void k_psi_tn(TnParams<T> P, const uint
       for (int j = 0; j < 3; ++j) {
         if (j >= d) continue;
         const int ps = edge[2 * (e0 + j) + 1];
-        T pa[16];
+        T pa[QP];
 #pragma unroll
-        for (int a = 0; a < 16; ++a) pa[a] = T(0);
+        for (int a = 0; a < QP; ++a) pa[a] = T(0);
 #pragma unroll 4
         for (int v = 0; v < RW; ++v) {
           const T hv = RG(ps, v);
 #pragma unroll
-          for (int a = 0; a < 16; ++a) pa[a] = tfma(T(W[offKj + (j * CP + v) * 16 + a]), hv, pa[a]);
+          for (int a = 0; a < QP; ++a) pa[a] = tfma(T(W[offKj + (j * CP + v) * QP + a]), hv, pa[a]);
         }
 #pragma unroll
-        for (int a = 0; a < 16; ++a) {
+        for (int a = 0; a < QP; ++a) {
           if (j == 0) p0[a] = pa[a];
           if (j == 1) p1[a] = pa[a];
           if (j == 2) p2[a] = pa[a];
@@ -120,7 +121,7 @@ __global__ __launch_bounds__(kTnThreads) void k_psi_tn(TnParams<T> P, const uint
       }
       if (d == 3) {
 #pragma unroll
-        for (int a = 0; a < 16; ++a) PL(a) = p0[a];
+        for (int a = 0; a < QP; ++a) PL(a) = p0[a];
       }
     }
     const int si = SAMPLE ? 0 : site_state(lo, hi, i);
@@ -146,7 +147,7 @@ __global__ __launch_bounds__(kTnThreads) void k_psi_tn(TnParams<T> P, const uint
         }
         if (Q) {
 #pragma unroll
-          for (int ip = 0; ip < 16; ++ip) {
+          for (int ip = 0; ip < QP; ++ip) {
             if (ip >= Q) continue;
 #pragma unroll
             for (int u = 0; u < 16; ++u) acc[u] = tfma(T(W[offK0 + ip * CP + uc + u]), q[ip], acc[u]);
@@ -231,8 +232,13 @@ hipError_t run_tn(const TnParams<T>& P, const uint64_t* m, int64_t R, double* lp
   if (R <= 0) return hipSuccess;
   const size_t lds = (size_t(P.W) * P.rw + 16) * kTnThreads * sizeof(T);
   if (lds > 64 * 1024 || P.rw > P.chip || P.rw < P.chi) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((k_psi_tn<T, SAMPLE>), dim3(unsigned((R + kTnThreads - 1) / kTnThreads)), dim3(kTnThreads),
-                     lds, st, P, m, R, lphi, sphi, SA);
+  const dim3 grid(unsigned((R + kTnThreads - 1) / kTnThreads));
+  if (P.qp == 8)
+    hipLaunchKernelGGL((k_psi_tn<T, 8, SAMPLE>), grid, dim3(kTnThreads), lds, st, P, m, R, lphi, sphi, SA);
+  else if (P.qp == 16)
+    hipLaunchKernelGGL((k_psi_tn<T, 16, SAMPLE>), grid, dim3(kTnThreads), lds, st, P, m, R, lphi, sphi, SA);
+  else
+    return hipErrorInvalidValue;
   return hipGetLastError();
 }
 

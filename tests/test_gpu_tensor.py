@@ -147,3 +147,33 @@ def test_unsupported_forms(nqs, ctx):
         ans.logpsi(w.samples, "bf16")
     with pytest.raises(nqs.NqsError):
         ans.vjp(w.samples, torch.ones(w.n_samples, dtype=torch.float64))
+
+
+@pytest.mark.parametrize("chi", [32, 64])
+def test_wide_tucker_rank(nqs, ctx, chi):
+    """chi' > 8 (11 at chi = 32, 16 at chi = 64): the 16-wide padding of the
+    projections and cores; whole K=6 sector.  At chi = 64 a thread's FP64 ring
+    (3 x 64 states) does not fit the LDS: FP64 is refused, FP32 runs."""
+    K, na, nb = 6, 3, 3
+    pp, pi = W.graph_nn_nnn(K)
+    prm = W.ansatz_params(K, chi, pp, pi, 0, 31 + chi, tensor=True)
+    assert max(q for _, _, q in W.tensor_block_sizes(K, chi, pp)) > 8
+    ans = nqs.Ansatz(ctx, K, na, nb, chi, pp, pi, 0, tensor=True)
+    ans.bind(prm)
+    sector = W.all_onvs(K, na, nb)
+    ref = oracle.amplitudes(K, chi, na, nb, pp, pi, 0, prm, sector, tensor=True)
+    la, sg = ans.logpsi(sector, "f32")
+    assert np.abs(la.cpu().numpy() - ref["logabs"]).max() < 5e-5
+    assert np.array_equal(sg.cpu().numpy(), ref["sign"])
+    if chi == 64:
+        with pytest.raises(nqs.NqsError):
+            ans.logpsi(sector, "f64")
+        s, c, l2, _, nu = ans.sample(2000, seed=4, precision="f32")
+        assert int(c.sum()) == 2000
+        return
+    la, sg = ans.logpsi(sector, "f64")
+    assert np.abs(la.cpu().numpy() - ref["logabs"]).max() < 1e-12
+    assert np.array_equal(sg.cpu().numpy(), ref["sign"])
+    s, c, l2, _, nu = ans.sample(2000, seed=4, precision="f64")
+    ru, rc = oracle.sample_unique(K, chi, na, nb, pp, pi, prm, 4, 2000, tensor=True)
+    assert np.array_equal(s.cpu().numpy().view(np.uint64), ru) and np.array_equal(c.cpu().numpy(), rc)
