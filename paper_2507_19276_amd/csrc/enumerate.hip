@@ -51,23 +51,32 @@ __device__ inline int first_changed_site(uint64_t xlo, uint64_t xhi) {
 // first changed site c1 of row m against its sample n, and the row's second
 // changed site c2 (K if none) with its local state at c1 packed as
 // c2 | state << 8
+// first changed site of the row (t0) and, packed in sec, the second changed
+// site c2 (bits 0-7), the row's state at c1 (bits 8-9), the third changed site
+// c3 (bits 16-23) and the row's state at c2 (bits 24-25); absent sites are K
 __device__ inline void row_sites(uint64_t mlo, uint64_t mhi, uint64_t nlo, uint64_t nhi, int K, uint8_t* t0,
-                                 uint16_t* sec) {
+                                 uint32_t* sec) {
   uint64_t xl = mlo ^ nlo, xh = mhi ^ nhi;
   const int c1 = first_changed_site(xl, xh);
   *t0 = uint8_t(c1);
   if (!sec) return;
-  const int P = 2 * c1;
-  int st;
-  if (P < 64) {
-    st = int((mlo >> P) & 3ull);
-    xl &= ~(3ull << P);
-  } else {
-    st = int((mhi >> (P - 64)) & 3ull);
-    xh &= ~(3ull << (P - 64));
-  }
+  auto take = [&](int c) {   // the row's state at site c; clears the site from the difference
+    const int P = 2 * c;
+    int st;
+    if (P < 64) {
+      st = int((mlo >> P) & 3ull);
+      xl &= ~(3ull << P);
+    } else {
+      st = int((mhi >> (P - 64)) & 3ull);
+      xh &= ~(3ull << (P - 64));
+    }
+    return st;
+  };
+  const int s1 = take(c1);
   const int c2 = (xl | xh) ? first_changed_site(xl, xh) : K;
-  *sec = uint16_t(c2 | (st << 8));
+  const int s2 = c2 < K ? take(c2) : 0;
+  const int c3 = (xl | xh) ? first_changed_site(xl, xh) : K;
+  *sec = uint32_t(c2) | (uint32_t(s1) << 8) | (uint32_t(c3) << 16) | (uint32_t(s2) << 24);
 }
 
 __device__ inline bool bit_at(uint64_t lo, uint64_t hi, int P) {
@@ -520,7 +529,7 @@ __global__ __launch_bounds__(256) void k_fill(HamDev H, EnumGeom G, const uint64
       rows.owner[r0] = int32_t(n);
       if (rows.rank) rows.rank[r0] = -1;
       if (rows.t0) rows.t0[r0] = uint8_t(H.K);
-      if (rows.sec) rows.sec[r0] = uint16_t(H.K);
+      if (rows.sec) rows.sec[r0] = uint32_t(H.K) | (uint32_t(H.K) << 16);
     }
     const int64_t u = Un[n];
     const int64_t d0 = r0 + 1 + Dn[n];

@@ -133,7 +133,8 @@ struct Rows {
   int32_t* owner;    // [R]
   int64_t* rank;     // [R]   (-1 for the sample's own row)
   uint8_t* t0;       // [R]   first site where m differs from its sample (K when equal); may be null
-  uint16_t* sec;     // [R]   second changed site | state of m at the first << 8; may be null
+  uint32_t* sec;     // [R]   c2 | state at c1 << 8 | c3 << 16 | state at c2 << 24 (next changed sites,
+                     //       K when absent); may be null
 };
 
 // ---- launchers (enumerate.hip) ----------------------------------------
@@ -205,17 +206,18 @@ struct PsiStates {
 };
 // node list written by nodes.hip
 struct NodeList {
-  uint64_t* m;                   // [nodes][2] ONV: the sample with one site changed
+  uint64_t* m;                   // [nodes][2] ONV: the sample with its rows' first (two) changes
   int32_t* owner;                // [nodes] sample
   uint8_t* c1;                   // [nodes] changed site
   uint8_t* e1;                   // [nodes] largest resume site of its rows
   int64_t* off;                  // [nodes] first storage entry
 };
-hipError_t launch_node_count(const uint8_t* t0, const uint16_t* sec, const int64_t* rowptr, int64_t n0, int64_t n1,
+bool node_pairs(int K);   // nodes keyed by the first two changes (else by the first)
+hipError_t launch_node_count(const uint8_t* t0, const uint32_t* sec, const int64_t* rowptr, int64_t n0, int64_t n1,
                              int64_t row_base, int K, int32_t* ncnt, int64_t* nent, hipStream_t st);
 hipError_t launch_node_scan(int64_t ns, int64_t cap, int32_t* ncnt, int64_t* nent, int64_t* nbase, int64_t* ebase,
                             int64_t* totals, hipStream_t st);
-hipError_t launch_node_assign(const uint8_t* t0, const uint16_t* sec, const uint64_t* samples,
+hipError_t launch_node_assign(const uint8_t* t0, const uint32_t* sec, const uint64_t* samples,
                               const int64_t* rowptr, int64_t n0, int64_t n1, int64_t row_base, int K,
                               const int64_t* nbase, const int64_t* ebase, const NodeList& nl, int32_t* row_node,
                               uint8_t* row_site, hipStream_t st);

@@ -1,17 +1,22 @@
-// Shared prefixes of the amplitude rows, one level deep.  A row m of sample n
-// differs from n at the sites c1 < c2 < ...; every row with the same first
-// change (c1, state of m at c1) runs through the same hidden states up to
-// its second changed site c2 (the conditionals of Eqs. (9)-(10) at a site
+// Shared prefixes of the amplitude rows.  A row m of sample n differs from n at
+// the sites c1 < c2 < c3 < ...; every row with the same first two changes
+// (c1, state of m at c1, c2, state at c2) runs through the same hidden states
+// up to its third changed site c3 (the conditionals of Eqs. (9)-(10) at a site
 // see only the occupations below it).  Such a group is a node: the ONV of n
-// with site c1 set to the row's state there.  The node is evaluated once from
-// c1 (resumed from its sample) and stores its carried states and log-product
-// states for sites c1 .. e1, e1 = the largest c2 of its rows; each row then
-// resumes at c2 from the node.  Rows with a single changed site resume at K.
+// with sites c1 and c2 set to the rows' states there (a row with a single
+// change has c2 = K and shares a node with the rows of the same first change
+// and no second one).  The node is evaluated from c1 (resumed from its sample)
+// and stores its carried states and log-product states for the sites
+// c1 .. e, e = the largest c3 of its rows; each row then resumes at c3 from the
+// node.  Rows with fewer than three changed sites resume at K.
+//
+// For K > 30 the table of pair keys does not fit the LDS; nodes are then keyed
+// by the first change alone and rows resume at their second changed site.
 //
 // Three launches per pass of rows, all deterministic:
-//   count:  one workgroup per sample marks the keys (c1, state) present among
-//           its rows in an LDS table and the largest c2 per key; writes the
-//           sample's node count and storage entries (sum of e1 - c1 + 1);
+//   count:  one workgroup per sample marks the keys present among its rows in
+//           an LDS table with the largest resume site per key; writes the
+//           sample's node count and storage entries (sum of e - c1 + 1);
 //   scan:   one workgroup: exclusive offsets over the samples; a sample's
 //           nodes are kept only if all of them fit the storage capacity
 //           (whole samples in order, so the choice is deterministic);
@@ -23,37 +28,88 @@
 namespace nqs {
 namespace {
 
-// table of one sample: e[key] = largest c2 + 1 (0 = key absent), key =
-// c1 * 4 + state at c1, from the bytes the fill kernel wrote per row (the
-// sample's own row has c1 = K)
-__device__ void build_table(const uint8_t* t0, const uint16_t* sec, int64_t r0, int64_t r1, int K, int* e) {
-  for (int k = threadIdx.x; k < 4 * K; k += blockDim.x) e[k] = 0;
+constexpr int kNodeThreads = 256;
+
+// key of a row and the site its row resumes at (pair keys when `pair`)
+struct RowKey {
+  int key, c1, res;
+};
+
+__device__ inline RowKey row_key(uint8_t t0, uint32_t v, int K, bool pair) {
+  RowKey k;
+  k.c1 = t0;
+  const int c2 = int(v & 0xFF), s1 = int((v >> 8) & 3), c3 = int((v >> 16) & 0xFF), s2 = int((v >> 24) & 3);
+  if (pair) {
+    k.key = ((k.c1 * 4 + s1) * (K + 1) + c2) * 4 + (c2 < K ? s2 : 0);
+    k.res = c3;
+  } else {
+    k.key = k.c1 * 4 + s1;
+    k.res = c2;
+  }
+  return k;
+}
+
+__device__ inline int key_c1(int key, int K, bool pair) { return pair ? key / (16 * (K + 1)) : key / 4; }
+
+// table of one sample: e[key] = largest resume site + 1 (0 = key absent); the
+// sample's own row (t0 = K) has no key
+__device__ void build_table(const uint8_t* t0, const uint32_t* sec, int64_t r0, int64_t r1, int K, bool pair,
+                            int T, int* e) {
+  for (int k = threadIdx.x; k < T; k += blockDim.x) e[k] = 0;
   __syncthreads();
   for (int64_t r = r0 + threadIdx.x; r < r1; r += blockDim.x) {
-    const int c1 = t0[r];
-    if (c1 >= K) continue;
-    const int v = sec[r];
-    atomicMax(&e[c1 * 4 + (v >> 8)], (v & 0xFF) + 1);
+    if (t0[r] >= K) continue;
+    const RowKey k = row_key(t0[r], sec[r], K, pair);
+    atomicMax(&e[k.key], k.res + 1);
   }
   __syncthreads();
 }
 
-__global__ __launch_bounds__(256) void k_node_count(const uint8_t* __restrict__ t0, const uint16_t* __restrict__ sec,
-                                                    const int64_t* rowptr, int64_t n0, int64_t row_base, int K,
-                                                    int32_t* ncnt, int64_t* nent) {
-  __shared__ int e[256];
+// block-wide exclusive scan of (count, entries) pairs held one per thread
+__device__ void block_scan(int& cnt, int64_t& ent, int* sc, int64_t* se, int& tot_cnt, int64_t& tot_ent) {
+  const int tid = threadIdx.x;
+  sc[tid] = cnt;
+  se[tid] = ent;
+  __syncthreads();
+  for (int d = 1; d < kNodeThreads; d <<= 1) {
+    const int vc = tid >= d ? sc[tid - d] : 0;
+    const int64_t ve = tid >= d ? se[tid - d] : 0;
+    __syncthreads();
+    sc[tid] += vc;
+    se[tid] += ve;
+    __syncthreads();
+  }
+  tot_cnt = sc[kNodeThreads - 1];
+  tot_ent = se[kNodeThreads - 1];
+  cnt = tid > 0 ? sc[tid - 1] : 0;
+  ent = tid > 0 ? se[tid - 1] : 0;
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(kNodeThreads) void k_node_count(const uint8_t* __restrict__ t0,
+                                                             const uint32_t* __restrict__ sec, const int64_t* rowptr,
+                                                             int64_t n0, int64_t row_base, int K, int pair_i,
+                                                             int32_t* ncnt, int64_t* nent) {
+  extern __shared__ int e[];
+  __shared__ int sc[kNodeThreads];
+  __shared__ int64_t se[kNodeThreads];
+  const bool pair = pair_i != 0;
+  const int T = pair ? 16 * K * (K + 1) : 4 * K;
   const int64_t n = n0 + blockIdx.x;
-  build_table(t0, sec, rowptr[n] - row_base, rowptr[n + 1] - row_base, K, e);
+  build_table(t0, sec, rowptr[n] - row_base, rowptr[n + 1] - row_base, K, pair, T, e);
+  int cnt = 0;
+  int64_t ent = 0;
+  for (int k = threadIdx.x; k < T; k += blockDim.x)
+    if (e[k]) {
+      ++cnt;
+      ent += (e[k] - 1) - key_c1(k, K, pair) + 1;
+    }
+  int tc;
+  int64_t te;
+  block_scan(cnt, ent, sc, se, tc, te);
   if (threadIdx.x == 0) {
-    int cnt = 0;
-    int64_t ent = 0;
-    for (int k = 0; k < 4 * K; ++k)
-      if (e[k]) {
-        ++cnt;
-        ent += (e[k] - 1) - k / 4 + 1;
-      }
-    ncnt[blockIdx.x] = cnt;
-    nent[blockIdx.x] = ent;
+    ncnt[blockIdx.x] = tc;
+    nent[blockIdx.x] = te;
   }
 }
 
@@ -104,62 +160,100 @@ __global__ __launch_bounds__(1024) void k_node_scan(int64_t ns, int64_t cap, int
   }
 }
 
-__global__ __launch_bounds__(256) void k_node_assign(const uint8_t* __restrict__ t0, const uint16_t* __restrict__ sec,
-                                                     const uint64_t* __restrict__ samples, const int64_t* rowptr,
-                                                     int64_t n0, int64_t row_base, int K, const int64_t* nbase,
-                                                     const int64_t* ebase, NodeList nl,
-                                                     int32_t* row_node, uint8_t* row_site) {
-  __shared__ int e[256];
-  __shared__ int id[256];
+__global__ __launch_bounds__(kNodeThreads) void k_node_assign(const uint8_t* __restrict__ t0,
+                                                              const uint32_t* __restrict__ sec,
+                                                              const uint64_t* __restrict__ samples,
+                                                              const int64_t* rowptr, int64_t n0, int64_t row_base,
+                                                              int K, int pair_i, const int64_t* nbase,
+                                                              const int64_t* ebase, NodeList nl, int32_t* row_node,
+                                                              uint8_t* row_site) {
+  extern __shared__ int e[];
+  __shared__ int sc[kNodeThreads];
+  __shared__ int64_t se[kNodeThreads];
+  const bool pair = pair_i != 0;
+  const int T = pair ? 16 * K * (K + 1) : 4 * K;
   const int64_t n = n0 + blockIdx.x;
   const int64_t r0 = rowptr[n] - row_base, r1 = rowptr[n + 1] - row_base;
-  build_table(t0, sec, r0, r1, K, e);
+  build_table(t0, sec, r0, r1, K, pair, T, e);
   const int64_t nb = nbase[blockIdx.x];
   const bool keep = nb >= 0;
   const uint64_t nlo = samples[2 * n], nhi = samples[2 * n + 1];
-  if (threadIdx.x == 0) {
-    int j = 0;
-    int64_t off = ebase[blockIdx.x];
-    for (int k = 0; k < 4 * K; ++k) {
-      id[k] = -1;
-      if (!e[k]) continue;
-      const int c1 = k / 4, e1 = e[k] - 1;
-      if (keep) {
-        const int64_t node = nb + j;
-        id[k] = int(node);
-        const int P = 2 * c1;
-        uint64_t lo = nlo, hi = nhi;
-        if (P < 64) lo = (lo & ~(3ull << P)) | (uint64_t(k & 3) << P);
-        else hi = (hi & ~(3ull << (P - 64))) | (uint64_t(k & 3) << (P - 64));
-        nl.m[2 * node] = lo;
-        nl.m[2 * node + 1] = hi;
-        nl.owner[node] = int32_t(n);
-        nl.c1[node] = uint8_t(c1);
-        nl.e1[node] = uint8_t(e1);
-        nl.off[node] = off;
-      }
-      ++j;
-      off += e1 - c1 + 1;
+  // each thread numbers the keys of one contiguous chunk, in key order
+  const int chunk = (T + kNodeThreads - 1) / kNodeThreads;
+  const int k0 = threadIdx.x * chunk, k1 = k0 + chunk < T ? k0 + chunk : T;
+  int cnt = 0;
+  int64_t ent = 0;
+  for (int k = k0; k < k1; ++k)
+    if (e[k]) {
+      ++cnt;
+      ent += (e[k] - 1) - key_c1(k, K, pair) + 1;
     }
+  int tc;
+  int64_t te;
+  block_scan(cnt, ent, sc, se, tc, te);
+  int j = cnt;
+  int64_t off = ebase[blockIdx.x] + ent;
+  for (int k = k0; k < k1; ++k) {
+    const int ek = e[k];
+    if (!ek) {
+      e[k] = -1;
+      continue;
+    }
+    const int c1 = key_c1(k, K, pair), last = ek - 1;
+    if (keep) {
+      const int64_t node = nb + j;
+      uint64_t lo = nlo, hi = nhi;
+      const int s1 = pair ? (k / (4 * (K + 1))) % 4 : k % 4;
+      int P = 2 * c1;
+      if (P < 64) lo = (lo & ~(3ull << P)) | (uint64_t(s1) << P);
+      else hi = (hi & ~(3ull << (P - 64))) | (uint64_t(s1) << (P - 64));
+      if (pair) {
+        const int c2 = (k / 4) % (K + 1), s2 = k % 4;
+        if (c2 < K) {
+          P = 2 * c2;
+          if (P < 64) lo = (lo & ~(3ull << P)) | (uint64_t(s2) << P);
+          else hi = (hi & ~(3ull << (P - 64))) | (uint64_t(s2) << (P - 64));
+        }
+      }
+      nl.m[2 * node] = lo;
+      nl.m[2 * node + 1] = hi;
+      nl.owner[node] = int32_t(n);
+      nl.c1[node] = uint8_t(c1);
+      nl.e1[node] = uint8_t(last);
+      nl.off[node] = off;
+      e[k] = int(node);
+    } else {
+      e[k] = -1;
+    }
+    ++j;
+    off += last - c1 + 1;
   }
   __syncthreads();
   for (int64_t r = r0 + threadIdx.x; r < r1; r += blockDim.x) {
-    const int c1 = int(t0[r]);
-    const int v = sec[r];
-    const int node = c1 < K ? id[c1 * 4 + (v >> 8)] : -1;
+    if (t0[r] >= K) {
+      row_node[r] = -1;
+      row_site[r] = uint8_t(K);
+      continue;
+    }
+    const RowKey k = row_key(t0[r], sec[r], K, pair);
+    const int node = e[k.key];
     row_node[r] = node;
-    row_site[r] = uint8_t(c1 >= K ? K : (node >= 0 ? (v & 0xFF) : c1));
+    row_site[r] = uint8_t(node >= 0 ? k.res : k.c1);
   }
 }
 
 }  // namespace
 
-hipError_t launch_node_count(const uint8_t* t0, const uint16_t* sec, const int64_t* rowptr, int64_t n0, int64_t n1,
+bool node_pairs(int K) { return 16 * K * (K + 1) * int(sizeof(int)) <= 60 * 1024; }
+
+hipError_t launch_node_count(const uint8_t* t0, const uint32_t* sec, const int64_t* rowptr, int64_t n0, int64_t n1,
                              int64_t row_base, int K, int32_t* ncnt, int64_t* nent, hipStream_t st) {
   if (n1 <= n0) return hipSuccess;
   if (K < 1 || K > 64) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_node_count, dim3(unsigned(n1 - n0)), dim3(256), 0, st, t0, sec, rowptr, n0, row_base, K,
-                     ncnt, nent);
+  const bool pair = node_pairs(K);
+  const size_t lds = size_t(pair ? 16 * K * (K + 1) : 4 * K) * sizeof(int);
+  hipLaunchKernelGGL(k_node_count, dim3(unsigned(n1 - n0)), dim3(kNodeThreads), lds, st, t0, sec, rowptr, n0,
+                     row_base, K, pair ? 1 : 0, ncnt, nent);
   return hipGetLastError();
 }
 
@@ -170,13 +264,15 @@ hipError_t launch_node_scan(int64_t ns, int64_t cap, int32_t* ncnt, int64_t* nen
   return hipGetLastError();
 }
 
-hipError_t launch_node_assign(const uint8_t* t0, const uint16_t* sec, const uint64_t* samples,
+hipError_t launch_node_assign(const uint8_t* t0, const uint32_t* sec, const uint64_t* samples,
                               const int64_t* rowptr, int64_t n0, int64_t n1, int64_t row_base, int K,
                               const int64_t* nbase, const int64_t* ebase, const NodeList& nl, int32_t* row_node,
                               uint8_t* row_site, hipStream_t st) {
   if (n1 <= n0) return hipSuccess;
-  hipLaunchKernelGGL(k_node_assign, dim3(unsigned(n1 - n0)), dim3(256), 0, st, t0, sec, samples, rowptr, n0,
-                     row_base, K, nbase, ebase, nl, row_node, row_site);
+  const bool pair = node_pairs(K);
+  const size_t lds = size_t(pair ? 16 * K * (K + 1) : 4 * K) * sizeof(int);
+  hipLaunchKernelGGL(k_node_assign, dim3(unsigned(n1 - n0)), dim3(kNodeThreads), lds, st, t0, sec, samples, rowptr,
+                     n0, row_base, K, pair ? 1 : 0, nbase, ebase, nl, row_node, row_site);
   return hipGetLastError();
 }
 

@@ -1025,9 +1025,11 @@ EnumGeom make_geom(int64_t n_conn, int64_t N) {
 }
 
 // node storage entries of a pass (one entry: a carried state and a log-product
-// state): one per 8 rows, at least one sample's worth (at most 4K nodes of at
-// most K+1 entries each)
+// state).  Nodes keyed by the first two changes need about 1.4 entries per
+// row (measured on the chain, lattice and dense workloads); nodes keyed by the
+// first change alone 0.05-0.16.  Samples beyond the cap resume at c1.
 int64_t node_entry_cap(int64_t pass_rows, int K) {
+  if (node_pairs(K)) return std::max<int64_t>(pass_rows / 2 * 3, int64_t(16) * K * (K + 1));
   return std::max<int64_t>(pass_rows / 8, int64_t(4) * K * (K + 1));
 }
 
@@ -1334,7 +1336,7 @@ nqs_status nqs_eloc(nqs_ctx* ctx, const nqs_instance* inst, const nqs_ansatz* an
     rs.npg = S.get<int8_t>(ecap);
     row_node = S.get<int32_t>(cap_used);
     row_site = S.get<uint8_t>(cap_used);
-    P.rows.sec = S.get<uint16_t>(cap_used);
+    P.rows.sec = S.get<uint32_t>(cap_used);
   }
   if (S.oom) return fail(NQS_ENOMEM, "workspace allocation failed");
   if (ans->nh) HIPCHK(launch_corr_theta(ans->corr(), samples, N, theta, Etab, opts->precision, stream));
@@ -1703,7 +1705,7 @@ nqs_status nqs_eloc_workspace_bytes(const nqs_instance* inst, const nqs_ansatz* 
       b += al(size_t(ecap) * 16) + al(size_t(ecap) * 4) + 2 * al(size_t(ecap)) + al(size_t(ecap) * 8);
       b += al(size_t(ecap) * 4) + al(size_t(ecap)) + al(size_t(ecap) * 8) + al(size_t(ecap));
       b += al(size_t(ecap) * ans->chip * esz) + al(size_t(ecap) * esz) + al(size_t(ecap) * 4) + al(size_t(ecap));
-      b += al(size_t(rows) * 4) + al(size_t(rows)) + al(size_t(rows) * 2);
+      b += al(size_t(rows) * 4) + al(size_t(rows)) + al(size_t(rows) * 4);
     }
   }
   b += 3 * al(size_t(N) * 8) + al(64);     // outputs the caller did not provide, batch sums

@@ -1,6 +1,6 @@
 """Resumed amplitude rows.  BF16 rows start at their first changed site from
-their sample's stored state; FP64/FP32 rows start at their second changed
-site from a node shared by the rows with the same first change (itself
+their sample's stored state; FP64/FP32 rows start at their third changed
+site from a node shared by the rows with the same first two changes (itself
 resumed from the sample).  The autoregressive conditionals at a site see only
 the occupations below it, so every result must be bit-identical to evaluating
 every row from site 0, on every workload, with and without row passes; and
@@ -96,10 +96,10 @@ def site_state(w0, w1, i):
 
 def test_site_count_matches_changed_sites(nqs, ctx):
     """Executed site evaluations.  FP32/FP64: the samples' pass (N K), one
-    node per (sample, first changed site, state there) from that site on, and
-    every row from its second changed site on.  BF16 (no node level): N K plus
-    every row from its first changed site.  Counted here from the row list of
-    the same call."""
+    node per (sample, first changed site and state there, second changed site
+    and state there) from its first changed site on, and every row from its
+    third changed site on.  BF16 (no node level): N K plus every row from its
+    first changed site.  Counted here from the row list of the same call."""
     w, inst, ans = setup(nqs, ctx, "c2", 64)
     kw = dict(eps=w.eps, n_eps=w.n_eps, seed=w.seed, stream_id=7)
     r = nqs.rows(ctx, inst, w.samples, **kw)
@@ -114,9 +114,11 @@ def test_site_count_matches_changed_sites(nqs, ctx):
         nodes = set()
         for k, c in enumerate(ch[1:], start=1):
             one += K - c[0]
-            nodes.add((c[0], site_state(rows[k, 0], rows[k, 1], c[0])))
-            two += K - (c[1] if len(c) > 1 else K)
-        two += sum(K - c1 for c1, _ in nodes)
+            c2 = c[1] if len(c) > 1 else K
+            s2 = site_state(rows[k, 0], rows[k, 1], c2) if c2 < K else 0
+            nodes.add((c[0], site_state(rows[k, 0], rows[k, 1], c[0]), c2, s2))
+            two += K - (c[2] if len(c) > 2 else K)
+        two += sum(K - key[0] for key in nodes)
     _, st = nqs.eloc(ctx, inst, ans, w.samples, precision="f32", **kw)
     assert st["n_site_rows"] == two
     _, st = nqs.eloc(ctx, inst, ans, w.samples, precision="bf16", **kw)
