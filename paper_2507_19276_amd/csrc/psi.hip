@@ -193,7 +193,20 @@ __global__ __launch_bounds__(256) void k_psi_mt(PsiParams<T> P, const uint64_t* 
       X.npg[so] = int8_t(sgn);
     }
   };
-  for (int i = i0; i < P.K; ++i) {
+  // a node wavefront stops after the largest resume site of its nodes' rows
+  int iend = P.K;
+  if constexpr (STORE == 2) {
+    int em = 0;
+#pragma unroll
+    for (int t = 0; t < NTL; ++t) em = te1[t] > em ? te1[t] : em;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      const int x = __shfl_xor(em, o);
+      em = x > em ? x : em;
+    }
+    iend = __builtin_amdgcn_readfirstlane(em < P.K ? em : P.K);
+  }
+  for (int i = i0; i < iend; ++i) {
     store_pre(i);
     V acc[NTL][NT], wv4[TPC], ev4[TPC];
     // w and eta of this site are needed only after the contractions
@@ -406,7 +419,7 @@ __global__ __launch_bounds__(256) void k_psi_mt(PsiParams<T> P, const uint64_t* 
     ca += osi & 1;
     cb += osi >> 1;
   }
-  store_pre(P.K);
+  store_pre(iend);
   const bool writer = NTL == 4 || (NTL == 2 ? (g & 1) == 0 : g == 0);
   if (writer && olive) {
     lphi[orow] = bad ? -INFINITY : 0.5 * (log(double(prod)) + double(pexp) * 0.69314718055994530942);

@@ -1400,12 +1400,9 @@ nqs_status nqs_eloc(nqs_ctx* ctx, const nqs_instance* inst, const nqs_ansatz* an
           rn.unode = nullptr;
           if ((s = run_amplitudes(ans, opts->precision, nl.m, nn, lphi_n, sphi_n, stream, &rn, PSI_NODE)) != NQS_OK)
             return s;
-          if (stats) {
-            std::vector<int64_t> tot(K + 1);
-            HIPCHK(hipMemcpyAsync(tot.data(), rs.tot, sizeof(int64_t) * (K + 1), hipMemcpyDeviceToHost, stream));
-            HIPCHK(hipStreamSynchronize(stream));
-            for (int k = 0; k <= K; ++k) site_rows += tot[k] * (K - k);
-          }
+          // a node is evaluated from its first changed site to the largest
+          // resume site of its rows: (entries - 1) sites
+          site_rows += tot2[1] - tot2[0];
         }
         rs.noff = nl.off;
         rs.nc1 = nl.c1;

@@ -97,8 +97,8 @@ def site_state(w0, w1, i):
 def test_site_count_matches_changed_sites(nqs, ctx):
     """Executed site evaluations.  FP32/FP64: the samples' pass (N K), one
     node per (sample, first changed site and state there, second changed site
-    and state there) from its first changed site on, and every row from its
-    third changed site on.  BF16 (no node level): N K plus every row from its
+    and state there) from its first changed site to the largest third changed
+    site of its rows, and every row from its third changed site on.  BF16 (no node level): N K plus every row from its
     first changed site.  Counted here from the row list of the same call."""
     w, inst, ans = setup(nqs, ctx, "c2", 64)
     kw = dict(eps=w.eps, n_eps=w.n_eps, seed=w.seed, stream_id=7)
@@ -111,14 +111,16 @@ def test_site_count_matches_changed_sites(nqs, ctx):
         rows = m[rp[s]:rp[s + 1]]
         ch = changed_sites(rows, w.samples[s], K)
         assert ch[0] == []            # the sample's own row
-        nodes = set()
+        nodes = {}
         for k, c in enumerate(ch[1:], start=1):
             one += K - c[0]
             c2 = c[1] if len(c) > 1 else K
             s2 = site_state(rows[k, 0], rows[k, 1], c2) if c2 < K else 0
-            nodes.add((c[0], site_state(rows[k, 0], rows[k, 1], c[0]), c2, s2))
-            two += K - (c[2] if len(c) > 2 else K)
-        two += sum(K - key[0] for key in nodes)
+            c3 = c[2] if len(c) > 2 else K
+            key = (c[0], site_state(rows[k, 0], rows[k, 1], c[0]), c2, s2)
+            nodes[key] = max(nodes.get(key, 0), c3)
+            two += K - c3
+        two += sum(e - key[0] for key, e in nodes.items())
     _, st = nqs.eloc(ctx, inst, ans, w.samples, precision="f32", **kw)
     assert st["n_site_rows"] == two
     _, st = nqs.eloc(ctx, inst, ans, w.samples, precision="bf16", **kw)
