@@ -40,7 +40,7 @@ PEAKS = {"f64": 78.6, "f32": 157.3, "bf16": 2500.0}   # MI355X dense MFMA, TFLOP
 # from the FETCH_SIZE / WRITE_SIZE counters (copy-calibrated) recorded in
 # profiles/; valid only for the kernel source they were taken on (first 16 hex
 # digits of the sha256 of psi.hip followed by device.h).
-MEASURED_TRAFFIC = {"f32": {"sha16": "f4fc29c3ccc6aa3b", "bytes_per_launch": 4.7045960e9}}
+MEASURED_TRAFFIC = {"f32": {"sha16": "296f4619b6e48725", "bytes_per_launch": 1.04347374e10}}
 KERNEL_SOURCES = ("psi.hip", "device.h")
 
 
