@@ -212,13 +212,13 @@ struct NodeList {
   uint8_t* e1;                   // [nodes] largest resume site of its rows
   int64_t* off;                  // [nodes] first storage entry
 };
-bool node_pairs(int K);   // nodes keyed by the first two changes (else by the first)
+bool node_pairs(int K);   // whether nodes can be keyed by the first two changes (else by the first)
 hipError_t launch_node_count(const uint8_t* t0, const uint32_t* sec, const int64_t* rowptr, int64_t n0, int64_t n1,
-                             int64_t row_base, int K, int32_t* ncnt, int64_t* nent, hipStream_t st);
+                             int64_t row_base, int K, bool pair, int32_t* ncnt, int64_t* nent, hipStream_t st);
 hipError_t launch_node_scan(int64_t ns, int64_t cap, int32_t* ncnt, int64_t* nent, int64_t* nbase, int64_t* ebase,
                             int64_t* totals, hipStream_t st);
 hipError_t launch_node_assign(const uint8_t* t0, const uint32_t* sec, const uint64_t* samples,
-                              const int64_t* rowptr, int64_t n0, int64_t n1, int64_t row_base, int K,
+                              const int64_t* rowptr, int64_t n0, int64_t n1, int64_t row_base, int K, bool pair,
                               const int64_t* nbase, const int64_t* ebase, const NodeList& nl, int32_t* row_node,
                               uint8_t* row_site, hipStream_t st);
 hipError_t launch_psi_f64(const PsiParams<double>& P, const uint64_t* m, int64_t R, double* lphi,

@@ -10,8 +10,9 @@
 // c1 .. e, e = the largest c3 of its rows; each row then resumes at c3 from the
 // node.  Rows with fewer than three changed sites resume at K.
 //
-// For K > 30 the table of pair keys does not fit the LDS; nodes are then keyed
-// by the first change alone and rows resume at their second changed site.
+// With `pair` false (chosen by the caller, and always for K > 30, where the
+// table of pair keys does not fit the LDS) nodes are keyed by the first change
+// alone and rows resume at their second changed site.
 //
 // Three launches per pass of rows, all deterministic:
 //   count:  one workgroup per sample marks the keys present among its rows in
@@ -247,10 +248,9 @@ __global__ __launch_bounds__(kNodeThreads) void k_node_assign(const uint8_t* __r
 bool node_pairs(int K) { return 16 * K * (K + 1) * int(sizeof(int)) <= 60 * 1024; }
 
 hipError_t launch_node_count(const uint8_t* t0, const uint32_t* sec, const int64_t* rowptr, int64_t n0, int64_t n1,
-                             int64_t row_base, int K, int32_t* ncnt, int64_t* nent, hipStream_t st) {
+                             int64_t row_base, int K, bool pair, int32_t* ncnt, int64_t* nent, hipStream_t st) {
   if (n1 <= n0) return hipSuccess;
-  if (K < 1 || K > 64) return hipErrorInvalidValue;
-  const bool pair = node_pairs(K);
+  if (K < 1 || K > 64 || (pair && !node_pairs(K))) return hipErrorInvalidValue;
   const size_t lds = size_t(pair ? 16 * K * (K + 1) : 4 * K) * sizeof(int);
   hipLaunchKernelGGL(k_node_count, dim3(unsigned(n1 - n0)), dim3(kNodeThreads), lds, st, t0, sec, rowptr, n0,
                      row_base, K, pair ? 1 : 0, ncnt, nent);
@@ -265,11 +265,11 @@ hipError_t launch_node_scan(int64_t ns, int64_t cap, int32_t* ncnt, int64_t* nen
 }
 
 hipError_t launch_node_assign(const uint8_t* t0, const uint32_t* sec, const uint64_t* samples,
-                              const int64_t* rowptr, int64_t n0, int64_t n1, int64_t row_base, int K,
+                              const int64_t* rowptr, int64_t n0, int64_t n1, int64_t row_base, int K, bool pair,
                               const int64_t* nbase, const int64_t* ebase, const NodeList& nl, int32_t* row_node,
                               uint8_t* row_site, hipStream_t st) {
   if (n1 <= n0) return hipSuccess;
-  const bool pair = node_pairs(K);
+  if (pair && !node_pairs(K)) return hipErrorInvalidValue;
   const size_t lds = size_t(pair ? 16 * K * (K + 1) : 4 * K) * sizeof(int);
   hipLaunchKernelGGL(k_node_assign, dim3(unsigned(n1 - n0)), dim3(kNodeThreads), lds, st, t0, sec, samples, rowptr,
                      n0, row_base, K, pair ? 1 : 0, nbase, ebase, nl, row_node, row_site);

@@ -1028,9 +1028,15 @@ EnumGeom make_geom(int64_t n_conn, int64_t N) {
 // state).  Nodes keyed by the first two changes need about 1.4 entries per
 // row (measured on the chain, lattice and dense workloads); nodes keyed by the
 // first change alone 0.05-0.16.  Samples beyond the cap resume at c1.
-int64_t node_entry_cap(int64_t pass_rows, int K) {
-  if (node_pairs(K)) return std::max<int64_t>(pass_rows / 2 * 3, int64_t(16) * K * (K + 1));
+int64_t node_entry_cap(int64_t pass_rows, int K, bool pair) {
+  if (pair) return std::max<int64_t>(pass_rows / 2 * 3, int64_t(16) * K * (K + 1));
   return std::max<int64_t>(pass_rows / 8, int64_t(4) * K * (K + 1));
+}
+
+// nodes keyed by the first two changes where the pair table fits the LDS
+bool pair_nodes(int K, int precision) {
+  (void)precision;
+  return node_pairs(K);
 }
 
 int64_t max_samples_per_pass(const std::vector<std::pair<int64_t, int64_t>>& passes) {
@@ -1304,10 +1310,12 @@ nqs_status nqs_eloc(nqs_ctx* ctx, const nqs_instance* inst, const nqs_ansatz* an
     lphi_s = S.get<double>(N);
     sphi_s = S.get<int8_t>(N);
   }
-  // one level of shared prefixes (FP64/FP32): node list, compact storage
+  // one level of shared prefixes (FP64/FP32; BF16 rows are cheap enough per
+  // site that a node pass does not pay): node list, compact storage
   const bool nodes = resume && opts->precision != NQS_BF16;
   const int64_t max_pass_samples = max_samples_per_pass(passes);
-  const int64_t ecap = node_entry_cap(cap_used, K);
+  const bool pair = pair_nodes(K, opts->precision);
+  const int64_t ecap = node_entry_cap(cap_used, K, pair);
   NodeList nl{};
   int32_t *ncnt = nullptr, *row_node = nullptr, *nperm = nullptr;
   int64_t *nent = nullptr, *nbase = nullptr, *ebase = nullptr, *ntot = nullptr;
@@ -1331,7 +1339,7 @@ nqs_status nqs_eloc(nqs_ctx* ctx, const nqs_instance* inst, const nqs_ansatz* an
     lphi_n = S.get<double>(ecap);
     sphi_n = S.get<int8_t>(ecap);
     rs.nhs = S.get<unsigned char>(size_t(ecap) * ans->chip * esz);
-    rs.npm = S.get<unsigned char>(size_t(ecap) * esz);
+    rs.npm = S.get<unsigned char>(size_t(ecap) * mantissa_bytes(opts->precision));
     rs.npe = S.get<int32_t>(ecap);
     rs.npg = S.get<int8_t>(ecap);
     row_node = S.get<int32_t>(cap_used);
@@ -1379,12 +1387,12 @@ nqs_status nqs_eloc(nqs_ctx* ctx, const nqs_instance* inst, const nqs_ansatz* an
       if (nodes) {
         // nodes of this pass: count, place (host learns the totals), assign
         const int64_t ns = n1 - n0, row_base = P.rowptr_host[n0];
-        HIPCHK(launch_node_count(P.rows.t0, P.rows.sec, P.rowptr, n0, n1, row_base, K, ncnt, nent, stream));
+        HIPCHK(launch_node_count(P.rows.t0, P.rows.sec, P.rowptr, n0, n1, row_base, K, pair, ncnt, nent, stream));
         HIPCHK(launch_node_scan(ns, ecap, ncnt, nent, nbase, ebase, ntot, stream));
         int64_t tot2[2] = {0, 0};
         HIPCHK(hipMemcpyAsync(tot2, ntot, sizeof tot2, hipMemcpyDeviceToHost, stream));
         HIPCHK(hipStreamSynchronize(stream));
-        HIPCHK(launch_node_assign(P.rows.t0, P.rows.sec, samples, P.rowptr, n0, n1, row_base, K, nbase, ebase, nl,
+        HIPCHK(launch_node_assign(P.rows.t0, P.rows.sec, samples, P.rowptr, n0, n1, row_base, K, pair, nbase, ebase, nl,
                                   row_node, row_site, stream));
         const int64_t nn = tot2[0];
         if (nn > 0) {
@@ -1696,12 +1704,13 @@ nqs_status nqs_eloc_workspace_bytes(const nqs_instance* inst, const nqs_ansatz* 
     b += al(size_t(N) * 8) + al(size_t(N));
     if (opts->precision != NQS_BF16) {
       // node level: per-sample counts, node list, node order, storage, rows' nodes
-      const int64_t ecap = node_entry_cap(rows, K);
+      const int64_t ecap = node_entry_cap(rows, K, pair_nodes(K, opts->precision));
       const size_t esz = state_bytes(opts->precision);
       b += al(size_t(N) * 4) + 3 * al(size_t(N) * 8) + al(16);
       b += al(size_t(ecap) * 16) + al(size_t(ecap) * 4) + 2 * al(size_t(ecap)) + al(size_t(ecap) * 8);
       b += al(size_t(ecap) * 4) + al(size_t(ecap)) + al(size_t(ecap) * 8) + al(size_t(ecap));
-      b += al(size_t(ecap) * ans->chip * esz) + al(size_t(ecap) * esz) + al(size_t(ecap) * 4) + al(size_t(ecap));
+      b += al(size_t(ecap) * ans->chip * esz) + al(size_t(ecap) * mantissa_bytes(opts->precision)) +
+           al(size_t(ecap) * 4) + al(size_t(ecap));
       b += al(size_t(rows) * 4) + al(size_t(rows)) + al(size_t(rows) * 4);
     }
   }

@@ -1,7 +1,7 @@
-"""Resumed amplitude rows.  BF16 rows start at their first changed site from
-their sample's stored state; FP64/FP32 rows start at their third changed
-site from a node shared by the rows with the same first two changes (itself
-resumed from the sample).  The autoregressive conditionals at a site see only
+"""Resumed amplitude rows.  FP64/FP32 rows start at their third changed site
+from a node shared by the rows with the same first two changes (itself
+resumed from the sample); BF16 rows at their first changed site from their
+sample's stored state.  The autoregressive conditionals at a site see only
 the occupations below it, so every result must be bit-identical to evaluating
 every row from site 0, on every workload, with and without row passes; and
 the executed site count must match the count from the row list."""
@@ -95,23 +95,25 @@ def site_state(w0, w1, i):
 
 
 def test_site_count_matches_changed_sites(nqs, ctx):
-    """Executed site evaluations.  FP32/FP64: the samples' pass (N K), one
-    node per (sample, first changed site and state there, second changed site
-    and state there) from its first changed site to the largest third changed
-    site of its rows, and every row from its third changed site on.  BF16 (no node level): N K plus every row from its
-    first changed site.  Counted here from the row list of the same call."""
+    """Executed site evaluations: the samples' pass (N K), then for FP32/FP64
+    one node per (sample, first changed site and state there, second changed
+    site and state there) from its first changed site to the largest third
+    changed site of its rows, and every row from its third changed site on;
+    for BF16 (no node level; measured: nodes do not pay for its cheaper sites)
+    every row from its first changed site on.  Counted here from the row list
+    of the same call."""
     w, inst, ans = setup(nqs, ctx, "c2", 64)
     kw = dict(eps=w.eps, n_eps=w.n_eps, seed=w.seed, stream_id=7)
     r = nqs.rows(ctx, inst, w.samples, **kw)
     rp = r["row_ptr"].cpu().numpy()
     m = r["m"].cpu().numpy().view(np.uint64)
     K = w.K
-    two = one = w.n_samples * K
+    two = one = lvl1 = w.n_samples * K
     for s in range(w.n_samples):
         rows = m[rp[s]:rp[s + 1]]
         ch = changed_sites(rows, w.samples[s], K)
         assert ch[0] == []            # the sample's own row
-        nodes = {}
+        nodes, nodes1 = {}, {}
         for k, c in enumerate(ch[1:], start=1):
             one += K - c[0]
             c2 = c[1] if len(c) > 1 else K
@@ -120,11 +122,16 @@ def test_site_count_matches_changed_sites(nqs, ctx):
             key = (c[0], site_state(rows[k, 0], rows[k, 1], c[0]), c2, s2)
             nodes[key] = max(nodes.get(key, 0), c3)
             two += K - c3
+            key1 = key[:2]
+            nodes1[key1] = max(nodes1.get(key1, 0), c2)
+            lvl1 += K - c2
         two += sum(e - key[0] for key, e in nodes.items())
+        lvl1 += sum(e - key[0] for key, e in nodes1.items())
     _, st = nqs.eloc(ctx, inst, ans, w.samples, precision="f32", **kw)
     assert st["n_site_rows"] == two
     _, st = nqs.eloc(ctx, inst, ans, w.samples, precision="bf16", **kw)
     assert st["n_site_rows"] == one
+    assert two < lvl1 < one
 
 
 def test_resume_matches_oracle_f64(nqs, ctx):
