@@ -60,6 +60,11 @@ def _load():
     lib.or_tucker_rank.argtypes = [_i, _i]
     lib.or_reweighted_cotangent.argtypes = [_i64, _p, _p, _p, _p, _p]
     lib.or_adamw.argtypes = [_i64, _p, _p, _p, _p, _i64, _d, _d, _d, _d, _d]
+    lib.or_amplitudes_cx.argtypes = [_i, _i, _i, _i, _p, _p, _i, _i, _p, _p, _i64, _p, _p, _p, _p, _i]
+    lib.or_grad_cx.argtypes = [_i, _i, _i, _i, _p, _p, _i, _i, _p, _p, _i64, _p, _p, _p, _i]
+    lib.or_eloc_cx.argtypes = [_i, _i, _i, _p, _p, _d, _i, _p, _p, _i, _i, _p, _p, _i64, _d, _i, _u64,
+                               _u64, _i64, _p, _p, _p, _p, _p, _p, _p, _p, _p, _p, _i]
+    lib.or_reweighted_cotangent_cx.argtypes = [_i64, _p, _p, _p, _p, _p, _p, _p]
     _lib = lib
     return lib
 
@@ -122,8 +127,15 @@ def connected(K, na, nb, h, eri, sample, e_core=0.0):
     return m, H
 
 
-def _variant(ising, tensor):
-    return int(bool(ising)) | (int(bool(tensor)) << 1)
+def _variant(ising, tensor, cplx=False):
+    if tensor and cplx:
+        raise ValueError("complex parameters are not combined with the tensor-RNN term")
+    return int(bool(ising)) | (int(bool(tensor)) << 1) | (int(bool(cplx)) << 2)
+
+
+def wrap_phase(x):
+    """Angles reduced to [-pi, pi]."""
+    return np.remainder(np.asarray(x) + np.pi, 2 * np.pi) - np.pi
 
 
 def tucker_rank(chi: int, d: int) -> int:
@@ -131,38 +143,48 @@ def tucker_rank(chi: int, d: int) -> int:
     return int(_load().or_tucker_rank(chi, d))
 
 
-def n_params(K, chi, parent_ptr, n_hidden, ising: bool = False, tensor: bool = False) -> int:
+def n_params(K, chi, parent_ptr, n_hidden, ising: bool = False, tensor: bool = False, cplx: bool = False) -> int:
     pp = _i32(parent_ptr)
-    return int(_load().or_n_params(K, chi, _ptr(pp), n_hidden, _variant(ising, tensor)))
+    return int(_load().or_n_params(K, chi, _ptr(pp), n_hidden, _variant(ising, tensor, cplx)))
 
 
 def amplitudes(K, chi, na, nb, parent_ptr, parent_idx, n_hidden, params, samples,
-               nthreads: int = 0, ising: bool = False, tensor: bool = False) -> Dict[str, np.ndarray]:
+               nthreads: int = 0, ising: bool = False, tensor: bool = False,
+               cplx: bool = False) -> Dict[str, np.ndarray]:
     """log|Phi|, sign Phi, log|f|, sign f for every sample (f: cos-RBM, or
-    Ising-RBM when ising; Phi with the BDG-TensorRNN term when tensor)."""
+    Ising-RBM when ising; Phi with the BDG-TensorRNN term when tensor).  With
+    complex parameters (cplx): phase_phi (the phase of Phi) in place of sign
+    Phi, and phase = the phase of Psi (sign f included), both in [-pi, pi]."""
     pp, pi, prm = _i32(parent_ptr), _i32(parent_idx), _f64(params)
     s = _u64a(samples).reshape(-1, 2)
     N = len(s)
     lphi, lf = np.zeros(N), np.zeros(N)
     sphi, sf = np.zeros(N, dtype=np.int32), np.zeros(N, dtype=np.int32)
+    if cplx:
+        ph = np.zeros(N)
+        _load().or_amplitudes_cx(K, chi, na, nb, _ptr(pp), _ptr(pi), n_hidden, _variant(ising, False, True),
+                                 _ptr(prm), _ptr(s), N, _ptr(lphi), _ptr(ph), _ptr(lf), _ptr(sf), nthreads)
+        return dict(lphi=lphi, phase_phi=ph, lf=lf, sf=sf, logabs=lphi + lf,
+                    phase=wrap_phase(ph + np.where(sf < 0, np.pi, 0.0)))
     _load().or_amplitudes(K, chi, na, nb, _ptr(pp), _ptr(pi), n_hidden, _variant(ising, tensor), _ptr(prm), _ptr(s), N,
                           _ptr(lphi), _ptr(sphi), _ptr(lf), _ptr(sf), nthreads)
     return dict(lphi=lphi, sphi=sphi, lf=lf, sf=sf, logabs=lphi + lf, sign=sphi * sf)
 
 
-def sample(K, chi, na, nb, parent_ptr, parent_idx, params, u, tensor: bool = False) -> np.ndarray:
+def sample(K, chi, na, nb, parent_ptr, parent_idx, params, u, tensor: bool = False,
+           cplx: bool = False) -> np.ndarray:
     """Exact autoregressive draws from Phi^2; u is uniform [N, K]."""
     pp, pi, prm = _i32(parent_ptr), _i32(parent_idx), _f64(params)
     uu = _f64(u)
     N = uu.shape[0]
     out = np.zeros((N, 2), dtype=np.uint64)
-    _load().or_sample(K, chi, na, nb, _ptr(pp), _ptr(pi), _variant(False, tensor), _ptr(prm), _ptr(uu), N,
+    _load().or_sample(K, chi, na, nb, _ptr(pp), _ptr(pi), _variant(False, tensor, cplx), _ptr(prm), _ptr(uu), N,
                       _ptr(out))
     return out
 
 
 def sample_unique(K, chi, na, nb, parent_ptr, parent_idx, params, seed: int, n_draws: int, draw_base: int = 0,
-                  tensor: bool = False):
+                  tensor: bool = False, cplx: bool = False):
     """Draws draw_base .. draw_base+n_draws-1 of the counter-keyed sampler (the
     uniform of draw t at site i comes from Philox4x32-10 at counter
     (t lo, t hi, i, 0x53414D50), key (seed lo, seed hi)), merged into unique
@@ -171,19 +193,27 @@ def sample_unique(K, chi, na, nb, parent_ptr, parent_idx, params, seed: int, n_d
     cap = max(int(n_draws), 1)
     out = np.zeros((cap, 2), dtype=np.uint64)
     cnt = np.zeros(cap, dtype=np.int64)
-    n = _load().or_sample_unique(K, chi, na, nb, _ptr(pp), _ptr(pi), _variant(False, tensor), _ptr(prm),
+    n = _load().or_sample_unique(K, chi, na, nb, _ptr(pp), _ptr(pi), _variant(False, tensor, cplx), _ptr(prm),
                                  int(seed) & 0xFFFFFFFFFFFFFFFF,
                                  int(draw_base), int(n_draws), cap, _ptr(out), _ptr(cnt))
     return out[:n], cnt[:n]
 
 
 def grad(K, chi, na, nb, parent_ptr, parent_idx, n_hidden, params, samples, g,
-         nthreads: int = 0, ising: bool = False, tensor: bool = False) -> np.ndarray:
-    """sum_n g_n d ln|Psi(n)| / d theta over the packed parameter vector."""
+         nthreads: int = 0, ising: bool = False, tensor: bool = False, cplx: bool = False,
+         g_phase=None) -> np.ndarray:
+    """sum_n g_n d ln|Psi(n)| / d theta over the packed parameter vector; with
+    complex parameters also + g_phase_n d phase(n) / d theta (the real and
+    imaginary part of a complex parameter are two entries)."""
     pp, pi, prm = _i32(parent_ptr), _i32(parent_idx), _f64(params)
     s = _u64a(samples).reshape(-1, 2)
     gg = _f64(g)
     out = np.zeros(prm.size)
+    if cplx:
+        gp = np.zeros(len(s)) if g_phase is None else _f64(g_phase)
+        _load().or_grad_cx(K, chi, na, nb, _ptr(pp), _ptr(pi), n_hidden, _variant(ising, False, True), _ptr(prm),
+                           _ptr(s), len(s), _ptr(gg), _ptr(gp), _ptr(out), nthreads)
+        return out
     _load().or_grad(K, chi, na, nb, _ptr(pp), _ptr(pi), n_hidden, _variant(ising, tensor), _ptr(prm), _ptr(s), len(s),
                     _ptr(gg), _ptr(out), nthreads)
     return out
@@ -191,13 +221,29 @@ def grad(K, chi, na, nb, parent_ptr, parent_idx, n_hidden, params, samples, g,
 
 def eloc(K, na, nb, h, eri, chi, parent_ptr, parent_idx, n_hidden, params, samples,
          eps=0.0, n_eps=0, seed=0, stream=0, e_core=0.0, nthreads: int = 0,
-         sample_base: int = 0, ising: bool = False, tensor: bool = False) -> Dict[str, np.ndarray]:
+         sample_base: int = 0, ising: bool = False, tensor: bool = False,
+         cplx: bool = False) -> Dict[str, np.ndarray]:
     """Semi-stochastic local energies and the reweighted numerators; the draws
-    of sample i use Philox counter word 0 = sample_base + i."""
+    of sample i use Philox counter word 0 = sample_base + i.  With complex
+    parameters eloc and etnum are complex128 and phase (of Psi) replaces sign."""
     h, eri = _f64(h), _f64(eri)
     pp, pi, prm = _i32(parent_ptr), _i32(parent_idx), _f64(params)
     s = _u64a(samples).reshape(-1, 2)
     N = len(s)
+    if cplx:
+        o = {k: np.zeros(N) for k in ("er", "ei", "tr", "ti", "logabs", "phase", "fsq")}
+        cnt = {k: np.zeros(N, dtype=np.int64) for k in ("n_det", "n_rem", "n_uniq")}
+        rc = _load().or_eloc_cx(K, na, nb, _ptr(h), _ptr(eri), e_core, chi, _ptr(pp), _ptr(pi), n_hidden,
+                                _variant(ising, False, True), _ptr(prm), _ptr(s), N, eps, n_eps, seed, stream,
+                                sample_base, _ptr(o["er"]), _ptr(o["ei"]), _ptr(o["tr"]), _ptr(o["ti"]),
+                                _ptr(o["logabs"]), _ptr(o["phase"]), _ptr(o["fsq"]), _ptr(cnt["n_det"]),
+                                _ptr(cnt["n_rem"]), _ptr(cnt["n_uniq"]), nthreads)
+        if rc != 0:
+            raise ValueError("sample outside the (n_alpha, n_beta) sector")
+        out = dict(eloc=o["er"] + 1j * o["ei"], etnum=o["tr"] + 1j * o["ti"], logabs=o["logabs"],
+                   phase=o["phase"], fsq=o["fsq"])
+        out.update(cnt)
+        return out
     out = {k: np.zeros(N) for k in ("eloc", "etnum", "logabs", "fsq")}
     sign = np.zeros(N, dtype=np.int8)
     cnt = {k: np.zeros(N, dtype=np.int64) for k in ("n_det", "n_rem", "n_uniq")}
@@ -259,6 +305,19 @@ def reweighted_cotangent(counts, etnum, fsq):
     return cot, float(E[0])
 
 
+def reweighted_cotangent_cx(counts, etnum, fsq):
+    """(cot_abs, cot_phase, E) for complex parameters: the cotangents of
+    ln|Psi| and of the phase in 2 Re <(E_loc - E)^* d ln Psi>, reweighted as in
+    Eq. (19); etnum complex."""
+    c, f2 = _f64(counts), _f64(fsq)
+    et = np.asarray(etnum)
+    tr, ti = _f64(et.real), _f64(et.imag)
+    ca, cp = np.zeros(len(c)), np.zeros(len(c))
+    E = np.zeros(1)
+    _load().or_reweighted_cotangent_cx(len(c), _ptr(c), _ptr(tr), _ptr(ti), _ptr(f2), _ptr(ca), _ptr(cp), _ptr(E))
+    return ca, cp, float(E[0])
+
+
 def adamw(params, grad, m, v, step, lr, beta1=0.9, beta2=0.999, eps=1e-8, weight_decay=0.0):
     """One AdamW step on copies: returns (params, m, v)."""
     p, g = _f64(params).copy(), _f64(grad)
@@ -269,15 +328,22 @@ def adamw(params, grad, m, v, step, lr, beta1=0.9, beta2=0.999, eps=1e-8, weight
 
 def vmc_step(K, na, nb, h, eri, chi, parent_ptr, parent_idx, n_hidden, params, m, v, step, n_draws,
              sample_seed, draw_base=0, eps=0.0, n_eps=0, eloc_seed=0, stream=0, lr=1e-3, beta1=0.9,
-             beta2=0.999, adam_eps=1e-8, weight_decay=0.0, e_core=0.0, ising=False, tensor=False):
+             beta2=0.999, adam_eps=1e-8, weight_decay=0.0, e_core=0.0, ising=False, tensor=False, cplx=False):
     """One VMC step in the paper's order: exact draws from Phi^2 merged into
     unique samples with counts, semi-stochastic local energies, the reweighted
     gradient of Eq. (19) (through the cotangent above and the gradient of
-    ln|Psi|), and one AdamW update."""
+    ln|Psi|, and of the phase with complex parameters), and one AdamW update
+    (complex parameters as pairs of reals)."""
     uniq, cnt = sample_unique(K, chi, na, nb, parent_ptr, parent_idx, params, sample_seed, n_draws, draw_base,
-                              tensor=tensor)
+                              tensor=tensor, cplx=cplx)
     out = eloc(K, na, nb, h, eri, chi, parent_ptr, parent_idx, n_hidden, params, uniq, eps=eps, n_eps=n_eps,
-               seed=eloc_seed, stream=stream, e_core=e_core, ising=ising, tensor=tensor)
+               seed=eloc_seed, stream=stream, e_core=e_core, ising=ising, tensor=tensor, cplx=cplx)
+    if cplx:
+        cot, cotp, E = reweighted_cotangent_cx(cnt.astype(np.float64), out["etnum"], out["fsq"])
+        g = grad(K, chi, na, nb, parent_ptr, parent_idx, n_hidden, params, uniq, cot, ising=ising, cplx=True,
+                 g_phase=cotp)
+        p, mm, vv = adamw(params, g, m, v, step, lr, beta1, beta2, adam_eps, weight_decay)
+        return dict(params=p, m=mm, v=vv, grad=g, E=E, samples=uniq, counts=cnt, eloc=out)
     cot, E = reweighted_cotangent(cnt.astype(np.float64), out["etnum"], out["fsq"])
     g = grad(K, chi, na, nb, parent_ptr, parent_idx, n_hidden, params, uniq, cot, ising=ising, tensor=tensor)
     p, mm, vv = adamw(params, g, m, v, step, lr, beta1, beta2, adam_eps, weight_decay)

@@ -39,7 +39,11 @@
 //     local state; a site without parents has h = v;
 //   - the conditional is normalised over the local states that keep the
 //     electron counts reachable (exact feasibility mask);
-//   - real parameters, phase = sign(w^T h + c) with sign(0) = +1;
+//   - real parameters: phase = sign(w^T h + c) with sign(0) = +1; complex
+//     parameters (M, v, w, c complex, eta real and non-negative; Sec. 2.1):
+//     P_t = h^dagger eta h, phase of site t = arg(w^T h + c) (no conjugation
+//     of w, arg 0 = 0), total phase their sum, reported in [-pi, pi]; the
+//     correlator stays real and its sign adds 0 or pi;
 //   - the deterministic set is |H_nm| >= eps with H_nm != 0, m != n; the
 //     remainder 0 < |H_nm| < eps is sampled with replacement with integer
 //     weights q = ceil(|H| 2^(40-e)), eps = f 2^e, f in [0.5,1);
@@ -47,6 +51,7 @@
 //     counter (sample index, draw index, stream lo, stream hi); the 128-bit
 //     output U (word 0 least significant) picks r = floor(U Q / 2^128).
 #include <cmath>
+#include <complex>
 #include <cstdint>
 #include <cstring>
 #include <limits>
@@ -482,11 +487,13 @@ void corr_eval(const Ansatz& A, const Det& n, double* logabs, int* sgn) {
 struct Amp {
   double lphi, lf;
   int sphi, sf;
+  double phase;   // phase of Phi (complex parameters); 0 for real parameters
   bool valid;
 };
 
 Amp amp_eval(const Ansatz& A, const Det& n) {
   Amp r;
+  r.phase = 0.0;
   r.valid = phi_eval(A, n, &r.lphi, &r.sphi, nullptr);
   r.lf = 0.0; r.sf = 1;
   if (A.nh) corr_eval(A, n, &r.lf, &r.sf);
@@ -622,10 +629,270 @@ void grad_accumulate(const Ansatz& A, const Det& n, double g, double* grad) {
 }
 
 // --------------------------------------------------------------------------
+// complex parameters (Sec. 2.1: the MPS-RNN over C^chi).  M, v, w, c are
+// complex and stored as (re, im) pairs; eta stays real.  Per site
+// h^s = sum_j M_ij^s h_j + v^s, P^s = sum_u eta_u |h^s_u|^2 (normalised over
+// the allowed states as in the real case), phase_i = arg(w_i^T h_i^{s_i} + c_i).
+// Packed layout per site: M (per parent, [4][chi][chi] pairs), v ([4][chi]
+// pairs), eta (chi reals), w (chi pairs), c (one pair); then the real
+// correlator block as in the real layout.
+// --------------------------------------------------------------------------
+typedef std::complex<double> cplx;
+
+struct CxAnsatz {
+  int K, chi, na, nb;
+  const int* pptr;
+  const int* pidx;
+  const double* prm;
+  std::vector<size_t> offM, offV, offEta, offW, offC;   // offsets in doubles
+  Ansatz corr;                                          // the correlator part (real)
+  size_t total = 0;
+  cplx at(size_t off) const { return cplx(prm[off], prm[off + 1]); }
+};
+
+CxAnsatz make_cx_ansatz(int K, int chi, int na, int nb, const int* pptr, const int* pidx, int nh, bool ising,
+                        const double* prm) {
+  CxAnsatz A;
+  A.K = K; A.chi = chi; A.na = na; A.nb = nb;
+  A.pptr = pptr; A.pidx = pidx; A.prm = prm;
+  size_t o = 0;
+  A.offM.resize(pptr[K]);
+  A.offV.resize(K); A.offEta.resize(K); A.offW.resize(K); A.offC.resize(K);
+  for (int i = 0; i < K; ++i) {
+    for (int e = pptr[i]; e < pptr[i + 1]; ++e) { A.offM[e] = o; o += size_t(8) * chi * chi; }
+    A.offV[i] = o; o += size_t(8) * chi;
+    A.offEta[i] = o; o += chi;
+    A.offW[i] = o; o += size_t(2) * chi;
+    A.offC[i] = o; o += 2;
+  }
+  Ansatz& C = A.corr;
+  C.K = K; C.chi = chi; C.na = na; C.nb = nb; C.nh = nh;
+  C.ising = nh > 0 && ising;
+  C.tensor = false;
+  C.pptr = pptr; C.pidx = pidx; C.prm = prm;
+  C.offB = o; o += nh;
+  C.offWc = o; o += size_t(nh) * 2 * K;
+  C.offW2 = o;
+  if (C.ising) o += size_t(nh) * 4 * K * K;
+  A.total = o;
+  C.total = o;
+  return A;
+}
+
+bool cx_allowed(const CxAnsatz& A, int i, int a_prev, int b_prev, int s) {
+  const int a = a_prev + (s & 1), b = b_prev + (s >> 1);
+  const int rest = A.K - 1 - i;
+  return a <= A.na && a + rest >= A.na && b <= A.nb && b + rest >= A.nb;
+}
+
+// h_i^s[u] = sum_{j in N(i)} sum_k M_ij^s[u][k] h_j[k] + v_i^s[u]
+void cx_site_candidates(const CxAnsatz& A, int i, const std::vector<cplx>& carried, cplx* cand) {
+  const int chi = A.chi;
+  for (int s = 0; s < 4; ++s)
+    for (int u = 0; u < chi; ++u) {
+      cplx acc = 0.0;
+      for (int e = A.pptr[i]; e < A.pptr[i + 1]; ++e) {
+        const int j = A.pidx[e];
+        for (int k = 0; k < chi; ++k)
+          acc += A.at(A.offM[e] + 2 * ((size_t(s) * chi + u) * chi + k)) * carried[size_t(j) * chi + k];
+      }
+      cand[s * chi + u] = acc + A.at(A.offV[i] + 2 * (size_t(s) * chi + u));
+    }
+}
+
+struct CxTrace {
+  std::vector<cplx> cand;    // [K][4][chi]
+  std::vector<double> p;     // [K][4]
+  std::vector<double> Z;     // [K]
+  std::vector<uint8_t> ok;   // [K][4]
+  std::vector<int> s;        // [K]
+  std::vector<cplx> z;       // [K]: w^T h + c
+};
+
+// log|Phi(n)| and the phase sum_i arg(w_i^T h_i + c_i) (not wrapped)
+bool cx_phi_eval(const CxAnsatz& A, const Det& n, double* logabs, double* phase, CxTrace* tr) {
+  const int K = A.K, chi = A.chi;
+  std::vector<cplx> carried(size_t(K) * chi, 0.0), cand(4 * chi);
+  if (tr) {
+    tr->cand.assign(size_t(K) * 4 * chi, 0.0);
+    tr->p.assign(size_t(K) * 4, 0.0);
+    tr->Z.assign(K, 0.0);
+    tr->ok.assign(size_t(K) * 4, 0);
+    tr->s.assign(K, 0);
+    tr->z.assign(K, 0.0);
+  }
+  double la = 0.0, ph = 0.0;
+  int a_prev = 0, b_prev = 0;
+  for (int i = 0; i < K; ++i) {
+    const int si = n.x[2 * i] + 2 * n.x[2 * i + 1];
+    cx_site_candidates(A, i, carried, cand.data());
+    double p[4], Z = 0.0;
+    bool ok[4];
+    for (int s = 0; s < 4; ++s) {
+      double acc = 0.0;
+      for (int u = 0; u < chi; ++u) acc += A.prm[A.offEta[i] + u] * std::norm(cand[s * chi + u]);
+      p[s] = acc;
+      ok[s] = cx_allowed(A, i, a_prev, b_prev, s);
+      if (ok[s]) Z += p[s];
+    }
+    if (!ok[si]) { *logabs = -std::numeric_limits<double>::infinity(); *phase = 0.0; return false; }
+    la += 0.5 * (std::log(p[si]) - std::log(Z));
+    cplx z = A.at(A.offC[i]);
+    for (int u = 0; u < chi; ++u) z += A.at(A.offW[i] + 2 * u) * cand[si * chi + u];
+    ph += std::arg(z);
+    for (int u = 0; u < chi; ++u) carried[size_t(i) * chi + u] = cand[si * chi + u];
+    if (tr) {
+      std::copy(cand.begin(), cand.end(), tr->cand.begin() + size_t(i) * 4 * chi);
+      for (int s = 0; s < 4; ++s) { tr->p[i * 4 + s] = p[s]; tr->ok[i * 4 + s] = ok[s]; }
+      tr->Z[i] = Z;
+      tr->s[i] = si;
+      tr->z[i] = z;
+    }
+    a_prev += si & 1;
+    b_prev += si >> 1;
+  }
+  *logabs = la;
+  *phase = ph;
+  return true;
+}
+
+double wrap_phase(double x) { return std::remainder(x, 2.0 * M_PI); }
+
+Amp cx_amp_eval(const CxAnsatz& A, const Det& n) {
+  Amp r;
+  r.sphi = 1;
+  r.valid = cx_phi_eval(A, n, &r.lphi, &r.phase, nullptr);
+  r.lf = 0.0; r.sf = 1;
+  if (A.corr.nh) corr_eval(A.corr, n, &r.lf, &r.sf);
+  return r;
+}
+
+// Reverse sweep of ga ln|Psi(n)| + gp phase(n) over the packed parameters.
+// A real function L of a complex quantity y has the gradient pair
+// G_y = dL/dRe y + i dL/dIm y; through y = a x (a fixed) it pulls back as
+// G_x = conj(a) G_y and G_a = conj(x) G_y.  From ln P: G_h = ga eta h
+// ([s = s_i]/P^{s_i} - [s allowed]/Z); from arg z: G_z = gp i z / |z|^2.
+void cx_grad_accumulate(const CxAnsatz& A, const Det& n, double ga, double gp, double* grad) {
+  const int K = A.K, chi = A.chi;
+  CxTrace tr;
+  double la, ph;
+  if (!cx_phi_eval(A, n, &la, &ph, &tr)) return;
+  auto add = [&](size_t off, cplx g) { grad[off] += g.real(); grad[off + 1] += g.imag(); };
+  std::vector<cplx> carried(size_t(K) * chi);
+  for (int i = 0; i < K; ++i)
+    for (int u = 0; u < chi; ++u) carried[size_t(i) * chi + u] = tr.cand[(size_t(i) * 4 + tr.s[i]) * chi + u];
+  std::vector<cplx> dcarry(size_t(K) * chi, 0.0), dcand(4 * chi);
+  for (int i = K - 1; i >= 0; --i) {
+    const int si = tr.s[i];
+    const double psi_ = tr.p[i * 4 + si], Z = tr.Z[i];
+    const double* eta = A.prm + A.offEta[i];
+    const cplx* cand = tr.cand.data() + size_t(i) * 4 * chi;
+    for (int s = 0; s < 4; ++s)
+      for (int u = 0; u < chi; ++u) {
+        cplx d = 0.0;
+        if (tr.ok[i * 4 + s]) {
+          if (s == si) d += ga * eta[u] * cand[s * chi + u] / psi_;
+          d -= ga * eta[u] * cand[s * chi + u] / Z;
+        }
+        if (s == si) d += dcarry[size_t(i) * chi + u];
+        dcand[s * chi + u] = d;
+      }
+    const cplx z = tr.z[i];
+    const double z2 = std::norm(z);
+    if (z2 > 0.0) {
+      const cplx Gz = gp * cplx(-z.imag(), z.real()) / z2;
+      add(A.offC[i], Gz);
+      for (int u = 0; u < chi; ++u) {
+        add(A.offW[i] + 2 * u, std::conj(cand[si * chi + u]) * Gz);
+        dcand[si * chi + u] += std::conj(A.at(A.offW[i] + 2 * u)) * Gz;
+      }
+    }
+    for (int u = 0; u < chi; ++u) {
+      double d = 0.5 * std::norm(cand[si * chi + u]) / psi_;
+      for (int s = 0; s < 4; ++s)
+        if (tr.ok[i * 4 + s]) d -= 0.5 * std::norm(cand[s * chi + u]) / Z;
+      grad[A.offEta[i] + u] += ga * d;
+    }
+    for (int s = 0; s < 4; ++s)
+      for (int u = 0; u < chi; ++u) add(A.offV[i] + 2 * (size_t(s) * chi + u), dcand[s * chi + u]);
+    for (int e = A.pptr[i]; e < A.pptr[i + 1]; ++e) {
+      const int j = A.pidx[e];
+      for (int s = 0; s < 4; ++s)
+        for (int u = 0; u < chi; ++u) {
+          const cplx du = dcand[s * chi + u];
+          for (int k = 0; k < chi; ++k) {
+            const size_t off = A.offM[e] + 2 * ((size_t(s) * chi + u) * chi + k);
+            add(off, du * std::conj(carried[size_t(j) * chi + k]));
+            dcarry[size_t(j) * chi + k] += std::conj(A.at(off)) * du;
+          }
+        }
+    }
+  }
+  const Ansatz& C = A.corr;
+  if (C.nh) {
+    const int nv = 2 * K;
+    for (int k = 0; k < C.nh; ++k) {
+      const double dth = -ga * std::tan(corr_theta(C, n, k));
+      grad[C.offB + k] += dth;
+      for (int P = 0; P < nv; ++P)
+        if (n.x[P]) grad[C.offWc + size_t(k) * nv + P] += dth;
+      if (C.ising)
+        for (int P = 0; P < nv; ++P) {
+          if (!n.x[P]) continue;
+          for (int Q = 0; Q < nv; ++Q)
+            if (n.x[Q]) grad[C.offW2 + (size_t(k) * nv + P) * nv + Q] += 0.5 * dth;
+        }
+    }
+  }
+}
+
+// exact autoregressive draws from Phi^2 with complex parameters (the same
+// selection rule as the real sampler; P^s from |h^s|^2)
+int cx_sample(int K, int chi, int na, int nb, const int* pptr, const int* pidx, const double* prm,
+              const double* u, int64_t N, uint64_t* out) {
+  CxAnsatz A = make_cx_ansatz(K, chi, na, nb, pptr, pidx, 0, false, prm);
+  for (int64_t t = 0; t < N; ++t) {
+    Det d;
+    d.n = 2 * K;
+    std::memset(d.x, 0, sizeof d.x);
+    std::vector<cplx> carried(size_t(K) * chi, 0.0), cand(4 * chi);
+    int a_prev = 0, b_prev = 0;
+    for (int i = 0; i < K; ++i) {
+      cx_site_candidates(A, i, carried, cand.data());
+      double p[4], Z = 0.0;
+      for (int s = 0; s < 4; ++s) {
+        double acc = 0.0;
+        for (int uu = 0; uu < chi; ++uu) acc += prm[A.offEta[i] + uu] * std::norm(cand[s * chi + uu]);
+        p[s] = cx_allowed(A, i, a_prev, b_prev, s) ? acc : 0.0;
+        Z += p[s];
+      }
+      const double target = u[t * K + i] * Z;
+      double run = 0.0;
+      int pick = -1, last = -1;
+      for (int s = 0; s < 4; ++s) {
+        if (p[s] <= 0.0) continue;
+        last = s;
+        run += p[s];
+        if (run > target) { pick = s; break; }
+      }
+      if (pick < 0) pick = last;
+      d.x[2 * i] = pick & 1;
+      d.x[2 * i + 1] = pick >> 1;
+      for (int uu = 0; uu < chi; ++uu) carried[size_t(i) * chi + uu] = cand[pick * chi + uu];
+      a_prev += pick & 1;
+      b_prev += pick >> 1;
+    }
+    det_to_words(d, out + 2 * t);
+  }
+  return 0;
+}
+
+// --------------------------------------------------------------------------
 // semi-stochastic local energy for one sample
 // --------------------------------------------------------------------------
 struct ElocOut {
   double eloc, etnum, logabs, fsq;
+  double eloc_im, etnum_im, phase;   // complex parameters: imaginary parts, phase of Psi(n)
   int sign;
   int64_t n_det, n_rem, n_uniq;
   uint64_t Q;
@@ -658,7 +925,11 @@ ElocOut eloc_one(const Ham& H, const Det& n, int64_t sample_idx, double eps, int
   o.logabs = an.lphi + an.lf;
   o.sign = an.sphi * an.sf;
   o.fsq = std::exp(2.0 * an.lf);
+  o.phase = wrap_phase(an.phase + (o.sign < 0 ? M_PI : 0.0));
+  // Psi(m)/Psi(n) = s e^{ln|Psi(m)| - ln|Psi(n)|} e^{i (phase_m - phase_n)} with the
+  // real signs s of Phi and f; for real parameters the phase factor is exactly 1
   double ed = 0.0, ed_t = 0.0;     // E^d and its reweighted numerator part
+  double ed_i = 0.0, ed_ti = 0.0;  // their imaginary parts
   std::vector<int64_t> rem;       // ranks of the remainder, in canonical order
   std::vector<uint64_t> q;
   for (size_t r = 0; r < conns.size(); ++r) {
@@ -668,8 +939,13 @@ ElocOut eloc_one(const Ham& H, const Det& n, int64_t sample_idx, double eps, int
       Det m = det_from_words(H.K, conns[r].m);
       const Amp am = amp(m);
       const int s = an.sphi * an.sf * am.sphi * am.sf;
-      ed += h * s * std::exp(am.lphi + am.lf - an.lphi - an.lf);
-      ed_t += h * s * std::exp(an.lf + am.lf + am.lphi - an.lphi);
+      const double x = h * s * std::exp(am.lphi + am.lf - an.lphi - an.lf);
+      const double xt = h * s * std::exp(an.lf + am.lf + am.lphi - an.lphi);
+      const double cr = std::cos(am.phase - an.phase), ci = std::sin(am.phase - an.phase);
+      ed += x * cr;
+      ed_t += xt * cr;
+      ed_i += x * ci;
+      ed_ti += xt * ci;
       ++o.n_det;
       if (det_ranks) det_ranks->push_back(int64_t(r));
     } else {
@@ -681,7 +957,7 @@ ElocOut eloc_one(const Ham& H, const Det& n, int64_t sample_idx, double eps, int
   uint64_t Q = 0;
   for (uint64_t x : q) Q += x;
   o.Q = Q;
-  double es = 0.0, es_t = 0.0;
+  double es = 0.0, es_t = 0.0, es_i = 0.0, es_ti = 0.0;
   if (n_eps > 0 && Q > 0) {
     std::vector<int64_t> picked;
     for (int k = 0; k < n_eps; ++k) {
@@ -705,15 +981,22 @@ ElocOut eloc_one(const Ham& H, const Det& n, int64_t sample_idx, double eps, int
       Det m = det_from_words(H.K, conns[rank].m);
       const Amp am = amp(m);
       const int s = an.sphi * an.sf * am.sphi * am.sf;
-      es += w * s * std::exp(am.lphi + am.lf - an.lphi - an.lf);
-      es_t += w * s * std::exp(an.lf + am.lf + am.lphi - an.lphi);
+      const double x = w * s * std::exp(am.lphi + am.lf - an.lphi - an.lf);
+      const double xt = w * s * std::exp(an.lf + am.lf + am.lphi - an.lphi);
+      const double cr = std::cos(am.phase - an.phase), ci = std::sin(am.phase - an.phase);
+      es += x * cr;
+      es_t += xt * cr;
+      es_i += x * ci;
+      es_ti += xt * ci;
     }
     std::sort(picked.begin(), picked.end());
     o.n_uniq = int64_t(std::unique(picked.begin(), picked.end()) - picked.begin());
   }
   o.eloc = Hnn + ed + es;
   o.etnum = o.fsq * Hnn + ed_t + es_t;
-  if (!an.valid || !std::isfinite(o.logabs)) { o.eloc = o.etnum = std::nan(""); }
+  o.eloc_im = ed_i + es_i;
+  o.etnum_im = ed_ti + es_ti;
+  if (!an.valid || !std::isfinite(o.logabs)) { o.eloc = o.etnum = o.eloc_im = o.etnum_im = std::nan(""); }
   return o;
 }
 
@@ -766,9 +1049,47 @@ int64_t or_connected(int K, int na, int nb, const double* h, const double* eri, 
 
 int or_tucker_rank(int chi, int d) { return tucker_rank(chi, d); }
 
+// variant bits: 1 Ising-RBM correlator, 2 BDG-TensorRNN, 4 complex parameters
+// (not combined with 2)
 int64_t or_n_params(int K, int chi, const int* pptr, int nh, int variant) {
+  if (variant & 4) {
+    if (variant & 2) return -1;
+    return int64_t(make_cx_ansatz(K, chi, 0, 0, pptr, nullptr, nh, variant & 1, nullptr).total);
+  }
   Ansatz A = make_ansatz(K, chi, 0, 0, pptr, nullptr, nh, variant, nullptr);
   return int64_t(A.total);
+}
+
+// complex parameters: log|Phi|, phase of Phi in [-pi, pi], log|f|, sign f
+int or_amplitudes_cx(int K, int chi, int na, int nb, const int* pptr, const int* pidx, int nh, int variant,
+                     const double* prm, const uint64_t* samples, int64_t N, double* lphi, double* phase,
+                     double* lf, int* sf, int nthreads) {
+  CxAnsatz A = make_cx_ansatz(K, chi, na, nb, pptr, pidx, nh, variant & 1, prm);
+#pragma omp parallel for schedule(dynamic, 16) num_threads(nthreads_or_default(nthreads))
+  for (int64_t i = 0; i < N; ++i) {
+    Det d = det_from_words(K, samples + 2 * i);
+    Amp a = cx_amp_eval(A, d);
+    lphi[i] = a.lphi; phase[i] = wrap_phase(a.phase); lf[i] = a.lf; sf[i] = a.sf;
+  }
+  return 0;
+}
+
+// complex parameters: sum_n (ga_n d ln|Psi(n)| + gp_n d phase(n)) / d theta
+// over the packed parameters (re and im of a complex parameter are two reals)
+int or_grad_cx(int K, int chi, int na, int nb, const int* pptr, const int* pidx, int nh, int variant,
+               const double* prm, const uint64_t* samples, int64_t N, const double* ga, const double* gp,
+               double* grad, int nthreads) {
+  CxAnsatz A = make_cx_ansatz(K, chi, na, nb, pptr, pidx, nh, variant & 1, prm);
+  const int nt = nthreads_or_default(nthreads);
+  std::vector<std::vector<double>> part(nt, std::vector<double>(A.total, 0.0));
+#pragma omp parallel for schedule(static) num_threads(nt)
+  for (int64_t i = 0; i < N; ++i) {
+    Det d = det_from_words(K, samples + 2 * i);
+    cx_grad_accumulate(A, d, ga[i], gp ? gp[i] : 0.0, part[omp_get_thread_num()].data());
+  }
+  for (int t = 0; t < nt; ++t)
+    for (size_t k = 0; k < A.total; ++k) grad[k] += part[t][k];
+  return 0;
 }
 
 // log|Phi|, sign Phi, log|f|, sign f for N samples
@@ -800,6 +1121,7 @@ double sampler_uniform(uint64_t seed, uint64_t t, int i) {
 // exact autoregressive draws from Phi^2 using the caller's uniforms u[N][K]
 int or_sample(int K, int chi, int na, int nb, const int* pptr, const int* pidx, int variant,
               const double* prm, const double* u, int64_t N, uint64_t* out) {
+  if (variant & 4) return cx_sample(K, chi, na, nb, pptr, pidx, prm, u, N, out);
   Ansatz A = make_ansatz(K, chi, na, nb, pptr, pidx, 0, variant & 2, prm);
   for (int64_t t = 0; t < N; ++t) {
     Det d;
@@ -908,6 +1230,34 @@ int or_eloc(int K, int na, int nb, const double* h, const double* eri, double ec
   return 0;
 }
 
+// complex parameters: E_loc and Etilde_num as (re, im), log|Psi|, the phase
+// of Psi in [-pi, pi] (the correlator's sign included), |f|^2
+int or_eloc_cx(int K, int na, int nb, const double* h, const double* eri, double ecore,
+               int chi, const int* pptr, const int* pidx, int nh, int variant, const double* prm,
+               const uint64_t* samples, int64_t N, double eps, int n_eps, uint64_t seed,
+               uint64_t stream, int64_t sample_base, double* eloc, double* eloc_im, double* etnum,
+               double* etnum_im, double* logabs, double* phase, double* fsq, int64_t* n_det,
+               int64_t* n_rem, int64_t* n_uniq, int nthreads) {
+  Ham H{K, h, eri, ecore};
+  CxAnsatz A = make_cx_ansatz(K, chi, na, nb, pptr, pidx, nh, variant & 1, prm);
+  for (int64_t i = 0; i < N; ++i) {
+    Det d = det_from_words(K, samples + 2 * i);
+    if (!count_ok(d, K, na, nb)) return -1;
+  }
+  auto amp = [&](const Det& d) { return cx_amp_eval(A, d); };
+#pragma omp parallel for schedule(dynamic, 1) num_threads(nthreads_or_default(nthreads))
+  for (int64_t i = 0; i < N; ++i) {
+    Det d = det_from_words(K, samples + 2 * i);
+    ElocOut o = eloc_one(H, d, sample_base + i, eps, n_eps, seed, stream, amp, nullptr, nullptr);
+    eloc[i] = o.eloc; eloc_im[i] = o.eloc_im; etnum[i] = o.etnum; etnum_im[i] = o.etnum_im;
+    logabs[i] = o.logabs; phase[i] = o.phase; fsq[i] = o.fsq;
+    if (n_det) n_det[i] = o.n_det;
+    if (n_rem) n_rem[i] = o.n_rem;
+    if (n_uniq) n_uniq[i] = o.n_uniq;
+  }
+  return 0;
+}
+
 // one sample in detail: deterministic ranks, drawn ranks (in draw order), Q
 int or_eloc_detail(int K, int na, int nb, const double* h, const double* eri, double ecore,
                    int chi, const int* pptr, const int* pidx, int nh, int variant, const double* prm,
@@ -947,6 +1297,28 @@ int or_reweighted_cotangent(int64_t N, const double* counts, const double* etnum
   return 0;
 }
 
+// Complex parameters: the gradient of E = <H> over the real and imaginary
+// parts of the parameters is 2 Re <(E_loc - E)^* d ln Psi> with d ln Psi =
+// d ln|Psi| + i d phase, i.e. 2 <Re(E_loc - E) d ln|Psi| + Im E_loc d phase>;
+// reweighted as in Eq. (19): cot_abs_n = 2 c_n (Re Etilde_num(n) - |f_n|^2 E)
+// / sum c |f|^2 and cot_phase_n = 2 c_n Im Etilde_num(n) / sum c |f|^2, with
+// E = sum c Re Etilde_num / sum c |f|^2.
+int or_reweighted_cotangent_cx(int64_t N, const double* counts, const double* etnum, const double* etnum_im,
+                               const double* fsq, double* cot_abs, double* cot_phase, double* E_out) {
+  double sc_f2 = 0.0, sc_et = 0.0;
+  for (int64_t n = 0; n < N; ++n) {
+    sc_f2 += counts[n] * fsq[n];
+    sc_et += counts[n] * etnum[n];
+  }
+  const double E = sc_et / sc_f2;
+  for (int64_t n = 0; n < N; ++n) {
+    cot_abs[n] = 2.0 * counts[n] * (etnum[n] - fsq[n] * E) / sc_f2;
+    cot_phase[n] = 2.0 * counts[n] * etnum_im[n] / sc_f2;
+  }
+  *E_out = E;
+  return 0;
+}
+
 // One AdamW step (Loshchilov and Hutter, decoupled weight decay; the
 // formulation of PyTorch's AdamW): p <- p (1 - lr wd); m <- b1 m + (1 - b1) g;
 // v <- b2 v + (1 - b2) g^2; p <- p - lr (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps).
@@ -982,7 +1354,7 @@ int or_eloc_table(int K, int na, int nb, const double* h, const double* eri, dou
       if (km < key) lo = mid + 1; else hi = mid;
     }
     Amp a;
-    a.lf = 0.0; a.sf = 1; a.valid = true;
+    a.lf = 0.0; a.sf = 1; a.phase = 0.0; a.valid = true;
     const u128 kf = lo < T ? ((u128(keys[2 * lo + 1]) << 64) | keys[2 * lo]) : 0;
     const double v = (lo < T && kf == key) ? vals[lo] : 0.0;
     a.lphi = std::log(std::fabs(v));

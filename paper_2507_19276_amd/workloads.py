@@ -36,6 +36,9 @@ Conventions (shared by every consumer):
   factor matrices K^(0) (output mode) and K^(1..d) (one per parent, ascending),
   each chi x chi' row-major, then the cores U^s (s = 0..3), each chi'^(d+1)
   with index order [i', a_1, ..., a_d]; chi' = ceil(chi^(2/(d+1))).
+  With complex parameters the same order, M, v, w and c complex and stored
+  as (re, im) pairs (M: 4 x chi x chi pairs, v: 4 x chi pairs, w: chi pairs,
+  c: one pair), eta real; the correlator block stays real.
 """
 from __future__ import annotations
 
@@ -197,9 +200,13 @@ def tensor_block_sizes(K: int, chi: int, parent_ptr: np.ndarray) -> List[Tuple[i
 
 
 def n_params(K: int, chi: int, parent_ptr: np.ndarray, n_hidden: int, ising: bool = False,
-             tensor: bool = False) -> int:
+             tensor: bool = False, cplx: bool = False) -> int:
     sum_d = int(parent_ptr[-1])
     corr = n_hidden * (2 * K + 1) + (n_hidden * 4 * K * K if ising else 0)
+    if cplx:
+        # M, v, w, c complex (two reals each), eta real
+        assert not tensor
+        return sum_d * 8 * chi * chi + K * (8 * chi + chi + 2 * chi + 2) + (corr if n_hidden else 0)
     tens = sum((d + 1) * chi * q + 4 * q ** (d + 1) for _, d, q in tensor_block_sizes(K, chi, parent_ptr)) \
         if tensor else 0
     return sum_d * 4 * chi * chi + K * (4 * chi + chi + chi + 1) + (corr if n_hidden else 0) + tens
@@ -207,7 +214,7 @@ def n_params(K: int, chi: int, parent_ptr: np.ndarray, n_hidden: int, ising: boo
 
 def ansatz_params(K: int, chi: int, parent_ptr: np.ndarray, parent_idx: np.ndarray,
                   n_hidden: int, seed: int, corr_scale: float = 0.1, ising: bool = False,
-                  tensor: bool = False, tensor_scale: float = 0.1) -> np.ndarray:
+                  tensor: bool = False, tensor_scale: float = 0.1, cplx: bool = False) -> np.ndarray:
     """Random-init parameters in the packed layout (module docstring):
     M ~ N(0, var 1/(chi*max(d_i,1))), v ~ N(0,1), eta ~ U[0.5,1.5], w, c ~ N(0,1),
     correlator b, W ~ N(0, corr_scale^2), Ising W2 ~ N(0, corr_scale^2 / K) (its
@@ -216,9 +223,31 @@ def ansatz_params(K: int, chi: int, parent_ptr: np.ndarray, parent_idx: np.ndarr
     in the hidden states at two parents, so random states can grow without
     bound along a K = 20 chain: at tensor_scale = 0.3 some reach |h| ~ 1e79,
     beyond FP32; at 0.1 the largest |h| is ~25 and the term still shifts
-    log|Phi| by ~0.15)."""
+    log|Phi| by ~0.15).  With cplx: M, v, w, c complex, stored as (re, im)
+    pairs, each part with half the variance of the real case (so that |M|^2,
+    |v|^2 have the real case's mean); eta as in the real case."""
     rng = np.random.default_rng(seed)
     out: List[np.ndarray] = []
+    if cplx:
+        assert not tensor
+        h = math.sqrt(0.5)
+        for i in range(K):
+            d = int(parent_ptr[i + 1] - parent_ptr[i])
+            std = 1.0 / math.sqrt(chi * max(d, 1))
+            for _ in range(d):
+                out.append(rng.standard_normal(8 * chi * chi) * (std * h))   # M (re, im)
+            out.append(rng.standard_normal(8 * chi) * h)      # v
+            out.append(rng.uniform(0.5, 1.5, chi))            # eta
+            out.append(rng.standard_normal(2 * chi) * h)      # w
+            out.append(rng.standard_normal(2) * h)            # c
+        if n_hidden:
+            out.append(rng.standard_normal(n_hidden) * corr_scale)
+            out.append(rng.standard_normal(n_hidden * 2 * K) * corr_scale)
+            if ising:
+                out.append(rng.standard_normal(n_hidden * 4 * K * K) * (corr_scale / math.sqrt(K)))
+        p = np.concatenate(out).astype(np.float64)
+        assert p.size == n_params(K, chi, parent_ptr, n_hidden, ising, False, True)
+        return p
     for i in range(K):
         d = int(parent_ptr[i + 1] - parent_ptr[i])
         std = 1.0 / math.sqrt(chi * max(d, 1))
@@ -326,6 +355,7 @@ class Workload:
     precision: str
     ising: bool = False
     tensor: bool = False
+    cplx: bool = False
 
     @property
     def n_samples(self) -> int:
@@ -364,6 +394,8 @@ def make_workload(name: str, n_samples: Optional[int] = None, seed_offset: int =
         (chi' = 7), 4096 unique samples, eps=1e-3, N_eps=64
     c2i c2 with an Ising-RBM correlator, N_h = 2 N_v = 80 (alpha = 2, as in
         Sec. 4), 4096 unique samples
+    c1c c1 with complex parameters and a cos-RBM correlator, N_h = 12
+    c2c c2 with complex parameters (chi = 16 complex units), 4096 unique samples
     """
     base = SEED_BASE + 1000 * seed_offset
     spec = {
@@ -387,9 +419,14 @@ def make_workload(name: str, n_samples: Optional[int] = None, seed_offset: int =
                     eps=0.0, neps=0, prec="f64", s=9, tensor=True),
         "c2t": dict(K=20, ne=(10, 10), integ="chain", graph="nnn", chi=16, nh=0, N=4096, uniq=True,
                     eps=1e-3, neps=64, prec="f32", s=10, tensor=True),
+        "c1c": dict(K=6, ne=(3, 3), integ="chain", graph="chain", chi=4, nh=12, N=256, uniq=False,
+                    eps=0.0, neps=0, prec="f64", s=11, cplx=True),
+        "c2c": dict(K=20, ne=(10, 10), integ="chain", graph="chain", chi=16, nh=0, N=4096, uniq=True,
+                    eps=1e-3, neps=64, prec="f32", s=12, cplx=True),
     }[name]
     ising = spec.get("ising", False)
     tensor = spec.get("tensor", False)
+    cplx = spec.get("cplx", False)
     K = spec["K"]
     seed = base + 100 * spec["s"]
     if spec["integ"] == "chain":
@@ -401,14 +438,14 @@ def make_workload(name: str, n_samples: Optional[int] = None, seed_offset: int =
     else:
         h, eri = lattice_integrals((3, 3, 2), seed + 1)
     pp, pi = _graph(spec["graph"], K)
-    params = ansatz_params(K, spec["chi"], pp, pi, spec["nh"], seed + 2, ising=ising, tensor=tensor)
+    params = ansatz_params(K, spec["chi"], pp, pi, spec["nh"], seed + 2, ising=ising, tensor=tensor, cplx=cplx)
     N = spec["N"] if n_samples is None else n_samples
     na, nb = spec["ne"]
     samples = random_onvs(K, na, nb, N, seed + 3, unique=spec["uniq"])
     return Workload(name=name, K=K, n_alpha=na, n_beta=nb, h=h, eri=eri, e_core=0.0,
                     chi=spec["chi"], parent_ptr=pp, parent_idx=pi, n_hidden=spec["nh"],
                     params=params, samples=samples, eps=spec["eps"], n_eps=spec["neps"],
-                    seed=seed + 4, precision=spec["prec"], ising=ising, tensor=tensor)
+                    seed=seed + 4, precision=spec["prec"], ising=ising, tensor=tensor, cplx=cplx)
 
 
 def serving_instances(seed_offset: int = 0) -> List[Dict]:
