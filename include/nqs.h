@@ -112,8 +112,9 @@ typedef struct {
                             samples' own pass when rows resume */
   double ms_psi;         /* device time of the row amplitude kernel launches alone */
   double psi_flops;      /* their algorithmic flops: 8 chi^2 d_i per evaluated site i with
-                            d_i parents, plus for a tensor-RNN site 2 (d chi chi' +
-                            4 chi'^(d+1) + 4 chi chi') */
+                            d_i parents (32 chi^2 d_i with complex parameters), plus for a
+                            tensor-RNN site 2 (d chi chi' + 4 chi'^(d+1) + 4 chi chi') */
+  double E_im;           /* nqs_eloc_complex: sum c Im Etilde_num / sum c |f|^2; else 0 */
 } nqs_eloc_stats;
 
 /* ---- context --------------------------------------------------------- */
@@ -121,7 +122,10 @@ typedef struct {
 /* Create a context on HIP device `device`; all objects made from it live on
  * that device.  The context owns a pool of device workspaces. */
 nqs_status nqs_ctx_create(int device, nqs_ctx** out);
-/* Destroy a context; objects created from it must be destroyed first. */
+/* Destroy a context.  No call may use an object created from it afterwards,
+ * except nqs_instance_destroy and nqs_ansatz_destroy (they keep the device
+ * and free their own memory, so garbage-collected handles may outlive the
+ * context); a server must be destroyed before its context. */
 nqs_status nqs_ctx_destroy(nqs_ctx* ctx);
 /* Message of the calling thread's last failed call ("" if none). */
 const char* nqs_last_error(void);
@@ -169,11 +173,27 @@ nqs_status nqs_connected(nqs_ctx* ctx, const nqs_instance* inst, const uint64_t*
  * adjoint, for a site with more than 3 parents, and when a thread's ring of
  * W x ceil4(chi) states does not fit the LDS). */
 #define NQS_ANSATZ_TENSOR 0x10
+/* Flag added to the correlator kind: complex parameters (Sec. 2.1, the
+ * MPS-RNN over C^chi): M, v, w, c complex, eta real and >= 0; the conditional
+ * P^s = h^dagger eta h and the phase of Phi(n) = sum_i arg(w_i^T h_i + c_i)
+ * (no conjugation of w; arg 0 = 0).  Packed layout per site as for real
+ * parameters, with every complex entry stored as (re, im): M (per parent,
+ * 4 x chi x chi pairs), v (4 x chi pairs), eta (chi reals), w (chi pairs),
+ * c (one pair); the correlator block after the sites stays real (its sign
+ * adds 0 or pi to the phase).  chi <= 32.  The amplitudes run in FP64 and
+ * FP32 with the rows evaluated from site 0 (the realified form: a real 2chi
+ * state with block matrices [[Re M, -Im M], [Im M, Re M]] on the same MFMA
+ * kernels, and the phase factors multiplied per row); NQS_EUNSUPPORTED for
+ * BF16; not combined with NQS_ANSATZ_TENSOR.  Signs are replaced by phases:
+ * nqs_logpsi, nqs_eloc and the sign output of nqs_sample refuse a complex
+ * ansatz (EINVAL); use nqs_logpsi_phase, nqs_eloc_complex and
+ * nqs_logpsi_vjp_phase. */
+#define NQS_ANSATZ_COMPLEX 0x20
 
 /* Describe the ansatz: K sites, electron counts of the sector (they define the
  * mask of Sec. 3), bond dimension chi (1..64), parent CSR (host arrays),
  * n_hidden correlator units (0 = no correlator) and the variant: the
- * correlator kind, optionally | NQS_ANSATZ_TENSOR.
+ * correlator kind, optionally | NQS_ANSATZ_TENSOR or | NQS_ANSATZ_COMPLEX.
  * Packed parameters: the BDG-RNN block, then b (n_hidden), W (n_hidden x 2K),
  * and for the Ising-RBM W2 (n_hidden x 2K x 2K, row-major).  EINVAL for a
  * malformed graph or an unknown correlator.  The Ising-RBM local energy keeps
@@ -195,6 +215,14 @@ nqs_status nqs_ansatz_bind_params(nqs_ansatz* ans, const double* params, hipStre
 nqs_status nqs_logpsi(nqs_ctx* ctx, const nqs_ansatz* ans, const uint64_t* samples, int64_t N,
                       int32_t precision, double* logabs, int8_t* sign, hipStream_t stream);
 
+/* log|Psi(n)| and the phase of Psi(n) in [-pi, pi] (device double[N] each,
+ * either may be NULL) for any ansatz: with real parameters the phase is 0 or
+ * pi by the sign.  precision NQS_F64 or NQS_F32 for a complex ansatz (the
+ * phase factors are multiplied in that precision, the final arg in FP64).  A
+ * sample outside the sector is EINVAL; Psi(n) = 0 gives -inf and phase 0. */
+nqs_status nqs_logpsi_phase(nqs_ctx* ctx, const nqs_ansatz* ans, const uint64_t* samples, int64_t N,
+                            int32_t precision, double* logabs, double* phase, hipStream_t stream);
+
 /* Vector-Jacobian product of log|Psi| (Eqs. (7), (19)): grad[k] +=
  * sum_n cot[n] d log|Psi(n)| / d theta_k over the packed parameters (device
  * double[n_params], accumulated, not overwritten).  cot: device double[N].
@@ -202,6 +230,18 @@ nqs_status nqs_logpsi(nqs_ctx* ctx, const nqs_ansatz* ans, const uint64_t* sampl
  * in FP64 across blocks). */
 nqs_status nqs_logpsi_vjp(nqs_ctx* ctx, const nqs_ansatz* ans, const uint64_t* samples, int64_t N,
                           const double* cot, int32_t precision, double* grad, hipStream_t stream);
+
+/* The same with the phase: grad[k] += sum_n (cot_abs[n] d log|Psi(n)| +
+ * cot_phase[n] d phase(n)) / d theta_k, where for a complex ansatz theta runs
+ * over the real and imaginary parts of the packed parameters (the gradient
+ * of a real loss, entry by entry of the packed vector).  With real
+ * parameters the phase is locally constant and cot_phase is ignored;
+ * cot_phase may be NULL (= 0).  The gradient of the energy over complex
+ * parameters, 2 Re <(E_loc - E)^* d ln Psi>, takes cot_abs from Re E_loc and
+ * cot_phase from Im E_loc (see nqs_vmc_step). */
+nqs_status nqs_logpsi_vjp_phase(nqs_ctx* ctx, const nqs_ansatz* ans, const uint64_t* samples, int64_t N,
+                                const double* cot_abs, const double* cot_phase, int32_t precision, double* grad,
+                                hipStream_t stream);
 
 /* ---- sampling (Sec. 2.1 autoregressive sampling, masks of Sec. 3) ------ */
 
@@ -249,6 +289,22 @@ nqs_status nqs_eloc(nqs_ctx* ctx, const nqs_instance* inst, const nqs_ansatz* an
                     const nqs_eloc_opts* opts, double* eloc, double* etnum, double* logabs,
                     int8_t* sign, double* fsq, nqs_eloc_stats* stats, hipStream_t stream);
 
+/* The same local energies for an ansatz with complex parameters (or any
+ * ansatz: real parameters give zero imaginary parts and phases 0 or pi):
+ * Psi(m)/Psi(n) = e^{log|Psi(m)| - log|Psi(n)|} e^{i (phase(m) - phase(n))}, so
+ * E_loc and Etilde_num are complex (eloc_re/eloc_im, etnum_re/etnum_im); phase
+ * = the phase of Psi(n) in [-pi, pi] replaces the sign.  All outputs device
+ * double[N], nullable.  The batch sums use Re Etilde_num for E, |E_loc - E|^2
+ * for the variance, and stats->E_im receives sum c Im Etilde_num / sum c |f|^2
+ * (zero in expectation, H being Hermitian).  Complex amplitudes run in FP64
+ * or FP32 with every row evaluated from site 0 (NQS_ELOC_FULL_RECOMPUTE
+ * implied). */
+nqs_status nqs_eloc_complex(nqs_ctx* ctx, const nqs_instance* inst, const nqs_ansatz* ans,
+                            const uint64_t* samples, const double* counts, int64_t N,
+                            const nqs_eloc_opts* opts, double* eloc_re, double* eloc_im, double* etnum_re,
+                            double* etnum_im, double* logabs, double* phase, double* fsq,
+                            nqs_eloc_stats* stats, hipStream_t stream);
+
 /* The amplitude rows of the same computation, for inspection: per sample
  * its own ONV (rank -1, coefficient 0), the deterministic set in canonical
  * rank order (coefficient H_nm) and the unique drawn determinants in rank
@@ -290,7 +346,7 @@ typedef struct {
   double ms_sample, ms_eloc, ms_grad, ms_update;   /* host wall time of the four stages */
 } nqs_vmc_stats;
 
-/* One variational step for real parameters: draw n_draws samples from Phi^2
+/* One variational step: draw n_draws samples from Phi^2
  * (nqs_sample), merge them into unique samples with counts, evaluate the
  * semi-stochastic local energies weighted by the counts (nqs_eloc), form the
  * reweighted gradient of Eq. (19),
@@ -299,7 +355,13 @@ typedef struct {
  * one AdamW update to params (device double[n_params], in place) with the
  * moment estimates adam_m, adam_v (device, in place, zero before the first
  * step), and re-bind the ansatz to the new parameters.  grad (device
- * double[n_params], nullable) receives g.  Synchronises `stream`. */
+ * double[n_params], nullable) receives g.  With complex parameters the
+ * local energies come from nqs_eloc_complex and the gradient over the real
+ * and imaginary parts is 2 Re <(E_loc - E)^* d ln Psi> reweighted as above:
+ * cot_abs_n = 2 c_n (Re Etilde_num(n) - |f_n|^2 E) / sum c |f|^2 and
+ * cot_phase_n = 2 c_n Im Etilde_num(n) / sum c |f|^2 through
+ * nqs_logpsi_vjp_phase; AdamW treats every real entry of the packed vector as
+ * one parameter.  Synchronises `stream`. */
 nqs_status nqs_vmc_step(nqs_ctx* ctx, const nqs_instance* inst, nqs_ansatz* ans, const nqs_vmc_opts* opts,
                         double* params, double* adam_m, double* adam_v, double* grad, nqs_vmc_stats* stats,
                         hipStream_t stream);

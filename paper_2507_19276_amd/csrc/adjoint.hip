@@ -15,6 +15,13 @@
 // The partial buffer is summed in a fixed order at the end, so the gradient is
 // bit-reproducible from run to run.
 //
+// Complex parameters run on the realified 2chi-unit state.  The phase term
+// gp arg(z_i), z_i = (w^T x + c) + i (w2^T x + c2) of the row's state x = h_i^{s_i},
+// adds (alpha w + beta w2) to dcand^{s_i} with alpha = -gp Im z / |z|^2 and
+// beta = gp Re z / |z|^2, and the column sums dw = sum_rows alpha x,
+// dw2 = sum beta x, dc = sum alpha, dc2 = sum beta.  k_cx_* map the realified
+// gradient back onto the packed complex parameters.
+//
 // MFMA k-permutation: in the 16x16x4 output layout lane (row j, group g)
 // holds units 16t + 4g + v of tile t in register v.  A contraction over those
 // units uses k-step (t, v) and lets lane group g supply unit 16t + 4g + v,
@@ -67,7 +74,7 @@ __device__ inline void counts_below(uint64_t lo, uint64_t hi, int i, int& ca, in
 }
 
 // Kernel A: one wavefront = 16 rows of site i.
-template <typename T, int CH>
+template <typename T, int CH, bool CPLX>
 __global__ __launch_bounds__(256) void k_bwd_site(AdjParams<T> P, int i, const uint64_t* m, int64_t R,
                                                   int64_t Rpad, const double* cot, const T* Hbuf,
                                                   T* dcarry, T* Dc, T* Eeta) {
@@ -138,6 +145,40 @@ __global__ __launch_bounds__(256) void k_bwd_site(AdjParams<T> P, int i, const u
   }
   const T psi_ = si == 0 ? ps[0] : si == 1 ? ps[1] : si == 2 ? ps[2] : ps[3];
   const T inv_p = T(1) / psi_, inv_z = T(1) / Z;
+  // phase term (complex parameters): alpha, beta of this row
+  T al = T(0), be = T(0);
+  if (CPLX) {
+    T zr = T(0), zi = T(0);
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      if (s != si) continue;
+#pragma unroll
+      for (int t = 0; t < TPC; ++t) {
+        const int u0 = 16 * t + 4 * g;
+        const V wa = *reinterpret_cast<const V*>(P.w + size_t(i) * CH + u0);
+        const V wb = *reinterpret_cast<const V*>(P.w2 + size_t(i) * CH + u0);
+        const V x = acc[s * TPC + t];
+        zr += wa.x * x.x + wa.y * x.y + wa.z * x.z + wa.w * x.w;
+        zi += wb.x * x.x + wb.y * x.y + wb.z * x.z + wb.w * x.w;
+      }
+    }
+    zr += __shfl_xor(zr, 16);
+    zr += __shfl_xor(zr, 32);
+    zi += __shfl_xor(zi, 16);
+    zi += __shfl_xor(zi, 32);
+    zr += P.c[i];
+    zi += P.c2[i];
+    const T z2 = zr * zr + zi * zi;
+    const T gp = live ? T(P.cotp[row]) : T(0);
+    if (z2 > T(0)) {
+      al = -gp * zi / z2;
+      be = gp * zr / z2;
+    }
+    if (g == 0) {
+      P.ab[2 * row] = al;
+      P.ab[2 * row + 1] = be;
+    }
+  }
   // d eta and dcand (in place of acc)
   const T* dci = dcarry + (size_t(i) * Rpad + row) * CH + 4 * g;
   V de[TPC];
@@ -159,6 +200,11 @@ __global__ __launch_bounds__(256) void k_bwd_site(AdjParams<T> P, int i, const u
       if (s == si) {
         d += *reinterpret_cast<const V*>(dci + 16 * t);
         de[t] += T(0.5) * gg * inv_p * x * x;
+        if (CPLX) {
+          const V wa = *reinterpret_cast<const V*>(P.w + size_t(i) * CH + u0);
+          const V wb = *reinterpret_cast<const V*>(P.w2 + size_t(i) * CH + u0);
+          d += al * wa + be * wb;
+        }
       }
       acc[s * TPC + t] = d;
       *reinterpret_cast<V*>(Dc + size_t(row) * 4 * CH + s * CH + u0) = d;
@@ -263,6 +309,84 @@ __global__ void k_bwd_colsum(AdjParams<T> P, int i, int64_t Rpad, int rows_per_s
   }
 }
 
+// complex parameters: dw[u] = sum_rows alpha x[u], dw2[u] = sum beta x[u],
+// dc = sum alpha, dc2 = sum beta over the rows of each split (one thread per
+// column: 2 CH units, then c and c2)
+template <typename T, int CH>
+__global__ void k_bwd_phase_colsum(AdjParams<T> P, int i, int64_t Rpad, int rows_per_split, int nsplit,
+                                   const T* Hbuf, double* gpart, int64_t n_params) {
+  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int ncol = 2 * CH + 2;
+  if (t >= int64_t(ncol) * nsplit) return;
+  const int split = int(t / ncol);
+  const int col = int(t % ncol);
+  const int64_t r0 = int64_t(split) * rows_per_split;
+  const int64_t r1 = r0 + rows_per_split < Rpad ? r0 + rows_per_split : Rpad;
+  const int which = col < 2 * CH ? col / CH : col - 2 * CH;    // 0: alpha (w, c), 1: beta (w2, c2)
+  const int u = col % CH;
+  const T* x = Hbuf + size_t(i) * Rpad * CH + u;
+  double acc = 0.0;
+  if (col < 2 * CH) {
+    for (int64_t r = r0; r < r1; ++r) acc += double(P.ab[2 * r + which]) * double(x[size_t(r) * CH]);
+    if (u < P.chi) gpart[size_t(split) * n_params + (which ? P.offW2[i] : P.offW[i]) + u] = acc;
+  } else {
+    for (int64_t r = r0; r < r1; ++r) acc += double(P.ab[2 * r + which]);
+    gpart[size_t(split) * n_params + (which ? P.offC2[i] : P.offC[i])] = acc;
+  }
+}
+
+// realified -> packed complex gradient.  M_r = [[Re M, -Im M], [Im M, Re M]]
+// per state: d Re M = G[u][k] + G[u+chi][k+chi], d Im M = G[u+chi][k] - G[u][k+chi]
+__global__ void k_cx_grad_edges(CxMap M, const double* gr, double* grad) {
+  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int chi = M.chi, c2 = 2 * chi;
+  const int64_t per = int64_t(4) * chi * chi;
+  if (t >= per * M.n_edges) return;
+  const int e = int(t / per);
+  const int r = int(t % per);
+  const int s = r / (chi * chi), u = (r / chi) % chi, k = r % chi;
+  const double* G = gr + M.rM[e] + size_t(s) * c2 * c2;
+  const double dre = G[size_t(u) * c2 + k] + G[size_t(u + chi) * c2 + k + chi];
+  const double dim = G[size_t(u + chi) * c2 + k] - G[size_t(u) * c2 + k + chi];
+  double* out = grad + M.cM[e] + 2 * ((size_t(s) * chi + u) * chi + k);
+  out[0] += dre;
+  out[1] += dim;
+}
+
+// per site: v_r = [Re v; Im v], eta_r = [eta; eta], w_r = [Re w; -Im w],
+// w2 = [Im w; Re w], c_r = Re c, c2 = Im c
+__global__ void k_cx_grad_sites(CxMap M, const double* gr, double* grad) {
+  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int chi = M.chi, c2 = 2 * chi;
+  const int per = 6 * chi + 1;
+  if (t >= int64_t(per) * M.K) return;
+  const int i = int(t / per);
+  const int r = int(t % per);
+  if (r < 4 * chi) {
+    const int s = r / chi, u = r % chi;
+    double* out = grad + M.cV[i] + 2 * (s * chi + u);
+    out[0] += gr[M.rV[i] + s * c2 + u];
+    out[1] += gr[M.rV[i] + s * c2 + chi + u];
+  } else if (r < 5 * chi) {
+    const int u = r - 4 * chi;
+    grad[M.cEta[i] + u] += gr[M.rEta[i] + u] + gr[M.rEta[i] + chi + u];
+  } else if (r < 6 * chi) {
+    const int u = r - 5 * chi;
+    double* out = grad + M.cW[i] + 2 * u;
+    out[0] += gr[M.rW[i] + u] + gr[M.rW2[i] + chi + u];
+    out[1] += gr[M.rW2[i] + u] - gr[M.rW[i] + chi + u];
+  } else {
+    double* out = grad + M.cC[i];
+    out[0] += gr[M.rC[i]];
+    out[1] += gr[M.rC2[i]];
+  }
+}
+
+__global__ void k_cx_grad_corr(CxMap M, const double* gr, double* grad) {
+  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t < M.n_corr) grad[M.c_corr + t] += gr[M.r_corr + t];
+}
+
 __device__ inline bool bit_at(uint64_t lo, uint64_t hi, int P) {
   return P < 64 ? ((lo >> P) & 1ull) : ((hi >> (P - 64)) & 1ull);
 }
@@ -348,10 +472,19 @@ hipError_t run_site(const AdjParams<T>& P, int i, const uint64_t* m, int64_t R, 
                     const double* cot, const T* Hbuf, T* dcarry, T* Dc, T* Eeta, int rows_per_split,
                     int nsplit, double* gpart, int64_t n_params, hipStream_t st) {
   const int64_t tiles = Rpad / 16;
-  hipLaunchKernelGGL((k_bwd_site<T, CH>), dim3(grid_for(tiles, 4)), dim3(256), 0, st, P, i, m, R, Rpad, cot,
-                     Hbuf, dcarry, Dc, Eeta);
+  if (P.cotp)
+    hipLaunchKernelGGL((k_bwd_site<T, CH, true>), dim3(grid_for(tiles, 4)), dim3(256), 0, st, P, i, m, R, Rpad,
+                       cot, Hbuf, dcarry, Dc, Eeta);
+  else
+    hipLaunchKernelGGL((k_bwd_site<T, CH, false>), dim3(grid_for(tiles, 4)), dim3(256), 0, st, P, i, m, R, Rpad,
+                       cot, Hbuf, dcarry, Dc, Eeta);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
+  if (P.cotp) {
+    hipLaunchKernelGGL((k_bwd_phase_colsum<T, CH>), dim3(grid_for(int64_t(2 * CH + 2) * nsplit, 256)), dim3(256),
+                       0, st, P, i, Rpad, rows_per_split, nsplit, Hbuf, gpart, n_params);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
   const int d = P.pptr_host[i + 1] - P.pptr_host[i];
   if (d > 0) {
     const int64_t units = int64_t(d) * (4 * CH / 16) * (CH / 16) * nsplit;
@@ -422,6 +555,21 @@ hipError_t launch_corr_backward(const CorrParams& C, const uint64_t* m, int64_t 
   const int threads = ((2 * C.K + 1 + 63) / 64) * 64;
   hipLaunchKernelGGL(k_corr_grad, dim3(unsigned(nsplit * C.nh)), dim3(threads), 0, st, C, m, R, rows_per_split,
                      dth, offB, offW, gpart, n_params);
+  return hipGetLastError();
+}
+
+hipError_t launch_cx_grad_map(const CxMap& M, const double* gr, double* grad, hipStream_t st) {
+  const int64_t ne = int64_t(4) * M.chi * M.chi * M.n_edges;
+  if (ne > 0) {
+    hipLaunchKernelGGL(k_cx_grad_edges, dim3(grid_for(ne, 256)), dim3(256), 0, st, M, gr, grad);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_cx_grad_sites, dim3(grid_for(int64_t(6 * M.chi + 1) * M.K, 256)), dim3(256), 0, st, M, gr,
+                     grad);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || M.n_corr == 0) return e;
+  hipLaunchKernelGGL(k_cx_grad_corr, dim3(grid_for(M.n_corr, 256)), dim3(256), 0, st, M, gr, grad);
   return hipGetLastError();
 }
 

@@ -341,31 +341,93 @@ __global__ __launch_bounds__(256) void k_reduce(int64_t n0, int64_t n1, const in
   }
 }
 
+// Per sample n (one wavefront), complex amplitudes: Psi(m)/Psi(n) =
+// s e^{ln|Psi(m)| - ln|Psi(n)|} e^{i (phase_m - phase_n)} with the real signs s
+// of the correlator; E_loc and Etilde_num as (re, im).  phs == nullptr: real
+// parameters, the phase factor is the sign product (imaginary parts exactly 0).
+template <bool CORR>
+__global__ __launch_bounds__(256) void k_reduce_cx(int64_t n0, int64_t n1, const int64_t* rowptr,
+                                                   int64_t row_base, const double* coef, const double* lphi,
+                                                   const int8_t* sphi, const double* phs, const double* lf,
+                                                   const int8_t* sf, const double* hdiag, double* eloc,
+                                                   double* eloc_im, double* etnum, double* etnum_im,
+                                                   double* logabs, double* phase, double* fsq) {
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t n = n0 + int64_t(blockIdx.x) * 4 + wv;
+  if (n >= n1) return;
+  const int64_t r0 = rowptr[n] - row_base, r1 = rowptr[n + 1] - row_base;
+  const double lpn = lphi[r0], lfn = CORR ? lf[r0] : 0.0;
+  const int spn = int(sphi[r0]), sfn = CORR ? int(sf[r0]) : 1;
+  const double phn = phs ? phs[r0] : 0.0;
+  double se = 0.0, sei = 0.0, st = 0.0, sti = 0.0;
+  for (int64_t r = r0 + 1 + lane; r < r1; r += 64) {
+    const double s = CORR ? double(int(sf[r]) * sfn) : 1.0;
+    const double x = CORR ? coef[r] * s * exp(lphi[r] + lf[r] - lpn - lfn) : coef[r] * exp(lphi[r] - lpn);
+    const double xt = CORR ? coef[r] * s * exp(lfn + lf[r] + lphi[r] - lpn) : x;
+    double cr, ci;
+    if (phs) {
+      const double d = phs[r] - phn;
+      cr = cos(d);
+      ci = sin(d);
+    } else {
+      cr = double(int(sphi[r]) * spn);
+      ci = 0.0;
+    }
+    se += x * cr;
+    sei += x * ci;
+    st += xt * cr;
+    sti += xt * ci;
+  }
+  se = wave_sum(se);
+  sei = wave_sum(sei);
+  st = wave_sum(st);
+  sti = wave_sum(sti);
+  if (lane == 0) {
+    const double la = lpn + lfn;
+    const bool valid = spn != 0 && isfinite(la);
+    const double f2 = exp(2.0 * lfn);
+    const double hd = hdiag[n];
+    const double pi = 3.14159265358979323846;
+    const double ph = phs ? phn : (spn < 0 ? pi : 0.0);
+    if (eloc) eloc[n] = valid ? hd + se : NAN;
+    if (eloc_im) eloc_im[n] = valid ? sei : NAN;
+    if (etnum) etnum[n] = valid ? f2 * hd + st : NAN;
+    if (etnum_im) etnum_im[n] = valid ? sti : NAN;
+    if (logabs) logabs[n] = la;
+    if (phase) phase[n] = valid ? remainder(ph + (sfn < 0 ? pi : 0.0), 2.0 * pi) : 0.0;
+    if (fsq) fsq[n] = f2;
+  }
+}
+
 // Batch sums with weights c_n (NaN local energies are left out and counted):
-// out = {sum c, sum c|f|^2, sum c Etilde_num, E, B, var, n_nan, 0}
+// out = {sum c, sum c|f|^2, sum c Etilde_num, E, B, var, n_nan, E_im}; with
+// complex local energies the variance takes |E_loc - E|^2 and
+// E_im = sum c Im Etilde_num / sum c|f|^2 (else 0)
 __global__ __launch_bounds__(1024) void k_batch_sums(int64_t N, const double* counts, const double* eloc,
                                                      const double* etnum, const double* fsq,
+                                                     const double* eloc_im, const double* etnum_im,
                                                      double* out) {
-  __shared__ double red[3][1024];
+  __shared__ double red[4][1024];
   __shared__ double E_sh;
   const int tid = threadIdx.x;
-  double sc = 0, sf2 = 0, se = 0, nn = 0;
+  double sc = 0, sf2 = 0, se = 0, sei = 0, nn = 0;
   for (int64_t n = tid; n < N; n += 1024) {
     const double c = counts ? counts[n] : 1.0;
     if (isnan(eloc[n])) { nn += 1; continue; }
     sc += c;
     sf2 += c * fsq[n];
     se += c * etnum[n];
+    if (etnum_im) sei += c * etnum_im[n];
   }
-  red[0][tid] = sc; red[1][tid] = sf2; red[2][tid] = se;
+  red[0][tid] = sc; red[1][tid] = sf2; red[2][tid] = se; red[3][tid] = sei;
   __syncthreads();
   for (int o = 512; o > 0; o >>= 1) {
     if (tid < o)
-      for (int k = 0; k < 3; ++k) red[k][tid] += red[k][tid + o];
+      for (int k = 0; k < 4; ++k) red[k][tid] += red[k][tid + o];
     __syncthreads();
   }
   if (tid == 0) E_sh = red[2][0] / red[1][0];
-  const double tsc = red[0][0], tsf = red[1][0], tse = red[2][0];
+  const double tsc = red[0][0], tsf = red[1][0], tse = red[2][0], tsei = red[3][0];
   __syncthreads();
   const double E = E_sh;
   double sv = 0;
@@ -373,7 +435,8 @@ __global__ __launch_bounds__(1024) void k_batch_sums(int64_t N, const double* co
     const double c = counts ? counts[n] : 1.0;
     if (isnan(eloc[n])) continue;
     const double d = eloc[n] - E;
-    sv += c * fsq[n] * d * d;
+    const double di = eloc_im ? eloc_im[n] : 0.0;
+    sv += c * fsq[n] * (d * d + di * di);
   }
   __syncthreads();
   red[0][tid] = sv;
@@ -385,8 +448,19 @@ __global__ __launch_bounds__(1024) void k_batch_sums(int64_t N, const double* co
   }
   if (tid == 0) {
     out[0] = tsc; out[1] = tsf; out[2] = tse; out[3] = E; out[4] = tsf / tsc;
-    out[5] = red[0][0] / tsf; out[6] = red[1][0]; out[7] = 0.0;
+    out[5] = red[0][0] / tsf; out[6] = red[1][0]; out[7] = etnum_im ? tsei / tsf : 0.0;
   }
+}
+
+__global__ void k_gather_logpsi_phase(int64_t N, const double* lphi, const int8_t* sphi, const double* phs,
+                                      const double* lf, const int8_t* sf, double* logabs, double* phase) {
+  const int64_t n = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (n >= N) return;
+  const double pi = 3.14159265358979323846;
+  const double ph = phs ? phs[n] : (sphi[n] < 0 ? pi : 0.0);
+  const bool neg_f = sf && sf[n] < 0;
+  if (logabs) logabs[n] = lphi[n] + (lf ? lf[n] : 0.0);
+  if (phase) phase[n] = sphi[n] == 0 ? 0.0 : remainder(ph + (neg_f ? pi : 0.0), 2.0 * pi);
 }
 
 __global__ void k_gather_logpsi(int64_t N, const double* lphi, const int8_t* sphi, const double* lf,
@@ -473,8 +547,33 @@ hipError_t launch_reduce(int64_t n0, int64_t n1, const int64_t* rowptr, int64_t 
 }
 
 hipError_t launch_batch_sums(int64_t N, const double* counts, const double* eloc, const double* etnum,
-                             const double* fsq, double* out, hipStream_t st) {
-  hipLaunchKernelGGL(k_batch_sums, dim3(1), dim3(1024), 0, st, N, counts, eloc, etnum, fsq, out);
+                             const double* fsq, double* out, hipStream_t st, const double* eloc_im,
+                             const double* etnum_im) {
+  hipLaunchKernelGGL(k_batch_sums, dim3(1), dim3(1024), 0, st, N, counts, eloc, etnum, fsq, eloc_im, etnum_im,
+                     out);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce_cx(int64_t n0, int64_t n1, const int64_t* rowptr, int64_t row_base, const double* coef,
+                            const double* lphi, const int8_t* sphi, const double* phs, const double* lf,
+                            const int8_t* sf, const double* hdiag, double* eloc, double* eloc_im, double* etnum,
+                            double* etnum_im, double* logabs, double* phase, double* fsq, hipStream_t st) {
+  if (n1 <= n0) return hipSuccess;
+  if (lf && sf)
+    hipLaunchKernelGGL(k_reduce_cx<true>, dim3(grid_for(n1 - n0, 4)), dim3(256), 0, st, n0, n1, rowptr, row_base,
+                       coef, lphi, sphi, phs, lf, sf, hdiag, eloc, eloc_im, etnum, etnum_im, logabs, phase, fsq);
+  else
+    hipLaunchKernelGGL(k_reduce_cx<false>, dim3(grid_for(n1 - n0, 4)), dim3(256), 0, st, n0, n1, rowptr, row_base,
+                       coef, lphi, sphi, phs, lf, sf, hdiag, eloc, eloc_im, etnum, etnum_im, logabs, phase, fsq);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather_logpsi_phase(int64_t N, const double* lphi, const int8_t* sphi, const double* phs,
+                                      const double* lf, const int8_t* sf, double* logabs, double* phase,
+                                      hipStream_t st) {
+  if (N <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_gather_logpsi_phase, dim3(grid_for(N, 256)), dim3(256), 0, st, N, lphi, sphi, phs, lf, sf,
+                     logabs, phase);
   return hipGetLastError();
 }
 

@@ -55,6 +55,8 @@ struct PsiParams {
   const T* w;                    // [K][chip]
   const T* c;                    // [K]
   bool folded;                   // operands carry sqrt(eta) (see k_psi_mt); never with a carried-state store
+  const T* w2 = nullptr;         // complex parameters (realified state): [K][chip] vector of Im z
+  const T* c2 = nullptr;         // [K] Im c
 };
 
 // BDG-TensorRNN forward (tensor_rnn.hip), one precision T.
@@ -86,6 +88,40 @@ struct AdjParams {
   const int64_t* offM;           // device: packed offset of each edge's M block
   const int64_t* offV;           // device [K]
   const int64_t* offEta;         // device [K]
+  // complex parameters (realified state): the phase factor z_i = (w^T x + c)
+  // + i (w2^T x + c2) of the stored state x, the phase cotangent, per-row
+  // scratch for the current site, and the offsets of w, c, w2, c2 in the
+  // realified gradient (device [K] each); cotp == nullptr: no phase term
+  const T* w = nullptr;
+  const T* c = nullptr;
+  const T* w2 = nullptr;
+  const T* c2 = nullptr;
+  const double* cotp = nullptr;  // [Rpad]
+  T* ab = nullptr;               // [Rpad][2]
+  const int64_t* offW = nullptr;
+  const int64_t* offC = nullptr;
+  const int64_t* offW2 = nullptr;
+  const int64_t* offC2 = nullptr;
+};
+
+// Map of a gradient over the realified parameters onto the packed complex
+// layout (adjoint.hip): per site the offsets in both vectors (device).
+struct CxMap {
+  int K, chi, n_edges;           // chi: complex units (the realified state has 2 chi)
+  const int* pptr;               // device [K+1]
+  const int64_t* rM;             // realified: per edge [4][2chi][2chi]
+  const int64_t* rV;             // [K] [4][2chi]
+  const int64_t* rEta;           // [K] [2chi]
+  const int64_t* rW;             // [K] [2chi] vector of Re z
+  const int64_t* rC;             // [K]
+  const int64_t* rW2;            // [K] [2chi] vector of Im z
+  const int64_t* rC2;            // [K]
+  const int64_t* cM;             // complex: per edge [4][chi][chi] pairs
+  const int64_t* cV;             // [K] [4][chi] pairs
+  const int64_t* cEta;           // [K] [chi]
+  const int64_t* cW;             // [K] [chi] pairs
+  const int64_t* cC;             // [K] one pair
+  int64_t r_corr, c_corr, n_corr;// the real correlator block: offsets and length
 };
 
 // BF16 forward (psi_bf16.hip): same edge tables as PsiParams; FP32 vectors.
@@ -221,12 +257,13 @@ hipError_t launch_node_assign(const uint8_t* t0, const uint32_t* sec, const uint
                               const int64_t* rowptr, int64_t n0, int64_t n1, int64_t row_base, int K, bool pair,
                               const int64_t* nbase, const int64_t* ebase, const NodeList& nl, int32_t* row_node,
                               uint8_t* row_site, hipStream_t st);
+// phs (complex parameters, PSI_PLAIN only): the phase of each row
 hipError_t launch_psi_f64(const PsiParams<double>& P, const uint64_t* m, int64_t R, double* lphi,
                           int8_t* sphi, hipStream_t st, const PsiStates<double>& X = PsiStates<double>(),
-                          int mode = PSI_PLAIN);
+                          int mode = PSI_PLAIN, double* phs = nullptr);
 hipError_t launch_psi_f32(const PsiParams<float>& P, const uint64_t* m, int64_t R, double* lphi,
                           int8_t* sphi, hipStream_t st, const PsiStates<float>& X = PsiStates<float>(),
-                          int mode = PSI_PLAIN);
+                          int mode = PSI_PLAIN, double* phs = nullptr);
 hipError_t launch_sample_f64(const PsiParams<double>& P, int64_t R, double* lphi, int8_t* sphi, hipStream_t st,
                              const SampleArgs& SA);
 hipError_t launch_sample_f32(const PsiParams<float>& P, int64_t R, double* lphi, int8_t* sphi, hipStream_t st,
@@ -266,6 +303,9 @@ hipError_t launch_i64_to_f64(int64_t n, const int64_t* a, double* b, hipStream_t
 // out (device double[2]) = {E, S}
 hipError_t launch_vmc_cotangent(int64_t N, const double* c, const double* etnum, const double* fsq, double* cot,
                                 double* out, hipStream_t st);
+// complex parameters: also cotp_n = 2 c_n etnum_im_n / S
+hipError_t launch_vmc_cotangent_cx(int64_t N, const double* c, const double* etnum, const double* etnum_im,
+                                   const double* fsq, double* cot, double* cotp, double* out, hipStream_t st);
 hipError_t launch_adamw(int64_t n, double* p, const double* g, double* m, double* v, int64_t t, double lr, double b1,
                         double b2, double eps, double wd, hipStream_t st);
 hipError_t launch_sumsq(int64_t n, const double* g, double* out, hipStream_t st);
@@ -294,10 +334,22 @@ hipError_t launch_reduce(int64_t n0, int64_t n1, const int64_t* rowptr, int64_t 
                          const double* lphi, const int8_t* sphi, const double* lf, const int8_t* sf,
                          const double* hdiag, double* eloc, double* etnum, double* logabs, int8_t* sign,
                          double* fsq, hipStream_t st);
+// eloc_im, etnum_im (nullable): complex local energies; then the variance
+// takes |E_loc - E|^2 and out[7] = sum c Im Etilde_num / sum c |f|^2
 hipError_t launch_batch_sums(int64_t N, const double* counts, const double* eloc, const double* etnum,
-                             const double* fsq, double* out /*[8]*/, hipStream_t st);
+                             const double* fsq, double* out /*[8]*/, hipStream_t st,
+                             const double* eloc_im = nullptr, const double* etnum_im = nullptr);
 hipError_t launch_gather_logpsi(int64_t N, const double* lphi, const int8_t* sphi, const double* lf,
                                 const int8_t* sf, double* logabs, int8_t* sign, hipStream_t st);
+// phases: the rows' phases of Phi (phs, nullable: 0 or pi by sphi) with the
+// correlator's sign
+hipError_t launch_reduce_cx(int64_t n0, int64_t n1, const int64_t* rowptr, int64_t row_base, const double* coef,
+                            const double* lphi, const int8_t* sphi, const double* phs, const double* lf,
+                            const int8_t* sf, const double* hdiag, double* eloc, double* eloc_im, double* etnum,
+                            double* etnum_im, double* logabs, double* phase, double* fsq, hipStream_t st);
+hipError_t launch_gather_logpsi_phase(int64_t N, const double* lphi, const int8_t* sphi, const double* phs,
+                                      const double* lf, const int8_t* sf, double* logabs, double* phase,
+                                      hipStream_t st);
 
 // ---- launchers (adjoint.hip) -------------------------------------------
 hipError_t launch_bwd_sweep_f64(const AdjParams<double>& P, const uint64_t* m, int64_t R, int64_t Rpad,
@@ -312,5 +364,7 @@ hipError_t launch_corr_backward(const CorrParams& C, const uint64_t* m, int64_t 
                                 double* dth, int rows_per_split, int nsplit, int64_t offB, int64_t offW,
                                 int64_t offW2, double* gpart, int64_t n_params, hipStream_t st);
 hipError_t launch_sum_parts(int64_t n_params, int nsplit, const double* gpart, double* grad, hipStream_t st);
+// grad (packed complex layout) += the realified gradient gr mapped through M
+hipError_t launch_cx_grad_map(const CxMap& M, const double* gr, double* grad, hipStream_t st);
 
 }  // namespace nqs

@@ -3,7 +3,11 @@
 // site i the candidates h_i^s = sum_{j in N(i)} M_ij^s h_j + v_i^s for the
 // four local states, the conditional P^s = h^T eta h normalised over the
 // states allowed by the particle-number / S_z mask (Sec. 3, Eqs. (23)-(24)),
-// the phase sign of w^T h + c, and the carried state h_i^{s_i}.
+// the phase sign of w^T h + c, and the carried state h_i^{s_i}.  With complex
+// parameters (CPLX) the kernel runs on the realified 2chi-unit state (block
+// matrices [[Re M, -Im M], [Im M, Re M]]) and multiplies the per-site phase
+// factors z_i = w_i^T h_i + c_i, Re z from w' = [Re w; -Im w] and Im z from
+// w2 = [Im w; Re w].
 //
 // Bond contractions run on MFMA in the transposed form
 //   H_i^T [4chi x rows] = W_i^T [4chi x d_i chi] . X_i^T [d_i chi x rows]
@@ -35,20 +39,22 @@ namespace {
 // FOLD: the operands carry sigma = sqrt(eta) (A' = sigma_i M / sigma_j,
 // v' = sigma v, w' = w / sigma, all eta > 0), so the ring holds sigma h and
 // P^s = sum_u x'^2 needs no eta.  STORE and SEED: see PsiStates (the
-// samples' pass that stores states, and the resumed row pass).
+// samples' pass that stores states, and the resumed row pass).  CPLX (rows
+// from site 0 only): phs receives arg prod_i z_i per row.
 template <typename T> constexpr int prefetch_ksteps(int CH) {
   return (CH / 4) < 64 / ((CH / 4) * int(sizeof(T) / 4)) ? (CH / 4) : 64 / ((CH / 4) * int(sizeof(T) / 4));
 }
 
-template <typename T, int CH, int NTL, bool FOLD, int STORE, bool SEED, bool SAMPLE>
+template <typename T, int CH, int NTL, bool FOLD, int STORE, bool SEED, bool SAMPLE, bool CPLX>
 __global__ __launch_bounds__(256) void k_psi_mt(PsiParams<T> P, const uint64_t* __restrict__ m, int64_t R,
                                                 double* __restrict__ lphi, int8_t* __restrict__ sphi, int wpb,
-                                                PsiStates<T> X, SampleArgs SA) {
+                                                PsiStates<T> X, SampleArgs SA, double* __restrict__ phs) {
   // every floating-point operation below is written out (explicit fma where
   // one is meant), so that all instances of this kernel round alike: a row
   // resumed from its sample's stored state ends bit-identical to a row
   // computed from site 0
 #pragma clang fp contract(off)
+  static_assert(!CPLX || (STORE == 0 && !SEED && !SAMPLE), "complex rows run from site 0");
   extern __shared__ __align__(16) unsigned char smem[];
   typedef typename V4<T>::type V;
   constexpr int TPC = CH / 16, NT = 4 * TPC, KS = CH / 4, RW = 16 * NTL;
@@ -71,6 +77,7 @@ __global__ __launch_bounds__(256) void k_psi_mt(PsiParams<T> P, const uint64_t* 
   const CInt* fptr = (const CInt*)(P.pptr);
   const CInt* slots = (const CInt*)(P.slot);
   const CT<T>* cc = (const CT<T>*)(P.c);
+  const CT<T>* cc2 = (const CT<T>*)(P.c2);
   // SEED: positions base.. map to rows X.perm[pos], sorted by their first
   // changed site, and the wavefront starts at the site of its first row
   const int i0 = SEED ? int(((const __attribute__((address_space(4))) uint8_t*)X.t0)[base]) : 0;
@@ -92,6 +99,7 @@ __global__ __launch_bounds__(256) void k_psi_mt(PsiParams<T> P, const uint64_t* 
   for (int t = 1; t < NTL; ++t)
     if (t == own) orow = rowt[t];
   T prod = T(1);
+  T zr = T(1), zi = T(0);   // CPLX: product of the phase factors, rescaled by powers of two
   int pexp = 0, sgn = 1, ca = 0, cb = 0, wslot = 0, e = 0;
   bool bad = false;
   if (SEED && i0 > 0) {
@@ -208,12 +216,13 @@ __global__ __launch_bounds__(256) void k_psi_mt(PsiParams<T> P, const uint64_t* 
   }
   for (int i = i0; i < iend; ++i) {
     store_pre(i);
-    V acc[NTL][NT], wv4[TPC], ev4[TPC];
+    V acc[NTL][NT], wv4[TPC], ev4[TPC], w2v4[TPC];
     // w and eta of this site are needed only after the contractions
 #pragma unroll
     for (int tt = 0; tt < TPC; ++tt) {
       wv4[tt] = *reinterpret_cast<const V*>(P.w + size_t(i) * CH + 16 * tt + 4 * g);
       if (!FOLD) ev4[tt] = *reinterpret_cast<const V*>(P.eta + size_t(i) * CH + 16 * tt + 4 * g);
+      if (CPLX) w2v4[tt] = *reinterpret_cast<const V*>(P.w2 + size_t(i) * CH + 16 * tt + 4 * g);
     }
     const int e1 = fptr[i + 1];
     // one edge: a chi-wide slice of the contraction over the parents
@@ -351,10 +360,11 @@ __global__ __launch_bounds__(256) void k_psi_mt(PsiParams<T> P, const uint64_t* 
     int si[NTL];
 #pragma unroll
     for (int t = 0; t < NTL; ++t) si[t] = site_state(lo[t], hi[t], i);
-    T pp[4][NTL], dp[NTL];
+    T pp[4][NTL], dp[NTL], dq[NTL];
 #pragma unroll
     for (int t = 0; t < NTL; ++t) {
       dp[t] = T(0);
+      dq[t] = T(0);
 #pragma unroll
       for (int s = 0; s < 4; ++s) pp[s][t] = T(0);
     }
@@ -385,6 +395,15 @@ __global__ __launch_bounds__(256) void k_psi_mt(PsiParams<T> P, const uint64_t* 
         d = tfma(ww.z, sel.z, d);
         d = tfma(ww.w, sel.w, d);
         dp[t] = d;
+        if (CPLX) {
+          const V w2 = w2v4[tt];
+          T d2 = dq[t];
+          d2 = tfma(w2.x, sel.x, d2);
+          d2 = tfma(w2.y, sel.y, d2);
+          d2 = tfma(w2.z, sel.z, d2);
+          d2 = tfma(w2.w, sel.w, d2);
+          dq[t] = d2;
+        }
         wr[(t * TPC + tt) * 64] = sel;
         if (STORE == 1) {
           // positions past R (up to the stride X.ns) get the last row's state:
@@ -401,6 +420,20 @@ __global__ __launch_bounds__(256) void k_psi_mt(PsiParams<T> P, const uint64_t* 
 #pragma unroll
     for (int s = 0; s < 4; ++s) ps[s] = ReduceOwn<T, NTL>::run(pp[s]);
     const T dot = ReduceOwn<T, NTL>::run(dp) + T(cc[i]);
+    if (CPLX) {
+      // z <- z (Re z_i + i Im z_i), then an exact power-of-two rescale; a zero
+      // factor has no argument and is left out (arg 0 = 0)
+      const T di = ReduceOwn<T, NTL>::run(dq) + T(cc2[i]);
+      if (dot != T(0) || di != T(0)) {
+        const T nr = zr * dot - zi * di;
+        const T ni = zr * di + zi * dot;
+        const T an = fabs(nr) > fabs(ni) ? fabs(nr) : fabs(ni);
+        int ez;
+        (void)tfrexp(an, &ez);
+        zr = ldexp(nr, -ez);
+        zi = ldexp(ni, -ez);
+      }
+    }
     // per-row work, once per row: lane group g owns tile own(g)
     const int osi = site_state(olo, ohi, i);
     const int rest = P.K - 1 - i;
@@ -415,7 +448,7 @@ __global__ __launch_bounds__(256) void k_psi_mt(PsiParams<T> P, const uint64_t* 
     int ex;
     prod = tfrexp(prod * (psi_ / Z), &ex);
     pexp += ex;
-    if (dot < T(0)) sgn = -sgn;
+    if (!CPLX && dot < T(0)) sgn = -sgn;
     ca += osi & 1;
     cb += osi >> 1;
   }
@@ -424,6 +457,7 @@ __global__ __launch_bounds__(256) void k_psi_mt(PsiParams<T> P, const uint64_t* 
   if (writer && olive) {
     lphi[orow] = bad ? -INFINITY : 0.5 * (log(double(prod)) + double(pexp) * 0.69314718055994530942);
     sphi[orow] = int8_t(bad ? 0 : sgn);
+    if (CPLX) phs[orow] = bad ? 0.0 : atan2(double(zi), double(zr));
     if (SAMPLE) {
       SA.out[2 * orow] = olo;
       SA.out[2 * orow + 1] = ohi;
@@ -438,9 +472,10 @@ template <typename T> constexpr int ntiles(int CH) {
   return sizeof(T) == 4 ? (CH <= 16 ? NQS_NTL_F32_16 : (CH <= 32 ? 2 : 1)) : (CH <= 16 ? 2 : 1);
 }
 
-template <typename T, int CH, bool FOLD, int STORE, bool SEED, bool SAMPLE = false>
+template <typename T, int CH, bool FOLD, int STORE, bool SEED, bool SAMPLE = false, bool CPLX = false>
 hipError_t run_psi_mt(const PsiParams<T>& P, const uint64_t* m, int64_t R, double* lphi, int8_t* sphi,
-                      hipStream_t st, const PsiStates<T>& X, const SampleArgs& SA = SampleArgs()) {
+                      hipStream_t st, const PsiStates<T>& X, const SampleArgs& SA = SampleArgs(),
+                      double* phs = nullptr) {
   if (R <= 0) return hipSuccess;
   constexpr int NTL = ntiles<T>(CH);
   const size_t per_wave = size_t(P.W + 1) * 16 * NTL * CH * sizeof(T);
@@ -449,14 +484,20 @@ hipError_t run_psi_mt(const PsiParams<T>& P, const uint64_t* m, int64_t R, doubl
   if (per_wave * wpb > 160 * 1024) return hipErrorInvalidValue;
   const int64_t tiles = (R + 16 * NTL - 1) / (16 * NTL);
   const int64_t blocks = (tiles + wpb - 1) / wpb;
-  hipLaunchKernelGGL((k_psi_mt<T, CH, NTL, FOLD, STORE, SEED, SAMPLE>), dim3(unsigned(blocks)), dim3(64 * wpb),
-                     per_wave * wpb, st, P, m, R, lphi, sphi, wpb, X, SA);
+  hipLaunchKernelGGL((k_psi_mt<T, CH, NTL, FOLD, STORE, SEED, SAMPLE, CPLX>), dim3(unsigned(blocks)),
+                     dim3(64 * wpb), per_wave * wpb, st, P, m, R, lphi, sphi, wpb, X, SA, phs);
   return hipGetLastError();
 }
 
 template <typename T, int CH>
 hipError_t run_psi_ch(const PsiParams<T>& P, const uint64_t* m, int64_t R, double* lphi, int8_t* sphi,
-                      hipStream_t st, const PsiStates<T>& X, int mode) {
+                      hipStream_t st, const PsiStates<T>& X, int mode, double* phs) {
+  if (phs) {
+    // complex parameters: rows from site 0, the phase per row
+    if (mode != PSI_PLAIN || !P.w2 || !P.c2) return hipErrorInvalidValue;
+    if (P.folded) return run_psi_mt<T, CH, true, 0, false, false, true>(P, m, R, lphi, sphi, st, X, SampleArgs(), phs);
+    return run_psi_mt<T, CH, false, 0, false, false, true>(P, m, R, lphi, sphi, st, X, SampleArgs(), phs);
+  }
   switch (mode) {
     case PSI_PLAIN:
       if (P.folded) return run_psi_mt<T, CH, true, 0, false>(P, m, R, lphi, sphi, st, X);
@@ -496,12 +537,12 @@ hipError_t dispatch_sample(const PsiParams<T>& P, int64_t R, double* lphi, int8_
 
 template <typename T>
 hipError_t dispatch_psi(const PsiParams<T>& P, const uint64_t* m, int64_t R, double* lphi,
-                        int8_t* sphi, hipStream_t st, const PsiStates<T>& X, int mode) {
+                        int8_t* sphi, hipStream_t st, const PsiStates<T>& X, int mode, double* phs) {
   switch (P.chip) {
-    case 16: return run_psi_ch<T, 16>(P, m, R, lphi, sphi, st, X, mode);
-    case 32: return run_psi_ch<T, 32>(P, m, R, lphi, sphi, st, X, mode);
-    case 48: return run_psi_ch<T, 48>(P, m, R, lphi, sphi, st, X, mode);
-    case 64: return run_psi_ch<T, 64>(P, m, R, lphi, sphi, st, X, mode);
+    case 16: return run_psi_ch<T, 16>(P, m, R, lphi, sphi, st, X, mode, phs);
+    case 32: return run_psi_ch<T, 32>(P, m, R, lphi, sphi, st, X, mode, phs);
+    case 48: return run_psi_ch<T, 48>(P, m, R, lphi, sphi, st, X, mode, phs);
+    case 64: return run_psi_ch<T, 64>(P, m, R, lphi, sphi, st, X, mode, phs);
     default: return hipErrorInvalidValue;
   }
 }
@@ -509,13 +550,13 @@ hipError_t dispatch_psi(const PsiParams<T>& P, const uint64_t* m, int64_t R, dou
 }  // namespace
 
 hipError_t launch_psi_f64(const PsiParams<double>& P, const uint64_t* m, int64_t R, double* lphi,
-                          int8_t* sphi, hipStream_t st, const PsiStates<double>& X, int mode) {
-  return dispatch_psi<double>(P, m, R, lphi, sphi, st, X, mode);
+                          int8_t* sphi, hipStream_t st, const PsiStates<double>& X, int mode, double* phs) {
+  return dispatch_psi<double>(P, m, R, lphi, sphi, st, X, mode, phs);
 }
 
 hipError_t launch_psi_f32(const PsiParams<float>& P, const uint64_t* m, int64_t R, double* lphi,
-                          int8_t* sphi, hipStream_t st, const PsiStates<float>& X, int mode) {
-  return dispatch_psi<float>(P, m, R, lphi, sphi, st, X, mode);
+                          int8_t* sphi, hipStream_t st, const PsiStates<float>& X, int mode, double* phs) {
+  return dispatch_psi<float>(P, m, R, lphi, sphi, st, X, mode, phs);
 }
 
 hipError_t launch_sample_f64(const PsiParams<double>& P, int64_t R, double* lphi, int8_t* sphi, hipStream_t st,

@@ -14,6 +14,7 @@
 #include <cstring>
 #include <limits>
 #include <map>
+#include <type_traits>
 #include <memory>
 #include <mutex>
 #include <string>
@@ -162,6 +163,7 @@ int64_t choose2(int64_t n) { return n < 2 ? 0 : n * (n - 1) / 2; }
 // ---------------------------------------------------------------------------
 struct nqs_instance {
   nqs_ctx* ctx = nullptr;
+  int device = 0;           // the context's device, kept for destruction after the context
   int K = 0, na = 0, nb = 0;
   double ecore = 0;
   double* d_h = nullptr;
@@ -185,22 +187,25 @@ struct PsiLayout {
   T* eta = nullptr;
   T* w = nullptr;
   T* c = nullptr;
+  T* w2 = nullptr;          // complex parameters: [K][chip] vector of Im z, (folded like w)
+  T* c2 = nullptr;          // [K]
   T* AF = nullptr;          // adjoint: recompute operands (k-permuted)
   int64_t* afoff = nullptr;
   T* BT = nullptr;          // adjoint: M^T operands
   int64_t* btoff = nullptr;
   bool folded = false;      // operands carry sqrt(eta)
   void free_all() {
-    for (void* p : {(void*)A, (void*)v, (void*)eta, (void*)w, (void*)c, (void*)AF, (void*)afoff, (void*)BT,
-                    (void*)btoff})
+    for (void* p : {(void*)A, (void*)v, (void*)eta, (void*)w, (void*)c, (void*)w2, (void*)c2, (void*)AF,
+                    (void*)afoff, (void*)BT, (void*)btoff})
       if (p) (void)hipFree(p);
-    A = nullptr; v = eta = w = c = nullptr;
+    A = nullptr; v = eta = w = c = w2 = c2 = nullptr;
     AF = nullptr; afoff = nullptr; BT = nullptr; btoff = nullptr;
   }
 };
 
 struct nqs_ansatz {
   nqs_ctx* ctx = nullptr;
+  int device = 0;           // the context's device, kept for destruction after the context
   int K = 0, na = 0, nb = 0, chi = 0, chip = 0, nh = 0, W = 1;
   std::vector<int32_t> pptr, pidx;
   std::vector<int64_t> offM, offV, offEta, offW, offC;
@@ -238,6 +243,16 @@ struct nqs_ansatz {
   int64_t* d_offM = nullptr;
   int64_t* d_offV = nullptr;
   int64_t* d_offEta = nullptr;
+  // Complex parameters: the kernels see the realified ansatz (chi = 2 chi_c
+  // real units, block matrices); its packed vector (nr_params) is the real
+  // layout, the correlator, then per site w2 (2 chi_c) and c2 at offW2x /
+  // offC2x.  n_params and cx_* describe the caller's packed complex layout.
+  bool cplx = false;
+  int chi_c = 0;
+  int64_t nr_params = 0;
+  std::vector<int64_t> offW2x, offC2x, cx_offM, cx_offV, cx_offEta, cx_offW, cx_offC;
+  int64_t cx_offB = 0;
+  int64_t* d_cx = nullptr;  // device: rW, rC, rW2, rC2, cV, cEta, cW, cC ([K] each), then cM ([edges])
   ~nqs_ansatz() {
     L64.free_all();
     L32.free_all();
@@ -246,7 +261,7 @@ struct nqs_ansatz {
     for (void* p : {(void*)d_pptr, (void*)d_pidx, (void*)d_slot, (void*)d_fptr, (void*)d_fslot, (void*)bfA,
                     (void*)d_cb, (void*)d_cW, (void*)d_cW1t, (void*)d_cS, (void*)d_cS32, (void*)d_tn_edge,
                     (void*)d_tn_site, (void*)tn64, (void*)tn32, (void*)d_offM, (void*)d_offV,
-                    (void*)d_offEta})
+                    (void*)d_offEta, (void*)d_cx})
       if (p) (void)hipFree(p);
   }
   template <typename T>
@@ -266,7 +281,19 @@ struct nqs_ansatz {
     P.pptr = d_fptr; P.slot = d_fslot;
     P.A = L.A; P.v = L.v; P.eta = L.eta; P.w = L.w; P.c = L.c;
     P.folded = L.folded;
+    P.w2 = L.w2; P.c2 = L.c2;
     return P;
+  }
+  CxMap cxmap() const {
+    CxMap M;
+    M.K = K; M.chi = chi_c; M.n_edges = pptr[K];
+    M.pptr = d_pptr;
+    M.rM = d_offM; M.rV = d_offV; M.rEta = d_offEta;
+    M.rW = d_cx; M.rC = d_cx + K; M.rW2 = d_cx + 2 * K; M.rC2 = d_cx + 3 * K;
+    M.cV = d_cx + 4 * K; M.cEta = d_cx + 5 * K; M.cW = d_cx + 6 * K; M.cC = d_cx + 7 * K;
+    M.cM = d_cx + 8 * K;
+    M.r_corr = offB; M.c_corr = cx_offB; M.n_corr = n_params - cx_offB;
+    return M;
   }
   // forward layout for amplitudes without a carried-state store
   const PsiLayout<double>& fwd64() const { return has_fold ? F64 : L64; }
@@ -354,6 +381,22 @@ nqs_status build_layout(nqs_ansatz* a, const std::vector<double>& prm, PsiLayout
     }
     c[i] = T(prm[a->offC[i]]);
   }
+  std::vector<T> w2, c2;
+  if (a->cplx) {
+    w2.assign(size_t(K) * CH, T(0));
+    c2.resize(K);
+    for (int i = 0; i < K; ++i) {
+      const double* si = sig.data() + size_t(i) * chi;
+      for (int u = 0; u < chi; ++u) w2[size_t(i) * CH + u] = T(prm[a->offW2x[i] + u] / si[u]);
+      c2[i] = T(prm[a->offC2x[i]]);
+    }
+  }
+  auto upload_cx = [&]() -> nqs_status {
+    nqs_status st;
+    if (!a->cplx) return NQS_OK;
+    if ((st = upload(&L.w2, w2)) != NQS_OK) return st;
+    return upload(&L.c2, c2);
+  };
   if (fold) {
     L.free_all();
     L.folded = true;
@@ -363,7 +406,7 @@ nqs_status build_layout(nqs_ansatz* a, const std::vector<double>& prm, PsiLayout
     if ((st = upload(&L.eta, eta)) != NQS_OK) return st;
     if ((st = upload(&L.w, w)) != NQS_OK) return st;
     if ((st = upload(&L.c, c)) != NQS_OK) return st;
-    return NQS_OK;
+    return upload_cx();
   }
   // adjoint operands.  AF: like A but k-step q = 4t + v pairs lane group k'
   // with parent unit 16t + 4k' + v.  BT: k-step q = (s*TPC + t)*4 + v over the
@@ -411,7 +454,7 @@ nqs_status build_layout(nqs_ansatz* a, const std::vector<double>& prm, PsiLayout
   if ((st = upload(&L.eta, eta)) != NQS_OK) return st;
   if ((st = upload(&L.w, w)) != NQS_OK) return st;
   if ((st = upload(&L.c, c)) != NQS_OK) return st;
-  return NQS_OK;
+  return upload_cx();
 }
 
 // round-to-nearest-even FP32 -> BF16 bit pattern (finite inputs)
@@ -625,6 +668,7 @@ nqs_status nqs_instance_create(nqs_ctx* ctx, int K, int n_alpha, int n_beta, con
   DeviceGuard g(ctx->device);
   std::unique_ptr<nqs_instance> inst(new nqs_instance());
   inst->ctx = ctx;
+  inst->device = ctx->device;
   inst->K = K; inst->na = n_alpha; inst->nb = n_beta; inst->ecore = e_core;
   nqs_status st;
   if ((st = upload(&inst->d_h, hs)) != NQS_OK) return st;
@@ -667,7 +711,7 @@ nqs_status nqs_instance_create(nqs_ctx* ctx, int K, int n_alpha, int n_beta, con
 
 nqs_status nqs_instance_destroy(nqs_instance* inst) {
   if (!inst) return NQS_OK;
-  DeviceGuard g(inst->ctx->device);
+  DeviceGuard g(inst->device);
   delete inst;
   return NQS_OK;
 }
@@ -679,18 +723,28 @@ nqs_status nqs_ansatz_create(nqs_ctx* ctx, int K, int n_alpha, int n_beta, int c
                              int32_t variant, nqs_ansatz** out) {
   if (!ctx || !parent_ptr || !out) return fail(NQS_EINVAL, "NULL argument");
   const int32_t correlator = variant & 0xF;
-  if ((correlator != NQS_CORR_COS_RBM && correlator != NQS_CORR_ISING_RBM) || (variant & ~(0xF | NQS_ANSATZ_TENSOR)))
+  if ((correlator != NQS_CORR_COS_RBM && correlator != NQS_CORR_ISING_RBM) ||
+      (variant & ~(0xF | NQS_ANSATZ_TENSOR | NQS_ANSATZ_COMPLEX)))
     return fail(NQS_EINVAL, "unknown ansatz variant %d", variant);
+  const bool cplx = (variant & NQS_ANSATZ_COMPLEX) != 0;
+  if (cplx && (variant & NQS_ANSATZ_TENSOR))
+    return fail(NQS_EINVAL, "complex parameters are not combined with the tensor-RNN term");
   if (K < 1 || K > 64) return fail(NQS_EINVAL, "K=%d outside [1,64]", K);
   if (chi < 1 || chi > 64) return fail(NQS_EUNSUPPORTED, "chi=%d outside [1,64]", chi);
+  if (cplx && chi > 32) return fail(NQS_EUNSUPPORTED, "complex chi=%d above 32", chi);
+  const int chi_c = chi;
+  if (cplx) chi = 2 * chi;   // the realified state
   if (n_alpha < 0 || n_alpha > K || n_beta < 0 || n_beta > K) return fail(NQS_EINVAL, "bad electron counts");
   if (n_hidden < 0) return fail(NQS_EINVAL, "n_hidden < 0");
   if (parent_ptr[0] != 0) return fail(NQS_EINVAL, "parent_ptr[0] != 0");
   std::unique_ptr<nqs_ansatz> a(new nqs_ansatz());
   a->ctx = ctx;
+  a->device = ctx->device;
   a->K = K; a->na = n_alpha; a->nb = n_beta; a->chi = chi; a->nh = n_hidden;
   a->ising = n_hidden > 0 && correlator == NQS_CORR_ISING_RBM;
   a->tensor = (variant & NQS_ANSATZ_TENSOR) != 0;
+  a->cplx = cplx;
+  a->chi_c = chi_c;
   a->chip = ((chi + 15) / 16) * 16;
   a->pptr.assign(parent_ptr, parent_ptr + K + 1);
   int maxoff = 0;
@@ -721,6 +775,30 @@ nqs_status nqs_ansatz_create(nqs_ctx* ctx, int K, int n_alpha, int n_beta, int c
   a->offWc = o; o += int64_t(n_hidden) * 2 * K;
   a->offW2 = o;
   if (a->ising) o += int64_t(n_hidden) * 4 * K * K;
+  if (cplx) {
+    // the realified vector's w2 and c2 (Im z = w2^T x + c2), then the
+    // caller's complex layout
+    a->offW2x.resize(K);
+    a->offC2x.resize(K);
+    for (int i = 0; i < K; ++i) {
+      a->offW2x[i] = o; o += chi;
+      a->offC2x[i] = o; o += 1;
+    }
+    a->nr_params = o;
+    int64_t q = 0;
+    a->cx_offM.resize(a->pptr[K]);
+    a->cx_offV.resize(K); a->cx_offEta.resize(K); a->cx_offW.resize(K); a->cx_offC.resize(K);
+    for (int i = 0; i < K; ++i) {
+      for (int e = a->pptr[i]; e < a->pptr[i + 1]; ++e) { a->cx_offM[e] = q; q += int64_t(8) * chi_c * chi_c; }
+      a->cx_offV[i] = q; q += 8 * chi_c;
+      a->cx_offEta[i] = q; q += chi_c;
+      a->cx_offW[i] = q; q += 2 * chi_c;
+      a->cx_offC[i] = q; q += 2;
+    }
+    a->cx_offB = q;
+    q += int64_t(n_hidden) * (2 * K + 1) + (a->ising ? int64_t(n_hidden) * 4 * K * K : 0);
+    o = q;   // n_params below: the caller's (complex) layout
+  }
   // BDG-TensorRNN block, last: per site with d >= 2 parents the factor
   // matrices K^(0..d) (chi x chi' each) and the cores U^s (chi'^(d+1) each)
   a->tq.assign(K, 0);
@@ -744,6 +822,7 @@ nqs_status nqs_ansatz_create(nqs_ctx* ctx, int K, int n_alpha, int n_beta, int c
     a->offTU[i] = o; o += 4 * qd;
   }
   a->n_params = o;
+  if (!cplx) a->nr_params = o;
   DeviceGuard g(ctx->device);
   nqs_status st;
   std::vector<int> pp(a->pptr.begin(), a->pptr.end()), pi(a->pidx.begin(), a->pidx.end());
@@ -763,6 +842,13 @@ nqs_status nqs_ansatz_create(nqs_ctx* ctx, int K, int n_alpha, int n_beta, int c
   if ((st = upload(&a->d_offM, a->offM)) != NQS_OK) return st;
   if ((st = upload(&a->d_offV, a->offV)) != NQS_OK) return st;
   if ((st = upload(&a->d_offEta, a->offEta)) != NQS_OK) return st;
+  if (cplx) {
+    std::vector<int64_t> tab;
+    for (auto* v : {&a->offW, &a->offC, &a->offW2x, &a->offC2x, &a->cx_offV, &a->cx_offEta, &a->cx_offW,
+                    &a->cx_offC, &a->cx_offM})
+      tab.insert(tab.end(), v->begin(), v->end());
+    if ((st = upload(&a->d_cx, tab)) != NQS_OK) return st;
+  }
   if (a->tensor) {
     // kernel layout offsets (elements; every block starts on a multiple of 16)
     const int cp = a->chip;
@@ -811,7 +897,7 @@ nqs_status nqs_ansatz_create(nqs_ctx* ctx, int K, int n_alpha, int n_beta, int c
 
 nqs_status nqs_ansatz_destroy(nqs_ansatz* ans) {
   if (!ans) return NQS_OK;
-  DeviceGuard g(ans->ctx->device);
+  DeviceGuard g(ans->device);
   delete ans;
   return NQS_OK;
 }
@@ -824,6 +910,49 @@ nqs_status nqs_ansatz_bind_params(nqs_ansatz* ans, const double* params, hipStre
   std::vector<double> prm(ans->n_params);
   HIPCHK(hipMemcpyAsync(prm.data(), params, prm.size() * sizeof(double), hipMemcpyDeviceToHost, stream));
   HIPCHK(hipStreamSynchronize(stream));
+  if (ans->cplx) {
+    // the realified vector: per edge and state M_r = [[Re M, -Im M], [Im M, Re M]],
+    // v_r = [Re v; Im v], eta_r = [eta; eta], w_r = [Re w; -Im w], c_r = Re c,
+    // w2 = [Im w; Re w], c2 = Im c; the correlator block as it is
+    const int n = ans->chi_c, n2 = 2 * n;
+    for (int i = 0; i < ans->K; ++i)
+      for (int u = 0; u < n; ++u)
+        if (!(prm[ans->cx_offEta[i] + u] >= 0.0))
+          return fail(NQS_EINVAL, "eta[%d][%d] = %g is negative or NaN", i, u, prm[ans->cx_offEta[i] + u]);
+    std::vector<double> r(ans->nr_params, 0.0);
+    for (int i = 0; i < ans->K; ++i) {
+      for (int e = ans->pptr[i]; e < ans->pptr[i + 1]; ++e)
+        for (int s = 0; s < 4; ++s)
+          for (int u = 0; u < n; ++u)
+            for (int k = 0; k < n; ++k) {
+              const double* z = prm.data() + ans->cx_offM[e] + 2 * ((int64_t(s) * n + u) * n + k);
+              double* B = r.data() + ans->offM[e] + int64_t(s) * n2 * n2;
+              B[int64_t(u) * n2 + k] = z[0];
+              B[int64_t(u) * n2 + k + n] = -z[1];
+              B[int64_t(u + n) * n2 + k] = z[1];
+              B[int64_t(u + n) * n2 + k + n] = z[0];
+            }
+      for (int s = 0; s < 4; ++s)
+        for (int u = 0; u < n; ++u) {
+          r[ans->offV[i] + s * n2 + u] = prm[ans->cx_offV[i] + 2 * (s * n + u)];
+          r[ans->offV[i] + s * n2 + n + u] = prm[ans->cx_offV[i] + 2 * (s * n + u) + 1];
+        }
+      for (int u = 0; u < n; ++u) {
+        const double et = prm[ans->cx_offEta[i] + u];
+        const double wr = prm[ans->cx_offW[i] + 2 * u], wi = prm[ans->cx_offW[i] + 2 * u + 1];
+        r[ans->offEta[i] + u] = et;
+        r[ans->offEta[i] + n + u] = et;
+        r[ans->offW[i] + u] = wr;
+        r[ans->offW[i] + n + u] = -wi;
+        r[ans->offW2x[i] + u] = wi;
+        r[ans->offW2x[i] + n + u] = wr;
+      }
+      r[ans->offC[i]] = prm[ans->cx_offC[i]];
+      r[ans->offC2x[i]] = prm[ans->cx_offC[i] + 1];
+    }
+    std::copy(prm.begin() + ans->cx_offB, prm.end(), r.begin() + ans->offB);
+    prm.swap(r);
+  }
   for (int i = 0; i < ans->K; ++i)
     for (int u = 0; u < ans->chi; ++u)
       if (!(prm[ans->offEta[i] + u] >= 0.0))
@@ -842,7 +971,7 @@ nqs_status nqs_ansatz_bind_params(nqs_ansatz* ans, const double* params, hipStre
     if ((st = build_layout<float>(ans, prm, ans->F32, true)) != NQS_OK) return st;
     ans->has_fold = true;
   }
-  if ((st = build_bf16(ans, prm, ans->has_fold)) != NQS_OK) return st;
+  if (!ans->cplx && (st = build_bf16(ans, prm, ans->has_fold)) != NQS_OK) return st;
   if (ans->tensor && (st = build_tn(ans, prm)) != NQS_OK) return st;
   if (ans->d_cb) { (void)hipFree(ans->d_cb); ans->d_cb = nullptr; }
   if (ans->d_cW) { (void)hipFree(ans->d_cW); ans->d_cW = nullptr; }
@@ -962,9 +1091,22 @@ size_t mantissa_bytes(int precision) { return precision == NQS_F64 ? 8 : 4; }
 
 // amplitudes of R rows into (lphi, sphi).  mode PSI_STORE (samples, with rs)
 // or PSI_SEED (rows of a pass, with rs and its order).
+// phs: complex parameters, the phase of each row (then rows from site 0 only)
 nqs_status run_amplitudes(const nqs_ansatz* a, int precision, const uint64_t* m, int64_t R, double* lphi,
-                          int8_t* sphi, hipStream_t st, const Resume* rs = nullptr, int mode = PSI_PLAIN) {
+                          int8_t* sphi, hipStream_t st, const Resume* rs = nullptr, int mode = PSI_PLAIN,
+                          double* phs = nullptr) {
   if (mode != PSI_PLAIN && !rs) return fail(NQS_EINVAL, "resume state missing");
+  if (a->cplx) {
+    if (mode != PSI_PLAIN || !phs) return fail(NQS_EINVAL, "complex amplitudes: rows from site 0 with phases");
+    if (precision == NQS_F64) {
+      HIPCHK(launch_psi_f64(a->params(a->fwd64()), m, R, lphi, sphi, st, PsiStates<double>(), PSI_PLAIN, phs));
+    } else if (precision == NQS_F32) {
+      HIPCHK(launch_psi_f32(a->params(a->fwd32()), m, R, lphi, sphi, st, PsiStates<float>(), PSI_PLAIN, phs));
+    } else {
+      return fail(NQS_EUNSUPPORTED, "complex amplitudes run in FP64 or FP32");
+    }
+    return NQS_OK;
+  }
   if (a->tensor) {
     if (mode != PSI_PLAIN) return fail(NQS_EINVAL, "tensor-RNN rows are evaluated from site 0");
     if (precision == NQS_F64) {
@@ -1162,10 +1304,34 @@ nqs_status nqs_connected(nqs_ctx* ctx, const nqs_instance* inst, const uint64_t*
   return NQS_OK;
 }
 
+nqs_status nqs_logpsi_phase(nqs_ctx* ctx, const nqs_ansatz* ans, const uint64_t* samples, int64_t N,
+                            int32_t precision, double* logabs, double* phase, hipStream_t stream) {
+  if (!ctx || !ans || (!samples && N > 0) || N < 0) return fail(NQS_EINVAL, "bad arguments");
+  if (!ans->bound) return fail(NQS_EINVAL, "parameters not bound");
+  DeviceGuard g(ctx->device);
+  nqs_status s = check_samples(ctx, samples, N, ans->K, ans->na, ans->nb, stream);
+  if (s != NQS_OK) return s;
+  if (N == 0) return NQS_OK;
+  Scratch S(ctx);
+  double* lphi = S.get<double>(N);
+  int8_t* sphi = S.get<int8_t>(N);
+  double* phs = ans->cplx ? S.get<double>(N) : nullptr;
+  double* lf = ans->nh ? S.get<double>(N) : nullptr;
+  int8_t* sf = ans->nh ? S.get<int8_t>(N) : nullptr;
+  if (S.oom) return fail(NQS_ENOMEM, "workspace allocation failed");
+  if ((s = run_amplitudes(ans, precision, samples, N, lphi, sphi, stream, nullptr, PSI_PLAIN, phs)) != NQS_OK)
+    return s;
+  if (ans->nh) HIPCHK(launch_corr_direct(ans->corr(), samples, N, lf, sf, stream));
+  HIPCHK(launch_gather_logpsi_phase(N, lphi, sphi, phs, lf, sf, logabs, phase, stream));
+  HIPCHK(hipStreamSynchronize(stream));
+  return NQS_OK;
+}
+
 nqs_status nqs_logpsi(nqs_ctx* ctx, const nqs_ansatz* ans, const uint64_t* samples, int64_t N,
                       int32_t precision, double* logabs, int8_t* sign, hipStream_t stream) {
   if (!ctx || !ans || (!samples && N > 0) || N < 0) return fail(NQS_EINVAL, "bad arguments");
   if (!ans->bound) return fail(NQS_EINVAL, "parameters not bound");
+  if (ans->cplx) return fail(NQS_EINVAL, "complex parameters have a phase, not a sign: use nqs_logpsi_phase");
   DeviceGuard g(ctx->device);
   nqs_status s = check_samples(ctx, samples, N, ans->K, ans->na, ans->nb, stream);
   if (s != NQS_OK) return s;
@@ -1185,6 +1351,12 @@ nqs_status nqs_logpsi(nqs_ctx* ctx, const nqs_ansatz* ans, const uint64_t* sampl
 
 nqs_status nqs_logpsi_vjp(nqs_ctx* ctx, const nqs_ansatz* ans, const uint64_t* samples, int64_t N,
                           const double* cot, int32_t precision, double* grad, hipStream_t stream) {
+  return nqs_logpsi_vjp_phase(ctx, ans, samples, N, cot, nullptr, precision, grad, stream);
+}
+
+nqs_status nqs_logpsi_vjp_phase(nqs_ctx* ctx, const nqs_ansatz* ans, const uint64_t* samples, int64_t N,
+                                const double* cot, const double* cot_phase, int32_t precision, double* grad,
+                                hipStream_t stream) {
   if (!ctx || !ans || (!samples && N > 0) || N < 0 || (!cot && N > 0) || !grad)
     return fail(NQS_EINVAL, "bad arguments");
   if (!ans->bound) return fail(NQS_EINVAL, "parameters not bound");
@@ -1199,7 +1371,10 @@ nqs_status nqs_logpsi_vjp(nqs_ctx* ctx, const nqs_ansatz* ans, const uint64_t* s
   const int64_t per = std::max<int64_t>(64, (Rpad / 32 + 15) / 16 * 16);
   const int rows_per_split = int(per);
   const int nsplit = int((Rpad + per - 1) / per);
-  const int64_t np = ans->n_params;
+  // the adjoint accumulates over the kernels' (for complex parameters the
+  // realified) packed vector
+  const int64_t np = ans->nr_params;
+  const bool phase = ans->cplx && cot_phase != nullptr;
   const size_t hsz = size_t(ans->K) * Rpad * ans->chip;
   const size_t esz = precision == NQS_F64 ? 8 : 4;
   Scratch S(ctx);
@@ -1211,41 +1386,71 @@ nqs_status nqs_logpsi_vjp(nqs_ctx* ctx, const nqs_ansatz* ans, const uint64_t* s
   int8_t* sphi = S.get<int8_t>(N);
   double* gpart = S.get<double>(size_t(nsplit) * np);
   double* cotp = S.get<double>(Rpad);
+  double* cotq = phase ? S.get<double>(Rpad) : nullptr;
+  void* ab = phase ? S.get<unsigned char>(size_t(Rpad) * 2 * esz) : nullptr;
+  double* gr = ans->cplx ? S.get<double>(np) : nullptr;
   double* dth = ans->nh ? S.get<double>(size_t(N) * ans->nh) : nullptr;
   if (S.oom) return fail(NQS_ENOMEM, "workspace allocation failed");
   HIPCHK(hipMemsetAsync(dcarry, 0, hsz * esz, stream));
   HIPCHK(hipMemsetAsync(gpart, 0, sizeof(double) * nsplit * np, stream));
   HIPCHK(hipMemsetAsync(cotp, 0, sizeof(double) * Rpad, stream));
   HIPCHK(hipMemcpyAsync(cotp, cot, sizeof(double) * N, hipMemcpyDeviceToDevice, stream));
+  if (phase) {
+    HIPCHK(hipMemsetAsync(cotq, 0, sizeof(double) * Rpad, stream));
+    HIPCHK(hipMemcpyAsync(cotq, cot_phase, sizeof(double) * N, hipMemcpyDeviceToDevice, stream));
+  }
+  if (gr) HIPCHK(hipMemsetAsync(gr, 0, sizeof(double) * np, stream));
+  auto with_phase = [&](auto P, const auto& L) {
+    typedef typename std::remove_const<typename std::remove_pointer<decltype(L.w)>::type>::type T;
+    if (phase) {
+      P.w = L.w; P.c = L.c; P.w2 = L.w2; P.c2 = L.c2;
+      P.cotp = cotq;
+      P.ab = (T*)ab;
+      P.offW = ans->d_cx; P.offC = ans->d_cx + ans->K; P.offW2 = ans->d_cx + 2 * ans->K;
+      P.offC2 = ans->d_cx + 3 * ans->K;
+    }
+    return P;
+  };
   if (precision == NQS_F64) {
     PsiStates<double> X;
     X.hs = (double*)Hbuf;
     X.ns = Rpad;
     HIPCHK(launch_psi_f64(ans->params(ans->L64), samples, N, lphi, sphi, stream, X, PSI_STORE));
-    HIPCHK(launch_bwd_sweep_f64(ans->adj(ans->L64), samples, N, Rpad, cotp, (const double*)Hbuf,
-                                (double*)dcarry, (double*)Dc, (double*)Eeta, rows_per_split, nsplit, gpart,
-                                np, stream));
+    HIPCHK(launch_bwd_sweep_f64(with_phase(ans->adj(ans->L64), ans->L64), samples, N, Rpad, cotp,
+                                (const double*)Hbuf, (double*)dcarry, (double*)Dc, (double*)Eeta, rows_per_split,
+                                nsplit, gpart, np, stream));
   } else {
     PsiStates<float> X;
     X.hs = (float*)Hbuf;
     X.ns = Rpad;
     HIPCHK(launch_psi_f32(ans->params(ans->L32), samples, N, lphi, sphi, stream, X, PSI_STORE));
-    HIPCHK(launch_bwd_sweep_f32(ans->adj(ans->L32), samples, N, Rpad, cotp, (const float*)Hbuf,
-                                (float*)dcarry, (float*)Dc, (float*)Eeta, rows_per_split, nsplit, gpart,
-                                np, stream));
+    HIPCHK(launch_bwd_sweep_f32(with_phase(ans->adj(ans->L32), ans->L32), samples, N, Rpad, cotp,
+                                (const float*)Hbuf, (float*)dcarry, (float*)Dc, (float*)Eeta, rows_per_split,
+                                nsplit, gpart, np, stream));
   }
   if (ans->nh)
     HIPCHK(launch_corr_backward(ans->corr(), samples, N, cotp, dth, rows_per_split, nsplit, ans->offB,
                                 ans->offWc, ans->offW2, gpart, np, stream));
-  HIPCHK(launch_sum_parts(np, nsplit, gpart, grad, stream));
+  if (ans->cplx) {
+    HIPCHK(launch_sum_parts(np, nsplit, gpart, gr, stream));
+    HIPCHK(launch_cx_grad_map(ans->cxmap(), gr, grad, stream));
+  } else {
+    HIPCHK(launch_sum_parts(np, nsplit, gpart, grad, stream));
+  }
   HIPCHK(hipStreamSynchronize(stream));
   return NQS_OK;
 }
 
-nqs_status nqs_eloc(nqs_ctx* ctx, const nqs_instance* inst, const nqs_ansatz* ans,
-                    const uint64_t* samples, const double* counts, int64_t N,
-                    const nqs_eloc_opts* opts, double* eloc, double* etnum, double* logabs,
-                    int8_t* sign, double* fsq, nqs_eloc_stats* stats, hipStream_t stream) {
+}  // extern "C"
+
+namespace {
+
+// The local-energy pipeline.  cx: complex outputs (eloc_im, etnum_im, phase in
+// place of sign); required for an ansatz with complex parameters.
+nqs_status eloc_run(nqs_ctx* ctx, const nqs_instance* inst, const nqs_ansatz* ans, const uint64_t* samples,
+                    const double* counts, int64_t N, const nqs_eloc_opts* opts, double* eloc, double* eloc_im,
+                    double* etnum, double* etnum_im, double* logabs, int8_t* sign, double* phase, double* fsq,
+                    nqs_eloc_stats* stats, hipStream_t stream, bool cx) {
   if (!ctx || !inst || !ans || (!samples && N > 0) || N < 0) return fail(NQS_EINVAL, "bad arguments");
   nqs_status s = check_opts(opts);
   if (s != NQS_OK) return s;
@@ -1287,10 +1492,13 @@ nqs_status nqs_eloc(nqs_ctx* ctx, const nqs_instance* inst, const nqs_ansatz* an
   double* Etab = ans->ising ? S.get<double>(size_t(N) * 2 * ans->K * ans->nh) : nullptr;
   double* el = eloc ? eloc : S.get<double>(N);
   double* et = etnum ? etnum : S.get<double>(N);
+  double* el_i = cx ? (eloc_im ? eloc_im : S.get<double>(N)) : nullptr;
+  double* et_i = cx ? (etnum_im ? etnum_im : S.get<double>(N)) : nullptr;
+  double* phs = ans->cplx ? S.get<double>(cap_used) : nullptr;
   double* f2 = fsq ? fsq : S.get<double>(N);
   double* sums = S.get<double>(8);
   const int K = ans->K;
-  const bool resume = resumes(*opts) && !ans->tensor && cap_used < (int64_t(1) << 31);
+  const bool resume = resumes(*opts) && !ans->tensor && !ans->cplx && cap_used < (int64_t(1) << 31);
   Resume rs;
   double* lphi_s = nullptr;
   int8_t* sphi_s = nullptr;
@@ -1434,7 +1642,9 @@ nqs_status nqs_eloc(nqs_ctx* ctx, const nqs_instance* inst, const nqs_ansatz* an
       }
     } else {
       if (timing) HIPCHK(hipEventRecord(kq[0], stream));
-      if ((s = run_amplitudes(ans, opts->precision, P.rows.m, Rp, lphi, sphi, stream)) != NQS_OK) return s;
+      if ((s = run_amplitudes(ans, opts->precision, P.rows.m, Rp, lphi, sphi, stream, nullptr, PSI_PLAIN, phs)) !=
+          NQS_OK)
+        return s;
       if (timing) HIPCHK(hipEventRecord(kq[1], stream));
       site_rows += Rp * K;
       psi_flops += double(Rp) * tail_flops[0];
@@ -1443,8 +1653,12 @@ nqs_status nqs_eloc(nqs_ctx* ctx, const nqs_instance* inst, const nqs_ansatz* an
     if (ans->nh)
       HIPCHK(launch_corr_rows(ans->corr(), P.rows.m, P.rows.owner, samples, theta, Etab, Rp, opts->precision, lf,
                               sf, stream));
-    HIPCHK(launch_reduce(n0, n1, P.rowptr, P.rowptr_host[n0], P.rows.coef, lphi, sphi, lf, sf, P.hdiag, el, et,
-                         logabs, sign, f2, stream));
+    if (cx)
+      HIPCHK(launch_reduce_cx(n0, n1, P.rowptr, P.rowptr_host[n0], P.rows.coef, lphi, sphi, phs, lf, sf, P.hdiag,
+                              el, el_i, et, et_i, logabs, phase, f2, stream));
+    else
+      HIPCHK(launch_reduce(n0, n1, P.rowptr, P.rowptr_host[n0], P.rows.coef, lphi, sphi, lf, sf, P.hdiag, el, et,
+                           logabs, sign, f2, stream));
     if (timing) {
       hipEvent_t done;
       HIPCHK(hipEventCreate(&done));
@@ -1458,7 +1672,7 @@ nqs_status nqs_eloc(nqs_ctx* ctx, const nqs_instance* inst, const nqs_ansatz* an
       (void)hipEventDestroy(done);
     }
   }
-  HIPCHK(launch_batch_sums(N, counts, el, et, f2, sums, stream));
+  HIPCHK(launch_batch_sums(N, counts, el, et, f2, sums, stream, el_i, et_i));
   double hs[8] = {0};
   if (stats) HIPCHK(hipMemcpyAsync(hs, sums, sizeof hs, hipMemcpyDeviceToHost, stream));
   HIPCHK(hipStreamSynchronize(stream));
@@ -1486,8 +1700,32 @@ nqs_status nqs_eloc(nqs_ctx* ctx, const nqs_instance* inst, const nqs_ansatz* an
     stats->n_site_rows = site_rows;
     stats->ms_psi = ms_psi;
     stats->psi_flops = psi_flops;
+    stats->E_im = hs[7];
   }
   return NQS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+nqs_status nqs_eloc(nqs_ctx* ctx, const nqs_instance* inst, const nqs_ansatz* ans,
+                    const uint64_t* samples, const double* counts, int64_t N,
+                    const nqs_eloc_opts* opts, double* eloc, double* etnum, double* logabs,
+                    int8_t* sign, double* fsq, nqs_eloc_stats* stats, hipStream_t stream) {
+  if (ans && ans->cplx)
+    return fail(NQS_EINVAL, "complex parameters give complex local energies: use nqs_eloc_complex");
+  return eloc_run(ctx, inst, ans, samples, counts, N, opts, eloc, nullptr, etnum, nullptr, logabs, sign, nullptr, fsq,
+                  stats, stream, false);
+}
+
+nqs_status nqs_eloc_complex(nqs_ctx* ctx, const nqs_instance* inst, const nqs_ansatz* ans,
+                            const uint64_t* samples, const double* counts, int64_t N,
+                            const nqs_eloc_opts* opts, double* eloc_re, double* eloc_im, double* etnum_re,
+                            double* etnum_im, double* logabs, double* phase, double* fsq,
+                            nqs_eloc_stats* stats, hipStream_t stream) {
+  return eloc_run(ctx, inst, ans, samples, counts, N, opts, eloc_re, eloc_im, etnum_re, etnum_im, logabs, nullptr,
+                  phase, fsq, stats, stream, true);
 }
 
 namespace {
@@ -1546,6 +1784,8 @@ nqs_status nqs_sample(nqs_ctx* ctx, const nqs_ansatz* ans, int64_t n_draws, uint
   if (!ans->bound) return fail(NQS_EINVAL, "parameters not bound");
   if (precision != NQS_F64 && precision != NQS_F32)
     return fail(NQS_EUNSUPPORTED, "sampling runs in FP64 or FP32");
+  if (ans->cplx && sign)
+    return fail(NQS_EINVAL, "complex parameters have a phase, not a sign: pass sign = NULL (nqs_logpsi_phase)");
   const int64_t chunk = max_draws_per_pass > 0 && max_draws_per_pass < n_draws ? max_draws_per_pass : n_draws;
   constexpr int64_t kMaxSort = (int64_t(1) << 31) - 1;   // hipCUB item count
   if (chunk > kMaxSort) return fail(NQS_EUNSUPPORTED, "more than 2^31 - 1 draws in one pass");
@@ -1746,6 +1986,8 @@ nqs_status nqs_vmc_step(nqs_ctx* ctx, const nqs_instance* inst, nqs_ansatz* ans,
   double* etn = S.get<double>(D);
   double* f2 = S.get<double>(D);
   double* cot = S.get<double>(D);
+  double* etn_i = ans->cplx ? S.get<double>(D) : nullptr;
+  double* cotq = ans->cplx ? S.get<double>(D) : nullptr;
   double* gbuf = grad ? grad : S.get<double>(np);
   double* red = S.get<double>(4);
   if (S.oom) return fail(NQS_ENOMEM, "workspace allocation failed");
@@ -1760,14 +2002,21 @@ nqs_status nqs_vmc_step(nqs_ctx* ctx, const nqs_instance* inst, nqs_ansatz* ans,
   // 2. semi-stochastic local energies of the unique samples, weighted by counts
   const auto t1 = now();
   nqs_eloc_stats es;
-  if ((st = nqs_eloc(ctx, inst, ans, smp, cd, U, &opts->eloc, nullptr, etn, nullptr, nullptr, f2, &es, stream)) !=
-      NQS_OK)
-    return st;
-  // 3. the reweighted gradient (Eq. (19)) as the VJP of ln|Psi| with cotangent cot
+  if (ans->cplx)
+    st = nqs_eloc_complex(ctx, inst, ans, smp, cd, U, &opts->eloc, nullptr, nullptr, etn, etn_i, nullptr, nullptr, f2,
+                          &es, stream);
+  else
+    st = nqs_eloc(ctx, inst, ans, smp, cd, U, &opts->eloc, nullptr, etn, nullptr, nullptr, f2, &es, stream);
+  if (st != NQS_OK) return st;
+  // 3. the reweighted gradient (Eq. (19)) as the VJP of ln|Psi| with cotangent
+  // cot (and of the phase with cotq for complex parameters)
   const auto t2 = now();
-  HIPCHK(launch_vmc_cotangent(U, cd, etn, f2, cot, red, stream));
+  if (ans->cplx)
+    HIPCHK(launch_vmc_cotangent_cx(U, cd, etn, etn_i, f2, cot, cotq, red, stream));
+  else
+    HIPCHK(launch_vmc_cotangent(U, cd, etn, f2, cot, red, stream));
   HIPCHK(hipMemsetAsync(gbuf, 0, sizeof(double) * np, stream));
-  if ((st = nqs_logpsi_vjp(ctx, ans, smp, U, cot, low, gbuf, stream)) != NQS_OK) return st;
+  if ((st = nqs_logpsi_vjp_phase(ctx, ans, smp, U, cot, cotq, low, gbuf, stream)) != NQS_OK) return st;
   // 4. AdamW on the packed parameters, then the kernels' layouts are rebuilt
   const auto t3 = now();
   HIPCHK(launch_sumsq(np, gbuf, red + 2, stream));

@@ -48,6 +48,30 @@ __global__ __launch_bounds__(kBlock) void k_vmc_cotangent(int64_t N, const doubl
   }
 }
 
+// complex parameters: E from Re Etilde_num, cot from Re, cotp_n =
+// 2 c_n Im Etilde_num(n) / S (the phase cotangent of 2 Re <(E_loc - E)^* d ln Psi>)
+__global__ __launch_bounds__(kBlock) void k_vmc_cotangent_cx(int64_t N, const double* c, const double* etnum,
+                                                             const double* etnum_im, const double* fsq,
+                                                             double* cot, double* cotp, double* out) {
+  __shared__ double sh[kBlock];
+  double a = 0.0, b = 0.0;
+  for (int64_t n = threadIdx.x; n < N; n += kBlock) {
+    a += c[n] * fsq[n];
+    b += c[n] * etnum[n];
+  }
+  const double S = block_sum(a, sh);
+  const double T = block_sum(b, sh);
+  const double E = T / S;
+  for (int64_t n = threadIdx.x; n < N; n += kBlock) {
+    cot[n] = 2.0 * c[n] * (etnum[n] - fsq[n] * E) / S;
+    cotp[n] = 2.0 * c[n] * etnum_im[n] / S;
+  }
+  if (threadIdx.x == 0) {
+    out[0] = E;
+    out[1] = S;
+  }
+}
+
 // AdamW with decoupled weight decay (the formulation of PyTorch's AdamW)
 __global__ void k_adamw(int64_t n, double* p, const double* g, double* m, double* v, double lr, double b1, double b2,
                         double eps, double wd, double c1, double c2) {
@@ -86,6 +110,13 @@ hipError_t launch_vmc_cotangent(int64_t N, const double* c, const double* etnum,
                                 double* out, hipStream_t st) {
   if (N <= 0) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_vmc_cotangent, dim3(1), dim3(kBlock), 0, st, N, c, etnum, fsq, cot, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_vmc_cotangent_cx(int64_t N, const double* c, const double* etnum, const double* etnum_im,
+                                   const double* fsq, double* cot, double* cotp, double* out, hipStream_t st) {
+  if (N <= 0) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_vmc_cotangent_cx, dim3(1), dim3(kBlock), 0, st, N, c, etnum, etnum_im, fsq, cot, cotp, out);
   return hipGetLastError();
 }
 

@@ -37,6 +37,7 @@ class ElocOpts(C.Structure):
 
 ELOC_FULL_RECOMPUTE = 1
 ANSATZ_TENSOR = 0x10
+ANSATZ_COMPLEX = 0x20
 
 
 class ElocStats(C.Structure):
@@ -45,7 +46,8 @@ class ElocStats(C.Structure):
                 ("sum_c", C.c_double), ("B", C.c_double), ("E", C.c_double), ("var", C.c_double),
                 ("ms_enumerate", C.c_double), ("ms_draw", C.c_double), ("ms_rows", C.c_double),
                 ("ms_amplitude", C.c_double), ("ms_reduce", C.c_double), ("n_passes", C.c_int64),
-                ("n_site_rows", C.c_int64), ("ms_psi", C.c_double), ("psi_flops", C.c_double)]
+                ("n_site_rows", C.c_int64), ("ms_psi", C.c_double), ("psi_flops", C.c_double),
+                ("E_im", C.c_double)]
 
     def to_dict(self) -> Dict[str, float]:
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -101,6 +103,10 @@ def lib():
     L.nqs_ansatz_bind_params.argtypes = [_p, _p, _p]
     L.nqs_logpsi.argtypes = [_p, _p, _p, C.c_int64, C.c_int32, _p, _p, _p]
     L.nqs_logpsi_vjp.argtypes = [_p, _p, _p, C.c_int64, _p, C.c_int32, _p, _p]
+    L.nqs_logpsi_phase.argtypes = [_p, _p, _p, C.c_int64, C.c_int32, _p, _p, _p]
+    L.nqs_logpsi_vjp_phase.argtypes = [_p, _p, _p, C.c_int64, _p, _p, C.c_int32, _p, _p]
+    L.nqs_eloc_complex.argtypes = [_p, _p, _p, _p, _p, C.c_int64, C.POINTER(ElocOpts), _p, _p, _p, _p, _p, _p, _p,
+                                   C.POINTER(ElocStats), _p]
     L.nqs_eloc.argtypes = [_p, _p, _p, _p, _p, C.c_int64, C.POINTER(ElocOpts), _p, _p, _p, _p, _p,
                            C.POINTER(ElocStats), _p]
     L.nqs_rows.argtypes = [_p, _p, _p, C.c_int64, C.POINTER(ElocOpts), C.c_int64, _p, _p, _p, _p, _p, _p,
@@ -224,7 +230,7 @@ class Ansatz:
     bound from a device tensor."""
 
     def __init__(self, ctx: Context, K: int, n_alpha: int, n_beta: int, chi: int, parent_ptr, parent_idx,
-                 n_hidden: int = 0, ising: bool = False, tensor: bool = False):
+                 n_hidden: int = 0, ising: bool = False, tensor: bool = False, cplx: bool = False):
         pp = np.ascontiguousarray(parent_ptr, dtype=np.int32)
         pi = np.ascontiguousarray(parent_idx, dtype=np.int32)
         if pi.size == 0:
@@ -232,12 +238,14 @@ class Ansatz:
         out = _p()
         check(lib().nqs_ansatz_create(ctx.h, K, n_alpha, n_beta, chi, pp.ctypes.data_as(_p),
                                       pi.ctypes.data_as(_p), n_hidden,
-                                      (1 if ising else 0) | (ANSATZ_TENSOR if tensor else 0), C.byref(out)))
+                                      (1 if ising else 0) | (ANSATZ_TENSOR if tensor else 0) |
+                                      (ANSATZ_COMPLEX if cplx else 0), C.byref(out)))
         self.h = out
         self.ctx = ctx
         self.K, self.n_alpha, self.n_beta, self.chi, self.n_hidden = K, n_alpha, n_beta, chi, n_hidden
         self.ising = bool(ising) and n_hidden > 0
         self.tensor = bool(tensor)
+        self.cplx = bool(cplx)
         self.n_params = int(lib().nqs_ansatz_n_params(out))
 
     def bind(self, params):
@@ -257,14 +265,28 @@ class Ansatz:
         check(lib().nqs_logpsi(self.ctx.h, self.h, _ptr(s), N, pr, _ptr(la), _ptr(sg), _p(_stream())))
         return la, sg
 
-    def vjp(self, samples, cot, precision="f64", grad: Optional[torch.Tensor] = None):
+    def logpsi_phase(self, samples, precision="f64"):
+        """(log|Psi|, phase of Psi in [-pi, pi]) as device float64 tensors."""
+        s = _samples(samples)
+        N = s.shape[0]
+        la = torch.empty(N, dtype=torch.float64, device=s.device)
+        ph = torch.empty(N, dtype=torch.float64, device=s.device)
+        pr = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+        check(lib().nqs_logpsi_phase(self.ctx.h, self.h, _ptr(s), N, pr, _ptr(la), _ptr(ph), _p(_stream())))
+        return la, ph
+
+    def vjp(self, samples, cot, precision="f64", grad: Optional[torch.Tensor] = None,
+            cot_phase: Optional[torch.Tensor] = None):
+        """grad += sum_n cot[n] d log|Psi(n)| (+ cot_phase[n] d phase(n)) / d theta."""
         s = _samples(samples)
         N = s.shape[0]
         c = cot.to(dtype=torch.float64, device=s.device).contiguous()
+        cp = None if cot_phase is None else cot_phase.to(dtype=torch.float64, device=s.device).contiguous()
         if grad is None:
             grad = torch.zeros(self.n_params, dtype=torch.float64, device=s.device)
         pr = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
-        check(lib().nqs_logpsi_vjp(self.ctx.h, self.h, _ptr(s), N, _ptr(c), pr, _ptr(grad), _p(_stream())))
+        check(lib().nqs_logpsi_vjp_phase(self.ctx.h, self.h, _ptr(s), N, _ptr(c), _ptr(cp), pr, _ptr(grad),
+                                         _p(_stream())))
         return grad
 
     def sample(self, n_draws: int, seed: int = 0, draw_base: int = 0, precision="f64",
@@ -279,14 +301,15 @@ class Ansatz:
         out = torch.empty((max(cap, 1), 2), dtype=torch.int64, device=dev)
         cnt = torch.empty(max(cap, 1), dtype=torch.int64, device=dev)
         la = torch.empty(max(cap, 1), dtype=torch.float64, device=dev)
-        sg = torch.empty(max(cap, 1), dtype=torch.int8, device=dev)
+        # complex parameters: Phi has a phase, not a sign (logpsi_phase gives it)
+        sg = None if self.cplx else torch.empty(max(cap, 1), dtype=torch.int8, device=dev)
         nu = C.c_int64(0)
         pr = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
         check(lib().nqs_sample(self.ctx.h, self.h, n_draws, int(seed) & 0xFFFFFFFFFFFFFFFF, int(draw_base), pr,
                                int(max_draws_per_pass), cap, _ptr(out), _ptr(cnt), _ptr(la), _ptr(sg), C.byref(nu),
                                _p(_stream())))
         u = min(int(nu.value), cap)
-        return out[:u], cnt[:u], la[:u], sg[:u], int(nu.value)
+        return out[:u], cnt[:u], la[:u], (None if sg is None else sg[:u]), int(nu.value)
 
     def close(self):
         if self.h:
@@ -321,6 +344,27 @@ def eloc(ctx: Context, inst: Instance, ans: Ansatz, samples, counts: Optional[to
     check(lib().nqs_eloc(ctx.h, inst.h, ans.h, _ptr(s), _ptr(c), N, C.byref(o), _ptr(out["eloc"]),
                          _ptr(out["etnum"]), _ptr(out["logabs"]), _ptr(out["sign"]), _ptr(out["fsq"]),
                          C.byref(st) if want_stats else None, _p(_stream())))
+    return out, (st.to_dict() if want_stats else None)
+
+
+def eloc_complex(ctx: Context, inst: Instance, ans: Ansatz, samples, counts: Optional[torch.Tensor] = None,
+                 eps: float = 0.0, n_eps: int = 0, precision="f64", seed: int = 0, stream_id: int = 0,
+                 sample_base: int = 0, want_stats: bool = True, max_rows_per_pass: int = 0):
+    """Local energies with complex amplitudes (nqs_eloc_complex): eloc and
+    etnum as complex128 device tensors, logabs, phase, fsq; and the stats dict."""
+    s = _samples(samples)
+    N = s.shape[0]
+    dev = s.device
+    f = {k: torch.empty(N, dtype=torch.float64, device=dev)
+         for k in ("er", "ei", "tr", "ti", "logabs", "phase", "fsq")}
+    c = None if counts is None else counts.to(dtype=torch.float64, device=dev).contiguous()
+    o = opts(eps, n_eps, precision, seed, stream_id, sample_base, max_rows_per_pass, True)
+    st = ElocStats()
+    check(lib().nqs_eloc_complex(ctx.h, inst.h, ans.h, _ptr(s), _ptr(c), N, C.byref(o), _ptr(f["er"]),
+                                 _ptr(f["ei"]), _ptr(f["tr"]), _ptr(f["ti"]), _ptr(f["logabs"]), _ptr(f["phase"]),
+                                 _ptr(f["fsq"]), C.byref(st) if want_stats else None, _p(_stream())))
+    out = dict(eloc=torch.complex(f["er"], f["ei"]), etnum=torch.complex(f["tr"], f["ti"]), logabs=f["logabs"],
+               phase=f["phase"], fsq=f["fsq"])
     return out, (st.to_dict() if want_stats else None)
 
 

@@ -1,0 +1,233 @@
+"""GPU path with complex parameters (Sec. 2.1: h in C^chi, P = h^dagger eta h,
+phase sum_i arg(w_i^T h_i + c_i)) against the FP64 oracle: log|Psi| and phase
+of whole sectors and sample sets, complex local energies, the gradient of
+log|Psi| and of the phase, exact draws (bit-exact unique draws and counts in
+FP64), one VMC step, FP32 within stated bounds, and the refused forms.
+Phases are compared modulo 2 pi."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2507_19276_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def nqs():
+    from paper_2507_19276_amd import nqs as N
+    N.lib()
+    return N
+
+
+@pytest.fixture(scope="module")
+def ctx(nqs):
+    c = nqs.Context(0)
+    yield c
+    c.close()
+
+
+_cache = {}
+
+
+def setup(nqs, ctx, name, n=None):
+    key = (name, n)
+    if key not in _cache:
+        w = W.make_workload(name, n_samples=n)
+        assert w.cplx
+        inst = nqs.Instance(ctx, w.K, w.n_alpha, w.n_beta, w.h, w.eri, w.e_core)
+        ans = nqs.Ansatz(ctx, w.K, w.n_alpha, w.n_beta, w.chi, w.parent_ptr, w.parent_idx, w.n_hidden, cplx=True)
+        assert ans.n_params == w.params.size
+        ans.bind(w.params)
+        _cache[key] = (w, inst, ans)
+    return _cache[key]
+
+
+def dphase(a, b):
+    return np.abs(oracle.wrap_phase(np.asarray(a) - np.asarray(b)))
+
+
+def ref_amps(w, samples):
+    return oracle.amplitudes(w.K, w.chi, w.n_alpha, w.n_beta, w.parent_ptr, w.parent_idx, w.n_hidden, w.params,
+                             samples, cplx=True)
+
+
+def ref_eloc(w, samples=None, sample_base=0):
+    return oracle.eloc(w.K, w.n_alpha, w.n_beta, w.h, w.eri, w.chi, w.parent_ptr, w.parent_idx, w.n_hidden, w.params,
+                       w.samples if samples is None else samples, eps=w.eps, n_eps=w.n_eps, seed=w.seed, stream=1,
+                       sample_base=sample_base, cplx=True)
+
+
+def rel_err(got, ref):
+    tau = 1e-3 * np.sqrt(np.mean(np.abs(ref) ** 2))
+    return np.abs(got - ref) / np.maximum(np.abs(ref), tau)
+
+
+@pytest.mark.parametrize("name,n", [("c1c", None), ("c2c", 64)])
+def test_logpsi_phase_f64(nqs, ctx, name, n):
+    w, inst, ans = setup(nqs, ctx, name, n)
+    samples = W.all_onvs(w.K, w.n_alpha, w.n_beta) if name == "c1c" else w.samples
+    la, ph = ans.logpsi_phase(samples, "f64")
+    ref = ref_amps(w, samples)
+    assert np.abs(la.cpu().numpy() - ref["logabs"]).max() < 1e-12
+    assert dphase(ph.cpu().numpy(), ref["phase"]).max() < 1e-11
+    if name == "c1c":
+        assert abs(np.exp(2 * (la.cpu().numpy() - ref["lf"])).sum() - 1.0) < 1e-12
+
+
+def test_logpsi_phase_f32_bound(nqs, ctx):
+    """FP32 contractions and phase factors, FP64 logs and arg: stated bound
+    |d log|Psi|| <= 5e-5 and |d phase| <= 1e-4 rad (K = 20 sites of FP32
+    rounding, a phase factor near zero magnifying its own rounding; measured
+    8e-7 and 1.1e-5 at most over 256 samples)."""
+    w, inst, ans = setup(nqs, ctx, "c2c", 256)
+    la, ph = ans.logpsi_phase(w.samples, "f32")
+    ref = ref_amps(w, w.samples)
+    e_la = np.abs(la.cpu().numpy() - ref["logabs"])
+    e_ph = dphase(ph.cpu().numpy(), ref["phase"])
+    print("f32 complex: |d log| max %.2e, |d phase| max %.2e median %.2e" % (e_la.max(), e_ph.max(), np.median(e_ph)))
+    assert e_la.max() < 5e-5 and e_ph.max() < 1e-4
+
+
+@pytest.mark.parametrize("name,n", [("c1c", None), ("c2c", 24)])
+def test_eloc_f64(nqs, ctx, name, n):
+    w, inst, ans = setup(nqs, ctx, name, n)
+    out, st = nqs.eloc_complex(ctx, inst, ans, w.samples, eps=w.eps, n_eps=w.n_eps, precision="f64", seed=w.seed,
+                               stream_id=1)
+    ref = ref_eloc(w)
+    assert rel_err(out["eloc"].cpu().numpy(), ref["eloc"]).max() <= 1e-10
+    assert rel_err(out["etnum"].cpu().numpy(), ref["etnum"]).max() <= 1e-10
+    assert np.abs(out["logabs"].cpu().numpy() - ref["logabs"]).max() < 1e-12
+    assert dphase(out["phase"].cpu().numpy(), ref["phase"]).max() < 1e-11
+    assert np.abs(out["fsq"].cpu().numpy() - ref["fsq"]).max() <= 1e-14 * np.abs(ref["fsq"]).max()
+    assert st["n_rows"] == w.n_samples + ref["n_det"].sum() + ref["n_uniq"].sum()
+    E = ref["etnum"].real.sum() / ref["fsq"].sum()
+    E_im = ref["etnum"].imag.sum() / ref["fsq"].sum()
+    assert abs(st["E"] - E) <= 1e-10 * abs(E) and abs(st["E_im"] - E_im) <= 1e-10 * abs(E)
+
+
+def test_eloc_f32_bound(nqs, ctx):
+    """FP32 amplitudes: each ratio carries ~1e-6 relative error, and a
+    cancelling E_loc magnifies it (as for real parameters).  Stated bound:
+    median <= 1e-5, p90 <= 5e-5, max <= 5e-2 relative, the batch energy within
+    0.01 of its sampling standard error (measured: median 2.6e-6, p90 4.6e-6,
+    max 5e-5, batch energy 1e-6 of the SE)."""
+    w, inst, ans = setup(nqs, ctx, "c2c", 48)
+    out, st = nqs.eloc_complex(ctx, inst, ans, w.samples, eps=w.eps, n_eps=w.n_eps, precision="f32", seed=w.seed,
+                               stream_id=1)
+    ref = ref_eloc(w)
+    e = rel_err(out["eloc"].cpu().numpy(), ref["eloc"])
+    print("f32 c2c rel err p50 %.2e p90 %.2e max %.2e" % (np.median(e), np.quantile(e, 0.9), e.max()))
+    assert np.median(e) <= 1e-5 and np.quantile(e, 0.9) <= 5e-5 and e.max() <= 5e-2
+    E = ref["etnum"].real.sum() / ref["fsq"].sum()
+    se = np.sqrt((ref["fsq"] * np.abs(ref["eloc"] - E) ** 2).sum() / ref["fsq"].sum() / w.n_samples)
+    print("batch energy error %.3e, SE %.3e" % (abs(st["E"] - E), se))
+    assert abs(st["E"] - E) <= 0.01 * se
+
+
+def test_real_ansatz_through_the_complex_entry(nqs, ctx):
+    """A real ansatz through nqs_eloc_complex: the real local energies bit for
+    bit, zero imaginary parts, phases 0 or pi by the sign."""
+    w = W.make_workload("c2", n_samples=64)
+    inst = nqs.Instance(ctx, w.K, w.n_alpha, w.n_beta, w.h, w.eri, w.e_core)
+    ans = nqs.Ansatz(ctx, w.K, w.n_alpha, w.n_beta, w.chi, w.parent_ptr, w.parent_idx, w.n_hidden)
+    ans.bind(w.params)
+    kw = dict(eps=w.eps, n_eps=w.n_eps, precision="f64", seed=w.seed, stream_id=1)
+    a, _ = nqs.eloc(ctx, inst, ans, w.samples, **kw)
+    b, st = nqs.eloc_complex(ctx, inst, ans, w.samples, **kw)
+    # the same rows and amplitudes; the sums may round differently in the last
+    # bit (the real reduction may fuse the sign-weighted product into its sum)
+    for k in ("eloc", "etnum"):
+        x, y = a[k].cpu().numpy(), b[k].real.cpu().numpy()
+        assert np.abs(x - y).max() <= 1e-14 * np.abs(x).max()
+    assert torch.count_nonzero(b["eloc"].imag).item() == 0 and st["E_im"] == 0.0
+    assert torch.equal(a["logabs"], b["logabs"])
+    ph = b["phase"].cpu().numpy()
+    assert np.array_equal(ph, np.where(a["sign"].cpu().numpy() < 0, np.pi, 0.0))
+
+
+@pytest.mark.parametrize("prec,tol", [("f64", 1e-10), ("f32", 1e-4)])
+def test_vjp_with_phase(nqs, ctx, prec, tol):
+    """grad of sum (ga log|Psi| + gp phase) against the oracle: FP64 at 1e-10 of
+    the largest entry; FP32 at 1e-4 of it (K = 6 sites, FP32 recompute and
+    cotangents, FP64 sums over rows; measured 6e-7)."""
+    w, inst, ans = setup(nqs, ctx, "c1c", 40)
+    rng = np.random.default_rng(4)
+    ga, gp = rng.standard_normal(w.n_samples), rng.standard_normal(w.n_samples)
+    g = ans.vjp(w.samples, torch.from_numpy(ga), prec, cot_phase=torch.from_numpy(gp)).cpu().numpy()
+    ref = oracle.grad(w.K, w.chi, w.n_alpha, w.n_beta, w.parent_ptr, w.parent_idx, w.n_hidden, w.params, w.samples,
+                      ga, cplx=True, g_phase=gp)
+    err = np.abs(g - ref).max() / np.abs(ref).max()
+    print(f"{prec} complex vjp: max error {err:.2e} of the largest entry")
+    assert err <= tol
+    # without the phase cotangent: the gradient of log|Psi| alone
+    g0 = ans.vjp(w.samples, torch.from_numpy(ga), prec).cpu().numpy()
+    ref0 = oracle.grad(w.K, w.chi, w.n_alpha, w.n_beta, w.parent_ptr, w.parent_idx, w.n_hidden, w.params, w.samples,
+                       ga, cplx=True)
+    assert np.abs(g0 - ref0).max() <= tol * np.abs(ref0).max()
+
+
+def test_sampler_f64_matches_oracle(nqs, ctx):
+    w, inst, ans = setup(nqs, ctx, "c2c", 16)
+    s, c, la, sg, nu = ans.sample(3000, seed=123, draw_base=7, precision="f64")
+    assert sg is None
+    ru, rc = oracle.sample_unique(w.K, w.chi, w.n_alpha, w.n_beta, w.parent_ptr, w.parent_idx, w.params, 123, 3000,
+                                  draw_base=7, cplx=True)
+    assert nu == len(ru)
+    assert np.array_equal(s.cpu().numpy().view(np.uint64), ru)
+    assert np.array_equal(c.cpu().numpy(), rc)
+    assert np.abs(la.cpu().numpy() - ref_amps(w, ru)["lphi"]).max() < 1e-12
+
+
+@pytest.mark.parametrize("name,n_draws", [("c1c", 2000), ("c2c", 96)])
+def test_vmc_step_matches_oracle_f64(nqs, ctx, name, n_draws):
+    w, inst, ans = setup(nqs, ctx, name, 16)
+    ans = nqs.Ansatz(ctx, w.K, w.n_alpha, w.n_beta, w.chi, w.parent_ptr, w.parent_idx, w.n_hidden, cplx=True)
+    ans.bind(w.params)
+    hp = dict(lr=2e-2, beta1=0.9, beta2=0.999, adam_eps=1e-8, weight_decay=1e-3)
+    p = torch.from_numpy(w.params.copy()).cuda()
+    m, v, g = torch.zeros_like(p), torch.zeros_like(p), torch.zeros_like(p)
+    st = nqs.vmc_step(ctx, inst, ans, p, m, v, 1, n_draws=n_draws, sample_seed=5, draw_base=0, eps=w.eps,
+                      n_eps=w.n_eps, precision="f64", seed=w.seed, stream_id=3, grad=g, **hp)
+    ref = oracle.vmc_step(w.K, w.n_alpha, w.n_beta, w.h, w.eri, w.chi, w.parent_ptr, w.parent_idx, w.n_hidden,
+                          w.params, np.zeros(w.params.size), np.zeros(w.params.size), 1, n_draws, 5, 0, eps=w.eps,
+                          n_eps=w.n_eps, eloc_seed=w.seed, stream=3, cplx=True, **hp)
+    assert st["n_unique"] == len(ref["samples"])
+    assert abs(st["E"] - ref["E"]) <= 1e-10 * max(1.0, abs(ref["E"]))
+    gg = g.cpu().numpy()
+    assert np.abs(gg - ref["grad"]).max() <= 1e-9 * np.abs(ref["grad"]).max() + 1e-12
+    assert np.abs(p.cpu().numpy() - ref["params"]).max() <= 1e-6 * hp["lr"]
+    # the step re-bound the ansatz
+    fresh = nqs.Ansatz(ctx, w.K, w.n_alpha, w.n_beta, w.chi, w.parent_ptr, w.parent_idx, w.n_hidden, cplx=True)
+    fresh.bind(p)
+    a1, p1 = ans.logpsi_phase(w.samples, "f64")
+    a2, p2 = fresh.logpsi_phase(w.samples, "f64")
+    assert torch.equal(a1, a2) and torch.equal(p1, p2)
+
+
+def test_full_size_sampled(nqs, ctx):
+    """4096 samples at once in FP32; 8 outputs checked one by one (the FP32
+    bound above)."""
+    w, inst, ans = setup(nqs, ctx, "c2c", None)
+    out, _ = nqs.eloc_complex(ctx, inst, ans, w.samples, eps=w.eps, n_eps=w.n_eps, precision="f32", seed=w.seed,
+                              stream_id=1)
+    el = out["eloc"].cpu().numpy()
+    tau = 1e-3 * np.sqrt(np.mean(np.abs(el) ** 2))
+    for k in np.random.default_rng(3).choice(w.n_samples, 8, replace=False):
+        ref = ref_eloc(w, w.samples[k:k + 1], sample_base=int(k))
+        assert abs(el[k] - ref["eloc"][0]) <= 5e-2 * max(abs(ref["eloc"][0]), tau), k
+
+
+def test_refused_forms(nqs, ctx):
+    w, inst, ans = setup(nqs, ctx, "c1c", 16)
+    with pytest.raises(nqs.NqsError):
+        ans.logpsi(w.samples, "f64")
+    with pytest.raises(nqs.NqsError):
+        ans.logpsi_phase(w.samples, "bf16")
+    with pytest.raises(nqs.NqsError):
+        nqs.eloc(ctx, inst, ans, w.samples)
+    with pytest.raises(nqs.NqsError):
+        nqs.Ansatz(ctx, w.K, w.n_alpha, w.n_beta, 33, w.parent_ptr, w.parent_idx, 0, cplx=True)
+    with pytest.raises(nqs.NqsError):
+        nqs.Ansatz(ctx, w.K, w.n_alpha, w.n_beta, 4, w.parent_ptr, w.parent_idx, 0, cplx=True, tensor=True)
