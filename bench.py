@@ -287,7 +287,7 @@ def run_next_bench(args):
         w = workloads.make_workload(name)
         inst = nqs.Instance(ctx, w.K, w.n_alpha, w.n_beta, w.h, w.eri, w.e_core)
         ans = nqs.Ansatz(ctx, w.K, w.n_alpha, w.n_beta, w.chi, w.parent_ptr, w.parent_idx, w.n_hidden,
-                         ising=w.ising, tensor=w.tensor)
+                         ising=w.ising, tensor=w.tensor, cplx=w.cplx)
         ans.bind(w.params)
         s = torch.from_numpy(w.samples.view(np.int64)).cuda().contiguous()
         return w, inst, ans, s
@@ -347,6 +347,32 @@ def run_next_bench(args):
         print(f"# tensor {prec}: {w.n_samples / dt:.0f} E_loc/s, row kernel {st['ms_psi']:.2f} ms, {fl:.2f} TFLOP/s",
               file=sys.stderr, flush=True)
     out["bdg_tensor_rnn_nnn_K20_chi16"] = tens
+    # complex parameters, chain chi=16 complex units (the realified 32-unit state on MFMA), 4096 samples
+    w, inst, ans, s = make("c2c")
+    cx = {}
+    for prec in ("f32", "f64"):
+        kw = dict(eps=w.eps, n_eps=w.n_eps, precision=prec, stream_id=0)
+        dt, (o, st) = timed(lambda: nqs.eloc_complex(ctx, inst, ans, s, seed=w.seed, **kw), 3)
+        fl = st["psi_flops"] / (st["ms_psi"] * 1e-3) / 1e12
+        cx[prec] = {"local_energies_per_s": w.n_samples / dt, "ms_per_step": dt * 1e3,
+                    "row_kernel_ms": st["ms_psi"], "site_rows": st["n_site_rows"], "E_im": st["E_im"],
+                    "roofline": {"bound": "mfma", "achieved": fl, "peak": PEAKS[prec], "unit": "TFLOP/s",
+                                 "frac": fl / PEAKS[prec], "flops_per_launch": st["psi_flops"],
+                                 "kernel": f"k_psi_mt<{'float' if prec == 'f32' else 'double'},32,...,CPLX>"}}
+        print(f"# complex {prec}: {w.n_samples / dt:.0f} E_loc/s, row kernel {st['ms_psi']:.2f} ms, "
+              f"{fl:.2f} TFLOP/s", file=sys.stderr, flush=True)
+    p = torch.from_numpy(w.params.copy()).cuda()
+    m, v = torch.zeros_like(p), torch.zeros_like(p)
+    steps = []
+    for k in range(1, 4):
+        t0 = time.perf_counter()
+        st = nqs.vmc_step(ctx, inst, ans, p, m, v, k, n_draws=4096, sample_seed=k, draw_base=4096 * k,
+                          eps=w.eps, n_eps=w.n_eps, precision="f32", seed=k, lr=1e-3)
+        steps.append((time.perf_counter() - t0, st))
+    cx["vmc_step_ms"] = float(np.mean([t for t, _ in steps[1:]])) * 1e3
+    cx["vmc_stage_ms"] = {k: steps[-1][1][k] for k in ("ms_sample", "ms_eloc", "ms_grad", "ms_update")}
+    out["complex_chain_K20_chi16"] = cx
+    print(f"# complex vmc step: {cx['vmc_step_ms']:.2f} ms", file=sys.stderr, flush=True)
     # one VMC step (4096 draws, FP32 path), chain chi=16
     w, inst, ans, s = make("c2")
     p = torch.from_numpy(w.params.copy()).cuda()
@@ -365,13 +391,14 @@ def run_next_bench(args):
                                        "E": [st["E"] for _, st in steps]}
     print(f"# vmc step: {dt * 1e3:.2f} ms", file=sys.stderr, flush=True)
     line = {
-        "metric": "next rows: exact sampling, Ising-RBM and BDG-TensorRNN local energies, VMC step",
+        "metric": "next rows: exact sampling, Ising-RBM, BDG-TensorRNN and complex-parameter local energies, "
+                  "VMC step",
         "value": out["sampler_chain_K20_chi16"]["f32"]["draws_per_s"],
         "unit": "draws/s (FP32 sampler; the other figures in the sub-objects)",
         "n_gpus": 1, "steps": 1, "warmup": 1, "ms_per_step": out["sampler_chain_K20_chi16"]["f32"]["ms"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": "chain K=20 10a+10b: c2 (chain chi=16), c2i (+Ising-RBM N_h=80), "
-                               "c2t (NN+NNN BDG-TensorRNN chi=16)"},
+                               "c2t (NN+NNN BDG-TensorRNN chi=16), c2c (chain, complex chi=16)"},
         **out,
     }
     print(json.dumps(line), flush=True)
@@ -393,7 +420,7 @@ def main():
                     help="HBM bytes per amplitude-kernel launch from rocprofv3 PMC counters")
     ap.add_argument("--serve", action="store_true")
     ap.add_argument("--next", action="store_true",
-                    help="time the sampler, the Ising-RBM and BDG-TensorRNN paths and one VMC step")
+                    help="time the sampler, the Ising-RBM, BDG-TensorRNN and complex paths and one VMC step")
     ap.add_argument("--requests", type=int, default=500)
     ap.add_argument("--load", type=float, default=0.8)
     ap.add_argument("--slots", type=int, default=4)

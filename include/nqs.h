@@ -181,10 +181,10 @@ nqs_status nqs_connected(nqs_ctx* ctx, const nqs_instance* inst, const uint64_t*
  * 4 x chi x chi pairs), v (4 x chi pairs), eta (chi reals), w (chi pairs),
  * c (one pair); the correlator block after the sites stays real (its sign
  * adds 0 or pi to the phase).  chi <= 32.  The amplitudes run in FP64 and
- * FP32 with the rows evaluated from site 0 (the realified form: a real 2chi
- * state with block matrices [[Re M, -Im M], [Im M, Re M]] on the same MFMA
- * kernels, and the phase factors multiplied per row); NQS_EUNSUPPORTED for
- * BF16; not combined with NQS_ANSATZ_TENSOR.  Signs are replaced by phases:
+ * FP32 (the realified form: a real 2chi state with block matrices
+ * [[Re M, -Im M], [Im M, Re M]] on the same MFMA kernels, the phase factors
+ * multiplied per row and carried with the resumed rows' prefix states);
+ * NQS_EUNSUPPORTED for BF16; not combined with NQS_ANSATZ_TENSOR.  Signs are replaced by phases:
  * nqs_logpsi, nqs_eloc and the sign output of nqs_sample refuse a complex
  * ansatz (EINVAL); use nqs_logpsi_phase, nqs_eloc_complex and
  * nqs_logpsi_vjp_phase. */
@@ -297,8 +297,7 @@ nqs_status nqs_eloc(nqs_ctx* ctx, const nqs_instance* inst, const nqs_ansatz* an
  * double[N], nullable.  The batch sums use Re Etilde_num for E, |E_loc - E|^2
  * for the variance, and stats->E_im receives sum c Im Etilde_num / sum c |f|^2
  * (zero in expectation, H being Hermitian).  Complex amplitudes run in FP64
- * or FP32 with every row evaluated from site 0 (NQS_ELOC_FULL_RECOMPUTE
- * implied). */
+ * or FP32; rows resume as in nqs_eloc, bit-identical to NQS_ELOC_FULL_RECOMPUTE. */
 nqs_status nqs_eloc_complex(nqs_ctx* ctx, const nqs_instance* inst, const nqs_ansatz* ans,
                             const uint64_t* samples, const double* counts, int64_t N,
                             const nqs_eloc_opts* opts, double* eloc_re, double* eloc_im, double* etnum_re,

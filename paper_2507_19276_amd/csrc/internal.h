@@ -224,6 +224,7 @@ struct PsiStates {
   T* pm = nullptr;               // [K+1][ns] product mantissa before site i
   int32_t* pe = nullptr;         // [K+1][ns] product exponent
   int8_t* pg = nullptr;          // [K+1][ns] sign
+  T* pz = nullptr;               // complex parameters: [K+1][ns][2] phase-factor product before site i
   int64_t ns = 0;                // sample stride
   const int32_t* perm = nullptr; // SEED: [R] row of each position
   const uint8_t* t0 = nullptr;   // SEED: [R] first changed site of each position (ascending)
@@ -235,6 +236,7 @@ struct PsiStates {
   T* npm = nullptr;              // [entries]
   int32_t* npe = nullptr;        // [entries]
   int8_t* npg = nullptr;         // [entries]
+  T* npz = nullptr;              // complex parameters: [entries][2]
   const int64_t* noff = nullptr; // [nodes]
   const uint8_t* nc1 = nullptr;  // [nodes] the node's changed site
   const uint8_t* ne1 = nullptr;  // [nodes] the last site its rows resume at

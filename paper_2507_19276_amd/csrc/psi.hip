@@ -39,8 +39,9 @@ namespace {
 // FOLD: the operands carry sigma = sqrt(eta) (A' = sigma_i M / sigma_j,
 // v' = sigma v, w' = w / sigma, all eta > 0), so the ring holds sigma h and
 // P^s = sum_u x'^2 needs no eta.  STORE and SEED: see PsiStates (the
-// samples' pass that stores states, and the resumed row pass).  CPLX (rows
-// from site 0 only): phs receives arg prod_i z_i per row.
+// samples' pass that stores states, and the resumed row pass).  CPLX: phs
+// receives arg prod_i z_i per row; the stored and resumed prefix states carry
+// the product of the phase factors so far (pz, npz).
 template <typename T> constexpr int prefetch_ksteps(int CH) {
   return (CH / 4) < 64 / ((CH / 4) * int(sizeof(T) / 4)) ? (CH / 4) : 64 / ((CH / 4) * int(sizeof(T) / 4));
 }
@@ -54,7 +55,7 @@ __global__ __launch_bounds__(256) void k_psi_mt(PsiParams<T> P, const uint64_t* 
   // resumed from its sample's stored state ends bit-identical to a row
   // computed from site 0
 #pragma clang fp contract(off)
-  static_assert(!CPLX || (STORE == 0 && !SEED && !SAMPLE), "complex rows run from site 0");
+  static_assert(!CPLX || !SAMPLE, "sampling needs no phase");
   extern __shared__ __align__(16) unsigned char smem[];
   typedef typename V4<T>::type V;
   constexpr int TPC = CH / 16, NT = 4 * TPC, KS = CH / 4, RW = 16 * NTL;
@@ -138,11 +139,19 @@ __global__ __launch_bounds__(256) void k_psi_mt(PsiParams<T> P, const uint64_t* 
       prod = X.npm[so];
       pexp = X.npe[so];
       sgn = X.npg[so];
+      if (CPLX) {
+        zr = X.npz[2 * so];
+        zi = X.npz[2 * so + 1];
+      }
     } else {
       const size_t so = size_t(i0) * X.ns + X.owner[orow];
       prod = X.pm[so];
       pexp = X.pe[so];
       sgn = X.pg[so];
+      if (CPLX) {
+        zr = X.pz[2 * so];
+        zi = X.pz[2 * so + 1];
+      }
     }
     (void)ond;
     const uint64_t below = low_bits(2 * i0), belowh = low_bits(2 * i0 - 64);
@@ -193,12 +202,20 @@ __global__ __launch_bounds__(256) void k_psi_mt(PsiParams<T> P, const uint64_t* 
       X.pm[so] = prod;
       X.pe[so] = pexp;
       X.pg[so] = int8_t(sgn);
+      if (CPLX) {
+        X.pz[2 * so] = zr;
+        X.pz[2 * so + 1] = zi;
+      }
     }
     if (STORE == 2 && writer && olive && i >= sc1 && i <= se1) {
       const size_t so = size_t(soff + (i - sc1));
       X.npm[so] = prod;
       X.npe[so] = pexp;
       X.npg[so] = int8_t(sgn);
+      if (CPLX) {
+        X.npz[2 * so] = zr;
+        X.npz[2 * so + 1] = zi;
+      }
     }
   };
   // a node wavefront stops after the largest resume site of its nodes' rows
@@ -493,10 +510,28 @@ template <typename T, int CH>
 hipError_t run_psi_ch(const PsiParams<T>& P, const uint64_t* m, int64_t R, double* lphi, int8_t* sphi,
                       hipStream_t st, const PsiStates<T>& X, int mode, double* phs) {
   if (phs) {
-    // complex parameters: rows from site 0, the phase per row
-    if (mode != PSI_PLAIN || !P.w2 || !P.c2) return hipErrorInvalidValue;
-    if (P.folded) return run_psi_mt<T, CH, true, 0, false, false, true>(P, m, R, lphi, sphi, st, X, SampleArgs(), phs);
-    return run_psi_mt<T, CH, false, 0, false, false, true>(P, m, R, lphi, sphi, st, X, SampleArgs(), phs);
+    // complex parameters: the phase of each row
+    if (!P.w2 || !P.c2) return hipErrorInvalidValue;
+    const SampleArgs no;
+    switch (mode) {
+      case PSI_PLAIN:
+        if (P.folded) return run_psi_mt<T, CH, true, 0, false, false, true>(P, m, R, lphi, sphi, st, X, no, phs);
+        return run_psi_mt<T, CH, false, 0, false, false, true>(P, m, R, lphi, sphi, st, X, no, phs);
+      case PSI_STORE:
+        if (!X.pz && X.pm) return hipErrorInvalidValue;
+        if (P.folded) return run_psi_mt<T, CH, true, 1, false, false, true>(P, m, R, lphi, sphi, st, X, no, phs);
+        return run_psi_mt<T, CH, false, 1, false, false, true>(P, m, R, lphi, sphi, st, X, no, phs);
+      case PSI_SEED:
+        if (!X.pz || (X.unode && !X.npz)) return hipErrorInvalidValue;
+        if (P.folded) return run_psi_mt<T, CH, true, 0, true, false, true>(P, m, R, lphi, sphi, st, X, no, phs);
+        return run_psi_mt<T, CH, false, 0, true, false, true>(P, m, R, lphi, sphi, st, X, no, phs);
+      case PSI_NODE:
+        if (!X.pz || !X.npz) return hipErrorInvalidValue;
+        if (P.folded) return run_psi_mt<T, CH, true, 2, true, false, true>(P, m, R, lphi, sphi, st, X, no, phs);
+        return run_psi_mt<T, CH, false, 2, true, false, true>(P, m, R, lphi, sphi, st, X, no, phs);
+      default:
+        return hipErrorInvalidValue;
+    }
   }
   switch (mode) {
     case PSI_PLAIN:

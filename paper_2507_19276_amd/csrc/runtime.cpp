@@ -1032,6 +1032,7 @@ struct Resume {
   void* pm = nullptr;       // [K+1][N] T (BF16: float)
   int32_t* pe = nullptr;    // [K+1][N]
   int8_t* pg = nullptr;     // [K+1][N]
+  void* pz = nullptr;       // complex parameters: [K+1][N][2] T
   int64_t ns = 0;
   int32_t* perm = nullptr;  // [rows of a pass] row of each sorted position
   uint8_t* t0 = nullptr;    // [rows of a pass] sorted first changed sites
@@ -1043,6 +1044,7 @@ struct Resume {
   void* npm = nullptr;      // [entries] T
   int32_t* npe = nullptr;
   int8_t* npg = nullptr;
+  void* npz = nullptr;      // complex parameters: [entries][2] T
   const int64_t* noff = nullptr;
   const uint8_t* nc1 = nullptr;
   const uint8_t* ne1 = nullptr;
@@ -1056,6 +1058,7 @@ PsiStates<T> states(const Resume& r) {
   X.pm = static_cast<T*>(r.pm);
   X.pe = r.pe;
   X.pg = r.pg;
+  X.pz = static_cast<T*>(r.pz);
   X.ns = r.ns;
   X.perm = r.perm;
   X.t0 = r.t0;
@@ -1064,6 +1067,7 @@ PsiStates<T> states(const Resume& r) {
   X.npm = static_cast<T*>(r.npm);
   X.npe = r.npe;
   X.npg = r.npg;
+  X.npz = static_cast<T*>(r.npz);
   X.noff = r.noff;
   X.nc1 = r.nc1;
   X.ne1 = r.ne1;
@@ -1091,17 +1095,19 @@ size_t mantissa_bytes(int precision) { return precision == NQS_F64 ? 8 : 4; }
 
 // amplitudes of R rows into (lphi, sphi).  mode PSI_STORE (samples, with rs)
 // or PSI_SEED (rows of a pass, with rs and its order).
-// phs: complex parameters, the phase of each row (then rows from site 0 only)
+// phs: complex parameters, the phase of each row
 nqs_status run_amplitudes(const nqs_ansatz* a, int precision, const uint64_t* m, int64_t R, double* lphi,
                           int8_t* sphi, hipStream_t st, const Resume* rs = nullptr, int mode = PSI_PLAIN,
                           double* phs = nullptr) {
   if (mode != PSI_PLAIN && !rs) return fail(NQS_EINVAL, "resume state missing");
   if (a->cplx) {
-    if (mode != PSI_PLAIN || !phs) return fail(NQS_EINVAL, "complex amplitudes: rows from site 0 with phases");
+    if (!phs) return fail(NQS_EINVAL, "complex amplitudes need their phases");
     if (precision == NQS_F64) {
-      HIPCHK(launch_psi_f64(a->params(a->fwd64()), m, R, lphi, sphi, st, PsiStates<double>(), PSI_PLAIN, phs));
+      HIPCHK(launch_psi_f64(a->params(a->fwd64()), m, R, lphi, sphi, st,
+                            rs ? states<double>(*rs) : PsiStates<double>(), mode, phs));
     } else if (precision == NQS_F32) {
-      HIPCHK(launch_psi_f32(a->params(a->fwd32()), m, R, lphi, sphi, st, PsiStates<float>(), PSI_PLAIN, phs));
+      HIPCHK(launch_psi_f32(a->params(a->fwd32()), m, R, lphi, sphi, st,
+                            rs ? states<float>(*rs) : PsiStates<float>(), mode, phs));
     } else {
       return fail(NQS_EUNSUPPORTED, "complex amplitudes run in FP64 or FP32");
     }
@@ -1498,16 +1504,19 @@ nqs_status eloc_run(nqs_ctx* ctx, const nqs_instance* inst, const nqs_ansatz* an
   double* f2 = fsq ? fsq : S.get<double>(N);
   double* sums = S.get<double>(8);
   const int K = ans->K;
-  const bool resume = resumes(*opts) && !ans->tensor && !ans->cplx && cap_used < (int64_t(1) << 31);
+  const bool resume = resumes(*opts) && !ans->tensor && cap_used < (int64_t(1) << 31);
   Resume rs;
   double* lphi_s = nullptr;
   int8_t* sphi_s = nullptr;
+  double* phs_s = nullptr;   // complex parameters: phases of the samples' pass and of the node pass
+  double* phs_n = nullptr;
   if (resume) {
     rs.hs = S.get<unsigned char>(size_t(K) * N * ans->chip * state_bytes(opts->precision));
     if (opts->precision == NQS_BF16) rs.he = S.get<int32_t>(size_t(K) * N);
     rs.pm = S.get<unsigned char>(size_t(K + 1) * N * mantissa_bytes(opts->precision));
     rs.pe = S.get<int32_t>(size_t(K + 1) * N);
     rs.pg = S.get<int8_t>(size_t(K + 1) * N);
+    if (ans->cplx) rs.pz = S.get<unsigned char>(size_t(K + 1) * N * 2 * mantissa_bytes(opts->precision));
     rs.ns = N;
     rs.perm = S.get<int32_t>(cap_used);
     rs.t0 = S.get<uint8_t>(cap_used);
@@ -1517,6 +1526,7 @@ nqs_status eloc_run(nqs_ctx* ctx, const nqs_instance* inst, const nqs_ansatz* an
     rs.owner = P.rows.owner;
     lphi_s = S.get<double>(N);
     sphi_s = S.get<int8_t>(N);
+    if (ans->cplx) phs_s = S.get<double>(N);
   }
   // one level of shared prefixes (FP64/FP32; BF16 rows are cheap enough per
   // site that a node pass does not pay): node list, compact storage
@@ -1550,6 +1560,10 @@ nqs_status eloc_run(nqs_ctx* ctx, const nqs_instance* inst, const nqs_ansatz* an
     rs.npm = S.get<unsigned char>(size_t(ecap) * mantissa_bytes(opts->precision));
     rs.npe = S.get<int32_t>(ecap);
     rs.npg = S.get<int8_t>(ecap);
+    if (ans->cplx) {
+      rs.npz = S.get<unsigned char>(size_t(ecap) * 2 * mantissa_bytes(opts->precision));
+      phs_n = S.get<double>(ecap);
+    }
     row_node = S.get<int32_t>(cap_used);
     row_site = S.get<uint8_t>(cap_used);
     P.rows.sec = S.get<uint32_t>(cap_used);
@@ -1572,7 +1586,8 @@ nqs_status eloc_run(nqs_ctx* ctx, const nqs_instance* inst, const nqs_ansatz* an
   if (resume) {
     // the samples' own pass: carried and log-product states at every site
     if (timing) HIPCHK(hipEventRecord(pe[0], stream));
-    if ((s = run_amplitudes(ans, opts->precision, samples, N, lphi_s, sphi_s, stream, &rs, PSI_STORE)) != NQS_OK)
+    if ((s = run_amplitudes(ans, opts->precision, samples, N, lphi_s, sphi_s, stream, &rs, PSI_STORE, phs_s)) !=
+        NQS_OK)
       return s;
     site_rows += int64_t(N) * K;
     if (timing) {
@@ -1614,7 +1629,8 @@ nqs_status eloc_run(nqs_ctx* ctx, const nqs_instance* inst, const nqs_ansatz* an
           rn.nc1 = nl.c1;
           rn.ne1 = nl.e1;
           rn.unode = nullptr;
-          if ((s = run_amplitudes(ans, opts->precision, nl.m, nn, lphi_n, sphi_n, stream, &rn, PSI_NODE)) != NQS_OK)
+          if ((s = run_amplitudes(ans, opts->precision, nl.m, nn, lphi_n, sphi_n, stream, &rn, PSI_NODE, phs_n)) !=
+              NQS_OK)
             return s;
           // a node is evaluated from its first changed site to the largest
           // resume site of its rows: (entries - 1) sites
@@ -1628,7 +1644,7 @@ nqs_status eloc_run(nqs_ctx* ctx, const nqs_instance* inst, const nqs_ansatz* an
       }
       HIPCHK(launch_order_t0(key, Rp, K, rs.cnt, rs.tot, rs.perm, rs.t0, stream));
       if (timing) HIPCHK(hipEventRecord(kq[0], stream));
-      if ((s = run_amplitudes(ans, opts->precision, P.rows.m, Rp, lphi, sphi, stream, &rs, PSI_SEED)) != NQS_OK)
+      if ((s = run_amplitudes(ans, opts->precision, P.rows.m, Rp, lphi, sphi, stream, &rs, PSI_SEED, phs)) != NQS_OK)
         return s;
       if (timing) HIPCHK(hipEventRecord(kq[1], stream));
       if (stats) {

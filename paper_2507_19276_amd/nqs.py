@@ -349,7 +349,7 @@ def eloc(ctx: Context, inst: Instance, ans: Ansatz, samples, counts: Optional[to
 
 def eloc_complex(ctx: Context, inst: Instance, ans: Ansatz, samples, counts: Optional[torch.Tensor] = None,
                  eps: float = 0.0, n_eps: int = 0, precision="f64", seed: int = 0, stream_id: int = 0,
-                 sample_base: int = 0, want_stats: bool = True, max_rows_per_pass: int = 0):
+                 sample_base: int = 0, want_stats: bool = True, max_rows_per_pass: int = 0, resume: bool = True):
     """Local energies with complex amplitudes (nqs_eloc_complex): eloc and
     etnum as complex128 device tensors, logabs, phase, fsq; and the stats dict."""
     s = _samples(samples)
@@ -358,7 +358,7 @@ def eloc_complex(ctx: Context, inst: Instance, ans: Ansatz, samples, counts: Opt
     f = {k: torch.empty(N, dtype=torch.float64, device=dev)
          for k in ("er", "ei", "tr", "ti", "logabs", "phase", "fsq")}
     c = None if counts is None else counts.to(dtype=torch.float64, device=dev).contiguous()
-    o = opts(eps, n_eps, precision, seed, stream_id, sample_base, max_rows_per_pass, True)
+    o = opts(eps, n_eps, precision, seed, stream_id, sample_base, max_rows_per_pass, resume)
     st = ElocStats()
     check(lib().nqs_eloc_complex(ctx.h, inst.h, ans.h, _ptr(s), _ptr(c), N, C.byref(o), _ptr(f["er"]),
                                  _ptr(f["ei"]), _ptr(f["tr"]), _ptr(f["ti"]), _ptr(f["logabs"]), _ptr(f["phase"]),

@@ -231,3 +231,17 @@ def test_refused_forms(nqs, ctx):
         nqs.Ansatz(ctx, w.K, w.n_alpha, w.n_beta, 33, w.parent_ptr, w.parent_idx, 0, cplx=True)
     with pytest.raises(nqs.NqsError):
         nqs.Ansatz(ctx, w.K, w.n_alpha, w.n_beta, 4, w.parent_ptr, w.parent_idx, 0, cplx=True, tensor=True)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_resumed_rows_bit_identical(nqs, ctx, prec):
+    """Rows resumed from the samples' and the nodes' stored states (with the
+    product of the phase factors so far) give the same bits as every row
+    evaluated from site 0."""
+    w, inst, ans = setup(nqs, ctx, "c2c", 128)
+    kw = dict(eps=w.eps, n_eps=w.n_eps, precision=prec, seed=w.seed, stream_id=2)
+    a, sa = nqs.eloc_complex(ctx, inst, ans, w.samples, **kw)
+    b, sb = nqs.eloc_complex(ctx, inst, ans, w.samples, resume=False, **kw)
+    for k in ("eloc", "etnum", "logabs", "phase"):
+        assert torch.equal(a[k], b[k]), k
+    assert sa["n_site_rows"] < sb["n_site_rows"] // 2
