@@ -168,9 +168,10 @@ nqs_status nqs_connected(nqs_ctx* ctx, const nqs_instance* inst, const uint64_t*
  * chi' = ceil(chi^(2/(d+1))); its parameters follow everything else: per such
  * site ascending, K^(0) (output mode) and K^(1..d) (one per parent, ascending),
  * each chi x chi' row-major, then U^s for s = 0..3, each chi'^(d+1) with index
- * order [i', a_1, .., a_d].  Forward, local energy and sampling run in FP64 and
- * FP32 (rows evaluated from site 0; NQS_EUNSUPPORTED for BF16, for the
- * adjoint, for a site with more than 3 parents, and when a thread's ring of
+ * order [i', a_1, .., a_d].  Forward, local energy, sampling, the adjoint
+ * (nqs_logpsi_vjp, the factor matrices and cores included) and the VMC step
+ * run in FP64 and FP32 (rows evaluated from site 0; NQS_EUNSUPPORTED for BF16,
+ * for a site with more than 3 parents, and when a thread's ring of
  * W x ceil4(chi) states does not fit the LDS). */
 #define NQS_ANSATZ_TENSOR 0x10
 /* Flag added to the correlator kind: complex parameters (Sec. 2.1, the

@@ -124,7 +124,8 @@ __global__ __launch_bounds__(256) void k_bwd_site(AdjParams<T> P, int i, const u
       const int u0 = 16 * t + 4 * g;
       const V vv = *reinterpret_cast<const V*>(vi + s * CH + u0);
       const V ee = *reinterpret_cast<const V*>(ei + u0);
-      const V x = acc[s * TPC + t] + vv;
+      V x = acc[s * TPC + t] + vv;
+      if (P.tadd) x += *reinterpret_cast<const V*>(P.tadd + (size_t(row) * 4 + s) * CH + u0);
       acc[s * TPC + t] = x;
       p += ee.x * x.x * x.x + ee.y * x.y * x.y + ee.z * x.z * x.z + ee.w * x.w * x.w;
     }
@@ -498,11 +499,19 @@ hipError_t run_site(const AdjParams<T>& P, int i, const uint64_t* m, int64_t R, 
 }
 
 template <typename T>
-hipError_t run_sweep(const AdjParams<T>& P, const uint64_t* m, int64_t R, int64_t Rpad, const double* cot,
+hipError_t run_sweep(const AdjParams<T>& P0, const uint64_t* m, int64_t R, int64_t Rpad, const double* cot,
                      const T* Hbuf, T* dcarry, T* Dc, T* Eeta, int rows_per_split, int nsplit, double* gpart,
-                     int64_t n_params, hipStream_t st) {
-  for (int i = P.K - 1; i >= 0; --i) {
+                     int64_t n_params, hipStream_t st, const TnAdj<T>* tn) {
+  for (int i = P0.K - 1; i >= 0; --i) {
     hipError_t e;
+    // a tensor site: its term t^s of every row first (added to the recomputed
+    // candidates), its own gradient and the parents' cotangents after dcand
+    const bool tsite = tn && tn->tq_host[i] > 0;
+    AdjParams<T> P = P0;
+    P.tadd = tsite ? tn->TT : nullptr;
+    if (tsite && (e = launch_tn_bwd_site(*tn, P0.pidx, i, 0, Rpad, Hbuf, Dc, dcarry, rows_per_split, nsplit, gpart,
+                                         n_params, st)) != hipSuccess)
+      return e;
     switch (P.chip) {
       case 16: e = run_site<T, 16>(P, i, m, R, Rpad, cot, Hbuf, dcarry, Dc, Eeta, rows_per_split, nsplit, gpart, n_params, st); break;
       case 32: e = run_site<T, 32>(P, i, m, R, Rpad, cot, Hbuf, dcarry, Dc, Eeta, rows_per_split, nsplit, gpart, n_params, st); break;
@@ -511,6 +520,9 @@ hipError_t run_sweep(const AdjParams<T>& P, const uint64_t* m, int64_t R, int64_
       default: e = hipErrorInvalidValue;
     }
     if (e != hipSuccess) return e;
+    if (tsite && (e = launch_tn_bwd_site(*tn, P0.pidx, i, 1, Rpad, Hbuf, Dc, dcarry, rows_per_split, nsplit, gpart,
+                                         n_params, st)) != hipSuccess)
+      return e;
   }
   return hipSuccess;
 }
@@ -520,17 +532,17 @@ hipError_t run_sweep(const AdjParams<T>& P, const uint64_t* m, int64_t R, int64_
 hipError_t launch_bwd_sweep_f64(const AdjParams<double>& P, const uint64_t* m, int64_t R, int64_t Rpad,
                                 const double* cot, const double* Hbuf, double* dcarry, double* Dc,
                                 double* Eeta, int rows_per_split, int nsplit, double* gpart,
-                                int64_t n_params, hipStream_t st) {
+                                int64_t n_params, hipStream_t st, const TnAdj<double>* tn) {
   return run_sweep<double>(P, m, R, Rpad, cot, Hbuf, dcarry, Dc, Eeta, rows_per_split, nsplit, gpart,
-                           n_params, st);
+                           n_params, st, tn);
 }
 
 hipError_t launch_bwd_sweep_f32(const AdjParams<float>& P, const uint64_t* m, int64_t R, int64_t Rpad,
                                 const double* cot, const float* Hbuf, float* dcarry, float* Dc,
                                 float* Eeta, int rows_per_split, int nsplit, double* gpart,
-                                int64_t n_params, hipStream_t st) {
+                                int64_t n_params, hipStream_t st, const TnAdj<float>* tn) {
   return run_sweep<float>(P, m, R, Rpad, cot, Hbuf, dcarry, Dc, Eeta, rows_per_split, nsplit, gpart,
-                          n_params, st);
+                          n_params, st, tn);
 }
 
 hipError_t launch_corr_backward(const CorrParams& C, const uint64_t* m, int64_t R, const double* cot,

@@ -102,6 +102,23 @@ struct AdjParams {
   const int64_t* offC = nullptr;
   const int64_t* offW2 = nullptr;
   const int64_t* offC2 = nullptr;
+  const T* tadd = nullptr;       // tensor term of the current site's candidates [Rpad][4][chip] (nullable)
+};
+
+// The tensor term's part of the adjoint sweep (host-side description; the
+// row scratch is device memory of the current site)
+template <typename T>
+struct TnAdj {
+  TnParams<T> P;                 // the forward's kernel layout
+  const int* tq_host;            // [K] chi' of each site (0: no tensor term)
+  const int* d_host;             // [K] in-degrees
+  const int64_t* offTK_host;     // [K] packed offsets of K^(0..d)
+  const int64_t* offTU_host;     // [K] packed offsets of U^s
+  T* TT;                         // [Rpad][4][chip] tensor term of the candidates
+  T* PJ;                         // [Rpad][3][16] projections
+  T* QS;                         // [Rpad][4][16] core contractions
+  T* DQ;                         // [Rpad][4][16]
+  T* DP;                         // [Rpad][3][16]
 };
 
 // Map of a gradient over the realified parameters onto the packed complex
@@ -291,10 +308,21 @@ hipError_t launch_unique(const uint64_t* m, const double* lphi, const int8_t* sp
 hipError_t launch_fill_i64(int64_t* p, int64_t n, int64_t v, hipStream_t st);
 // ---- BDG-TensorRNN (tensor_rnn.hip) --------------------------------------
 size_t tn_lds_bytes(int W, int rw, int precision);
+// hs (nullable): store the carried state of every row r < ns and site for the adjoint
 hipError_t launch_psi_tn_f64(const TnParams<double>& P, const uint64_t* m, int64_t R, double* lphi, int8_t* sphi,
-                             hipStream_t st);
+                             hipStream_t st, double* hs = nullptr, int64_t ns = 0);
 hipError_t launch_psi_tn_f32(const TnParams<float>& P, const uint64_t* m, int64_t R, double* lphi, int8_t* sphi,
-                             hipStream_t st);
+                             hipStream_t st, float* hs = nullptr, int64_t ns = 0);
+// adjoint of the tensor term at site i (tensor_rnn.hip): stage 0 = the
+// projections, core contraction and t^s of every row (into A.TT, added to the
+// recomputed candidates), stage 1 = the cotangents of the parents' states and
+// the gradient of K0, K_j, U into gpart
+hipError_t launch_tn_bwd_site(const TnAdj<double>& A, const int* pidx, int i, int stage, int64_t Rpad,
+                              const double* Hbuf, const double* Dc, double* dcarry, int rows_per_split, int nsplit,
+                              double* gpart, int64_t n_params, hipStream_t st);
+hipError_t launch_tn_bwd_site(const TnAdj<float>& A, const int* pidx, int i, int stage, int64_t Rpad,
+                              const float* Hbuf, const float* Dc, float* dcarry, int rows_per_split, int nsplit,
+                              double* gpart, int64_t n_params, hipStream_t st);
 hipError_t launch_sample_tn_f64(const TnParams<double>& P, int64_t R, double* lphi, int8_t* sphi, hipStream_t st,
                                 const SampleArgs& SA);
 hipError_t launch_sample_tn_f32(const TnParams<float>& P, int64_t R, double* lphi, int8_t* sphi, hipStream_t st,
@@ -354,14 +382,15 @@ hipError_t launch_gather_logpsi_phase(int64_t N, const double* lphi, const int8_
                                       hipStream_t st);
 
 // ---- launchers (adjoint.hip) -------------------------------------------
+// tn (nullable): the tensor term's part of the sweep
 hipError_t launch_bwd_sweep_f64(const AdjParams<double>& P, const uint64_t* m, int64_t R, int64_t Rpad,
                                 const double* cot, const double* Hbuf, double* dcarry, double* Dc,
                                 double* Eeta, int rows_per_split, int nsplit, double* gpart,
-                                int64_t n_params, hipStream_t st);
+                                int64_t n_params, hipStream_t st, const TnAdj<double>* tn = nullptr);
 hipError_t launch_bwd_sweep_f32(const AdjParams<float>& P, const uint64_t* m, int64_t R, int64_t Rpad,
                                 const double* cot, const float* Hbuf, float* dcarry, float* Dc,
                                 float* Eeta, int rows_per_split, int nsplit, double* gpart,
-                                int64_t n_params, hipStream_t st);
+                                int64_t n_params, hipStream_t st, const TnAdj<float>* tn = nullptr);
 hipError_t launch_corr_backward(const CorrParams& C, const uint64_t* m, int64_t R, const double* cot,
                                 double* dth, int rows_per_split, int nsplit, int64_t offB, int64_t offW,
                                 int64_t offW2, double* gpart, int64_t n_params, hipStream_t st);

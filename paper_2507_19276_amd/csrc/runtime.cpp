@@ -1368,7 +1368,8 @@ nqs_status nqs_logpsi_vjp_phase(nqs_ctx* ctx, const nqs_ansatz* ans, const uint6
   if (!ans->bound) return fail(NQS_EINVAL, "parameters not bound");
   if (precision != NQS_F64 && precision != NQS_F32)
     return fail(NQS_EUNSUPPORTED, "the adjoint runs in FP64 or FP32");
-  if (ans->tensor) return fail(NQS_EUNSUPPORTED, "no adjoint for the tensor-RNN term");
+  if (ans->tensor && precision == NQS_F64 && !ans->tn_f64_ok)
+    return fail(NQS_EUNSUPPORTED, "FP64 tensor-RNN ring does not fit the LDS");
   DeviceGuard g(ctx->device);
   nqs_status s = check_samples(ctx, samples, N, ans->K, ans->na, ans->nb, stream);
   if (s != NQS_OK) return s;
@@ -1396,7 +1397,26 @@ nqs_status nqs_logpsi_vjp_phase(nqs_ctx* ctx, const nqs_ansatz* ans, const uint6
   void* ab = phase ? S.get<unsigned char>(size_t(Rpad) * 2 * esz) : nullptr;
   double* gr = ans->cplx ? S.get<double>(np) : nullptr;
   double* dth = ans->nh ? S.get<double>(size_t(N) * ans->nh) : nullptr;
+  // tensor term: row scratch of the current site (t^s, projections, core, their cotangents)
+  void* tnb = ans->tensor ? S.get<unsigned char>(size_t(Rpad) * (4 * ans->chip + 14 * 16) * esz) : nullptr;
   if (S.oom) return fail(NQS_ENOMEM, "workspace allocation failed");
+  std::vector<int> tdeg(ans->K);
+  for (int i = 0; i < ans->K; ++i) tdeg[i] = ans->pptr[i + 1] - ans->pptr[i];
+  auto tn_adj = [&](auto* base, const auto& P) {
+    typedef typename std::remove_pointer<decltype(base)>::type T;
+    TnAdj<T> A;
+    A.P = P;
+    A.tq_host = ans->tq.data();
+    A.d_host = tdeg.data();
+    A.offTK_host = ans->offTK.data();
+    A.offTU_host = ans->offTU.data();
+    A.TT = base;
+    A.PJ = A.TT + size_t(Rpad) * 4 * ans->chip;
+    A.QS = A.PJ + size_t(Rpad) * 3 * 16;
+    A.DQ = A.QS + size_t(Rpad) * 4 * 16;
+    A.DP = A.DQ + size_t(Rpad) * 4 * 16;
+    return A;
+  };
   HIPCHK(hipMemsetAsync(dcarry, 0, hsz * esz, stream));
   HIPCHK(hipMemsetAsync(gpart, 0, sizeof(double) * nsplit * np, stream));
   HIPCHK(hipMemsetAsync(cotp, 0, sizeof(double) * Rpad, stream));
@@ -1417,22 +1437,35 @@ nqs_status nqs_logpsi_vjp_phase(nqs_ctx* ctx, const nqs_ansatz* ans, const uint6
     }
     return P;
   };
+  if (ans->tensor) HIPCHK(hipMemsetAsync(Hbuf, 0, hsz * esz, stream));   // units past ceil4(chi) stay zero
   if (precision == NQS_F64) {
-    PsiStates<double> X;
-    X.hs = (double*)Hbuf;
-    X.ns = Rpad;
-    HIPCHK(launch_psi_f64(ans->params(ans->L64), samples, N, lphi, sphi, stream, X, PSI_STORE));
+    TnAdj<double> A{};
+    if (ans->tensor) {
+      A = tn_adj((double*)tnb, ans->tn<double>(ans->tn64));
+      HIPCHK(launch_psi_tn_f64(A.P, samples, N, lphi, sphi, stream, (double*)Hbuf, Rpad));
+    } else {
+      PsiStates<double> X;
+      X.hs = (double*)Hbuf;
+      X.ns = Rpad;
+      HIPCHK(launch_psi_f64(ans->params(ans->L64), samples, N, lphi, sphi, stream, X, PSI_STORE));
+    }
     HIPCHK(launch_bwd_sweep_f64(with_phase(ans->adj(ans->L64), ans->L64), samples, N, Rpad, cotp,
                                 (const double*)Hbuf, (double*)dcarry, (double*)Dc, (double*)Eeta, rows_per_split,
-                                nsplit, gpart, np, stream));
+                                nsplit, gpart, np, stream, ans->tensor ? &A : nullptr));
   } else {
-    PsiStates<float> X;
-    X.hs = (float*)Hbuf;
-    X.ns = Rpad;
-    HIPCHK(launch_psi_f32(ans->params(ans->L32), samples, N, lphi, sphi, stream, X, PSI_STORE));
+    TnAdj<float> A{};
+    if (ans->tensor) {
+      A = tn_adj((float*)tnb, ans->tn<float>(ans->tn32));
+      HIPCHK(launch_psi_tn_f32(A.P, samples, N, lphi, sphi, stream, (float*)Hbuf, Rpad));
+    } else {
+      PsiStates<float> X;
+      X.hs = (float*)Hbuf;
+      X.ns = Rpad;
+      HIPCHK(launch_psi_f32(ans->params(ans->L32), samples, N, lphi, sphi, stream, X, PSI_STORE));
+    }
     HIPCHK(launch_bwd_sweep_f32(with_phase(ans->adj(ans->L32), ans->L32), samples, N, Rpad, cotp,
                                 (const float*)Hbuf, (float*)dcarry, (float*)Dc, (float*)Eeta, rows_per_split,
-                                nsplit, gpart, np, stream));
+                                nsplit, gpart, np, stream, ans->tensor ? &A : nullptr));
   }
   if (ans->nh)
     HIPCHK(launch_corr_backward(ans->corr(), samples, N, cotp, dth, rows_per_split, nsplit, ans->offB,

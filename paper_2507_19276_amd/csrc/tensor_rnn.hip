@@ -30,10 +30,13 @@ namespace {
 
 constexpr int kTnThreads = 64;
 
+// hs (nullable, not with SAMPLE): the carried state h_i^{s_i} of every row r <
+// ns and site i as hs[(i ns + r) chip + u], u < rw (the adjoint's layout; rows
+// past R repeat the last row, units from rw on are left as they are)
 template <typename T, int QP, bool SAMPLE>
 __global__ __launch_bounds__(kTnThreads) void k_psi_tn(TnParams<T> P, const uint64_t* __restrict__ m, int64_t R,
                                                        double* __restrict__ lphi, int8_t* __restrict__ sphi,
-                                                       SampleArgs SA) {
+                                                       SampleArgs SA, T* __restrict__ hs, int64_t ns) {
 #pragma clang fp contract(off)
   extern __shared__ __align__(16) unsigned char smem[];
   const int tid = threadIdx.x;
@@ -171,6 +174,8 @@ __global__ __launch_bounds__(kTnThreads) void k_psi_tn(TnParams<T> P, const uint
       return Pacc;
     };
     for (int s = 0; s < 4; ++s) Ps[s] = candidate(s, true, !SAMPLE);
+    if (!SAMPLE && hs && r < ns)
+      for (int u = 0; u < RW; ++u) hs[(size_t(i) * ns + r) * CP + u] = RG(wslot, u);
     const int rest = P.K - 1 - i;
     T Z = T(0);
 #pragma unroll
@@ -228,33 +233,240 @@ __global__ __launch_bounds__(kTnThreads) void k_psi_tn(TnParams<T> P, const uint
 
 template <typename T, bool SAMPLE>
 hipError_t run_tn(const TnParams<T>& P, const uint64_t* m, int64_t R, double* lphi, int8_t* sphi, hipStream_t st,
-                  const SampleArgs& SA) {
+                  const SampleArgs& SA, T* hs = nullptr, int64_t ns = 0) {
   if (R <= 0) return hipSuccess;
   const size_t lds = (size_t(P.W) * P.rw + 16) * kTnThreads * sizeof(T);
   if (lds > 64 * 1024 || P.rw > P.chip || P.rw < P.chi) return hipErrorInvalidValue;
-  const dim3 grid(unsigned((R + kTnThreads - 1) / kTnThreads));
+  // the store covers rows up to ns, which the grid must reach
+  const int64_t span = hs ? (ns > R ? ns : R) : R;
+  const dim3 grid(unsigned((span + kTnThreads - 1) / kTnThreads));
   if (P.qp == 8)
-    hipLaunchKernelGGL((k_psi_tn<T, 8, SAMPLE>), grid, dim3(kTnThreads), lds, st, P, m, R, lphi, sphi, SA);
+    hipLaunchKernelGGL((k_psi_tn<T, 8, SAMPLE>), grid, dim3(kTnThreads), lds, st, P, m, R, lphi, sphi, SA, hs, ns);
   else if (P.qp == 16)
-    hipLaunchKernelGGL((k_psi_tn<T, 16, SAMPLE>), grid, dim3(kTnThreads), lds, st, P, m, R, lphi, sphi, SA);
+    hipLaunchKernelGGL((k_psi_tn<T, 16, SAMPLE>), grid, dim3(kTnThreads), lds, st, P, m, R, lphi, sphi, SA, hs, ns);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();
 }
 
+// ---- adjoint of the tensor term ------------------------------------------
+// For a site i with a tensor term and the rows r < Rpad of the adjoint's sweep
+// (carried states Hbuf[(site Rpad + r) chip + u] from the forward's store):
+//   pre:  p_j = K_j^T h_(parent j), q^s = U^s (p_1 x .. x p_d), t^s = K0 q^s;
+//         t is added to the candidates the sweep's site kernel recomputes;
+//   post: dq^s = K0^T dcand^s, dp_j[b] = sum over s, i', a with a_j = b of
+//         dq^s[i'] U^s[i'][a] prod_{l != j} p_l[a_l], dcarry_(parent j) += K_j dp_j;
+//   cols: dK0 = sum_rows sum_s dcand^s q^s^T, dK_j = sum_rows h_j dp_j^T,
+//         dU^s[i'][a] = sum_rows dq^s[i'] prod_j p_j[a_j], per split of rows.
+// One thread per row (pre, post) or per (split, gradient entry) (cols); the
+// weights come from the forward's kernel layout.  Row scratch p, q, dp, dq is
+// [row][3 or 4][kTq].
+constexpr int kTq = 16;
+
+template <typename T>
+struct TnSite {
+  int e0, d, Q, offK0, offKj, offU;
+};
+
+template <typename T>
+__device__ inline TnSite<T> tn_site(const TnParams<T>& P, int i) {
+  TnSite<T> S;
+  S.e0 = P.pptr[i];
+  S.d = P.pptr[i + 1] - S.e0;
+  S.Q = P.site[8 * i + 4];
+  S.offK0 = P.site[8 * i + 5];
+  S.offKj = P.site[8 * i + 6];
+  S.offU = P.site[8 * i + 7];
+  return S;
+}
+
+// U^s[i'][a_1..a_d] in the kernel layout (last index padded to qp)
+template <typename T>
+__device__ inline T tn_core(const TnParams<T>& P, const TnSite<T>& S, int s, int ip, int a1, int a2, int a3) {
+  if (S.d == 2) return P.prm[S.offU + (size_t(s * S.Q + ip) * S.Q + a1) * P.qp + a2];
+  return P.prm[S.offU + (size_t(s * S.Q + ip) * S.Q * S.Q + a1 * S.Q + a2) * P.qp + a3];
+}
+
+template <typename T>
+__global__ void k_tn_bwd_pre(TnParams<T> P, const int* pidx, int i, int64_t Rpad, const T* Hbuf, T* TT, T* PJ,
+                             T* QS) {
+  const int64_t r = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (r >= Rpad) return;
+  const TnSite<T> S = tn_site(P, i);
+  const int CP = P.chip, chi = P.chi, Q = S.Q;
+  T p[3][kTq], q[4][kTq];
+  for (int j = 0; j < S.d; ++j) {
+    const T* h = Hbuf + (size_t(pidx[S.e0 + j]) * Rpad + r) * CP;
+    for (int a = 0; a < Q; ++a) {
+      T acc = T(0);
+      for (int v = 0; v < chi; ++v) acc += P.prm[S.offKj + (j * CP + v) * P.qp + a] * h[v];
+      p[j][a] = acc;
+      PJ[(size_t(r) * 3 + j) * kTq + a] = acc;
+    }
+  }
+  const int Q3 = S.d == 3 ? Q : 1;
+  for (int s = 0; s < 4; ++s)
+    for (int ip = 0; ip < Q; ++ip) {
+      T acc = T(0);
+      for (int a1 = 0; a1 < Q; ++a1)
+        for (int a2 = 0; a2 < Q; ++a2)
+          for (int a3 = 0; a3 < Q3; ++a3) {
+            T f = p[0][a1] * p[1][a2];
+            if (S.d == 3) f *= p[2][a3];
+            acc += tn_core(P, S, s, ip, a1, a2, a3) * f;
+          }
+      q[s][ip] = acc;
+      QS[(size_t(r) * 4 + s) * kTq + ip] = acc;
+    }
+  for (int s = 0; s < 4; ++s)
+    for (int u = 0; u < CP; ++u) {
+      T t = T(0);
+      if (u < chi)
+        for (int ip = 0; ip < Q; ++ip) t += P.prm[S.offK0 + ip * CP + u] * q[s][ip];
+      TT[(size_t(r) * 4 + s) * CP + u] = t;
+    }
+}
+
+template <typename T>
+__global__ void k_tn_bwd_post(TnParams<T> P, const int* pidx, int i, int64_t Rpad, const T* Dc, const T* PJ, T* DQ,
+                              T* DP, T* dcarry) {
+  const int64_t r = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (r >= Rpad) return;
+  const TnSite<T> S = tn_site(P, i);
+  const int CP = P.chip, chi = P.chi, Q = S.Q;
+  T p[3][kTq], dq[4][kTq], dp[3][kTq];
+  for (int j = 0; j < S.d; ++j)
+    for (int a = 0; a < Q; ++a) {
+      p[j][a] = PJ[(size_t(r) * 3 + j) * kTq + a];
+      dp[j][a] = T(0);
+    }
+  for (int s = 0; s < 4; ++s)
+    for (int ip = 0; ip < Q; ++ip) {
+      T acc = T(0);
+      for (int u = 0; u < chi; ++u) acc += P.prm[S.offK0 + ip * CP + u] * Dc[(size_t(r) * 4 + s) * CP + u];
+      dq[s][ip] = acc;
+      DQ[(size_t(r) * 4 + s) * kTq + ip] = acc;
+    }
+  const int Q3 = S.d == 3 ? Q : 1;
+  for (int s = 0; s < 4; ++s)
+    for (int ip = 0; ip < Q; ++ip) {
+      const T g = dq[s][ip];
+      if (g == T(0)) continue;
+      for (int a1 = 0; a1 < Q; ++a1)
+        for (int a2 = 0; a2 < Q; ++a2)
+          for (int a3 = 0; a3 < Q3; ++a3) {
+            const T u = tn_core(P, S, s, ip, a1, a2, a3) * g;
+            if (S.d == 2) {
+              dp[0][a1] += u * p[1][a2];
+              dp[1][a2] += u * p[0][a1];
+            } else {
+              dp[0][a1] += u * p[1][a2] * p[2][a3];
+              dp[1][a2] += u * p[0][a1] * p[2][a3];
+              dp[2][a3] += u * p[0][a1] * p[1][a2];
+            }
+          }
+    }
+  for (int j = 0; j < S.d; ++j) {
+    for (int b = 0; b < Q; ++b) DP[(size_t(r) * 3 + j) * kTq + b] = dp[j][b];
+    T* dc = dcarry + (size_t(pidx[S.e0 + j]) * Rpad + r) * CP;
+    for (int v = 0; v < chi; ++v) {
+      T acc = T(0);
+      for (int b = 0; b < Q; ++b) acc += P.prm[S.offKj + (j * CP + v) * P.qp + b] * dp[j][b];
+      dc[v] += acc;
+    }
+  }
+}
+
+template <typename T>
+__global__ void k_tn_bwd_cols(TnParams<T> P, const int* pidx, int i, int64_t Rpad, int rows_per_split, int nsplit,
+                              const T* Hbuf, const T* Dc, const T* PJ, const T* QS, const T* DQ, const T* DP,
+                              int64_t offTK, int64_t offTU, double* gpart, int64_t n_params) {
+  const TnSite<T> S = tn_site(P, i);
+  const int CP = P.chip, chi = P.chi, Q = S.Q, d = S.d;
+  int nQd = 1;
+  for (int k = 0; k < d; ++k) nQd *= Q;
+  const int nK = chi * Q, ncol = (d + 1) * nK + 4 * Q * nQd;
+  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= int64_t(ncol) * nsplit) return;
+  const int split = int(t / ncol), col = int(t % ncol);
+  const int64_t r0 = int64_t(split) * rows_per_split;
+  const int64_t r1 = r0 + rows_per_split < Rpad ? r0 + rows_per_split : Rpad;
+  double acc = 0.0;
+  int64_t out;
+  if (col < nK) {                       // dK0[u][i']
+    const int u = col / Q, ip = col % Q;
+    for (int64_t r = r0; r < r1; ++r)
+      for (int s = 0; s < 4; ++s)
+        acc += double(Dc[(size_t(r) * 4 + s) * CP + u]) * double(QS[(size_t(r) * 4 + s) * kTq + ip]);
+    out = offTK + col;
+  } else if (col < (d + 1) * nK) {      // dK_j[v][b]
+    const int c = col - nK, j = c / nK, v = (c / Q) % chi, b = c % Q;
+    const T* h = Hbuf + size_t(pidx[S.e0 + j]) * Rpad * CP + v;
+    for (int64_t r = r0; r < r1; ++r) acc += double(h[size_t(r) * CP]) * double(DP[(size_t(r) * 3 + j) * kTq + b]);
+    out = offTK + (j + 1) * nK + v * Q + b;
+  } else {                              // dU^s[i'][a_1..a_d], a_d fastest
+    const int c = col - (d + 1) * nK, s = c / (Q * nQd), ip = (c / nQd) % Q, f = c % nQd;
+    int a[3] = {0, 0, 0}, rem = f;
+    for (int j = d - 1; j >= 0; --j) {
+      a[j] = rem % Q;
+      rem /= Q;
+    }
+    for (int64_t r = r0; r < r1; ++r) {
+      T prod = DQ[(size_t(r) * 4 + s) * kTq + ip];
+      for (int j = 0; j < d; ++j) prod *= PJ[(size_t(r) * 3 + j) * kTq + a[j]];
+      acc += double(prod);
+    }
+    out = offTU + (int64_t(s) * Q + ip) * nQd + f;
+  }
+  gpart[size_t(split) * n_params + out] = acc;
+}
+
+template <typename T>
+hipError_t tn_bwd_site(const TnAdj<T>& A, const int* pidx, int i, int stage, int64_t Rpad, const T* Hbuf,
+                       const T* Dc, T* dcarry, int rows_per_split, int nsplit, double* gpart, int64_t n_params,
+                       hipStream_t st) {
+  const unsigned rb = unsigned((Rpad + 63) / 64);
+  if (stage == 0) {
+    hipLaunchKernelGGL(k_tn_bwd_pre<T>, dim3(rb), dim3(64), 0, st, A.P, pidx, i, Rpad, Hbuf, A.TT, A.PJ, A.QS);
+    return hipGetLastError();
+  }
+  hipLaunchKernelGGL(k_tn_bwd_post<T>, dim3(rb), dim3(64), 0, st, A.P, pidx, i, Rpad, Dc, A.PJ, A.DQ, A.DP, dcarry);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int Q = A.tq_host[i], d = A.d_host[i];
+  int64_t nQd = 1;
+  for (int k = 0; k < d; ++k) nQd *= Q;
+  const int64_t ncol = int64_t(d + 1) * A.P.chi * Q + 4 * Q * nQd;
+  hipLaunchKernelGGL(k_tn_bwd_cols<T>, dim3(unsigned((ncol * nsplit + 255) / 256)), dim3(256), 0, st, A.P, pidx, i,
+                     Rpad, rows_per_split, nsplit, Hbuf, Dc, A.PJ, A.QS, A.DQ, A.DP, A.offTK_host[i],
+                     A.offTU_host[i], gpart, n_params);
+  return hipGetLastError();
+}
+
 }  // namespace
+
+hipError_t launch_tn_bwd_site(const TnAdj<double>& A, const int* pidx, int i, int stage, int64_t Rpad,
+                              const double* Hbuf, const double* Dc, double* dcarry, int rows_per_split, int nsplit,
+                              double* gpart, int64_t n_params, hipStream_t st) {
+  return tn_bwd_site<double>(A, pidx, i, stage, Rpad, Hbuf, Dc, dcarry, rows_per_split, nsplit, gpart, n_params, st);
+}
+hipError_t launch_tn_bwd_site(const TnAdj<float>& A, const int* pidx, int i, int stage, int64_t Rpad,
+                              const float* Hbuf, const float* Dc, float* dcarry, int rows_per_split, int nsplit,
+                              double* gpart, int64_t n_params, hipStream_t st) {
+  return tn_bwd_site<float>(A, pidx, i, stage, Rpad, Hbuf, Dc, dcarry, rows_per_split, nsplit, gpart, n_params, st);
+}
 
 size_t tn_lds_bytes(int W, int rw, int precision) {
   return (size_t(W) * rw + 16) * kTnThreads * (precision == 0 ? 8 : 4);
 }
 
 hipError_t launch_psi_tn_f64(const TnParams<double>& P, const uint64_t* m, int64_t R, double* lphi, int8_t* sphi,
-                             hipStream_t st) {
-  return run_tn<double, false>(P, m, R, lphi, sphi, st, SampleArgs());
+                             hipStream_t st, double* hs, int64_t ns) {
+  return run_tn<double, false>(P, m, R, lphi, sphi, st, SampleArgs(), hs, ns);
 }
 hipError_t launch_psi_tn_f32(const TnParams<float>& P, const uint64_t* m, int64_t R, double* lphi, int8_t* sphi,
-                             hipStream_t st) {
-  return run_tn<float, false>(P, m, R, lphi, sphi, st, SampleArgs());
+                             hipStream_t st, float* hs, int64_t ns) {
+  return run_tn<float, false>(P, m, R, lphi, sphi, st, SampleArgs(), hs, ns);
 }
 hipError_t launch_sample_tn_f64(const TnParams<double>& P, int64_t R, double* lphi, int8_t* sphi, hipStream_t st,
                                 const SampleArgs& SA) {

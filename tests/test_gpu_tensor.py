@@ -1,7 +1,8 @@
 """GPU BDG-TensorRNN (Sec. 2.2, Eqs. (12)-(13)) against the FP64 oracle:
 log|Psi| of whole sectors and sample sets, local energies, exact draws from
-Phi^2 (bit-exact unique draws and counts in FP64), FP32 within the stated
-bounds, and the unsupported forms rejected cleanly."""
+Phi^2 (bit-exact unique draws and counts in FP64), the gradient through the
+tensor term and one VMC step, FP32 within the stated bounds, and the
+unsupported forms rejected cleanly."""
 import numpy as np
 import pytest
 import torch
@@ -145,8 +146,47 @@ def test_unsupported_forms(nqs, ctx):
     w, inst, ans = setup(nqs, ctx, "c1t")
     with pytest.raises(nqs.NqsError):
         ans.logpsi(w.samples, "bf16")
-    with pytest.raises(nqs.NqsError):
-        ans.vjp(w.samples, torch.ones(w.n_samples, dtype=torch.float64))
+
+
+@pytest.mark.parametrize("name,n,prec,tol", [("c1t", None, "f64", 1e-10), ("c8t", 64, "f64", 1e-10),
+                                             ("c2t", 24, "f64", 1e-10), ("c8t", 64, "f32", 1e-4),
+                                             ("c2t", 24, "f32", 1e-4)])
+def test_vjp(nqs, ctx, name, n, prec, tol):
+    """Gradient of sum g log|Psi| over all parameters, the tensor factors and
+    cores included (sites with two and three parents), against the oracle:
+    FP64 at 1e-10 of the largest entry, FP32 at 1e-4 of it."""
+    w, inst, ans = setup(nqs, ctx, name, n)
+    g = np.random.default_rng(8).standard_normal(w.n_samples)
+    got = ans.vjp(w.samples, torch.from_numpy(g), prec).cpu().numpy()
+    ref = oracle.grad(w.K, w.chi, w.n_alpha, w.n_beta, w.parent_ptr, w.parent_idx, 0, w.params, w.samples, g,
+                      tensor=True)
+    err = np.abs(got - ref).max() / np.abs(ref).max()
+    base = W.n_params(w.K, w.chi, w.parent_ptr, 0)
+    terr = np.abs(got[base:] - ref[base:]).max() / np.abs(ref[base:]).max()
+    print(f"{name} {prec} tensor vjp: max error {err:.2e} of the largest entry ({terr:.2e} on the tensor block)")
+    assert err <= tol and terr <= tol
+
+
+def test_vmc_step_matches_oracle_f64(nqs, ctx):
+    """One VMC step with the tensor term (sampling, local energies, the
+    adjoint through the tensor term, AdamW) against the oracle's step."""
+    w = W.make_workload("c8t", n_samples=16)
+    inst = nqs.Instance(ctx, w.K, w.n_alpha, w.n_beta, w.h, w.eri, w.e_core)
+    ans = nqs.Ansatz(ctx, w.K, w.n_alpha, w.n_beta, w.chi, w.parent_ptr, w.parent_idx, 0, tensor=True)
+    ans.bind(w.params)
+    hp = dict(lr=2e-2, beta1=0.9, beta2=0.999, adam_eps=1e-8, weight_decay=1e-3)
+    p = torch.from_numpy(w.params.copy()).cuda()
+    m, v, g = torch.zeros_like(p), torch.zeros_like(p), torch.zeros_like(p)
+    st = nqs.vmc_step(ctx, inst, ans, p, m, v, 1, n_draws=2000, sample_seed=5, precision="f64", seed=w.seed,
+                      stream_id=3, grad=g, **hp)
+    ref = oracle.vmc_step(w.K, w.n_alpha, w.n_beta, w.h, w.eri, w.chi, w.parent_ptr, w.parent_idx, 0, w.params,
+                          np.zeros(w.params.size), np.zeros(w.params.size), 1, 2000, 5, 0, eloc_seed=w.seed,
+                          stream=3, tensor=True, **hp)
+    assert st["n_unique"] == len(ref["samples"])
+    assert abs(st["E"] - ref["E"]) <= 1e-10 * max(1.0, abs(ref["E"]))
+    gg = g.cpu().numpy()
+    assert np.abs(gg - ref["grad"]).max() <= 1e-9 * np.abs(ref["grad"]).max() + 1e-12
+    assert np.abs(p.cpu().numpy() - ref["params"]).max() <= 1e-6 * hp["lr"]
 
 
 @pytest.mark.parametrize("chi", [32, 64])
