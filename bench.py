@@ -404,6 +404,87 @@ def run_next_bench(args):
     print(json.dumps(line), flush=True)
 
 
+def run_configs_bench(args):
+    """The other synthetic configurations at one GPU: K=50 with the cos-RBM
+    (BF16 against FP32 and FP64), the dense K=20 and the 3x3x2 lattice K=18 at
+    chi=64 (FP32 and FP64 local energies, FP32 and FP64 gradients of 8192
+    samples).  Per precision: throughput, stage times, the row kernel against
+    its MFMA peak, and the batch energy against the FP64 GPU path in units of its
+    sampling standard error (equal energy error).  One JSON line."""
+    import numpy as np
+    import torch
+    from paper_2507_19276_amd import nqs, workloads
+
+    torch.cuda.set_device(0)
+    ctx = nqs.Context(0)
+    out = {}
+    plan = {"c3": ("bf16", "f32", "f64"), "c4a": ("f32", "f64"), "c4b": ("f32", "f64")}
+    for name, precs in plan.items():
+        w = workloads.make_workload(name)
+        inst = nqs.Instance(ctx, w.K, w.n_alpha, w.n_beta, w.h, w.eri, w.e_core)
+        ans = nqs.Ansatz(ctx, w.K, w.n_alpha, w.n_beta, w.chi, w.parent_ptr, w.parent_idx, w.n_hidden)
+        ans.bind(w.params)
+        s = torch.from_numpy(w.samples.view(np.int64)).cuda().contiguous()
+        res, energies = {}, {}
+        for prec in precs:
+            kw = dict(eps=w.eps, n_eps=w.n_eps, precision=prec, seed=w.seed, stream_id=0)
+            nqs.eloc(ctx, inst, ans, s, **kw)
+            torch.cuda.synchronize()
+            reps = 2
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                o, st = nqs.eloc(ctx, inst, ans, s, **kw)
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) / reps
+            el = o["eloc"].cpu().numpy()
+            f2 = o["fsq"].cpu().numpy()
+            ok = np.isfinite(el)
+            E = float(st["E"])
+            # standard error of the |f|^2-weighted mean (a self-normalised estimator):
+            # sqrt(sum w^2 (E_loc - E)^2) / sum w, and its effective sample count
+            wf = f2[ok]
+            se = float(np.sqrt((wf ** 2 * (el[ok] - E) ** 2).sum()) / wf.sum())
+            ess = float(wf.sum() ** 2 / (wf ** 2).sum())
+            energies[prec] = (E, se)
+            fl = st["psi_flops"] / (st["ms_psi"] * 1e-3) / 1e12
+            res[prec] = {"local_energies_per_s": w.n_samples / dt, "ms_per_step": dt * 1e3, "rows": st["n_rows"],
+                         "site_rows": st["n_site_rows"], "E": E, "sampling_se": se, "effective_samples": ess,
+                         "stage_ms": {k: st[k] for k in ("ms_enumerate", "ms_draw", "ms_rows", "ms_amplitude",
+                                                          "ms_reduce", "ms_psi")},
+                         "roofline": {"bound": "mfma", "achieved": fl, "peak": PEAKS[prec], "unit": "TFLOP/s",
+                                      "frac": fl / PEAKS[prec], "flops_per_launch": st["psi_flops"],
+                                      "kernel": "row amplitude kernel"}}
+            print(f"# {name} {prec}: {w.n_samples / dt:.0f} E_loc/s, {st['n_rows']} rows, row kernel "
+                  f"{st['ms_psi']:.1f} ms at {fl:.1f} TFLOP/s", file=sys.stderr, flush=True)
+        E64, se64 = energies["f64"]
+        for prec in precs:
+            res[prec]["energy_error_in_se_vs_f64_gpu"] = abs(energies[prec][0] - E64) / se64
+        if name in ("c4a", "c4b"):
+            g = torch.randn(w.n_samples, dtype=torch.float64, device="cuda")
+            for prec in ("f32", "f64"):
+                ans.vjp(s, g, prec)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                ans.vjp(s, g, prec)
+                torch.cuda.synchronize()
+                res[f"vjp_{prec}_ms"] = (time.perf_counter() - t0) * 1e3
+                print(f"# {name} vjp {prec}: {res[f'vjp_{prec}_ms']:.1f} ms", file=sys.stderr, flush=True)
+        res["workload"] = {"K": w.K, "n_alpha": w.n_alpha, "n_beta": w.n_beta, "chi": w.chi, "n_hidden": w.n_hidden,
+                           "samples": w.n_samples, "eps": w.eps, "n_eps": w.n_eps}
+        out[name] = res
+        del inst, ans
+    line = {
+        "metric": "local energies/sec at fixed bond dim D on the other configurations",
+        "value": out["c3"]["bf16"]["local_energies_per_s"], "unit": "local energies/s (c3, BF16; the rest below)",
+        "n_gpus": 1, "steps": 2, "warmup": 1, "ms_per_step": out["c3"]["bf16"]["ms_per_step"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16", "data": "synthetic",
+        "config": {"workload": "c3 K=50 NN+NNN chi=32 cos-RBM N_h=100 16384 samples; c4a K=20 15a+15b dense "
+                               "NN+NNN chi=64 8192 samples; c4b K=18 3x3x2 lattice chi=64 8192 samples"},
+        **out,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -421,6 +502,8 @@ def main():
     ap.add_argument("--serve", action="store_true")
     ap.add_argument("--next", action="store_true",
                     help="time the sampler, the Ising-RBM, BDG-TensorRNN and complex paths and one VMC step")
+    ap.add_argument("--configs", action="store_true",
+                    help="time the K=50, dense K=20 and lattice K=18 configurations per precision")
     ap.add_argument("--requests", type=int, default=500)
     ap.add_argument("--load", type=float, default=0.8)
     ap.add_argument("--slots", type=int, default=4)
@@ -435,6 +518,8 @@ def main():
         run_serve_bench(args)
     elif args.next:
         run_next_bench(args)
+    elif args.configs:
+        run_configs_bench(args)
     else:
         run_eloc_bench(args)
 
