@@ -338,12 +338,13 @@ def run_next_bench(args):
         kw = dict(eps=w.eps, n_eps=w.n_eps, precision=prec, stream_id=0)
         dt, (o, st) = timed(lambda: nqs.eloc(ctx, inst, ans, s, seed=w.seed, **kw), 3)
         fl = st["psi_flops"] / (st["ms_psi"] * 1e-3) / 1e12
-        peak = 157.3 if prec == "f32" else 78.6
         tens[prec] = {"local_energies_per_s": w.n_samples / dt, "ms_per_step": dt * 1e3,
                       "row_kernel_ms": st["ms_psi"], "site_rows": st["n_site_rows"],
-                      "roofline": {"bound": "alu", "achieved": fl, "peak": peak, "unit": "TFLOP/s",
-                                   "frac": fl / peak, "kernel": f"k_psi_tn<{'float' if prec == 'f32' else 'double'},false>",
-                                   "flops_per_launch": st["psi_flops"]}}
+                      "roofline": {"bound": "mfma", "achieved": fl, "peak": PEAKS[prec], "unit": "TFLOP/s",
+                                   "frac": fl / PEAKS[prec],
+                                   "kernel": f"k_psi_mt<{'float' if prec == 'f32' else 'double'},16,...,TN> (rows)",
+                                   "flops_per_launch": st["psi_flops"],
+                                   "note": "algorithmic flops (chi' = 7 unpadded) of the resumed rows"}}
         print(f"# tensor {prec}: {w.n_samples / dt:.0f} E_loc/s, row kernel {st['ms_psi']:.2f} ms, {fl:.2f} TFLOP/s",
               file=sys.stderr, flush=True)
     out["bdg_tensor_rnn_nnn_K20_chi16"] = tens

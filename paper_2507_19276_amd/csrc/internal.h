@@ -57,6 +57,12 @@ struct PsiParams {
   bool folded;                   // operands carry sqrt(eta) (see k_psi_mt); never with a carried-state store
   const T* w2 = nullptr;         // complex parameters (realified state): [K][chip] vector of Im z
   const T* c2 = nullptr;         // [K] Im c
+  // BDG-TensorRNN term on MFMA (chip <= 32, chi' <= 8): the operand stream
+  // (per tensor site: projections [parent][k-step][lane], core
+  // [k-step][tile 0..1][lane], output factor [state][tile][v][lane], built in
+  // runtime.cpp) and per site {chi' (0: none), offsets of the three parts}
+  const T* TA = nullptr;
+  const int* tsite = nullptr;    // [K][4]
 };
 
 // BDG-TensorRNN forward (tensor_rnn.hip), one precision T.

@@ -46,7 +46,7 @@ template <typename T> constexpr int prefetch_ksteps(int CH) {
   return (CH / 4) < 64 / ((CH / 4) * int(sizeof(T) / 4)) ? (CH / 4) : 64 / ((CH / 4) * int(sizeof(T) / 4));
 }
 
-template <typename T, int CH, int NTL, bool FOLD, int STORE, bool SEED, bool SAMPLE, bool CPLX>
+template <typename T, int CH, int NTL, bool FOLD, int STORE, bool SEED, bool SAMPLE, bool CPLX, bool TN>
 __global__ __launch_bounds__(256) void k_psi_mt(PsiParams<T> P, const uint64_t* __restrict__ m, int64_t R,
                                                 double* __restrict__ lphi, int8_t* __restrict__ sphi, int wpb,
                                                 PsiStates<T> X, SampleArgs SA, double* __restrict__ phs) {
@@ -79,6 +79,7 @@ __global__ __launch_bounds__(256) void k_psi_mt(PsiParams<T> P, const uint64_t* 
   const CInt* slots = (const CInt*)(P.slot);
   const CT<T>* cc = (const CT<T>*)(P.c);
   const CT<T>* cc2 = (const CT<T>*)(P.c2);
+  const CInt* tsite = (const CInt*)(P.tsite);
   // SEED: positions base.. map to rows X.perm[pos], sorted by their first
   // changed site, and the wavefront starts at the site of its first row
   const int i0 = SEED ? int(((const __attribute__((address_space(4))) uint8_t*)X.t0)[base]) : 0;
@@ -241,9 +242,21 @@ __global__ __launch_bounds__(256) void k_psi_mt(PsiParams<T> P, const uint64_t* 
       if (!FOLD) ev4[tt] = *reinterpret_cast<const V*>(P.eta + size_t(i) * CH + 16 * tt + 4 * g);
       if (CPLX) w2v4[tt] = *reinterpret_cast<const V*>(P.w2 + size_t(i) * CH + 16 * tt + 4 * g);
     }
-    const int e1 = fptr[i + 1];
-    // one edge: a chi-wide slice of the contraction over the parents
-    auto edge = [&]() {
+    const int e0s = fptr[i], e1 = fptr[i + 1];
+    // TN: the site's tensor term (chi' = tQ, 0 for none) and its operand streams
+    int tQ = 0, toP = 0, toC = 0, toK = 0;
+    if constexpr (TN) {
+      tQ = tsite[4 * i];
+      toP = tsite[4 * i + 1];
+      toC = tsite[4 * i + 2];
+      toK = tsite[4 * i + 3];
+    }
+    V pr0[NTL], pr1[NTL], pr2[NTL];   // TN: projections p_j = K_j^T h_j of the parents
+#pragma unroll
+    for (int t = 0; t < NTL; ++t) pr2[t] = V{0, 0, 0, 0};
+    // one edge: a chi-wide slice of the contraction over the parents (TN: and
+    // the projection of the parent's state into pt)
+    auto edge = [&](V (&pt)[NTL]) {
       const T* Ae = Ab + size_t(e) * ES;
       V b[NTL][TPC];
       const V* rp = ring + size_t(slots[e]) * SLOT;
@@ -269,6 +282,21 @@ __global__ __launch_bounds__(256) void k_psi_mt(PsiParams<T> P, const uint64_t* 
       for (int q = 0; q < PQ; ++q)
 #pragma unroll
         for (int ot = 0; ot < NT; ++ot) an[q][ot] = nx[q][ot];
+      if constexpr (TN) {
+        if (tQ > 0) {
+          // projection of this parent's state: one 16-row output tile whose
+          // lane group g holds p[2g + v] in registers v = 0, 1
+          const T* Ap = P.TA + toP + size_t(e - e0s) * KS * 64 + lane;
+#pragma unroll
+          for (int t = 0; t < NTL; ++t) pt[t] = V{0, 0, 0, 0};
+#pragma unroll
+          for (int q = 0; q < KS; ++q) {
+            const T a = Ap[q * 64];
+#pragma unroll
+            for (int t = 0; t < NTL; ++t) pt[t] = mfma(a, b[t][q / 4][q % 4], pt[t]);
+          }
+        }
+      }
     };
     if (!BPF) fetch_bias(i);
     // the contractions run at raised wave priority: an MFMA then issues as soon
@@ -280,7 +308,63 @@ __global__ __launch_bounds__(256) void k_psi_mt(PsiParams<T> P, const uint64_t* 
 #pragma unroll
       for (int t = 0; t < NTL; ++t) acc[t][ot] = vn[ot];
     if (BPF) fetch_bias(i + 1 < P.K ? i + 1 : i);
-    do edge(); while (++e < e1);
+    if (TN && tQ > 0) {
+      // a tensor site has 2 or 3 parents: each edge's projection into its own registers
+      edge(pr0);
+      ++e;
+      edge(pr1);
+      if (++e < e1) {
+        edge(pr2);
+        ++e;
+      }
+    } else {
+      do edge(pr0); while (++e < e1);
+    }
+    if constexpr (TN) {
+      if (tQ > 0) {
+        // core contraction q^s[i'] = sum_a U^s[i'][a] prod_j p_j[a_j] as two
+        // 16-row MFMA tiles over (s, i') (8 rows per state), the k-steps over
+        // (a_1 .. a_(d-1), v) with a_d = 2g + v from the lane's own projection
+        // registers and the other factors broadcast from the row's four lanes;
+        // then t^s = K0 q^s into the candidates, k-steps over the lane's own q
+        // registers
+        const int d = e1 - e0s;
+        const T* Ac = P.TA + toC + lane;
+        const T* Ak = P.TA + toK + lane;
+#pragma unroll
+        for (int t = 0; t < NTL; ++t) {
+          const V plast = d == 3 ? pr2[t] : pr1[t];
+          V q0 = V{0, 0, 0, 0}, q1 = V{0, 0, 0, 0};
+          int kk = 0;
+#pragma unroll
+          for (int a1 = 0; a1 < 8; ++a1) {
+            if (a1 >= tQ) break;
+            // p_1[a1] from the lane of the row that holds it (a = 2 g + v)
+            const T b0 = __shfl(pr0[t][a1 & 1], j + 16 * (a1 >> 1));
+#pragma unroll
+            for (int a2 = 0; a2 < 8; ++a2) {
+              if (a2 >= (d == 3 ? tQ : 1)) break;
+              const T f = d == 3 ? b0 * __shfl(pr1[t][a2 & 1], j + 16 * (a2 >> 1)) : b0;
+#pragma unroll
+              for (int v = 0; v < 2; ++v) {
+                const T bv = f * plast[v];
+                q0 = mfma(Ac[(size_t(kk) * 2 + 0) * 64], bv, q0);
+                q1 = mfma(Ac[(size_t(kk) * 2 + 1) * 64], bv, q1);
+                ++kk;
+              }
+            }
+          }
+#pragma unroll
+          for (int s = 0; s < 4; ++s)
+#pragma unroll
+            for (int tt = 0; tt < TPC; ++tt)
+#pragma unroll
+              for (int v = 0; v < 4; ++v)
+                acc[t][s * TPC + tt] =
+                    mfma(Ak[((s * TPC + tt) * 4 + v) * 64], s < 2 ? q0[v] : q1[v], acc[t][s * TPC + tt]);
+        }
+      }
+    }
     __builtin_amdgcn_s_setprio(0);
     if constexpr (SAMPLE) {
       // sampling: the row's local state is drawn from its masked conditionals
@@ -489,7 +573,8 @@ template <typename T> constexpr int ntiles(int CH) {
   return sizeof(T) == 4 ? (CH <= 16 ? NQS_NTL_F32_16 : (CH <= 32 ? 2 : 1)) : (CH <= 16 ? 2 : 1);
 }
 
-template <typename T, int CH, bool FOLD, int STORE, bool SEED, bool SAMPLE = false, bool CPLX = false>
+template <typename T, int CH, bool FOLD, int STORE, bool SEED, bool SAMPLE = false, bool CPLX = false,
+          bool TN = false>
 hipError_t run_psi_mt(const PsiParams<T>& P, const uint64_t* m, int64_t R, double* lphi, int8_t* sphi,
                       hipStream_t st, const PsiStates<T>& X, const SampleArgs& SA = SampleArgs(),
                       double* phs = nullptr) {
@@ -501,7 +586,7 @@ hipError_t run_psi_mt(const PsiParams<T>& P, const uint64_t* m, int64_t R, doubl
   if (per_wave * wpb > 160 * 1024) return hipErrorInvalidValue;
   const int64_t tiles = (R + 16 * NTL - 1) / (16 * NTL);
   const int64_t blocks = (tiles + wpb - 1) / wpb;
-  hipLaunchKernelGGL((k_psi_mt<T, CH, NTL, FOLD, STORE, SEED, SAMPLE, CPLX>), dim3(unsigned(blocks)),
+  hipLaunchKernelGGL((k_psi_mt<T, CH, NTL, FOLD, STORE, SEED, SAMPLE, CPLX, TN>), dim3(unsigned(blocks)),
                      dim3(64 * wpb), per_wave * wpb, st, P, m, R, lphi, sphi, wpb, X, SA, phs);
   return hipGetLastError();
 }
@@ -509,6 +594,30 @@ hipError_t run_psi_mt(const PsiParams<T>& P, const uint64_t* m, int64_t R, doubl
 template <typename T, int CH>
 hipError_t run_psi_ch(const PsiParams<T>& P, const uint64_t* m, int64_t R, double* lphi, int8_t* sphi,
                       hipStream_t st, const PsiStates<T>& X, int mode, double* phs) {
+  if (P.TA) {
+    // tensor term on MFMA (chip <= 32, chi' <= 8)
+    if constexpr (CH <= 32) {
+      if (phs) return hipErrorInvalidValue;
+      const SampleArgs no;
+      switch (mode) {
+        case PSI_PLAIN:
+          if (P.folded) return run_psi_mt<T, CH, true, 0, false, false, false, true>(P, m, R, lphi, sphi, st, X, no);
+          return run_psi_mt<T, CH, false, 0, false, false, false, true>(P, m, R, lphi, sphi, st, X, no);
+        case PSI_STORE:
+          if (P.folded) return run_psi_mt<T, CH, true, 1, false, false, false, true>(P, m, R, lphi, sphi, st, X, no);
+          return run_psi_mt<T, CH, false, 1, false, false, false, true>(P, m, R, lphi, sphi, st, X, no);
+        case PSI_SEED:
+          if (P.folded) return run_psi_mt<T, CH, true, 0, true, false, false, true>(P, m, R, lphi, sphi, st, X, no);
+          return run_psi_mt<T, CH, false, 0, true, false, false, true>(P, m, R, lphi, sphi, st, X, no);
+        case PSI_NODE:
+          if (P.folded) return run_psi_mt<T, CH, true, 2, true, false, false, true>(P, m, R, lphi, sphi, st, X, no);
+          return run_psi_mt<T, CH, false, 2, true, false, false, true>(P, m, R, lphi, sphi, st, X, no);
+        default:
+          return hipErrorInvalidValue;
+      }
+    }
+    return hipErrorInvalidValue;
+  }
   if (phs) {
     // complex parameters: the phase of each row
     if (!P.w2 || !P.c2) return hipErrorInvalidValue;
@@ -554,6 +663,14 @@ hipError_t run_psi_ch(const PsiParams<T>& P, const uint64_t* m, int64_t R, doubl
 template <typename T, int CH>
 hipError_t run_sample_ch(const PsiParams<T>& P, int64_t R, double* lphi, int8_t* sphi, hipStream_t st,
                          const SampleArgs& SA) {
+  if (P.TA) {
+    if constexpr (CH <= 32) {
+      if (P.folded)
+        return run_psi_mt<T, CH, true, 0, false, true, false, true>(P, nullptr, R, lphi, sphi, st, PsiStates<T>(), SA);
+      return run_psi_mt<T, CH, false, 0, false, true, false, true>(P, nullptr, R, lphi, sphi, st, PsiStates<T>(), SA);
+    }
+    return hipErrorInvalidValue;
+  }
   if (P.folded) return run_psi_mt<T, CH, true, 0, false, true>(P, nullptr, R, lphi, sphi, st, PsiStates<T>(), SA);
   return run_psi_mt<T, CH, false, 0, false, true>(P, nullptr, R, lphi, sphi, st, PsiStates<T>(), SA);
 }

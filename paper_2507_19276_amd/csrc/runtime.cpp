@@ -189,16 +189,17 @@ struct PsiLayout {
   T* c = nullptr;
   T* w2 = nullptr;          // complex parameters: [K][chip] vector of Im z, (folded like w)
   T* c2 = nullptr;          // [K]
+  T* TA = nullptr;          // BDG-TensorRNN term on MFMA (PsiParams::TA)
   T* AF = nullptr;          // adjoint: recompute operands (k-permuted)
   int64_t* afoff = nullptr;
   T* BT = nullptr;          // adjoint: M^T operands
   int64_t* btoff = nullptr;
   bool folded = false;      // operands carry sqrt(eta)
   void free_all() {
-    for (void* p : {(void*)A, (void*)v, (void*)eta, (void*)w, (void*)c, (void*)w2, (void*)c2, (void*)AF,
-                    (void*)afoff, (void*)BT, (void*)btoff})
+    for (void* p : {(void*)A, (void*)v, (void*)eta, (void*)w, (void*)c, (void*)w2, (void*)c2, (void*)TA,
+                    (void*)AF, (void*)afoff, (void*)BT, (void*)btoff})
       if (p) (void)hipFree(p);
-    A = nullptr; v = eta = w = c = w2 = c2 = nullptr;
+    A = nullptr; v = eta = w = c = w2 = c2 = TA = nullptr;
     AF = nullptr; afoff = nullptr; BT = nullptr; btoff = nullptr;
   }
 };
@@ -240,6 +241,12 @@ struct nqs_ansatz {
   int tn_qp = 16;           // 8 when every chi' <= 8
   bool tn_f64_ok = true;    // the FP64 ring fits the LDS
   std::vector<int> tn_edge_host, tn_site_host;
+  // the tensor term on the MFMA forward (chip <= 32 and every chi' <= 8): per
+  // site {chi', offsets of projections, core, output factor} in PsiLayout::TA
+  bool tn_mfma = false;
+  std::vector<int> tsite_host;
+  int64_t ta_size = 0;
+  int* d_tsite = nullptr;
   int64_t* d_offM = nullptr;
   int64_t* d_offV = nullptr;
   int64_t* d_offEta = nullptr;
@@ -261,7 +268,7 @@ struct nqs_ansatz {
     for (void* p : {(void*)d_pptr, (void*)d_pidx, (void*)d_slot, (void*)d_fptr, (void*)d_fslot, (void*)bfA,
                     (void*)d_cb, (void*)d_cW, (void*)d_cW1t, (void*)d_cS, (void*)d_cS32, (void*)d_tn_edge,
                     (void*)d_tn_site, (void*)tn64, (void*)tn32, (void*)d_offM, (void*)d_offV,
-                    (void*)d_offEta, (void*)d_cx})
+                    (void*)d_offEta, (void*)d_cx, (void*)d_tsite})
       if (p) (void)hipFree(p);
   }
   template <typename T>
@@ -282,6 +289,8 @@ struct nqs_ansatz {
     P.A = L.A; P.v = L.v; P.eta = L.eta; P.w = L.w; P.c = L.c;
     P.folded = L.folded;
     P.w2 = L.w2; P.c2 = L.c2;
+    P.TA = tn_mfma ? L.TA : nullptr;
+    P.tsite = d_tsite;
     return P;
   }
   CxMap cxmap() const {
@@ -391,8 +400,68 @@ nqs_status build_layout(nqs_ansatz* a, const std::vector<double>& prm, PsiLayout
       c2[i] = T(prm[a->offC2x[i]]);
     }
   }
+  // the tensor term's MFMA operands (see PsiParams::TA); A row m of a tile
+  // carries logical row o(m) so that lane group g holds rows 4g + v in its
+  // output registers v (f64 MFMA rows g + 4v)
+  std::vector<T> TA;
+  if (a->tn_mfma) {
+    TA.assign(a->ta_size, T(0));
+    auto orow = [](int m) { return sizeof(T) == 8 ? 4 * (m & 3) + (m >> 2) : m; };
+    const int KSq = CH / 4, TPCq = CH / 16;
+    for (int i = 0; i < K; ++i) {
+      const int Q = a->tsite_host[4 * i];
+      if (!Q) continue;
+      const int d = a->pptr[i + 1] - a->pptr[i];
+      const double* si = sig.data() + size_t(i) * chi;
+      T* P0 = TA.data() + a->tsite_host[4 * i + 1];
+      T* C0 = TA.data() + a->tsite_host[4 * i + 2];
+      T* K0s = TA.data() + a->tsite_host[4 * i + 3];
+      const double* Kp = prm.data() + a->offTK[i];            // K^(0..d), chi x chi' each
+      const double* Up = prm.data() + a->offTU[i];            // U^s, chi'^(d+1) each
+      // projections: output row o -> p index a = 2 (o / 4) + o % 4 for o % 4 < 2
+      for (int jx = 0; jx < d; ++jx) {
+        const double* sj = sig.data() + size_t(a->pidx[a->pptr[i] + jx]) * chi;
+        for (int q = 0; q < KSq; ++q)
+          for (int l = 0; l < 64; ++l) {
+            const int o = orow(l & 15), pa = 2 * (o >> 2) + (o & 3);
+            const int k = 16 * (q >> 2) + 4 * (l >> 4) + (q & 3);
+            double val = 0.0;
+            if ((o & 3) < 2 && pa < Q && k < chi) val = Kp[size_t(jx + 1) * chi * Q + size_t(k) * Q + pa] / sj[k];
+            P0[(size_t(jx) * KSq + q) * 64 + l] = T(val);
+          }
+      }
+      // core: k-step kk = (a_1 [, a_2]) * 2 + v, lane group g supplies a_d = 2 g + v;
+      // tile mt row o holds (s, i') = ((16 mt + o) / 8, (16 mt + o) % 8)
+      int nlead = 1;
+      for (int k = 0; k < d - 1; ++k) nlead *= Q;
+      size_t qd = 1;
+      for (int k = 0; k < d; ++k) qd *= Q;
+      for (int kk = 0; kk < nlead * 2; ++kk)
+        for (int mt = 0; mt < 2; ++mt)
+          for (int l = 0; l < 64; ++l) {
+            const int row = 16 * mt + orow(l & 15), s_ = row / 8, ip = row % 8;
+            const int ad = 2 * (l >> 4) + (kk & 1), lead = kk >> 1;
+            double val = 0.0;
+            if (ip < Q && ad < Q) val = Up[(size_t(s_) * Q + ip) * qd + size_t(lead) * Q + ad];
+            C0[(size_t(kk) * 2 + mt) * 64 + l] = T(val);
+          }
+      // output factor: for state s, tile tt, k-step v, lane group g supplies the q
+      // row 4g + v of core tile s / 2, i.e. (s', i') = (2 (s / 2) + g / 2, 4 (g % 2) + v)
+      for (int s_ = 0; s_ < 4; ++s_)
+        for (int tt = 0; tt < TPCq; ++tt)
+          for (int v = 0; v < 4; ++v)
+            for (int l = 0; l < 64; ++l) {
+              const int u = 16 * tt + orow(l & 15), g = l >> 4;
+              const int sq = 2 * (s_ / 2) + g / 2, ip = 4 * (g % 2) + v;
+              double val = 0.0;
+              if (sq == s_ && ip < Q && u < chi) val = si[u] * Kp[size_t(u) * Q + ip];
+              K0s[((size_t(s_) * TPCq + tt) * 4 + v) * 64 + l] = T(val);
+            }
+    }
+  }
   auto upload_cx = [&]() -> nqs_status {
     nqs_status st;
+    if (a->tn_mfma && (st = upload(&L.TA, TA)) != NQS_OK) return st;
     if (!a->cplx) return NQS_OK;
     if ((st = upload(&L.w2, w2)) != NQS_OK) return st;
     return upload(&L.c2, c2);
@@ -890,6 +959,27 @@ nqs_status nqs_ansatz_create(nqs_ctx* ctx, int K, int n_alpha, int n_beta, int c
     if ((st = upload(&a->d_tn_site, site)) != NQS_OK) return st;
     a->tn_edge_host = edge;
     a->tn_site_host = site;
+    // the MFMA forward carries the tensor term when chip <= 32 and chi' <= 8
+    a->tn_mfma = a->chip <= 32 && qmax <= 8;
+    if (a->tn_mfma) {
+      const int KSq = a->chip / 4, TPCq = a->chip / 16;
+      std::vector<int> ts(size_t(K) * 4, 0);
+      int64_t cur = 0;
+      for (int i = 0; i < K; ++i) {
+        const int tq = a->tq[i], d = a->pptr[i + 1] - a->pptr[i];
+        if (!tq) continue;
+        int nlead = 1;
+        for (int k = 0; k < d - 1; ++k) nlead *= tq;
+        ts[4 * i] = tq;
+        ts[4 * i + 1] = int(cur); cur += int64_t(d) * KSq * 64;
+        ts[4 * i + 2] = int(cur); cur += int64_t(nlead) * 2 * 2 * 64;
+        ts[4 * i + 3] = int(cur); cur += int64_t(4) * TPCq * 4 * 64;
+      }
+      if (cur >= (int64_t(1) << 31)) return fail(NQS_EUNSUPPORTED, "tensor-RNN operand stream too large");
+      a->ta_size = cur;
+      a->tsite_host = ts;
+      if ((st = upload(&a->d_tsite, ts)) != NQS_OK) return st;
+    }
   }
   *out = a.release();
   return NQS_OK;
@@ -1113,7 +1203,9 @@ nqs_status run_amplitudes(const nqs_ansatz* a, int precision, const uint64_t* m,
     }
     return NQS_OK;
   }
-  if (a->tensor) {
+  if (a->tensor && precision == NQS_BF16) return fail(NQS_EUNSUPPORTED, "the tensor-RNN runs in FP64 or FP32");
+  if (a->tensor && !a->tn_mfma) {
+    // the thread-per-row kernel (chi' > 8 or chi > 32)
     if (mode != PSI_PLAIN) return fail(NQS_EINVAL, "tensor-RNN rows are evaluated from site 0");
     if (precision == NQS_F64) {
       if (!a->tn_f64_ok) return fail(NQS_EUNSUPPORTED, "FP64 tensor-RNN ring does not fit the LDS");
@@ -1537,7 +1629,7 @@ nqs_status eloc_run(nqs_ctx* ctx, const nqs_instance* inst, const nqs_ansatz* an
   double* f2 = fsq ? fsq : S.get<double>(N);
   double* sums = S.get<double>(8);
   const int K = ans->K;
-  const bool resume = resumes(*opts) && !ans->tensor && cap_used < (int64_t(1) << 31);
+  const bool resume = resumes(*opts) && (!ans->tensor || ans->tn_mfma) && cap_used < (int64_t(1) << 31);
   Resume rs;
   double* lphi_s = nullptr;
   int8_t* sphi_s = nullptr;
@@ -1861,10 +1953,10 @@ nqs_status nqs_sample(nqs_ctx* ctx, const nqs_ansatz* ans, int64_t n_draws, uint
     SA.k1 = uint32_t(seed >> 32);
     SA.p0 = draw_base + d0;
     SA.out = m;
-    if (ans->tensor && precision == NQS_F64) {
+    if (ans->tensor && !ans->tn_mfma && precision == NQS_F64) {
       if (!ans->tn_f64_ok) return fail(NQS_EUNSUPPORTED, "FP64 tensor-RNN ring does not fit the LDS");
       HIPCHK(launch_sample_tn_f64(ans->tn<double>(ans->tn64), ch, lphi, sphi, stream, SA));
-    } else if (ans->tensor) {
+    } else if (ans->tensor && !ans->tn_mfma) {
       HIPCHK(launch_sample_tn_f32(ans->tn<float>(ans->tn32), ch, lphi, sphi, stream, SA));
     } else if (precision == NQS_F64) {
       HIPCHK(launch_sample_f64(ans->params(ans->fwd64()), ch, lphi, sphi, stream, SA));

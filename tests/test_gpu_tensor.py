@@ -217,3 +217,17 @@ def test_wide_tucker_rank(nqs, ctx, chi):
     s, c, l2, _, nu = ans.sample(2000, seed=4, precision="f64")
     ru, rc = oracle.sample_unique(K, chi, na, nb, pp, pi, prm, 4, 2000, tensor=True)
     assert np.array_equal(s.cpu().numpy().view(np.uint64), ru) and np.array_equal(c.cpu().numpy(), rc)
+
+
+@pytest.mark.parametrize("name,prec", [("c2t", "f32"), ("c2t", "f64"), ("c8t", "f64")])
+def test_resumed_rows_bit_identical(nqs, ctx, name, prec):
+    """With chi' <= 8 the tensor term runs on the MFMA forward, whose rows
+    resume from the samples' and the nodes' stored states: the same bits as
+    every row evaluated from site 0, with far fewer site evaluations."""
+    w, inst, ans = setup(nqs, ctx, name, 128)
+    kw = dict(eps=w.eps, n_eps=w.n_eps, precision=prec, seed=w.seed, stream_id=2)
+    a, sa = nqs.eloc(ctx, inst, ans, w.samples, **kw)
+    b, sb = nqs.eloc(ctx, inst, ans, w.samples, resume=False, **kw)
+    for k in ("eloc", "etnum", "logabs", "sign"):
+        assert torch.equal(a[k], b[k]), k
+    assert sa["n_site_rows"] < sb["n_site_rows"]
