@@ -570,7 +570,7 @@ __global__ __launch_bounds__(256) void k_psi_mt(PsiParams<T> P, const uint64_t* 
 #define NQS_NTL_F32_16 4
 #endif
 template <typename T> constexpr int ntiles(int CH) {
-  return sizeof(T) == 4 ? (CH <= 16 ? NQS_NTL_F32_16 : (CH <= 32 ? 2 : 1)) : (CH <= 32 ? 2 : 1);
+  return sizeof(T) == 4 ? (CH <= 16 ? NQS_NTL_F32_16 : (CH <= 32 ? 4 : 1)) : (CH <= 32 ? 2 : 1);
 }
 
 template <typename T, int CH, bool FOLD, int STORE, bool SEED, bool SAMPLE = false, bool CPLX = false,
