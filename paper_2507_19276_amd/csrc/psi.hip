@@ -433,8 +433,12 @@ __global__ __launch_bounds__(256) void k_psi_mt(PsiParams<T> P, const uint64_t* 
         const V ww = wv4[tt];
 #pragma unroll
         for (int t = 0; t < NTL; ++t) {
-          const V sel01 = (ch[t] & 1) ? acc[t][1 * TPC + tt] : acc[t][0 * TPC + tt];
-          const V sel23 = (ch[t] & 1) ? acc[t][3 * TPC + tt] : acc[t][2 * TPC + tt];
+          // named copies: a select between two elements of acc would otherwise
+          // become an indexed read and move acc to scratch
+          const V x0 = acc[t][0 * TPC + tt], x1 = acc[t][1 * TPC + tt];
+          const V x2 = acc[t][2 * TPC + tt], x3 = acc[t][3 * TPC + tt];
+          const V sel01 = (ch[t] & 1) ? x1 : x0;
+          const V sel23 = (ch[t] & 1) ? x3 : x2;
           const V sel = (ch[t] & 2) ? sel23 : sel01;
           T d = dp[t];
           d = tfma(ww.x, sel.x, d);
@@ -447,8 +451,11 @@ __global__ __launch_bounds__(256) void k_psi_mt(PsiParams<T> P, const uint64_t* 
       }
       wslot = wslot + 1 == P.W ? 0 : wslot + 1;
       const T dot = ReduceOwn<T, NTL>::run(dp) + T(cc[i]);
+      // the drawn state's weight by selects (an indexed read would put pr in scratch)
+      const T w01 = (pick & 1) ? pr[1] : pr[0];
+      const T w23 = (pick & 1) ? pr[3] : pr[2];
       int ex;
-      prod = tfrexp(prod * (pr[pick] / Z), &ex);
+      prod = tfrexp(prod * (((pick & 2) ? w23 : w01) / Z), &ex);
       pexp += ex;
       if (dot < T(0)) sgn = -sgn;
       ca += pick & 1;
@@ -579,7 +586,10 @@ hipError_t run_psi_mt(const PsiParams<T>& P, const uint64_t* m, int64_t R, doubl
                       hipStream_t st, const PsiStates<T>& X, const SampleArgs& SA = SampleArgs(),
                       double* phs = nullptr) {
   if (R <= 0) return hipSuccess;
-  constexpr int NTL = ntiles<T>(CH);
+  // the sampling epilogue and the tensor term need more registers: at chip 32
+  // two tiles in FP32 (four spill) and one for the FP64 tensor term
+  constexpr int NTL = TN && sizeof(T) == 8 && CH == 32 ? 1
+                      : ((SAMPLE || TN) && sizeof(T) == 4 && CH == 32 ? 2 : ntiles<T>(CH));
   const size_t per_wave = size_t(P.W + 1) * 16 * NTL * CH * sizeof(T);
   int wpb = 4;
   while (wpb > 1 && per_wave * wpb > 64 * 1024) wpb >>= 1;
