@@ -37,8 +37,12 @@ __device__ inline int occ_below(uint64_t lo, uint64_t hi, int P) {
                 : __popcll(lo) + __popcll(hi & ((1ull << (P - 64)) - 1ull));
 }
 
+// by selects: a branch on the word would let the compiler treat (lo, hi) as a
+// two-element array indexed by P / 64 and move it to scratch
 __device__ inline void flip(uint64_t& lo, uint64_t& hi, int P) {
-  if (P < 64) lo ^= 1ull << P; else hi ^= 1ull << (P - 64);
+  const uint64_t bit = 1ull << (P & 63);
+  lo ^= P < 64 ? bit : 0ull;
+  hi ^= P < 64 ? 0ull : bit;
 }
 
 // site (spatial orbital) of the lowest set spin-orbital bit of a nonzero XOR
@@ -60,16 +64,14 @@ __device__ inline void row_sites(uint64_t mlo, uint64_t mhi, uint64_t nlo, uint6
   const int c1 = first_changed_site(xl, xh);
   *t0 = uint8_t(c1);
   if (!sec) return;
-  auto take = [&](int c) {   // the row's state at site c; clears the site from the difference
+  auto take = [&](int c) {   // the row's state at site c; clears the site from the difference (by selects)
     const int P = 2 * c;
-    int st;
-    if (P < 64) {
-      st = int((mlo >> P) & 3ull);
-      xl &= ~(3ull << P);
-    } else {
-      st = int((mhi >> (P - 64)) & 3ull);
-      xh &= ~(3ull << (P - 64));
-    }
+    const bool low = P < 64;
+    const int sh = P & 63;
+    const int st = int(((low ? mlo : mhi) >> sh) & 3ull);
+    const uint64_t keep = ~(3ull << sh);
+    xl &= low ? keep : ~0ull;
+    xh &= low ? ~0ull : keep;
     return st;
   };
   const int s1 = take(c1);
@@ -552,14 +554,13 @@ __global__ __launch_bounds__(256) void k_fill(HamDev H, EnumGeom G, const uint64
 // plain definition); <PQ||PQ> = (pp|qq) - delta_{sigma_P sigma_Q} (pq|qp) from
 // the K x K tables of those entries
 __device__ inline int next_set(uint64_t& lo, uint64_t& hi) {
-  int P;
-  if (lo) {
-    P = __ffsll((unsigned long long)lo) - 1;
-    lo &= lo - 1;
-  } else {
-    P = 64 + __ffsll((unsigned long long)hi) - 1;
-    hi &= hi - 1;
-  }
+  // by selects (a branch per word would put (lo, hi) in scratch)
+  const bool l = lo != 0;
+  const uint64_t w = l ? lo : hi;
+  const int P = (l ? 0 : 64) + __ffsll((unsigned long long)w) - 1;
+  const uint64_t nw = w & (w - 1);
+  lo = l ? nw : lo;
+  hi = l ? hi : nw;
   return P;
 }
 
