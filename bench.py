@@ -486,6 +486,62 @@ def run_configs_bench(args):
     print(json.dumps(line), flush=True)
 
 
+def run_speedups_bench(args):
+    """Exact against semi-stochastic local energies (Sec. 3: every connected
+    determinant as a deterministic row, eps = 0, against the screened set plus
+    N_eps draws), FP64 as in the paper, on the hydrogen-chain stand-ins whose
+    relative costs the paper reports: K = 16 / 32 / 48 with chi = 50 and
+    2048 samples (eps = 0.01, N_eps = 100), and K = 50 with chi = 10.  The
+    semi-stochastic side runs the 2048 samples in one call; the exact side runs
+    a 64-sample subset of them (its rows per sample are the closed-form N_conn)
+    in passes of at most 8 M rows, and both are reported per sample.  One JSON
+    line."""
+    import numpy as np
+    import torch
+    from paper_2507_19276_amd import nqs, workloads
+
+    torch.cuda.set_device(0)
+    ctx = nqs.Context(0)
+    cases = [(16, 50), (32, 50), (48, 50), (50, 10)]
+    res = []
+    for K, chi in cases:
+        h, eri = workloads.chain_integrals(K, 20250725 + 31 * K)
+        pp, pi = workloads.graph_chain(K)
+        params = workloads.ansatz_params(K, chi, pp, pi, 0, 20250725 + 31 * K + 1)
+        na = nb = K // 2
+        smp = workloads.random_onvs(K, na, nb, 2048, 20250725 + 31 * K + 2)
+        inst = nqs.Instance(ctx, K, na, nb, h, eri, 0.0)
+        ans = nqs.Ansatz(ctx, K, na, nb, chi, pp, pi, 0)
+        ans.bind(params)
+        one = {}
+        for mode, eps, n_eps, n in (("semi", 0.01, 100, 2048), ("exact", 0.0, 0, 64)):
+            s = torch.from_numpy(smp[:n].view(np.int64)).cuda().contiguous()
+            kw = dict(eps=eps, n_eps=n_eps, precision="f64", seed=7, stream_id=0, max_rows_per_pass=8_000_000)
+            nqs.eloc(ctx, inst, ans, s, **kw)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            o, st = nqs.eloc(ctx, inst, ans, s, **kw)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            one[mode] = {"samples": n, "rows_per_sample": st["n_rows"] / n, "ms_per_sample": dt * 1e3 / n,
+                         "amplitude_ms_per_sample": st["ms_amplitude"] / n, "E_loc_mean": float(o["eloc"].mean())}
+            print(f"# K={K} chi={chi} {mode}: {st['n_rows'] / n:.0f} rows/sample, {dt * 1e3 / n:.4f} ms/sample",
+                  file=sys.stderr, flush=True)
+        res.append({"K": K, "chi": chi, "graph": "chain", **one,
+                    "time_ratio": one["exact"]["ms_per_sample"] / one["semi"]["ms_per_sample"],
+                    "amplitude_time_ratio": one["exact"]["amplitude_ms_per_sample"]
+                    / one["semi"]["amplitude_ms_per_sample"],
+                    "rows_ratio": one["exact"]["rows_per_sample"] / one["semi"]["rows_per_sample"]})
+    line = {"metric": "exact / semi-stochastic local-energy time per sample", "unit": "ratio", "n_gpus": 1,
+            "dtype": "f64", "data": "synthetic",
+            "config": {"workload": "hydrogen-chain stand-ins: chain integrals, chain BDG-RNN, half filling, "
+                                   "eps=0.01, N_eps=100 against eps=0"},
+            "paper_context": {"psi_evaluation_speedup_K16_32_48_chi50": [43, 418, 1359],
+                              "eloc_cost_fraction_K50_chi10": 0.0005},
+            "cases": res}
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -505,6 +561,8 @@ def main():
                     help="time the sampler, the Ising-RBM, BDG-TensorRNN and complex paths and one VMC step")
     ap.add_argument("--configs", action="store_true",
                     help="time the K=50, dense K=20 and lattice K=18 configurations per precision")
+    ap.add_argument("--speedups", action="store_true",
+                    help="exact against semi-stochastic local energies on the hydrogen-chain stand-ins (FP64)")
     ap.add_argument("--requests", type=int, default=500)
     ap.add_argument("--load", type=float, default=0.8)
     ap.add_argument("--slots", type=int, default=4)
@@ -521,6 +579,8 @@ def main():
         run_next_bench(args)
     elif args.configs:
         run_configs_bench(args)
+    elif args.speedups:
+        run_speedups_bench(args)
     else:
         run_eloc_bench(args)
 
