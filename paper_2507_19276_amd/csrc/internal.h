@@ -55,6 +55,7 @@ struct PsiParams {
   const T* w;                    // [K][chip]
   const T* c;                    // [K]
   bool folded;                   // operands carry sqrt(eta) (see k_psi_mt); never with a carried-state store
+  bool d1 = false;               // every site has exactly one edge (pptr[i+1] - pptr[i] == 1)
   const T* w2 = nullptr;         // complex parameters (realified state): [K][chip] vector of Im z
   const T* c2 = nullptr;         // [K] Im c
   // BDG-TensorRNN term on MFMA (chip <= 32, chi' <= 8): the operand stream

@@ -46,7 +46,7 @@ template <typename T> constexpr int prefetch_ksteps(int CH) {
   return (CH / 4) < 64 / ((CH / 4) * int(sizeof(T) / 4)) ? (CH / 4) : 64 / ((CH / 4) * int(sizeof(T) / 4));
 }
 
-template <typename T, int CH, int NTL, bool FOLD, int STORE, bool SEED, bool SAMPLE, bool CPLX, bool TN>
+template <typename T, int CH, int NTL, bool FOLD, int STORE, bool SEED, bool SAMPLE, bool CPLX, bool TN, bool D1>
 __global__ __launch_bounds__(256) void k_psi_mt(PsiParams<T> P, const uint64_t* __restrict__ m, int64_t R,
                                                 double* __restrict__ lphi, int8_t* __restrict__ sphi, int wpb,
                                                 PsiStates<T> X, SampleArgs SA, double* __restrict__ phs) {
@@ -256,7 +256,9 @@ __global__ __launch_bounds__(256) void k_psi_mt(PsiParams<T> P, const uint64_t* 
     for (int t = 0; t < NTL; ++t) pr2[t] = V{0, 0, 0, 0};
     // one edge: a chi-wide slice of the contraction over the parents (TN: and
     // the projection of the parent's state into pt)
-    auto edge = [&](V (&pt)[NTL]) {
+    // (D1: every site has exactly one edge, whose first MFMAs start from the
+    // bias registers instead of copies of them in the accumulators)
+    auto edge = [&](V (&pt)[NTL], auto first) {
       const T* Ae = Ab + size_t(e) * ES;
       V b[NTL][TPC];
       const V* rp = ring + size_t(slots[e]) * SLOT;
@@ -276,7 +278,8 @@ __global__ __launch_bounds__(256) void k_psi_mt(PsiParams<T> P, const uint64_t* 
         for (int ot = 0; ot < NT; ++ot) {
           const T a = q < PQ ? an[q < PQ ? q : 0][ot] : Ae[(q * NT + ot) * 64];
 #pragma unroll
-          for (int t = 0; t < NTL; ++t) acc[t][ot] = mfma(a, b[t][q / 4][q % 4], acc[t][ot]);
+          for (int t = 0; t < NTL; ++t)
+            acc[t][ot] = mfma(a, b[t][q / 4][q % 4], decltype(first)::value && q == 0 ? vn[ot] : acc[t][ot]);
         }
 #pragma unroll
       for (int q = 0; q < PQ; ++q)
@@ -303,22 +306,28 @@ __global__ __launch_bounds__(256) void k_psi_mt(PsiParams<T> P, const uint64_t* 
     // as the matrix core frees up, and the other wavefronts' epilogues fill
     // the VALU slots in between
     __builtin_amdgcn_s_setprio(PRIO);
-#pragma unroll
-    for (int ot = 0; ot < NT; ++ot)
-#pragma unroll
-      for (int t = 0; t < NTL; ++t) acc[t][ot] = vn[ot];
-    if (BPF) fetch_bias(i + 1 < P.K ? i + 1 : i);
-    if (TN && tQ > 0) {
-      // a tensor site has 2 or 3 parents: each edge's projection into its own registers
-      edge(pr0);
+    if constexpr (D1) {
+      edge(pr0, std::true_type{});
       ++e;
-      edge(pr1);
-      if (++e < e1) {
-        edge(pr2);
-        ++e;
-      }
+      if (BPF) fetch_bias(i + 1 < P.K ? i + 1 : i);
     } else {
-      do edge(pr0); while (++e < e1);
+#pragma unroll
+      for (int ot = 0; ot < NT; ++ot)
+#pragma unroll
+        for (int t = 0; t < NTL; ++t) acc[t][ot] = vn[ot];
+      if (BPF) fetch_bias(i + 1 < P.K ? i + 1 : i);
+      if (TN && tQ > 0) {
+        // a tensor site has 2 or 3 parents: each edge's projection into its own registers
+        edge(pr0, std::false_type{});
+        ++e;
+        edge(pr1, std::false_type{});
+        if (++e < e1) {
+          edge(pr2, std::false_type{});
+          ++e;
+        }
+      } else {
+        do edge(pr0, std::false_type{}); while (++e < e1);
+      }
     }
     if constexpr (TN) {
       if (tQ > 0) {
@@ -581,7 +590,7 @@ template <typename T> constexpr int ntiles(int CH) {
 }
 
 template <typename T, int CH, bool FOLD, int STORE, bool SEED, bool SAMPLE = false, bool CPLX = false,
-          bool TN = false>
+          bool TN = false, bool D1 = false>
 hipError_t run_psi_mt(const PsiParams<T>& P, const uint64_t* m, int64_t R, double* lphi, int8_t* sphi,
                       hipStream_t st, const PsiStates<T>& X, const SampleArgs& SA = SampleArgs(),
                       double* phs = nullptr) {
@@ -596,9 +605,56 @@ hipError_t run_psi_mt(const PsiParams<T>& P, const uint64_t* m, int64_t R, doubl
   if (per_wave * wpb > 160 * 1024) return hipErrorInvalidValue;
   const int64_t tiles = (R + 16 * NTL - 1) / (16 * NTL);
   const int64_t blocks = (tiles + wpb - 1) / wpb;
-  hipLaunchKernelGGL((k_psi_mt<T, CH, NTL, FOLD, STORE, SEED, SAMPLE, CPLX, TN>), dim3(unsigned(blocks)),
+  static_assert(!(D1 && TN), "a tensor site has two or three edges");
+  hipLaunchKernelGGL((k_psi_mt<T, CH, NTL, FOLD, STORE, SEED, SAMPLE, CPLX, TN, D1>), dim3(unsigned(blocks)),
                      dim3(64 * wpb), per_wave * wpb, st, P, m, R, lphi, sphi, wpb, X, SA, phs);
   return hipGetLastError();
+}
+
+// the eloc modes without the tensor term; D1: every site has one edge
+template <typename T, int CH, bool D1>
+hipError_t run_psi_modes(const PsiParams<T>& P, const uint64_t* m, int64_t R, double* lphi, int8_t* sphi,
+                         hipStream_t st, const PsiStates<T>& X, int mode, double* phs) {
+  if (phs) {
+    // complex parameters: the phase of each row
+    if (!P.w2 || !P.c2) return hipErrorInvalidValue;
+    const SampleArgs no;
+    switch (mode) {
+      case PSI_PLAIN:
+        if (P.folded) return run_psi_mt<T, CH, true, 0, false, false, true, false, D1>(P, m, R, lphi, sphi, st, X, no, phs);
+        return run_psi_mt<T, CH, false, 0, false, false, true, false, D1>(P, m, R, lphi, sphi, st, X, no, phs);
+      case PSI_STORE:
+        if (!X.pz && X.pm) return hipErrorInvalidValue;
+        if (P.folded) return run_psi_mt<T, CH, true, 1, false, false, true, false, D1>(P, m, R, lphi, sphi, st, X, no, phs);
+        return run_psi_mt<T, CH, false, 1, false, false, true, false, D1>(P, m, R, lphi, sphi, st, X, no, phs);
+      case PSI_SEED:
+        if (!X.pz || (X.unode && !X.npz)) return hipErrorInvalidValue;
+        if (P.folded) return run_psi_mt<T, CH, true, 0, true, false, true, false, D1>(P, m, R, lphi, sphi, st, X, no, phs);
+        return run_psi_mt<T, CH, false, 0, true, false, true, false, D1>(P, m, R, lphi, sphi, st, X, no, phs);
+      case PSI_NODE:
+        if (!X.pz || !X.npz) return hipErrorInvalidValue;
+        if (P.folded) return run_psi_mt<T, CH, true, 2, true, false, true, false, D1>(P, m, R, lphi, sphi, st, X, no, phs);
+        return run_psi_mt<T, CH, false, 2, true, false, true, false, D1>(P, m, R, lphi, sphi, st, X, no, phs);
+      default:
+        return hipErrorInvalidValue;
+    }
+  }
+  switch (mode) {
+    case PSI_PLAIN:
+      if (P.folded) return run_psi_mt<T, CH, true, 0, false, false, false, false, D1>(P, m, R, lphi, sphi, st, X);
+      return run_psi_mt<T, CH, false, 0, false, false, false, false, D1>(P, m, R, lphi, sphi, st, X);
+    case PSI_STORE:
+      if (P.folded) return run_psi_mt<T, CH, true, 1, false, false, false, false, D1>(P, m, R, lphi, sphi, st, X);
+      return run_psi_mt<T, CH, false, 1, false, false, false, false, D1>(P, m, R, lphi, sphi, st, X);
+    case PSI_SEED:
+      if (P.folded) return run_psi_mt<T, CH, true, 0, true, false, false, false, D1>(P, m, R, lphi, sphi, st, X);
+      return run_psi_mt<T, CH, false, 0, true, false, false, false, D1>(P, m, R, lphi, sphi, st, X);
+    case PSI_NODE:
+      if (P.folded) return run_psi_mt<T, CH, true, 2, true, false, false, false, D1>(P, m, R, lphi, sphi, st, X);
+      return run_psi_mt<T, CH, false, 2, true, false, false, false, D1>(P, m, R, lphi, sphi, st, X);
+    default:
+      return hipErrorInvalidValue;
+  }
 }
 
 template <typename T, int CH>
@@ -628,46 +684,10 @@ hipError_t run_psi_ch(const PsiParams<T>& P, const uint64_t* m, int64_t R, doubl
     }
     return hipErrorInvalidValue;
   }
-  if (phs) {
-    // complex parameters: the phase of each row
-    if (!P.w2 || !P.c2) return hipErrorInvalidValue;
-    const SampleArgs no;
-    switch (mode) {
-      case PSI_PLAIN:
-        if (P.folded) return run_psi_mt<T, CH, true, 0, false, false, true>(P, m, R, lphi, sphi, st, X, no, phs);
-        return run_psi_mt<T, CH, false, 0, false, false, true>(P, m, R, lphi, sphi, st, X, no, phs);
-      case PSI_STORE:
-        if (!X.pz && X.pm) return hipErrorInvalidValue;
-        if (P.folded) return run_psi_mt<T, CH, true, 1, false, false, true>(P, m, R, lphi, sphi, st, X, no, phs);
-        return run_psi_mt<T, CH, false, 1, false, false, true>(P, m, R, lphi, sphi, st, X, no, phs);
-      case PSI_SEED:
-        if (!X.pz || (X.unode && !X.npz)) return hipErrorInvalidValue;
-        if (P.folded) return run_psi_mt<T, CH, true, 0, true, false, true>(P, m, R, lphi, sphi, st, X, no, phs);
-        return run_psi_mt<T, CH, false, 0, true, false, true>(P, m, R, lphi, sphi, st, X, no, phs);
-      case PSI_NODE:
-        if (!X.pz || !X.npz) return hipErrorInvalidValue;
-        if (P.folded) return run_psi_mt<T, CH, true, 2, true, false, true>(P, m, R, lphi, sphi, st, X, no, phs);
-        return run_psi_mt<T, CH, false, 2, true, false, true>(P, m, R, lphi, sphi, st, X, no, phs);
-      default:
-        return hipErrorInvalidValue;
-    }
+  if constexpr (CH <= 32) {
+    if (P.d1) return run_psi_modes<T, CH, true>(P, m, R, lphi, sphi, st, X, mode, phs);
   }
-  switch (mode) {
-    case PSI_PLAIN:
-      if (P.folded) return run_psi_mt<T, CH, true, 0, false>(P, m, R, lphi, sphi, st, X);
-      return run_psi_mt<T, CH, false, 0, false>(P, m, R, lphi, sphi, st, X);
-    case PSI_STORE:
-      if (P.folded) return run_psi_mt<T, CH, true, 1, false>(P, m, R, lphi, sphi, st, X);
-      return run_psi_mt<T, CH, false, 1, false>(P, m, R, lphi, sphi, st, X);
-    case PSI_SEED:
-      if (P.folded) return run_psi_mt<T, CH, true, 0, true>(P, m, R, lphi, sphi, st, X);
-      return run_psi_mt<T, CH, false, 0, true>(P, m, R, lphi, sphi, st, X);
-    case PSI_NODE:
-      if (P.folded) return run_psi_mt<T, CH, true, 2, true>(P, m, R, lphi, sphi, st, X);
-      return run_psi_mt<T, CH, false, 2, true>(P, m, R, lphi, sphi, st, X);
-    default:
-      return hipErrorInvalidValue;
-  }
+  return run_psi_modes<T, CH, false>(P, m, R, lphi, sphi, st, X, mode, phs);
 }
 
 template <typename T, int CH>

@@ -208,6 +208,7 @@ struct nqs_ansatz {
   nqs_ctx* ctx = nullptr;
   int device = 0;           // the context's device, kept for destruction after the context
   int K = 0, na = 0, nb = 0, chi = 0, chip = 0, nh = 0, W = 1;
+  bool d1 = false;          // every site has exactly one forward edge (a chain: the single-edge kernels)
   std::vector<int32_t> pptr, pidx;
   std::vector<int64_t> offM, offV, offEta, offW, offC;
   int64_t offB = 0, offWc = 0, n_params = 0;
@@ -285,6 +286,7 @@ struct nqs_ansatz {
   PsiParams<T> params(const PsiLayout<T>& L) const {
     PsiParams<T> P;
     P.K = K; P.chi = chi; P.chip = chip; P.na = na; P.nb = nb; P.W = W;
+    P.d1 = d1;
     P.pptr = d_fptr; P.slot = d_fslot;
     P.A = L.A; P.v = L.v; P.eta = L.eta; P.w = L.w; P.c = L.c;
     P.folded = L.folded;
@@ -906,6 +908,8 @@ nqs_status nqs_ansatz_create(nqs_ctx* ctx, int K, int n_alpha, int n_beta, int c
     for (int e = a->pptr[i]; e < a->pptr[i + 1]; ++e) fslot.push_back(slot[e]);
     fptr.push_back(int(fslot.size()));
   }
+  a->d1 = true;
+  for (int i = 0; i < K; ++i) a->d1 = a->d1 && fptr[i + 1] - fptr[i] == 1;
   if ((st = upload(&a->d_fptr, fptr)) != NQS_OK) return st;
   if ((st = upload(&a->d_fslot, fslot)) != NQS_OK) return st;
   if ((st = upload(&a->d_offM, a->offM)) != NQS_OK) return st;
