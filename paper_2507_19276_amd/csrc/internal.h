@@ -159,6 +159,7 @@ struct B16Params {
   const float* w;                // [K][chip]
   const float* c;                // [K]
   bool folded;                   // operands carry sqrt(eta)
+  bool d1 = false;               // every site has exactly one edge
 };
 // States of the BF16 forward's STORE / SEED modes (as PsiStates): carried
 // states as BF16 with one power-of-two exponent per (site, row).

@@ -94,7 +94,7 @@ __device__ inline int wave_max(int x) {
 
 template <int CH> constexpr int ntiles_b16() { return CH <= 16 ? 4 : (CH <= 32 ? 2 : 1); }
 
-template <int CH, int NTL, bool FOLD, bool STORE, bool SEED>
+template <int CH, int NTL, bool FOLD, bool STORE, bool SEED, bool D1>
 __global__ __launch_bounds__(256) void k_psi_b16(B16Params P, const uint64_t* __restrict__ m, int64_t R,
                                                  double* __restrict__ lphi, int8_t* __restrict__ sphi, int wpb,
                                                  B16States X) {
@@ -212,7 +212,7 @@ __global__ __launch_bounds__(256) void k_psi_b16(B16Params P, const uint64_t* __
   };
   for (int i = i0; i < P.K; ++i) {
     store_pre(i);
-    f4 acc[NTL][NT], wv4[TPC], ev4[TPC];
+    f4 acc[NTL][NT], vs[NT], wv4[TPC], ev4[TPC];
 #pragma unroll
     for (int tt = 0; tt < TPC; ++tt) {
       wv4[tt] = *reinterpret_cast<const f4*>(P.w + size_t(i) * CH + 16 * tt + 4 * g);
@@ -222,7 +222,9 @@ __global__ __launch_bounds__(256) void k_psi_b16(B16Params P, const uint64_t* __
     // the parents' common exponent
     int eref = -(1 << 30);
     for (int ee = e; ee < e1; ++ee) eref = max(eref, __builtin_amdgcn_readfirstlane(Ering[slots[ee] * 64]));
-    auto edge = [&]() {
+    // (D1: every site has exactly one edge, whose first MFMAs start from the
+    // scaled bias registers instead of copies of them in the accumulators)
+    auto edge = [&](auto first) {
       const u2* Ae = Ab + int64_t(e) * EQ;
       const int ep = __builtin_amdgcn_readfirstlane(Ering[slots[e] * 64]);
       u2 b[NTL][TPC];
@@ -251,7 +253,7 @@ __global__ __launch_bounds__(256) void k_psi_b16(B16Params P, const uint64_t* __
 #pragma unroll
           for (int t = 0; t < NTL; ++t) {
             const u4 bq = {b[t][2 * q].x, b[t][2 * q].y, b[t][2 * q + 1].x, b[t][2 * q + 1].y};
-            acc[t][ot] = mfma_k32(a, bq, acc[t][ot]);
+            acc[t][ot] = mfma_k32(a, bq, decltype(first)::value && q == 0 ? vs[ot] : acc[t][ot]);
           }
         }
       if constexpr (ODD) {
@@ -263,7 +265,8 @@ __global__ __launch_bounds__(256) void k_psi_b16(B16Params P, const uint64_t* __
           else
             a = (Ae + int64_t(NP) * NT * 64 * 2)[ot * 64 + lane];
 #pragma unroll
-          for (int t = 0; t < NTL; ++t) acc[t][ot] = mfma_k16(a, b[t][TPC - 1], acc[t][ot]);
+          for (int t = 0; t < NTL; ++t)
+            acc[t][ot] = mfma_k16(a, b[t][TPC - 1], decltype(first)::value && NP == 0 ? vs[ot] : acc[t][ot]);
         }
       }
       if (APF) {
@@ -274,21 +277,29 @@ __global__ __launch_bounds__(256) void k_psi_b16(B16Params P, const uint64_t* __
     if (!BPF) fetch_bias(i);
     const float sc = ldexpf(1.0f, -eref);
     __builtin_amdgcn_s_setprio(PRIO);
-    if (eref == 0) {
+    if constexpr (D1) {
 #pragma unroll
-      for (int ot = 0; ot < NT; ++ot)
-#pragma unroll
-        for (int t = 0; t < NTL; ++t) acc[t][ot] = vn[ot];
+      for (int ot = 0; ot < NT; ++ot) vs[ot] = vn[ot] * sc;   // exact: sc is a power of two
+      if (BPF) fetch_bias(i + 1 < P.K ? i + 1 : i);
+      edge(std::true_type{});
+      ++e;
     } else {
+      if (eref == 0) {
 #pragma unroll
-      for (int ot = 0; ot < NT; ++ot) {
-        const f4 vs = vn[ot] * sc;
+        for (int ot = 0; ot < NT; ++ot)
 #pragma unroll
-        for (int t = 0; t < NTL; ++t) acc[t][ot] = vs;
+          for (int t = 0; t < NTL; ++t) acc[t][ot] = vn[ot];
+      } else {
+#pragma unroll
+        for (int ot = 0; ot < NT; ++ot) {
+          const f4 vsc = vn[ot] * sc;
+#pragma unroll
+          for (int t = 0; t < NTL; ++t) acc[t][ot] = vsc;
+        }
       }
+      if (BPF) fetch_bias(i + 1 < P.K ? i + 1 : i);
+      do edge(std::false_type{}); while (++e < e1);
     }
-    if (BPF) fetch_bias(i + 1 < P.K ? i + 1 : i);
-    do edge(); while (++e < e1);
     __builtin_amdgcn_s_setprio(0);
     // epilogue (FP32): P^s, selection, w.h; the new states are written after
     // the renormalisation decision
@@ -391,7 +402,7 @@ __global__ __launch_bounds__(256) void k_psi_b16(B16Params P, const uint64_t* __
   }
 }
 
-template <int CH, bool FOLD, bool STORE, bool SEED>
+template <int CH, bool FOLD, bool STORE, bool SEED, bool D1>
 hipError_t run_b16(const B16Params& P, const uint64_t* m, int64_t R, double* lphi, int8_t* sphi, hipStream_t st,
                    const B16States& X) {
   if (R <= 0) return hipSuccess;
@@ -403,27 +414,37 @@ hipError_t run_b16(const B16Params& P, const uint64_t* m, int64_t R, double* lph
   if (per_wave * wpb > 160 * 1024) return hipErrorInvalidValue;
   const int64_t tiles = (R + 16 * NTL - 1) / (16 * NTL);
   const int64_t blocks = (tiles + wpb - 1) / wpb;
-  hipLaunchKernelGGL((k_psi_b16<CH, NTL, FOLD, STORE, SEED>), dim3(unsigned(blocks)), dim3(64 * wpb),
+  hipLaunchKernelGGL((k_psi_b16<CH, NTL, FOLD, STORE, SEED, D1>), dim3(unsigned(blocks)), dim3(64 * wpb),
                      per_wave * wpb, st, P, m, R, lphi, sphi, wpb, X);
   return hipGetLastError();
+}
+
+// D1: every site has one edge
+template <int CH, bool D1>
+hipError_t run_b16_modes(const B16Params& P, const uint64_t* m, int64_t R, double* lphi, int8_t* sphi,
+                         hipStream_t st, const B16States& X, int mode) {
+  switch (mode) {
+    case PSI_PLAIN:
+      if (P.folded) return run_b16<CH, true, false, false, D1>(P, m, R, lphi, sphi, st, X);
+      return run_b16<CH, false, false, false, D1>(P, m, R, lphi, sphi, st, X);
+    case PSI_STORE:
+      if (P.folded) return run_b16<CH, true, true, false, D1>(P, m, R, lphi, sphi, st, X);
+      return run_b16<CH, false, true, false, D1>(P, m, R, lphi, sphi, st, X);
+    case PSI_SEED:
+      if (P.folded) return run_b16<CH, true, false, true, D1>(P, m, R, lphi, sphi, st, X);
+      return run_b16<CH, false, false, true, D1>(P, m, R, lphi, sphi, st, X);
+    default:
+      return hipErrorInvalidValue;
+  }
 }
 
 template <int CH>
 hipError_t run_b16_ch(const B16Params& P, const uint64_t* m, int64_t R, double* lphi, int8_t* sphi,
                       hipStream_t st, const B16States& X, int mode) {
-  switch (mode) {
-    case PSI_PLAIN:
-      if (P.folded) return run_b16<CH, true, false, false>(P, m, R, lphi, sphi, st, X);
-      return run_b16<CH, false, false, false>(P, m, R, lphi, sphi, st, X);
-    case PSI_STORE:
-      if (P.folded) return run_b16<CH, true, true, false>(P, m, R, lphi, sphi, st, X);
-      return run_b16<CH, false, true, false>(P, m, R, lphi, sphi, st, X);
-    case PSI_SEED:
-      if (P.folded) return run_b16<CH, true, false, true>(P, m, R, lphi, sphi, st, X);
-      return run_b16<CH, false, false, true>(P, m, R, lphi, sphi, st, X);
-    default:
-      return hipErrorInvalidValue;
+  if constexpr (CH <= 32) {
+    if (P.d1) return run_b16_modes<CH, true>(P, m, R, lphi, sphi, st, X, mode);
   }
+  return run_b16_modes<CH, false>(P, m, R, lphi, sphi, st, X, mode);
 }
 
 }  // namespace

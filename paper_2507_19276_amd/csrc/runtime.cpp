@@ -1232,7 +1232,7 @@ nqs_status run_amplitudes(const nqs_ansatz* a, int precision, const uint64_t* m,
     B16Params P{};
     P.K = a->K; P.chi = a->chi; P.chip = a->chip; P.na = a->na; P.nb = a->nb; P.W = a->W;
     P.pptr = a->d_fptr; P.slot = a->d_fslot; P.A = a->bfA;
-    P.v = L.v; P.eta = L.eta; P.w = L.w; P.c = L.c; P.folded = L.folded;
+    P.v = L.v; P.eta = L.eta; P.w = L.w; P.c = L.c; P.folded = L.folded; P.d1 = a->d1;
     hipError_t e = launch_psi_bf16(P, m, R, lphi, sphi, st, rs ? states_b16(*rs) : B16States(), mode);
     if (e == hipErrorNotSupported) return fail(NQS_EUNSUPPORTED, "BF16 amplitude path not available");
     HIPCHK(e);
