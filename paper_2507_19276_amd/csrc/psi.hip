@@ -701,6 +701,15 @@ hipError_t run_sample_ch(const PsiParams<T>& P, int64_t R, double* lphi, int8_t*
     }
     return hipErrorInvalidValue;
   }
+  if constexpr (CH <= 32) {
+    if (P.d1) {
+      if (P.folded)
+        return run_psi_mt<T, CH, true, 0, false, true, false, false, true>(P, nullptr, R, lphi, sphi, st, PsiStates<T>(),
+                                                                          SA);
+      return run_psi_mt<T, CH, false, 0, false, true, false, false, true>(P, nullptr, R, lphi, sphi, st, PsiStates<T>(),
+                                                                         SA);
+    }
+  }
   if (P.folded) return run_psi_mt<T, CH, true, 0, false, true>(P, nullptr, R, lphi, sphi, st, PsiStates<T>(), SA);
   return run_psi_mt<T, CH, false, 0, false, true>(P, nullptr, R, lphi, sphi, st, PsiStates<T>(), SA);
 }
