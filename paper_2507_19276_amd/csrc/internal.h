@@ -255,7 +255,8 @@ struct PsiStates {
   const uint8_t* t0 = nullptr;   // SEED: [R] first changed site of each position (ascending)
   const int32_t* owner = nullptr;// SEED: [rows] sample of each row
   // one level of shared prefixes (nodes.hip), compact per node: entry
-  // noff[u] + k holds the carried state after site nc1[u] + k (k < ne1 - nc1)
+  // noff[u] + k holds the carried state after site nc1[u] + k (k < ne1 - nc1;
+  // only where nmask[u] has bit nc1[u] + k, if nmask is given)
   // and the log-product state before site nc1[u] + k (k <= ne1 - nc1)
   T* nhs = nullptr;              // [entries][chip]
   T* npm = nullptr;              // [entries]
@@ -266,6 +267,9 @@ struct PsiStates {
   const uint8_t* nc1 = nullptr;  // [nodes] the node's changed site
   const uint8_t* ne1 = nullptr;  // [nodes] the last site its rows resume at
   const int32_t* unode = nullptr;// SEED rows: [rows] node the row resumes from (-1: its sample)
+  // node units: bit i set where some row reads the carried state after site i
+  // (the other carried states are not stored; null: all are)
+  const uint64_t* nmask = nullptr;
 };
 // node list written by nodes.hip
 struct NodeList {
@@ -274,6 +278,7 @@ struct NodeList {
   uint8_t* c1;                   // [nodes] changed site
   uint8_t* e1;                   // [nodes] largest resume site of its rows
   int64_t* off;                  // [nodes] first storage entry
+  uint64_t* need;                // [nodes] bit s: some row reads the carried state after site s
 };
 bool node_pairs(int K);   // whether nodes can be keyed by the first two changes (else by the first)
 hipError_t launch_node_count(const uint8_t* t0, const uint32_t* sec, const int64_t* rowptr, int64_t n0, int64_t n1,
@@ -281,9 +286,15 @@ hipError_t launch_node_count(const uint8_t* t0, const uint32_t* sec, const int64
 hipError_t launch_node_scan(int64_t ns, int64_t cap, int32_t* ncnt, int64_t* nent, int64_t* nbase, int64_t* ebase,
                             int64_t* totals, hipStream_t st);
 hipError_t launch_node_assign(const uint8_t* t0, const uint32_t* sec, const uint64_t* samples,
-                              const int64_t* rowptr, int64_t n0, int64_t n1, int64_t row_base, int K, bool pair,
-                              const int64_t* nbase, const int64_t* ebase, const NodeList& nl, int32_t* row_node,
-                              uint8_t* row_site, hipStream_t st);
+                              const int64_t* rowptr, int64_t n0, int64_t n1, int64_t row_base, int K, int W,
+                              bool pair, const int64_t* nbase, const int64_t* ebase, const NodeList& nl,
+                              int32_t* row_node, uint8_t* row_site, hipStream_t st);
+// need[row_node[perm[p]]] |= the sites below the row's wavefront start whose
+// carried states the row pass reads from the node, for rows whose wavefront
+// starts below their own resume site (rows sorted by resume site t0s; at most
+// 64 rows per wavefront of the forward kernels)
+hipError_t launch_node_need(const int32_t* perm, const uint8_t* t0s, int64_t R, int W, const int32_t* row_node,
+                            const uint8_t* nc1, uint64_t* need, hipStream_t st);
 // phs (complex parameters, PSI_PLAIN only): the phase of each row
 hipError_t launch_psi_f64(const PsiParams<double>& P, const uint64_t* m, int64_t R, double* lphi,
                           int8_t* sphi, hipStream_t st, const PsiStates<double>& X = PsiStates<double>(),

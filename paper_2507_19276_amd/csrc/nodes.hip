@@ -24,6 +24,11 @@
 //   assign: one workgroup per sample rebuilds the table, numbers its nodes in
 //           key order, writes the node list and, per row, the node and the
 //           site it resumes at (rows of samples without nodes resume at c1).
+// The assign launch also marks, per node, the sites whose carried states its
+// rows read when they resume at their own resume sites (need); after the rows
+// are sorted by resume site, a fourth launch adds the sites read by rows whose
+// wavefront starts below their own site.  The node pass stores only those
+// carried states (and every log-product state).
 #include "internal.h"
 
 namespace nqs {
@@ -52,18 +57,35 @@ __device__ inline RowKey row_key(uint8_t t0, uint32_t v, int K, bool pair) {
 
 __device__ inline int key_c1(int key, int K, bool pair) { return pair ? key / (16 * (K + 1)) : key / 4; }
 
-// table of one sample: e[key] = largest resume site + 1 (0 = key absent); the
-// sample's own row (t0 = K) has no key
+// table of one sample: e[key] = the set of its rows' resume sites, bit res - 1
+// (0 = key absent; res > c1 >= 0); the sample's own row (t0 = K) has no key.
+// M = unsigned int for pair keys (K <= 30), unsigned long long for first-change
+// keys.
+template <typename M>
 __device__ void build_table(const uint8_t* t0, const uint32_t* sec, int64_t r0, int64_t r1, int K, bool pair,
-                            int T, int* e) {
+                            int T, M* e) {
   for (int k = threadIdx.x; k < T; k += blockDim.x) e[k] = 0;
   __syncthreads();
   for (int64_t r = r0 + threadIdx.x; r < r1; r += blockDim.x) {
     if (t0[r] >= K) continue;
     const RowKey k = row_key(t0[r], sec[r], K, pair);
-    atomicMax(&e[k.key], k.res + 1);
+    atomicOr(&e[k.key], M(1) << (k.res - 1));
   }
   __syncthreads();
+}
+
+// the largest resume site in a table entry
+template <typename M> __device__ inline int last_res(M m) {
+  return sizeof(M) == 4 ? 32 - __clz(uint32_t(m)) : 64 - __clzll((unsigned long long)m);
+}
+
+// the sites (bit s) whose carried states rows resuming at the sites of m read
+// from a node with changed site c1: s in [res - W + 1, res - 1], s >= c1
+template <typename M> __device__ inline uint64_t need_of(M m, int W, int c1) {
+  const uint64_t b = uint64_t(m);   // bit res - 1
+  uint64_t need = 0;
+  for (int w = 0; w < W - 1; ++w) need |= b >> w;
+  return need & ~((1ull << c1) - 1ull);
 }
 
 // block-wide exclusive scan of (count, entries) pairs held one per thread
@@ -87,14 +109,16 @@ __device__ void block_scan(int& cnt, int64_t& ent, int* sc, int64_t* se, int& to
   __syncthreads();
 }
 
+template <typename M>
 __global__ __launch_bounds__(kNodeThreads) void k_node_count(const uint8_t* __restrict__ t0,
                                                              const uint32_t* __restrict__ sec, const int64_t* rowptr,
-                                                             int64_t n0, int64_t row_base, int K, int pair_i,
-                                                             int32_t* ncnt, int64_t* nent) {
-  extern __shared__ int e[];
+                                                             int64_t n0, int64_t row_base, int K, int32_t* ncnt,
+                                                             int64_t* nent) {
+  extern __shared__ unsigned long long lds_table[];
+  M* e = reinterpret_cast<M*>(lds_table);
   __shared__ int sc[kNodeThreads];
   __shared__ int64_t se[kNodeThreads];
-  const bool pair = pair_i != 0;
+  constexpr bool pair = sizeof(M) == 4;
   const int T = pair ? 16 * K * (K + 1) : 4 * K;
   const int64_t n = n0 + blockIdx.x;
   build_table(t0, sec, rowptr[n] - row_base, rowptr[n + 1] - row_base, K, pair, T, e);
@@ -103,7 +127,7 @@ __global__ __launch_bounds__(kNodeThreads) void k_node_count(const uint8_t* __re
   for (int k = threadIdx.x; k < T; k += blockDim.x)
     if (e[k]) {
       ++cnt;
-      ent += (e[k] - 1) - key_c1(k, K, pair) + 1;
+      ent += last_res(e[k]) - key_c1(k, K, pair) + 1;
     }
   int tc;
   int64_t te;
@@ -161,17 +185,19 @@ __global__ __launch_bounds__(1024) void k_node_scan(int64_t ns, int64_t cap, int
   }
 }
 
+template <typename M>
 __global__ __launch_bounds__(kNodeThreads) void k_node_assign(const uint8_t* __restrict__ t0,
                                                               const uint32_t* __restrict__ sec,
                                                               const uint64_t* __restrict__ samples,
                                                               const int64_t* rowptr, int64_t n0, int64_t row_base,
-                                                              int K, int pair_i, const int64_t* nbase,
+                                                              int K, int W, const int64_t* nbase,
                                                               const int64_t* ebase, NodeList nl, int32_t* row_node,
                                                               uint8_t* row_site) {
-  extern __shared__ int e[];
+  extern __shared__ unsigned long long lds_table[];
+  M* e = reinterpret_cast<M*>(lds_table);
   __shared__ int sc[kNodeThreads];
   __shared__ int64_t se[kNodeThreads];
-  const bool pair = pair_i != 0;
+  constexpr bool pair = sizeof(M) == 4;
   const int T = pair ? 16 * K * (K + 1) : 4 * K;
   const int64_t n = n0 + blockIdx.x;
   const int64_t r0 = rowptr[n] - row_base, r1 = rowptr[n + 1] - row_base;
@@ -187,20 +213,21 @@ __global__ __launch_bounds__(kNodeThreads) void k_node_assign(const uint8_t* __r
   for (int k = k0; k < k1; ++k)
     if (e[k]) {
       ++cnt;
-      ent += (e[k] - 1) - key_c1(k, K, pair) + 1;
+      ent += last_res(e[k]) - key_c1(k, K, pair) + 1;
     }
   int tc;
   int64_t te;
   block_scan(cnt, ent, sc, se, tc, te);
   int j = cnt;
   int64_t off = ebase[blockIdx.x] + ent;
+  // after numbering, e[k] holds the key's node (all ones: none)
   for (int k = k0; k < k1; ++k) {
-    const int ek = e[k];
+    const M ek = e[k];
     if (!ek) {
-      e[k] = -1;
+      e[k] = M(~M(0));
       continue;
     }
-    const int c1 = key_c1(k, K, pair), last = ek - 1;
+    const int c1 = key_c1(k, K, pair), last = last_res(ek);
     if (keep) {
       const int64_t node = nb + j;
       uint64_t lo = nlo, hi = nhi;
@@ -222,9 +249,10 @@ __global__ __launch_bounds__(kNodeThreads) void k_node_assign(const uint8_t* __r
       nl.c1[node] = uint8_t(c1);
       nl.e1[node] = uint8_t(last);
       nl.off[node] = off;
-      e[k] = int(node);
+      nl.need[node] = need_of(ek, W, c1);
+      e[k] = M(node);
     } else {
-      e[k] = -1;
+      e[k] = M(~M(0));
     }
     ++j;
     off += last - c1 + 1;
@@ -237,10 +265,37 @@ __global__ __launch_bounds__(kNodeThreads) void k_node_assign(const uint8_t* __r
       continue;
     }
     const RowKey k = row_key(t0[r], sec[r], K, pair);
-    const int node = e[k.key];
+    const M ek = e[k.key];
+    const int node = ek == M(~M(0)) ? -1 : int(ek);
     row_node[r] = node;
     row_site[r] = uint8_t(node >= 0 ? k.res : k.c1);
   }
+}
+
+// thread per sorted row position p: a wavefront of the row pass starts at the
+// resume site of its first position, a multiple of its row count (16, 32 or
+// 64), and reads the carried states of the W - 1 sites below that start; the
+// positions are sorted by resume site, so that start lies between the site at
+// the 64-aligned position at or below p and p's own site.  Where the two are
+// equal the assign launch has marked the sites already (from the row's own
+// resume site); otherwise the range marked covers both ends (and only sites
+// from the node's changed site on: below it the row reads its sample's
+// states).
+__global__ __launch_bounds__(256) void k_node_need(const int32_t* __restrict__ perm, const uint8_t* __restrict__ t0s,
+                                                   int64_t R, int W, const int32_t* __restrict__ row_node,
+                                                   const uint8_t* __restrict__ nc1, uint64_t* __restrict__ need) {
+  const int64_t p = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  if (p >= R) return;
+  const int s0 = t0s[p & ~int64_t(63)];
+  if (s0 == int(t0s[p])) return;
+  const int nd = row_node[perm[p]];
+  if (nd < 0) return;
+  const int start = s0 - W + 1;
+  const int lo = start > int(nc1[nd]) ? start : int(nc1[nd]);
+  const int hi = int(t0s[p]) - 1;   // <= 63
+  if (hi < lo) return;
+  const uint64_t upto = hi >= 63 ? ~0ull : (1ull << (hi + 1)) - 1ull;
+  atomicOr(reinterpret_cast<unsigned long long*>(need + nd), (unsigned long long)(upto & ~((1ull << lo) - 1ull)));
 }
 
 }  // namespace
@@ -251,9 +306,12 @@ hipError_t launch_node_count(const uint8_t* t0, const uint32_t* sec, const int64
                              int64_t row_base, int K, bool pair, int32_t* ncnt, int64_t* nent, hipStream_t st) {
   if (n1 <= n0) return hipSuccess;
   if (K < 1 || K > 64 || (pair && !node_pairs(K))) return hipErrorInvalidValue;
-  const size_t lds = size_t(pair ? 16 * K * (K + 1) : 4 * K) * sizeof(int);
-  hipLaunchKernelGGL(k_node_count, dim3(unsigned(n1 - n0)), dim3(kNodeThreads), lds, st, t0, sec, rowptr, n0,
-                     row_base, K, pair ? 1 : 0, ncnt, nent);
+  if (pair)
+    hipLaunchKernelGGL(k_node_count<unsigned int>, dim3(unsigned(n1 - n0)), dim3(kNodeThreads),
+                       size_t(16 * K * (K + 1)) * 4, st, t0, sec, rowptr, n0, row_base, K, ncnt, nent);
+  else
+    hipLaunchKernelGGL(k_node_count<unsigned long long>, dim3(unsigned(n1 - n0)), dim3(kNodeThreads),
+                       size_t(4 * K) * 8, st, t0, sec, rowptr, n0, row_base, K, ncnt, nent);
   return hipGetLastError();
 }
 
@@ -265,14 +323,28 @@ hipError_t launch_node_scan(int64_t ns, int64_t cap, int32_t* ncnt, int64_t* nen
 }
 
 hipError_t launch_node_assign(const uint8_t* t0, const uint32_t* sec, const uint64_t* samples,
-                              const int64_t* rowptr, int64_t n0, int64_t n1, int64_t row_base, int K, bool pair,
-                              const int64_t* nbase, const int64_t* ebase, const NodeList& nl, int32_t* row_node,
-                              uint8_t* row_site, hipStream_t st) {
+                              const int64_t* rowptr, int64_t n0, int64_t n1, int64_t row_base, int K, int W,
+                              bool pair, const int64_t* nbase, const int64_t* ebase, const NodeList& nl,
+                              int32_t* row_node, uint8_t* row_site, hipStream_t st) {
   if (n1 <= n0) return hipSuccess;
-  if (pair && !node_pairs(K)) return hipErrorInvalidValue;
-  const size_t lds = size_t(pair ? 16 * K * (K + 1) : 4 * K) * sizeof(int);
-  hipLaunchKernelGGL(k_node_assign, dim3(unsigned(n1 - n0)), dim3(kNodeThreads), lds, st, t0, sec, samples, rowptr,
-                     n0, row_base, K, pair ? 1 : 0, nbase, ebase, nl, row_node, row_site);
+  if (K < 1 || K > 64 || W < 1 || W > 64 || (pair && !node_pairs(K))) return hipErrorInvalidValue;
+  if (pair)
+    hipLaunchKernelGGL(k_node_assign<unsigned int>, dim3(unsigned(n1 - n0)), dim3(kNodeThreads),
+                       size_t(16 * K * (K + 1)) * 4, st, t0, sec, samples, rowptr, n0, row_base, K, W, nbase, ebase,
+                       nl, row_node, row_site);
+  else
+    hipLaunchKernelGGL(k_node_assign<unsigned long long>, dim3(unsigned(n1 - n0)), dim3(kNodeThreads),
+                       size_t(4 * K) * 8, st, t0, sec, samples, rowptr, n0, row_base, K, W, nbase, ebase, nl,
+                       row_node, row_site);
+  return hipGetLastError();
+}
+
+hipError_t launch_node_need(const int32_t* perm, const uint8_t* t0s, int64_t R, int W, const int32_t* row_node,
+                            const uint8_t* nc1, uint64_t* need, hipStream_t st) {
+  if (R <= 0) return hipSuccess;
+  if (W < 1 || W > 64) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_node_need, dim3(unsigned((R + 255) / 256)), dim3(256), 0, st, perm, t0s, R, W, row_node, nc1,
+                     need);
   return hipGetLastError();
 }
 

@@ -190,11 +190,13 @@ __global__ __launch_bounds__(256) void k_psi_mt(PsiParams<T> P, const uint64_t* 
   }
   int tc1[NTL], te1[NTL];
   int64_t toff[NTL];
+  uint64_t tneed[NTL];   // STORE 2: the sites whose carried states some row reads
 #pragma unroll
   for (int t = 0; t < NTL; ++t) {
     tc1[t] = STORE == 2 ? int(X.nc1[rowt[t]]) : 0;
     te1[t] = STORE == 2 ? int(X.ne1[rowt[t]]) : -1;
     toff[t] = STORE == 2 ? X.noff[rowt[t]] : 0;
+    tneed[t] = STORE == 2 && X.nmask ? X.nmask[rowt[t]] : ~0ull;
   }
   auto store_pre = [&](int i) {
     const bool writer = NTL == 4 || (NTL == 2 ? (g & 1) == 0 : g == 0);
@@ -528,7 +530,7 @@ __global__ __launch_bounds__(256) void k_psi_mt(PsiParams<T> P, const uint64_t* 
           const int64_t r = base + 16 * t + j;
           if (r < X.ns) *reinterpret_cast<V*>(X.hs + (size_t(i) * X.ns + r) * CH + 16 * tt + 4 * g) = sel;
         }
-        if (STORE == 2 && base + 16 * t + j < R && i >= tc1[t] && i < te1[t])
+        if (STORE == 2 && base + 16 * t + j < R && i >= tc1[t] && i < te1[t] && ((tneed[t] >> i) & 1ull))
           *reinterpret_cast<V*>(X.nhs + size_t(toff[t] + (i - tc1[t])) * CH + 16 * tt + 4 * g) = sel;
       }
     }
@@ -606,6 +608,7 @@ hipError_t run_psi_mt(const PsiParams<T>& P, const uint64_t* m, int64_t R, doubl
   const int64_t tiles = (R + 16 * NTL - 1) / (16 * NTL);
   const int64_t blocks = (tiles + wpb - 1) / wpb;
   static_assert(!(D1 && TN), "a tensor site has two or three edges");
+  static_assert(NTL <= 4, "the node-need marks assume at most 64 rows per wavefront");
   hipLaunchKernelGGL((k_psi_mt<T, CH, NTL, FOLD, STORE, SEED, SAMPLE, CPLX, TN, D1>), dim3(unsigned(blocks)),
                      dim3(64 * wpb), per_wave * wpb, st, P, m, R, lphi, sphi, wpb, X, SA, phs);
   return hipGetLastError();

@@ -1143,6 +1143,7 @@ struct Resume {
   const uint8_t* nc1 = nullptr;
   const uint8_t* ne1 = nullptr;
   const int32_t* unode = nullptr;
+  const uint64_t* nmask = nullptr;   // node pass: carried states some row reads
 };
 
 template <typename T>
@@ -1166,6 +1167,7 @@ PsiStates<T> states(const Resume& r) {
   X.nc1 = r.nc1;
   X.ne1 = r.ne1;
   X.unode = r.unode;
+  X.nmask = r.nmask;
   return X;
 }
 
@@ -1667,6 +1669,8 @@ nqs_status eloc_run(nqs_ctx* ctx, const nqs_instance* inst, const nqs_ansatz* an
   int32_t *ncnt = nullptr, *row_node = nullptr, *nperm = nullptr;
   int64_t *nent = nullptr, *nbase = nullptr, *ebase = nullptr, *ntot = nullptr;
   uint8_t *row_site = nullptr, *nt0s = nullptr;
+  int32_t* ncnt_s = nullptr;
+  int64_t* ntot_s = nullptr;
   double* lphi_n = nullptr;
   int8_t* sphi_n = nullptr;
   if (nodes) {
@@ -1683,6 +1687,9 @@ nqs_status eloc_run(nqs_ctx* ctx, const nqs_instance* inst, const nqs_ansatz* an
     nl.off = S.get<int64_t>(ecap);
     nperm = S.get<int32_t>(ecap);
     nt0s = S.get<uint8_t>(ecap);
+    nl.need = S.get<uint64_t>(ecap);
+    ncnt_s = S.get<int32_t>(size_t(order_blocks(cap_used)) * (K + 1));
+    ntot_s = S.get<int64_t>(K + 1);
     lphi_n = S.get<double>(ecap);
     sphi_n = S.get<int8_t>(ecap);
     rs.nhs = S.get<unsigned char>(size_t(ecap) * ans->chip * esz);
@@ -1744,12 +1751,15 @@ nqs_status eloc_run(nqs_ctx* ctx, const nqs_instance* inst, const nqs_ansatz* an
         int64_t tot2[2] = {0, 0};
         HIPCHK(hipMemcpyAsync(tot2, ntot, sizeof tot2, hipMemcpyDeviceToHost, stream));
         HIPCHK(hipStreamSynchronize(stream));
-        HIPCHK(launch_node_assign(P.rows.t0, P.rows.sec, samples, P.rowptr, n0, n1, row_base, K, pair, nbase, ebase, nl,
-                                  row_node, row_site, stream));
+        HIPCHK(launch_node_assign(P.rows.t0, P.rows.sec, samples, P.rowptr, n0, n1, row_base, K, ans->W, pair, nbase,
+                                  ebase, nl, row_node, row_site, stream));
         const int64_t nn = tot2[0];
+        // the rows' order first: it fixes which node states the row pass reads
+        HIPCHK(launch_order_t0(row_site, Rp, K, rs.cnt, rs.tot, rs.perm, rs.t0, stream));
         if (nn > 0) {
+          HIPCHK(launch_node_need(rs.perm, rs.t0, Rp, ans->W, row_node, nl.c1, nl.need, stream));
           // the node pass: resumed from the samples at the changed site, stores compactly
-          HIPCHK(launch_order_t0(nl.c1, nn, K, rs.cnt, rs.tot, nperm, nt0s, stream));
+          HIPCHK(launch_order_t0(nl.c1, nn, K, ncnt_s, ntot_s, nperm, nt0s, stream));
           Resume rn = rs;
           rn.perm = nperm;
           rn.t0 = nt0s;
@@ -1758,6 +1768,7 @@ nqs_status eloc_run(nqs_ctx* ctx, const nqs_instance* inst, const nqs_ansatz* an
           rn.nc1 = nl.c1;
           rn.ne1 = nl.e1;
           rn.unode = nullptr;
+          rn.nmask = nl.need;
           if ((s = run_amplitudes(ans, opts->precision, nl.m, nn, lphi_n, sphi_n, stream, &rn, PSI_NODE, phs_n)) !=
               NQS_OK)
             return s;
@@ -1769,9 +1780,9 @@ nqs_status eloc_run(nqs_ctx* ctx, const nqs_instance* inst, const nqs_ansatz* an
         rs.nc1 = nl.c1;
         rs.ne1 = nl.e1;
         rs.unode = row_node;
-        key = row_site;
+      } else {
+        HIPCHK(launch_order_t0(key, Rp, K, rs.cnt, rs.tot, rs.perm, rs.t0, stream));
       }
-      HIPCHK(launch_order_t0(key, Rp, K, rs.cnt, rs.tot, rs.perm, rs.t0, stream));
       if (timing) HIPCHK(hipEventRecord(kq[0], stream));
       if ((s = run_amplitudes(ans, opts->precision, P.rows.m, Rp, lphi, sphi, stream, &rs, PSI_SEED, phs)) != NQS_OK)
         return s;
@@ -2097,6 +2108,7 @@ nqs_status nqs_eloc_workspace_bytes(const nqs_instance* inst, const nqs_ansatz* 
       b += al(size_t(ecap) * ans->chip * esz) + al(size_t(ecap) * mantissa_bytes(opts->precision)) +
            al(size_t(ecap) * 4) + al(size_t(ecap));
       b += al(size_t(rows) * 4) + al(size_t(rows)) + al(size_t(rows) * 4);
+      b += al(size_t(ecap) * 8) + al(size_t(order_blocks(rows)) * (K + 1) * 4) + al(size_t(K + 1) * 8);
     }
   }
   b += 3 * al(size_t(N) * 8) + al(64);     // outputs the caller did not provide, batch sums
