@@ -190,13 +190,16 @@ __global__ __launch_bounds__(256) void k_psi_mt(PsiParams<T> P, const uint64_t* 
   }
   int tc1[NTL], te1[NTL];
   int64_t toff[NTL];
-  uint64_t tneed[NTL];   // STORE 2: the sites whose carried states some row reads
+  // STORE 2: the sites whose carried states some row reads (the tensor-term
+  // kernels store all: they have no registers to spare)
+  constexpr bool NEED = STORE == 2 && !TN;
+  uint64_t tneed[NTL];
 #pragma unroll
   for (int t = 0; t < NTL; ++t) {
     tc1[t] = STORE == 2 ? int(X.nc1[rowt[t]]) : 0;
     te1[t] = STORE == 2 ? int(X.ne1[rowt[t]]) : -1;
     toff[t] = STORE == 2 ? X.noff[rowt[t]] : 0;
-    tneed[t] = STORE == 2 && X.nmask ? X.nmask[rowt[t]] : ~0ull;
+    tneed[t] = NEED && X.nmask ? X.nmask[rowt[t]] : ~0ull;
   }
   auto store_pre = [&](int i) {
     const bool writer = NTL == 4 || (NTL == 2 ? (g & 1) == 0 : g == 0);
@@ -530,7 +533,7 @@ __global__ __launch_bounds__(256) void k_psi_mt(PsiParams<T> P, const uint64_t* 
           const int64_t r = base + 16 * t + j;
           if (r < X.ns) *reinterpret_cast<V*>(X.hs + (size_t(i) * X.ns + r) * CH + 16 * tt + 4 * g) = sel;
         }
-        if (STORE == 2 && base + 16 * t + j < R && i >= tc1[t] && i < te1[t] && ((tneed[t] >> i) & 1ull))
+        if (STORE == 2 && base + 16 * t + j < R && i >= tc1[t] && i < te1[t] && (!NEED || ((tneed[t] >> i) & 1ull)))
           *reinterpret_cast<V*>(X.nhs + size_t(toff[t] + (i - tc1[t])) * CH + 16 * tt + 4 * g) = sel;
       }
     }
