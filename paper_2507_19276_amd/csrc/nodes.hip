@@ -16,8 +16,9 @@
 //
 // Three launches per pass of rows, all deterministic:
 //   count:  one workgroup per sample marks the keys present among its rows in
-//           an LDS table with the largest resume site per key; writes the
-//           sample's node count and storage entries (sum of e - c1 + 1);
+//           an LDS table holding the set of resume sites per key (a bit mask,
+//           whose highest site is e); writes the sample's node count and
+//           storage entries (sum of e - c1 + 1);
 //   scan:   one workgroup: exclusive offsets over the samples; a sample's
 //           nodes are kept only if all of them fit the storage capacity
 //           (whole samples in order, so the choice is deterministic);
@@ -28,7 +29,8 @@
 // rows read when they resume at their own resume sites (need); after the rows
 // are sorted by resume site, a fourth launch adds the sites read by rows whose
 // wavefront starts below their own site.  The node pass stores only those
-// carried states (and every log-product state).
+// carried states (and every log-product state); the tensor-term kernels store
+// all of them.
 #include "internal.h"
 
 namespace nqs {
