@@ -15,7 +15,7 @@
 //            position is the bucket's base (sum of the lower totals) plus its
 //            block offset, the rows of the bucket in earlier rounds, the rows
 //            of the bucket in lower wavefronts of the round and the rows of the
-//            bucket in lower lanes (one ballot per distinct key), so equal keys
+//            bucket in lower lanes (one ballot per key bit), so equal keys
 //            keep row order.
 #include "internal.h"
 
@@ -89,21 +89,17 @@ __global__ __launch_bounds__(256) void k_t0_scatter(const uint8_t* __restrict__ 
     const int64_t r = rb + threadIdx.x;
     const bool valid = r < r1;
     const int t = valid ? int(t0[r]) : K;
-    // rank among the lower lanes of this wavefront with the same key: one
-    // ballot per distinct key present in the wavefront
-    int rank = 0;
-    bool done = !valid;
-    while (__ballot(!done)) {
-      if (!done) {
-        const int lead = __builtin_amdgcn_readfirstlane(t);
-        const uint64_t mk = __ballot(t == lead);
-        if (t == lead) {
-          rank = __popcll(mk & below);
-          done = true;
-          if ((mk & below) == 0) wc[wv][lead] = __popcll(mk);
-        }
-      }
+    // the lanes of this wavefront with the same key (keys <= 64: one ballot per
+    // key bit), and the rank among the lower ones
+    uint64_t peers = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < 7; ++b) {
+      const bool bit = (t >> b) & 1;
+      const uint64_t bb = __ballot(bit);
+      peers &= bit ? bb : ~bb;
     }
+    const int rank = __popcll(peers & below);
+    if (valid && (peers & below) == 0) wc[wv][t] = __popcll(peers);
     __syncthreads();
     int pos = 0;
     if (valid) {
