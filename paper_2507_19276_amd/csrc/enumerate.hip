@@ -500,19 +500,42 @@ __global__ __launch_bounds__(256) void k_fill(HamDev H, EnumGeom G, const uint64
   const int64_t r0 = rowptr[n] - row_base;
   int64_t pos = r0 + 1 + segd_off[n * G.S + s];
   const int c0 = s * G.cps, c1 = min(c0 + G.cps, G.nchunks);
-  const uint64_t lt = __lanemask_lt();
+  // the deterministic ranks of 64 chunks at a time, compacted: lane l takes the
+  // l-th set bit of the round (rank order), so every lane evaluates an element
   for (int cb = c0; cb < c1; cb += 64) {
     const int cl = cb + lane;
     const uint64_t mk = cl < c1 ? masks[n * G.nchunks + cl] : 0ull;
-    uint64_t nz = __ballot(mk != 0ull);
-    while (nz) {
-      const int b = __ffsll((unsigned long long)nz) - 1;
-      nz &= nz - 1;
-      const uint64_t mask = __shfl(mk, b);
-      const uint32_t r = uint32_t(cb + b) * 64u + uint32_t(lane);
-      if ((mask >> lane) & 1ull) {
+    const int cnt = __popcll(mk);
+    int incl = cnt;   // inclusive scan of the set-bit counts over the lanes
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const int v = __shfl_up(incl, d);
+      if (lane >= d) incl += v;
+    }
+    const int excl = incl - cnt;
+    const int total = __shfl(incl, 63);
+    for (int j0 = 0; j0 < total; j0 += 64) {
+      const int j = j0 + lane;
+      // the chunk holding set bit j: the last lane c with excl_c <= j
+      int c = 0;
+#pragma unroll
+      for (int step = 32; step > 0; step >>= 1)
+        if (__shfl(excl, c + step) <= j) c += step;
+      // the position of its (j - excl_c)-th set bit, by halving
+      const uint64_t m = __shfl(mk, c);
+      int kk = j - __shfl(excl, c), bit = 0;
+#pragma unroll
+      for (int w = 32; w > 0; w >>= 1) {
+        const int cw = __popcll((m >> bit) & ((1ull << w) - 1ull));
+        if (kk >= cw) {
+          bit += w;
+          kk -= cw;
+        }
+      }
+      if (j < total) {
+        const uint32_t r = uint32_t(cb + c) * 64u + uint32_t(bit);
         const Elem e = element(H, L, lo, hi, r);
-        const int64_t at = pos + __popcll(mask & lt);
+        const int64_t at = pos + j;
         rows.m[2 * at] = e.mlo;
         rows.m[2 * at + 1] = e.mhi;
         rows.coef[at] = e.H;
@@ -520,8 +543,8 @@ __global__ __launch_bounds__(256) void k_fill(HamDev H, EnumGeom G, const uint64
         if (rows.rank) rows.rank[at] = int64_t(r);
         if (rows.t0) row_sites(e.mlo, e.mhi, lo, hi, H.K, rows.t0 + at, rows.sec ? rows.sec + at : nullptr);
       }
-      pos += __popcll(mask);
     }
+    pos += total;
   }
   if (s == 0) {
     if (lane == 0) {
