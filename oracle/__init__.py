@@ -28,6 +28,16 @@ _u64 = C.c_uint64
 _p = C.c_void_p
 
 
+def use_library(path: str) -> None:
+    """Load the oracle from another build of oracle.cpp (for instance one
+    compiled for the host CPU by build.build(native=True)); call before any
+    other function of this module."""
+    global _LIB_PATH, _lib
+    if _lib is not None:
+        raise RuntimeError("the oracle library is already loaded")
+    _LIB_PATH = path
+
+
 def _load():
     global _lib
     if _lib is not None:
@@ -46,24 +56,25 @@ def _load():
     lib.or_connected.restype = _i64
     lib.or_n_params.argtypes = [_i, _i, _p, _i, _i]
     lib.or_n_params.restype = _i64
-    lib.or_amplitudes.argtypes = [_i, _i, _i, _i, _p, _p, _i, _i, _p, _p, _i64, _p, _p, _p, _p, _i]
+    lib.or_amplitudes.argtypes = [_i, _i, _i, _i, _p, _p, _i, _i, _p, _p, _i64, _p, _p, _p, _p, _p, _p, _i]
     lib.or_sample.argtypes = [_i, _i, _i, _i, _p, _p, _i, _p, _p, _i64, _p]
     lib.or_sample_unique.argtypes = [_i, _i, _i, _i, _p, _p, _i, _p, _u64, _i64, _i64, _i64, _p, _p]
     lib.or_sample_unique.restype = _i64
     lib.or_grad.argtypes = [_i, _i, _i, _i, _p, _p, _i, _i, _p, _p, _i64, _p, _p, _i]
     lib.or_eloc.argtypes = [_i, _i, _i, _p, _p, _d, _i, _p, _p, _i, _i, _p, _p, _i64, _d, _i, _u64,
-                            _u64, _i64, _p, _p, _p, _p, _p, _p, _p, _p, _i]
+                            _u64, _i64, _p, _p, _p, _p, _p, _p, _p, _p, _p, _p, _i, _p, _p, _p, _i]
     lib.or_eloc_detail.argtypes = [_i, _i, _i, _p, _p, _d, _i, _p, _p, _i, _i, _p, _p, _i64, _d, _i,
                                    _u64, _u64, _p, _i64, _p, _p, _p, _p]
     lib.or_eloc_table.argtypes = [_i, _i, _i, _p, _p, _d, _p, _p, _i64, _p, _i64, _d, _i, _u64,
                                   _u64, _p, _i]
     lib.or_tucker_rank.argtypes = [_i, _i]
+    lib.or_project_eta.argtypes = [_i, _i, _p, _i, _i, _p]
     lib.or_reweighted_cotangent.argtypes = [_i64, _p, _p, _p, _p, _p]
     lib.or_adamw.argtypes = [_i64, _p, _p, _p, _p, _i64, _d, _d, _d, _d, _d]
     lib.or_amplitudes_cx.argtypes = [_i, _i, _i, _i, _p, _p, _i, _i, _p, _p, _i64, _p, _p, _p, _p, _i]
     lib.or_grad_cx.argtypes = [_i, _i, _i, _i, _p, _p, _i, _i, _p, _p, _i64, _p, _p, _p, _i]
     lib.or_eloc_cx.argtypes = [_i, _i, _i, _p, _p, _d, _i, _p, _p, _i, _i, _p, _p, _i64, _d, _i, _u64,
-                               _u64, _i64, _p, _p, _p, _p, _p, _p, _p, _p, _p, _p, _i]
+                               _u64, _i64, _p, _p, _p, _p, _p, _p, _p, _p, _p, _p, _p, _i]
     lib.or_reweighted_cotangent_cx.argtypes = [_i64, _p, _p, _p, _p, _p, _p, _p]
     _lib = lib
     return lib
@@ -154,7 +165,10 @@ def amplitudes(K, chi, na, nb, parent_ptr, parent_idx, n_hidden, params, samples
     """log|Phi|, sign Phi, log|f|, sign f for every sample (f: cos-RBM, or
     Ising-RBM when ising; Phi with the BDG-TensorRNN term when tensor).  With
     complex parameters (cplx): phase_phi (the phase of Phi) in place of sign
-    Phi, and phase = the phase of Psi (sign f included), both in [-pi, pi]."""
+    Phi, and phase = the phase of Psi (sign f included), both in [-pi, pi].
+    Real parameters also give the sign margins: margin_phi = min over sites of
+    |w.h + c| / (||w|| ||h|| + |c|) and margin_f = min over hidden units of
+    |cos theta| / (1 + |theta|) (inf without a correlator)."""
     pp, pi, prm = _i32(parent_ptr), _i32(parent_idx), _f64(params)
     s = _u64a(samples).reshape(-1, 2)
     N = len(s)
@@ -166,9 +180,11 @@ def amplitudes(K, chi, na, nb, parent_ptr, parent_idx, n_hidden, params, samples
                                  _ptr(prm), _ptr(s), N, _ptr(lphi), _ptr(ph), _ptr(lf), _ptr(sf), nthreads)
         return dict(lphi=lphi, phase_phi=ph, lf=lf, sf=sf, logabs=lphi + lf,
                     phase=wrap_phase(ph + np.where(sf < 0, np.pi, 0.0)))
+    mphi, mf = np.zeros(N), np.zeros(N)
     _load().or_amplitudes(K, chi, na, nb, _ptr(pp), _ptr(pi), n_hidden, _variant(ising, tensor), _ptr(prm), _ptr(s), N,
-                          _ptr(lphi), _ptr(sphi), _ptr(lf), _ptr(sf), nthreads)
-    return dict(lphi=lphi, sphi=sphi, lf=lf, sf=sf, logabs=lphi + lf, sign=sphi * sf)
+                          _ptr(lphi), _ptr(sphi), _ptr(lf), _ptr(sf), _ptr(mphi), _ptr(mf), nthreads)
+    return dict(lphi=lphi, sphi=sphi, lf=lf, sf=sf, logabs=lphi + lf, sign=sphi * sf, margin_phi=mphi,
+                margin_f=mf)
 
 
 def sample(K, chi, na, nb, parent_ptr, parent_idx, params, u, tensor: bool = False,
@@ -222,35 +238,50 @@ def grad(K, chi, na, nb, parent_ptr, parent_idx, n_hidden, params, samples, g,
 def eloc(K, na, nb, h, eri, chi, parent_ptr, parent_idx, n_hidden, params, samples,
          eps=0.0, n_eps=0, seed=0, stream=0, e_core=0.0, nthreads: int = 0,
          sample_base: int = 0, ising: bool = False, tensor: bool = False,
-         cplx: bool = False) -> Dict[str, np.ndarray]:
+         cplx: bool = False, kappa=()) -> Dict[str, np.ndarray]:
     """Semi-stochastic local energies and the reweighted numerators; the draws
     of sample i use Philox counter word 0 = sample_base + i.  With complex
-    parameters eloc and etnum are complex128 and phase (of Psi) replaces sign."""
+    parameters eloc and etnum are complex128 and phase (of Psi) replaces sign.
+    sabs[i] = |H_nn| + sum over the summed terms of |coefficient| |Psi(m)/Psi(n)|
+    (each draw counted once per draw): the scale of the cancellation in the
+    sum, which bounds how far a relative error of the amplitude ratios can
+    move E_loc.  Real parameters: margin_phi / margin_f are the sign margins of
+    the sample (see amplitudes), and for each of up to four kappa values
+    aflip[i, q] = sum over the terms of |term| times 2 (+ 2 kappa / margin_f
+    of the row where that is below kappa) for the terms whose row, or whose
+    sample, has a sign margin below kappa: how far sign flips under state
+    errors of relative size kappa can move E_loc."""
     h, eri = _f64(h), _f64(eri)
     pp, pi, prm = _i32(parent_ptr), _i32(parent_idx), _f64(params)
     s = _u64a(samples).reshape(-1, 2)
     N = len(s)
     if cplx:
-        o = {k: np.zeros(N) for k in ("er", "ei", "tr", "ti", "logabs", "phase", "fsq")}
+        o = {k: np.zeros(N) for k in ("er", "ei", "tr", "ti", "logabs", "phase", "fsq", "sabs")}
         cnt = {k: np.zeros(N, dtype=np.int64) for k in ("n_det", "n_rem", "n_uniq")}
         rc = _load().or_eloc_cx(K, na, nb, _ptr(h), _ptr(eri), e_core, chi, _ptr(pp), _ptr(pi), n_hidden,
                                 _variant(ising, False, True), _ptr(prm), _ptr(s), N, eps, n_eps, seed, stream,
                                 sample_base, _ptr(o["er"]), _ptr(o["ei"]), _ptr(o["tr"]), _ptr(o["ti"]),
                                 _ptr(o["logabs"]), _ptr(o["phase"]), _ptr(o["fsq"]), _ptr(cnt["n_det"]),
-                                _ptr(cnt["n_rem"]), _ptr(cnt["n_uniq"]), nthreads)
+                                _ptr(cnt["n_rem"]), _ptr(cnt["n_uniq"]), _ptr(o["sabs"]), nthreads)
         if rc != 0:
             raise ValueError("sample outside the (n_alpha, n_beta) sector")
         out = dict(eloc=o["er"] + 1j * o["ei"], etnum=o["tr"] + 1j * o["ti"], logabs=o["logabs"],
-                   phase=o["phase"], fsq=o["fsq"])
+                   phase=o["phase"], fsq=o["fsq"], sabs=o["sabs"])
         out.update(cnt)
         return out
-    out = {k: np.zeros(N) for k in ("eloc", "etnum", "logabs", "fsq")}
+    kap = np.ascontiguousarray(np.atleast_1d(np.asarray(kappa, dtype=np.float64)))
+    if kap.size > 4:
+        raise ValueError("at most four kappa values")
+    out = {k: np.zeros(N) for k in ("eloc", "etnum", "logabs", "fsq", "sabs", "margin_phi", "margin_f")}
+    out["aflip"] = np.zeros((N, kap.size))
     sign = np.zeros(N, dtype=np.int8)
     cnt = {k: np.zeros(N, dtype=np.int64) for k in ("n_det", "n_rem", "n_uniq")}
     rc = _load().or_eloc(K, na, nb, _ptr(h), _ptr(eri), e_core, chi, _ptr(pp), _ptr(pi), n_hidden,
                          _variant(ising, tensor), _ptr(prm), _ptr(s), N, eps, n_eps, seed, stream, sample_base, _ptr(out["eloc"]),
                          _ptr(out["etnum"]), _ptr(out["logabs"]), _ptr(sign), _ptr(out["fsq"]),
-                         _ptr(cnt["n_det"]), _ptr(cnt["n_rem"]), _ptr(cnt["n_uniq"]), nthreads)
+                         _ptr(cnt["n_det"]), _ptr(cnt["n_rem"]), _ptr(cnt["n_uniq"]), _ptr(out["sabs"]),
+                         _ptr(kap), int(kap.size), _ptr(out["aflip"]), _ptr(out["margin_phi"]), _ptr(out["margin_f"]),
+                         nthreads)
     if rc != 0:
         raise ValueError("sample outside the (n_alpha, n_beta) sector")
     out["sign"] = sign
@@ -326,6 +357,14 @@ def adamw(params, grad, m, v, step, lr, beta1=0.9, beta2=0.999, eps=1e-8, weight
     return p, mm, vv
 
 
+def project_eta(K, chi, parent_ptr, n_hidden, params, ising=False, tensor=False, cplx=False):
+    """A copy of the packed parameters with every negative eta entry set to 0
+    (the constraint eta >= 0 of Sec. 2.1)."""
+    pp, p = _i32(parent_ptr), _f64(params).copy()
+    _load().or_project_eta(K, chi, _ptr(pp), n_hidden, _variant(ising, tensor, cplx), _ptr(p))
+    return p
+
+
 def vmc_step(K, na, nb, h, eri, chi, parent_ptr, parent_idx, n_hidden, params, m, v, step, n_draws,
              sample_seed, draw_base=0, eps=0.0, n_eps=0, eloc_seed=0, stream=0, lr=1e-3, beta1=0.9,
              beta2=0.999, adam_eps=1e-8, weight_decay=0.0, e_core=0.0, ising=False, tensor=False, cplx=False):
@@ -333,7 +372,8 @@ def vmc_step(K, na, nb, h, eri, chi, parent_ptr, parent_idx, n_hidden, params, m
     unique samples with counts, semi-stochastic local energies, the reweighted
     gradient of Eq. (19) (through the cotangent above and the gradient of
     ln|Psi|, and of the phase with complex parameters), and one AdamW update
-    (complex parameters as pairs of reals)."""
+    (complex parameters as pairs of reals) followed by the projection of eta
+    onto eta >= 0."""
     uniq, cnt = sample_unique(K, chi, na, nb, parent_ptr, parent_idx, params, sample_seed, n_draws, draw_base,
                               tensor=tensor, cplx=cplx)
     out = eloc(K, na, nb, h, eri, chi, parent_ptr, parent_idx, n_hidden, params, uniq, eps=eps, n_eps=n_eps,
@@ -343,8 +383,10 @@ def vmc_step(K, na, nb, h, eri, chi, parent_ptr, parent_idx, n_hidden, params, m
         g = grad(K, chi, na, nb, parent_ptr, parent_idx, n_hidden, params, uniq, cot, ising=ising, cplx=True,
                  g_phase=cotp)
         p, mm, vv = adamw(params, g, m, v, step, lr, beta1, beta2, adam_eps, weight_decay)
+        p = project_eta(K, chi, parent_ptr, n_hidden, p, ising=ising, cplx=True)
         return dict(params=p, m=mm, v=vv, grad=g, E=E, samples=uniq, counts=cnt, eloc=out)
     cot, E = reweighted_cotangent(cnt.astype(np.float64), out["etnum"], out["fsq"])
     g = grad(K, chi, na, nb, parent_ptr, parent_idx, n_hidden, params, uniq, cot, ising=ising, tensor=tensor)
     p, mm, vv = adamw(params, g, m, v, step, lr, beta1, beta2, adam_eps, weight_decay)
+    p = project_eta(K, chi, parent_ptr, n_hidden, p, ising=ising, tensor=tensor)
     return dict(params=p, m=mm, v=vv, grad=g, E=E, samples=uniq, counts=cnt, eloc=out)

@@ -6,7 +6,8 @@
 // slow, obviously correct definitions.  It shares no code, header, table or
 // helper with the HIP library.
 //
-// Build: g++ -O2 -fopenmp -ffp-contract=off -shared -fPIC (see build.py).
+// Build: g++ -O3 -march=x86-64-v3 -fopenmp -ffp-contract=off -shared -fPIC (see build.py;
+// the CPU-baseline timing uses -march=native for the host it runs on).
 // -ffp-contract=off is essential: Hamiltonian elements are compared bit for
 // bit with the GPU, so no multiply-add may be fused behind our back.
 //
@@ -405,7 +406,10 @@ void site_candidates(const Ansatz& A, int i, const std::vector<double>& carried,
 }
 
 // log|Phi(n)| and sign Phi(n); returns false for an ONV outside the sector.
-bool phi_eval(const Ansatz& A, const Det& n, double* logabs, int* sgn, Trace* tr) {
+// margin (nullable): the smallest relative size of the sign argument over
+// the sites, |w_i . h_i + c_i| / (||w_i|| ||h_i|| + |c_i|); a perturbation of
+// the states of relative norm rho can flip the sign only where it is < rho.
+bool phi_eval(const Ansatz& A, const Det& n, double* logabs, int* sgn, Trace* tr, double* margin = nullptr) {
   const int K = A.K, chi = A.chi;
   std::vector<double> carried(size_t(K) * chi, 0.0);
   std::vector<double> cand(4 * chi);
@@ -436,6 +440,15 @@ bool phi_eval(const Ansatz& A, const Det& n, double* logabs, int* sgn, Trace* tr
     double t = A.prm[A.offC[i]];
     for (int u = 0; u < chi; ++u) t += A.prm[A.offW[i] + u] * cand[si * chi + u];
     if (t < 0) sg = -sg;
+    if (margin) {
+      double ww = 0.0, hh = 0.0;
+      for (int u = 0; u < chi; ++u) {
+        ww += A.prm[A.offW[i] + u] * A.prm[A.offW[i] + u];
+        hh += cand[si * chi + u] * cand[si * chi + u];
+      }
+      const double mu = std::fabs(t) / (std::sqrt(ww) * std::sqrt(hh) + std::fabs(A.prm[A.offC[i]]));
+      if (i == 0 || mu < *margin) *margin = mu;
+    }
     for (int u = 0; u < chi; ++u) carried[size_t(i) * chi + u] = cand[si * chi + u];
     if (tr) {
       std::copy(cand.begin(), cand.end(), tr->cand.begin() + size_t(i) * 4 * chi);
@@ -471,7 +484,9 @@ double corr_theta(const Ansatz& A, const Det& n, int k) {
   return th;
 }
 
-void corr_eval(const Ansatz& A, const Det& n, double* logabs, int* sgn) {
+// margin (nullable): min_k |cos theta_k| / (1 + |theta_k|), the distance of
+// the correlator from a sign change relative to the size of its argument
+void corr_eval(const Ansatz& A, const Det& n, double* logabs, int* sgn, double* margin = nullptr) {
   double la = 0.0;
   int sg = 1;
   for (int k = 0; k < A.nh; ++k) {
@@ -479,6 +494,10 @@ void corr_eval(const Ansatz& A, const Det& n, double* logabs, int* sgn) {
     const double c = std::cos(th);
     la += std::log(std::fabs(c));
     if (c < 0) sg = -sg;
+    if (margin) {
+      const double mu = std::fabs(c) / (1.0 + std::fabs(th));
+      if (k == 0 || mu < *margin) *margin = mu;
+    }
   }
   *logabs = la;
   *sgn = sg;
@@ -489,14 +508,15 @@ struct Amp {
   int sphi, sf;
   double phase;   // phase of Phi (complex parameters); 0 for real parameters
   bool valid;
+  double mphi = HUGE_VAL, mf = HUGE_VAL;   // sign margins of Phi and of f (real parameters)
 };
 
 Amp amp_eval(const Ansatz& A, const Det& n) {
   Amp r;
   r.phase = 0.0;
-  r.valid = phi_eval(A, n, &r.lphi, &r.sphi, nullptr);
+  r.valid = phi_eval(A, n, &r.lphi, &r.sphi, nullptr, &r.mphi);
   r.lf = 0.0; r.sf = 1;
-  if (A.nh) corr_eval(A, n, &r.lf, &r.sf);
+  if (A.nh) corr_eval(A, n, &r.lf, &r.sf, &r.mf);
   return r;
 }
 
@@ -892,6 +912,9 @@ int cx_sample(int K, int chi, int na, int nb, const int* pptr, const int* pidx, 
 // --------------------------------------------------------------------------
 struct ElocOut {
   double eloc, etnum, logabs, fsq;
+  double sabs;                       // |H_nn| + sum over the summed terms of |coefficient| |Psi(m)/Psi(n)|
+  double aflip[4];                   // per kappa: sum of |term| x flip_weight over the terms
+  double mphi, mf;                   // sign margins of Phi(n) and f(n)
   double eloc_im, etnum_im, phase;   // complex parameters: imaginary parts, phase of Psi(n)
   int sign;
   int64_t n_det, n_rem, n_uniq;
@@ -913,15 +936,29 @@ uint64_t scaled_draw(const uint32_t U[4], uint64_t Q) {
   return uint64_t(t >> 64);
 }
 
+// How much a term x of E_loc(n) may move, beyond the relative error of its
+// ratio, when the states carry relative errors up to kappa: a sign of Phi whose
+// margin is below kappa (the row's, or the sample's, which flips every term)
+// may flip, moving the term by up to 2|x|; a correlator factor with
+// |cos theta| / (1 + |theta|) below kappa may also change its size by up to a
+// factor 1 + kappa / margin.  Returns the multiple of |x| to allow.
+double flip_weight(const Amp& an, const Amp& am, double kappa) {
+  if (!(am.mphi < kappa || an.mphi < kappa || am.mf < kappa)) return 0.0;
+  return 2.0 + (am.mf < kappa ? 2.0 * kappa / am.mf : 0.0);
+}
+
 template <class AmpFn>
 ElocOut eloc_one(const Ham& H, const Det& n, int64_t sample_idx, double eps, int n_eps,
                  uint64_t seed, uint64_t stream, AmpFn amp,
-                 std::vector<int64_t>* det_ranks, std::vector<int64_t>* draw_ranks) {
+                 std::vector<int64_t>* det_ranks, std::vector<int64_t>* draw_ranks,
+                 const double* kappa = nullptr, int n_kappa = 0) {
   ElocOut o{};
   std::vector<Conn> conns;
   connected(H, n, conns);
   const double Hnn = diag_element(H, n);
   const Amp an = amp(n);
+  o.mphi = an.mphi;
+  o.mf = an.mf;
   o.logabs = an.lphi + an.lf;
   o.sign = an.sphi * an.sf;
   o.fsq = std::exp(2.0 * an.lf);
@@ -946,6 +983,8 @@ ElocOut eloc_one(const Ham& H, const Det& n, int64_t sample_idx, double eps, int
       ed_t += xt * cr;
       ed_i += x * ci;
       ed_ti += xt * ci;
+      o.sabs += std::fabs(x);
+      for (int q = 0; q < n_kappa; ++q) o.aflip[q] += std::fabs(x) * flip_weight(an, am, kappa[q]);
       ++o.n_det;
       if (det_ranks) det_ranks->push_back(int64_t(r));
     } else {
@@ -988,11 +1027,14 @@ ElocOut eloc_one(const Ham& H, const Det& n, int64_t sample_idx, double eps, int
       es_t += xt * cr;
       es_i += x * ci;
       es_ti += xt * ci;
+      o.sabs += std::fabs(x);
+      for (int q = 0; q < n_kappa; ++q) o.aflip[q] += std::fabs(x) * flip_weight(an, am, kappa[q]);
     }
     std::sort(picked.begin(), picked.end());
     o.n_uniq = int64_t(std::unique(picked.begin(), picked.end()) - picked.begin());
   }
   o.eloc = Hnn + ed + es;
+  o.sabs += std::fabs(Hnn);
   o.etnum = o.fsq * Hnn + ed_t + es_t;
   o.eloc_im = ed_i + es_i;
   o.etnum_im = ed_ti + es_ti;
@@ -1095,13 +1137,15 @@ int or_grad_cx(int K, int chi, int na, int nb, const int* pptr, const int* pidx,
 // log|Phi|, sign Phi, log|f|, sign f for N samples
 int or_amplitudes(int K, int chi, int na, int nb, const int* pptr, const int* pidx, int nh, int variant,
                   const double* prm, const uint64_t* samples, int64_t N, double* lphi,
-                  int* sphi, double* lf, int* sf, int nthreads) {
+                  int* sphi, double* lf, int* sf, double* mphi, double* mf, int nthreads) {
   Ansatz A = make_ansatz(K, chi, na, nb, pptr, pidx, nh, variant, prm);
 #pragma omp parallel for schedule(dynamic, 16) num_threads(nthreads_or_default(nthreads))
   for (int64_t i = 0; i < N; ++i) {
     Det d = det_from_words(K, samples + 2 * i);
     Amp a = amp_eval(A, d);
     lphi[i] = a.lphi; sphi[i] = a.sphi; lf[i] = a.lf; sf[i] = a.sf;
+    if (mphi) mphi[i] = a.mphi;
+    if (mf) mf[i] = a.mf;
   }
   return 0;
 }
@@ -1209,7 +1253,9 @@ int or_eloc(int K, int na, int nb, const double* h, const double* eri, double ec
             const uint64_t* samples, int64_t N, double eps, int n_eps, uint64_t seed,
             uint64_t stream, int64_t sample_base, double* eloc, double* etnum, double* logabs,
             int8_t* sign, double* fsq, int64_t* n_det, int64_t* n_rem, int64_t* n_uniq,
+            double* sabs, const double* kappa, int n_kappa, double* aflip, double* mphi, double* mf,
             int nthreads) {
+  if (n_kappa < 0 || n_kappa > 4) return -2;
   Ham H{K, h, eri, ecore};
   Ansatz A = make_ansatz(K, chi, na, nb, pptr, pidx, nh, variant, prm);
   for (int64_t i = 0; i < N; ++i) {
@@ -1220,12 +1266,16 @@ int or_eloc(int K, int na, int nb, const double* h, const double* eri, double ec
 #pragma omp parallel for schedule(dynamic, 1) num_threads(nthreads_or_default(nthreads))
   for (int64_t i = 0; i < N; ++i) {
     Det d = det_from_words(K, samples + 2 * i);
-    ElocOut o = eloc_one(H, d, sample_base + i, eps, n_eps, seed, stream, amp, nullptr, nullptr);
+    ElocOut o = eloc_one(H, d, sample_base + i, eps, n_eps, seed, stream, amp, nullptr, nullptr, kappa, n_kappa);
     eloc[i] = o.eloc; etnum[i] = o.etnum; logabs[i] = o.logabs; sign[i] = int8_t(o.sign);
     fsq[i] = o.fsq;
     if (n_det) n_det[i] = o.n_det;
     if (n_rem) n_rem[i] = o.n_rem;
     if (n_uniq) n_uniq[i] = o.n_uniq;
+    if (sabs) sabs[i] = o.sabs;
+    for (int q = 0; q < n_kappa && aflip; ++q) aflip[i * n_kappa + q] = o.aflip[q];
+    if (mphi) mphi[i] = o.mphi;
+    if (mf) mf[i] = o.mf;
   }
   return 0;
 }
@@ -1237,7 +1287,7 @@ int or_eloc_cx(int K, int na, int nb, const double* h, const double* eri, double
                const uint64_t* samples, int64_t N, double eps, int n_eps, uint64_t seed,
                uint64_t stream, int64_t sample_base, double* eloc, double* eloc_im, double* etnum,
                double* etnum_im, double* logabs, double* phase, double* fsq, int64_t* n_det,
-               int64_t* n_rem, int64_t* n_uniq, int nthreads) {
+               int64_t* n_rem, int64_t* n_uniq, double* sabs, int nthreads) {
   Ham H{K, h, eri, ecore};
   CxAnsatz A = make_cx_ansatz(K, chi, na, nb, pptr, pidx, nh, variant & 1, prm);
   for (int64_t i = 0; i < N; ++i) {
@@ -1254,6 +1304,7 @@ int or_eloc_cx(int K, int na, int nb, const double* h, const double* eri, double
     if (n_det) n_det[i] = o.n_det;
     if (n_rem) n_rem[i] = o.n_rem;
     if (n_uniq) n_uniq[i] = o.n_uniq;
+    if (sabs) sabs[i] = o.sabs;
   }
   return 0;
 }
@@ -1332,6 +1383,21 @@ int or_adamw(int64_t n, double* p, const double* g, double* m, double* v, int64_
     const double mh = m[k] / c1, vh = v[k] / c2;
     p[k] -= lr * mh / (std::sqrt(vh) + eps);
   }
+  return 0;
+}
+
+// Projection of the packed parameters onto the constraint eta >= 0 of the
+// conditional P = h^T eta h (Sec. 2.1): every negative eta entry becomes 0
+// (NaN stays NaN, so a diverged step is still refused when bound).  Applied
+// after each AdamW update of a VMC step: projected gradient descent.
+int or_project_eta(int K, int chi, const int* pptr, int nh, int variant, double* p) {
+  const bool cx = (variant & 4) != 0;
+  std::vector<size_t> off;
+  if (cx) off = make_cx_ansatz(K, chi, 0, 0, pptr, nullptr, nh, (variant & 1) != 0, nullptr).offEta;
+  else off = make_ansatz(K, chi, 0, 0, pptr, nullptr, nh, variant, nullptr).offEta;
+  for (int i = 0; i < K; ++i)
+    for (int u = 0; u < chi; ++u)
+      if (p[off[i] + u] < 0.0) p[off[i] + u] = 0.0;
   return 0;
 }
 
