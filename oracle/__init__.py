@@ -56,13 +56,13 @@ def _load():
     lib.or_connected.restype = _i64
     lib.or_n_params.argtypes = [_i, _i, _p, _i, _i]
     lib.or_n_params.restype = _i64
-    lib.or_amplitudes.argtypes = [_i, _i, _i, _i, _p, _p, _i, _i, _p, _p, _i64, _p, _p, _p, _p, _p, _p, _i]
+    lib.or_amplitudes.argtypes = [_i, _i, _i, _i, _p, _p, _i, _i, _p, _p, _i64, _p, _p, _p, _p, _p, _p, _p, _i]
     lib.or_sample.argtypes = [_i, _i, _i, _i, _p, _p, _i, _p, _p, _i64, _p]
     lib.or_sample_unique.argtypes = [_i, _i, _i, _i, _p, _p, _i, _p, _u64, _i64, _i64, _i64, _p, _p]
     lib.or_sample_unique.restype = _i64
     lib.or_grad.argtypes = [_i, _i, _i, _i, _p, _p, _i, _i, _p, _p, _i64, _p, _p, _i]
     lib.or_eloc.argtypes = [_i, _i, _i, _p, _p, _d, _i, _p, _p, _i, _i, _p, _p, _i64, _d, _i, _u64,
-                            _u64, _i64, _p, _p, _p, _p, _p, _p, _p, _p, _p, _p, _i, _p, _p, _p, _i]
+                            _u64, _i64, _p, _p, _p, _p, _p, _p, _p, _p, _p, _p, _p, _i, _d, _p, _p, _p, _i]
     lib.or_eloc_detail.argtypes = [_i, _i, _i, _p, _p, _d, _i, _p, _p, _i, _i, _p, _p, _i64, _d, _i,
                                    _u64, _u64, _p, _i64, _p, _p, _p, _p]
     lib.or_eloc_table.argtypes = [_i, _i, _i, _p, _p, _d, _p, _p, _i64, _p, _i64, _d, _i, _u64,
@@ -168,7 +168,9 @@ def amplitudes(K, chi, na, nb, parent_ptr, parent_idx, n_hidden, params, samples
     Phi, and phase = the phase of Psi (sign f included), both in [-pi, pi].
     Real parameters also give the sign margins: margin_phi = min over sites of
     |w.h + c| / (||w|| ||h|| + |c|) and margin_f = min over hidden units of
-    |cos theta| / (1 + |theta|) (inf without a correlator)."""
+    |cos theta| / (1 + |theta|) (inf without a correlator), and
+    corr_sens = sum over hidden units of (1 + |theta|) / |cos theta| (0
+    without a correlator)."""
     pp, pi, prm = _i32(parent_ptr), _i32(parent_idx), _f64(params)
     s = _u64a(samples).reshape(-1, 2)
     N = len(s)
@@ -180,11 +182,11 @@ def amplitudes(K, chi, na, nb, parent_ptr, parent_idx, n_hidden, params, samples
                                  _ptr(prm), _ptr(s), N, _ptr(lphi), _ptr(ph), _ptr(lf), _ptr(sf), nthreads)
         return dict(lphi=lphi, phase_phi=ph, lf=lf, sf=sf, logabs=lphi + lf,
                     phase=wrap_phase(ph + np.where(sf < 0, np.pi, 0.0)))
-    mphi, mf = np.zeros(N), np.zeros(N)
+    mphi, mf, fs = np.zeros(N), np.zeros(N), np.zeros(N)
     _load().or_amplitudes(K, chi, na, nb, _ptr(pp), _ptr(pi), n_hidden, _variant(ising, tensor), _ptr(prm), _ptr(s), N,
-                          _ptr(lphi), _ptr(sphi), _ptr(lf), _ptr(sf), _ptr(mphi), _ptr(mf), nthreads)
+                          _ptr(lphi), _ptr(sphi), _ptr(lf), _ptr(sf), _ptr(mphi), _ptr(mf), _ptr(fs), nthreads)
     return dict(lphi=lphi, sphi=sphi, lf=lf, sf=sf, logabs=lphi + lf, sign=sphi * sf, margin_phi=mphi,
-                margin_f=mf)
+                margin_f=mf, corr_sens=fs)
 
 
 def sample(K, chi, na, nb, parent_ptr, parent_idx, params, u, tensor: bool = False,
@@ -238,7 +240,7 @@ def grad(K, chi, na, nb, parent_ptr, parent_idx, n_hidden, params, samples, g,
 def eloc(K, na, nb, h, eri, chi, parent_ptr, parent_idx, n_hidden, params, samples,
          eps=0.0, n_eps=0, seed=0, stream=0, e_core=0.0, nthreads: int = 0,
          sample_base: int = 0, ising: bool = False, tensor: bool = False,
-         cplx: bool = False, kappa=()) -> Dict[str, np.ndarray]:
+         cplx: bool = False, bounds=(), u_f: float = 0.0) -> Dict[str, np.ndarray]:
     """Semi-stochastic local energies and the reweighted numerators; the draws
     of sample i use Philox counter word 0 = sample_base + i.  With complex
     parameters eloc and etnum are complex128 and phase (of Psi) replaces sign.
@@ -246,11 +248,14 @@ def eloc(K, na, nb, h, eri, chi, parent_ptr, parent_idx, n_hidden, params, sampl
     (each draw counted once per draw): the scale of the cancellation in the
     sum, which bounds how far a relative error of the amplitude ratios can
     move E_loc.  Real parameters: margin_phi / margin_f are the sign margins of
-    the sample (see amplitudes), and for each of up to four kappa values
-    aflip[i, q] = sum over the terms of |term| times 2 (+ 2 kappa / margin_f
-    of the row where that is below kappa) for the terms whose row, or whose
-    sample, has a sign margin below kappa: how far sign flips under state
-    errors of relative size kappa can move E_loc."""
+    the sample (see amplitudes).  bounds = up to four (L, kappa) pairs and u_f
+    give ebound[i, q] = sum over the terms of |term| times
+    expm1(2 L + u_f (corr_sens(m) + corr_sens(n))), plus 2 where a sign may
+    flip (a Phi margin of the row or the sample below kappa, or the row's
+    correlator margin below 8 u_f), plus 2 (8 u_f) / margin_f where that
+    margin is below 8 u_f: how far E_loc can move when every log|Phi| is off
+    by at most L, states carry relative errors up to kappa and each cos theta
+    relative errors up to u_f (1 + |theta|)."""
     h, eri = _f64(h), _f64(eri)
     pp, pi, prm = _i32(parent_ptr), _i32(parent_idx), _f64(params)
     s = _u64a(samples).reshape(-1, 2)
@@ -269,19 +274,20 @@ def eloc(K, na, nb, h, eri, chi, parent_ptr, parent_idx, n_hidden, params, sampl
                    phase=o["phase"], fsq=o["fsq"], sabs=o["sabs"])
         out.update(cnt)
         return out
-    kap = np.ascontiguousarray(np.atleast_1d(np.asarray(kappa, dtype=np.float64)))
-    if kap.size > 4:
-        raise ValueError("at most four kappa values")
+    bl = np.ascontiguousarray(np.asarray([b[0] for b in bounds], dtype=np.float64).reshape(-1))
+    bk = np.ascontiguousarray(np.asarray([b[1] for b in bounds], dtype=np.float64).reshape(-1))
+    if bl.size > 4:
+        raise ValueError("at most four bound columns")
     out = {k: np.zeros(N) for k in ("eloc", "etnum", "logabs", "fsq", "sabs", "margin_phi", "margin_f")}
-    out["aflip"] = np.zeros((N, kap.size))
+    out["ebound"] = np.zeros((N, bl.size))
     sign = np.zeros(N, dtype=np.int8)
     cnt = {k: np.zeros(N, dtype=np.int64) for k in ("n_det", "n_rem", "n_uniq")}
     rc = _load().or_eloc(K, na, nb, _ptr(h), _ptr(eri), e_core, chi, _ptr(pp), _ptr(pi), n_hidden,
                          _variant(ising, tensor), _ptr(prm), _ptr(s), N, eps, n_eps, seed, stream, sample_base, _ptr(out["eloc"]),
                          _ptr(out["etnum"]), _ptr(out["logabs"]), _ptr(sign), _ptr(out["fsq"]),
                          _ptr(cnt["n_det"]), _ptr(cnt["n_rem"]), _ptr(cnt["n_uniq"]), _ptr(out["sabs"]),
-                         _ptr(kap), int(kap.size), _ptr(out["aflip"]), _ptr(out["margin_phi"]), _ptr(out["margin_f"]),
-                         nthreads)
+                         _ptr(bl), _ptr(bk), int(bl.size), float(u_f), _ptr(out["ebound"]), _ptr(out["margin_phi"]),
+                         _ptr(out["margin_f"]), nthreads)
     if rc != 0:
         raise ValueError("sample outside the (n_alpha, n_beta) sector")
     out["sign"] = sign

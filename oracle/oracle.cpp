@@ -485,8 +485,12 @@ double corr_theta(const Ansatz& A, const Det& n, int k) {
 }
 
 // margin (nullable): min_k |cos theta_k| / (1 + |theta_k|), the distance of
-// the correlator from a sign change relative to the size of its argument
-void corr_eval(const Ansatz& A, const Det& n, double* logabs, int* sgn, double* margin = nullptr) {
+// the correlator from a sign change relative to the size of its argument;
+// sens (nullable): sum_k (1 + |theta_k|) / |cos theta_k|, so that relative
+// errors of size u (1 + |theta_k|) in each cos theta_k move log|f| by at most
+// u sens to first order
+void corr_eval(const Ansatz& A, const Det& n, double* logabs, int* sgn, double* margin = nullptr,
+               double* sens = nullptr) {
   double la = 0.0;
   int sg = 1;
   for (int k = 0; k < A.nh; ++k) {
@@ -498,6 +502,7 @@ void corr_eval(const Ansatz& A, const Det& n, double* logabs, int* sgn, double* 
       const double mu = std::fabs(c) / (1.0 + std::fabs(th));
       if (k == 0 || mu < *margin) *margin = mu;
     }
+    if (sens) *sens = (k == 0 ? 0.0 : *sens) + (1.0 + std::fabs(th)) / std::fabs(c);
   }
   *logabs = la;
   *sgn = sg;
@@ -509,6 +514,7 @@ struct Amp {
   double phase;   // phase of Phi (complex parameters); 0 for real parameters
   bool valid;
   double mphi = HUGE_VAL, mf = HUGE_VAL;   // sign margins of Phi and of f (real parameters)
+  double sens = 0.0;                        // log sensitivity of f (corr_eval)
 };
 
 Amp amp_eval(const Ansatz& A, const Det& n) {
@@ -516,7 +522,7 @@ Amp amp_eval(const Ansatz& A, const Det& n) {
   r.phase = 0.0;
   r.valid = phi_eval(A, n, &r.lphi, &r.sphi, nullptr, &r.mphi);
   r.lf = 0.0; r.sf = 1;
-  if (A.nh) corr_eval(A, n, &r.lf, &r.sf, &r.mf);
+  if (A.nh) corr_eval(A, n, &r.lf, &r.sf, &r.mf, &r.sens);
   return r;
 }
 
@@ -913,7 +919,7 @@ int cx_sample(int K, int chi, int na, int nb, const int* pptr, const int* pidx, 
 struct ElocOut {
   double eloc, etnum, logabs, fsq;
   double sabs;                       // |H_nn| + sum over the summed terms of |coefficient| |Psi(m)/Psi(n)|
-  double aflip[4];                   // per kappa: sum of |term| x flip_weight over the terms
+  double ebound[4];                  // per bound column: sum of |term| x term_weight over the terms
   double mphi, mf;                   // sign margins of Phi(n) and f(n)
   double eloc_im, etnum_im, phase;   // complex parameters: imaginary parts, phase of Psi(n)
   int sign;
@@ -936,22 +942,37 @@ uint64_t scaled_draw(const uint32_t U[4], uint64_t Q) {
   return uint64_t(t >> 64);
 }
 
-// How much a term x of E_loc(n) may move, beyond the relative error of its
-// ratio, when the states carry relative errors up to kappa: a sign of Phi whose
-// margin is below kappa (the row's, or the sample's, which flips every term)
-// may flip, moving the term by up to 2|x|; a correlator factor with
-// |cos theta| / (1 + |theta|) below kappa may also change its size by up to a
-// factor 1 + kappa / margin.  Returns the multiple of |x| to allow.
-double flip_weight(const Amp& an, const Amp& am, double kappa) {
-  if (!(am.mphi < kappa || an.mphi < kappa || am.mf < kappa)) return 0.0;
-  return 2.0 + (am.mf < kappa ? 2.0 * kappa / am.mf : 0.0);
+// Error model of the reduced-precision paths (one column per precision):
+// the bond contractions carry relative state errors up to kappa and move
+// log|Phi| of any row by at most L; the correlator's cos theta is evaluated
+// with relative error u_f (1 + |theta|), which moves log|f| by at most
+// u_f sens and can flip its sign only where its margin is below
+// kappa_f = 8 u_f.
+struct BoundCol {
+  double L, kappa;
+};
+
+// How far a term x of E_loc(n) may move under that model, as a multiple of
+// |x|: its ratio is within e^{+-delta}, delta = 2 L + u_f (sens(m) + sens(n))
+// (both amplitudes' log errors), giving e^delta - 1; where a sign can flip (a
+// Phi margin of the row or of the sample below kappa, or the row's correlator
+// margin below kappa_f) the term may also change sign, adding 2, and a
+// correlator margin below kappa_f may grow |f(m)| by up to 1 + kappa_f /
+// margin, adding 2 kappa_f / margin.
+double term_weight(const Amp& an, const Amp& am, const BoundCol& b, double u_f) {
+  const double kf = 8.0 * u_f;
+  const double delta = 2.0 * b.L + u_f * (am.sens + an.sens);
+  double w = std::expm1(delta);
+  if (am.mphi < b.kappa || an.mphi < b.kappa || am.mf < kf) w += 2.0;
+  if (am.mf < kf) w += 2.0 * kf / am.mf;
+  return w;
 }
 
 template <class AmpFn>
 ElocOut eloc_one(const Ham& H, const Det& n, int64_t sample_idx, double eps, int n_eps,
                  uint64_t seed, uint64_t stream, AmpFn amp,
                  std::vector<int64_t>* det_ranks, std::vector<int64_t>* draw_ranks,
-                 const double* kappa = nullptr, int n_kappa = 0) {
+                 const BoundCol* cols = nullptr, int n_cols = 0, double u_f = 0.0) {
   ElocOut o{};
   std::vector<Conn> conns;
   connected(H, n, conns);
@@ -984,7 +1005,7 @@ ElocOut eloc_one(const Ham& H, const Det& n, int64_t sample_idx, double eps, int
       ed_i += x * ci;
       ed_ti += xt * ci;
       o.sabs += std::fabs(x);
-      for (int q = 0; q < n_kappa; ++q) o.aflip[q] += std::fabs(x) * flip_weight(an, am, kappa[q]);
+      for (int q = 0; q < n_cols; ++q) o.ebound[q] += std::fabs(x) * term_weight(an, am, cols[q], u_f);
       ++o.n_det;
       if (det_ranks) det_ranks->push_back(int64_t(r));
     } else {
@@ -1028,7 +1049,7 @@ ElocOut eloc_one(const Ham& H, const Det& n, int64_t sample_idx, double eps, int
       es_i += x * ci;
       es_ti += xt * ci;
       o.sabs += std::fabs(x);
-      for (int q = 0; q < n_kappa; ++q) o.aflip[q] += std::fabs(x) * flip_weight(an, am, kappa[q]);
+      for (int q = 0; q < n_cols; ++q) o.ebound[q] += std::fabs(x) * term_weight(an, am, cols[q], u_f);
     }
     std::sort(picked.begin(), picked.end());
     o.n_uniq = int64_t(std::unique(picked.begin(), picked.end()) - picked.begin());
@@ -1137,7 +1158,7 @@ int or_grad_cx(int K, int chi, int na, int nb, const int* pptr, const int* pidx,
 // log|Phi|, sign Phi, log|f|, sign f for N samples
 int or_amplitudes(int K, int chi, int na, int nb, const int* pptr, const int* pidx, int nh, int variant,
                   const double* prm, const uint64_t* samples, int64_t N, double* lphi,
-                  int* sphi, double* lf, int* sf, double* mphi, double* mf, int nthreads) {
+                  int* sphi, double* lf, int* sf, double* mphi, double* mf, double* fsens, int nthreads) {
   Ansatz A = make_ansatz(K, chi, na, nb, pptr, pidx, nh, variant, prm);
 #pragma omp parallel for schedule(dynamic, 16) num_threads(nthreads_or_default(nthreads))
   for (int64_t i = 0; i < N; ++i) {
@@ -1146,6 +1167,7 @@ int or_amplitudes(int K, int chi, int na, int nb, const int* pptr, const int* pi
     lphi[i] = a.lphi; sphi[i] = a.sphi; lf[i] = a.lf; sf[i] = a.sf;
     if (mphi) mphi[i] = a.mphi;
     if (mf) mf[i] = a.mf;
+    if (fsens) fsens[i] = a.sens;
   }
   return 0;
 }
@@ -1253,9 +1275,11 @@ int or_eloc(int K, int na, int nb, const double* h, const double* eri, double ec
             const uint64_t* samples, int64_t N, double eps, int n_eps, uint64_t seed,
             uint64_t stream, int64_t sample_base, double* eloc, double* etnum, double* logabs,
             int8_t* sign, double* fsq, int64_t* n_det, int64_t* n_rem, int64_t* n_uniq,
-            double* sabs, const double* kappa, int n_kappa, double* aflip, double* mphi, double* mf,
-            int nthreads) {
-  if (n_kappa < 0 || n_kappa > 4) return -2;
+            double* sabs, const double* bound_L, const double* bound_kappa, int n_cols, double u_f,
+            double* ebound, double* mphi, double* mf, int nthreads) {
+  if (n_cols < 0 || n_cols > 4) return -2;
+  BoundCol cols[4];
+  for (int q = 0; q < n_cols; ++q) cols[q] = BoundCol{bound_L[q], bound_kappa[q]};
   Ham H{K, h, eri, ecore};
   Ansatz A = make_ansatz(K, chi, na, nb, pptr, pidx, nh, variant, prm);
   for (int64_t i = 0; i < N; ++i) {
@@ -1266,14 +1290,14 @@ int or_eloc(int K, int na, int nb, const double* h, const double* eri, double ec
 #pragma omp parallel for schedule(dynamic, 1) num_threads(nthreads_or_default(nthreads))
   for (int64_t i = 0; i < N; ++i) {
     Det d = det_from_words(K, samples + 2 * i);
-    ElocOut o = eloc_one(H, d, sample_base + i, eps, n_eps, seed, stream, amp, nullptr, nullptr, kappa, n_kappa);
+    ElocOut o = eloc_one(H, d, sample_base + i, eps, n_eps, seed, stream, amp, nullptr, nullptr, cols, n_cols, u_f);
     eloc[i] = o.eloc; etnum[i] = o.etnum; logabs[i] = o.logabs; sign[i] = int8_t(o.sign);
     fsq[i] = o.fsq;
     if (n_det) n_det[i] = o.n_det;
     if (n_rem) n_rem[i] = o.n_rem;
     if (n_uniq) n_uniq[i] = o.n_uniq;
     if (sabs) sabs[i] = o.sabs;
-    for (int q = 0; q < n_kappa && aflip; ++q) aflip[i * n_kappa + q] = o.aflip[q];
+    for (int q = 0; q < n_cols && ebound; ++q) ebound[i * n_cols + q] = o.ebound[q];
     if (mphi) mphi[i] = o.mphi;
     if (mf) mf[i] = o.mf;
   }

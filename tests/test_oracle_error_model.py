@@ -108,34 +108,63 @@ def test_correlator_margin_closed_form():
     np.testing.assert_allclose(a["margin_f"], want, rtol=1e-14)
 
 
-def test_flip_allowance_counts_the_rows_below_kappa():
-    """A_n(kappa) = 2 sum |H r| over the terms whose row (or sample) has a
-    sign margin below kappa: none below the smallest margin, every term at
-    kappa >= 1 (margins never exceed 1), and the rows in between one by one."""
+def test_bound_weights_without_correlator():
+    """Without a correlator: L > 0 and kappa below every margin give
+    expm1(2L) (S_n - |H_nn|); L = 0 and a kappa between margins give 2 x the
+    |term| mass of the rows whose margin, or whose sample's, is below kappa;
+    kappa >= 1 (margins never exceed 1) counts every term."""
     w = W.make_workload("c1")
     smp = w.samples[:16]
     terms = _terms(w, smp)
     mus = np.concatenate([t[2]["margin_phi"] for t in terms])
-    kaps = (0.5 * mus.min(), float(np.median(mus)), 1.0)
+    cols = ((1e-3, 0.5 * mus.min()), (0.0, float(np.median(mus))), (0.0, 1.0))
     ref = oracle.eloc(w.K, w.n_alpha, w.n_beta, w.h, w.eri, w.chi, w.parent_ptr, w.parent_idx, 0, w.params, smp,
-                      kappa=kaps)
+                      bounds=cols, u_f=0.0)
     for k, (hd, t, amp) in enumerate(terms):
+        S = ref["sabs"][k] - abs(hd)
+        assert abs(ref["ebound"][k, 0] - np.expm1(2e-3) * S) <= 1e-12 * S
         mrow, msmp = amp["margin_phi"][1:], amp["margin_phi"][0]
-        for q, kap in enumerate(kaps):
-            flip = (mrow < kap) | (msmp < kap)
-            want = 2.0 * np.abs(t[flip]).sum()
-            assert abs(ref["aflip"][k, q] - want) <= 1e-12 * max(want, 1.0), (k, kap)
-        assert ref["aflip"][k, 0] == 0.0
-        assert abs(ref["aflip"][k, 2] - 2 * (ref["sabs"][k] - abs(hd))) <= 1e-12 * ref["sabs"][k]
+        flip = (mrow < cols[1][1]) | (msmp < cols[1][1])
+        want = 2.0 * np.abs(t[flip]).sum()
+        assert abs(ref["ebound"][k, 1] - want) <= 1e-12 * max(want, 1.0), k
+        assert abs(ref["ebound"][k, 2] - 2 * S) <= 1e-12 * S
 
 
-def test_flip_allowance_bounds_an_actual_flip():
+def test_correlator_sensitivity_and_its_bound_weight():
+    """corr_sens = sum_k (1 + |theta_k|) / |cos theta_k| (closed form at W = 0);
+    with L = 0, kappa = 0 and u_f > 0 (no margin below 8 u_f here) each term
+    gets the weight expm1(u_f (corr_sens(m) + corr_sens(n)))."""
+    w = W.make_workload("c1")
+    nh = 6
+    pr = np.concatenate([w.params, np.zeros(nh + nh * 2 * w.K)])
+    b = np.array([0.3, -1.2, 1.5, 2.9, -0.7, 1.1])
+    pr[w.params.size:w.params.size + nh] = b
+    a = oracle.amplitudes(w.K, w.chi, w.n_alpha, w.n_beta, w.parent_ptr, w.parent_idx, nh, pr, w.samples[:4])
+    np.testing.assert_allclose(a["corr_sens"], np.sum((1 + np.abs(b)) / np.abs(np.cos(b))), rtol=1e-14)
+    prm = W.ansatz_params(w.K, w.chi, w.parent_ptr, w.parent_idx, nh, 23)
+    smp = w.samples[:10]
+    uf = 1e-4
+    ref = oracle.eloc(w.K, w.n_alpha, w.n_beta, w.h, w.eri, w.chi, w.parent_ptr, w.parent_idx, nh, prm, smp,
+                      bounds=((0.0, 0.0),), u_f=uf)
+    for k, s in enumerate(smp):
+        rm, rh = oracle.connected(w.K, w.n_alpha, w.n_beta, w.h, w.eri, s)
+        keep = rh != 0.0
+        rm, rh = rm[keep], rh[keep]
+        amp = oracle.amplitudes(w.K, w.chi, w.n_alpha, w.n_beta, w.parent_ptr, w.parent_idx, nh, prm,
+                                np.vstack([s[None], rm]))
+        assert np.all(amp["margin_f"] >= 8 * uf)
+        x = np.abs(rh) * np.exp(amp["logabs"][1:] - amp["logabs"][0])
+        want = (x * np.expm1(uf * (amp["corr_sens"][1:] + amp["corr_sens"][0]))).sum()
+        assert abs(ref["ebound"][k, 0] - want) <= 1e-12 * want
+
+
+def test_bound_covers_an_actual_flip():
     """Make the sign of Phi at site 0 (parentless, h = v^{s_0}) the sign of
     v^{s_0}[0] (w_0 = e_0, c_0 = 0) and set that component to +delta or
     -delta for the local state s = 1: rows whose site 0 is in state 1, of
     samples whose site 0 is not, change sign and nothing else changes beyond
-    O(delta).  Their row margin is delta / ||v^1||, so the allowance at a
-    kappa above it covers the change; at a kappa below every margin it is 0
+    O(delta).  Their row margin is delta / ||v^1||, so the bound at a kappa
+    above it covers the change; at a kappa below every margin it is 0
     although E_loc moved: the flip term of the bound is needed."""
     w = W.make_workload("c1")
     chi = w.chi
@@ -153,9 +182,9 @@ def test_flip_allowance_bounds_an_actual_flip():
     s0 = (allv[:, 0] & 1).astype(int) + 2 * ((allv[:, 0] >> 1) & 1).astype(int)
     smp = allv[s0 != 1][:40]
     a = oracle.eloc(w.K, w.n_alpha, w.n_beta, w.h, w.eri, chi, w.parent_ptr, w.parent_idx, 0, p, smp,
-                    kappa=(1e-3 * mu, 4 * mu))
+                    bounds=((0.0, 1e-3 * mu), (1e-7, 4 * mu)))
     b = oracle.eloc(w.K, w.n_alpha, w.n_beta, w.h, w.eri, chi, w.parent_ptr, w.parent_idx, 0, q, smp)
     dE = np.abs(a["eloc"] - b["eloc"])
     assert dE.max() > 1e-2
-    assert np.all(dE <= a["aflip"][:, 1] + 1e-6 * a["sabs"])
-    assert np.all(a["aflip"][:, 0] == 0.0)
+    assert np.all(dE <= a["ebound"][:, 1])
+    assert np.all(a["ebound"][:, 0] == 0.0)
