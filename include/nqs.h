@@ -36,9 +36,21 @@
  * failure of a call made by the calling thread.
  *
  * Streams: device work is ordered on the hipStream_t passed in (0 = the null
- * stream).  Calls that size data-dependent work (nqs_eloc, nqs_rows)
- * synchronise that stream once internally; all calls have completed their
- * device work when they return, unless stated otherwise.
+ * stream).  Every call has completed its device work when it returns, unless
+ * stated otherwise; the host waits on that stream (and only on it) at the
+ * points each call lists.  nqs_eloc / nqs_eloc_complex wait
+ *   1. after validating the samples (the result decides EINVAL),
+ *   2. after enumeration, screening and draws, to read the row count of
+ *      every sample (it sizes the row buffers and the passes),
+ *   3. once per amplitude pass in FP64 / FP32 with resumed rows, to read the
+ *      number of shared-prefix nodes of the pass (it sizes the node pass),
+ *   4. at the end;
+ * with a stats pointer also once per pass for the stage timers and the
+ * per-site row totals.  nqs_ansatz_bind_params waits to copy the parameters
+ * to the host, where they are laid out per precision.  Workspace blocks go
+ * back to the context's pool behind the work queued on the call's stream
+ * (an event recorded on it), on error paths too, so a block is never handed
+ * to another call while a queued kernel may still use it.
  */
 #ifndef NQS_H
 #define NQS_H
@@ -64,7 +76,9 @@ enum {
 typedef enum {
   NQS_F64 = 0,   /* bond contractions in FP64 (the paper's precision, Sec. 3) */
   NQS_F32 = 1,   /* FP32 operands on MFMA, FP32 accumulate */
-  NQS_BF16 = 2   /* BF16 operands on MFMA, FP32 accumulate, per-row scaled hidden states */
+  NQS_BF16 = 2,  /* BF16 operands on MFMA, FP32 accumulate, per-row scaled hidden states */
+  NQS_BF16X3 = 3 /* the same with every operand split into two BF16 parts (hi + lo) and three
+                    MFMAs per product (hi.hi + hi.lo + lo.hi): relative errors near 2^-15 */
 } nqs_precision;
 
 typedef struct nqs_ctx nqs_ctx;
@@ -208,7 +222,9 @@ int64_t nqs_ansatz_n_params(const nqs_ansatz* ans);
 /* Copy the packed FP64 parameters (device pointer, nqs_ansatz_n_params
  * doubles) into the library's kernel layouts for every precision.  The caller's
  * buffer may be freed or changed afterwards; call again after an update.
- * EINVAL if some eta < 0 (checked on the device copy). */
+ * EINVAL if some eta < 0 or NaN (nothing changes then).  A failure after the
+ * old layouts were released (device memory) leaves the ansatz unbound: every
+ * call refuses it with EINVAL until a bind succeeds. */
 nqs_status nqs_ansatz_bind_params(nqs_ansatz* ans, const double* params, hipStream_t stream);
 
 /* log|Psi(n)| (device double[N]) and sign Psi(n) (device int8[N]) of N samples.
@@ -283,8 +299,10 @@ nqs_status nqs_sample(nqs_ctx* ctx, const nqs_ansatz* ans, int64_t n_draws, uint
  * The proposal is P(m) = q_m / sum q with q_m = ceil(|H_nm| 2^(40-e)),
  * eps = f 2^e, f in [0.5,1); draw k of sample s uses Philox4x32-10 with key
  * (seed lo, seed hi) and counter (sample_base + s, k, stream_id lo, hi).
- * stats (host, nullable) receives the batch sums of Sec. 2.3.  Synchronises
- * `stream` once to size the amplitude rows. */
+ * stats (host, nullable) receives the batch sums of Sec. 2.3.  Host waits on
+ * `stream`: see "Streams" above.  Combinations the amplitude kernels do not
+ * run (BF16 with complex parameters or the tensor term) fail with
+ * NQS_EUNSUPPORTED before any work is queued. */
 nqs_status nqs_eloc(nqs_ctx* ctx, const nqs_instance* inst, const nqs_ansatz* ans,
                     const uint64_t* samples, const double* counts, int64_t N,
                     const nqs_eloc_opts* opts, double* eloc, double* etnum, double* logabs,
@@ -354,7 +372,9 @@ typedef struct {
  * (for f = 1 the plain VMC gradient of Eq. (7)), through nqs_logpsi_vjp, apply
  * one AdamW update to params (device double[n_params], in place) with the
  * moment estimates adam_m, adam_v (device, in place, zero before the first
- * step), and re-bind the ansatz to the new parameters.  grad (device
+ * step), project eta onto eta >= 0 (negative entries become 0: the
+ * constraint of Sec. 2.1, a projected gradient step), and re-bind the ansatz
+ * to the new parameters.  grad (device
  * double[n_params], nullable) receives g.  With complex parameters the
  * local energies come from nqs_eloc_complex and the gradient over the real
  * and imaginary parts is 2 Re <(E_loc - E)^* d ln Psi> reweighted as above:

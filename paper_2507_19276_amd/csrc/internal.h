@@ -154,6 +154,7 @@ struct B16Params {
   const int* pptr;               // [K+1] forward edges (never empty per site)
   const int* slot;               // [edges] ring slot read by each edge (W: zero slot)
   const uint16_t* A;             // BF16 A stream, per forward edge + one zero edge (runtime.cpp)
+  const uint16_t* Alo = nullptr; // the same stream's lo parts (split form)
   const float* v;                // [K][4][chip]
   const float* eta;              // [K][chip]
   const float* w;                // [K][chip]
@@ -165,6 +166,7 @@ struct B16Params {
 // states as BF16 with one power-of-two exponent per (site, row).
 struct B16States {
   uint16_t* hs = nullptr;        // [K][ns][chip] BF16 carried state / 2^he
+  uint16_t* hs_lo = nullptr;     // split form: the lo parts of hs
   int32_t* he = nullptr;         // [K][ns]
   float* pm = nullptr;           // [K+1][ns]
   int32_t* pe = nullptr;         // [K+1][ns]
@@ -358,6 +360,8 @@ hipError_t launch_vmc_cotangent_cx(int64_t N, const double* c, const double* etn
 hipError_t launch_adamw(int64_t n, double* p, const double* g, double* m, double* v, int64_t t, double lr, double b1,
                         double b2, double eps, double wd, hipStream_t st);
 hipError_t launch_sumsq(int64_t n, const double* g, double* out, hipStream_t st);
+// eta >= 0 (Sec. 2.1): p[off[i] + u] = 0 where it is negative, i < K, u < chi
+hipError_t launch_project_eta(int K, int chi, const int64_t* off, double* p, hipStream_t st);
 // ---- row order by first changed site (order.hip) ----------------------
 // chunk of rows per block of the counting sort
 constexpr int kOrderChunk = 16384;
@@ -368,7 +372,7 @@ inline int64_t order_blocks(int64_t R) { return (R + kOrderChunk - 1) / kOrderCh
 hipError_t launch_order_t0(const uint8_t* t0, int64_t R, int K, int32_t* cnt, int64_t* tot, int32_t* perm,
                            uint8_t* t0s, hipStream_t st);
 hipError_t launch_psi_bf16(const B16Params& P, const uint64_t* m, int64_t R, double* lphi, int8_t* sphi,
-                           hipStream_t st, const B16States& X = B16States(), int mode = PSI_PLAIN);
+                           hipStream_t st, const B16States& X, int mode, bool split);
 // theta[N][nh] of the samples; with the Ising-RBM also (when E is not null) the
 // per-sample row-update table E[N][2K][nh] (see energy.hip), FP64 for
 // precision NQS_F64, else FP32

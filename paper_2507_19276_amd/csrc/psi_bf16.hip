@@ -24,6 +24,14 @@
 // of the wavefront leaves [2^-40, 2^40]; then it is renormalised by 2^(e/2)
 // with e the exponent of that Z, which keeps every operand far from the ends
 // of the FP32/BF16 range whatever the magnitudes of v and M.
+//
+// Split form (SPLIT): every operand is carried as two BF16 parts, x = hi + lo
+// with hi = bf16(x) and lo = bf16(x - hi), the A stream as well (built on the
+// host) and the carried states (hi and lo quads in the ring); each k-step
+// runs three MFMAs, hi.hi + hi.lo + lo.hi, all on the BF16 matrix cores with
+// FP32 accumulation.  The dropped lo.lo product and the representation error
+// are below 2^-16 of each product, so the states carry relative errors near
+// 2^-15 instead of 2^-8.  Power-of-two scaling applies to both parts alike.
 #include "device.h"
 #include <type_traits>
 
@@ -94,7 +102,7 @@ __device__ inline int wave_max(int x) {
 
 template <int CH> constexpr int ntiles_b16() { return CH <= 16 ? 4 : (CH <= 32 ? 2 : 1); }
 
-template <int CH, int NTL, bool FOLD, bool STORE, bool SEED, bool D1>
+template <int CH, int NTL, bool FOLD, bool STORE, bool SEED, bool D1, bool SPLIT>
 __global__ __launch_bounds__(256) void k_psi_b16(B16Params P, const uint64_t* __restrict__ m, int64_t R,
                                                  double* __restrict__ lphi, int8_t* __restrict__ sphi, int wpb,
                                                  B16States X) {
@@ -103,22 +111,24 @@ __global__ __launch_bounds__(256) void k_psi_b16(B16Params P, const uint64_t* __
 #pragma clang fp contract(off)
   extern __shared__ __align__(16) unsigned char smem[];
   constexpr int TPC = CH / 16, NT = 4 * TPC, NP = TPC / 2, ODD = TPC & 1, RW = 16 * NTL;
-  constexpr int SLOT = NTL * TPC * 64;                          // quads per ring slot
+  constexpr int SLOT = NTL * TPC * 64;                          // quads per ring slot and part
+  constexpr int PARTS = SPLIT ? 2 : 1;                          // hi (and lo) quads per slot
   constexpr int64_t EQ = int64_t(NP) * NT * 64 * 2 + ODD * NT * 64;       // A stream: u2 units per edge
-  constexpr bool APF = NT * (NP ? 4 : 2) <= 32;                 // fetch the next edge's first k-step ahead
+  constexpr bool APF = NT * (NP ? 4 : 2) * PARTS <= 32;         // fetch the next edge's first k-step ahead
   constexpr bool BPF = NT * 4 <= 32;                            // fetch the next site's bias ahead
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   const int j = lane & 15, g = lane >> 4;
   const int own = NTL == 4 ? g : (NTL == 2 ? (g >> 1) : 0);
   const int64_t base = (int64_t(blockIdx.x) * wpb + wv) * RW;
   if (base >= R) return;   // surplus wavefront of the last block (no block barrier below)
-  // per wavefront: (W+1) slots of quads, then (W+1) exponents, all lane-private
-  // (every lane keeps its own copy of the wavefront-uniform exponents)
-  const size_t wbytes = size_t(P.W + 1) * (SLOT * 8 + 64 * 4);
+  // per wavefront: (W+1) slots of quads (each slot: the hi part, then with
+  // SPLIT the lo part), then (W+1) exponents, all lane-private (every lane
+  // keeps its own copy of the wavefront-uniform exponents)
+  const size_t wbytes = size_t(P.W + 1) * (SLOT * 8 * PARTS + 64 * 4);
   u2* ring = reinterpret_cast<u2*>(smem + size_t(wv) * wbytes) + lane;
-  int* Ering = reinterpret_cast<int*>(smem + size_t(wv) * wbytes + size_t(P.W + 1) * SLOT * 8) + lane;
+  int* Ering = reinterpret_cast<int*>(smem + size_t(wv) * wbytes + size_t(P.W + 1) * SLOT * 8 * PARTS) + lane;
 #pragma unroll
-  for (int k = 0; k < NTL * TPC; ++k) ring[(P.W * NTL * TPC + k) * 64] = u2{0u, 0u};
+  for (int k = 0; k < NTL * TPC * PARTS; ++k) ring[size_t(P.W) * SLOT * PARTS + k * 64] = u2{0u, 0u};
   Ering[P.W * 64] = 0;
   const CInt* fptr = (const CInt*)(P.pptr);
   const CInt* slots = (const CInt*)(P.slot);
@@ -156,15 +166,21 @@ __global__ __launch_bounds__(256) void k_psi_b16(B16Params P, const uint64_t* __
         emax = max(emax, es[t]);
       }
       const int ew = __builtin_amdgcn_readfirstlane(wave_max(emax));
-      u2* wr = ring + size_t(s % P.W) * SLOT;
+      u2* wr = ring + size_t(s % P.W) * SLOT * PARTS;
 #pragma unroll
       for (int t = 0; t < NTL; ++t) {
-        const u2* src = reinterpret_cast<const u2*>(X.hs + (size_t(s) * X.ns + X.owner[rowt[t]]) * CH + 4 * g);
+        const size_t so = (size_t(s) * X.ns + X.owner[rowt[t]]) * CH + 4 * g;
+        const u2* src = reinterpret_cast<const u2*>(X.hs + so);
 #pragma unroll
         for (int tt = 0; tt < TPC; ++tt) {
           u2 q = src[4 * tt];
           if (es[t] != ew) q = scale_bf16(q, es[t] - ew);
           wr[(t * TPC + tt) * 64] = q;
+          if constexpr (SPLIT) {
+            u2 ql = reinterpret_cast<const u2*>(X.hs_lo + so)[4 * tt];
+            if (es[t] != ew) ql = scale_bf16(ql, es[t] - ew);
+            wr[SLOT + (t * TPC + tt) * 64] = ql;
+          }
         }
       }
       Ering[(s % P.W) * 64] = ew;
@@ -182,18 +198,20 @@ __global__ __launch_bounds__(256) void k_psi_b16(B16Params P, const uint64_t* __
   // A stream in u2 units: per edge NP pair steps of [ot][lane] u4, then (ODD)
   // one step of [ot][lane] u2
   const u2* __restrict__ Ab = reinterpret_cast<const u2*>(P.A);
+  const u2* __restrict__ Abl = reinterpret_cast<const u2*>(P.Alo);   // SPLIT: lo parts, same layout
   typedef typename std::conditional<(NP > 0), u4, u2>::type FA;   // first k-step operand type
-  FA an[APF ? NT : 1];
-  auto first_step = [&](int64_t edge, FA (&dst)[APF ? NT : 1]) {
+  FA an[APF ? NT : 1], anl[APF ? NT : 1];   // anl: lo parts (SPLIT only)
+  auto first_step = [&](const u2* base, int64_t edge, FA (&dst)[APF ? NT : 1]) {
 #pragma unroll
     for (int ot = 0; ot < (APF ? NT : 1); ++ot) {
       if constexpr (NP > 0)
-        dst[ot] = reinterpret_cast<const u4*>(Ab + edge * EQ)[ot * 64 + lane];
+        dst[ot] = reinterpret_cast<const u4*>(base + edge * EQ)[ot * 64 + lane];
       else
-        dst[ot] = (Ab + edge * EQ)[ot * 64 + lane];
+        dst[ot] = (base + edge * EQ)[ot * 64 + lane];
     }
   };
-  if (APF) first_step(e, an);
+  if (APF) first_step(Ab, e, an);
+  if (APF && SPLIT) first_step(Abl, e, anl);
   f4 vn[NT];
   auto fetch_bias = [&](int i) {
 #pragma unroll
@@ -226,52 +244,85 @@ __global__ __launch_bounds__(256) void k_psi_b16(B16Params P, const uint64_t* __
     // scaled bias registers instead of copies of them in the accumulators)
     auto edge = [&](auto first) {
       const u2* Ae = Ab + int64_t(e) * EQ;
+      const u2* Ael = Abl + int64_t(e) * EQ;
       const int ep = __builtin_amdgcn_readfirstlane(Ering[slots[e] * 64]);
-      u2 b[NTL][TPC];
-      const u2* rp = ring + size_t(slots[e]) * SLOT;
+      u2 b[NTL][TPC], bl[NTL][SPLIT ? TPC : 1];
+      const u2* rp = ring + size_t(slots[e]) * SLOT * PARTS;
 #pragma unroll
       for (int t = 0; t < NTL; ++t)
 #pragma unroll
-        for (int tt = 0; tt < TPC; ++tt) b[t][tt] = rp[(t * TPC + tt) * 64];
+        for (int tt = 0; tt < TPC; ++tt) {
+          b[t][tt] = rp[(t * TPC + tt) * 64];
+          if constexpr (SPLIT) bl[t][tt] = rp[SLOT + (t * TPC + tt) * 64];
+        }
       if (ep != eref) {
 #pragma unroll
         for (int t = 0; t < NTL; ++t)
 #pragma unroll
-          for (int tt = 0; tt < TPC; ++tt) b[t][tt] = scale_bf16(b[t][tt], ep - eref);
+          for (int tt = 0; tt < TPC; ++tt) {
+            b[t][tt] = scale_bf16(b[t][tt], ep - eref);
+            if constexpr (SPLIT) bl[t][tt] = scale_bf16(bl[t][tt], ep - eref);
+          }
       }
-      FA nx[APF ? NT : 1];
-      if (APF) first_step(int64_t(e) + 1, nx);   // the stream carries one zero edge past the last
+      FA nx[APF ? NT : 1], nxl[APF ? NT : 1];
+      if (APF) first_step(Ab, int64_t(e) + 1, nx);   // the stream carries one zero edge past the last
+      if (APF && SPLIT) first_step(Abl, int64_t(e) + 1, nxl);
 #pragma unroll
       for (int q = 0; q < NP; ++q)
 #pragma unroll
         for (int ot = 0; ot < NT; ++ot) {
-          u4 a;
+          u4 a, al;
           if constexpr (NP > 0 && APF)
             a = q == 0 ? an[ot] : reinterpret_cast<const u4*>(Ae)[(q * NT + ot) * 64 + lane];
           else
             a = reinterpret_cast<const u4*>(Ae)[(q * NT + ot) * 64 + lane];
+          if constexpr (SPLIT) {
+            if constexpr (NP > 0 && APF)
+              al = q == 0 ? anl[ot] : reinterpret_cast<const u4*>(Ael)[(q * NT + ot) * 64 + lane];
+            else
+              al = reinterpret_cast<const u4*>(Ael)[(q * NT + ot) * 64 + lane];
+          }
 #pragma unroll
           for (int t = 0; t < NTL; ++t) {
             const u4 bq = {b[t][2 * q].x, b[t][2 * q].y, b[t][2 * q + 1].x, b[t][2 * q + 1].y};
             acc[t][ot] = mfma_k32(a, bq, decltype(first)::value && q == 0 ? vs[ot] : acc[t][ot]);
+            if constexpr (SPLIT) {
+              const u4 bql = {bl[t][2 * q].x, bl[t][2 * q].y, bl[t][2 * q + 1].x, bl[t][2 * q + 1].y};
+              acc[t][ot] = mfma_k32(a, bql, acc[t][ot]);
+              acc[t][ot] = mfma_k32(al, bq, acc[t][ot]);
+            }
           }
         }
       if constexpr (ODD) {
 #pragma unroll
         for (int ot = 0; ot < NT; ++ot) {
-          u2 a;
+          u2 a, al;
           if constexpr (NP == 0 && APF)
             a = an[ot];
           else
             a = (Ae + int64_t(NP) * NT * 64 * 2)[ot * 64 + lane];
+          if constexpr (SPLIT) {
+            if constexpr (NP == 0 && APF)
+              al = anl[ot];
+            else
+              al = (Ael + int64_t(NP) * NT * 64 * 2)[ot * 64 + lane];
+          }
 #pragma unroll
-          for (int t = 0; t < NTL; ++t)
+          for (int t = 0; t < NTL; ++t) {
             acc[t][ot] = mfma_k16(a, b[t][TPC - 1], decltype(first)::value && NP == 0 ? vs[ot] : acc[t][ot]);
+            if constexpr (SPLIT) {
+              acc[t][ot] = mfma_k16(a, bl[t][TPC - 1], acc[t][ot]);
+              acc[t][ot] = mfma_k16(al, b[t][TPC - 1], acc[t][ot]);
+            }
+          }
         }
       }
       if (APF) {
 #pragma unroll
-        for (int ot = 0; ot < NT; ++ot) an[ot] = nx[ot];
+        for (int ot = 0; ot < NT; ++ot) {
+          an[ot] = nx[ot];
+          if constexpr (SPLIT) anl[ot] = nxl[ot];
+        }
       }
     };
     if (!BPF) fetch_bias(i);
@@ -370,7 +421,7 @@ __global__ __launch_bounds__(256) void k_psi_b16(B16Params P, const uint64_t* __
     if (zmax > 0.0f && zmax < INFINITY) (void)frexpf(zmax, &ez);
     const int kz = (ez > 40 || ez < -40) ? (ez >> 1) : 0;
     const int enew = eref + kz;
-    u2* wr = ring + size_t(wslot) * SLOT;
+    u2* wr = ring + size_t(wslot) * SLOT * PARTS;
 #pragma unroll
     for (int t = 0; t < NTL; ++t)
 #pragma unroll
@@ -379,9 +430,18 @@ __global__ __launch_bounds__(256) void k_psi_b16(B16Params P, const uint64_t* __
         if (kz != 0) v = v * ldexpf(1.0f, -kz);
         const u2 q = pack_bf16(v);
         wr[(t * TPC + tt) * 64] = q;
+        u2 ql = u2{0u, 0u};
+        if constexpr (SPLIT) {
+          ql = pack_bf16(v - unpack_bf16(q));   // v - hi is exact in FP32
+          wr[SLOT + (t * TPC + tt) * 64] = ql;
+        }
         if (STORE) {
           const int64_t r = base + 16 * t + j;
-          if (r < X.ns) *reinterpret_cast<u2*>(X.hs + (size_t(i) * X.ns + r) * CH + 16 * tt + 4 * g) = q;
+          const size_t so = (size_t(i) * X.ns + r) * CH + 16 * tt + 4 * g;
+          if (r < X.ns) {
+            *reinterpret_cast<u2*>(X.hs + so) = q;
+            if constexpr (SPLIT) *reinterpret_cast<u2*>(X.hs_lo + so) = ql;
+          }
         }
       }
     Ering[wslot * 64] = enew;
@@ -402,60 +462,70 @@ __global__ __launch_bounds__(256) void k_psi_b16(B16Params P, const uint64_t* __
   }
 }
 
-template <int CH, bool FOLD, bool STORE, bool SEED, bool D1>
+template <int CH, bool FOLD, bool STORE, bool SEED, bool D1, bool SPLIT>
 hipError_t run_b16(const B16Params& P, const uint64_t* m, int64_t R, double* lphi, int8_t* sphi, hipStream_t st,
                    const B16States& X) {
   if (R <= 0) return hipSuccess;
+  if (SPLIT && (!P.Alo || (STORE && !X.hs_lo) || (SEED && !X.hs_lo))) return hipErrorInvalidValue;
   constexpr int NTL = ntiles_b16<CH>();
   constexpr int TPC = CH / 16;
-  const size_t per_wave = size_t(P.W + 1) * (NTL * TPC * 64 * 8 + 64 * 4);
+  const size_t per_wave = size_t(P.W + 1) * (NTL * TPC * 64 * 8 * (SPLIT ? 2 : 1) + 64 * 4);
   int wpb = 4;
   while (wpb > 1 && per_wave * wpb > 64 * 1024) wpb >>= 1;
   if (per_wave * wpb > 160 * 1024) return hipErrorInvalidValue;
   const int64_t tiles = (R + 16 * NTL - 1) / (16 * NTL);
   const int64_t blocks = (tiles + wpb - 1) / wpb;
-  hipLaunchKernelGGL((k_psi_b16<CH, NTL, FOLD, STORE, SEED, D1>), dim3(unsigned(blocks)), dim3(64 * wpb),
+  hipLaunchKernelGGL((k_psi_b16<CH, NTL, FOLD, STORE, SEED, D1, SPLIT>), dim3(unsigned(blocks)), dim3(64 * wpb),
                      per_wave * wpb, st, P, m, R, lphi, sphi, wpb, X);
   return hipGetLastError();
 }
 
 // D1: every site has one edge
-template <int CH, bool D1>
+template <int CH, bool D1, bool SPLIT>
 hipError_t run_b16_modes(const B16Params& P, const uint64_t* m, int64_t R, double* lphi, int8_t* sphi,
                          hipStream_t st, const B16States& X, int mode) {
   switch (mode) {
     case PSI_PLAIN:
-      if (P.folded) return run_b16<CH, true, false, false, D1>(P, m, R, lphi, sphi, st, X);
-      return run_b16<CH, false, false, false, D1>(P, m, R, lphi, sphi, st, X);
+      if (P.folded) return run_b16<CH, true, false, false, D1, SPLIT>(P, m, R, lphi, sphi, st, X);
+      return run_b16<CH, false, false, false, D1, SPLIT>(P, m, R, lphi, sphi, st, X);
     case PSI_STORE:
-      if (P.folded) return run_b16<CH, true, true, false, D1>(P, m, R, lphi, sphi, st, X);
-      return run_b16<CH, false, true, false, D1>(P, m, R, lphi, sphi, st, X);
+      if (P.folded) return run_b16<CH, true, true, false, D1, SPLIT>(P, m, R, lphi, sphi, st, X);
+      return run_b16<CH, false, true, false, D1, SPLIT>(P, m, R, lphi, sphi, st, X);
     case PSI_SEED:
-      if (P.folded) return run_b16<CH, true, false, true, D1>(P, m, R, lphi, sphi, st, X);
-      return run_b16<CH, false, false, true, D1>(P, m, R, lphi, sphi, st, X);
+      if (P.folded) return run_b16<CH, true, false, true, D1, SPLIT>(P, m, R, lphi, sphi, st, X);
+      return run_b16<CH, false, false, true, D1, SPLIT>(P, m, R, lphi, sphi, st, X);
     default:
       return hipErrorInvalidValue;
   }
 }
 
-template <int CH>
+template <int CH, bool SPLIT>
 hipError_t run_b16_ch(const B16Params& P, const uint64_t* m, int64_t R, double* lphi, int8_t* sphi,
                       hipStream_t st, const B16States& X, int mode) {
   if constexpr (CH <= 32) {
-    if (P.d1) return run_b16_modes<CH, true>(P, m, R, lphi, sphi, st, X, mode);
+    if (P.d1) return run_b16_modes<CH, true, SPLIT>(P, m, R, lphi, sphi, st, X, mode);
   }
-  return run_b16_modes<CH, false>(P, m, R, lphi, sphi, st, X, mode);
+  return run_b16_modes<CH, false, SPLIT>(P, m, R, lphi, sphi, st, X, mode);
 }
 
 }  // namespace
 
 hipError_t launch_psi_bf16(const B16Params& P, const uint64_t* m, int64_t R, double* lphi, int8_t* sphi,
-                           hipStream_t st, const B16States& X, int mode) {
+                           hipStream_t st, const B16States& X, int mode, bool split) {
+  if (split) {
+    switch (P.chip) {
+      case 16: return run_b16_ch<16, true>(P, m, R, lphi, sphi, st, X, mode);
+      case 32: return run_b16_ch<32, true>(P, m, R, lphi, sphi, st, X, mode);
+      case 48: return run_b16_ch<48, true>(P, m, R, lphi, sphi, st, X, mode);
+      case 64: return run_b16_ch<64, true>(P, m, R, lphi, sphi, st, X, mode);
+      default: return hipErrorInvalidValue;
+    }
+  }
   switch (P.chip) {
-    case 16: return run_b16_ch<16>(P, m, R, lphi, sphi, st, X, mode);
-    case 32: return run_b16_ch<32>(P, m, R, lphi, sphi, st, X, mode);
-    case 48: return run_b16_ch<48>(P, m, R, lphi, sphi, st, X, mode);
-    case 64: return run_b16_ch<64>(P, m, R, lphi, sphi, st, X, mode);
+    case 16: return run_b16_ch<16, false>(P, m, R, lphi, sphi, st, X, mode);
+    case 32: return run_b16_ch<32, false>(P, m, R, lphi, sphi, st, X, mode);
+    case 48: return run_b16_ch<48, false>(P, m, R, lphi, sphi, st, X, mode);
+    case 64: return run_b16_ch<64, false>(P, m, R, lphi, sphi, st, X, mode);
     default: return hipErrorInvalidValue;
   }
 }

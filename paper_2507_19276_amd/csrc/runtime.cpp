@@ -80,7 +80,38 @@ struct nqs_ctx {
   size_t in_use = 0, cached = 0, peak = 0;
   size_t cap = 0;                             // 0 = no limit on in_use + cached
   int64_t fail_at = 0;                        // test hook: k-th acquire fails
+  // blocks handed back with work still queued on their stream: they count as
+  // in use until the event recorded after that work has completed
+  std::vector<std::pair<hipEvent_t, std::vector<void*>>> pending;
 
+  void free_block_locked(void* p) {
+    auto it = sizes.find(p);
+    if (it == sizes.end()) return;
+    in_use -= it->second;
+    cached += it->second;
+    free_blocks.emplace(it->second, p);
+  }
+  // move the pending blocks whose work has completed to the free list
+  // (wait: block until all of them have)
+  void reclaim_locked(bool wait) {
+    for (size_t k = 0; k < pending.size();) {
+      const hipError_t e = wait ? hipEventSynchronize(pending[k].first) : hipEventQuery(pending[k].first);
+      if (e == hipErrorNotReady) {
+        (void)hipGetLastError();   // not an error: keep it out of the next launch check
+        ++k;
+        continue;
+      }
+      if (e != hipSuccess) (void)hipGetLastError();
+      (void)hipEventDestroy(pending[k].first);
+      for (void* p : pending[k].second) free_block_locked(p);
+      pending[k] = std::move(pending.back());
+      pending.pop_back();
+    }
+  }
+  void reclaim(bool wait) {
+    std::lock_guard<std::mutex> lk(mu);
+    reclaim_locked(wait);
+  }
   void drop_cache() {
     for (auto& kv : free_blocks) { (void)hipFree(kv.second); sizes.erase(kv.second); }
     free_blocks.clear();
@@ -90,6 +121,7 @@ struct nqs_ctx {
     bytes = size_class(bytes);
     std::lock_guard<std::mutex> lk(mu);
     if (fail_at > 0 && --fail_at == 0) return nullptr;
+    if (!pending.empty()) reclaim_locked(false);
     auto it = free_blocks.find(bytes);
     if (it != free_blocks.end()) {
       void* p = it->second;
@@ -107,10 +139,31 @@ struct nqs_ctx {
       cached -= big->first;
       free_blocks.erase(big);
     }
+    if (cap && in_use + bytes > cap && !pending.empty()) {
+      reclaim_locked(true);   // wait for the pending blocks, then try the cache again
+      it = free_blocks.find(bytes);
+      if (it != free_blocks.end()) {
+        void* p = it->second;
+        const size_t sz = it->first;
+        free_blocks.erase(it);
+        cached -= sz;
+        in_use += sz;
+        peak = std::max(peak, in_use);
+        return p;
+      }
+      while (in_use + cached + bytes > cap && !free_blocks.empty()) {
+        auto big = std::prev(free_blocks.end());
+        (void)hipFree(big->second);
+        sizes.erase(big->second);
+        cached -= big->first;
+        free_blocks.erase(big);
+      }
+    }
     if (cap && in_use + bytes > cap) return nullptr;
     void* p = nullptr;
     if (hipMalloc(&p, bytes) != hipSuccess) {
       (void)hipGetLastError();
+      reclaim_locked(true);
       drop_cache();   // release the cache and retry once
       if (hipMalloc(&p, bytes) != hipSuccess) { (void)hipGetLastError(); return nullptr; }
     }
@@ -122,26 +175,50 @@ struct nqs_ctx {
   void release(void* p) {
     if (!p) return;
     std::lock_guard<std::mutex> lk(mu);
-    auto it = sizes.find(p);
-    if (it == sizes.end()) return;
-    in_use -= it->second;
-    cached += it->second;
-    free_blocks.emplace(it->second, p);
+    free_block_locked(p);
+  }
+  // hand back blocks that work queued on `st` may still use: they return to
+  // the free list once everything queued on `st` so far has completed
+  void release_after(std::vector<void*>& ps, hipStream_t st) {
+    if (ps.empty()) return;
+    hipEvent_t ev = nullptr;
+    if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess || hipEventRecord(ev, st) != hipSuccess) {
+      (void)hipGetLastError();
+      if (ev) (void)hipEventDestroy(ev);
+      (void)hipStreamSynchronize(st);   // no event: wait for the stream instead
+      (void)hipGetLastError();
+      std::lock_guard<std::mutex> lk(mu);
+      for (void* p : ps) free_block_locked(p);
+      ps.clear();
+      return;
+    }
+    std::lock_guard<std::mutex> lk(mu);
+    pending.emplace_back(ev, std::move(ps));
+    ps.clear();
   }
   ~nqs_ctx() {
+    for (auto& pe : pending) {
+      (void)hipEventSynchronize(pe.first);
+      (void)hipEventDestroy(pe.first);
+    }
     for (auto& kv : sizes) (void)hipFree(kv.first);
   }
 };
 
 namespace {
 
-// Workspace of one call: blocks return to the pool when the call ends (after
-// the call has synchronised its stream).
+// Workspace of one call on one stream: when the call returns (on any path,
+// errors included) its blocks go back to the pool behind the work the call
+// queued on that stream, so no other call is handed a block a queued kernel
+// may still write.
 struct Scratch {
   nqs_ctx* ctx;
+  hipStream_t st;
   std::vector<void*> blocks;
   bool oom = false;
-  explicit Scratch(nqs_ctx* c) : ctx(c) {}
+  Scratch(nqs_ctx* c, hipStream_t s) : ctx(c), st(s) {}
+  Scratch(const Scratch&) = delete;
+  Scratch& operator=(const Scratch&) = delete;
   template <typename T>
   T* get(size_t count) {
     void* p = ctx->acquire(std::max<size_t>(count, 1) * sizeof(T));
@@ -149,7 +226,7 @@ struct Scratch {
     blocks.push_back(p);
     return static_cast<T*>(p);
   }
-  ~Scratch() { for (void* p : blocks) ctx->release(p); }
+  ~Scratch() { ctx->release_after(blocks, st); }
 };
 
 uint64_t magic(uint64_t d) { return d == 0 ? 0 : ((uint64_t(1) << 32) + d - 1) / d; }
@@ -222,6 +299,7 @@ struct nqs_ansatz {
   PsiLayout<float> L32, F32;
   bool has_fold = false;
   uint16_t* bfA = nullptr;  // BF16 forward A stream (folded when has_fold)
+  uint16_t* bfAlo = nullptr;  // its lo parts: bf16(x - bf16(x)), for the split BF16 form
   double* d_cb = nullptr;   // correlator b
   double* d_cW = nullptr;   // correlator W
   bool ising = false;       // Ising-RBM correlator (quadratic couplings W2)
@@ -267,6 +345,7 @@ struct nqs_ansatz {
     F64.free_all();
     F32.free_all();
     for (void* p : {(void*)d_pptr, (void*)d_pidx, (void*)d_slot, (void*)d_fptr, (void*)d_fslot, (void*)bfA,
+                    (void*)bfAlo,
                     (void*)d_cb, (void*)d_cW, (void*)d_cW1t, (void*)d_cS, (void*)d_cS32, (void*)d_tn_edge,
                     (void*)d_tn_site, (void*)tn64, (void*)tn32, (void*)d_offM, (void*)d_offV,
                     (void*)d_offEta, (void*)d_cx, (void*)d_tsite})
@@ -544,6 +623,8 @@ uint16_t to_bf16(float f) {
 // k = 16 (2q + e/4) + 4 g + e%4 (pair step q, element e) or 16 (TPC-1) + 4 g + e
 // (odd step): each lane's own quads of the parent state.  With fold the
 // operands carry sigma = sqrt(eta) as in build_layout.  Round to nearest even.
+// A second stream of the same layout holds the lo parts of the split form:
+// bf16(x - bf16(x)) with the difference taken in FP64.
 nqs_status build_bf16(nqs_ansatz* a, const std::vector<double>& prm, bool fold) {
   const int K = a->K, chi = a->chi, CH = a->chip, NT = CH / 4, TPC = CH / 16, NP = TPC / 2;
   const size_t EQ = size_t(NP) * NT * 64 * 8 + size_t(TPC & 1) * NT * 64 * 4;   // bf16 values per edge
@@ -551,17 +632,28 @@ nqs_status build_bf16(nqs_ansatz* a, const std::vector<double>& prm, bool fold) 
   if (fold)
     for (int i = 0; i < K; ++i)
       for (int u = 0; u < chi; ++u) sig[size_t(i) * chi + u] = std::sqrt(prm[a->offEta[i] + u]);
-  std::vector<uint16_t> A;
-  auto value = [&](int e, int i, int o, int k) -> uint16_t {
+  std::vector<uint16_t> A, Alo;
+  auto value = [&](int e, int i, int o, int k) {
     const int s = o / CH, u = o % CH;
-    if (u >= chi || k >= chi) return 0;
+    if (u >= chi || k >= chi) {
+      Alo.push_back(0);
+      return uint16_t(0);
+    }
     const double* M = prm.data() + a->offM[e];
     const double v = sig[size_t(i) * chi + u] * M[(size_t(s) * chi + u) * chi + k] /
                      sig[size_t(a->pidx[e]) * chi + k];
-    return to_bf16(float(v));
+    const uint16_t hi = to_bf16(float(v));
+    uint32_t bits = uint32_t(hi) << 16;
+    float fhi;
+    std::memcpy(&fhi, &bits, 4);
+    Alo.push_back(to_bf16(float(v - double(fhi))));
+    return hi;
   };
   for (int i = 0; i < K; ++i) {
-    if (a->pptr[i + 1] == a->pptr[i]) A.resize(A.size() + EQ, 0);   // zero edge
+    if (a->pptr[i + 1] == a->pptr[i]) {   // zero edge
+      A.resize(A.size() + EQ, 0);
+      Alo.resize(Alo.size() + EQ, 0);
+    }
     for (int e = a->pptr[i]; e < a->pptr[i + 1]; ++e) {
       for (int q = 0; q < NP; ++q)
         for (int ot = 0; ot < NT; ++ot)
@@ -576,8 +668,11 @@ nqs_status build_bf16(nqs_ansatz* a, const std::vector<double>& prm, bool fold) 
     }
   }
   A.resize(A.size() + EQ, 0);   // fetch-ahead edge
+  Alo.resize(Alo.size() + EQ, 0);
   if (a->bfA) { (void)hipFree(a->bfA); a->bfA = nullptr; }
-  return upload(&a->bfA, A);
+  if (a->bfAlo) { (void)hipFree(a->bfAlo); a->bfAlo = nullptr; }
+  nqs_status st = upload(&a->bfA, A);
+  return st != NQS_OK ? st : upload(&a->bfAlo, Alo);
 }
 
 // algorithmic flops of one site of one row: 8 chi^2 d (four candidates, d
@@ -682,6 +777,7 @@ nqs_status nqs_ctx_pool_bytes(const nqs_ctx* ctx, size_t* in_use, size_t* cached
   if (!ctx) return fail(NQS_EINVAL, "ctx is NULL");
   auto* c = const_cast<nqs_ctx*>(ctx);
   std::lock_guard<std::mutex> lk(c->mu);
+  c->reclaim_locked(true);   // blocks still behind queued work count once that work is done
   if (in_use) *in_use = c->in_use;
   if (cached) *cached = c->cached;
   return NQS_OK;
@@ -690,6 +786,7 @@ nqs_status nqs_ctx_pool_bytes(const nqs_ctx* ctx, size_t* in_use, size_t* cached
 nqs_status nqs_ctx_pool_peak(nqs_ctx* ctx, size_t* peak, int reset) {
   if (!ctx) return fail(NQS_EINVAL, "ctx is NULL");
   std::lock_guard<std::mutex> lk(ctx->mu);
+  ctx->reclaim_locked(true);   // a reset starts from the blocks still in use, not those behind finished work
   if (peak) *peak = ctx->peak;
   if (reset) ctx->peak = ctx->in_use;
   return NQS_OK;
@@ -1051,6 +1148,10 @@ nqs_status nqs_ansatz_bind_params(nqs_ansatz* ans, const double* params, hipStre
     for (int u = 0; u < ans->chi; ++u)
       if (!(prm[ans->offEta[i] + u] >= 0.0))
         return fail(NQS_EINVAL, "eta[%d][%d] = %g is negative or NaN", i, u, prm[ans->offEta[i] + u]);
+  // the old layouts are replaced from here on: until every one is rebuilt the
+  // ansatz counts as unbound, so a failure below leaves calls refusing it
+  // instead of launching on half-built layouts
+  ans->bound = false;
   nqs_status st;
   if ((st = build_layout<double>(ans, prm, ans->L64, false)) != NQS_OK) return st;
   if ((st = build_layout<float>(ans, prm, ans->L32, false)) != NQS_OK) return st;
@@ -1106,7 +1207,7 @@ namespace {
 nqs_status check_samples(nqs_ctx* ctx, const uint64_t* samples, int64_t N, int K, int na, int nb,
                          hipStream_t st) {
   if (N == 0) return NQS_OK;
-  Scratch S(ctx);
+  Scratch S(ctx, st);
   int* bad = S.get<int>(1);
   if (!bad) return fail(NQS_ENOMEM, "workspace allocation failed");
   HIPCHK(hipMemsetAsync(bad, 0, sizeof(int), st));
@@ -1122,6 +1223,7 @@ nqs_status check_samples(nqs_ctx* ctx, const uint64_t* samples, int64_t N, int K
 // states and log-product states, and the order of the current pass's rows.
 struct Resume {
   void* hs = nullptr;       // [K][N][chip] T (BF16: uint16)
+  uint16_t* hs_lo = nullptr;  // split BF16: the lo parts of hs
   int32_t* he = nullptr;    // BF16: [K][N] state exponents
   void* pm = nullptr;       // [K+1][N] T (BF16: float)
   int32_t* pe = nullptr;    // [K+1][N]
@@ -1174,6 +1276,7 @@ PsiStates<T> states(const Resume& r) {
 B16States states_b16(const Resume& r) {
   B16States X;
   X.hs = static_cast<uint16_t*>(r.hs);
+  X.hs_lo = r.hs_lo;
   X.he = r.he;
   X.pm = static_cast<float*>(r.pm);
   X.pe = r.pe;
@@ -1185,7 +1288,11 @@ B16States states_b16(const Resume& r) {
   return X;
 }
 
-// bytes per element of the resume state arrays: carried state, log-product mantissa
+// BF16 operands on MFMA, plain or split (hi + lo parts)
+bool is_bf16(int precision) { return precision == NQS_BF16 || precision == NQS_BF16X3; }
+
+// bytes per element of the resume state arrays: carried state (BF16 forms: the
+// hi part), log-product mantissa
 size_t state_bytes(int precision) { return precision == NQS_F64 ? 8 : (precision == NQS_F32 ? 4 : 2); }
 size_t mantissa_bytes(int precision) { return precision == NQS_F64 ? 8 : 4; }
 
@@ -1209,7 +1316,7 @@ nqs_status run_amplitudes(const nqs_ansatz* a, int precision, const uint64_t* m,
     }
     return NQS_OK;
   }
-  if (a->tensor && precision == NQS_BF16) return fail(NQS_EUNSUPPORTED, "the tensor-RNN runs in FP64 or FP32");
+  if (a->tensor && is_bf16(precision)) return fail(NQS_EUNSUPPORTED, "the tensor-RNN runs in FP64 or FP32");
   if (a->tensor && !a->tn_mfma) {
     // the thread-per-row kernel (chi' > 8 or chi > 32)
     if (mode != PSI_PLAIN) return fail(NQS_EINVAL, "tensor-RNN rows are evaluated from site 0");
@@ -1229,13 +1336,14 @@ nqs_status run_amplitudes(const nqs_ansatz* a, int precision, const uint64_t* m,
   } else if (precision == NQS_F32) {
     HIPCHK(launch_psi_f32(a->params(a->fwd32()), m, R, lphi, sphi, st,
                           rs ? states<float>(*rs) : PsiStates<float>(), mode));
-  } else if (precision == NQS_BF16) {
+  } else if (is_bf16(precision)) {
     const PsiLayout<float>& L = a->fwd32();
     B16Params P{};
     P.K = a->K; P.chi = a->chi; P.chip = a->chip; P.na = a->na; P.nb = a->nb; P.W = a->W;
-    P.pptr = a->d_fptr; P.slot = a->d_fslot; P.A = a->bfA;
+    P.pptr = a->d_fptr; P.slot = a->d_fslot; P.A = a->bfA; P.Alo = a->bfAlo;
     P.v = L.v; P.eta = L.eta; P.w = L.w; P.c = L.c; P.folded = L.folded; P.d1 = a->d1;
-    hipError_t e = launch_psi_bf16(P, m, R, lphi, sphi, st, rs ? states_b16(*rs) : B16States(), mode);
+    hipError_t e = launch_psi_bf16(P, m, R, lphi, sphi, st, rs ? states_b16(*rs) : B16States(), mode,
+                                   precision == NQS_BF16X3);
     if (e == hipErrorNotSupported) return fail(NQS_EUNSUPPORTED, "BF16 amplitude path not available");
     HIPCHK(e);
   } else {
@@ -1383,7 +1491,7 @@ nqs_status check_opts(const nqs_eloc_opts* o) {
   if (!(o->eps >= 0.0) || std::isinf(o->eps)) return fail(NQS_EINVAL, "eps must be finite and >= 0");
   if (o->n_eps < 0) return fail(NQS_EINVAL, "n_eps < 0");
   if (o->n_eps > 1024) return fail(NQS_EUNSUPPORTED, "n_eps > 1024 per sample");
-  if (o->precision < 0 || o->precision > 2) return fail(NQS_EINVAL, "unknown precision");
+  if (o->precision < 0 || o->precision > 3) return fail(NQS_EINVAL, "unknown precision");
   if (o->max_rows_per_pass < 0) return fail(NQS_EINVAL, "max_rows_per_pass < 0");
   if (o->flags & ~NQS_ELOC_FULL_RECOMPUTE) return fail(NQS_EINVAL, "unknown flags 0x%x", unsigned(o->flags));
   return NQS_OK;
@@ -1391,6 +1499,16 @@ nqs_status check_opts(const nqs_eloc_opts* o) {
 
 // rows resume from their samples' states
 bool resumes(const nqs_eloc_opts& o) { return !(o.flags & NQS_ELOC_FULL_RECOMPUTE); }
+
+// precision / ansatz combinations the amplitude kernels do not run: refused
+// before a call queues any work
+nqs_status check_supported(const nqs_ansatz* a, int precision) {
+  if (is_bf16(precision) && a->cplx) return fail(NQS_EUNSUPPORTED, "complex amplitudes run in FP64 or FP32");
+  if (is_bf16(precision) && a->tensor) return fail(NQS_EUNSUPPORTED, "the tensor-RNN runs in FP64 or FP32");
+  if (a->tensor && !a->tn_mfma && precision == NQS_F64 && !a->tn_f64_ok)
+    return fail(NQS_EUNSUPPORTED, "FP64 tensor-RNN ring does not fit the LDS");
+  return NQS_OK;
+}
 
 }  // namespace
 
@@ -1416,7 +1534,7 @@ nqs_status nqs_logpsi_phase(nqs_ctx* ctx, const nqs_ansatz* ans, const uint64_t*
   nqs_status s = check_samples(ctx, samples, N, ans->K, ans->na, ans->nb, stream);
   if (s != NQS_OK) return s;
   if (N == 0) return NQS_OK;
-  Scratch S(ctx);
+  Scratch S(ctx, stream);
   double* lphi = S.get<double>(N);
   int8_t* sphi = S.get<int8_t>(N);
   double* phs = ans->cplx ? S.get<double>(N) : nullptr;
@@ -1440,7 +1558,7 @@ nqs_status nqs_logpsi(nqs_ctx* ctx, const nqs_ansatz* ans, const uint64_t* sampl
   nqs_status s = check_samples(ctx, samples, N, ans->K, ans->na, ans->nb, stream);
   if (s != NQS_OK) return s;
   if (N == 0) return NQS_OK;
-  Scratch S(ctx);
+  Scratch S(ctx, stream);
   double* lphi = S.get<double>(N);
   int8_t* sphi = S.get<int8_t>(N);
   double* lf = ans->nh ? S.get<double>(N) : nullptr;
@@ -1482,7 +1600,7 @@ nqs_status nqs_logpsi_vjp_phase(nqs_ctx* ctx, const nqs_ansatz* ans, const uint6
   const bool phase = ans->cplx && cot_phase != nullptr;
   const size_t hsz = size_t(ans->K) * Rpad * ans->chip;
   const size_t esz = precision == NQS_F64 ? 8 : 4;
-  Scratch S(ctx);
+  Scratch S(ctx, stream);
   void* Hbuf = S.get<unsigned char>(hsz * esz);
   void* dcarry = S.get<unsigned char>(hsz * esz);
   void* Dc = S.get<unsigned char>(size_t(Rpad) * 4 * ans->chip * esz);
@@ -1595,13 +1713,14 @@ nqs_status eloc_run(nqs_ctx* ctx, const nqs_instance* inst, const nqs_ansatz* an
   if (ans->K != inst->K || ans->na != inst->na || ans->nb != inst->nb)
     return fail(NQS_EINVAL, "ansatz and instance describe different sectors");
   if (N > (int64_t(1) << 31) - 1) return fail(NQS_EUNSUPPORTED, "N too large");
+  if ((s = check_supported(ans, opts->precision)) != NQS_OK) return s;
   DeviceGuard g(ctx->device);
   if ((s = check_samples(ctx, samples, N, inst->K, inst->na, inst->nb, stream)) != NQS_OK) return s;
   if (N == 0) {
     if (stats) { std::memset(stats, 0, sizeof *stats); stats->n_conn = inst->H.n_conn; }
     return NQS_OK;
   }
-  Scratch S(ctx);
+  Scratch S(ctx, stream);
   hipEvent_t ev[3] = {}, pe[3] = {};
   const bool timing = stats != nullptr;
   if (timing) {
@@ -1643,7 +1762,8 @@ nqs_status eloc_run(nqs_ctx* ctx, const nqs_instance* inst, const nqs_ansatz* an
   double* phs_n = nullptr;
   if (resume) {
     rs.hs = S.get<unsigned char>(size_t(K) * N * ans->chip * state_bytes(opts->precision));
-    if (opts->precision == NQS_BF16) rs.he = S.get<int32_t>(size_t(K) * N);
+    if (is_bf16(opts->precision)) rs.he = S.get<int32_t>(size_t(K) * N);
+    if (opts->precision == NQS_BF16X3) rs.hs_lo = S.get<uint16_t>(size_t(K) * N * ans->chip);
     rs.pm = S.get<unsigned char>(size_t(K + 1) * N * mantissa_bytes(opts->precision));
     rs.pe = S.get<int32_t>(size_t(K + 1) * N);
     rs.pg = S.get<int8_t>(size_t(K + 1) * N);
@@ -1661,7 +1781,7 @@ nqs_status eloc_run(nqs_ctx* ctx, const nqs_instance* inst, const nqs_ansatz* an
   }
   // one level of shared prefixes (FP64/FP32; BF16 rows are cheap enough per
   // site that a node pass does not pay): node list, compact storage
-  const bool nodes = resume && opts->precision != NQS_BF16;
+  const bool nodes = resume && !is_bf16(opts->precision);
   const int64_t max_pass_samples = max_samples_per_pass(passes);
   const bool pair = pair_nodes(K, opts->precision);
   const int64_t ecap = node_entry_cap(cap_used, K, pair);
@@ -1886,24 +2006,31 @@ nqs_status nqs_eloc_complex(nqs_ctx* ctx, const nqs_instance* inst, const nqs_an
 
 namespace {
 // a pool block released when the holder goes out of scope
+// (behind the work queued on its stream, as for Scratch)
 struct PoolBlock {
   nqs_ctx* ctx = nullptr;
+  hipStream_t st = nullptr;
   void* p = nullptr;
   PoolBlock() = default;
   PoolBlock(const PoolBlock&) = delete;
   PoolBlock& operator=(const PoolBlock&) = delete;
-  bool get(nqs_ctx* c, size_t bytes) {
+  bool get(nqs_ctx* c, size_t bytes, hipStream_t s) {
     reset();
     ctx = c;
+    st = s;
     p = c->acquire(std::max<size_t>(bytes, 1));
     return p != nullptr;
   }
   void reset() {
-    if (p) ctx->release(p);
+    if (p) {
+      std::vector<void*> v{p};
+      ctx->release_after(v, st);
+    }
     p = nullptr;
   }
   void swap(PoolBlock& o) {
     std::swap(ctx, o.ctx);
+    std::swap(st, o.st);
     std::swap(p, o.p);
   }
   ~PoolBlock() { reset(); }
@@ -1916,10 +2043,10 @@ struct UniqueSet {
   int64_t* c = nullptr;
   double* l = nullptr;
   int8_t* s = nullptr;
-  bool alloc(nqs_ctx* ctx, int64_t n) {
+  bool alloc(nqs_ctx* ctx, int64_t n, hipStream_t st) {
     const size_t n8 = size_t(std::max<int64_t>(n, 1));
     const size_t bm = n8 * 16, bc = n8 * 8, bl = n8 * 8, bs = (n8 + 255) / 256 * 256;
-    if (!blk.get(ctx, bm + bc + bl + bs)) return false;
+    if (!blk.get(ctx, bm + bc + bl + bs, st)) return false;
     char* q = static_cast<char*>(blk.p);
     m = reinterpret_cast<uint64_t*>(q);
     c = reinterpret_cast<int64_t*>(q + bm);
@@ -1949,7 +2076,7 @@ nqs_status nqs_sample(nqs_ctx* ctx, const nqs_ansatz* ans, int64_t n_draws, uint
   *n_unique = 0;
   if (n_draws == 0) return NQS_OK;
   const bool two = 2 * ans->K > 64;
-  Scratch S(ctx);
+  Scratch S(ctx, stream);
   uint64_t* m = S.get<uint64_t>(size_t(chunk) * 2);
   double* lphi = S.get<double>(chunk);
   int8_t* sphi = S.get<int8_t>(chunk);
@@ -1980,7 +2107,7 @@ nqs_status nqs_sample(nqs_ctx* ctx, const nqs_ansatz* ans, int64_t n_draws, uint
     }
     const int64_t n = u + ch;
     if (n > kMaxSort) return fail(NQS_EUNSUPPORTED, "more than 2^31 - 1 unique draws plus one pass");
-    Scratch T(ctx);
+    Scratch T(ctx, stream);
     const uint64_t* im = m;
     const double* il = lphi;
     const int8_t* is = sphi;
@@ -2023,7 +2150,7 @@ nqs_status nqs_sample(nqs_ctx* ctx, const nqs_ansatz* ans, int64_t n_draws, uint
       *n_unique = h;
     } else {
       UniqueSet next;
-      if (!next.alloc(ctx, n)) return fail(NQS_ENOMEM, "workspace allocation failed");
+      if (!next.alloc(ctx, n, stream)) return fail(NQS_ENOMEM, "workspace allocation failed");
       HIPCHK(launch_unique(im, il, is, iw, n, two, w, n, next.m, next.c, next.l, next.s, nu, stream));
       HIPCHK(hipMemcpyAsync(&u, nu, sizeof u, hipMemcpyDeviceToHost, stream));
       HIPCHK(hipStreamSynchronize(stream));   // the old set and this pass's buffers are free after this
@@ -2047,7 +2174,7 @@ nqs_status nqs_rows(nqs_ctx* ctx, const nqs_instance* inst, const uint64_t* samp
   DeviceGuard g(ctx->device);
   if ((s = check_samples(ctx, samples, N, inst->K, inst->na, inst->nb, stream)) != NQS_OK) return s;
   if (N == 0) { if (n_rows) *n_rows = 0; return NQS_OK; }
-  Scratch S(ctx);
+  Scratch S(ctx, stream);
   Pipeline P{};
   if ((s = count_and_draw(S, inst, samples, N, *opts, P, stream, nullptr)) != NQS_OK) return s;
   const int64_t R = P.R, w = std::min(R, cap);
@@ -2093,12 +2220,13 @@ nqs_status nqs_eloc_workspace_bytes(const nqs_instance* inst, const nqs_ansatz* 
     // samples' carried and log-product states, the pass's row order
     const int K = ans->K;
     b += al(size_t(K) * N * ans->chip * state_bytes(opts->precision));
-    if (opts->precision == NQS_BF16) b += al(size_t(K) * N * 4);
+    if (is_bf16(opts->precision)) b += al(size_t(K) * N * 4);
+    if (opts->precision == NQS_BF16X3) b += al(size_t(K) * N * ans->chip * 2);
     b += al(size_t(K + 1) * N * mantissa_bytes(opts->precision)) + al(size_t(K + 1) * N * 4);
     b += al(size_t(K + 1) * N) + al(size_t(rows) * 4) + 2 * al(size_t(rows));
     b += al(size_t(order_blocks(rows)) * (K + 1) * 4) + al(size_t(K + 1) * 8);
     b += al(size_t(N) * 8) + al(size_t(N));
-    if (opts->precision != NQS_BF16) {
+    if (!is_bf16(opts->precision)) {
       // node level: per-sample counts, node list, node order, storage, rows' nodes
       const int64_t ecap = node_entry_cap(rows, K, pair_nodes(K, opts->precision));
       const size_t esz = state_bytes(opts->precision);
@@ -2136,7 +2264,7 @@ nqs_status nqs_vmc_step(nqs_ctx* ctx, const nqs_instance* inst, nqs_ansatz* ans,
     return std::chrono::duration<double, std::milli>(b - a).count();
   };
   const int64_t D = opts->n_draws;
-  Scratch S(ctx);
+  Scratch S(ctx, stream);
   uint64_t* smp = S.get<uint64_t>(size_t(D) * 2);
   int64_t* cnt = S.get<int64_t>(D);
   double* cd = S.get<double>(D);
@@ -2179,6 +2307,11 @@ nqs_status nqs_vmc_step(nqs_ctx* ctx, const nqs_instance* inst, nqs_ansatz* ans,
   HIPCHK(launch_sumsq(np, gbuf, red + 2, stream));
   HIPCHK(launch_adamw(np, params, gbuf, adam_m, adam_v, opts->step, opts->lr, opts->beta1, opts->beta2,
                       opts->adam_eps, opts->weight_decay, stream));
+  // projected step: eta >= 0 (Sec. 2.1); the caller's packed layout (complex: cEta of the map)
+  if (ans->cplx)
+    HIPCHK(launch_project_eta(ans->K, ans->chi_c, ans->d_cx + 5 * ans->K, params, stream));
+  else
+    HIPCHK(launch_project_eta(ans->K, ans->chi, ans->d_offEta, params, stream));
   double hred[4] = {0, 0, 0, 0};
   HIPCHK(hipMemcpyAsync(hred, red, sizeof hred, hipMemcpyDeviceToHost, stream));
   HIPCHK(hipStreamSynchronize(stream));

@@ -87,6 +87,15 @@ __global__ void k_adamw(int64_t n, double* p, const double* g, double* m, double
   v[k] = vk;
 }
 
+// projection onto eta >= 0: one workgroup per site, one thread per unit; a
+// NaN stays NaN (the re-bind then refuses it)
+__global__ void k_project_eta(int chi, const int64_t* off, double* p) {
+  const int u = threadIdx.x;
+  if (u >= chi) return;
+  double* e = p + off[blockIdx.x] + u;
+  if (*e < 0.0) *e = 0.0;
+}
+
 // one workgroup: out = sum g^2
 __global__ __launch_bounds__(kBlock) void k_sumsq(int64_t n, const double* g, double* out) {
   __shared__ double sh[kBlock];
@@ -125,6 +134,12 @@ hipError_t launch_adamw(int64_t n, double* p, const double* g, double* m, double
   if (n <= 0) return hipSuccess;
   const double c1 = 1.0 - std::pow(b1, double(t)), c2 = 1.0 - std::pow(b2, double(t));
   hipLaunchKernelGGL(k_adamw, dim3(blocks_for(n)), dim3(256), 0, st, n, p, g, m, v, lr, b1, b2, eps, wd, c1, c2);
+  return hipGetLastError();
+}
+
+hipError_t launch_project_eta(int K, int chi, const int64_t* off, double* p, hipStream_t st) {
+  if (K <= 0 || chi <= 0 || chi > 1024) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_project_eta, dim3(K), dim3(chi), 0, st, chi, off, p);
   return hipGetLastError();
 }
 

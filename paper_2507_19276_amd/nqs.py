@@ -20,7 +20,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libnqs.so")
 
 NQS_OK, NQS_EINVAL, NQS_ENOMEM, NQS_EDEVICE, NQS_EUNSUPPORTED, NQS_EBUSY = range(6)
-PRECISIONS = {"f64": 0, "f32": 1, "bf16": 2}
+PRECISIONS = {"f64": 0, "f32": 1, "bf16": 2, "bf16x3": 3}
 
 
 class NqsError(RuntimeError):
@@ -247,13 +247,20 @@ class Ansatz:
         self.tensor = bool(tensor)
         self.cplx = bool(cplx)
         self.n_params = int(lib().nqs_ansatz_n_params(out))
+        # bind generation and a copy of the bound parameters: LogPsi.backward
+        # uses them to take the gradient at its forward's parameters
+        self.version = 0
+        self._bound = None
 
     def bind(self, params):
         if isinstance(params, np.ndarray):
             params = torch.from_numpy(np.ascontiguousarray(params, dtype=np.float64))
         p = params.detach().to(dtype=torch.float64, device=f"cuda:{self.ctx.device}").contiguous()
         assert p.numel() == self.n_params
+        self.version += 1
+        self._bound = None
         check(lib().nqs_ansatz_bind_params(self.h, _ptr(p), _p(_stream())))
+        self._bound = p.clone() if p.data_ptr() == params.data_ptr() else p
         return self
 
     def logpsi(self, samples, precision="f64"):
@@ -382,8 +389,11 @@ def vmc_step(ctx: Context, inst: Instance, ans: Ansatz, params: torch.Tensor, ad
                 opts(eps, n_eps, precision, seed, stream_id), float(lr), float(beta1), float(beta2),
                 float(adam_eps), float(weight_decay), int(step))
     st = VmcStats()
+    ans.version += 1
+    ans._bound = None
     check(lib().nqs_vmc_step(ctx.h, inst.h, ans.h, C.byref(o), _ptr(params), _ptr(adam_m), _ptr(adam_v),
                              _ptr(grad), C.byref(st), _p(_stream())))
+    ans._bound = params.detach().clone()   # the step re-bound the ansatz to the updated parameters
     return st.to_dict()
 
 
@@ -431,13 +441,25 @@ class LogPsi(torch.autograd.Function):
         la, _ = ans.logpsi(samples, precision)
         ctx_.ans = ans
         ctx_.precision = precision
-        ctx_.save_for_backward(_samples(samples))
+        ctx_.version = ans.version
+        ctx_.save_for_backward(_samples(samples), params)
         return la
 
     @staticmethod
     def backward(ctx_, g):
-        (s,) = ctx_.saved_tensors
-        grad = ctx_.ans.vjp(s, g.contiguous(), ctx_.precision)
+        s, params = ctx_.saved_tensors
+        ans = ctx_.ans
+        if ans.version == ctx_.version:
+            return ans.vjp(s, g.contiguous(), ctx_.precision), None, None, None
+        # the ansatz was bound to other parameters after this forward: take the
+        # gradient at the forward's parameters, then restore the newer binding
+        current = ans._bound
+        ans.bind(params)
+        try:
+            grad = ans.vjp(s, g.contiguous(), ctx_.precision)
+        finally:
+            if current is not None:
+                ans.bind(current)
         return grad, None, None, None
 
 
