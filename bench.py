@@ -1,25 +1,31 @@
 """Throughput of the semi-stochastic local energy on one MI355X.
 
 Default: one step = one nqs_eloc call over the whole synthetic batch of the
-chain workload (K = 20 spatial orbitals, 10a+10b, chain BDG-RNN chi = 16, 4096
-unique samples, eps = 1e-3, N_eps = 64): enumerate every connected
-determinant, screen, draw, evaluate the amplitude of every row, reduce.
-Integrals, parameters and samples are resident in HBM before the timed
-region; outputs stay on the device.  The headline precision is FP32 bond
-contractions (FP64 Hamiltonian elements, ratios and sums); FP64 and BF16 are
-timed alongside.  The CPU-baseline leg runs the FP64 oracle on the same
-4096 samples with the draws of one GPU step and reports the GPU error
-against it.
+K = 50 workload (50 spatial orbitals, 25a+25b, chain-like integrals with decay
+length 2, BDG-RNN on the nearest + next-nearest neighbour graph with chi = 32,
+cos-RBM correlator with 100 hidden units, 16384 distinct samples drawn exactly
+from Phi^2 with their counts, eps = 1e-2, N_eps = 100): enumerate every
+connected determinant, screen, draw, evaluate the amplitude of every row and
+the correlator, reduce.  Integrals, parameters and samples are resident in HBM
+before the timed region (the samples are drawn on the GPU by nqs_sample
+beforehand); outputs stay on the device.  The headline precision is FP64, the
+paper's (Sec. 3); FP32, BF16 and split-BF16 (hi + lo parts, three MFMA
+products) bond contractions are timed alongside.  The
+same is reported for the K = 20 chain workload (chi = 16, 4096 samples,
+eps = 1e-3, N_eps = 64).
 
---next: the sampler, the Ising-RBM and BDG-TensorRNN local energies and one
-VMC step, each on its own K = 20 workload, with the roofline of its dominant
-kernel.
+Equal energy error: on the K = 20 batch and a 256-sample block of the K = 50
+batch, the batch energy sum c Etilde / sum c |f|^2 of every precision over 8
+draw seeds against the same samples' exact energy (eps = 0, FP64); where a
+precision's error exceeds the FP64 path's, the FP64 N_eps that matches it and
+the throughput ratio there.
 
---serve: the serving workload instead (500 Poisson-arriving requests over 12
-resident instances, norb in {12,20,36,50} x chi in {16,32,64}, BF16 path,
-eps = 1e-2, N_eps = 100, batch sizes log-uniform in [256, 16384]) at 0.8 x
-the measured capacity; reports total local energies/s and latency
-percentiles.
+The CPU-baseline leg runs the FP64 oracle (built for the host CPU) on a block
+of the K = 50 batch with the draws of one GPU call and reports the GPU error
+per precision against it, with the stated per-sample bound of each precision.
+
+--workload c2: the K = 20 chain workload as the headline instead.
+--next / --serve / --configs / --speedups: see their functions.
 
 Prints one JSON line.
 """
@@ -28,20 +34,31 @@ import json
 import math
 import os
 import sys
+import tempfile
 import threading
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-WORKLOAD = "c2"
-PEAKS = {"f64": 78.6, "f32": 157.3, "bf16": 2500.0}   # MI355X dense MFMA, TFLOP/s
-# HBM bytes per launch of the row amplitude kernel of the headline precision,
-# from the FETCH_SIZE / WRITE_SIZE counters (copy-calibrated) recorded in
-# profiles/; valid only for the kernel source they were taken on (first 16 hex
-# digits of the sha256 of psi.hip followed by device.h).
-MEASURED_TRAFFIC = {"f32": {"sha16": "2fe67cfa4b7b69aa", "bytes_per_launch": 1.0433553e10}}
+PEAKS = {"f64": 78.6, "f32": 157.3, "bf16": 2500.0, "bf16x3": 2500.0}   # MI355X dense MFMA, TFLOP/s
+# error model of the stated per-sample bounds (the GPU tests hold the
+# derivation): bond contractions with unit roundoff u keep states within a
+# relative error 8 u and log|Phi| within 8 K u; cos theta of the correlator
+# is evaluated in FP32 within a relative error U_F (1 + |theta|)
+UNIT_ROUNDOFF = {"f64": 2.0 ** -53, "f32": 2.0 ** -24, "bf16": 2.0 ** -8, "bf16x3": 2.0 ** -15}
+U_F = 2.0 ** -22
+# HBM bytes per launch of the headline row amplitude kernel, from the
+# FETCH_SIZE / WRITE_SIZE counters (copy-calibrated) recorded in profiles/;
+# valid only for the kernel source they were taken on (first 16 hex digits of
+# the sha256 of psi.hip followed by device.h) and for that workload.
+MEASURED_TRAFFIC = {}
 KERNEL_SOURCES = ("psi.hip", "device.h")
+WORKLOAD_TEXT = {
+    "c2": "chain K=20 10a+10b, BDG-RNN chain chi=16, 4096 distinct samples drawn from Phi^2, eps=1e-3, N_eps=64",
+    "c3": "chain-like K=50 25a+25b, BDG-RNN NN+NNN chi=32 x cos-RBM N_h=100, 16384 distinct samples drawn "
+          "from Phi^2, eps=1e-2, N_eps=100",
+}
 
 
 def kernel_sha16():
@@ -52,34 +69,174 @@ def kernel_sha16():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(prec):
-    rec = MEASURED_TRAFFIC.get(prec)
+def measured_traffic(workload, prec):
+    rec = MEASURED_TRAFFIC.get((workload, prec))
     if rec is None or rec["sha16"] != kernel_sha16():
         return None
     return rec["bytes_per_launch"]
 
 
-def cpu_baseline(w, seed, gpu_out):
-    """The FP64 oracle on the full batch with the draws of the GPU step that
-    used `seed`; returns the baseline record and the GPU error against it."""
+def phi2_batch(nqs, workloads, ans, w):
+    """The workload's batch: distinct ONVs drawn exactly from Phi^2 on the GPU
+    (nqs_sample, FP64, counter-keyed), with their counts; topped up with
+    uniform valid ONVs only if the draws held fewer distinct ONVs."""
+    import numpy as np
+    import torch
+    seed = w.seed + workloads.PHI2_SEED_OFFSET
+
+    def draw(n):
+        s, c, _, _, _ = ans.sample(n, seed=seed, precision="f64")
+        return s, c
+
+    s, c, n = workloads.draw_until_unique(draw, w.n_samples)
+    smp = s.cpu().numpy().view(np.uint64)
+    cnt = c.cpu().numpy()
+    smp, cnt, added = workloads.top_up(smp, cnt, w.K, w.n_alpha, w.n_beta, w.n_samples, seed)
+    dev = torch.from_numpy(np.ascontiguousarray(smp).view(np.int64)).cuda()
+    return dev, torch.from_numpy(cnt.astype(np.float64)).cuda(), n, added, seed
+
+
+def setup_workload(nqs, workloads, ctx, name):
+    w = workloads.make_workload(name)
+    inst = nqs.Instance(ctx, w.K, w.n_alpha, w.n_beta, w.h, w.eri, w.e_core)
+    ans = nqs.Ansatz(ctx, w.K, w.n_alpha, w.n_beta, w.chi, w.parent_ptr, w.parent_idx, w.n_hidden)
+    ans.bind(w.params)
+    samples, counts, n_draws, added, sseed = phi2_batch(nqs, workloads, ans, w)
+    return dict(w=w, inst=inst, ans=ans, samples=samples, counts=counts, n_draws=n_draws, added=added,
+                sample_seed=sseed)
+
+
+def time_precisions(nqs, ctx, W, precs, steps, warmup, full_recompute=False, ref_seed=None):
+    """steps timed nqs_eloc calls per precision (after warmup); per-call stage
+    times from the library's device events; one extra call with ref_seed keeps
+    its outputs (for the oracle comparison)."""
+    import numpy as np
+    import torch
+    w = W["w"]
+    N = w.n_samples
+    res, keep = {}, {}
+
+    def step(k, prec):
+        return nqs.eloc(ctx, W["inst"], W["ans"], W["samples"], counts=W["counts"], eps=w.eps, n_eps=w.n_eps,
+                        precision=prec, seed=w.seed + k, stream_id=0, resume=not full_recompute)
+
+    for prec in precs:
+        for k in range(warmup):
+            step(k, prec)
+        torch.cuda.synchronize()
+        sts = []
+        t0 = time.perf_counter()
+        for k in range(steps):
+            _, st = step(1000 + k, prec)
+            sts.append(st)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        mean = {k: float(np.mean([st[k] for st in sts])) for k in
+                ("ms_enumerate", "ms_draw", "ms_rows", "ms_amplitude", "ms_reduce", "ms_psi", "psi_flops", "n_rows",
+                 "n_site_rows", "n_det_rows", "n_draw_rows")}
+        res[prec] = {"value": steps * N / dt, "ms_per_step": dt / steps * 1e3, "stats": mean, "E": sts[-1]["E"]}
+        print(f"# {w.name} {prec}: {steps} steps in {dt:.3f} s ({dt / steps * 1e3:.2f} ms/step), "
+              f"rows/step {mean['n_rows']:.0f}, row amplitude kernel {mean['ms_psi']:.3f} ms",
+              file=sys.stderr, flush=True)
+        if ref_seed is not None:
+            out, st = nqs.eloc(ctx, W["inst"], W["ans"], W["samples"], counts=W["counts"], eps=w.eps,
+                               n_eps=w.n_eps, precision=prec, seed=ref_seed, stream_id=0)
+            keep[prec] = {k: v.cpu().numpy() for k, v in out.items()}
+    return res, keep
+
+
+def equal_error(nqs, ctx, W, precs, n_sub, seeds=8, max_rows=16_000_000):
+    """Batch energy of each precision over `seeds` draw seeds against the exact
+    energy of the same samples (eps = 0, FP64), on the first n_sub samples of
+    the batch.  Where a precision's RMS error over the seeds exceeds the FP64
+    path's, the FP64 N_eps with the same expected RMS error (the draw variance
+    scales as 1/N_eps, Sec. 2.4) is timed and checked, and the throughput ratio
+    at that N_eps is given."""
+    import numpy as np
+    import torch
+    w = W["w"]
+    smp = W["samples"][:n_sub]
+    cnt = W["counts"][:n_sub]
+    kw = dict(counts=cnt, stream_id=5, max_rows_per_pass=max_rows)
+    _, st = nqs.eloc(ctx, W["inst"], W["ans"], smp, eps=0.0, n_eps=0, precision="f64", **kw)
+    E_ex = st["E"]
+
+    def run(prec, n_eps, reps=seeds):
+        Es, ts = [], []
+        for s in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, st = nqs.eloc(ctx, W["inst"], W["ans"], smp, eps=w.eps, n_eps=n_eps, precision=prec,
+                             seed=777 + s, **kw)
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+            Es.append(st["E"])
+        d = np.array(Es) - E_ex
+        return {"n_eps": n_eps, "mean_error": float(d.mean()), "se_of_mean": float(d.std(ddof=1) / math.sqrt(reps)),
+                "rms_error": float(np.sqrt(np.mean(d ** 2))), "local_energies_per_s": n_sub / float(np.median(ts))}
+
+    out = {"samples": n_sub, "seeds": seeds, "E_exact_f64_eps0": E_ex, "eps": w.eps}
+    for prec in precs:
+        out[prec] = run(prec, w.n_eps)
+    r64 = out["f64"]["rms_error"]
+    for prec in precs:
+        if prec == "f64":
+            continue
+        rp = out[prec]["rms_error"]
+        if rp <= r64 or r64 == 0.0:
+            out[prec]["at_equal_error"] = {"vs": "f64 at the same N_eps",
+                                           "speedup": out[prec]["local_energies_per_s"]
+                                           / out["f64"]["local_energies_per_s"]}
+            continue
+        n_match = max(1, int(round(w.n_eps * (r64 / rp) ** 2)))
+        m = run("f64", n_match)
+        out[prec]["at_equal_error"] = {"vs": f"f64 at N_eps={n_match}", "f64": m,
+                                       "speedup": out[prec]["local_energies_per_s"] / m["local_energies_per_s"]}
+    return out
+
+
+def cpu_baseline(W, keep, seed, n_sub, threads):
+    """The FP64 oracle, built for this host, on the first n_sub samples with the
+    draws of the GPU call that used `seed`; returns the baseline record and the
+    GPU error against it per precision (with the stated bound)."""
     import numpy as np
     import oracle
-    threads = os.cpu_count() or 1
+    from oracle import build as oracle_build
+    native = os.path.join(tempfile.mkdtemp(prefix="oracle_native_"), "liboracle.so")
+    try:
+        oracle_build.build(native=True, out=native)
+        oracle.use_library(native)
+        build = "g++ -O3 -march=native (host build)"
+    except Exception as e:   # fall back to the shipped x86-64-v3 build
+        build = f"shipped x86-64-v3 build ({type(e).__name__})"
+    w = W["w"]
+    smp = W["samples"][:n_sub].cpu().numpy().view(np.uint64)
+    cols = ("f32", "bf16", "bf16x3")
+    bounds = tuple((8.0 * w.K * UNIT_ROUNDOFF[p], 8.0 * UNIT_ROUNDOFF[p]) for p in cols)
     t0 = time.perf_counter()
     ref = oracle.eloc(w.K, w.n_alpha, w.n_beta, w.h, w.eri, w.chi, w.parent_ptr, w.parent_idx, w.n_hidden,
-                      w.params, w.samples, eps=w.eps, n_eps=w.n_eps, seed=seed, stream=0, nthreads=threads)
+                      w.params, smp, eps=w.eps, n_eps=w.n_eps, seed=seed, stream=0, nthreads=threads,
+                      bounds=bounds, u_f=U_F)
     dt = time.perf_counter() - t0
-    rec = {"value": w.n_samples / dt, "unit": "local energies/s", "cores": threads, "kind": "oracle",
-           "sample": f"all {w.n_samples} samples of the benchmark batch, FP64 oracle, {dt:.1f} s"}
+    rec = {"value": n_sub / dt, "unit": "local energies/s", "cores": threads, "kind": "oracle",
+           "sample": f"the first {n_sub} of the {w.n_samples} samples of the benchmark batch ({w.name}), with the "
+                     f"draws of one GPU call; FP64 oracle, {build}, {dt:.1f} s"}
     e_ref = ref["eloc"]
-    E_ref = ref["etnum"].sum() / ref["fsq"].sum()
-    se = math.sqrt((ref["fsq"] * (e_ref - E_ref) ** 2).sum() / ref["fsq"].sum() / w.n_samples)
     tau = 1e-3 * float(np.sqrt(np.mean(e_ref ** 2)))
     errs = {}
-    for prec, (el, E) in gpu_out.items():
-        r = np.abs(el - e_ref) / np.maximum(np.abs(e_ref), tau)
-        errs[prec] = {"p50": float(np.median(r)), "p99": float(np.quantile(r, 0.99)), "max": float(r.max()),
-                      "dE_over_SE": abs(E - E_ref) / se}
+    for prec, out in keep.items():
+        el = out["eloc"][:n_sub]
+        dE = np.abs(el - e_ref)
+        r = dE / np.maximum(np.abs(e_ref), tau)
+        rec_p = {"p50": float(np.median(r)), "p99": float(np.quantile(r, 0.99)), "max": float(r.max()),
+                 "dE_over_S_max": float((dE / ref["sabs"]).max())}
+        if prec in cols:
+            bound = ref["ebound"][:, cols.index(prec)]
+            ok = ref["margin_f"] >= 8 * U_F      # a correlator this close to a zero has no bound
+            rec_p["bound_ratio_max"] = float((dE[ok] / bound[ok]).max()) if ok.any() else None
+            rec_p["bound_over_S_p50"] = float(np.median(bound / ref["sabs"]))
+            rec_p["samples_without_bound"] = int((~ok).sum())
+        errs[prec] = rec_p
     return rec, errs
 
 
@@ -89,13 +246,7 @@ def run_eloc_bench(args):
     from paper_2507_19276_amd import nqs, workloads
 
     torch.cuda.set_device(0)
-    w = workloads.make_workload(WORKLOAD)
     ctx = nqs.Context(0)
-    inst = nqs.Instance(ctx, w.K, w.n_alpha, w.n_beta, w.h, w.eri, w.e_core)
-    ans = nqs.Ansatz(ctx, w.K, w.n_alpha, w.n_beta, w.chi, w.parent_ptr, w.parent_idx, w.n_hidden)
-    ans.bind(w.params)
-    samples = torch.from_numpy(w.samples.view(np.int64)).cuda().contiguous()
-    N = w.n_samples
     if args.copy_calibration_mib:
         nbytes = args.copy_calibration_mib << 20
         a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
@@ -103,70 +254,77 @@ def run_eloc_bench(args):
         b.copy_(a)
         torch.cuda.synchronize()
         print(f"# copy calibration: {nbytes} bytes read, {nbytes} bytes written", file=sys.stderr)
-
-    def step(k, prec):
-        return nqs.eloc(ctx, inst, ans, samples, eps=w.eps, n_eps=w.n_eps, precision=prec,
-                        seed=w.seed + k, stream_id=0, resume=not args.full_recompute)
-
     precs = list(dict.fromkeys(args.precisions.split(",")))
     head_prec = precs[0]
-    results, keep = {}, {}
-    for prec in precs:
-        for k in range(args.warmup):
-            step(k, prec)
-        torch.cuda.synchronize()
-        amp_ms, psi_ms, psi_fl, rows = [], [], [], []
-        t0 = time.perf_counter()
-        for k in range(args.steps):
-            out, st = step(1000 + k, prec)
-            amp_ms.append(st["ms_amplitude"])
-            psi_ms.append(st["ms_psi"])
-            psi_fl.append(st["psi_flops"])
-            rows.append(st["n_rows"])
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
-        results[prec] = dict(dt=dt, amp_ms=float(np.mean(amp_ms)), psi_ms=float(np.mean(psi_ms)),
-                             psi_flops=float(np.mean(psi_fl)), rows=float(np.mean(rows)), st=st)
-        print(f"# {prec}: {args.steps} steps in {dt:.3f} s, rows/step {np.mean(rows):.0f}, "
-              f"site-rows/step {st['n_site_rows']}, amplitude stage {np.mean(amp_ms):.3f} ms, "
-              f"row amplitude kernel {np.mean(psi_ms):.3f} ms", file=sys.stderr, flush=True)
-        if not args.no_cpu_baseline:
-            out, st = step(7, prec)
-            keep[prec] = (out["eloc"].cpu().numpy(), st["E"])
-
+    head_name = args.workload
+    other = "c2" if head_name == "c3" else "c3"
+    ref_seed = 424242
+    Wh = setup_workload(nqs, workloads, ctx, head_name)
+    print(f"# {head_name}: {Wh['w'].n_samples} distinct samples from {Wh['n_draws']} draws of Phi^2 "
+          f"({Wh['added']} topped up)", file=sys.stderr, flush=True)
+    results, keep = time_precisions(nqs, ctx, Wh, precs, args.steps, args.warmup, args.full_recompute,
+                                    ref_seed=None if args.no_cpu_baseline else ref_seed)
+    N = Wh["w"].n_samples
     head = results[head_prec]
-    value = args.steps * N / head["dt"]
-    achieved = head["psi_flops"] / (head["psi_ms"] * 1e-3) / 1e12
+    hs = head["stats"]
+    achieved = hs["psi_flops"] / (hs["ms_psi"] * 1e-3) / 1e12
     peak = PEAKS[head_prec]
+    wh = Wh["w"]
     line = {
         "metric": "local energies/sec at fixed bond dim D",
-        "value": value,
+        "value": head["value"],
         "unit": "local energies/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": head["dt"] / args.steps * 1e3,
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": head_prec,
         "data": "synthetic",
-        "config": {"workload": "chain K=20 10a+10b, BDG-RNN chain chi=16, 4096 unique samples, "
-                               "eps=1e-3, N_eps=64", "global_batch": N, "precision": head_prec},
-        "rows_per_step": head["rows"],
-        "by_precision": {p: {"value": args.steps * N / r["dt"], "amplitude_stage_ms": r["amp_ms"],
-                             "row_kernel_ms": r["psi_ms"], "row_kernel_tflops": r["psi_flops"] / r["psi_ms"] / 1e9,
-                             "ms_per_step": r["dt"] / args.steps * 1e3} for p, r in results.items()},
-        "site_rows_per_step": int(head["st"]["n_site_rows"]),
+        "config": {"workload": WORKLOAD_TEXT[head_name], "global_batch": N, "precision": head_prec,
+                   "samples_from": f"{Wh['n_draws']} exact draws of Phi^2 (nqs_sample, seed {Wh['sample_seed']}), "
+                                   f"{Wh['added']} topped up"},
+        "rows_per_step": hs["n_rows"],
+        "site_rows_per_step": hs["n_site_rows"],
+        "by_precision": {p: {"value": r["value"], "ms_per_step": r["ms_per_step"],
+                             "row_kernel_ms": r["stats"]["ms_psi"],
+                             "row_kernel_tflops": r["stats"]["psi_flops"] / r["stats"]["ms_psi"] / 1e9,
+                             "row_kernel_frac_of_peak": r["stats"]["psi_flops"] / r["stats"]["ms_psi"] / 1e9
+                             / PEAKS[p],
+                             "stages_ms": {k: r["stats"][k] for k in ("ms_enumerate", "ms_draw", "ms_rows",
+                                                                       "ms_amplitude", "ms_reduce")},
+                             "H_elements_per_s_enumerate": N * int(Wh["inst"].n_conn)
+                             / (r["stats"]["ms_enumerate"] * 1e-3),
+                             "batch_energy": r["E"]} for p, r in results.items()},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "frac": achieved / peak,
-                     "traffic": args.traffic_bytes if args.traffic_bytes else measured_traffic(head_prec),
+                     "traffic": args.traffic_bytes if args.traffic_bytes else measured_traffic(head_name, head_prec),
                      "kernel": "k_psi_mt (row amplitude kernel: bond contractions and conditionals)",
-                     "flops_per_launch": head["psi_flops"], "ms_per_launch": head["psi_ms"],
+                     "flops_per_launch": hs["psi_flops"], "ms_per_launch": hs["ms_psi"],
                      "kernel_sha16": kernel_sha16()},
     }
+    if not args.headline_only:
+        Wo = setup_workload(nqs, workloads, ctx, other)
+        ro, _ = time_precisions(nqs, ctx, Wo, precs, max(2, args.steps // 2), 1)
+        line[other] = {"workload": WORKLOAD_TEXT[other],
+                       "by_precision": {p: {"value": r["value"], "ms_per_step": r["ms_per_step"],
+                                            "row_kernel_ms": r["stats"]["ms_psi"],
+                                            "row_kernel_frac_of_peak": r["stats"]["psi_flops"]
+                                            / r["stats"]["ms_psi"] / 1e9 / PEAKS[p]}
+                                        for p, r in ro.items()}}
+        eq = {}
+        for Wx, n_sub in ((Wh, 256 if head_name == "c3" else Wh["w"].n_samples),
+                          (Wo, 256 if other == "c3" else Wo["w"].n_samples)):
+            eq[Wx["w"].name] = equal_error(nqs, ctx, Wx, precs, n_sub)
+            print(f"# equal error {Wx['w'].name}: " + ", ".join(
+                f"{p} rms {eq[Wx['w'].name][p]['rms_error']:.3e}" for p in precs), file=sys.stderr, flush=True)
+        line["equal_energy_error"] = eq
+        del Wo
     if not args.no_cpu_baseline:
-        rec, errs = cpu_baseline(w, w.seed + 7, keep)
+        threads = min(16, os.cpu_count() or 1)
+        rec, errs = cpu_baseline(Wh, keep, ref_seed, 256 if head_name == "c3" else Wh["w"].n_samples, threads)
         line["cpu_baseline"] = rec
         line["eloc_error_vs_fp64_oracle"] = errs
     print(json.dumps(line), flush=True)
@@ -547,8 +705,12 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--precisions", default="f32,f64,bf16",
+    ap.add_argument("--precisions", default="f64,f32,bf16,bf16x3",
                     help="comma list; the first is the headline")
+    ap.add_argument("--workload", default="c3", choices=("c2", "c3"),
+                    help="headline workload: c3 (K=50, chi=32, cos-RBM, 16384 samples) or c2 (K=20, chi=16)")
+    ap.add_argument("--headline-only", action="store_true",
+                    help="skip the second workload and the equal-energy-error study")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--full-recompute", action="store_true",
                     help="evaluate every amplitude row from site 0 (no resumption at the first changed site)")

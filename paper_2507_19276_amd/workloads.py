@@ -330,6 +330,51 @@ def uniforms(shape, seed: int) -> np.ndarray:
     return np.random.default_rng(seed).random(shape)
 
 
+# seed of the exact draws from Phi^2 that make a workload's sample batch
+# (the workload's seed plus this offset)
+PHI2_SEED_OFFSET = 11
+
+
+def draw_until_unique(draw, n_unique: int, max_draws: int = 1 << 22):
+    """Sample batch of n_unique distinct ONVs from a counter-keyed sampler.
+
+    draw(n) must return (unique ONVs, counts) of the draws 0 .. n-1; a
+    counter-keyed sampler (each draw a function of its index) only appends
+    draws when n grows.  Starting from n = n_unique, each round adds the
+    number of ONVs still missing, so no round can overshoot: the loop stops at
+    the smallest n whose draws hold n_unique distinct ONVs (or at max_draws).
+    Returns (ONVs, counts, n) as draw returned them; fewer than n_unique ONVs
+    only if max_draws was reached.  This is bookkeeping around a sampler that
+    is passed in; no draw is made here."""
+    n = int(n_unique)
+    while True:
+        u, c = draw(n)
+        if len(u) >= n_unique or n >= max_draws:
+            return u, c, n
+        n = min(n + n_unique - len(u), int(max_draws))
+
+
+def top_up(samples: np.ndarray, counts: np.ndarray, K: int, n_alpha: int, n_beta: int, N: int,
+           seed: int):
+    """Fill a batch of distinct ONVs up to N with uniform random valid ONVs not
+    already in it (count 1 each): used only when the draws held fewer than N
+    distinct ONVs.  Returns (samples, counts, number added)."""
+    have = {onv_to_int(r) for r in samples}
+    extra = []
+    if len(samples) < N:
+        pool = random_onvs(K, n_alpha, n_beta, min(4 * N, math.comb(K, n_alpha) * math.comb(K, n_beta)), seed)
+        for r in pool:
+            if onv_to_int(r) not in have:
+                have.add(onv_to_int(r))
+                extra.append(r)
+                if len(samples) + len(extra) == N:
+                    break
+    if not extra:
+        return samples, counts, 0
+    return (np.vstack([samples, np.asarray(extra, dtype=np.uint64)]),
+            np.concatenate([counts, np.ones(len(extra), dtype=counts.dtype)]), len(extra))
+
+
 # ---------------------------------------------------------------------------
 # the five workloads
 # ---------------------------------------------------------------------------

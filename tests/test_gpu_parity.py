@@ -11,6 +11,7 @@ import pytest
 import torch
 
 import oracle
+from bounds import KAPPA_F, U_F, bounds, log_bound, stated_bound
 from paper_2507_19276_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
@@ -114,7 +115,7 @@ def test_logpsi_f64(nqs, ctx, name, n):
     assert np.array_equal(sg.cpu().numpy(), ref["sign"])
 
 
-def _eloc_pair(nqs, ctx, name, n, precision, eps=None, n_eps=None, seed=None):
+def _eloc_pair(nqs, ctx, name, n, precision, eps=None, n_eps=None, seed=None, with_bounds=False):
     w, inst, ans = setup(nqs, ctx, name, n)
     eps = w.eps if eps is None else eps
     n_eps = w.n_eps if n_eps is None else n_eps
@@ -122,7 +123,8 @@ def _eloc_pair(nqs, ctx, name, n, precision, eps=None, n_eps=None, seed=None):
     out, st = nqs.eloc(ctx, inst, ans, w.samples, eps=eps, n_eps=n_eps, precision=precision, seed=seed,
                        stream_id=1)
     ref = oracle.eloc(w.K, w.n_alpha, w.n_beta, w.h, w.eri, w.chi, w.parent_ptr, w.parent_idx, w.n_hidden,
-                      w.params, w.samples, eps=eps, n_eps=n_eps, seed=seed, stream=1)
+                      w.params, w.samples, eps=eps, n_eps=n_eps, seed=seed, stream=1,
+                      bounds=bounds(w.K) if with_bounds else (), u_f=U_F)
     got = {k: v.cpu().numpy() for k, v in out.items()}
     return w, got, ref, st
 
@@ -148,17 +150,16 @@ def test_eloc_f64(nqs, ctx, name, n):
 
 
 def test_eloc_f32_bound(nqs, ctx):
-    """FP32 bond contractions (FP64 Hamiltonian elements, ratios and sums).
-    Each ratio Psi(m)/Psi(n) carries about K sites x a few FP32 roundings of
-    log P (u = 6e-8), i.e. ~1e-5 relative for K = 20, and E_loc sums such
-    terms with some cancellation.  Stated bound: p99 of the relative error
-    <= 5e-5, max <= 2e-4 (measured p50 ~5e-7, p99 ~1.2e-5)."""
-    w, got, ref, st = _eloc_pair(nqs, ctx, "c2", 128, "f32")
+    """FP32 bond contractions (FP64 Hamiltonian elements, ratios and sums)
+    within the stated per-sample bound (tests/bounds.py; derivation in
+    test_gpu_precision_bounds.py) on 128 samples, and log|Psi| within
+    L = 8 K 2^-24."""
+    w, got, ref, st = _eloc_pair(nqs, ctx, "c2", 128, "f32", with_bounds=True)
+    dE = np.abs(got["eloc"] - ref["eloc"])
     e = rel_err(got["eloc"], ref["eloc"])
     print("f32 c2 rel err p50 %.2e p99 %.2e max %.2e" % (np.median(e), np.quantile(e, 0.99), e.max()))
-    assert np.quantile(e, 0.99) <= 5e-5 and e.max() <= 2e-4
-    la = got["logabs"]
-    assert np.abs(la - ref["logabs"]).max() < 2e-5
+    assert np.all(dE <= stated_bound("f32", ref))
+    assert np.abs(got["logabs"] - ref["logabs"]).max() <= log_bound("f32", w.K)
 
 
 def test_counts_weight_batch_sums(nqs, ctx):
@@ -233,46 +234,41 @@ def test_full_size_bench_config_sampled(nqs, ctx):
     32 sampled local energies checked one by one against the oracle, and
     properties of all 4096 (finite, sign of Psi(n) nonzero, row counts)."""
     w, inst, ans = setup(nqs, ctx, "c2")
-    for prec, tol in (("f64", 1e-10), ("f32", 1e-4)):
+    pick = np.random.default_rng(0).choice(w.n_samples, 32, replace=False)
+    # the draw counter uses the sample's position in the batch: pass it through sample_base
+    refs = [oracle.eloc(w.K, w.n_alpha, w.n_beta, w.h, w.eri, w.chi, w.parent_ptr, w.parent_idx, w.n_hidden,
+                        w.params, w.samples[k:k + 1], eps=w.eps, n_eps=w.n_eps, seed=w.seed, stream=1,
+                        sample_base=int(k), bounds=bounds(w.K), u_f=U_F) for k in pick]
+    for prec in ("f64", "f32"):
         out, st = nqs.eloc(ctx, inst, ans, w.samples, eps=w.eps, n_eps=w.n_eps, precision=prec,
                            seed=w.seed, stream_id=1)
         el = out["eloc"].cpu().numpy()
         assert np.isfinite(el).all() and np.all(out["sign"].cpu().numpy() != 0)
-        pick = np.random.default_rng(0).choice(w.n_samples, 32, replace=False)
-        # the draw counter uses the sample's position in the batch: pass it through sample_base
-        for k in pick:
-            ref = oracle.eloc(w.K, w.n_alpha, w.n_beta, w.h, w.eri, w.chi, w.parent_ptr, w.parent_idx,
-                              w.n_hidden, w.params, w.samples[k:k + 1], eps=w.eps, n_eps=w.n_eps,
-                              seed=w.seed, stream=1, sample_base=int(k))
-            assert rel_err(np.array([el[k]]), ref["eloc"])[0] <= tol or \
-                abs(el[k] - ref["eloc"][0]) <= tol * max(abs(ref["eloc"][0]), 1e-3 * np.sqrt(np.mean(el ** 2)))
+        for k, ref in zip(pick, refs):
+            if prec == "f64":
+                assert abs(el[k] - ref["eloc"][0]) <= 1e-10 * max(abs(ref["eloc"][0]),
+                                                                  1e-3 * np.sqrt(np.mean(el ** 2)))
+            else:
+                assert abs(el[k] - ref["eloc"][0]) <= stated_bound("f32", ref)[0]
         assert st["n_rows"] > w.n_samples
 
 
 @pytest.mark.parametrize("name,n", [("c2", 256), ("c3", 48)])
 def test_eloc_bf16_bound(nqs, ctx, name, n):
     """BF16 operands on MFMA (FP32 accumulate, per-row power-of-two scaled hidden
-    states; FP64 Hamiltonian elements, ratios and sums).  BF16 keeps 8
-    significant bits (u = 2^-9), so every site perturbs log P by O(u) and
-    log|Psi| carries ~sqrt(K) u: stated bound median |d log|Psi|| <= 1e-2,
-    p99 <= 5e-2.  Per-sample local energies inherit the cancellation of the
-    random-initialised ansatz (FP32 shows a ~200x amplification of its unit
-    roundoff), so they are reported, not bounded; the batch energy
-    <E> = sum Etilde / sum |f|^2 must stay within one sampling standard error
-    of the oracle's, the standard error of the |f|^2-weighted mean being
-    sqrt(sum w^2 (E_loc - E)^2) / sum w (sqrt(var / N) for equal weights; the
-    random-initialised cos-RBM of c3 spreads |f|^2 over many decades, so few
-    samples carry the mean; measured: 0.82 SE on c2, 0.17 SE on c3)."""
-    w, got, ref, st = _eloc_pair(nqs, ctx, name, n, "bf16")
-    e = rel_err(got["eloc"], ref["eloc"])
+    states; FP64 Hamiltonian elements, ratios and sums) within the stated
+    per-sample bound (tests/bounds.py).  The bound is wide: with 8
+    significant bits about 2 % of the rows of these random-initialised
+    ansatze change sign (their sign margins are below kappa), and that term
+    dominates it."""
+    w, got, ref, st = _eloc_pair(nqs, ctx, name, n, "bf16", with_bounds=True)
+    assert np.all(ref["margin_f"] >= KAPPA_F)
+    dE = np.abs(got["eloc"] - ref["eloc"])
+    bound = stated_bound("bf16", ref)
     dl = np.abs(got["logabs"] - ref["logabs"])
-    E_ref = ref["etnum"].sum() / ref["fsq"].sum()
-    se = np.sqrt((ref["fsq"] ** 2 * (ref["eloc"] - E_ref) ** 2).sum()) / ref["fsq"].sum()
-    dE = abs(st["E"] - E_ref)
-    print("bf16 %s E_loc rel err p50 %.2e p99 %.2e | logabs err p50 %.2e p99 %.2e | dE/SE %.3f"
-          % (name, np.median(e), np.quantile(e, 0.99), np.median(dl), np.quantile(dl, 0.99), dE / se))
-    assert np.median(dl) <= 1e-2 and np.quantile(dl, 0.99) <= 5e-2
-    assert dE <= 1.0 * se
+    print("bf16 %s |dE|/bound max %.3f | logabs err p50 %.2e max %.2e"
+          % (name, (dE / bound).max(), np.median(dl), dl.max()))
+    assert np.all(dE <= bound)
 
 
 @pytest.mark.parametrize("name,n", [("c1", None), ("c4b", 32)])

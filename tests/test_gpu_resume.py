@@ -54,7 +54,7 @@ def first_changed_sites(m, s, K):
     return out
 
 
-@pytest.mark.parametrize("prec", ["f64", "f32", "bf16"])
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16", "bf16x3"])
 @pytest.mark.parametrize("name,n", [("c1", None), ("c2", 200), ("c3", 24), ("c4a", 24), ("c4b", 40)])
 def test_resume_bit_identical(nqs, ctx, name, n, prec):
     w, inst, ans = setup(nqs, ctx, name, n)
@@ -68,7 +68,7 @@ def test_resume_bit_identical(nqs, ctx, name, n, prec):
     assert st_res["n_site_rows"] < st_full["n_site_rows"]
 
 
-@pytest.mark.parametrize("prec", ["f64", "f32", "bf16"])
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16", "bf16x3"])
 def test_resume_with_passes(nqs, ctx, prec):
     """Several passes: each pass sorts its own rows; results are unchanged."""
     w, inst, ans = setup(nqs, ctx, "c2", 200)

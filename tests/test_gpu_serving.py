@@ -1,10 +1,14 @@
 """Serving form: continuous batching of local-energy requests from several
-resident instances; each result is the same alone and in the mix, admission
-never exceeds the device-memory budget, failures stay contained."""
+resident instances; each result is the same alone and in the mix, served
+results match the FP64 oracle (FP64 at its bar, FP32 and BF16 within the
+stated per-sample bound), admission never exceeds the device-memory budget,
+failures stay contained."""
 import numpy as np
 import pytest
 import torch
 
+import oracle
+from bounds import U_F, bounds, stated_bound
 from paper_2507_19276_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
@@ -20,7 +24,8 @@ def nqs():
 @pytest.fixture(scope="module")
 def env(nqs):
     ctx = nqs.Context(0)
-    specs = [s for s in W.serving_instances() if (s["K"], s["chi"]) in ((12, 16), (20, 32), (36, 16), (50, 64))]
+    specs = [s for s in W.serving_instances()
+             if (s["K"], s["chi"]) in ((12, 16), (20, 32), (36, 16), (50, 64), (36, 64))]
     objs = []
     for s in specs:
         inst = nqs.Instance(ctx, s["K"], s["n_alpha"], s["n_beta"], s["h"], s["eri"])
@@ -151,3 +156,86 @@ def test_passes_and_footprint_bound(nqs, env, prec):
     assert peak <= bound, (peak, bound)
     for name in ("eloc", "etnum", "logabs", "sign", "fsq"):
         assert np.array_equal(one[name].cpu().numpy(), many[name].cpu().numpy()), name
+
+
+def _serve_all(nqs, ctx, objs, reqs, n_slots=4, budget=8 << 30, max_rows=200_000):
+    srv = nqs.Server(ctx, n_slots=n_slots, budget_bytes=budget, max_rows_per_pass=max_rows)
+    tickets = {}
+    for k, r in enumerate(reqs):
+        s, inst, ans = r["obj"] if "obj" in r else objs[r["i"]]
+        t = srv.submit(inst, ans, r["samples"], eps=1e-2, n_eps=100, precision=r["prec"], seed=r["seed"], tag=k)
+        tickets[t] = k
+    got = {}
+    while len(got) < len(reqs):
+        c = srv.wait(180.0)
+        assert c is not None, "timed out waiting for a completion"
+        got[tickets[c["ticket"]]] = c
+    info = srv.info()
+    srv.close()
+    return got, info
+
+
+def test_served_results_match_oracle(nqs, env):
+    """Requests of every precision over the K = 12, 20, 36 and 50 instances,
+    BF16 at chi = 64 on K = 36 and K = 50 among them, served concurrently; the
+    first samples of each request against the oracle with the request's own
+    draws (request-local draw counters)."""
+    ctx, objs = env
+    pick = {(s["K"], s["chi"]): i for i, (s, _, _) in enumerate(objs)}
+    plan = [((12, 16), "f64", 300), ((20, 32), "f32", 200), ((36, 64), "bf16", 120), ((50, 64), "bf16", 64),
+            ((36, 64), "f32", 90), ((50, 64), "f64", 48), ((12, 16), "bf16", 400), ((20, 32), "f64", 150)]
+    reqs = []
+    for k, (key, prec, n) in enumerate(plan):
+        s, _, _ = objs[pick[key]]
+        smp = W.random_onvs(s["K"], s["n_alpha"], s["n_beta"], n, 7000 + k)
+        reqs.append(dict(i=pick[key], samples=torch.from_numpy(smp.view(np.int64)).cuda(), smp=smp,
+                         seed=3000 + k, prec=prec))
+    got, info = _serve_all(nqs, ctx, objs, reqs)
+    assert info["peak_in_flight"] >= 2
+    for k, r in enumerate(reqs):
+        c = got[k]
+        assert c["status"] == 0, c["message"]
+        s, _, _ = objs[r["i"]]
+        nb = 3 if s["K"] >= 36 else 6
+        ref = oracle.eloc(s["K"], s["n_alpha"], s["n_beta"], s["h"], s["eri"], s["chi"], s["parent_ptr"],
+                          s["parent_idx"], 0, s["params"], r["smp"][:nb], eps=1e-2, n_eps=100, seed=r["seed"],
+                          stream=0, bounds=bounds(s["K"]), u_f=U_F)
+        el = c["out"]["eloc"].cpu().numpy()[:nb]
+        dE = np.abs(el - ref["eloc"])
+        if r["prec"] == "f64":
+            tau = 1e-3 * np.sqrt(np.mean(ref["eloc"] ** 2))
+            assert np.all(dE <= 1e-10 * np.maximum(np.abs(ref["eloc"]), tau)), (k, dE)
+        else:
+            bound = stated_bound(r["prec"], ref)
+            print(f"request {k} K={s['K']} chi={s['chi']} {r['prec']}: |dE|/bound {(dE / bound).max():.3e}")
+            assert np.all(dE <= bound), (k, dE, bound)
+
+
+def test_unsupported_request_in_the_mix(nqs, env):
+    """A BF16 request on a tensor-RNN ansatz (not supported in BF16) fails
+    alone with EUNSUPPORTED before queuing any work; the valid requests served
+    around it are bit-identical to running them alone."""
+    ctx, objs = env
+    s0, inst0, _ = objs[0]
+    tens = nqs.Ansatz(ctx, s0["K"], s0["n_alpha"], s0["n_beta"], 16, s0["parent_ptr"], s0["parent_idx"], 0,
+                      tensor=True)
+    tens.bind(W.ansatz_params(s0["K"], 16, s0["parent_ptr"], s0["parent_idx"], 0, 99, tensor=True))
+    reqs = _requests(objs, 8, 4)
+    bad = W.random_onvs(s0["K"], s0["n_alpha"], s0["n_beta"], 500, 77)
+    reqs.insert(3, dict(obj=(s0, inst0, tens), samples=torch.from_numpy(bad.view(np.int64)).cuda(), seed=5,
+                        prec="bf16"))
+    alone = {}
+    for k, r in enumerate(reqs):
+        if "obj" in r:
+            continue
+        s, inst, ans = objs[r["i"]]
+        out, _ = nqs.eloc(ctx, inst, ans, r["samples"], eps=1e-2, n_eps=100, precision=r["prec"], seed=r["seed"],
+                          max_rows_per_pass=200_000)
+        alone[k] = {n: v.clone() for n, v in out.items()}
+    got, _ = _serve_all(nqs, ctx, objs, reqs)
+    assert got[3]["status"] == nqs.NQS_EUNSUPPORTED
+    for k, a in alone.items():
+        assert got[k]["status"] == 0, got[k]["message"]
+        for name in ("eloc", "etnum", "logabs", "sign", "fsq"):
+            assert np.array_equal(a[name].cpu().numpy(), got[k]["out"][name].cpu().numpy(), equal_nan=True), (k, name)
+    tens.close()
