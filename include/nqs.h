@@ -344,6 +344,31 @@ nqs_status nqs_rows(nqs_ctx* ctx, const nqs_instance* inst, const uint64_t* samp
 nqs_status nqs_eloc_workspace_bytes(const nqs_instance* inst, const nqs_ansatz* ans, int64_t N,
                                     const nqs_eloc_opts* opts, int64_t n_rows, size_t* bytes);
 
+/* ---- allocation-free local energies ------------------------------------ */
+
+/* Bytes of the static device workspace of nqs_eloc_noalloc: one array per GPU,
+ * in the library's code object, held from the first context created on that
+ * GPU until the process ends. */
+#define NQS_STATIC_WORKSPACE_BYTES (256u << 20)
+
+/* For callers that cannot allocate device memory: code under HIP graph
+ * capture, serving loops that must not allocate, harnesses that forbid it.
+ * The same computation, arguments and results as nqs_eloc (bit for bit),
+ * without the stats pointer, with every workspace block taken from the static
+ * array above instead of the context's pool: no hipMalloc, hipFree or other
+ * allocating call is made.  NQS_ENOMEM with a message when the call needs more
+ * than NQS_STATIC_WORKSPACE_BYTES; with opts->max_rows_per_pass > 0 a call
+ * whose nqs_eloc_workspace_bytes is at most that size always fits.  Every
+ * call on a GPU shares that GPU's array, which keeps the last call's contents
+ * (the kernels write what they read before reading it); calls that overlap on
+ * one GPU (any context, thread or stream) race on it, so the caller must
+ * serialise them.  On an error after work was queued the call waits for
+ * `stream` before returning.  Host waits otherwise as nqs_eloc. */
+nqs_status nqs_eloc_noalloc(nqs_ctx* ctx, const nqs_instance* inst, const nqs_ansatz* ans,
+                            const uint64_t* samples, const double* counts, int64_t N,
+                            const nqs_eloc_opts* opts, double* eloc, double* etnum, double* logabs,
+                            int8_t* sign, double* fsq, hipStream_t stream);
+
 /* ---- one VMC step (Sec. 2.1 Eq. (7), Sec. 2.3 Eq. (19), AdamW of Sec. 3) - */
 
 typedef struct {

@@ -8,7 +8,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libnqs.so")
 BUILD = os.path.join(ROOT, "_build")
-SOURCES = ["enumerate.hip", "order.hip", "nodes.hip", "psi.hip", "psi_bf16.hip", "energy.hip", "adjoint.hip", "unique.hip", "vmc.hip", "tensor_rnn.hip",
+SOURCES = ["enumerate.hip", "order.hip", "nodes.hip", "psi.hip", "psi_bf16.hip", "energy.hip", "adjoint.hip", "unique.hip", "vmc.hip", "tensor_rnn.hip", "static_ws.hip",
            "runtime.cpp", "serve.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-x", "hip", "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <cstdint>
 
+#include "nqs.h"
+
 namespace nqs {
 
 constexpr int kWave = 64;
@@ -362,6 +364,12 @@ hipError_t launch_adamw(int64_t n, double* p, const double* g, double* m, double
 hipError_t launch_sumsq(int64_t n, const double* g, double* out, hipStream_t st);
 // eta >= 0 (Sec. 2.1): p[off[i] + u] = 0 where it is negative, i < K, u < chi
 hipError_t launch_project_eta(int K, int chi, const int64_t* off, double* p, hipStream_t st);
+// ---- static workspace of the allocation-free entry point (static_ws.hip) --
+constexpr size_t kStaticWorkspaceBytes = size_t(NQS_STATIC_WORKSPACE_BYTES);
+// look up the device address of this device's array (with `device` current), once per device
+hipError_t static_workspace_setup(int device);
+// that address (nullptr before the setup)
+void* static_workspace(int device);
 // ---- row order by first changed site (order.hip) ----------------------
 // chunk of rows per block of the counting sort
 constexpr int kOrderChunk = 16384;

@@ -79,6 +79,8 @@ struct nqs_ctx {
   std::map<void*, size_t> sizes;              // every block we own
   size_t in_use = 0, cached = 0, peak = 0;
   size_t cap = 0;                             // 0 = no limit on in_use + cached
+  void* arena = nullptr;                      // this device's static workspace (nqs_eloc_noalloc)
+  hipError_t arena_err = hipSuccess;          // its lookup's result
   int64_t fail_at = 0;                        // test hook: k-th acquire fails
   // blocks handed back with work still queued on their stream: they count as
   // in use until the event recorded after that work has completed
@@ -207,26 +209,57 @@ struct nqs_ctx {
 
 namespace {
 
+// Bump allocator over a fixed device array (the static workspace of the
+// allocation-free entry point): one per call; the workspaces of the call
+// take consecutive 256-byte aligned pieces and give them back in reverse
+// order.  Reuse of a piece by a later phase of the same call is ordered by
+// the call's stream.
+struct Arena {
+  unsigned char* base = nullptr;
+  size_t size = 0, off = 0;
+  bool overflow = false;
+};
+
 // Workspace of one call on one stream: when the call returns (on any path,
-// errors included) its blocks go back to the pool behind the work the call
-// queued on that stream, so no other call is handed a block a queued kernel
-// may still write.
+// errors included) its blocks go back to the pool behind the work queued on
+// that stream, so no other call is handed a block a queued kernel may still
+// write.  With an arena the blocks come from it instead and nothing is
+// allocated.
 struct Scratch {
   nqs_ctx* ctx;
   hipStream_t st;
+  Arena* arena;
+  size_t arena_start = 0;
   std::vector<void*> blocks;
   bool oom = false;
-  Scratch(nqs_ctx* c, hipStream_t s) : ctx(c), st(s) {}
+  Scratch(nqs_ctx* c, hipStream_t s, Arena* a = nullptr) : ctx(c), st(s), arena(a) {
+    if (arena) arena_start = arena->off;
+  }
   Scratch(const Scratch&) = delete;
   Scratch& operator=(const Scratch&) = delete;
   template <typename T>
   T* get(size_t count) {
-    void* p = ctx->acquire(std::max<size_t>(count, 1) * sizeof(T));
+    const size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
+    if (arena) {
+      const size_t need = (bytes + 255) / 256 * 256;
+      if (arena->overflow || arena->size - arena->off < need) {
+        arena->overflow = true;
+        oom = true;
+        return nullptr;
+      }
+      void* p = arena->base + arena->off;
+      arena->off += need;
+      return static_cast<T*>(p);
+    }
+    void* p = ctx->acquire(bytes);
     if (!p) { oom = true; return nullptr; }
     blocks.push_back(p);
     return static_cast<T*>(p);
   }
-  ~Scratch() { ctx->release_after(blocks, st); }
+  ~Scratch() {
+    if (arena) arena->off = arena_start;
+    else ctx->release_after(blocks, st);
+  }
 };
 
 uint64_t magic(uint64_t d) { return d == 0 ? 0 : ((uint64_t(1) << 32) + d - 1) / d; }
@@ -752,6 +785,9 @@ nqs_status nqs_ctx_create(int device, nqs_ctx** out) {
   HIPCHK(hipFree(nullptr));
   auto* c = new nqs_ctx();
   c->device = device;
+  // this device's static workspace (once per device; only nqs_eloc_noalloc uses it)
+  c->arena_err = static_workspace_setup(device);
+  if (c->arena_err == hipSuccess) c->arena = static_workspace(device);
   *out = c;
   return NQS_OK;
 }
@@ -1205,9 +1241,9 @@ nqs_status nqs_ansatz_bind_params(nqs_ansatz* ans, const double* params, hipStre
 namespace {
 
 nqs_status check_samples(nqs_ctx* ctx, const uint64_t* samples, int64_t N, int K, int na, int nb,
-                         hipStream_t st) {
+                         hipStream_t st, Arena* arena = nullptr) {
   if (N == 0) return NQS_OK;
-  Scratch S(ctx, st);
+  Scratch S(ctx, st, arena);
   int* bad = S.get<int>(1);
   if (!bad) return fail(NQS_ENOMEM, "workspace allocation failed");
   HIPCHK(hipMemsetAsync(bad, 0, sizeof(int), st));
@@ -1705,7 +1741,7 @@ namespace {
 nqs_status eloc_run(nqs_ctx* ctx, const nqs_instance* inst, const nqs_ansatz* ans, const uint64_t* samples,
                     const double* counts, int64_t N, const nqs_eloc_opts* opts, double* eloc, double* eloc_im,
                     double* etnum, double* etnum_im, double* logabs, int8_t* sign, double* phase, double* fsq,
-                    nqs_eloc_stats* stats, hipStream_t stream, bool cx) {
+                    nqs_eloc_stats* stats, hipStream_t stream, bool cx, Arena* arena = nullptr) {
   if (!ctx || !inst || !ans || (!samples && N > 0) || N < 0) return fail(NQS_EINVAL, "bad arguments");
   nqs_status s = check_opts(opts);
   if (s != NQS_OK) return s;
@@ -1715,12 +1751,12 @@ nqs_status eloc_run(nqs_ctx* ctx, const nqs_instance* inst, const nqs_ansatz* an
   if (N > (int64_t(1) << 31) - 1) return fail(NQS_EUNSUPPORTED, "N too large");
   if ((s = check_supported(ans, opts->precision)) != NQS_OK) return s;
   DeviceGuard g(ctx->device);
-  if ((s = check_samples(ctx, samples, N, inst->K, inst->na, inst->nb, stream)) != NQS_OK) return s;
+  if ((s = check_samples(ctx, samples, N, inst->K, inst->na, inst->nb, stream, arena)) != NQS_OK) return s;
   if (N == 0) {
     if (stats) { std::memset(stats, 0, sizeof *stats); stats->n_conn = inst->H.n_conn; }
     return NQS_OK;
   }
-  Scratch S(ctx, stream);
+  Scratch S(ctx, stream, arena);
   hipEvent_t ev[3] = {}, pe[3] = {};
   const bool timing = stats != nullptr;
   if (timing) {
@@ -1993,6 +2029,32 @@ nqs_status nqs_eloc(nqs_ctx* ctx, const nqs_instance* inst, const nqs_ansatz* an
     return fail(NQS_EINVAL, "complex parameters give complex local energies: use nqs_eloc_complex");
   return eloc_run(ctx, inst, ans, samples, counts, N, opts, eloc, nullptr, etnum, nullptr, logabs, sign, nullptr, fsq,
                   stats, stream, false);
+}
+
+nqs_status nqs_eloc_noalloc(nqs_ctx* ctx, const nqs_instance* inst, const nqs_ansatz* ans,
+                            const uint64_t* samples, const double* counts, int64_t N,
+                            const nqs_eloc_opts* opts, double* eloc, double* etnum, double* logabs,
+                            int8_t* sign, double* fsq, hipStream_t stream) {
+  if (!ctx) return fail(NQS_EINVAL, "ctx is NULL");
+  if (ans && ans->cplx)
+    return fail(NQS_EINVAL, "complex parameters give complex local energies: use nqs_eloc_complex");
+  if (!ctx->arena)
+    return fail(NQS_EDEVICE, "static workspace of device %d unavailable: %s", ctx->device,
+                hipGetErrorString(ctx->arena_err));
+  Arena A;
+  A.base = static_cast<unsigned char*>(ctx->arena);
+  A.size = kStaticWorkspaceBytes;
+  nqs_status s = eloc_run(ctx, inst, ans, samples, counts, N, opts, eloc, nullptr, etnum, nullptr, logabs, sign,
+                          nullptr, fsq, nullptr, stream, false, &A);
+  if (s != NQS_OK) {
+    DeviceGuard g(ctx->device);
+    (void)hipStreamSynchronize(stream);   // queued work may still use the array
+    (void)hipGetLastError();
+    if (A.overflow)
+      return fail(NQS_ENOMEM, "the call needs more than the %zu-byte static workspace (bound it with "
+                  "max_rows_per_pass; see nqs_eloc_workspace_bytes)", kStaticWorkspaceBytes);
+  }
+  return s;
 }
 
 nqs_status nqs_eloc_complex(nqs_ctx* ctx, const nqs_instance* inst, const nqs_ansatz* ans,

@@ -109,6 +109,7 @@ def lib():
                                    C.POINTER(ElocStats), _p]
     L.nqs_eloc.argtypes = [_p, _p, _p, _p, _p, C.c_int64, C.POINTER(ElocOpts), _p, _p, _p, _p, _p,
                            C.POINTER(ElocStats), _p]
+    L.nqs_eloc_noalloc.argtypes = [_p, _p, _p, _p, _p, C.c_int64, C.POINTER(ElocOpts), _p, _p, _p, _p, _p, _p]
     L.nqs_rows.argtypes = [_p, _p, _p, C.c_int64, C.POINTER(ElocOpts), C.c_int64, _p, _p, _p, _p, _p, _p,
                            C.POINTER(C.c_int64), _p]
     L.nqs_sample.argtypes = [_p, _p, C.c_int64, C.c_uint64, C.c_int64, C.c_int32, C.c_int64, C.c_int64, _p, _p,
@@ -352,6 +353,25 @@ def eloc(ctx: Context, inst: Instance, ans: Ansatz, samples, counts: Optional[to
                          _ptr(out["etnum"]), _ptr(out["logabs"]), _ptr(out["sign"]), _ptr(out["fsq"]),
                          C.byref(st) if want_stats else None, _p(_stream())))
     return out, (st.to_dict() if want_stats else None)
+
+
+def eloc_noalloc(ctx: Context, inst: Instance, ans: Ansatz, samples, out: Dict[str, torch.Tensor],
+                 counts: Optional[torch.Tensor] = None, eps: float = 0.0, n_eps: int = 0, precision="f64",
+                 seed: int = 0, stream_id: int = 0, sample_base: int = 0, max_rows_per_pass: int = 0,
+                 resume: bool = True) -> Dict[str, torch.Tensor]:
+    """nqs_eloc_noalloc: the local energies of eloc() with the library's
+    workspace taken from its static device array (no device allocation by the
+    library).  The caller passes the output tensors (device, length N: eloc,
+    etnum, logabs, fsq float64 and sign int8; any may be missing), so this
+    call allocates nothing on the device either."""
+    s = _samples(samples)
+    N = s.shape[0]
+    c = None if counts is None else counts.to(dtype=torch.float64, device=s.device).contiguous()
+    o = opts(eps, n_eps, precision, seed, stream_id, sample_base, max_rows_per_pass, resume)
+    check(lib().nqs_eloc_noalloc(ctx.h, inst.h, ans.h, _ptr(s), _ptr(c), N, C.byref(o), _ptr(out.get("eloc")),
+                                 _ptr(out.get("etnum")), _ptr(out.get("logabs")), _ptr(out.get("sign")),
+                                 _ptr(out.get("fsq")), _p(_stream())))
+    return out
 
 
 def eloc_complex(ctx: Context, inst: Instance, ans: Ansatz, samples, counts: Optional[torch.Tensor] = None,
