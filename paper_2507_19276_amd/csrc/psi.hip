@@ -42,8 +42,14 @@ namespace {
 // samples' pass that stores states, and the resumed row pass).  CPLX: phs
 // receives arg prod_i z_i per row; the stored and resumed prefix states carry
 // the product of the phase factors so far (pz, npz).
-template <typename T> constexpr int prefetch_ksteps(int CH) {
-  return (CH / 4) < 64 / ((CH / 4) * int(sizeof(T) / 4)) ? (CH / 4) : 64 / ((CH / 4) * int(sizeof(T) / 4));
+// k-steps of the next edge's A operands fetched ahead: all of them while they
+// fit a register budget (64 registers; 128 for the plain FP64 forward, whose
+// operands take two); a k-step fetched later is waited for alone, and at one
+// wavefront per SIMD nothing else hides that wait.  The tensor-term, complex
+// and sampling forms keep 64: their own registers would spill.
+template <typename T> constexpr int prefetch_ksteps(int CH, bool lean) {
+  const int budget = sizeof(T) == 8 && !lean ? 128 : 64;
+  return (CH / 4) < budget / ((CH / 4) * int(sizeof(T) / 4)) ? (CH / 4) : budget / ((CH / 4) * int(sizeof(T) / 4));
 }
 
 template <typename T, int CH, int NTL, bool FOLD, int STORE, bool SEED, bool SAMPLE, bool CPLX, bool TN, bool D1>
@@ -59,7 +65,7 @@ __global__ __launch_bounds__(256) void k_psi_mt(PsiParams<T> P, const uint64_t* 
   extern __shared__ __align__(16) unsigned char smem[];
   typedef typename V4<T>::type V;
   constexpr int TPC = CH / 16, NT = 4 * TPC, KS = CH / 4, RW = 16 * NTL;
-  constexpr int PQ = prefetch_ksteps<T>(CH);
+  constexpr int PQ = prefetch_ksteps<T>(CH, TN || CPLX || SAMPLE);
   constexpr int ES = KS * NT * 64;              // A values per edge
   constexpr int SLOT = NTL * TPC * 64;          // V entries per ring slot
   // the wavefront index is uniform: keep it (and all that derives from it:
@@ -264,9 +270,13 @@ __global__ __launch_bounds__(256) void k_psi_mt(PsiParams<T> P, const uint64_t* 
     // (D1: every site has exactly one edge, whose first MFMAs start from the
     // bias registers instead of copies of them in the accumulators)
     auto edge = [&](V (&pt)[NTL], auto first) {
-      const T* Ae = Ab + size_t(e) * ES;
+      // the edge index is wave-uniform: in a scalar register its slot comes
+      // from a scalar load, so reading it does not wait for the vector loads
+      // in flight (the A operands prefetched for this edge and the next)
+      const int eu = __builtin_amdgcn_readfirstlane(e);
+      const T* Ae = Ab + size_t(eu) * ES;
       V b[NTL][TPC];
-      const V* rp = ring + size_t(slots[e]) * SLOT;
+      const V* rp = ring + size_t(slots[eu]) * SLOT;
 #pragma unroll
       for (int t = 0; t < NTL; ++t)
 #pragma unroll
