@@ -52,7 +52,9 @@ U_F = 2.0 ** -22
 # FETCH_SIZE / WRITE_SIZE counters (copy-calibrated) recorded in profiles/;
 # valid only for the kernel source they were taken on (first 16 hex digits of
 # the sha256 of psi.hip followed by device.h) and for that workload.
-MEASURED_TRAFFIC = {}
+MEASURED_TRAFFIC = {
+    ("c3", "f64"): {"sha16": "66195d1df5bef68d", "bytes_per_launch": 34.587e9 + 7.262e9},
+}
 KERNEL_SOURCES = ("psi.hip", "device.h")
 WORKLOAD_TEXT = {
     "c2": "chain K=20 10a+10b, BDG-RNN chain chi=16, 4096 distinct samples drawn from Phi^2, eps=1e-3, N_eps=64",
