@@ -33,8 +33,9 @@ namespace {
 //
 // The accumulators start from the bias v_i^s, so after the contractions
 // acc[t][s*TPC + tt] holds the candidates h_i^s for units 16 tt + 4 g + 0..3.
-// The A operands of the next edge are fetched before the current edge's
-// MFMAs, so their latency hides behind the contractions and the epilogue.
+// The A operands are fetched PQ k-steps ahead of their MFMAs (see
+// prefetch_ksteps), across edge and site boundaries, so their latency hides
+// behind the contractions and the epilogue.
 //
 // FOLD: the operands carry sigma = sqrt(eta) (A' = sigma_i M / sigma_j,
 // v' = sigma v, w' = w / sigma, all eta > 0), so the ring holds sigma h and
@@ -42,14 +43,20 @@ namespace {
 // samples' pass that stores states, and the resumed row pass).  CPLX: phs
 // receives arg prod_i z_i per row; the stored and resumed prefix states carry
 // the product of the phase factors so far (pz, npz).
-// k-steps of the next edge's A operands fetched ahead: all of them while they
-// fit a register budget (64 registers; 128 for the plain FP64 forward, whose
-// operands take two); a k-step fetched later is waited for alone, and at one
-// wavefront per SIMD nothing else hides that wait.  The tensor-term, complex
-// and sampling forms keep 64: their own registers would spill.
+// A operands in flight: PQ k-steps of the A stream, the largest divisor of
+// the KS k-steps of an edge whose NT values per lane fit 128 registers (64 in
+// the tensor-term, complex and sampling forms, whose own registers would
+// spill otherwise).  The stream is read as a rolling window: k-step q takes
+// its values from slot q % PQ, which then receives k-step q + PQ (of this
+// edge, or of the next edge past the last k-step), so every load is issued PQ
+// k-steps before its MFMAs and no register copies are needed between edges.
+// At one wavefront per SIMD nothing else hides a load that is waited for.
 template <typename T> constexpr int prefetch_ksteps(int CH, bool lean) {
-  const int budget = sizeof(T) == 8 && !lean ? 128 : 64;
-  return (CH / 4) < budget / ((CH / 4) * int(sizeof(T) / 4)) ? (CH / 4) : budget / ((CH / 4) * int(sizeof(T) / 4));
+  const int ks = CH / 4, per = (CH / 4) * int(sizeof(T) / 4), budget = lean ? 64 : 128;
+  int pq = 1;
+  for (int d = 1; d <= ks; ++d)
+    if (ks % d == 0 && d * per <= budget) pq = d;
+  return pq;
 }
 
 template <typename T, int CH, int NTL, bool FOLD, int STORE, bool SEED, bool SAMPLE, bool CPLX, bool TN, bool D1>
@@ -66,6 +73,7 @@ __global__ __launch_bounds__(256) void k_psi_mt(PsiParams<T> P, const uint64_t* 
   typedef typename V4<T>::type V;
   constexpr int TPC = CH / 16, NT = 4 * TPC, KS = CH / 4, RW = 16 * NTL;
   constexpr int PQ = prefetch_ksteps<T>(CH, TN || CPLX || SAMPLE);
+  static_assert(KS % PQ == 0, "the A window slots repeat every PQ k-steps");
   constexpr int ES = KS * NT * 64;              // A values per edge
   constexpr int SLOT = NTL * TPC * 64;          // V entries per ring slot
   // the wavefront index is uniform: keep it (and all that derives from it:
@@ -281,25 +289,19 @@ __global__ __launch_bounds__(256) void k_psi_mt(PsiParams<T> P, const uint64_t* 
       for (int t = 0; t < NTL; ++t)
 #pragma unroll
         for (int tt = 0; tt < TPC; ++tt) b[t][tt] = rp[(t * TPC + tt) * 64];
-      // next edge (the A stream carries one zero edge past the last one)
-      T nx[PQ][NT];
-#pragma unroll
-      for (int q = 0; q < PQ; ++q)
-#pragma unroll
-        for (int ot = 0; ot < NT; ++ot) nx[q][ot] = Ae[ES + (q * NT + ot) * 64];
+      // rolling A window: slot q % PQ, once its MFMAs are issued, receives
+      // k-step q + PQ of the stream (past this edge's last k-step: the next
+      // edge's; the stream carries one zero edge past the last one)
 #pragma unroll
       for (int q = 0; q < KS; ++q)
 #pragma unroll
         for (int ot = 0; ot < NT; ++ot) {
-          const T a = q < PQ ? an[q < PQ ? q : 0][ot] : Ae[(q * NT + ot) * 64];
+          const T a = an[q % PQ][ot];
 #pragma unroll
           for (int t = 0; t < NTL; ++t)
             acc[t][ot] = mfma(a, b[t][q / 4][q % 4], decltype(first)::value && q == 0 ? vn[ot] : acc[t][ot]);
+          an[q % PQ][ot] = Ae[((q + PQ) * NT + ot) * 64];
         }
-#pragma unroll
-      for (int q = 0; q < PQ; ++q)
-#pragma unroll
-        for (int ot = 0; ot < NT; ++ot) an[q][ot] = nx[q][ot];
       if constexpr (TN) {
         if (tQ > 0) {
           // projection of this parent's state: one 16-row output tile whose
