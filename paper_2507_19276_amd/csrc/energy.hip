@@ -40,7 +40,11 @@ __device__ inline double tabs(double x) { return fabs(x); }
 __device__ inline float tabs(float x) { return fabsf(x); }
 
 // theta(m) = theta(n) + sum_{created P} W_:P - sum_{annihilated P} W_:P; one
-// thread per row; cos and log in precision T, the sum of logs in FP64.
+// thread per row.  FP32: cos and log per hidden unit in FP32, the sum of logs
+// in FP64 (the form the FP32 error bound is stated for).  FP64: the product of
+// the cosines with a power of two split off every 8 factors (|cos| of a
+// rounded angle stays far above 2^-128, so 8 factors cannot underflow), and
+// one log per row: log |prod_k cos| = log |mantissa| + exponent log 2.
 template <typename T>
 __global__ void k_corr_rows(CorrParams C, const uint64_t* m, const int32_t* owner,
                             const uint64_t* samples, const double* theta, int64_t R, double* lf,
@@ -63,14 +67,36 @@ __global__ void k_corr_rows(CorrParams C, const uint64_t* m, const int32_t* owne
   const double* th0 = theta + o * C.nh;
   double acc = 0.0;
   int s = 1;
-  for (int k = 0; k < C.nh; ++k) {
-    double th = th0[k];
-    const double* Wk = C.W + size_t(k) * nv;
-    for (int a = 0; a < na; ++a) th += Wk[add[a]];
-    for (int a = 0; a < nr; ++a) th -= Wk[rem[a]];
-    const T c = tcos(T(th));
-    acc += double(tlog(tabs(c)));
-    if (c < T(0)) s = -s;
+  if constexpr (sizeof(T) == 8) {
+    double pm = 1.0;
+    int pe = 0;
+    for (int k = 0; k < C.nh; ++k) {
+      double th = th0[k];
+      const double* Wk = C.W + size_t(k) * nv;
+      for (int a = 0; a < na; ++a) th += Wk[add[a]];
+      for (int a = 0; a < nr; ++a) th -= Wk[rem[a]];
+      pm *= cos(th);
+      if ((k & 7) == 7) {
+        int e;
+        pm = frexp(pm, &e);
+        pe += e;
+      }
+    }
+    int e;
+    pm = frexp(pm, &e);
+    pe += e;
+    acc = log(fabs(pm)) + double(pe) * 0.69314718055994530942;
+    s = pm < 0.0 ? -1 : 1;
+  } else {
+    for (int k = 0; k < C.nh; ++k) {
+      double th = th0[k];
+      const double* Wk = C.W + size_t(k) * nv;
+      for (int a = 0; a < na; ++a) th += Wk[add[a]];
+      for (int a = 0; a < nr; ++a) th -= Wk[rem[a]];
+      const T c = tcos(T(th));
+      acc += double(tlog(tabs(c)));
+      if (c < T(0)) s = -s;
+    }
   }
   lf[r] = acc;
   sf[r] = int8_t(s);

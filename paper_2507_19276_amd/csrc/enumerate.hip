@@ -118,8 +118,9 @@ __device__ bool decode_lists(const HamDev& H, uint64_t lo, uint64_t hi, Lists& L
   return __popcll(ma) == H.na && __popcll(mb) == H.nb && stray_lo == 0 && stray_hi == 0;
 }
 
-__device__ inline size_t eidx(int K, int p, int q, int r, int s) {
-  return ((size_t(p) * K + q) * K + r) * K + s;
+// (32-bit arithmetic: K <= 64, so K^4 < 2^32)
+__device__ inline uint32_t eidx(int K, int p, int q, int r, int s) {
+  return ((uint32_t(p) * K + q) * K + r) * K + s;
 }
 
 // S(i) = number of pairs (i', j') with i' < i in lexicographic order of i<j<n
@@ -155,6 +156,9 @@ __device__ inline int apply_double(uint64_t& lo, uint64_t& hi, int I, int J, int
 }
 
 // Matrix element H_mn and m for canonical rank r of the sample (lo, hi).
+// FULL = false: |H_mn| only (the screening and the proposal weights need no
+// sign and no m), in e.H.
+template <bool FULL = true>
 __device__ Elem element(const HamDev& H, const Lists& L, uint64_t lo, uint64_t hi, uint32_t r) {
   const int K = H.K;
   Elem e;
@@ -176,6 +180,10 @@ __device__ Elem element(const HamDev& H, const Lists& L, uint64_t lo, uint64_t h
       const double g1 = H.eri[eidx(K, a, i, j, j)];
       const double g2 = ((J & 1) == sg) ? H.eri[eidx(K, a, j, j, i)] : 0.0;
       acc += (g1 - g2);
+    }
+    if constexpr (!FULL) {
+      e.H = fabs(acc);
+      return e;
     }
     const int I = 2 * i + sg, A = 2 * a + sg;
     uint64_t ml = lo, mh = hi;
@@ -202,6 +210,10 @@ __device__ Elem element(const HamDev& H, const Lists& L, uint64_t lo, uint64_t h
     const int a = sg ? L.vb[aa] : L.va[aa];
     const int b = sg ? L.vb[bb] : L.va[bb];
     const double val = H.eri[eidx(K, i, a, j, b)] - H.eri[eidx(K, j, a, i, b)];
+    if constexpr (!FULL) {
+      e.H = fabs(val);
+      return e;
+    }
     uint64_t ml = lo, mh = hi;
     const int g = apply_double(ml, mh, 2 * i + sg, 2 * j + sg, 2 * a + sg, 2 * b + sg);
     e.H = g ? -val : val;
@@ -220,6 +232,10 @@ __device__ Elem element(const HamDev& H, const Lists& L, uint64_t lo, uint64_t h
   const uint32_t bb = sb - jj * uint32_t(H.vb);
   const int i = L.oa[ii], a = L.va[aa], j = L.ob[jj], b = L.vb[bb];
   double val = H.eri[eidx(K, i, a, j, b)];
+  if constexpr (!FULL) {
+    e.H = fabs(val);
+    return e;
+  }
   if ((i <= j) != (a <= b)) val = -val;
   const int Ia = 2 * i, Jb = 2 * j + 1, Aa = 2 * a, Bb = 2 * b + 1;
   uint64_t ml = lo, mh = hi;
@@ -297,7 +313,7 @@ __global__ __launch_bounds__(256) void k_enum_count(HamDev H, EnumGeom G, const 
   for (int c = c0; c < c1; ++c) {
     const uint32_t r = uint32_t(c) * 64u + uint32_t(lane);
     double hv = 0.0;
-    if (ok && r < H.n_conn) hv = element(H, L, lo, hi, r).H;
+    if (ok && r < H.n_conn) hv = element<false>(H, L, lo, hi, r).H;
     const double ah = fabs(hv);
     const bool det = hv != 0.0 && ah >= eps;
     const uint64_t q = (hv != 0.0 && !det) ? proposal_weight(ah, qshift) : 0ull;

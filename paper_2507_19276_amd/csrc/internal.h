@@ -48,9 +48,12 @@ struct DrawKeys {
 // a result.
 template <typename T>
 struct PsiParams {
-  int K, chi, chip, na, nb, W;   // W = ring slots = max parent offset + 1
+  int K, chi, chip, na, nb, W;   // W = LDS ring slots (the most carried states live at once)
   const int* pptr;               // [K+1] forward edges of site i: pptr[i]..pptr[i+1]-1 (never empty)
-  const int* slot;               // [edges] ring slot read by each edge (W for a parentless site's zero edge)
+  const int* slot;               // [edges] ring slot read by each edge (W: a parentless site's zero edge)
+  const int* wsl;                // [K] ring slot receiving site i's carried state
+  const uint64_t* live;          // [K+1] bit s: the state of site s < i is read by a site >= i (live[K] = 0:
+                                 // rows with no change below K, the samples' own rows among them, resume at K)
   const T* A;                    // [edges + 1][CH/4][CH/4][64] k-permuted MFMA A operands, see runtime.cpp
   const T* v;                    // [K][4][chip]
   const T* eta;                  // [K][chip]
@@ -152,9 +155,11 @@ struct CxMap {
 
 // BF16 forward (psi_bf16.hip): same edge tables as PsiParams; FP32 vectors.
 struct B16Params {
-  int K, chi, chip, na, nb, W;
+  int K, chi, chip, na, nb, W;   // W, slot, wsl, live: the ring as in PsiParams
   const int* pptr;               // [K+1] forward edges (never empty per site)
-  const int* slot;               // [edges] ring slot read by each edge (W: zero slot)
+  const int* slot;               // [edges] ring slot read by each edge (W: a parentless site's zero edge)
+  const int* wsl;                // [K]
+  const uint64_t* live;          // [K+1]
   const uint16_t* A;             // BF16 A stream, per forward edge + one zero edge (runtime.cpp)
   const uint16_t* Alo = nullptr; // the same stream's lo parts (split form)
   const float* v;                // [K][4][chip]

@@ -83,14 +83,14 @@ __global__ __launch_bounds__(256) void k_psi_mt(PsiParams<T> P, const uint64_t* 
   const int own = NTL == 4 ? g : (NTL == 2 ? (g >> 1) : 0);
   const int64_t base = (int64_t(blockIdx.x) * wpb + wv) * RW;
   if (base >= R) return;   // surplus wavefront of the last block (no block barrier below)
-  // ring: slots 0..W-1 carry states, slot W stays zero (read by the zero edges);
-  // entry ((slot * NTL + t) * TPC + tt) * 64 + lane belongs to this lane only
-  V* ring = reinterpret_cast<V*>(smem) + size_t(wv) * (P.W + 1) * SLOT + lane;
-#pragma unroll
-  for (int k = 0; k < NTL * TPC; ++k) ring[(P.W * NTL * TPC + k) * 64] = V{0, 0, 0, 0};
+  // ring: W slots of carried states (site i writes slot wsl[i]; a zero edge,
+  // slot index W, reads no slot); entry ((slot * NTL + t) * TPC + tt) * 64 +
+  // lane belongs to this lane only
+  V* ring = reinterpret_cast<V*>(smem) + size_t(wv) * P.W * SLOT + lane;
   // edge tables and c are uniform and read-only: scalar loads
   const CInt* fptr = (const CInt*)(P.pptr);
   const CInt* slots = (const CInt*)(P.slot);
+  const CInt* wsl = (const CInt*)(P.wsl);
   const CT<T>* cc = (const CT<T>*)(P.c);
   const CT<T>* cc2 = (const CT<T>*)(P.c2);
   const CInt* tsite = (const CInt*)(P.tsite);
@@ -116,7 +116,7 @@ __global__ __launch_bounds__(256) void k_psi_mt(PsiParams<T> P, const uint64_t* 
     if (t == own) orow = rowt[t];
   T prod = T(1);
   T zr = T(1), zi = T(0);   // CPLX: product of the phase factors, rescaled by powers of two
-  int pexp = 0, sgn = 1, ca = 0, cb = 0, wslot = 0, e = 0;
+  int pexp = 0, sgn = 1, ca = 0, cb = 0, e = 0;
   bool bad = false;
   if (SEED && i0 > 0) {
     // carried states of the parents of sites >= i0 and the log-product state
@@ -125,7 +125,6 @@ __global__ __launch_bounds__(256) void k_psi_mt(PsiParams<T> P, const uint64_t* 
     // With a node level (X.unode), a row's node covers the sites from its
     // changed site nc1 on: the node agrees with the row below the row's
     // resume site, the sample below nc1.
-    const int s0 = i0 - P.W + 1 > 0 ? i0 - P.W + 1 : 0;
     int nd[NTL], nb[NTL];
     int64_t no[NTL];
 #pragma unroll
@@ -134,8 +133,10 @@ __global__ __launch_bounds__(256) void k_psi_mt(PsiParams<T> P, const uint64_t* 
       nb[t] = nd[t] >= 0 ? int(X.nc1[nd[t]]) : P.K + 1;
       no[t] = nd[t] >= 0 ? X.noff[nd[t]] : 0;
     }
-    for (int s = s0; s < i0; ++s) {
-      V* wr = ring + size_t(s % P.W) * SLOT;
+    // the states live at i0 (read by a site >= i0; distinct slots)
+    for (uint64_t lv = ((const __attribute__((address_space(4))) uint64_t*)P.live)[i0]; lv; lv &= lv - 1) {
+      const int s = __builtin_ctzll(lv);
+      V* wr = ring + size_t(wsl[s]) * SLOT;
 #pragma unroll
       for (int t = 0; t < NTL; ++t) {
         const T* src = s >= nb[t] ? X.nhs + size_t(no[t] + (s - nb[t])) * CH + 4 * g
@@ -172,7 +173,6 @@ __global__ __launch_bounds__(256) void k_psi_mt(PsiParams<T> P, const uint64_t* 
     const uint64_t below = low_bits(2 * i0), belowh = low_bits(2 * i0 - 64);
     ca = __popcll(olo & below & 0x5555555555555555ull) + __popcll(ohi & belowh & 0x5555555555555555ull);
     cb = __popcll(olo & below & 0xAAAAAAAAAAAAAAAAull) + __popcll(ohi & belowh & 0xAAAAAAAAAAAAAAAAull);
-    wslot = i0 % P.W;
     e = fptr[i0];
   }
   const T* __restrict__ Ab = P.A + lane;
@@ -253,6 +253,7 @@ __global__ __launch_bounds__(256) void k_psi_mt(PsiParams<T> P, const uint64_t* 
   }
   for (int i = i0; i < iend; ++i) {
     store_pre(i);
+    const int wslot = wsl[i];
     V acc[NTL][NT], wv4[TPC], ev4[TPC], w2v4[TPC];
     // w and eta of this site are needed only after the contractions
 #pragma unroll
@@ -275,8 +276,8 @@ __global__ __launch_bounds__(256) void k_psi_mt(PsiParams<T> P, const uint64_t* 
     for (int t = 0; t < NTL; ++t) pr2[t] = V{0, 0, 0, 0};
     // one edge: a chi-wide slice of the contraction over the parents (TN: and
     // the projection of the parent's state into pt)
-    // (D1: every site has exactly one edge, whose first MFMAs start from the
-    // bias registers instead of copies of them in the accumulators)
+    // (first: the edge's first MFMAs start from the bias registers instead of
+    // copies of them in the accumulators)
     auto edge = [&](V (&pt)[NTL], auto first) {
       // the edge index is wave-uniform: in a scalar register its slot comes
       // from a scalar load, so reading it does not wait for the vector loads
@@ -284,11 +285,13 @@ __global__ __launch_bounds__(256) void k_psi_mt(PsiParams<T> P, const uint64_t* 
       const int eu = __builtin_amdgcn_readfirstlane(e);
       const T* Ae = Ab + size_t(eu) * ES;
       V b[NTL][TPC];
-      const V* rp = ring + size_t(slots[eu]) * SLOT;
+      const int sl = slots[eu];
+      const bool zero = sl >= P.W;   // a parentless site's zero edge: zero operand
+      const V* rp = ring + size_t(zero ? 0 : sl) * SLOT;
 #pragma unroll
       for (int t = 0; t < NTL; ++t)
 #pragma unroll
-        for (int tt = 0; tt < TPC; ++tt) b[t][tt] = rp[(t * TPC + tt) * 64];
+        for (int tt = 0; tt < TPC; ++tt) b[t][tt] = zero ? V{0, 0, 0, 0} : rp[(t * TPC + tt) * 64];
       // rolling A window: slot q % PQ, once its MFMAs are issued, receives
       // k-step q + PQ of the stream (past this edge's last k-step: the next
       // edge's; the stream carries one zero edge past the last one)
@@ -328,13 +331,13 @@ __global__ __launch_bounds__(256) void k_psi_mt(PsiParams<T> P, const uint64_t* 
       ++e;
       if (BPF) fetch_bias(i + 1 < P.K ? i + 1 : i);
     } else {
-#pragma unroll
-      for (int ot = 0; ot < NT; ++ot)
-#pragma unroll
-        for (int t = 0; t < NTL; ++t) acc[t][ot] = vn[ot];
-      if (BPF) fetch_bias(i + 1 < P.K ? i + 1 : i);
       if (TN && tQ > 0) {
         // a tensor site has 2 or 3 parents: each edge's projection into its own registers
+#pragma unroll
+        for (int ot = 0; ot < NT; ++ot)
+#pragma unroll
+          for (int t = 0; t < NTL; ++t) acc[t][ot] = vn[ot];
+        if (BPF) fetch_bias(i + 1 < P.K ? i + 1 : i);
         edge(pr0, std::false_type{});
         ++e;
         edge(pr1, std::false_type{});
@@ -343,7 +346,12 @@ __global__ __launch_bounds__(256) void k_psi_mt(PsiParams<T> P, const uint64_t* 
           ++e;
         }
       } else {
-        do edge(pr0, std::false_type{}); while (++e < e1);
+        // the first edge's MFMAs start from the bias registers (no copies of
+        // them in the accumulators), the later edges accumulate
+        edge(pr0, std::true_type{});
+        ++e;
+        if (BPF) fetch_bias(i + 1 < P.K ? i + 1 : i);
+        for (; e < e1; ++e) edge(pr0, std::false_type{});
       }
     }
     if constexpr (TN) {
@@ -475,7 +483,6 @@ __global__ __launch_bounds__(256) void k_psi_mt(PsiParams<T> P, const uint64_t* 
           wr[(t * TPC + tt) * 64] = sel;
         }
       }
-      wslot = wslot + 1 == P.W ? 0 : wslot + 1;
       const T dot = ReduceOwn<T, NTL>::run(dp) + T(cc[i]);
       // the drawn state's weight by selects (an indexed read would put pr in scratch)
       const T w01 = (pick & 1) ? pr[1] : pr[0];
@@ -549,7 +556,6 @@ __global__ __launch_bounds__(256) void k_psi_mt(PsiParams<T> P, const uint64_t* 
           *reinterpret_cast<V*>(X.nhs + size_t(toff[t] + (i - tc1[t])) * CH + 16 * tt + 4 * g) = sel;
       }
     }
-    wslot = wslot + 1 == P.W ? 0 : wslot + 1;
     T ps[4];
 #pragma unroll
     for (int s = 0; s < 4; ++s) ps[s] = ReduceOwn<T, NTL>::run(pp[s]);
@@ -616,7 +622,7 @@ hipError_t run_psi_mt(const PsiParams<T>& P, const uint64_t* m, int64_t R, doubl
   // two tiles in FP32 (four spill) and one for the FP64 tensor term
   constexpr int NTL = TN && sizeof(T) == 8 && CH == 32 ? 1
                       : ((SAMPLE || TN) && sizeof(T) == 4 && CH == 32 ? 2 : ntiles<T>(CH));
-  const size_t per_wave = size_t(P.W + 1) * 16 * NTL * CH * sizeof(T);
+  const size_t per_wave = size_t(P.W) * 16 * NTL * CH * sizeof(T);
   int wpb = 4;
   while (wpb > 1 && per_wave * wpb > 64 * 1024) wpb >>= 1;
   if (per_wave * wpb > 160 * 1024) return hipErrorInvalidValue;

@@ -114,24 +114,29 @@ __global__ __launch_bounds__(256) void k_psi_b16(B16Params P, const uint64_t* __
   constexpr int SLOT = NTL * TPC * 64;                          // quads per ring slot and part
   constexpr int PARTS = SPLIT ? 2 : 1;                          // hi (and lo) quads per slot
   constexpr int64_t EQ = int64_t(NP) * NT * 64 * 2 + ODD * NT * 64;       // A stream: u2 units per edge
-  constexpr bool APF = NT * (NP ? 4 : 2) * PARTS <= 32;         // fetch the next edge's first k-step ahead
+  // A operands: with pair steps only and where it costs no occupancy (32
+  // registers), a rolling window of one k-step (each k-step's slot, once its
+  // MFMAs are issued, receives the next k-step of the stream, the next edge's
+  // first past the last); otherwise the next edge's first k-step is fetched
+  // ahead where it fits
+  constexpr bool ROLL = !ODD && NT * 4 * PARTS <= 32;
+  constexpr bool APF = !ROLL && NT * (NP ? 4 : 2) * PARTS <= 32;
   constexpr bool BPF = NT * 4 <= 32;                            // fetch the next site's bias ahead
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   const int j = lane & 15, g = lane >> 4;
   const int own = NTL == 4 ? g : (NTL == 2 ? (g >> 1) : 0);
   const int64_t base = (int64_t(blockIdx.x) * wpb + wv) * RW;
   if (base >= R) return;   // surplus wavefront of the last block (no block barrier below)
-  // per wavefront: (W+1) slots of quads (each slot: the hi part, then with
-  // SPLIT the lo part), then (W+1) exponents, all lane-private (every lane
-  // keeps its own copy of the wavefront-uniform exponents)
-  const size_t wbytes = size_t(P.W + 1) * (SLOT * 8 * PARTS + 64 * 4);
+  // per wavefront: W slots of quads (each slot: the hi part, then with SPLIT
+  // the lo part), then W exponents, all lane-private (every lane keeps its
+  // own copy of the wavefront-uniform exponents); site i writes slot wsl[i],
+  // a zero edge (slot index W) reads no slot
+  const size_t wbytes = size_t(P.W) * (SLOT * 8 * PARTS + 64 * 4);
   u2* ring = reinterpret_cast<u2*>(smem + size_t(wv) * wbytes) + lane;
-  int* Ering = reinterpret_cast<int*>(smem + size_t(wv) * wbytes + size_t(P.W + 1) * SLOT * 8 * PARTS) + lane;
-#pragma unroll
-  for (int k = 0; k < NTL * TPC * PARTS; ++k) ring[size_t(P.W) * SLOT * PARTS + k * 64] = u2{0u, 0u};
-  Ering[P.W * 64] = 0;
+  int* Ering = reinterpret_cast<int*>(smem + size_t(wv) * wbytes + size_t(P.W) * SLOT * 8 * PARTS) + lane;
   const CInt* fptr = (const CInt*)(P.pptr);
   const CInt* slots = (const CInt*)(P.slot);
+  const CInt* wsl = (const CInt*)(P.wsl);
   const CT<float>* cc = (const CT<float>*)(P.c);
   const int i0 = SEED ? int(((const __attribute__((address_space(4))) uint8_t*)X.t0)[base]) : 0;
   uint64_t lo[NTL], hi[NTL];
@@ -152,13 +157,14 @@ __global__ __launch_bounds__(256) void k_psi_b16(B16Params P, const uint64_t* __
   for (int t = 1; t < NTL; ++t)
     if (t == own) orow = rowt[t];
   float prod = 1.0f;
-  int pexp = 0, sgn = 1, ca = 0, cb = 0, wslot = 0, e = 0;
+  int pexp = 0, sgn = 1, ca = 0, cb = 0, e = 0;
   bool bad = false;
   if (SEED && i0 > 0) {
     // carried states of the parents of sites >= i0 from the rows' samples,
     // brought to one exponent per slot (the wavefront's largest)
-    const int s0 = i0 - P.W + 1 > 0 ? i0 - P.W + 1 : 0;
-    for (int s = s0; s < i0; ++s) {
+    // the states live at i0 (read by a site >= i0; distinct slots)
+    for (uint64_t lv = ((const __attribute__((address_space(4))) uint64_t*)P.live)[i0]; lv; lv &= lv - 1) {
+      const int s = __builtin_ctzll(lv);
       int es[NTL], emax = -(1 << 30);
 #pragma unroll
       for (int t = 0; t < NTL; ++t) {
@@ -166,7 +172,7 @@ __global__ __launch_bounds__(256) void k_psi_b16(B16Params P, const uint64_t* __
         emax = max(emax, es[t]);
       }
       const int ew = __builtin_amdgcn_readfirstlane(wave_max(emax));
-      u2* wr = ring + size_t(s % P.W) * SLOT * PARTS;
+      u2* wr = ring + size_t(wsl[s]) * SLOT * PARTS;
 #pragma unroll
       for (int t = 0; t < NTL; ++t) {
         const size_t so = (size_t(s) * X.ns + X.owner[rowt[t]]) * CH + 4 * g;
@@ -183,7 +189,7 @@ __global__ __launch_bounds__(256) void k_psi_b16(B16Params P, const uint64_t* __
           }
         }
       }
-      Ering[(s % P.W) * 64] = ew;
+      Ering[wsl[s] * 64] = ew;
     }
     const size_t so = size_t(i0) * X.ns + X.owner[orow];
     prod = X.pm[so];
@@ -192,7 +198,6 @@ __global__ __launch_bounds__(256) void k_psi_b16(B16Params P, const uint64_t* __
     const uint64_t below = low_bits(2 * i0), belowh = low_bits(2 * i0 - 64);
     ca = __popcll(olo & below & 0x5555555555555555ull) + __popcll(ohi & belowh & 0x5555555555555555ull);
     cb = __popcll(olo & below & 0xAAAAAAAAAAAAAAAAull) + __popcll(ohi & belowh & 0xAAAAAAAAAAAAAAAAull);
-    wslot = i0 % P.W;
     e = fptr[i0];
   }
   // A stream in u2 units: per edge NP pair steps of [ot][lane] u4, then (ODD)
@@ -200,18 +205,19 @@ __global__ __launch_bounds__(256) void k_psi_b16(B16Params P, const uint64_t* __
   const u2* __restrict__ Ab = reinterpret_cast<const u2*>(P.A);
   const u2* __restrict__ Abl = reinterpret_cast<const u2*>(P.Alo);   // SPLIT: lo parts, same layout
   typedef typename std::conditional<(NP > 0), u4, u2>::type FA;   // first k-step operand type
-  FA an[APF ? NT : 1], anl[APF ? NT : 1];   // anl: lo parts (SPLIT only)
-  auto first_step = [&](const u2* base, int64_t edge, FA (&dst)[APF ? NT : 1]) {
+  constexpr int NA = APF || ROLL ? NT : 1;
+  FA an[NA], anl[NA];   // anl: lo parts (SPLIT only)
+  auto first_step = [&](const u2* base, int64_t edge, FA (&dst)[NA]) {
 #pragma unroll
-    for (int ot = 0; ot < (APF ? NT : 1); ++ot) {
+    for (int ot = 0; ot < NA; ++ot) {
       if constexpr (NP > 0)
         dst[ot] = reinterpret_cast<const u4*>(base + edge * EQ)[ot * 64 + lane];
       else
         dst[ot] = (base + edge * EQ)[ot * 64 + lane];
     }
   };
-  if (APF) first_step(Ab, e, an);
-  if (APF && SPLIT) first_step(Abl, e, anl);
+  if (APF || ROLL) first_step(Ab, e, an);
+  if ((APF || ROLL) && SPLIT) first_step(Abl, e, anl);
   f4 vn[NT];
   auto fetch_bias = [&](int i) {
 #pragma unroll
@@ -230,30 +236,34 @@ __global__ __launch_bounds__(256) void k_psi_b16(B16Params P, const uint64_t* __
   };
   for (int i = i0; i < P.K; ++i) {
     store_pre(i);
-    f4 acc[NTL][NT], vs[NT], wv4[TPC], ev4[TPC];
+    const int wslot = wsl[i];
+    f4 acc[NTL][NT], wv4[TPC], ev4[TPC];
 #pragma unroll
     for (int tt = 0; tt < TPC; ++tt) {
       wv4[tt] = *reinterpret_cast<const f4*>(P.w + size_t(i) * CH + 16 * tt + 4 * g);
       if (!FOLD) ev4[tt] = *reinterpret_cast<const f4*>(P.eta + size_t(i) * CH + 16 * tt + 4 * g);
     }
     const int e1 = fptr[i + 1];
-    // the parents' common exponent
+    // the parents' common exponent (a zero edge counts as exponent 0)
     int eref = -(1 << 30);
-    for (int ee = e; ee < e1; ++ee) eref = max(eref, __builtin_amdgcn_readfirstlane(Ering[slots[ee] * 64]));
-    // (D1: every site has exactly one edge, whose first MFMAs start from the
-    // scaled bias registers instead of copies of them in the accumulators)
+    for (int ee = e; ee < e1; ++ee)
+      eref = max(eref, slots[ee] >= P.W ? 0 : __builtin_amdgcn_readfirstlane(Ering[slots[ee] * 64]));
+    // (first: the edge's first MFMAs start from the scaled bias registers
+    // instead of copies of them in the accumulators)
     auto edge = [&](auto first) {
       const u2* Ae = Ab + int64_t(e) * EQ;
       const u2* Ael = Abl + int64_t(e) * EQ;
-      const int ep = __builtin_amdgcn_readfirstlane(Ering[slots[e] * 64]);
+      const int sl = slots[e];
+      const bool zero = sl >= P.W;   // a parentless site's zero edge: zero operand
+      const int ep = zero ? 0 : __builtin_amdgcn_readfirstlane(Ering[sl * 64]);
       u2 b[NTL][TPC], bl[NTL][SPLIT ? TPC : 1];
-      const u2* rp = ring + size_t(slots[e]) * SLOT * PARTS;
+      const u2* rp = ring + size_t(zero ? 0 : sl) * SLOT * PARTS;
 #pragma unroll
       for (int t = 0; t < NTL; ++t)
 #pragma unroll
         for (int tt = 0; tt < TPC; ++tt) {
-          b[t][tt] = rp[(t * TPC + tt) * 64];
-          if constexpr (SPLIT) bl[t][tt] = rp[SLOT + (t * TPC + tt) * 64];
+          b[t][tt] = zero ? u2{0u, 0u} : rp[(t * TPC + tt) * 64];
+          if constexpr (SPLIT) bl[t][tt] = zero ? u2{0u, 0u} : rp[SLOT + (t * TPC + tt) * 64];
         }
       if (ep != eref) {
 #pragma unroll
@@ -265,19 +275,26 @@ __global__ __launch_bounds__(256) void k_psi_b16(B16Params P, const uint64_t* __
           }
       }
       FA nx[APF ? NT : 1], nxl[APF ? NT : 1];
-      if (APF) first_step(Ab, int64_t(e) + 1, nx);   // the stream carries one zero edge past the last
-      if (APF && SPLIT) first_step(Abl, int64_t(e) + 1, nxl);
+      // (the stream carries one zero edge past the last)
+      if constexpr (APF) {
+        first_step(Ab, int64_t(e) + 1, nx);
+        if constexpr (SPLIT) first_step(Abl, int64_t(e) + 1, nxl);
+      }
 #pragma unroll
       for (int q = 0; q < NP; ++q)
 #pragma unroll
         for (int ot = 0; ot < NT; ++ot) {
           u4 a, al;
-          if constexpr (NP > 0 && APF)
+          if constexpr (ROLL)
+            a = an[ot];
+          else if constexpr (NP > 0 && APF)
             a = q == 0 ? an[ot] : reinterpret_cast<const u4*>(Ae)[(q * NT + ot) * 64 + lane];
           else
             a = reinterpret_cast<const u4*>(Ae)[(q * NT + ot) * 64 + lane];
           if constexpr (SPLIT) {
-            if constexpr (NP > 0 && APF)
+            if constexpr (ROLL)
+              al = anl[ot];
+            else if constexpr (NP > 0 && APF)
               al = q == 0 ? anl[ot] : reinterpret_cast<const u4*>(Ael)[(q * NT + ot) * 64 + lane];
             else
               al = reinterpret_cast<const u4*>(Ael)[(q * NT + ot) * 64 + lane];
@@ -285,12 +302,16 @@ __global__ __launch_bounds__(256) void k_psi_b16(B16Params P, const uint64_t* __
 #pragma unroll
           for (int t = 0; t < NTL; ++t) {
             const u4 bq = {b[t][2 * q].x, b[t][2 * q].y, b[t][2 * q + 1].x, b[t][2 * q + 1].y};
-            acc[t][ot] = mfma_k32(a, bq, decltype(first)::value && q == 0 ? vs[ot] : acc[t][ot]);
+            acc[t][ot] = mfma_k32(a, bq, decltype(first)::value && q == 0 ? vn[ot] : acc[t][ot]);
             if constexpr (SPLIT) {
               const u4 bql = {bl[t][2 * q].x, bl[t][2 * q].y, bl[t][2 * q + 1].x, bl[t][2 * q + 1].y};
               acc[t][ot] = mfma_k32(a, bql, acc[t][ot]);
               acc[t][ot] = mfma_k32(al, bq, acc[t][ot]);
             }
+          }
+          if constexpr (ROLL) {
+            an[ot] = reinterpret_cast<const u4*>(Ae)[((q + 1) * NT + ot) * 64 + lane];
+            if constexpr (SPLIT) anl[ot] = reinterpret_cast<const u4*>(Ael)[((q + 1) * NT + ot) * 64 + lane];
           }
         }
       if constexpr (ODD) {
@@ -309,7 +330,7 @@ __global__ __launch_bounds__(256) void k_psi_b16(B16Params P, const uint64_t* __
           }
 #pragma unroll
           for (int t = 0; t < NTL; ++t) {
-            acc[t][ot] = mfma_k16(a, b[t][TPC - 1], decltype(first)::value && NP == 0 ? vs[ot] : acc[t][ot]);
+            acc[t][ot] = mfma_k16(a, b[t][TPC - 1], decltype(first)::value && NP == 0 ? vn[ot] : acc[t][ot]);
             if constexpr (SPLIT) {
               acc[t][ot] = mfma_k16(a, bl[t][TPC - 1], acc[t][ot]);
               acc[t][ot] = mfma_k16(al, b[t][TPC - 1], acc[t][ot]);
@@ -317,7 +338,7 @@ __global__ __launch_bounds__(256) void k_psi_b16(B16Params P, const uint64_t* __
           }
         }
       }
-      if (APF) {
+      if constexpr (APF) {
 #pragma unroll
         for (int ot = 0; ot < NT; ++ot) {
           an[ot] = nx[ot];
@@ -328,13 +349,22 @@ __global__ __launch_bounds__(256) void k_psi_b16(B16Params P, const uint64_t* __
     if (!BPF) fetch_bias(i);
     const float sc = ldexpf(1.0f, -eref);
     __builtin_amdgcn_s_setprio(PRIO);
-    if constexpr (D1) {
+    if constexpr (D1 || ROLL) {
+      // the bias at the parents' exponent, in place (exact: sc is a power of
+      // two); the first edge's MFMAs start from it, the later edges accumulate
+      // (D1: every site has exactly one edge)
+      if (eref != 0) {
 #pragma unroll
-      for (int ot = 0; ot < NT; ++ot) vs[ot] = vn[ot] * sc;   // exact: sc is a power of two
-      if (BPF) fetch_bias(i + 1 < P.K ? i + 1 : i);
+        for (int ot = 0; ot < NT; ++ot) vn[ot] = vn[ot] * sc;
+      }
       edge(std::true_type{});
       ++e;
+      if (BPF) fetch_bias(i + 1 < P.K ? i + 1 : i);
+      if constexpr (!D1)
+        for (; e < e1; ++e) edge(std::false_type{});
     } else {
+      // (the bias registers stay free for the next site's: fewer registers
+      // live through the first edge where no rolling window holds them)
       if (eref == 0) {
 #pragma unroll
         for (int ot = 0; ot < NT; ++ot)
@@ -452,7 +482,6 @@ __global__ __launch_bounds__(256) void k_psi_b16(B16Params P, const uint64_t* __
         if (g == 0 && r < X.ns) X.he[size_t(i) * X.ns + r] = enew;
       }
     }
-    wslot = wslot + 1 == P.W ? 0 : wslot + 1;
   }
   store_pre(P.K);
   const bool writer = NTL == 4 || (NTL == 2 ? (g & 1) == 0 : g == 0);
@@ -469,7 +498,7 @@ hipError_t run_b16(const B16Params& P, const uint64_t* m, int64_t R, double* lph
   if (SPLIT && (!P.Alo || (STORE && !X.hs_lo) || (SEED && !X.hs_lo))) return hipErrorInvalidValue;
   constexpr int NTL = ntiles_b16<CH>();
   constexpr int TPC = CH / 16;
-  const size_t per_wave = size_t(P.W + 1) * (NTL * TPC * 64 * 8 * (SPLIT ? 2 : 1) + 64 * 4);
+  const size_t per_wave = size_t(P.W) * (NTL * TPC * 64 * 8 * (SPLIT ? 2 : 1) + 64 * 4);
   int wpb = 4;
   while (wpb > 1 && per_wave * wpb > 64 * 1024) wpb >>= 1;
   if (per_wave * wpb > 160 * 1024) return hipErrorInvalidValue;

@@ -326,7 +326,10 @@ struct nqs_ansatz {
   int* d_pidx = nullptr;
   int* d_slot = nullptr;    // ring slot of each parent edge (pidx % W)
   int* d_fptr = nullptr;    // forward edge CSR: every parentless site gets one zero-weight edge
-  int* d_fslot = nullptr;   // forward edge slots (a dummy edge reads slot W, which stays zero)
+  int* d_fslot = nullptr;   // forward edge: ring slot of the parent's state (ring: the zero edge)
+  int ring = 1;             // LDS ring slots of the forward kernels (states live at once)
+  int* d_wsl = nullptr;     // [K] ring slot receiving site i's state
+  uint64_t* d_live = nullptr;   // [K+1] bit s: the state of site s < i is read by a site >= i
   bool bound = false;
   PsiLayout<double> L64, F64;   // F*: sqrt(eta)-folded forward layouts (when every eta > 0)
   PsiLayout<float> L32, F32;
@@ -377,7 +380,8 @@ struct nqs_ansatz {
     L32.free_all();
     F64.free_all();
     F32.free_all();
-    for (void* p : {(void*)d_pptr, (void*)d_pidx, (void*)d_slot, (void*)d_fptr, (void*)d_fslot, (void*)bfA,
+    for (void* p : {(void*)d_pptr, (void*)d_pidx, (void*)d_slot, (void*)d_fptr, (void*)d_fslot, (void*)d_wsl,
+                    (void*)d_live, (void*)bfA,
                     (void*)bfAlo,
                     (void*)d_cb, (void*)d_cW, (void*)d_cW1t, (void*)d_cS, (void*)d_cS32, (void*)d_tn_edge,
                     (void*)d_tn_site, (void*)tn64, (void*)tn32, (void*)d_offM, (void*)d_offV,
@@ -397,9 +401,9 @@ struct nqs_ansatz {
   template <typename T>
   PsiParams<T> params(const PsiLayout<T>& L) const {
     PsiParams<T> P;
-    P.K = K; P.chi = chi; P.chip = chip; P.na = na; P.nb = nb; P.W = W;
+    P.K = K; P.chi = chi; P.chip = chip; P.na = na; P.nb = nb; P.W = ring;
     P.d1 = d1;
-    P.pptr = d_fptr; P.slot = d_fslot;
+    P.pptr = d_fptr; P.slot = d_fslot; P.wsl = d_wsl; P.live = d_live;
     P.A = L.A; P.v = L.v; P.eta = L.eta; P.w = L.w; P.c = L.c;
     P.folded = L.folded;
     P.w2 = L.w2; P.c2 = L.c2;
@@ -1035,10 +1039,37 @@ nqs_status nqs_ansatz_create(nqs_ctx* ctx, int K, int n_alpha, int n_beta, int c
   std::vector<int> slot(pi.size());
   for (size_t e = 0; e < pi.size(); ++e) slot[e] = pi[e] % a->W;
   if ((st = upload(&a->d_slot, slot)) != NQS_OK) return st;
+  // LDS ring of the forward kernels: site i's carried state goes to slot
+  // wsl[i], one whose previous state no site after i reads (its last reader
+  // may be site i itself: a site reads its parents before it writes); the
+  // ring needs as many slots as states are live at once, which can be fewer
+  // than the largest parent offset.  live[i], i = 0..K: bit s set for each
+  // state s < i that a site >= i reads (a row resumed at i loads exactly
+  // these).  Rows resume at K too (a sample's own row, and a row with fewer
+  // changed sites than its resume level): live[K] = 0.
+  std::vector<int> lastu(K), wsl(K), holder;
+  std::vector<uint64_t> live(K + 1, 0);
+  for (int s = 0; s < K; ++s) lastu[s] = s;
+  for (int i = 0; i < K; ++i)
+    for (int e = a->pptr[i]; e < a->pptr[i + 1]; ++e) lastu[pi[e]] = std::max(lastu[pi[e]], i);
+  for (int i = 0; i < K; ++i) {
+    size_t k = 0;
+    while (k < holder.size() && lastu[holder[k]] > i) ++k;
+    if (k == holder.size()) holder.push_back(i); else holder[k] = i;
+    wsl[i] = int(k);
+  }
+  a->ring = int(holder.size());
+  for (int i = 0; i < K; ++i)
+    for (int s2 = 0; s2 < i; ++s2)
+      if (lastu[s2] >= i) live[i] |= 1ull << s2;
+  if ((st = upload(&a->d_wsl, wsl)) != NQS_OK) return st;
+  if ((st = upload(&a->d_live, live)) != NQS_OK) return st;
+  // forward edges: a parentless site gets one zero edge, marked by the slot
+  // index a->ring (no such slot: the kernels take a zero operand)
   std::vector<int> fptr(1, 0), fslot;
   for (int i = 0; i < K; ++i) {
-    if (a->pptr[i + 1] == a->pptr[i]) fslot.push_back(a->W);
-    for (int e = a->pptr[i]; e < a->pptr[i + 1]; ++e) fslot.push_back(slot[e]);
+    if (a->pptr[i + 1] == a->pptr[i]) fslot.push_back(a->ring);
+    for (int e = a->pptr[i]; e < a->pptr[i + 1]; ++e) fslot.push_back(wsl[pi[e]]);
     fptr.push_back(int(fslot.size()));
   }
   a->d1 = true;
@@ -1375,8 +1406,9 @@ nqs_status run_amplitudes(const nqs_ansatz* a, int precision, const uint64_t* m,
   } else if (is_bf16(precision)) {
     const PsiLayout<float>& L = a->fwd32();
     B16Params P{};
-    P.K = a->K; P.chi = a->chi; P.chip = a->chip; P.na = a->na; P.nb = a->nb; P.W = a->W;
-    P.pptr = a->d_fptr; P.slot = a->d_fslot; P.A = a->bfA; P.Alo = a->bfAlo;
+    P.K = a->K; P.chi = a->chi; P.chip = a->chip; P.na = a->na; P.nb = a->nb; P.W = a->ring;
+    P.pptr = a->d_fptr; P.slot = a->d_fslot; P.wsl = a->d_wsl; P.live = a->d_live;
+    P.A = a->bfA; P.Alo = a->bfAlo;
     P.v = L.v; P.eta = L.eta; P.w = L.w; P.c = L.c; P.folded = L.folded; P.d1 = a->d1;
     hipError_t e = launch_psi_bf16(P, m, R, lphi, sphi, st, rs ? states_b16(*rs) : B16States(), mode,
                                    precision == NQS_BF16X3);
