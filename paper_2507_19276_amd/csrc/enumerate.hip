@@ -126,12 +126,17 @@ __device__ inline uint32_t eidx(int K, int p, int q, int r, int s) {
 // S(i) = number of pairs (i', j') with i' < i in lexicographic order of i<j<n
 __device__ inline int pair_start(int i, int n) { return i * n - (i * (i + 1)) / 2; }
 
+// pair p -> (i, j): i = max{i : S(i) <= p}, the floor of the smaller root of
+// S(x) = p with b = 2n - 1.  For n <= 64 the FP32 estimate is within one of
+// it (b^2 - 8p < 2^24 is exact in FP32 and the square root carries an ulp or
+// two), so one correction step each way gives i exactly (checked for every
+// n <= 64 and p, with the square root off by up to two ulps either way).
 __device__ inline void unpair(uint32_t p, int n, int& i, int& j) {
   const float b = 2.0f * n - 1.0f;
   int ii = int((b - sqrtf(fmaxf(b * b - 8.0f * float(p), 0.0f))) * 0.5f);
   ii = max(0, min(ii, n - 2));
-  while (ii + 1 <= n - 2 && pair_start(ii + 1, n) <= int(p)) ++ii;
-  while (ii > 0 && pair_start(ii, n) > int(p)) --ii;
+  ii += (ii + 1 <= n - 2 && pair_start(ii + 1, n) <= int(p)) ? 1 : 0;
+  ii -= (ii > 0 && pair_start(ii, n) > int(p)) ? 1 : 0;
   i = ii;
   j = int(p) - pair_start(ii, n) + ii + 1;
 }
@@ -157,12 +162,13 @@ __device__ inline int apply_double(uint64_t& lo, uint64_t& hi, int I, int J, int
 
 // Matrix element H_mn and m for canonical rank r of the sample (lo, hi).
 // FULL = false: |H_mn| only (the screening and the proposal weights need no
-// sign and no m), in e.H.
-template <bool FULL = true>
+// sign and no m), in e.H.  KIND: 0 any rank; 2 (3) the caller knows r is a
+// same-spin (opposite-spin) double and the other kinds' code is left out.
+template <bool FULL = true, int KIND = 0>
 __device__ Elem element(const HamDev& H, const Lists& L, uint64_t lo, uint64_t hi, uint32_t r) {
   const int K = H.K;
   Elem e;
-  if (r < H.off_daa) {
+  if (KIND == 0 && r < H.off_daa) {
     // single excitation I -> A of spin sigma: |m> = g a+_A a_I |n>,
     // H_mn = g (h_AI + sum_{J occ} <AJ||IJ>), J ascending
     const int sg = r >= H.off_sb ? 1 : 0;
@@ -195,7 +201,7 @@ __device__ Elem element(const HamDev& H, const Lists& L, uint64_t lo, uint64_t h
     e.mlo = ml; e.mhi = mh;
     return e;
   }
-  if (r < H.off_dab) {
+  if (KIND == 2 || (KIND == 0 && r < H.off_dab)) {
     // same-spin double (i<j) -> (a<b): H_mn = g ((ai|bj) - (aj|bi))
     const int sg = r >= H.off_dbb ? 1 : 0;
     const uint32_t t = sg ? r - H.off_dbb : r - H.off_daa;
@@ -313,7 +319,15 @@ __global__ __launch_bounds__(256) void k_enum_count(HamDev H, EnumGeom G, const 
   for (int c = c0; c < c1; ++c) {
     const uint32_t r = uint32_t(c) * 64u + uint32_t(lane);
     double hv = 0.0;
-    if (ok && r < H.n_conn) hv = element<false>(H, L, lo, hi, r).H;
+    // the kind of excitation is uniform over a chunk except at the borders
+    // of the three rank ranges (scalar branches; a mixed chunk dispatches
+    // per lane)
+    const uint32_t cr0 = uint32_t(c) * 64u, cr1 = cr0 + 63u;
+    if (ok && r < H.n_conn) {
+      if (cr0 >= H.off_dab) hv = element<false, 3>(H, L, lo, hi, r).H;
+      else if (cr0 >= H.off_daa && cr1 < H.off_dab) hv = element<false, 2>(H, L, lo, hi, r).H;
+      else hv = element<false>(H, L, lo, hi, r).H;
+    }
     const double ah = fabs(hv);
     const bool det = hv != 0.0 && ah >= eps;
     const uint64_t q = (hv != 0.0 && !det) ? proposal_weight(ah, qshift) : 0ull;
