@@ -121,7 +121,11 @@ __global__ __launch_bounds__(256) void k_psi_b16(B16Params P, const uint64_t* __
   // ahead where it fits
   constexpr bool ROLL = !ODD && NT * 4 * PARTS <= 32;
   constexpr bool APF = !ROLL && NT * (NP ? 4 : 2) * PARTS <= 32;
-  constexpr bool BPF = NT * 4 <= 32;                            // fetch the next site's bias ahead
+  // the bias is fetched at the start of its site, not a site ahead: the 32
+  // registers a prefetch holds cost a wavefront per SIMD at chip 16 and 32
+  // (measured at chip 32: 124 -> 109 ms per launch on the K = 50 batch with
+  // three wavefronts per SIMD instead of two)
+  constexpr bool BPF = false;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   const int j = lane & 15, g = lane >> 4;
   const int own = NTL == 4 ? g : (NTL == 2 ? (g >> 1) : 0);
