@@ -12,6 +12,7 @@
 // This file is compiled without floating-point contraction: the matrix
 // elements are meant to equal a plain sequential evaluation bit for bit.
 #include "internal.h"
+#include <algorithm>
 #include "philox.h"
 
 #pragma clang fp contract(off)
@@ -180,12 +181,12 @@ __device__ Elem element(const HamDev& H, const Lists& L, uint64_t lo, uint64_t h
     const int a = sg ? L.vb[aa] : L.va[aa];
     double acc = H.h[a * K + i];
     const int ne = H.na + H.nb;
+    const double2* s3 = reinterpret_cast<const double2*>(H.s3) + (a * K + i) * K;   // ((ai|jj), (aj|ji)) over j
     for (int k = 0; k < ne; ++k) {
       const int J = L.occ[k];
-      const int j = J >> 1;
-      const double g1 = H.eri[eidx(K, a, i, j, j)];
-      const double g2 = ((J & 1) == sg) ? H.eri[eidx(K, a, j, j, i)] : 0.0;
-      acc += (g1 - g2);
+      const double2 g = s3[J >> 1];
+      const double g2 = ((J & 1) == sg) ? g.y : 0.0;
+      acc += (g.x - g2);
     }
     if constexpr (!FULL) {
       e.H = fabs(acc);
@@ -298,50 +299,232 @@ __global__ void k_validate(const uint64_t* samples, int64_t N, int K, int na, in
   if (a != na || b != nb || sl || sh) *bad = 1;
 }
 
-// Pass 1: per chunk the ballot of deterministic ranks and the inclusive
-// (within segment) prefix of remainder weights; per segment the totals.
-__global__ __launch_bounds__(256) void k_enum_count(HamDev H, EnumGeom G, const uint64_t* samples,
-                                                   int64_t N, double eps, int qshift,
-                                                   uint64_t* masks, uint64_t* qpref, uint64_t* segq,
-                                                   uint32_t* segd) {
+// Pass 1 (screening): per chunk of 64 ranks of a sample the ballot of the
+// deterministic ranks and the sum of the remainder's proposal weights, then per
+// segment the running sums.  |H_nm| alone decides both, so no sign and no ONV
+// is formed.  Doubles go by orbital pair: a workgroup stages the K x K integral
+// slab of one pair in LDS and serves every sample of a batch in which that pair
+// appears (hole and particle of the alpha spin for opposite-spin doubles, the
+// two holes for equal-spin ones), so a slab is read once per batch instead of
+// once per sample.  The ranks of one (sample, pair) form a contiguous block;
+// a wavefront walks it chunk by chunk, stores the chunks that lie wholly inside
+// and adds the two border chunks, which it shares with the neighbouring blocks,
+// with 64-bit atomics (exact in any order).  Singles go by sample.  A scan per
+// segment then turns the chunk sums into running sums.
+
+constexpr int kScrBatch = 256;   // samples per workgroup of the pair kernels (64 per wavefront)
+
+// (n_alpha, n_beta) electrons and no bit beyond 2K: the samples whose elements exist
+__device__ inline bool onv_ok(const HamDev& H, uint64_t lo, uint64_t hi) {
+  const uint64_t EVEN = 0x5555555555555555ull;
+  const int K2 = 2 * H.K;
+  const uint64_t slo = K2 >= 64 ? 0ull : (lo >> K2);
+  const uint64_t shi = K2 >= 128 ? 0ull : (K2 >= 64 ? (hi >> (K2 - 64)) : hi);
+  return __popcll(lo & EVEN) + __popcll(hi & EVEN) == H.na &&
+         __popcll(lo & ~EVEN) + __popcll(hi & ~EVEN) == H.nb && slo == 0 && shi == 0;
+}
+
+// the n lowest bits of a word (all for n >= 64, none for n <= 0)
+__device__ inline uint64_t lowest(int n) { return n <= 0 ? 0ull : (n >= 64 ? ~0ull : ((1ull << n) - 1ull)); }
+
+// occupied spin orbitals 2q + sigma with q < p
+__device__ inline int occ_below_spin(uint64_t lo, uint64_t hi, int p, int sigma) {
+  const uint64_t sp = sigma ? 0xAAAAAAAAAAAAAAAAull : 0x5555555555555555ull;
+  return __popcll(lo & sp & lowest(2 * p)) + __popcll(hi & sp & lowest(2 * p - 64));
+}
+
+// value of lane l (wave-uniform) of a 64-bit register
+__device__ inline uint64_t lane_u64(uint64_t x, int l) {
+  const uint32_t a = uint32_t(__builtin_amdgcn_readlane(int(uint32_t(x)), l));
+  const uint32_t b = uint32_t(__builtin_amdgcn_readlane(int(uint32_t(x >> 32)), l));
+  return (uint64_t(b) << 32) | a;
+}
+
+// the occupied and the virtual orbitals of one spin, ascending (lane p looks at orbital p)
+__device__ inline void spin_lists(const HamDev& H, uint64_t lo, uint64_t hi, int sigma, uint8_t* occ, uint8_t* vir) {
+  const int p = lane_id();
+  const bool in = p < H.K;
+  const bool x = in && bit_at(lo, hi, 2 * p + sigma);
+  const int r = __popcll(__ballot(x) & __lanemask_lt());
+  if (in) {
+    if (x) occ[r] = uint8_t(p); else vir[p - r] = uint8_t(p);
+  }
+  wave_sync();
+}
+
+__device__ inline void screen(double hv, double eps, int qshift, bool valid, bool& det, uint64_t& q) {
+  const double ah = fabs(hv);
+  det = valid && hv != 0.0 && ah >= eps;
+  q = (valid && hv != 0.0 && !det) ? proposal_weight(ah, qshift) : 0ull;
+}
+
+// the ranks [rb, re) of one sample (chunk row at masks/qsum + row); hval(e)
+// gives H at rank rb + e for the lanes inside the block.  Lane l takes rank
+// 64 c + l of chunk c; a chunk wholly inside the block is stored, a border
+// chunk is added atomically.
+template <class F>
+__device__ inline void scr_block(uint64_t* masks, uint64_t* qsum, int64_t row, uint32_t rb, uint32_t re, double eps,
+                                 int qshift, F&& hval) {
+  const uint32_t lane = uint32_t(lane_id());
+  for (uint32_t c = rb >> 6; c * 64u < re; ++c) {
+    const uint32_t r = c * 64u + lane;
+    const bool valid = r >= rb && r < re;
+    const double hv = valid ? hval(r - rb) : 0.0;
+    bool det;
+    uint64_t q;
+    screen(hv, eps, qshift, valid, det, q);
+    const uint64_t bal = __ballot(det);
+    const uint64_t qs = wave_sum_u64(q);
+    if (lane == 0) {
+      uint64_t* m = masks + row + c;
+      uint64_t* s = qsum + row + c;
+      if (c * 64u >= rb && c * 64u + 64u <= re) {
+        *m = bal;
+        *s = qs;
+      } else {
+        if (bal) atomicOr((unsigned long long*)m, (unsigned long long)bal);
+        if (qs) atomicAdd((unsigned long long*)s, (unsigned long long)qs);
+      }
+    }
+  }
+}
+
+__global__ void k_scr_zero(uint64_t* a, uint64_t* b, int64_t n) {
+  for (int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; t < n; t += int64_t(gridDim.x) * blockDim.x) {
+    a[t] = 0ull;
+    b[t] = 0ull;
+  }
+}
+
+// singles: one wavefront per sample over the ranks below off_daa
+__global__ __launch_bounds__(256) void k_scr_singles(HamDev H, EnumGeom G, const uint64_t* samples, int64_t N,
+                                                     double eps, int qshift, uint64_t* masks, uint64_t* qsum) {
   __shared__ Lists lists[4];
+  const int wv = threadIdx.x >> 6;
+  const int64_t n = int64_t(blockIdx.x) * 4 + wv;
+  if (n >= N) return;
+  const uint64_t lo = samples[2 * n], hi = samples[2 * n + 1];
+  Lists& L = lists[wv];
+  if (!decode_lists(H, lo, hi, L)) return;
+  scr_block(masks, qsum, n * G.nchunks, 0u, H.off_daa, eps, qshift,
+            [&](uint32_t r) { return element<false>(H, L, lo, hi, r).H; });
+}
+
+// opposite-spin doubles (i alpha -> a alpha, j beta -> b beta), workgroup per
+// (i, a), i != a, and batch of samples: slab (ia|jb) over (j, b), contiguous in HBM
+__global__ __launch_bounds__(256) void k_scr_os(HamDev H, EnumGeom G, const uint64_t* samples, int64_t N,
+                                                double eps, int qshift, uint64_t* masks, uint64_t* qsum) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int K = H.K;
+  const int i = int(blockIdx.x) / (K - 1), t = int(blockIdx.x) % (K - 1);
+  const int a = t + (t >= i ? 1 : 0);
+  double* slab = reinterpret_cast<double*>(smem);
+  const int wv = threadIdx.x >> 6, lane = lane_id();
+  uint8_t* occ = smem + size_t(K) * K * 8 + wv * 128;
+  uint8_t* vir = occ + 64;
+  const double* src = H.eri + (size_t(i) * K + a) * K * K;
+  for (int u = threadIdx.x; u < K * K; u += blockDim.x) slab[u] = src[u];
+  __syncthreads();
+  const int64_t n = int64_t(blockIdx.y) * kScrBatch + wv * 64 + lane;
+  uint64_t lo = 0, hi = 0;
+  bool ok = false;
+  if (n < N) {
+    lo = samples[2 * n];
+    hi = samples[2 * n + 1];
+    ok = bit_at(lo, hi, 2 * i) && !bit_at(lo, hi, 2 * a) && onv_ok(H, lo, hi);
+  }
+  for (uint64_t todo = __ballot(ok); todo; todo &= todo - 1) {
+    const int l = __ffsll((unsigned long long)todo) - 1;
+    const uint64_t slo = lane_u64(lo, l), shi = lane_u64(hi, l);
+    const uint32_t ii = uint32_t(occ_below_spin(slo, shi, i, 0));
+    const uint32_t aa = uint32_t(a - occ_below_spin(slo, shi, a, 0));
+    spin_lists(H, slo, shi, 1, occ, vir);
+    const uint32_t rb = H.off_dab + (ii * uint32_t(H.va) + aa) * H.nsb;
+    const int64_t sn = int64_t(blockIdx.y) * kScrBatch + wv * 64 + l;
+    scr_block(masks, qsum, sn * G.nchunks, rb, rb + H.nsb, eps, qshift, [&](uint32_t e) {
+      const uint32_t jj = mdiv(e, H.mg_vb);
+      const uint32_t bb = e - jj * uint32_t(H.vb);
+      return slab[int(occ[jj]) * K + int(vir[bb])];
+    });
+    wave_sync();   // the lists are rewritten for the next sample
+  }
+}
+
+// equal-spin doubles (i < j -> a < b, both spins), workgroup per hole pair
+// (i, j) and batch of samples: slab S[a][b] = (ia|jb); (ja|ib) = S[b][a] as the
+// stored integrals are exactly 8-fold symmetric
+__global__ __launch_bounds__(256) void k_scr_ss(HamDev H, EnumGeom G, const uint64_t* samples, int64_t N,
+                                                double eps, int qshift, uint64_t* masks, uint64_t* qsum) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int K = H.K;
+  int i, j;
+  unpair(blockIdx.x, K, i, j);
+  double* slab = reinterpret_cast<double*>(smem);
+  const int wv = threadIdx.x >> 6, lane = lane_id();
+  uint8_t* occ = smem + size_t(K) * K * 8 + wv * 128;
+  uint8_t* vir = occ + 64;
+  for (int u = threadIdx.x; u < K * K; u += blockDim.x) {
+    const int a = u / K, b = u % K;
+    slab[u] = H.eri[((size_t(i) * K + a) * K + j) * K + b];
+  }
+  __syncthreads();
+  const int64_t n = int64_t(blockIdx.y) * kScrBatch + wv * 64 + lane;
+  uint64_t lo = 0, hi = 0;
+  bool ok = false;
+  if (n < N) {
+    lo = samples[2 * n];
+    hi = samples[2 * n + 1];
+    ok = ((bit_at(lo, hi, 2 * i) && bit_at(lo, hi, 2 * j)) || (bit_at(lo, hi, 2 * i + 1) && bit_at(lo, hi, 2 * j + 1))) &&
+         onv_ok(H, lo, hi);
+  }
+  for (uint64_t todo = __ballot(ok); todo; todo &= todo - 1) {
+    const int l = __ffsll((unsigned long long)todo) - 1;
+    const uint64_t slo = lane_u64(lo, l), shi = lane_u64(hi, l);
+    const int64_t sn = int64_t(blockIdx.y) * kScrBatch + wv * 64 + l;
+    for (int sg = 0; sg < 2; ++sg) {
+      if (!bit_at(slo, shi, 2 * i + sg) || !bit_at(slo, shi, 2 * j + sg)) continue;
+      const int ne = sg ? H.nb : H.na, nv = sg ? H.vb : H.va;
+      const int ii = occ_below_spin(slo, shi, i, sg), jj = occ_below_spin(slo, shi, j, sg);
+      const uint32_t pij = uint32_t(pair_start(ii, ne) + (jj - ii - 1));
+      const uint32_t npv = sg ? H.npb_v : H.npa_v;
+      const uint32_t rb = (sg ? H.off_dbb : H.off_daa) + pij * npv;
+      spin_lists(H, slo, shi, sg, occ, vir);
+      scr_block(masks, qsum, sn * G.nchunks, rb, rb + npv, eps, qshift, [&](uint32_t pab) {
+        int aa, bb;
+        unpair(pab, nv, aa, bb);
+        const int av = vir[aa], bv = vir[bb];
+        return slab[av * K + bv] - slab[bv * K + av];
+      });
+      wave_sync();
+    }
+  }
+}
+
+// running sums: one wavefront per (sample, segment); qpref holds the chunk
+// sums on entry and their inclusive prefix within the segment on exit
+__global__ __launch_bounds__(256) void k_scr_scan(EnumGeom G, int64_t N, const uint64_t* masks, uint64_t* qpref,
+                                                  uint64_t* segq, uint32_t* segd) {
   const int wv = threadIdx.x >> 6, lane = lane_id();
   const int64_t unit = int64_t(blockIdx.x) * 4 + wv;
   if (unit >= N * G.S) return;
   const int64_t n = unit / G.S;
   const int s = int(unit % G.S);
-  const uint64_t lo = samples[2 * n], hi = samples[2 * n + 1];
-  Lists& L = lists[wv];
-  const bool ok = decode_lists(H, lo, hi, L);
   const int c0 = s * G.cps, c1 = min(c0 + G.cps, G.nchunks);
-  uint64_t runq = 0;
-  uint32_t rund = 0;
-  for (int c = c0; c < c1; ++c) {
-    const uint32_t r = uint32_t(c) * 64u + uint32_t(lane);
-    double hv = 0.0;
-    // the kind of excitation is uniform over a chunk except at the borders
-    // of the three rank ranges (scalar branches; a mixed chunk dispatches
-    // per lane)
-    const uint32_t cr0 = uint32_t(c) * 64u, cr1 = cr0 + 63u;
-    if (ok && r < H.n_conn) {
-      if (cr0 >= H.off_dab) hv = element<false, 3>(H, L, lo, hi, r).H;
-      else if (cr0 >= H.off_daa && cr1 < H.off_dab) hv = element<false, 2>(H, L, lo, hi, r).H;
-      else hv = element<false>(H, L, lo, hi, r).H;
-    }
-    const double ah = fabs(hv);
-    const bool det = hv != 0.0 && ah >= eps;
-    const uint64_t q = (hv != 0.0 && !det) ? proposal_weight(ah, qshift) : 0ull;
-    const uint64_t mask = __ballot(det);
-    runq += wave_sum_u64(q);
-    rund += uint32_t(__popcll(mask));
-    if (lane == 0) {
-      masks[n * G.nchunks + c] = mask;
-      qpref[n * G.nchunks + c] = runq;
-    }
+  const int64_t row = n * G.nchunks;
+  uint64_t carry = 0;
+  uint32_t d = 0;
+  for (int c = c0; c < c1; c += 64) {
+    const int cc = c + lane;
+    const uint64_t qv = cc < c1 ? qpref[row + cc] : 0ull;
+    const uint64_t mv = cc < c1 ? masks[row + cc] : 0ull;
+    const uint64_t incl = wave_incl_scan_u64(qv);
+    if (cc < c1) qpref[row + cc] = carry + incl;
+    carry += __shfl(incl, 63);
+    d += uint32_t(wave_sum_u64(uint64_t(__popcll(mv))));
   }
   if (lane == 0) {
-    segq[n * G.S + s] = runq;
-    segd[n * G.S + s] = rund;
+    segq[n * G.S + s] = carry;
+    segd[n * G.S + s] = d;
   }
 }
 
@@ -683,8 +866,32 @@ hipError_t launch_enum_count(const HamDev& H, const EnumGeom& G, const uint64_t*
                              double eps, int qshift, uint64_t* masks, uint64_t* qpref, uint64_t* segq,
                              uint32_t* segd, hipStream_t st) {
   if (N <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_enum_count, dim3(grid_for(N * G.S, 4)), dim3(256), 0, st, H, G, samples, N, eps,
-                     qshift, masks, qpref, segq, segd);
+  if (H.K < 1 || H.K > 64) return hipErrorInvalidValue;
+  const int64_t nc = N * G.nchunks;
+  hipLaunchKernelGGL(k_scr_zero, dim3(unsigned(std::min<int64_t>((nc + 255) / 256, 16384))), dim3(256), 0, st,
+                     masks, qpref, nc);
+  if (H.off_daa > 0)
+    hipLaunchKernelGGL(k_scr_singles, dim3(grid_for(N, 4)), dim3(256), 0, st, H, G, samples, N, eps, qshift,
+                       masks, qpref);
+  // pair kernels: grid x = orbital pairs (K(K-1)/2 hole pairs i < j, K(K-1)
+  // hole-particle pairs i != a), y = batches of kScrBatch samples (launched in
+  // slices of at most 65535 batches)
+  const size_t lds = size_t(H.K) * H.K * 8 + 4 * 128;
+  const int64_t nbatch = (N + kScrBatch - 1) / kScrBatch;
+  for (int64_t b0 = 0; b0 < nbatch; b0 += 65535) {
+    const int64_t nb = std::min<int64_t>(nbatch - b0, 65535);
+    const uint64_t* sm = samples + 2 * b0 * kScrBatch;
+    const int64_t Nb = std::min<int64_t>(N - b0 * kScrBatch, nb * kScrBatch);
+    uint64_t* mk = masks + b0 * kScrBatch * G.nchunks;
+    uint64_t* qs = qpref + b0 * kScrBatch * G.nchunks;
+    if (H.off_dab > H.off_daa)
+      hipLaunchKernelGGL(k_scr_ss, dim3(unsigned(H.K * (H.K - 1) / 2), unsigned(nb)), dim3(256), lds, st, H, G, sm, Nb, eps,
+                         qshift, mk, qs);
+    if (H.n_conn > H.off_dab)
+      hipLaunchKernelGGL(k_scr_os, dim3(unsigned(H.K * (H.K - 1)), unsigned(nb)), dim3(256), lds, st, H, G, sm, Nb, eps,
+                         qshift, mk, qs);
+  }
+  hipLaunchKernelGGL(k_scr_scan, dim3(grid_for(N * G.S, 4)), dim3(256), 0, st, G, N, masks, qpref, segq, segd);
   return hipGetLastError();
 }
 

@@ -19,6 +19,7 @@ struct HamDev {
   const double* h;     // [K][K]
   const double* eri;   // [K][K][K][K] chemist (pq|rs), exactly 8-fold symmetric
   const double* jk;    // [2][K][K]: (pp|qq) and (pq|qp), copies of eri entries for the diagonal
+  const double* s3;    // [K][K][K][2]: (ai|jj) and (aj|ji) at [a][i][j], copies of eri entries for the singles
   double ecore;
   int K, na, nb, va, vb;                 // va = K - na, vb = K - nb
   uint32_t off_sb, off_daa, off_dbb, off_dab, n_conn;

@@ -279,11 +279,13 @@ struct nqs_instance {
   double* d_h = nullptr;
   double* d_eri = nullptr;
   double* d_jk = nullptr;
+  double* d_s3 = nullptr;
   HamDev H{};
   ~nqs_instance() {
     if (d_h) (void)hipFree(d_h);
     if (d_eri) (void)hipFree(d_eri);
     if (d_jk) (void)hipFree(d_jk);
+    if (d_s3) (void)hipFree(d_s3);
   }
 };
 
@@ -888,8 +890,17 @@ nqs_status nqs_instance_create(nqs_ctx* ctx, int K, int n_alpha, int n_beta, con
       jk[size_t(K) * K + size_t(p) * K + q] = canon[((size_t(p) * K + q) * K + q) * K + p];
     }
   if ((st = upload(&inst->d_jk, jk)) != NQS_OK) return st;
+  std::vector<double> s3(size_t(2) * K * K * K);
+  for (int a = 0; a < K; ++a)
+    for (int i = 0; i < K; ++i)
+      for (int j = 0; j < K; ++j) {
+        const size_t o = ((size_t(a) * K + i) * K + j) * 2;
+        s3[o] = canon[((size_t(a) * K + i) * K + j) * K + j];
+        s3[o + 1] = canon[((size_t(a) * K + j) * K + j) * K + i];
+      }
+  if ((st = upload(&inst->d_s3, s3)) != NQS_OK) return st;
   HamDev& H = inst->H;
-  H.h = inst->d_h; H.eri = inst->d_eri; H.jk = inst->d_jk; H.ecore = e_core;
+  H.h = inst->d_h; H.eri = inst->d_eri; H.jk = inst->d_jk; H.s3 = inst->d_s3; H.ecore = e_core;
   H.K = K; H.na = n_alpha; H.nb = n_beta; H.va = K - n_alpha; H.vb = K - n_beta;
   const int64_t nsa = int64_t(n_alpha) * H.va, nsb = int64_t(n_beta) * H.vb;
   const int64_t daa = choose2(n_alpha) * choose2(H.va), dbb = choose2(n_beta) * choose2(H.vb);
