@@ -306,13 +306,8 @@ __global__ void k_validate(const uint64_t* samples, int64_t N, int K, int na, in
 // slab of one pair in LDS and serves every sample of a batch in which that pair
 // appears (hole and particle of the alpha spin for opposite-spin doubles, the
 // two holes for equal-spin ones), so a slab is read once per batch instead of
-// once per sample.  The ranks of one (sample, pair) form a contiguous block;
-// a wavefront walks it chunk by chunk, stores the chunks that lie wholly inside
-// and adds the two border chunks, which it shares with the neighbouring blocks,
-// with 64-bit atomics (exact in any order).  Singles go by sample.  A scan per
-// segment then turns the chunk sums into running sums.
-
-constexpr int kScrBatch = 256;   // samples per workgroup of the pair kernels (64 per wavefront)
+// once per sample.  Singles go by sample.  A scan per segment then turns the
+// chunk sums into running sums.
 
 // (n_alpha, n_beta) electrons and no bit beyond 2K: the samples whose elements exist
 __device__ inline bool onv_ok(const HamDev& H, uint64_t lo, uint64_t hi) {
@@ -338,18 +333,6 @@ __device__ inline uint64_t lane_u64(uint64_t x, int l) {
   const uint32_t a = uint32_t(__builtin_amdgcn_readlane(int(uint32_t(x)), l));
   const uint32_t b = uint32_t(__builtin_amdgcn_readlane(int(uint32_t(x >> 32)), l));
   return (uint64_t(b) << 32) | a;
-}
-
-// the occupied and the virtual orbitals of one spin, ascending (lane p looks at orbital p)
-__device__ inline void spin_lists(const HamDev& H, uint64_t lo, uint64_t hi, int sigma, uint8_t* occ, uint8_t* vir) {
-  const int p = lane_id();
-  const bool in = p < H.K;
-  const bool x = in && bit_at(lo, hi, 2 * p + sigma);
-  const int r = __popcll(__ballot(x) & __lanemask_lt());
-  if (in) {
-    if (x) occ[r] = uint8_t(p); else vir[p - r] = uint8_t(p);
-  }
-  wave_sync();
 }
 
 __device__ inline void screen(double hv, double eps, int qshift, bool valid, bool& det, uint64_t& q) {
@@ -410,22 +393,78 @@ __global__ __launch_bounds__(256) void k_scr_singles(HamDev H, EnumGeom G, const
             [&](uint32_t r) { return element<false>(H, L, lo, hi, r).H; });
 }
 
+// Pair kernels.  What screening makes of a double excitation's |H_nm| depends
+// on the four orbitals only, so a workgroup codes its slab once when it stages
+// it: -1 for a deterministic element, else the proposal weight (0 for a
+// vanishing one), an integer below 2^41 that FP64 holds exactly, as it holds
+// every sum of 64 of them.  The ranks of one (sample, pair) form a contiguous
+// block; a wavefront turns the blocks of its 64 samples into a list of chunk
+// tasks and gives each lane one chunk, which the lane walks rank by rank with
+// incremental indices, collecting its own deterministic bits and weight sum: no
+// cross-lane reduction per chunk.  A chunk wholly inside its block is stored;
+// a border chunk, shared with the neighbouring pair's block, is added with
+// 64-bit atomics (exact in any order).
+
+constexpr int kScrWaves = 4;                // wavefronts per workgroup of the pair kernels
+constexpr int kScrBatch = 64 * kScrWaves;   // samples per workgroup (64 per wavefront)
+
+__device__ inline double scr_code(double hv, double eps, int qshift) {
+  if (hv == 0.0) return 0.0;
+  const double ah = fabs(hv);
+  return ah >= eps ? -1.0 : ceil(ldexp(ah, qshift));
+}
+
+// the largest s with first[s] <= t (first ascending over 64 slots, first[0] = 0)
+__device__ inline int scr_slot(const int* first, int t) {
+  int s = 0;
+  for (int step = 32; step > 0; step >>= 1) s += first[s + step] <= t ? step : 0;
+  return s;
+}
+
+// one lane's chunk after its walk over the ranks k0 <= k < k1 of it: bits
+// holds the deterministic flags shifted in from the top (rank k1 - 1 at bit
+// 63), qacc the sum of the codes, i.e. the weight sum minus the number of
+// deterministic ranks (integers below 2^47, exact in FP64).  A chunk wholly
+// inside its block is stored, a border chunk added.
+__device__ inline void scr_finish(uint64_t* masks, uint64_t* qsum, int64_t at, int k0, int k1, uint64_t bits,
+                                  double qacc) {
+  bits = k1 == 64 ? bits : (bits >> (64 - k1));
+  const uint64_t q = uint64_t(qacc + double(__popcll(bits)));
+  if (k0 == 0 && k1 == 64) {
+    masks[at] = bits;
+    qsum[at] = q;
+  } else {
+    if (bits) atomicOr((unsigned long long*)(masks + at), (unsigned long long)bits);
+    if (q) atomicAdd((unsigned long long*)(qsum + at), (unsigned long long)q);
+  }
+}
+
+// per-wavefront LDS of the pair kernels: orbital lists of its 64 samples
+// (stride bytes each, a multiple of 4; nlist lists per sample), then per
+// sample its first task, its block starts and its number of spin-0 tasks
+__host__ __device__ inline size_t scr_wave_bytes(int stride, int nlist) {
+  return size_t(64) * stride * nlist + 4 * 64 * sizeof(int);
+}
+
 // opposite-spin doubles (i alpha -> a alpha, j beta -> b beta), workgroup per
-// (i, a), i != a, and batch of samples: slab (ia|jb) over (j, b), contiguous in HBM
-__global__ __launch_bounds__(256) void k_scr_os(HamDev H, EnumGeom G, const uint64_t* samples, int64_t N,
-                                                double eps, int qshift, uint64_t* masks, uint64_t* qsum) {
+// (i, a), i != a, and batch of samples: slab (ia|jb) over (j, b), contiguous in
+// HBM.  A sample's list holds its beta orbitals, occupied then virtual.
+__global__ __launch_bounds__(64 * kScrWaves) void k_scr_os(HamDev H, EnumGeom G, const uint64_t* samples, int64_t N,
+                                                           double eps, int qshift, int stride, uint64_t* masks,
+                                                           uint64_t* qsum) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int K = H.K;
   const int i = int(blockIdx.x) / (K - 1), t = int(blockIdx.x) % (K - 1);
   const int a = t + (t >= i ? 1 : 0);
-  double* slab = reinterpret_cast<double*>(smem);
+  double* code = reinterpret_cast<double*>(smem);
   const int wv = threadIdx.x >> 6, lane = lane_id();
-  uint8_t* occ = smem + size_t(K) * K * 8 + wv * 128;
-  uint8_t* vir = occ + 64;
+  uint8_t* orb = smem + size_t(K) * K * 8 + wv * scr_wave_bytes(stride, 1);
+  int* first = reinterpret_cast<int*>(orb + 64 * stride);
+  uint32_t* rbs = reinterpret_cast<uint32_t*>(first + 64);
   const double* src = H.eri + (size_t(i) * K + a) * K * K;
-  for (int u = threadIdx.x; u < K * K; u += blockDim.x) slab[u] = src[u];
-  __syncthreads();
-  const int64_t n = int64_t(blockIdx.y) * kScrBatch + wv * 64 + lane;
+  for (int u = threadIdx.x; u < K * K; u += blockDim.x) code[u] = scr_code(src[u], eps, qshift);
+  const int64_t nbase = int64_t(blockIdx.y) * kScrBatch + wv * 64;
+  const int64_t n = nbase + lane;
   uint64_t lo = 0, hi = 0;
   bool ok = false;
   if (n < N) {
@@ -433,70 +472,154 @@ __global__ __launch_bounds__(256) void k_scr_os(HamDev H, EnumGeom G, const uint
     hi = samples[2 * n + 1];
     ok = bit_at(lo, hi, 2 * i) && !bit_at(lo, hi, 2 * a) && onv_ok(H, lo, hi);
   }
+  const uint32_t nsb = H.nsb;
+  uint32_t rb = 0, nck = 0;
+  if (ok) {
+    const uint32_t ii = uint32_t(occ_below_spin(lo, hi, i, 0));
+    const uint32_t aa = uint32_t(a - occ_below_spin(lo, hi, a, 0));
+    rb = H.off_dab + (ii * uint32_t(H.va) + aa) * nsb;
+    nck = ((rb + nsb - 1u) >> 6) - (rb >> 6) + 1u;
+  }
   for (uint64_t todo = __ballot(ok); todo; todo &= todo - 1) {
     const int l = __ffsll((unsigned long long)todo) - 1;
     const uint64_t slo = lane_u64(lo, l), shi = lane_u64(hi, l);
-    const uint32_t ii = uint32_t(occ_below_spin(slo, shi, i, 0));
-    const uint32_t aa = uint32_t(a - occ_below_spin(slo, shi, a, 0));
-    spin_lists(H, slo, shi, 1, occ, vir);
-    const uint32_t rb = H.off_dab + (ii * uint32_t(H.va) + aa) * H.nsb;
-    const int64_t sn = int64_t(blockIdx.y) * kScrBatch + wv * 64 + l;
-    scr_block(masks, qsum, sn * G.nchunks, rb, rb + H.nsb, eps, qshift, [&](uint32_t e) {
-      const uint32_t jj = mdiv(e, H.mg_vb);
-      const uint32_t bb = e - jj * uint32_t(H.vb);
-      return slab[int(occ[jj]) * K + int(vir[bb])];
-    });
-    wave_sync();   // the lists are rewritten for the next sample
+    const bool in = lane < K;
+    const bool x = in && bit_at(slo, shi, 2 * lane + 1);
+    const int r = __popcll(__ballot(x) & __lanemask_lt());
+    if (in) orb[l * stride + (x ? r : H.nb + (lane - r))] = uint8_t(lane);
+  }
+  const uint32_t incl = uint32_t(wave_incl_scan_u64(nck));
+  first[lane] = int(incl - nck);
+  rbs[lane] = rb;
+  const int T = int(lane_u64(incl, 63));
+  __syncthreads();
+  const int nb = H.nb, vb = H.vb;
+  for (int t0 = 0; t0 < T; t0 += 64) {
+    const int tk = t0 + lane;
+    if (tk >= T) break;
+    const int s = scr_slot(first, tk);
+    const uint32_t b0 = rbs[s], b1 = b0 + nsb;
+    const uint32_t c = (b0 >> 6) + uint32_t(tk - first[s]);
+    const uint32_t cb = c * 64u;
+    const int k0 = int(max(b0, cb) - cb), k1 = int(min(b1, cb + 64u) - cb);
+    const uint32_t e = cb + uint32_t(k0) - b0;
+    const uint8_t* ol = orb + s * stride;
+    int jj = int(mdiv(e, H.mg_vb));
+    int vx = nb + int(e) - jj * vb;                 // list index of the beta particle
+    uint32_t rowoff = __umul24(ol[jj], uint32_t(K));
+    uint64_t bits = 0;
+    double qacc = 0.0;
+    for (int k = k0; k < k1; ++k) {
+      const double cv = code[rowoff + ol[vx]];
+      bits = (bits >> 1) | (cv < 0.0 ? 0x8000000000000000ull : 0ull);
+      qacc += cv;
+      const bool wrap = ++vx == K;
+      jj += wrap ? 1 : 0;
+      vx = wrap ? nb : vx;
+      rowoff = __umul24(ol[jj], uint32_t(K));
+    }
+    scr_finish(masks, qsum, (nbase + s) * G.nchunks + c, k0, k1, bits, qacc);
   }
 }
 
 // equal-spin doubles (i < j -> a < b, both spins), workgroup per hole pair
-// (i, j) and batch of samples: slab S[a][b] = (ia|jb); (ja|ib) = S[b][a] as the
-// stored integrals are exactly 8-fold symmetric
-__global__ __launch_bounds__(256) void k_scr_ss(HamDev H, EnumGeom G, const uint64_t* samples, int64_t N,
-                                                double eps, int qshift, uint64_t* masks, uint64_t* qsum) {
+// (i, j) and batch of samples: slab (ia|jb) - (ja|ib) over (a, b), where
+// (ja|ib) = (ib|ja) is the transposed entry as the stored integrals are exactly
+// 8-fold symmetric.  A sample's lists hold its virtual orbitals of each spin.
+__global__ __launch_bounds__(64 * kScrWaves) void k_scr_ss(HamDev H, EnumGeom G, const uint64_t* samples, int64_t N,
+                                                           double eps, int qshift, int stride, uint64_t* masks,
+                                                           uint64_t* qsum) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int K = H.K;
   int i, j;
   unpair(blockIdx.x, K, i, j);
-  double* slab = reinterpret_cast<double*>(smem);
+  double* code = reinterpret_cast<double*>(smem);
   const int wv = threadIdx.x >> 6, lane = lane_id();
-  uint8_t* occ = smem + size_t(K) * K * 8 + wv * 128;
-  uint8_t* vir = occ + 64;
+  uint8_t* vl = smem + size_t(K) * K * 8 + wv * scr_wave_bytes(stride, 2);
+  int* first = reinterpret_cast<int*>(vl + 2 * 64 * stride);
+  uint32_t* rbs = reinterpret_cast<uint32_t*>(first + 64);   // [2][64]
+  int* nck0s = reinterpret_cast<int*>(rbs + 128);
+  // stage (ia|jb) over (a, b), then code the upper triangle a < b (the only
+  // entries read) in place: entry (a, b) and its transpose belong to one thread
   for (int u = threadIdx.x; u < K * K; u += blockDim.x) {
     const int a = u / K, b = u % K;
-    slab[u] = H.eri[((size_t(i) * K + a) * K + j) * K + b];
+    code[u] = H.eri[((size_t(i) * K + a) * K + j) * K + b];
   }
   __syncthreads();
-  const int64_t n = int64_t(blockIdx.y) * kScrBatch + wv * 64 + lane;
+  for (int u = threadIdx.x; u < K * K; u += blockDim.x) {
+    const int a = u / K, b = u % K;
+    if (a < b) code[u] = scr_code(code[u] - code[b * K + a], eps, qshift);
+  }
+  const int64_t nbase = int64_t(blockIdx.y) * kScrBatch + wv * 64;
+  const int64_t n = nbase + lane;
   uint64_t lo = 0, hi = 0;
-  bool ok = false;
+  bool okv = false;
   if (n < N) {
     lo = samples[2 * n];
     hi = samples[2 * n + 1];
-    ok = ((bit_at(lo, hi, 2 * i) && bit_at(lo, hi, 2 * j)) || (bit_at(lo, hi, 2 * i + 1) && bit_at(lo, hi, 2 * j + 1))) &&
-         onv_ok(H, lo, hi);
+    okv = onv_ok(H, lo, hi);
   }
-  for (uint64_t todo = __ballot(ok); todo; todo &= todo - 1) {
-    const int l = __ffsll((unsigned long long)todo) - 1;
-    const uint64_t slo = lane_u64(lo, l), shi = lane_u64(hi, l);
-    const int64_t sn = int64_t(blockIdx.y) * kScrBatch + wv * 64 + l;
-    for (int sg = 0; sg < 2; ++sg) {
-      if (!bit_at(slo, shi, 2 * i + sg) || !bit_at(slo, shi, 2 * j + sg)) continue;
-      const int ne = sg ? H.nb : H.na, nv = sg ? H.vb : H.va;
-      const int ii = occ_below_spin(slo, shi, i, sg), jj = occ_below_spin(slo, shi, j, sg);
-      const uint32_t pij = uint32_t(pair_start(ii, ne) + (jj - ii - 1));
-      const uint32_t npv = sg ? H.npb_v : H.npa_v;
-      const uint32_t rb = (sg ? H.off_dbb : H.off_daa) + pij * npv;
-      spin_lists(H, slo, shi, sg, occ, vir);
-      scr_block(masks, qsum, sn * G.nchunks, rb, rb + npv, eps, qshift, [&](uint32_t pab) {
-        int aa, bb;
-        unpair(pab, nv, aa, bb);
-        const int av = vir[aa], bv = vir[bb];
-        return slab[av * K + bv] - slab[bv * K + av];
-      });
-      wave_sync();
+  // per spin: the block [rb, rb + npv) when both holes are occupied
+  uint32_t rbv[2] = {0u, 0u}, nck[2] = {0u, 0u};
+  bool ok[2];
+  for (int sg = 0; sg < 2; ++sg) {
+    ok[sg] = okv && bit_at(lo, hi, 2 * i + sg) && bit_at(lo, hi, 2 * j + sg);
+    const uint32_t npv = sg ? H.npb_v : H.npa_v;
+    if (ok[sg] && npv > 0u) {
+      const int ne = sg ? H.nb : H.na;
+      const int ii = occ_below_spin(lo, hi, i, sg), jj = occ_below_spin(lo, hi, j, sg);
+      rbv[sg] = (sg ? H.off_dbb : H.off_daa) + uint32_t(pair_start(ii, ne) + (jj - ii - 1)) * npv;
+      nck[sg] = ((rbv[sg] + npv - 1u) >> 6) - (rbv[sg] >> 6) + 1u;
     }
+    for (uint64_t todo = __ballot(nck[sg] > 0u); todo; todo &= todo - 1) {
+      const int l = __ffsll((unsigned long long)todo) - 1;
+      const uint64_t slo = lane_u64(lo, l), shi = lane_u64(hi, l);
+      const bool in = lane < K;
+      const bool x = in && bit_at(slo, shi, 2 * lane + sg);
+      const int r = __popcll(__ballot(x) & __lanemask_lt());
+      if (in && !x) vl[(sg * 64 + l) * stride + (lane - r)] = uint8_t(lane);
+    }
+  }
+  const uint32_t tot = nck[0] + nck[1];
+  const uint32_t incl = uint32_t(wave_incl_scan_u64(tot));
+  first[lane] = int(incl - tot);
+  rbs[lane] = rbv[0];
+  rbs[64 + lane] = rbv[1];
+  nck0s[lane] = int(nck[0]);
+  const int T = int(lane_u64(incl, 63));
+  __syncthreads();
+  for (int t0 = 0; t0 < T; t0 += 64) {
+    const int tk = t0 + lane;
+    if (tk >= T) break;
+    const int s = scr_slot(first, tk);
+    int u = tk - first[s];
+    const int n0 = nck0s[s];
+    const int sg = u < n0 ? 0 : 1;
+    u -= sg ? n0 : 0;
+    const uint32_t npv = sg ? H.npb_v : H.npa_v;
+    const uint32_t b0 = rbs[sg * 64 + s];
+    const uint32_t b1 = b0 + npv;
+    const uint32_t c = (b0 >> 6) + uint32_t(u);
+    const uint32_t cb = c * 64u;
+    const int k0 = int(max(b0, cb) - cb), k1 = int(min(b1, cb + 64u) - cb);
+    const uint32_t e = cb + uint32_t(k0) - b0;
+    const int nv = sg ? H.vb : H.va;
+    const uint8_t* ls = vl + (sg * 64 + s) * stride;
+    int aa, bb;
+    unpair(e, nv, aa, bb);
+    uint32_t rowoff = __umul24(ls[aa], uint32_t(K));
+    uint64_t bits = 0;
+    double qacc = 0.0;
+    for (int k = k0; k < k1; ++k) {
+      const double cv = code[rowoff + ls[bb]];
+      bits = (bits >> 1) | (cv < 0.0 ? 0x8000000000000000ull : 0ull);
+      qacc += cv;
+      const bool wrap = ++bb == nv;
+      aa += wrap ? 1 : 0;
+      bb = wrap ? aa + 1 : bb;
+      rowoff = __umul24(ls[aa], uint32_t(K));
+    }
+    scr_finish(masks, qsum, (nbase + s) * G.nchunks + c, k0, k1, bits, qacc);
   }
 }
 
@@ -875,8 +998,12 @@ hipError_t launch_enum_count(const HamDev& H, const EnumGeom& G, const uint64_t*
                        masks, qpref);
   // pair kernels: grid x = orbital pairs (K(K-1)/2 hole pairs i < j, K(K-1)
   // hole-particle pairs i != a), y = batches of kScrBatch samples (launched in
-  // slices of at most 65535 batches)
-  const size_t lds = size_t(H.K) * H.K * 8 + 4 * 128;
+  // slices of at most 65535 batches); LDS: the coded slab and per wavefront the
+  // orbital lists of its samples
+  const int st_os = (H.K + 3) & ~3, st_ss = (std::max(H.va, H.vb) + 3) & ~3;
+  const size_t slab = size_t(H.K) * H.K * 8;
+  const size_t lds_os = slab + kScrWaves * scr_wave_bytes(st_os, 1);
+  const size_t lds_ss = slab + kScrWaves * scr_wave_bytes(st_ss, 2);
   const int64_t nbatch = (N + kScrBatch - 1) / kScrBatch;
   for (int64_t b0 = 0; b0 < nbatch; b0 += 65535) {
     const int64_t nb = std::min<int64_t>(nbatch - b0, 65535);
@@ -885,11 +1012,11 @@ hipError_t launch_enum_count(const HamDev& H, const EnumGeom& G, const uint64_t*
     uint64_t* mk = masks + b0 * kScrBatch * G.nchunks;
     uint64_t* qs = qpref + b0 * kScrBatch * G.nchunks;
     if (H.off_dab > H.off_daa)
-      hipLaunchKernelGGL(k_scr_ss, dim3(unsigned(H.K * (H.K - 1) / 2), unsigned(nb)), dim3(256), lds, st, H, G, sm, Nb, eps,
-                         qshift, mk, qs);
+      hipLaunchKernelGGL(k_scr_ss, dim3(unsigned(H.K * (H.K - 1) / 2), unsigned(nb)), dim3(64 * kScrWaves), lds_ss, st,
+                         H, G, sm, Nb, eps, qshift, st_ss, mk, qs);
     if (H.n_conn > H.off_dab)
-      hipLaunchKernelGGL(k_scr_os, dim3(unsigned(H.K * (H.K - 1)), unsigned(nb)), dim3(256), lds, st, H, G, sm, Nb, eps,
-                         qshift, mk, qs);
+      hipLaunchKernelGGL(k_scr_os, dim3(unsigned(H.K * (H.K - 1)), unsigned(nb)), dim3(64 * kScrWaves), lds_os, st,
+                         H, G, sm, Nb, eps, qshift, st_os, mk, qs);
   }
   hipLaunchKernelGGL(k_scr_scan, dim3(grid_for(N * G.S, 4)), dim3(256), 0, st, G, N, masks, qpref, segq, segd);
   return hipGetLastError();
