@@ -4,6 +4,7 @@
 //   * the per-sample local-energy reduction (Eqs. (6), (18), (22)) and the
 //     batch sums of Sec. 2.3.
 #include "internal.h"
+#include <algorithm>
 #include <cmath>
 
 namespace nqs {
@@ -39,67 +40,164 @@ __device__ inline float tcos(float x) { return cosf(x); }
 __device__ inline double tabs(double x) { return fabs(x); }
 __device__ inline float tabs(float x) { return fabsf(x); }
 
+// cos in FP64 for |x| < 2^20 as a sine: x = (2q+1) pi/2 + r with |r| <= pi/2
+// by a Cody-Waite reduction with a two-constant FMA split of pi/2 (the first
+// FMA is exact, so r carries an absolute error near 2^-105 |q|), and
+// cos x = (-1)^(q+1) sin r with sin r from its Taylor series to r^21 (the
+// truncation term stays below 2^-59): r + r z (-1/6 + z P(z)), z = r^2, the
+// high-order terms of P by pairs.  Within 2 ulp of the true cosine and within
+// 2.3e-16 relative, also near its zeros (where r is small), against a
+// long-double cosine on the host.  Larger or non-finite arguments take the
+// library cosine.
+__device__ inline double cos_cw(double x) {
+  if (!(fabs(x) < 1048576.0)) return cos(x);
+  const double q = floor(x * 0.31830988618379067154);
+  const double q2 = fma(2.0, q, 1.0);
+  double r = fma(-q2, 1.5707963267948966, x);
+  r = fma(-q2, 6.123233995736766e-17, r);
+  const double z = r * r, z2 = z * z, z4 = z2 * z2;
+  const double p23 = fma(-1.0 / 5040.0, z, 1.0 / 120.0);
+  const double p45 = fma(-1.0 / 39916800.0, z, 1.0 / 362880.0);
+  const double p67 = fma(-1.0 / 1307674368000.0, z, 1.0 / 6227020800.0);
+  const double p89 = fma(-1.0 / 121645100408832000.0, z, 1.0 / 355687428096000.0);
+  const double p810 = fma(1.0 / 51090942171709440000.0, z2, p89);
+  const double P = fma(fma(p810, z2, p67), z4, fma(p45, z2, p23));
+  const double sn = fma(r * z, fma(P, z, -1.0 / 6.0), r);
+  return (int(q) & 1) ? sn : -sn;
+}
+
 // theta(m) = theta(n) + sum_{created P} W_:P - sum_{annihilated P} W_:P; one
 // thread per row.  FP32: cos and log per hidden unit in FP32, the sum of logs
 // in FP64 (the form the FP32 error bound is stated for).  FP64: the product of
 // the cosines with a power of two split off every 8 factors (|cos| of a
 // rounded angle stays far above 2^-128, so 8 factors cannot underflow), and
 // one log per row: log |prod_k cos| = log |mantissa| + exponent log 2.
+//
+// A row of the local energy differs from its sample by at most two created
+// and two annihilated spin orbitals, and their weights are read without
+// branches: an absent change reads a zero (theta + 0 is theta), and the loads
+// of hidden unit k + 1 are issued before the cosine of unit k.  With LDS, a
+// persistent workgroup per CU stages W as [k][2K + 1] with a zero last column
+// (the index of an absent change), so the only vector-memory load per hidden
+// unit is theta(n); without (W too large for LDS), W is read through a buffer
+// resource where an absent change takes the offset of W's end, which the range
+// check turns into a zero read.  Other rows take a plain loop over the changed
+// orbitals.
 template <typename T>
-__global__ void k_corr_rows(CorrParams C, const uint64_t* m, const int32_t* owner,
-                            const uint64_t* samples, const double* theta, int64_t R, double* lf,
-                            int8_t* sf) {
-  const int64_t r = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (r >= R) return;
-  const int64_t o = owner[r];
-  const uint64_t mlo = m[2 * r], mhi = m[2 * r + 1];
-  const uint64_t nlo = samples[2 * o], nhi = samples[2 * o + 1];
-  int add[4], rem[4], na = 0, nr = 0;
-  uint64_t x = mlo & ~nlo;
-  while (x && na < 4) { add[na++] = __ffsll((unsigned long long)x) - 1; x &= x - 1; }
-  x = mhi & ~nhi;
-  while (x && na < 4) { add[na++] = 64 + __ffsll((unsigned long long)x) - 1; x &= x - 1; }
-  x = nlo & ~mlo;
-  while (x && nr < 4) { rem[nr++] = __ffsll((unsigned long long)x) - 1; x &= x - 1; }
-  x = nhi & ~mhi;
-  while (x && nr < 4) { rem[nr++] = 64 + __ffsll((unsigned long long)x) - 1; x &= x - 1; }
-  const int nv = 2 * C.K;
-  const double* th0 = theta + o * C.nh;
-  double acc = 0.0;
-  int s = 1;
-  if constexpr (sizeof(T) == 8) {
-    double pm = 1.0;
-    int pe = 0;
-    for (int k = 0; k < C.nh; ++k) {
-      double th = th0[k];
-      const double* Wk = C.W + size_t(k) * nv;
-      for (int a = 0; a < na; ++a) th += Wk[add[a]];
-      for (int a = 0; a < nr; ++a) th -= Wk[rem[a]];
-      pm *= cos(th);
-      if ((k & 7) == 7) {
-        int e;
-        pm = frexp(pm, &e);
-        pe += e;
-      }
-    }
-    int e;
-    pm = frexp(pm, &e);
-    pe += e;
-    acc = log(fabs(pm)) + double(pe) * 0.69314718055994530942;
-    s = pm < 0.0 ? -1 : 1;
-  } else {
-    for (int k = 0; k < C.nh; ++k) {
-      double th = th0[k];
-      const double* Wk = C.W + size_t(k) * nv;
-      for (int a = 0; a < na; ++a) th += Wk[add[a]];
-      for (int a = 0; a < nr; ++a) th -= Wk[rem[a]];
+struct CorrAcc {
+  double pm = 1.0, acc = 0.0;
+  int pe = 0, s = 1;
+  __device__ void add(double th) {
+    if constexpr (sizeof(T) == 8) {
+      pm *= cos_cw(th);
+    } else {
       const T c = tcos(T(th));
       acc += double(tlog(tabs(c)));
       if (c < T(0)) s = -s;
     }
   }
-  lf[r] = acc;
-  sf[r] = int8_t(s);
+  __device__ void split() {
+    if constexpr (sizeof(T) == 8) {
+      int e;
+      pm = frexp(pm, &e);
+      pe += e;
+    }
+  }
+  __device__ void finish(double& lfo, int8_t& sfo) {
+    if constexpr (sizeof(T) == 8) {
+      int e;
+      const double m = frexp(pm, &e);
+      acc = log(fabs(m)) + double(pe + e) * 0.69314718055994530942;
+      s = m < 0.0 ? -1 : 1;
+    }
+    lfo = acc;
+    sfo = int8_t(s);
+  }
+};
+
+__device__ inline int low_bit(uint64_t lo, uint64_t hi) {
+  return lo ? __ffsll((unsigned long long)lo) - 1 : 64 + __ffsll((unsigned long long)hi) - 1;
+}
+
+constexpr int kCorrLdsThreads = 1024;
+constexpr size_t kCorrLdsMax = 128 * 1024;   // largest LDS copy of W
+
+template <typename T, bool LDS>
+__global__ __launch_bounds__(LDS ? kCorrLdsThreads : 256) void k_corr_rows(
+    CorrParams C, const uint64_t* m, const int32_t* owner, const uint64_t* samples, const double* theta, int64_t R,
+    double* lf, int8_t* sf) {
+  extern __shared__ double wl[];
+  const int nv = 2 * C.K, nh = C.nh, ws = nv + 1;
+  if constexpr (LDS) {
+    for (int u = threadIdx.x; u < nh * ws; u += blockDim.x) {
+      const int k = u / ws, P = u - k * ws;
+      wl[u] = P < nv ? C.W[size_t(k) * nv + P] : 0.0;
+    }
+    __syncthreads();
+  }
+  const uint32_t wbytes = uint32_t(nh) * uint32_t(nv) * 8u;
+  const __amdgpu_buffer_rsrc_t wr =
+      __builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(C.W), short(0), int(wbytes), 0x00020000);
+  const int64_t step = LDS ? int64_t(gridDim.x) * blockDim.x : R;
+  for (int64_t r = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; r < R; r += step) {
+    const int64_t o = owner[r];
+    const uint64_t mlo = m[2 * r], mhi = m[2 * r + 1];
+    const uint64_t nlo = samples[2 * o], nhi = samples[2 * o + 1];
+    uint64_t alo = mlo & ~nlo, ahi = mhi & ~nhi, rlo = nlo & ~mlo, rhi = nhi & ~mhi;
+    const int na = __popcll(alo) + __popcll(ahi), nr = __popcll(rlo) + __popcll(rhi);
+    const double* th0 = theta + o * nh;
+    CorrAcc<T> A;
+    if (na > 2 || nr > 2) {
+      for (int k = 0; k < nh; ++k) {
+        double th = th0[k];
+        for (uint64_t x = alo, y = ahi; x | y;) {
+          th += C.W[size_t(k) * nv + low_bit(x, y)];
+          if (x) x &= x - 1; else y &= y - 1;
+        }
+        for (uint64_t x = rlo, y = rhi; x | y;) {
+          th -= C.W[size_t(k) * nv + low_bit(x, y)];
+          if (x) x &= x - 1; else y &= y - 1;
+        }
+        A.add(th);
+        if ((k & 7) == 7) A.split();
+      }
+      A.finish(lf[r], sf[r]);
+      continue;
+    }
+    // created a0 < a1 and annihilated r0 < r1: LDS element offsets (absent:
+    // the zero column), or byte offsets into a row of W (absent: W's end)
+    const uint32_t absent = LDS ? uint32_t(nv) : wbytes;
+    const uint32_t unit = LDS ? 1u : 8u;
+    const uint32_t a0 = na > 0 ? uint32_t(low_bit(alo, ahi)) * unit : absent;
+    if (alo) alo &= alo - 1; else ahi &= ahi - 1;
+    const uint32_t a1 = na > 1 ? uint32_t(low_bit(alo, ahi)) * unit : absent;
+    const uint32_t r0 = nr > 0 ? uint32_t(low_bit(rlo, rhi)) * unit : absent;
+    if (rlo) rlo &= rlo - 1; else rhi &= rhi - 1;
+    const uint32_t r1 = nr > 1 ? uint32_t(low_bit(rlo, rhi)) * unit : absent;
+    auto ld = [&](uint32_t off, int k) -> double {
+      if constexpr (LDS) {
+        return wl[k * ws + int(off)];
+      } else {
+        return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(wr, off, k * nv * 8, 0));
+      }
+    };
+    double t = th0[0], wa0 = ld(a0, 0), wa1 = ld(a1, 0), wr0 = ld(r0, 0), wr1 = ld(r1, 0);
+    for (int k8 = 0; k8 < nh; k8 += 8) {
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int k = k8 + j;
+        if (k >= nh) break;
+        const double th = (((t + wa0) + wa1) - wr0) - wr1;
+        if (k + 1 < nh) {
+          t = th0[k + 1];
+          wa0 = ld(a0, k + 1); wa1 = ld(a1, k + 1); wr0 = ld(r0, k + 1); wr1 = ld(r1, k + 1);
+        }
+        A.add(th);
+      }
+      A.split();
+    }
+    A.finish(lf[r], sf[r]);
+  }
 }
 
 // direct evaluation for arbitrary ONVs (no owner): theta = b + W x
@@ -539,12 +637,29 @@ hipError_t launch_corr_rows(const CorrParams& C, const uint64_t* m, const int32_
                          st, C, C.S32, m, owner, samples, theta, (const float*)E, R, lf, sf);
     return hipGetLastError();
   }
-  if (precision == 0)
-    hipLaunchKernelGGL(k_corr_rows<double>, dim3(grid_for(R, 256)), dim3(256), 0, st, C, m, owner, samples,
+  // W in LDS when it fits: one persistent workgroup per CU (the device's CU
+  // count, read once per device); else a thread per row with W from L2
+  const size_t lds = size_t(C.nh) * (2 * C.K + 1) * sizeof(double);
+  if (lds <= kCorrLdsMax) {
+    static int cus[64] = {};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+    if (!cus[dev] && hipDeviceGetAttribute(&cus[dev], hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+      return hipErrorInvalidDevice;
+    const unsigned blocks = unsigned(std::min<int64_t>((R + kCorrLdsThreads - 1) / kCorrLdsThreads, cus[dev]));
+    if (precision == 0)
+      hipLaunchKernelGGL((k_corr_rows<double, true>), dim3(blocks), dim3(kCorrLdsThreads), lds, st, C, m, owner,
+                         samples, theta, R, lf, sf);
+    else
+      hipLaunchKernelGGL((k_corr_rows<float, true>), dim3(blocks), dim3(kCorrLdsThreads), lds, st, C, m, owner,
+                         samples, theta, R, lf, sf);
+  } else if (precision == 0) {
+    hipLaunchKernelGGL((k_corr_rows<double, false>), dim3(grid_for(R, 256)), dim3(256), 0, st, C, m, owner, samples,
                        theta, R, lf, sf);
-  else
-    hipLaunchKernelGGL(k_corr_rows<float>, dim3(grid_for(R, 256)), dim3(256), 0, st, C, m, owner, samples,
+  } else {
+    hipLaunchKernelGGL((k_corr_rows<float, false>), dim3(grid_for(R, 256)), dim3(256), 0, st, C, m, owner, samples,
                        theta, R, lf, sf);
+  }
   return hipGetLastError();
 }
 

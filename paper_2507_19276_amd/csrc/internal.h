@@ -189,10 +189,10 @@ struct CorrParams {
   int K, nh;
   const double* b;   // [nh]
   const double* W;   // [nh][2K]
-  // Ising-RBM (ising != 0): W transposed [2K][nh] and the symmetric part of
-  // the quadratic couplings S[P][Q][k] = (W2[k][P][Q] + W2[k][Q][P]) / 2
+  const double* W1t = nullptr;   // W transposed [2K][nh]
+  // Ising-RBM (ising != 0): the symmetric part of the quadratic couplings
+  // S[P][Q][k] = (W2[k][P][Q] + W2[k][Q][P]) / 2
   int ising = 0;
-  const double* W1t = nullptr;
   const double* S = nullptr;
   const float* S32 = nullptr;   // S rounded to FP32 (reduced-precision paths)
 };

@@ -1257,18 +1257,20 @@ nqs_status nqs_ansatz_bind_params(nqs_ansatz* ans, const double* params, hipStre
     std::vector<double> W(prm.begin() + ans->offWc, prm.begin() + ans->offWc + int64_t(nh) * nv);
     if ((st = upload(&ans->d_cb, b)) != NQS_OK) return st;
     if ((st = upload(&ans->d_cW, W)) != NQS_OK) return st;
+    // hidden unit fastest: W^T [P][k] (both correlators' row kernels read it)
+    std::vector<double> Wt(size_t(nv) * nh);
+    for (int k = 0; k < nh; ++k)
+      for (int P = 0; P < nv; ++P) Wt[size_t(P) * nh + k] = W[size_t(k) * nv + P];
+    if ((st = upload(&ans->d_cW1t, Wt)) != NQS_OK) return st;
     if (ans->ising) {
-      // hidden unit fastest: W^T [P][k] and S [P][Q][k] = (W2[k][P][Q] + W2[k][Q][P]) / 2
-      std::vector<double> Wt(size_t(nv) * nh), Sy(size_t(nv) * nv * nh);
+      // S [P][Q][k] = (W2[k][P][Q] + W2[k][Q][P]) / 2
+      std::vector<double> Sy(size_t(nv) * nv * nh);
       const double* W2 = prm.data() + ans->offW2;
       for (int k = 0; k < nh; ++k)
-        for (int P = 0; P < nv; ++P) {
-          Wt[size_t(P) * nh + k] = W[size_t(k) * nv + P];
+        for (int P = 0; P < nv; ++P)
           for (int Q = 0; Q < nv; ++Q)
             Sy[(size_t(P) * nv + Q) * nh + k] =
                 0.5 * (W2[(size_t(k) * nv + P) * nv + Q] + W2[(size_t(k) * nv + Q) * nv + P]);
-        }
-      if ((st = upload(&ans->d_cW1t, Wt)) != NQS_OK) return st;
       if ((st = upload(&ans->d_cS, Sy)) != NQS_OK) return st;
       std::vector<float> Sy32(Sy.begin(), Sy.end());
       if ((st = upload(&ans->d_cS32, Sy32)) != NQS_OK) return st;
