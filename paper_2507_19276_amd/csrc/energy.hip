@@ -66,12 +66,32 @@ __device__ inline double cos_cw(double x) {
   return (int(q) & 1) ? sn : -sn;
 }
 
+// The same in FP32 for |x| < 2^15 (a two-constant FMA split of pi/2 in FP32,
+// sin r to r^13: the truncation term stays below 2^-30): within 1.9 x 2^-24
+// absolute of the true cosine of the FP32 argument, against an FP64 cosine
+// on the host.  Larger or non-finite arguments take the library cosine.
+__device__ inline float cos_cw(float x) {
+  if (!(fabsf(x) < 32768.0f)) return cosf(x);
+  const float q = floorf(x * 0.318309886f);
+  const float q2 = fmaf(2.0f, q, 1.0f);
+  float r = fmaf(-q2, 1.57079637f, x);
+  r = fmaf(-q2, -4.37113883e-8f, r);
+  const float z = r * r;
+  float p = fmaf(1.0f / 6227020800.0f, z, -1.0f / 39916800.0f);
+  p = fmaf(p, z, 1.0f / 362880.0f);
+  p = fmaf(p, z, -1.0f / 5040.0f);
+  p = fmaf(p, z, 1.0f / 120.0f);
+  const float sn = fmaf(r * z, fmaf(p, z, -1.0f / 6.0f), r);
+  return (int(q) & 1) ? sn : -sn;
+}
+
 // theta(m) = theta(n) + sum_{created P} W_:P - sum_{annihilated P} W_:P; one
-// thread per row.  FP32: cos and log per hidden unit in FP32, the sum of logs
-// in FP64 (the form the FP32 error bound is stated for).  FP64: the product of
-// the cosines with a power of two split off every 8 factors (|cos| of a
-// rounded angle stays far above 2^-128, so 8 factors cannot underflow), and
-// one log per row: log |prod_k cos| = log |mantissa| + exponent log 2.
+// thread per row, theta in FP64.  The cosines are multiplied in FP64 with a
+// power of two split off every 8 factors (|cos| of a rounded angle stays far
+// above 2^-128, so 8 factors cannot underflow), and one FP64 log per row:
+// log |prod_k cos| = log |mantissa| + exponent log 2.  The FP32 form takes
+// each cosine in FP32 from theta rounded to FP32 (the form the FP32 error
+// bound is stated for: the product and the log add only FP64 roundings).
 //
 // A row of the local energy differs from its sample by at most two created
 // and two annihilated spin orbitals, and their weights are read without
@@ -85,33 +105,19 @@ __device__ inline double cos_cw(double x) {
 // orbitals.
 template <typename T>
 struct CorrAcc {
-  double pm = 1.0, acc = 0.0;
-  int pe = 0, s = 1;
-  __device__ void add(double th) {
-    if constexpr (sizeof(T) == 8) {
-      pm *= cos_cw(th);
-    } else {
-      const T c = tcos(T(th));
-      acc += double(tlog(tabs(c)));
-      if (c < T(0)) s = -s;
-    }
-  }
+  double pm = 1.0;
+  int pe = 0;
+  __device__ void add(double th) { pm *= double(cos_cw(T(th))); }
   __device__ void split() {
-    if constexpr (sizeof(T) == 8) {
-      int e;
-      pm = frexp(pm, &e);
-      pe += e;
-    }
+    int e;
+    pm = frexp(pm, &e);
+    pe += e;
   }
   __device__ void finish(double& lfo, int8_t& sfo) {
-    if constexpr (sizeof(T) == 8) {
-      int e;
-      const double m = frexp(pm, &e);
-      acc = log(fabs(m)) + double(pe + e) * 0.69314718055994530942;
-      s = m < 0.0 ? -1 : 1;
-    }
-    lfo = acc;
-    sfo = int8_t(s);
+    int e;
+    const double m = frexp(pm, &e);
+    lfo = log(fabs(m)) + double(pe + e) * 0.69314718055994530942;
+    sfo = int8_t(m < 0.0 ? -1 : 1);
   }
 };
 

@@ -8,7 +8,8 @@ operand as hi + lo BF16 parts, three products per MFMA step: the dropped
 lo.lo product and the parts' representation error are each below 2^-16 of a
 product); the correlator's cos theta is evaluated in FP32 on both paths from
 an FP64 theta, within a relative error u_f (1 + |theta|), u_f = 2^-22 (the
-rounding of theta plus cosf's own).  The oracle turns this into a bound per
+rounding of theta to FP32, the FP32 cosine's own error below 1.9 x 2^-24,
+and one FP64 product rounding per factor).  The oracle turns this into a bound per
 sample (oracle.eloc(..., bounds=BOUNDS(K), u_f=U_F)["ebound"]), summing over
 the terms of E_loc their |term| times how far the term can move."""
 import numpy as np
