@@ -162,6 +162,35 @@ def test_eloc_f32_bound(nqs, ctx):
     assert np.abs(got["logabs"] - ref["logabs"]).max() <= log_bound("f32", w.K)
 
 
+@pytest.mark.parametrize("nh", [203, 411])
+def test_correlator_hidden_widths(nqs, ctx, nh):
+    """A cos-RBM on the K = 20 chain with N_h = 203 (W in the correlator's LDS
+    copy, 203 x 41 x 8 B = 65 KB; N_h not a multiple of 8, so the last block
+    of the product is partial) and N_h = 411 (135 KB: past the 128 KB copy,
+    W read through the buffer form).  FP64 local energies and log|Psi| at the
+    FP64 bars, FP32 within the stated bound."""
+    w = W.make_workload("c2", n_samples=24)
+    params = W.ansatz_params(w.K, w.chi, w.parent_ptr, w.parent_idx, nh, seed=7100 + nh)
+    inst = nqs.Instance(ctx, w.K, w.n_alpha, w.n_beta, w.h, w.eri, w.e_core)
+    ans = nqs.Ansatz(ctx, w.K, w.n_alpha, w.n_beta, w.chi, w.parent_ptr, w.parent_idx, nh)
+    ans.bind(params)
+    ref = oracle.eloc(w.K, w.n_alpha, w.n_beta, w.h, w.eri, w.chi, w.parent_ptr, w.parent_idx, nh, params,
+                      w.samples, eps=w.eps, n_eps=w.n_eps, seed=w.seed, stream=1, bounds=bounds(w.K), u_f=U_F)
+    sens = oracle.amplitudes(w.K, w.chi, w.n_alpha, w.n_beta, w.parent_ptr, w.parent_idx, nh, params,
+                             w.samples)["corr_sens"]
+    assert np.all(ref["margin_f"] >= KAPPA_F)
+    for prec in ("f64", "f32"):
+        out, st = nqs.eloc(ctx, inst, ans, w.samples, eps=w.eps, n_eps=w.n_eps, precision=prec, seed=w.seed,
+                           stream_id=1)
+        got = {k: v.cpu().numpy() for k, v in out.items()}
+        if prec == "f64":
+            assert rel_err(got["eloc"], ref["eloc"]).max() <= 1e-10
+            assert np.abs(got["logabs"] - ref["logabs"]).max() < 1e-12
+        else:
+            assert np.all(np.abs(got["eloc"] - ref["eloc"]) <= stated_bound("f32", ref))
+            assert np.all(np.abs(got["logabs"] - ref["logabs"]) <= log_bound("f32", w.K) + U_F * sens)
+
+
 def test_counts_weight_batch_sums(nqs, ctx):
     w, inst, ans = setup(nqs, ctx, "c1")
     c = torch.arange(1, w.n_samples + 1, dtype=torch.float64)
