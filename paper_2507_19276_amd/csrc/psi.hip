@@ -501,6 +501,14 @@ __global__ __launch_bounds__(256) void k_psi_mt(PsiParams<T> P, const uint64_t* 
     int si[NTL];
 #pragma unroll
     for (int t = 0; t < NTL; ++t) si[t] = site_state(lo[t], hi[t], i);
+    // FP64: the drawn candidate as a one-hot blend (4 FP64 operations per
+    // double instead of 6 32-bit selects); the selected value plus signed
+    // zeros is that value
+    T oh[NTL][4];
+#pragma unroll
+    for (int t = 0; t < NTL; ++t)
+#pragma unroll
+      for (int s = 0; s < 4; ++s) oh[t][s] = si[t] == s ? T(1) : T(0);
     T pp[4][NTL], dp[NTL], dq[NTL];
 #pragma unroll
     for (int t = 0; t < NTL; ++t) {
@@ -527,9 +535,21 @@ __global__ __launch_bounds__(256) void k_psi_mt(PsiParams<T> P, const uint64_t* 
           q = tfma(ex.w, x[s].w, q);
           pp[s][t] = q;
         }
-        const V sel01 = (si[t] & 1) ? x[1] : x[0];
-        const V sel23 = (si[t] & 1) ? x[3] : x[2];
-        const V sel = (si[t] & 2) ? sel23 : sel01;
+        V sel;
+        if constexpr (sizeof(T) == 8 && !SAMPLE) {
+          sel = x[0] * oh[t][0];
+#pragma unroll
+          for (int s = 1; s < 4; ++s) {
+            sel.x = tfma(x[s].x, oh[t][s], sel.x);
+            sel.y = tfma(x[s].y, oh[t][s], sel.y);
+            sel.z = tfma(x[s].z, oh[t][s], sel.z);
+            sel.w = tfma(x[s].w, oh[t][s], sel.w);
+          }
+        } else {
+          const V sel01 = (si[t] & 1) ? x[1] : x[0];
+          const V sel23 = (si[t] & 1) ? x[3] : x[2];
+          sel = (si[t] & 2) ? sel23 : sel01;
+        }
         T d = dp[t];
         d = tfma(ww.x, sel.x, d);
         d = tfma(ww.y, sel.y, d);
