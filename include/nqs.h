@@ -149,9 +149,10 @@ const char* nqs_version(void);
 /* ---- instance: the Hamiltonian of Sec. 2.1 Eq. (2) ------------------- */
 
 /* Copy h (K*K) and eri (K^4) from host memory to the device and keep them
- * resident.  EINVAL if K < 1 or K > 64, n_alpha/n_beta outside [0,K], h not
- * symmetric or eri not 8-fold symmetric within 1e-10 * max|eri| (values are
- * replaced by their canonical representative). */
+ * resident.  EINVAL if K < 1 or K > 64, n_alpha/n_beta outside [0,K], an
+ * entry of h or eri or e_core not finite, h not symmetric or eri not 8-fold
+ * symmetric within 1e-10 * max|eri| (values are replaced by their canonical
+ * representative). */
 nqs_status nqs_instance_create(nqs_ctx* ctx, int K, int n_alpha, int n_beta, const double* h1,
                                const double* eri, double e_core, nqs_instance** out);
 nqs_status nqs_instance_destroy(nqs_instance* inst);

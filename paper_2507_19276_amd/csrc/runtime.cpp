@@ -850,6 +850,13 @@ nqs_status nqs_instance_create(nqs_ctx* ctx, int K, int n_alpha, int n_beta, con
   if (n_alpha < 0 || n_alpha > K || n_beta < 0 || n_beta > K)
     return fail(NQS_EINVAL, "electron counts (%d,%d) outside [0,K]", n_alpha, n_beta);
   const size_t K2 = size_t(K) * K, K4 = K2 * K2;
+  // non-finite values would pass the symmetry checks below (every comparison
+  // with NaN is false) and then screen as garbage
+  if (!std::isfinite(e_core)) return fail(NQS_EINVAL, "e_core is not finite");
+  for (size_t t = 0; t < K2; ++t)
+    if (!std::isfinite(h1[t])) return fail(NQS_EINVAL, "h has a non-finite entry at %zu", t);
+  for (size_t t = 0; t < K4; ++t)
+    if (!std::isfinite(eri[t])) return fail(NQS_EINVAL, "eri has a non-finite entry at %zu", t);
   for (int p = 0; p < K; ++p)
     for (int q = 0; q < K; ++q)
       if (std::fabs(h1[p * K + q] - h1[q * K + p]) > 1e-10 * (1.0 + std::fabs(h1[p * K + q])))

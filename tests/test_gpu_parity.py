@@ -224,6 +224,16 @@ def test_edge_cases(nqs, ctx):
         nqs.eloc(ctx, inst, ans, w.samples, eps=-1.0)
     with pytest.raises(nqs.NqsError):
         nqs.eloc(ctx, inst, ans, w.samples, n_eps=5000)
+    # non-finite integrals are rejected when the instance is created
+    eri = w.eri.copy()
+    eri[0, 1, 1, 0] = np.nan
+    with pytest.raises(nqs.NqsError) as e:
+        nqs.Instance(ctx, w.K, w.n_alpha, w.n_beta, w.h, eri, w.e_core)
+    assert e.value.code == nqs.NQS_EINVAL
+    h = w.h.copy()
+    h[0, 0] = np.inf
+    with pytest.raises(nqs.NqsError):
+        nqs.Instance(ctx, w.K, w.n_alpha, w.n_beta, h, w.eri, w.e_core)
 
 
 def test_allocation_failure_is_clean(nqs, ctx):
