@@ -103,6 +103,36 @@ def test_rows_bitexact(nqs, ctx, name, n, eps, n_eps):
             np.testing.assert_allclose(coef[a + 1 + nd[k]:b], wgt, rtol=1e-15, atol=0)
 
 
+@pytest.mark.parametrize("na,nb", [(1, 1), (1, 9), (9, 2), (0, 4), (5, 0), (10, 3), (2, 8)])
+def test_rows_bitexact_extreme_sectors(nqs, ctx, na, nb):
+    """Screening, draws and rows on K = 10 sectors at the edges: one electron or
+    one hole of a spin (blocks of a single rank, so every chunk holds several
+    blocks and is a border chunk), an empty or a full spin (no singles or no
+    doubles of it).  Deterministic ranks, Q, drawn ranks and the rows bit for
+    bit against the oracle."""
+    K, eps, n_eps = 10, 1e-2, 12
+    h, eri = W.chain_integrals(K, 9100 + 16 * na + nb)
+    inst = nqs.Instance(ctx, K, na, nb, h, eri, 0.0)
+    samples = W.random_onvs(K, na, nb, 12, 9200 + 16 * na + nb)
+    r = nqs.rows(ctx, inst, samples, eps=eps, n_eps=n_eps, seed=77, stream_id=5)
+    rp = r["row_ptr"].cpu().numpy()
+    rank = r["rank"].cpu().numpy()
+    m = u64(r["m"])
+    nd = r["n_det"].cpu().numpy()
+    Q = u64(r["Q"])
+    for k, s_ in enumerate(samples):
+        d = oracle.eloc_detail(K, na, nb, h, eri, 1, W.graph_chain(K)[0], W.graph_chain(K)[1], 0,
+                               W.ansatz_params(K, 1, *W.graph_chain(K), 0, seed=1), s_, k, eps, n_eps, seed=77,
+                               stream=5)
+        a, b = rp[k], rp[k + 1]
+        assert rank[a] == -1 and np.array_equal(m[a], s_)
+        assert nd[k] == len(d["det_ranks"]) and int(Q[k]) == d["Q"]
+        assert np.array_equal(rank[a + 1:a + 1 + nd[k]], d["det_ranks"])
+        assert np.array_equal(rank[a + 1 + nd[k]:b], np.unique(d["draw_ranks"]))
+        rm, _ = oracle.connected(K, na, nb, h, eri, s_)
+        assert np.array_equal(m[a + 1:b], rm[rank[a + 1:b]])
+
+
 @pytest.mark.parametrize("name,n", [("c1", None), ("c2", 64), ("c3", 16), ("c4a", 32), ("c4b", 32)])
 def test_logpsi_f64(nqs, ctx, name, n):
     w, inst, ans = setup(nqs, ctx, name, n)
