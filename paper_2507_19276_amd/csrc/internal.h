@@ -253,6 +253,14 @@ template <typename T> struct PsiParams;
 // PSI_NODE: SEED for the units of a node list (resumed from their samples)
 // plus the compact store of nodes.hip.
 enum { PSI_PLAIN = 0, PSI_STORE = 1, PSI_SEED = 2, PSI_NODE = 3 };
+// what the amplitude kernels read of a node (one 32-byte record, a single
+// cache line): log-product entries from off, carried-state slots from coff
+// for the sites marked in need, the changed site c1 and the last resume site e1
+struct alignas(32) NodeRec {
+  int64_t off, coff;
+  uint64_t need;
+  int32_t c1, e1;
+};
 template <typename T>
 struct PsiStates {
   T* hs = nullptr;               // [K][ns][chip] carried states
@@ -264,22 +272,17 @@ struct PsiStates {
   const int32_t* perm = nullptr; // SEED: [R] row of each position
   const uint8_t* t0 = nullptr;   // SEED: [R] first changed site of each position (ascending)
   const int32_t* owner = nullptr;// SEED: [rows] sample of each row
-  // one level of shared prefixes (nodes.hip), compact per node: entry
-  // noff[u] + k holds the carried state after site nc1[u] + k (k < ne1 - nc1;
-  // only where nmask[u] has bit nc1[u] + k, if nmask is given)
-  // and the log-product state before site nc1[u] + k (k <= ne1 - nc1)
-  T* nhs = nullptr;              // [entries][chip]
+  // one level of shared prefixes (nodes.hip), per node u with record
+  // nrec[u]: entry off + k holds the log-product state before site c1 + k
+  // (k <= e1 - c1); the carried state after site s (c1 <= s < e1) is in slot
+  // coff + popcount(need & bits below s), stored only where need has bit s
+  T* nhs = nullptr;              // [slots][chip]
   T* npm = nullptr;              // [entries]
   int32_t* npe = nullptr;        // [entries]
   int8_t* npg = nullptr;         // [entries]
   T* npz = nullptr;              // complex parameters: [entries][2]
-  const int64_t* noff = nullptr; // [nodes]
-  const uint8_t* nc1 = nullptr;  // [nodes] the node's changed site
-  const uint8_t* ne1 = nullptr;  // [nodes] the last site its rows resume at
+  const NodeRec* nrec = nullptr; // [nodes]
   const int32_t* unode = nullptr;// SEED rows: [rows] node the row resumes from (-1: its sample)
-  // node units: bit i set where some row reads the carried state after site i
-  // (the other carried states are not stored; null: all are)
-  const uint64_t* nmask = nullptr;
 };
 // node list written by nodes.hip
 struct NodeList {
@@ -287,14 +290,25 @@ struct NodeList {
   int32_t* owner;                // [nodes] sample
   uint8_t* c1;                   // [nodes] changed site
   uint8_t* e1;                   // [nodes] largest resume site of its rows
-  int64_t* off;                  // [nodes] first storage entry
+  int64_t* off;                  // [nodes] first storage entry (log-product states)
   uint64_t* need;                // [nodes] bit s: some row reads the carried state after site s
 };
-bool node_pairs(int K);   // whether nodes can be keyed by the first two changes (else by the first)
-hipError_t launch_node_count(const uint8_t* t0, const uint32_t* sec, const int64_t* rowptr, int64_t n0, int64_t n1,
-                             int64_t row_base, int K, bool pair, int32_t* ncnt, int64_t* nent, hipStream_t st);
-hipError_t launch_node_scan(int64_t ns, int64_t cap, int32_t* ncnt, int64_t* nent, int64_t* nbase, int64_t* ebase,
-                            int64_t* totals, hipStream_t st);
+// capacities of one pass's node storage: nodes, log-product entries, and the
+// carried-state slots the rows read at their own resume sites (the scan keeps
+// whole samples in order while all three fit)
+struct NodeCaps {
+  int64_t nodes, entries, own_slots;
+};
+// whether nodes can be keyed by the first two changes (the pair table fits the
+// LDS of a workgroup on the current device; else by the first change)
+bool node_pairs(int K);
+// slots beyond the rows' own reads that the wavefront starts can add: 64 K^2
+int64_t slot_reserve(int K);
+hipError_t launch_node_count(const uint8_t* t0, const uint32_t* sec, const uint64_t* samples, const int64_t* rowptr,
+                             int64_t n0, int64_t n1, int64_t row_base, int K, int W, bool pair, int32_t* ncnt,
+                             int64_t* nent, int64_t* nslt, hipStream_t st);
+hipError_t launch_node_scan(int64_t ns, const NodeCaps& cap, const int32_t* ncnt, const int64_t* nent,
+                            const int64_t* nslt, int64_t* nbase, int64_t* ebase, int64_t* totals, hipStream_t st);
 hipError_t launch_node_assign(const uint8_t* t0, const uint32_t* sec, const uint64_t* samples,
                               const int64_t* rowptr, int64_t n0, int64_t n1, int64_t row_base, int K, int W,
                               bool pair, const int64_t* nbase, const int64_t* ebase, const NodeList& nl,
@@ -305,6 +319,13 @@ hipError_t launch_node_assign(const uint8_t* t0, const uint32_t* sec, const uint
 // 64 rows per wavefront of the forward kernels)
 hipError_t launch_node_need(const int32_t* perm, const uint8_t* t0s, int64_t R, int W, const int32_t* row_node,
                             const uint8_t* nc1, uint64_t* need, hipStream_t st);
+// the records of the nn nodes of a pass.  compact: coff = sum over v < u of
+// popcount(need[v]) (bsum: slot_blocks(nn) entries, total: 1); beyond cap
+// slots every need and coff is zeroed and *overflow set.  Otherwise (the
+// tensor-term kernels) a slot per entry: coff = off, need = every site >= c1.
+int64_t slot_blocks(int64_t nn);
+hipError_t launch_node_records(const NodeList& nl, int64_t nn, bool compact, int64_t cap, int64_t* bsum,
+                               int64_t* total, NodeRec* rec, int* overflow, hipStream_t st);
 // phs (complex parameters, PSI_PLAIN only): the phase of each row
 hipError_t launch_psi_f64(const PsiParams<double>& P, const uint64_t* m, int64_t R, double* lphi,
                           int8_t* sphi, hipStream_t st, const PsiStates<double>& X = PsiStates<double>(),
@@ -385,6 +406,10 @@ inline int64_t order_blocks(int64_t R) { return (R + kOrderChunk - 1) / kOrderCh
 // (device); perm: [R] rows in (t0, row) order; t0s: [R] t0 of each position.
 hipError_t launch_order_t0(const uint8_t* t0, int64_t R, int K, int32_t* cnt, int64_t* tot, int32_t* perm,
                            uint8_t* t0s, hipStream_t st);
+// The same in (t0, t1, row) order (t1[r] in [0, K]); tmp_perm: [2 R] int32,
+// tmp_key: [2 R] bytes of scratch.
+hipError_t launch_order_t0_t1(const uint8_t* t0, const uint8_t* t1, int64_t R, int K, int32_t* cnt, int64_t* tot,
+                              int32_t* tmp_perm, uint8_t* tmp_key, int32_t* perm, uint8_t* t0s, hipStream_t st);
 hipError_t launch_psi_bf16(const B16Params& P, const uint64_t* m, int64_t R, double* lphi, int8_t* sphi,
                            hipStream_t st, const B16States& X, int mode, bool split);
 // theta[N][nh] of the samples; with the Ising-RBM also (when E is not null) the

@@ -123,6 +123,20 @@ __global__ __launch_bounds__(256) void k_t0_scatter(const uint8_t* __restrict__ 
   }
 }
 
+// dst[p] = src[perm[p]]
+__global__ __launch_bounds__(256) void k_gather_u8(const uint8_t* __restrict__ src, const int32_t* __restrict__ perm,
+                                                   int64_t n, uint8_t* __restrict__ dst) {
+  const int64_t p = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  if (p < n) dst[p] = src[perm[p]];
+}
+
+// out[p] = a[b[p]]
+__global__ __launch_bounds__(256) void k_compose(const int32_t* __restrict__ a, const int32_t* __restrict__ b,
+                                                 int64_t n, int32_t* __restrict__ out) {
+  const int64_t p = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  if (p < n) out[p] = a[b[p]];
+}
+
 }  // namespace
 
 hipError_t launch_order_t0(const uint8_t* t0, int64_t R, int K, int32_t* cnt, int64_t* tot, int32_t* perm,
@@ -133,6 +147,26 @@ hipError_t launch_order_t0(const uint8_t* t0, int64_t R, int K, int32_t* cnt, in
   hipLaunchKernelGGL(k_t0_count, dim3(unsigned(nb)), dim3(256), 0, st, t0, R, K, cnt);
   hipLaunchKernelGGL(k_t0_scan, dim3(unsigned(K + 1)), dim3(256), 0, st, cnt, nb, K, tot);
   hipLaunchKernelGGL(k_t0_scatter, dim3(unsigned(nb)), dim3(256), 0, st, t0, R, K, cnt, tot, perm, t0s);
+  return hipGetLastError();
+}
+
+// order by (t0, t1) ascending: a stable sort by t1, then a stable sort of
+// the result by t0 (least significant key first); tmp: 2 R int32 and 2 R bytes
+hipError_t launch_order_t0_t1(const uint8_t* t0, const uint8_t* t1, int64_t R, int K, int32_t* cnt, int64_t* tot,
+                              int32_t* tmp_perm, uint8_t* tmp_key, int32_t* perm, uint8_t* t0s, hipStream_t st) {
+  if (R <= 0) return hipSuccess;
+  if (K < 1 || K > 64 || R >= (int64_t(1) << 31)) return hipErrorInvalidValue;
+  int32_t* p1 = tmp_perm;       // position -> row, sorted by t1
+  int32_t* p2 = tmp_perm + R;   // position -> position of the first sort, sorted by t0
+  uint8_t* k1 = tmp_key;        // t1 in the first order (not used further)
+  uint8_t* g0 = tmp_key + R;    // t0 in the first order
+  hipError_t e = launch_order_t0(t1, R, K, cnt, tot, p1, k1, st);
+  if (e != hipSuccess) return e;
+  const unsigned blocks = unsigned((R + 255) / 256);
+  hipLaunchKernelGGL(k_gather_u8, dim3(blocks), dim3(256), 0, st, t0, p1, R, g0);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if ((e = launch_order_t0(g0, R, K, cnt, tot, p2, t0s, st)) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_compose, dim3(blocks), dim3(256), 0, st, p1, p2, R, perm);
   return hipGetLastError();
 }
 

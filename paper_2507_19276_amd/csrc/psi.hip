@@ -125,13 +125,20 @@ __global__ __launch_bounds__(256) void k_psi_mt(PsiParams<T> P, const uint64_t* 
     // With a node level (X.unode), a row's node covers the sites from its
     // changed site nc1 on: the node agrees with the row below the row's
     // resume site, the sample below nc1.
+    // The node's carried state after site s is in slot nco + popcount(nmk &
+    // bits below s); one record per node.
     int nd[NTL], nb[NTL];
-    int64_t no[NTL];
+    int64_t no[NTL], nco[NTL];
+    uint64_t nmk[NTL];
 #pragma unroll
     for (int t = 0; t < NTL; ++t) {
       nd[t] = X.unode ? X.unode[rowt[t]] : -1;
-      nb[t] = nd[t] >= 0 ? int(X.nc1[nd[t]]) : P.K + 1;
-      no[t] = nd[t] >= 0 ? X.noff[nd[t]] : 0;
+      NodeRec q{0, 0, 0ull, P.K + 1, 0};
+      if (nd[t] >= 0) q = X.nrec[nd[t]];
+      nb[t] = q.c1;
+      no[t] = q.off;
+      nco[t] = q.coff;
+      nmk[t] = q.need;
     }
     // the states live at i0 (read by a site >= i0; distinct slots)
     for (uint64_t lv = ((const __attribute__((address_space(4))) uint64_t*)P.live)[i0]; lv; lv &= lv - 1) {
@@ -139,7 +146,7 @@ __global__ __launch_bounds__(256) void k_psi_mt(PsiParams<T> P, const uint64_t* 
       V* wr = ring + size_t(wsl[s]) * SLOT;
 #pragma unroll
       for (int t = 0; t < NTL; ++t) {
-        const T* src = s >= nb[t] ? X.nhs + size_t(no[t] + (s - nb[t])) * CH + 4 * g
+        const T* src = s >= nb[t] ? X.nhs + size_t(nco[t] + __popcll(nmk[t] & low_bits(s))) * CH + 4 * g
                                   : X.hs + (size_t(s) * X.ns + X.owner[rowt[t]]) * CH + 4 * g;
 #pragma unroll
         for (int tt = 0; tt < TPC; ++tt) wr[(t * TPC + tt) * 64] = *reinterpret_cast<const V*>(src + 16 * tt);
@@ -198,22 +205,25 @@ __global__ __launch_bounds__(256) void k_psi_mt(PsiParams<T> P, const uint64_t* 
   int sc1 = 0, se1 = -1;
   int64_t soff = 0;
   if (STORE == 2) {
-    sc1 = X.nc1[orow];
-    se1 = X.ne1[orow];
-    soff = X.noff[orow];
+    const NodeRec q = X.nrec[orow];
+    sc1 = q.c1;
+    se1 = q.e1;
+    soff = q.off;
   }
+  // STORE 2: each unit's carried states go to the sites its record marks
+  // (the sites some row reads; every site from nc1 on for the tensor-term
+  // kernels)
   int tc1[NTL], te1[NTL];
   int64_t toff[NTL];
-  // STORE 2: the sites whose carried states some row reads (the tensor-term
-  // kernels store all: they have no registers to spare)
-  constexpr bool NEED = STORE == 2 && !TN;
   uint64_t tneed[NTL];
 #pragma unroll
   for (int t = 0; t < NTL; ++t) {
-    tc1[t] = STORE == 2 ? int(X.nc1[rowt[t]]) : 0;
-    te1[t] = STORE == 2 ? int(X.ne1[rowt[t]]) : -1;
-    toff[t] = STORE == 2 ? X.noff[rowt[t]] : 0;
-    tneed[t] = NEED && X.nmask ? X.nmask[rowt[t]] : ~0ull;
+    NodeRec q{0, 0, 0ull, 0, -1};
+    if (STORE == 2) q = X.nrec[rowt[t]];
+    tc1[t] = q.c1;
+    te1[t] = q.e1;
+    toff[t] = q.coff;
+    tneed[t] = q.need;
   }
   auto store_pre = [&](int i) {
     const bool writer = NTL == 4 || (NTL == 2 ? (g & 1) == 0 : g == 0);
@@ -572,8 +582,9 @@ __global__ __launch_bounds__(256) void k_psi_mt(PsiParams<T> P, const uint64_t* 
           const int64_t r = base + 16 * t + j;
           if (r < X.ns) *reinterpret_cast<V*>(X.hs + (size_t(i) * X.ns + r) * CH + 16 * tt + 4 * g) = sel;
         }
-        if (STORE == 2 && base + 16 * t + j < R && i >= tc1[t] && i < te1[t] && (!NEED || ((tneed[t] >> i) & 1ull)))
-          *reinterpret_cast<V*>(X.nhs + size_t(toff[t] + (i - tc1[t])) * CH + 16 * tt + 4 * g) = sel;
+        if (STORE == 2 && base + 16 * t + j < R && i < te1[t] && ((tneed[t] >> i) & 1ull))
+          *reinterpret_cast<V*>(X.nhs + size_t(toff[t] + __popcll(tneed[t] & low_bits(i))) * CH + 16 * tt + 4 * g) =
+              sel;
       }
     }
     T ps[4];

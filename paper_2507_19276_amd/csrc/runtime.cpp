@@ -1328,11 +1328,8 @@ struct Resume {
   int32_t* npe = nullptr;
   int8_t* npg = nullptr;
   void* npz = nullptr;      // complex parameters: [entries][2] T
-  const int64_t* noff = nullptr;
-  const uint8_t* nc1 = nullptr;
-  const uint8_t* ne1 = nullptr;
+  const NodeRec* nrec = nullptr;     // [nodes]
   const int32_t* unode = nullptr;
-  const uint64_t* nmask = nullptr;   // node pass: carried states some row reads
 };
 
 template <typename T>
@@ -1352,11 +1349,8 @@ PsiStates<T> states(const Resume& r) {
   X.npe = r.npe;
   X.npg = r.npg;
   X.npz = static_cast<T*>(r.npz);
-  X.noff = r.noff;
-  X.nc1 = r.nc1;
-  X.ne1 = r.ne1;
+  X.nrec = r.nrec;
   X.unode = r.unode;
-  X.nmask = r.nmask;
   return X;
 }
 
@@ -1466,20 +1460,36 @@ EnumGeom make_geom(int64_t n_conn, int64_t N) {
   return G;
 }
 
-// node storage entries of a pass (one entry: a carried state and a log-product
-// state).  Nodes keyed by the first two changes need about 1.4 entries per
-// row (measured on the chain, lattice and dense workloads); nodes keyed by the
-// first change alone 0.05-0.16.  Samples beyond the cap resume at c1.
-int64_t node_entry_cap(int64_t pass_rows, int K, bool pair) {
-  if (pair) return std::max<int64_t>(pass_rows / 2 * 3, int64_t(16) * K * (K + 1));
-  return std::max<int64_t>(pass_rows / 8, int64_t(4) * K * (K + 1));
+// node storage of a pass.  Measured per row on samples drawn from Phi^2 (chain
+// K = 20, dense K = 20, lattice K = 18, NN+NNN chain K = 50), nodes keyed by
+// the first two changes: 0.07-0.22 nodes, 0.95-3.3 log-product entries
+// (about K / 15) and 0.37-0.87 carried-state slots read at the rows' own
+// resume sites (about (W - 1) K / 100 with W - 1 parent offsets); keyed by
+// the first change alone, 0.05-0.16 entries.  The capacities leave a quarter
+// or more over these; samples beyond a capacity resume at c1.  The
+// tensor-term kernels store every carried state (a slot per entry).
+NodeCaps node_caps(int64_t pass_rows, int K, int W, bool pair, bool tn) {
+  const int64_t floor = int64_t(16) * K * (K + 1);
+  NodeCaps c;
+  if (tn) {
+    c.entries = pair ? std::max<int64_t>(pass_rows / 2 * 3, floor) : std::max<int64_t>(pass_rows / 8, floor / 4);
+    c.nodes = c.entries;
+    c.own_slots = c.entries;
+  } else {
+    c.nodes = std::max<int64_t>(pass_rows / 3, floor);
+    c.entries = std::max<int64_t>(pass_rows / 16 * (16 + K), floor);
+    c.own_slots = std::min(c.entries, std::max<int64_t>(pass_rows / 100 * (35 + int64_t(W - 1) * K), floor));
+  }
+  return c;
 }
 
+// carried-state slots to allocate: the rows' own reads plus the reserve for
+// the wavefront starts (tensor-term kernels: one per entry)
+int64_t node_slots(const NodeCaps& c, int K, bool tn) { return tn ? c.entries : c.own_slots + slot_reserve(K); }
+
 // nodes keyed by the first two changes where the pair table fits the LDS
-bool pair_nodes(int K, int precision) {
-  (void)precision;
-  return node_pairs(K);
-}
+// (tensor-term kernels: up to K = 30, as they store every carried state)
+bool pair_nodes(int K, bool tn) { return node_pairs(K) && (!tn || K <= 30); }
 
 int64_t max_samples_per_pass(const std::vector<std::pair<int64_t, int64_t>>& passes) {
   int64_t m = 1;
@@ -1871,12 +1881,18 @@ nqs_status eloc_run(nqs_ctx* ctx, const nqs_instance* inst, const nqs_ansatz* an
   // site that a node pass does not pay): node list, compact storage
   const bool nodes = resume && !is_bf16(opts->precision);
   const int64_t max_pass_samples = max_samples_per_pass(passes);
-  const bool pair = pair_nodes(K, opts->precision);
-  const int64_t ecap = node_entry_cap(cap_used, K, pair);
+  const bool tn = ans->tensor;
+  const bool pair = pair_nodes(K, tn);
+  const NodeCaps caps = node_caps(cap_used, K, ans->W, pair, tn);
+  const int64_t scap = node_slots(caps, K, tn);
   NodeList nl{};
   int32_t *ncnt = nullptr, *row_node = nullptr, *nperm = nullptr;
-  int64_t *nent = nullptr, *nbase = nullptr, *ebase = nullptr, *ntot = nullptr;
-  uint8_t *row_site = nullptr, *nt0s = nullptr;
+  int64_t *nent = nullptr, *nslt = nullptr, *nbase = nullptr, *ebase = nullptr, *ntot = nullptr;
+  int64_t* sbsum = nullptr;
+  NodeRec* nrec = nullptr;
+  int* sover = nullptr;
+  uint8_t *row_site = nullptr, *nt0s = nullptr, *ntmp_k = nullptr;
+  int32_t* ntmp_p = nullptr;
   int32_t* ncnt_s = nullptr;
   int64_t* ntot_s = nullptr;
   double* lphi_n = nullptr;
@@ -1885,34 +1901,43 @@ nqs_status eloc_run(nqs_ctx* ctx, const nqs_instance* inst, const nqs_ansatz* an
     const size_t esz = state_bytes(opts->precision);
     ncnt = S.get<int32_t>(max_pass_samples);
     nent = S.get<int64_t>(max_pass_samples);
+    nslt = S.get<int64_t>(max_pass_samples);
     nbase = S.get<int64_t>(max_pass_samples);
     ebase = S.get<int64_t>(max_pass_samples);
-    ntot = S.get<int64_t>(2);
-    nl.m = S.get<uint64_t>(size_t(ecap) * 2);
-    nl.owner = S.get<int32_t>(ecap);
-    nl.c1 = S.get<uint8_t>(ecap);
-    nl.e1 = S.get<uint8_t>(ecap);
-    nl.off = S.get<int64_t>(ecap);
-    nperm = S.get<int32_t>(ecap);
-    nt0s = S.get<uint8_t>(ecap);
-    nl.need = S.get<uint64_t>(ecap);
+    ntot = S.get<int64_t>(3);
+    nl.m = S.get<uint64_t>(size_t(caps.nodes) * 2);
+    nl.owner = S.get<int32_t>(caps.nodes);
+    nl.c1 = S.get<uint8_t>(caps.nodes);
+    nl.e1 = S.get<uint8_t>(caps.nodes);
+    nl.off = S.get<int64_t>(caps.nodes);
+    nperm = S.get<int32_t>(caps.nodes);
+    nt0s = S.get<uint8_t>(caps.nodes);
+    ntmp_p = S.get<int32_t>(size_t(caps.nodes) * 2);
+    ntmp_k = S.get<uint8_t>(size_t(caps.nodes) * 2);
+    nl.need = S.get<uint64_t>(caps.nodes);
+    nrec = S.get<NodeRec>(caps.nodes);
+    if (!tn) {
+      sbsum = S.get<int64_t>(slot_blocks(caps.nodes));
+      sover = S.get<int>(1);
+    }
     ncnt_s = S.get<int32_t>(size_t(order_blocks(cap_used)) * (K + 1));
     ntot_s = S.get<int64_t>(K + 1);
-    lphi_n = S.get<double>(ecap);
-    sphi_n = S.get<int8_t>(ecap);
-    rs.nhs = S.get<unsigned char>(size_t(ecap) * ans->chip * esz);
-    rs.npm = S.get<unsigned char>(size_t(ecap) * mantissa_bytes(opts->precision));
-    rs.npe = S.get<int32_t>(ecap);
-    rs.npg = S.get<int8_t>(ecap);
+    lphi_n = S.get<double>(caps.nodes);
+    sphi_n = S.get<int8_t>(caps.nodes);
+    rs.nhs = S.get<unsigned char>(size_t(scap) * ans->chip * esz);
+    rs.npm = S.get<unsigned char>(size_t(caps.entries) * mantissa_bytes(opts->precision));
+    rs.npe = S.get<int32_t>(caps.entries);
+    rs.npg = S.get<int8_t>(caps.entries);
     if (ans->cplx) {
-      rs.npz = S.get<unsigned char>(size_t(ecap) * 2 * mantissa_bytes(opts->precision));
-      phs_n = S.get<double>(ecap);
+      rs.npz = S.get<unsigned char>(size_t(caps.entries) * 2 * mantissa_bytes(opts->precision));
+      phs_n = S.get<double>(caps.nodes);
     }
     row_node = S.get<int32_t>(cap_used);
     row_site = S.get<uint8_t>(cap_used);
     P.rows.sec = S.get<uint32_t>(cap_used);
   }
   if (S.oom) return fail(NQS_ENOMEM, "workspace allocation failed");
+  if (sover) HIPCHK(hipMemsetAsync(sover, 0, sizeof(int), stream));
   if (ans->nh) HIPCHK(launch_corr_theta(ans->corr(), samples, N, theta, Etab, opts->precision, stream));
   float ms_rows = 0, ms_amp = 0, ms_red = 0, ms_psi = 0;
   int64_t site_rows = 0;
@@ -1954,8 +1979,9 @@ nqs_status eloc_run(nqs_ctx* ctx, const nqs_instance* inst, const nqs_ansatz* an
       if (nodes) {
         // nodes of this pass: count, place (host learns the totals), assign
         const int64_t ns = n1 - n0, row_base = P.rowptr_host[n0];
-        HIPCHK(launch_node_count(P.rows.t0, P.rows.sec, P.rowptr, n0, n1, row_base, K, pair, ncnt, nent, stream));
-        HIPCHK(launch_node_scan(ns, ecap, ncnt, nent, nbase, ebase, ntot, stream));
+        HIPCHK(launch_node_count(P.rows.t0, P.rows.sec, samples, P.rowptr, n0, n1, row_base, K, ans->W, pair, ncnt,
+                                 nent, nslt, stream));
+        HIPCHK(launch_node_scan(ns, caps, ncnt, nent, nslt, nbase, ebase, ntot, stream));
         int64_t tot2[2] = {0, 0};
         HIPCHK(hipMemcpyAsync(tot2, ntot, sizeof tot2, hipMemcpyDeviceToHost, stream));
         HIPCHK(hipStreamSynchronize(stream));
@@ -1966,17 +1992,25 @@ nqs_status eloc_run(nqs_ctx* ctx, const nqs_instance* inst, const nqs_ansatz* an
         HIPCHK(launch_order_t0(row_site, Rp, K, rs.cnt, rs.tot, rs.perm, rs.t0, stream));
         if (nn > 0) {
           HIPCHK(launch_node_need(rs.perm, rs.t0, Rp, ans->W, row_node, nl.c1, nl.need, stream));
+          // node records; carried-state slots only for the sites some row
+          // reads (the tensor-term kernels store every site, a slot per entry)
+          HIPCHK(launch_node_records(nl, nn, !tn, scap, sbsum, ntot + 2, nrec, sover, stream));
           // the node pass: resumed from the samples at the changed site, stores compactly
-          HIPCHK(launch_order_t0(nl.c1, nn, K, ncnt_s, ntot_s, nperm, nt0s, stream));
+          // node units by changed site, and from chi = 32 on by (changed
+          // site, last site): a wavefront starts at its first unit's changed
+          // site and stops after its units' last site.  At smaller chi a site
+          // costs little next to a unit's start, and the changed-site order,
+          // which keeps a sample's units together, measured faster.
+          if (ans->chip >= 32)
+            HIPCHK(launch_order_t0_t1(nl.c1, nl.e1, nn, K, ncnt_s, ntot_s, ntmp_p, ntmp_k, nperm, nt0s, stream));
+          else
+            HIPCHK(launch_order_t0(nl.c1, nn, K, ncnt_s, ntot_s, nperm, nt0s, stream));
           Resume rn = rs;
           rn.perm = nperm;
           rn.t0 = nt0s;
           rn.owner = nl.owner;
-          rn.noff = nl.off;
-          rn.nc1 = nl.c1;
-          rn.ne1 = nl.e1;
+          rn.nrec = nrec;
           rn.unode = nullptr;
-          rn.nmask = nl.need;
           if ((s = run_amplitudes(ans, opts->precision, nl.m, nn, lphi_n, sphi_n, stream, &rn, PSI_NODE, phs_n)) !=
               NQS_OK)
             return s;
@@ -1984,9 +2018,7 @@ nqs_status eloc_run(nqs_ctx* ctx, const nqs_instance* inst, const nqs_ansatz* an
           // resume site of its rows: (entries - 1) sites
           site_rows += tot2[1] - tot2[0];
         }
-        rs.noff = nl.off;
-        rs.nc1 = nl.c1;
-        rs.ne1 = nl.e1;
+        rs.nrec = nrec;
         rs.unode = row_node;
       } else {
         HIPCHK(launch_order_t0(key, Rp, K, rs.cnt, rs.tot, rs.perm, rs.t0, stream));
@@ -2038,8 +2070,11 @@ nqs_status eloc_run(nqs_ctx* ctx, const nqs_instance* inst, const nqs_ansatz* an
   }
   HIPCHK(launch_batch_sums(N, counts, el, et, f2, sums, stream, el_i, et_i));
   double hs[8] = {0};
+  int slot_overflow = 0;
   if (stats) HIPCHK(hipMemcpyAsync(hs, sums, sizeof hs, hipMemcpyDeviceToHost, stream));
+  if (sover) HIPCHK(hipMemcpyAsync(&slot_overflow, sover, sizeof(int), hipMemcpyDeviceToHost, stream));
   HIPCHK(hipStreamSynchronize(stream));
+  if (slot_overflow) return fail(NQS_EDEVICE, "node state slots exceeded their capacity");
   if (stats) {
     std::vector<int64_t> Dn(N), Un(N);
     HIPCHK(hipMemcpy(Dn.data(), P.Dn, sizeof(int64_t) * N, hipMemcpyDeviceToHost));
@@ -2342,15 +2377,23 @@ nqs_status nqs_eloc_workspace_bytes(const nqs_instance* inst, const nqs_ansatz* 
     b += al(size_t(N) * 8) + al(size_t(N));
     if (!is_bf16(opts->precision)) {
       // node level: per-sample counts, node list, node order, storage, rows' nodes
-      const int64_t ecap = node_entry_cap(rows, K, pair_nodes(K, opts->precision));
+      const bool tn = ans->tensor;
+      const NodeCaps c = node_caps(rows, K, ans->W, pair_nodes(K, tn), tn);
+      const int64_t nslots = node_slots(c, K, tn);
       const size_t esz = state_bytes(opts->precision);
-      b += al(size_t(N) * 4) + 3 * al(size_t(N) * 8) + al(16);
-      b += al(size_t(ecap) * 16) + al(size_t(ecap) * 4) + 2 * al(size_t(ecap)) + al(size_t(ecap) * 8);
-      b += al(size_t(ecap) * 4) + al(size_t(ecap)) + al(size_t(ecap) * 8) + al(size_t(ecap));
-      b += al(size_t(ecap) * ans->chip * esz) + al(size_t(ecap) * mantissa_bytes(opts->precision)) +
-           al(size_t(ecap) * 4) + al(size_t(ecap));
+      b += al(size_t(N) * 4) + 4 * al(size_t(N) * 8) + al(24);
+      b += al(size_t(c.nodes) * 16) + al(size_t(c.nodes) * 4) + 2 * al(size_t(c.nodes)) + al(size_t(c.nodes) * 8);
+      b += al(size_t(c.nodes) * 4) + al(size_t(c.nodes)) + al(size_t(c.nodes) * 8);
+      b += al(size_t(c.nodes) * 8) + al(size_t(c.nodes) * 2);
+      b += al(size_t(c.nodes) * sizeof(NodeRec));
+      if (!tn) b += al(size_t(slot_blocks(c.nodes)) * 8) + al(4);
+      b += al(size_t(c.nodes) * 8) + al(size_t(c.nodes));
+      b += al(size_t(nslots) * ans->chip * esz) + al(size_t(c.entries) * mantissa_bytes(opts->precision)) +
+           al(size_t(c.entries) * 4) + al(size_t(c.entries));
+      if (ans->cplx)
+        b += al(size_t(c.entries) * 2 * mantissa_bytes(opts->precision)) + al(size_t(c.nodes) * 8);
       b += al(size_t(rows) * 4) + al(size_t(rows)) + al(size_t(rows) * 4);
-      b += al(size_t(ecap) * 8) + al(size_t(order_blocks(rows)) * (K + 1) * 4) + al(size_t(K + 1) * 8);
+      b += al(size_t(order_blocks(rows)) * (K + 1) * 4) + al(size_t(K + 1) * 8);
     }
   }
   b += 3 * al(size_t(N) * 8) + al(64);     // outputs the caller did not provide, batch sums
