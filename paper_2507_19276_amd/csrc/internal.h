@@ -261,6 +261,14 @@ struct alignas(32) NodeRec {
   uint64_t need;
   int32_t c1, e1;
 };
+// a node's log-product state before a site (mantissa, power of two, sign) in
+// one 16-byte store: the node pass writes them scattered, one per unit
+template <typename T>
+struct alignas(16) LogProd {
+  T m;
+  int32_t e, s;
+};
+static_assert(sizeof(LogProd<float>) == 16 && sizeof(LogProd<double>) == 16, "one 16-byte store per entry");
 template <typename T>
 struct PsiStates {
   T* hs = nullptr;               // [K][ns][chip] carried states
@@ -277,9 +285,7 @@ struct PsiStates {
   // (k <= e1 - c1); the carried state after site s (c1 <= s < e1) is in slot
   // coff + popcount(need & bits below s), stored only where need has bit s
   T* nhs = nullptr;              // [slots][chip]
-  T* npm = nullptr;              // [entries]
-  int32_t* npe = nullptr;        // [entries]
-  int8_t* npg = nullptr;         // [entries]
+  LogProd<T>* nlp = nullptr;     // [entries]
   T* npz = nullptr;              // complex parameters: [entries][2]
   const NodeRec* nrec = nullptr; // [nodes]
   const int32_t* unode = nullptr;// SEED rows: [rows] node the row resumes from (-1: its sample)

@@ -159,9 +159,10 @@ __global__ __launch_bounds__(256) void k_psi_mt(PsiParams<T> P, const uint64_t* 
       if (t == own) { ond = nd[t]; onb = nb[t]; ono = no[t]; }
     if (i0 >= onb) {
       const size_t so = size_t(ono + (i0 - onb));
-      prod = X.npm[so];
-      pexp = X.npe[so];
-      sgn = X.npg[so];
+      const LogProd<T> lp = X.nlp[so];
+      prod = lp.m;
+      pexp = lp.e;
+      sgn = lp.s;
       if (CPLX) {
         zr = X.npz[2 * so];
         zi = X.npz[2 * so + 1];
@@ -239,9 +240,7 @@ __global__ __launch_bounds__(256) void k_psi_mt(PsiParams<T> P, const uint64_t* 
     }
     if (STORE == 2 && writer && olive && i >= sc1 && i <= se1) {
       const size_t so = size_t(soff + (i - sc1));
-      X.npm[so] = prod;
-      X.npe[so] = pexp;
-      X.npg[so] = int8_t(sgn);
+      X.nlp[so] = LogProd<T>{prod, pexp, sgn};
       if (CPLX) {
         X.npz[2 * so] = zr;
         X.npz[2 * so + 1] = zi;

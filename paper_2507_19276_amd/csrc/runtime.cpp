@@ -1324,9 +1324,7 @@ struct Resume {
   const int32_t* owner = nullptr;
   // one node level (FP64/FP32): node storage and the rows' nodes
   void* nhs = nullptr;      // [entries][chip] T
-  void* npm = nullptr;      // [entries] T
-  int32_t* npe = nullptr;
-  int8_t* npg = nullptr;
+  void* nlp = nullptr;      // [entries] LogProd<T> (16 bytes)
   void* npz = nullptr;      // complex parameters: [entries][2] T
   const NodeRec* nrec = nullptr;     // [nodes]
   const int32_t* unode = nullptr;
@@ -1345,9 +1343,7 @@ PsiStates<T> states(const Resume& r) {
   X.t0 = r.t0;
   X.owner = r.owner;
   X.nhs = static_cast<T*>(r.nhs);
-  X.npm = static_cast<T*>(r.npm);
-  X.npe = r.npe;
-  X.npg = r.npg;
+  X.nlp = static_cast<LogProd<T>*>(r.nlp);
   X.npz = static_cast<T*>(r.npz);
   X.nrec = r.nrec;
   X.unode = r.unode;
@@ -1925,9 +1921,7 @@ nqs_status eloc_run(nqs_ctx* ctx, const nqs_instance* inst, const nqs_ansatz* an
     lphi_n = S.get<double>(caps.nodes);
     sphi_n = S.get<int8_t>(caps.nodes);
     rs.nhs = S.get<unsigned char>(size_t(scap) * ans->chip * esz);
-    rs.npm = S.get<unsigned char>(size_t(caps.entries) * mantissa_bytes(opts->precision));
-    rs.npe = S.get<int32_t>(caps.entries);
-    rs.npg = S.get<int8_t>(caps.entries);
+    rs.nlp = S.get<LogProd<double>>(caps.entries);
     if (ans->cplx) {
       rs.npz = S.get<unsigned char>(size_t(caps.entries) * 2 * mantissa_bytes(opts->precision));
       phs_n = S.get<double>(caps.nodes);
@@ -2388,8 +2382,7 @@ nqs_status nqs_eloc_workspace_bytes(const nqs_instance* inst, const nqs_ansatz* 
       b += al(size_t(c.nodes) * sizeof(NodeRec));
       if (!tn) b += al(size_t(slot_blocks(c.nodes)) * 8) + al(4);
       b += al(size_t(c.nodes) * 8) + al(size_t(c.nodes));
-      b += al(size_t(nslots) * ans->chip * esz) + al(size_t(c.entries) * mantissa_bytes(opts->precision)) +
-           al(size_t(c.entries) * 4) + al(size_t(c.entries));
+      b += al(size_t(nslots) * ans->chip * esz) + al(size_t(c.entries) * sizeof(LogProd<double>));
       if (ans->cplx)
         b += al(size_t(c.entries) * 2 * mantissa_bytes(opts->precision)) + al(size_t(c.nodes) * 8);
       b += al(size_t(rows) * 4) + al(size_t(rows)) + al(size_t(rows) * 4);
