@@ -94,15 +94,18 @@ def site_state(w0, w1, i):
     return v & 3
 
 
-def test_site_count_matches_changed_sites(nqs, ctx):
+@pytest.mark.parametrize("name,n", [("c2", 64), ("c3", 6)])
+def test_site_count_matches_changed_sites(nqs, ctx, name, n):
     """Executed site evaluations: the samples' pass (N K), then for FP32/FP64
     one node per (sample, first changed site and state there, second changed
     site and state there) from its first changed site to the largest third
     changed site of its rows, and every row from its third changed site on;
     for BF16 (no node level; measured: nodes do not pay for its cheaper sites)
     every row from its first changed site on.  Counted here from the row list
-    of the same call."""
-    w, inst, ans = setup(nqs, ctx, "c2", 64)
+    of the same call.  K = 50 spans both ONV words and the compact pair keys
+    of large K (a node split in two would still give the same bits, but not
+    this count)."""
+    w, inst, ans = setup(nqs, ctx, name, n)
     kw = dict(eps=w.eps, n_eps=w.n_eps, seed=w.seed, stream_id=7)
     r = nqs.rows(ctx, inst, w.samples, **kw)
     rp = r["row_ptr"].cpu().numpy()
