@@ -488,6 +488,11 @@ nqs_status nqs_serve_info(nqs_server* srv, nqs_serve_status* out);
 /* Make the k-th subsequent workspace allocation of this context fail with
  * NQS_ENOMEM (k >= 1; 0 disables).  For failure-handling tests. */
 nqs_status nqs_ctx_fail_alloc_at(nqs_ctx* ctx, int64_t k);
+/* Scale the node storage capacities of this context's later local-energy
+ * calls by scale (0 < scale <= 1; 1 restores them; NQS_EINVAL otherwise):
+ * whole samples past a capacity get no nodes and their rows resume at their
+ * first changed site, with the same results.  For tests of that path. */
+nqs_status nqs_ctx_set_node_capacity(nqs_ctx* ctx, double scale);
 /* Bytes currently held by the context's workspace pool (in use, cached). */
 nqs_status nqs_ctx_pool_bytes(const nqs_ctx* ctx, size_t* in_use, size_t* cached);
 /* High-water mark of the pool's in-use bytes; reset != 0 restarts it at the

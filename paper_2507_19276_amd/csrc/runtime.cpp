@@ -11,6 +11,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <atomic>
 #include <cstring>
 #include <limits>
 #include <map>
@@ -82,6 +83,7 @@ struct nqs_ctx {
   void* arena = nullptr;                      // this device's static workspace (nqs_eloc_noalloc)
   hipError_t arena_err = hipSuccess;          // its lookup's result
   int64_t fail_at = 0;                        // test hook: k-th acquire fails
+  std::atomic<double> node_cap_scale{1.0};    // test hook: scales the node capacities
   // blocks handed back with work still queued on their stream: they count as
   // in use until the event recorded after that work has completed
   std::vector<std::pair<hipEvent_t, std::vector<void*>>> pending;
@@ -815,6 +817,12 @@ nqs_status nqs_ctx_fail_alloc_at(nqs_ctx* ctx, int64_t k) {
   return NQS_OK;
 }
 
+nqs_status nqs_ctx_set_node_capacity(nqs_ctx* ctx, double scale) {
+  if (!ctx || !(scale > 0.0 && scale <= 1.0)) return fail(NQS_EINVAL, "scale must be in (0, 1]");
+  ctx->node_cap_scale.store(scale);
+  return NQS_OK;
+}
+
 nqs_status nqs_ctx_pool_bytes(const nqs_ctx* ctx, size_t* in_use, size_t* cached) {
   if (!ctx) return fail(NQS_EINVAL, "ctx is NULL");
   auto* c = const_cast<nqs_ctx*>(ctx);
@@ -1464,7 +1472,7 @@ EnumGeom make_geom(int64_t n_conn, int64_t N) {
 // the first change alone, 0.05-0.16 entries.  The capacities leave a quarter
 // or more over these; samples beyond a capacity resume at c1.  The
 // tensor-term kernels store every carried state (a slot per entry).
-NodeCaps node_caps(int64_t pass_rows, int K, int W, bool pair, bool tn) {
+NodeCaps node_caps(int64_t pass_rows, int K, int W, bool pair, bool tn, double scale = 1.0) {
   const int64_t floor = int64_t(16) * K * (K + 1);
   NodeCaps c;
   if (tn) {
@@ -1475,6 +1483,11 @@ NodeCaps node_caps(int64_t pass_rows, int K, int W, bool pair, bool tn) {
     c.nodes = std::max<int64_t>(pass_rows / 3, floor);
     c.entries = std::max<int64_t>(pass_rows / 16 * (16 + K), floor);
     c.own_slots = std::min(c.entries, std::max<int64_t>(pass_rows / 100 * (35 + int64_t(W - 1) * K), floor));
+  }
+  if (scale < 1.0) {
+    c.nodes = std::max<int64_t>(1, int64_t(double(c.nodes) * scale));
+    c.entries = std::max<int64_t>(1, int64_t(double(c.entries) * scale));
+    c.own_slots = std::max<int64_t>(1, int64_t(double(c.own_slots) * scale));
   }
   return c;
 }
@@ -1879,7 +1892,7 @@ nqs_status eloc_run(nqs_ctx* ctx, const nqs_instance* inst, const nqs_ansatz* an
   const int64_t max_pass_samples = max_samples_per_pass(passes);
   const bool tn = ans->tensor;
   const bool pair = pair_nodes(K, tn);
-  const NodeCaps caps = node_caps(cap_used, K, ans->W, pair, tn);
+  const NodeCaps caps = node_caps(cap_used, K, ans->W, pair, tn, ctx->node_cap_scale.load());
   const int64_t scap = node_slots(caps, K, tn);
   NodeList nl{};
   int32_t *ncnt = nullptr, *row_node = nullptr, *nperm = nullptr;

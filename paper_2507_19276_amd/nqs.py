@@ -87,6 +87,7 @@ def lib():
     L.nqs_ctx_create.argtypes = [C.c_int, C.POINTER(_p)]
     L.nqs_ctx_destroy.argtypes = [_p]
     L.nqs_ctx_fail_alloc_at.argtypes = [_p, C.c_int64]
+    L.nqs_ctx_set_node_capacity.argtypes = [_p, C.c_double]
     L.nqs_ctx_pool_bytes.argtypes = [_p, C.POINTER(C.c_size_t), C.POINTER(C.c_size_t)]
     L.nqs_ctx_pool_peak.argtypes = [_p, C.POINTER(C.c_size_t), C.c_int]
     L.nqs_ctx_set_pool_limit.argtypes = [_p, C.c_size_t]
@@ -163,6 +164,9 @@ class Context:
 
     def fail_alloc_at(self, k: int):
         check(lib().nqs_ctx_fail_alloc_at(self.h, int(k)))
+
+    def set_node_capacity(self, scale: float):
+        check(lib().nqs_ctx_set_node_capacity(self.h, float(scale)))
 
     def pool_bytes(self):
         a, b = C.c_size_t(), C.c_size_t()

@@ -80,6 +80,27 @@ def test_resume_with_passes(nqs, ctx, prec):
         assert np.array_equal(full[k].cpu().numpy(), many[k].cpu().numpy(), equal_nan=True), (prec, k)
 
 
+@pytest.mark.parametrize("name,n,scale", [("c2", 64, 0.05), ("c3", 8, 0.3)])
+def test_node_capacity_fallback(nqs, ctx, name, n, scale):
+    """Whole samples past a node storage capacity get no nodes and their rows
+    resume at their first changed site from the sample: the results stay
+    bit-identical to evaluating every row from site 0, and the site count lies
+    between that of full node coverage and that of full recompute."""
+    w, inst, ans = setup(nqs, ctx, name, n)
+    for prec in ("f64", "f32"):
+        kw = dict(eps=w.eps, n_eps=w.n_eps, precision=prec, seed=w.seed, stream_id=3)
+        full, st_full = nqs.eloc(ctx, inst, ans, w.samples, resume=False, **kw)
+        _, st_all = nqs.eloc(ctx, inst, ans, w.samples, **kw)
+        ctx.set_node_capacity(scale)
+        try:
+            part, st_part = nqs.eloc(ctx, inst, ans, w.samples, **kw)
+        finally:
+            ctx.set_node_capacity(1.0)
+        for k in NAMES:
+            assert np.array_equal(full[k].cpu().numpy(), part[k].cpu().numpy(), equal_nan=True), (name, prec, k)
+        assert st_all["n_site_rows"] < st_part["n_site_rows"] < st_full["n_site_rows"], (name, prec)
+
+
 def changed_sites(m, s, K):
     """Sites (ascending) where row m differs from its sample s."""
     out = []
